@@ -1,0 +1,573 @@
+"""Pins of the FP64 oracle against what mathematics fixes independently of it:
+closed forms, conservation laws, convergence orders, SciPy's rotation routines,
+symmetries, and central finite differences for its gradients.
+
+Each test names the part of the oracle a plausible mistake would break.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.linalg import expm
+from scipy.spatial.transform import Rotation
+
+import workloads as W
+import oracle as O
+
+F64 = torch.float64
+
+
+def fp_batch(n=1, control=O.CTRL_ROTOR, integrator=O.RK4, dt=0.002, renorm=1, edit=None):
+    P = W.empty_params(n)
+    W.fill_fp_airframe(P, np.arange(n), np.full(n, W.MASS), np.tile(W.INERTIA, (n, 1)))
+    if edit:
+        edit(P)
+    return O.Batch(np.ones(n, np.int64), np.zeros(n), P, control, integrator, dt, renorm), P
+
+
+def id_batch(n=1, integrator=O.RK4, dt=0.002, gain=None, tau=None, edit=None):
+    P = W.empty_params(n)
+    W.fill_id_model(P, np.arange(n), np.tile(W.ID_GAIN if gain is None else gain, (n, 1)),
+                    np.tile(W.ID_TAU if tau is None else tau, (n, 1)))
+    if edit:
+        edit(P)
+    return O.Batch(np.ones(n, np.int64), np.ones(n), P, O.CTRL_ATT_PID, integrator, dt), P
+
+
+def run(b, x, u, n):
+    with torch.no_grad():
+        for _ in range(n):
+            x = b.step(x, u)
+    return x
+
+
+def unit_quats(rng, n):
+    q = rng.normal(size=(4, n))
+    return q / np.linalg.norm(q, axis=0)
+
+
+# ---- gravity, translation, integrator plumbing -------------------------------------
+
+@pytest.mark.parametrize("integ", [O.RK4, O.EULER])
+def test_free_fall_first_principles(integ):
+    """Zero rotor speed and command, k0 = 0: no thrust, only gravity. RK4 is exact
+    on the quadratic; explicit Euler has the closed-form lag g t dt / 2."""
+    rng = np.random.default_rng(0)
+    dt, n = 0.002, 400
+    b, _ = fp_batch(3, integrator=integ, dt=dt)
+    x = torch.zeros(17, 3, dtype=F64)
+    x[0:3] = torch.as_tensor(rng.uniform(-1, 1, (3, 3)))
+    x[3:7] = torch.as_tensor(unit_quats(rng, 3))
+    x[7:10] = torch.as_tensor(rng.normal(0, 1, (3, 3)))
+    y = run(b, x, torch.zeros(4, 3, dtype=F64), n)
+    t = n * dt
+    expect = x[0:3] + x[7:10] * t
+    expect[2] -= 0.5 * W.GRAVITY * t * t
+    if integ == O.EULER:
+        expect[2] += 0.5 * W.GRAVITY * t * dt
+    assert torch.allclose(y[0:3], expect, rtol=0, atol=1e-12)
+    assert torch.allclose(y[7:10], x[7:10] - torch.tensor([0, 0, W.GRAVITY * t], dtype=F64)[:, None], atol=1e-12)
+
+
+@pytest.mark.parametrize("integ", [O.RK4, O.EULER])
+def test_free_fall_identified(integ):
+    dt, n = 0.002, 300
+    b, _ = id_batch(2, integrator=integ, dt=dt)
+    x = torch.zeros(13, 2, dtype=F64)
+    x[3:6] = torch.tensor([[0.1, -0.2], [0.05, 0.1], [0.3, -0.4]], dtype=F64)
+    x[6:9] = torch.tensor([[1.0, 0.0], [0.0, -2.0], [0.5, 0.0]], dtype=F64)
+    u = torch.zeros(4, 2, dtype=F64)
+    y = run(b, x, u, n)
+    t = n * dt
+    expect = x[0:3] + x[6:9] * t
+    expect[2] -= 0.5 * W.GRAVITY * t * t
+    if integ == O.EULER:
+        expect[2] += 0.5 * W.GRAVITY * t * dt
+    assert torch.allclose(y[0:3], expect, atol=1e-12)
+
+
+# ---- hover: thrust curve, mixing symmetry, gravity sign -------------------------------
+
+def test_hover_first_principles_rotor():
+    b, P = fp_batch(2)
+    wh = math.sqrt(W.MASS * W.GRAVITY / (4 * W.K_THRUST))
+    x = torch.zeros(17, 2, dtype=F64)
+    x[0:3] = torch.tensor([[0.3, -1.0], [0.2, 0.0], [1.0, 2.0]], dtype=F64)
+    x[6] = 1.0
+    x[13:17] = wh
+    y = run(b, x, torch.full((4, 2), wh, dtype=F64), 1000)
+    assert torch.allclose(y, x, rtol=0, atol=1e-9 * wh)
+    assert torch.allclose(y[0:13], x[0:13], rtol=0, atol=1e-12)
+
+
+def test_hover_first_principles_pid():
+    """Zero attitude error and thrust command m g: integrators stay at zero, every
+    rotor is commanded the hover speed and the state does not move."""
+    b, P = fp_batch(2, control=O.CTRL_ATT_PID)
+    wh = math.sqrt(W.MASS * W.GRAVITY / (4 * W.K_THRUST))
+    x = torch.zeros(25, 2, dtype=F64)
+    x[6] = 1.0
+    x[13:17] = wh
+    u = torch.tensor([[0.0] * 2, [0.0] * 2, [0.0] * 2, [W.MASS * W.GRAVITY] * 2], dtype=F64)
+    y = run(b, x, u, 1000)
+    assert torch.allclose(y[0:13], x[0:13], atol=1e-11)
+    assert torch.allclose(y[13:17], x[13:17], rtol=1e-12)
+    assert torch.allclose(y[17:25], x[17:25], atol=1e-12)
+
+
+def test_hover_identified():
+    b, P = id_batch(2)
+    fh = W.MASS * W.GRAVITY / W.ID_CF
+    x = torch.zeros(13, 2, dtype=F64)
+    x[12] = fh
+    u = torch.tensor([[0.0] * 2] * 3 + [[fh] * 2], dtype=F64)
+    y = run(b, x, u, 1000)
+    assert torch.allclose(y, x, atol=1e-12)
+
+
+# ---- rotor dynamics --------------------------------------------------------------------
+
+@pytest.mark.parametrize("integ", [O.RK4, O.EULER])
+def test_rotor_discrete_closed_form_both_branches(integ):
+    """Linear rotor law: Omega_n - Omega_c = (Omega_0 - Omega_c) P(c dt)^n with
+    P(z) = 1 - z + z^2/2 - z^3/6 + z^4/24 (RK4) or 1 - z (Euler). Distinct
+    acceleration and deceleration coefficients pin the branch selection."""
+    cv_up, cv_dn, dt, n = 40.0, 15.0, 0.002, 200
+
+    def edit(P):
+        P["motor_up"][:] = (cv_up, 0.0)
+        P["motor_down"][:] = (cv_dn, 0.0)
+
+    b, _ = fp_batch(1, integrator=integ, dt=dt, edit=edit)
+    x = torch.zeros(17, 1, dtype=F64)
+    x[6] = 1.0
+    x[13:17, 0] = torch.tensor([10000.0, 20000.0, 12000.0, 18000.0], dtype=F64)
+    cmd = torch.tensor([[15000.0], [15000.0], [16000.0], [16000.0]], dtype=F64)
+    y = run(b, x, cmd, n)
+
+    def amp(z):
+        return 1 - z + z * z / 2 - z ** 3 / 6 + z ** 4 / 24 if integ == O.RK4 else 1 - z
+
+    for i in range(4):
+        c = cv_up if cmd[i, 0] >= x[13 + i, 0] else cv_dn
+        expect = cmd[i, 0] + (x[13 + i, 0] - cmd[i, 0]) * amp(c * dt) ** n
+        assert abs(float(y[13 + i, 0] - expect)) < 1e-9
+
+
+def test_rotor_quadratic_bernoulli():
+    """With c_d != 0 the error e = Omega_c - Omega obeys the Bernoulli equation
+    e' = -a e + c_d e^2 (a = c_v + 2 c_d Omega_c), solved in closed form; RK4
+    converges to it at fourth order."""
+    cv, cd = 20.0, 2e-3
+    wc, w0, T = 15000.0, 9000.0, 0.1
+
+    def edit(P):
+        P["motor_up"][:] = (cv, cd)
+        P["motor_down"][:] = (cv, cd)
+
+    a = cv + 2 * cd * wc
+    e0 = wc - w0
+    e_exact = a * e0 * math.exp(-a * T) / (a - cd * e0 * (1 - math.exp(-a * T)))
+    errs = []
+    for dt in (2e-3, 1e-3, 5e-4):
+        b, _ = fp_batch(1, dt=dt, edit=edit)
+        x = torch.zeros(17, 1, dtype=F64)
+        x[6] = 1.0
+        x[13:17] = w0
+        y = run(b, x, torch.full((4, 1), wc, dtype=F64), int(round(T / dt)))
+        errs.append(abs(float(wc - y[13, 0]) - e_exact))
+    assert errs[0] < 1e-2 * e0 * 1e-3
+    assert 12 < errs[0] / errs[1] < 20 and 12 < errs[1] / errs[2] < 20
+
+
+# ---- quaternion kinematics ---------------------------------------------------------------
+
+def _spin_batch(integ, dt, renorm):
+    def edit(P):
+        P["J"][:] = (2e-5, 2e-5, 2e-5)       # isotropic: w x J w = 0, w stays constant
+    return fp_batch(1, integrator=integ, dt=dt, renorm=renorm, edit=edit)[0]
+
+
+@pytest.mark.parametrize("integ", [O.RK4, O.EULER])
+def test_quaternion_norm_closed_form_without_renormalisation(integ):
+    """For constant w, q' = 1/2 q (x) [w,0] is linear with a skew generator; the
+    RK4 map scales |q|^2 by 1 - th^6/72 + th^8/576 per step, Euler by 1 + th^2,
+    th = |w| dt / 2."""
+    dt, n = 0.01, 100
+    w = np.array([20.0, -10.0, 25.0])
+    b = _spin_batch(integ, dt, renorm=0)
+    x = torch.zeros(17, 1, dtype=F64)
+    x[3:7, 0] = torch.as_tensor(unit_quats(np.random.default_rng(1), 1)[:, 0])
+    x[10:13, 0] = torch.as_tensor(w)
+    y = run(b, x, torch.zeros(4, 1, dtype=F64), n)
+    th = np.linalg.norm(w) * dt / 2
+    fac = (1 - th ** 6 / 72 + th ** 8 / 576) if integ == O.RK4 else (1 + th * th)
+    assert abs(float((y[3:7, 0] ** 2).sum()) - fac ** n) < 1e-12 * fac ** n
+
+
+def test_quaternion_constant_rate_matches_scipy():
+    """With renormalisation, integrating body rate w from q0 gives
+    q0 (x) exp(w t / 2) -- right multiplication, scalar last -- compared with
+    SciPy's Rotation composition; also checks |q| = 1."""
+    dt, n = 0.002, 500
+    rng = np.random.default_rng(2)
+    b = _spin_batch(O.RK4, dt, renorm=1)
+    for _ in range(3):
+        q0 = unit_quats(rng, 1)[:, 0]
+        w = rng.normal(0, 3, 3)
+        x = torch.zeros(17, 1, dtype=F64)
+        x[3:7, 0] = torch.as_tensor(q0)
+        x[10:13, 0] = torch.as_tensor(w)
+        y = run(b, x, torch.zeros(4, 1, dtype=F64), n)[3:7, 0].numpy()
+        ref = (Rotation.from_quat(q0) * Rotation.from_rotvec(w * n * dt)).as_quat()
+        if np.dot(ref, y) < 0:
+            ref = -ref
+        assert np.abs(y - ref).max() < 1e-10
+        assert abs(np.linalg.norm(y) - 1) < 1e-14
+
+
+def test_rotation_helpers_match_scipy():
+    rng = np.random.default_rng(3)
+    q = unit_quats(rng, 50)
+    Rz = Rotation.from_quat(q.T).apply([0.0, 0.0, 1.0]).T
+    assert np.allclose(O.body_z_in_world(torch.as_tensor(q)).numpy(), Rz, atol=1e-14)
+    roll, pitch = O.roll_pitch_from_quat(torch.as_tensor(q))
+    eul = Rotation.from_quat(q.T).as_euler("ZYX")         # yaw, pitch, roll
+    assert np.allclose(roll.numpy(), eul[:, 2], atol=1e-12)
+    assert np.allclose(pitch.numpy(), eul[:, 1], atol=1e-12)
+    psi = rng.uniform(-1, 1, (3, 50))
+    Rp = Rotation.from_euler("ZYX", psi[::-1].T).apply([0.0, 0.0, 1.0]).T
+    assert np.allclose(O.euler_zyx_body_z(torch.as_tensor(psi)).numpy(), Rp, atol=1e-14)
+    a, bq = unit_quats(rng, 20), unit_quats(rng, 20)
+    ref = (Rotation.from_quat(a.T) * Rotation.from_quat(bq.T)).as_quat().T
+    got = O.quat_mul(torch.as_tensor(a), torch.as_tensor(bq)).numpy()
+    sign = np.sign((ref * got).sum(0))
+    assert np.allclose(got, ref * sign, atol=1e-14)
+
+
+# ---- Euler's rigid-body equations ------------------------------------------------------------
+
+def test_torque_free_axisymmetric_precession():
+    """J_x = J_y: w_z constant and (w_x + i w_y) rotates at (J_z - J_x) w_z / J_x;
+    the RK4 phase error against that closed form shrinks at fourth order."""
+    Jx, Jz = W.INERTIA[0], W.INERTIA[2]
+    w0 = np.array([3.0, -2.0, 40.0])
+    lam = (Jz - Jx) * w0[2] / Jx
+    errs = []
+    for dt in (2e-3, 1e-3):
+        n = int(round(1.0 / dt))
+        b, P = fp_batch(1, dt=dt)
+        x = torch.zeros(17, 1, dtype=F64)
+        x[6] = 1.0
+        x[10:13, 0] = torch.as_tensor(w0)
+        y = run(b, x, torch.zeros(4, 1, dtype=F64), n)[10:13, 0].numpy()
+        c = (w0[0] + 1j * w0[1]) * np.exp(1j * lam * n * dt)
+        assert abs(y[2] - w0[2]) < 1e-12
+        errs.append(abs(complex(y[0], y[1]) - c))
+    assert errs[1] < 1e-6
+    assert 13 < errs[0] / errs[1] < 19, errs
+
+
+def test_torque_free_triaxial_conservation():
+    """Triaxial J: kinetic energy, |J w| and the world-frame angular momentum
+    R(q) J w are invariants; their RK4 drift shrinks at fourth order."""
+    def edit(P):
+        P["J"][:] = (1.3e-5, 1.55e-5, 2.3e-5)
+    J = np.array([1.3e-5, 1.55e-5, 2.3e-5])
+    w0 = np.array([8.0, -12.0, 5.0])
+    q0 = unit_quats(np.random.default_rng(4), 1)[:, 0]
+    drifts = []
+    for dt in (4e-3, 2e-3):
+        b, _ = fp_batch(1, dt=dt, edit=edit)
+        x = torch.zeros(17, 1, dtype=F64)
+        x[3:7, 0] = torch.as_tensor(q0)
+        x[10:13, 0] = torch.as_tensor(w0)
+        y = run(b, x, torch.zeros(4, 1, dtype=F64), int(round(1.0 / dt)))
+        w, q = y[10:13, 0].numpy(), y[3:7, 0].numpy()
+        E0, E = 0.5 * (J * w0 * w0).sum(), 0.5 * (J * w * w).sum()
+        L0 = Rotation.from_quat(q0).apply(J * w0)
+        L = Rotation.from_quat(q).apply(J * w)
+        assert abs(E - E0) < 1e-6 * E0
+        assert abs(np.linalg.norm(J * w) - np.linalg.norm(J * w0)) < 1e-6 * np.linalg.norm(J * w0)
+        assert np.abs(L - L0).max() < 1e-6 * np.linalg.norm(L0)
+        drifts.append(np.abs(L - L0).max())
+    assert 10 < drifts[0] / drifts[1] < 24
+
+
+# ---- integrator order ------------------------------------------------------------------------
+
+@pytest.mark.parametrize("integ,ratio", [(O.RK4, 16.0), (O.EULER, 2.0)])
+def test_convergence_order(integ, ratio):
+    """Held rotor commands above the initial speeds (no branch change), tilted
+    and spinning: error at T against a dt/64 RK4 reference halves like dt^order."""
+    T, dt0 = 0.2, 4e-3
+    x = torch.zeros(17, 1, dtype=F64)
+    x[3:7, 0] = torch.tensor([0.1, -0.2, 0.05, 0.97], dtype=F64) / math.sqrt(0.01 + 0.04 + 0.0025 + 0.97 ** 2)
+    x[7:10, 0] = torch.tensor([0.5, -0.3, 0.2], dtype=F64)
+    x[10:13, 0] = torch.tensor([2.0, -1.0, 3.0], dtype=F64)
+    x[13:17, 0] = torch.tensor([13000.0, 14000.0, 13500.0, 14200.0], dtype=F64)
+    cmd = torch.tensor([[15500.0], [15000.0], [16000.0], [15200.0]], dtype=F64)
+    bref, _ = fp_batch(1, integrator=O.RK4, dt=dt0 / 64)
+    ref = run(bref, x, cmd, int(round(T / (dt0 / 64))))
+    errs = []
+    for k in range(3):
+        dt = dt0 / 2 ** k
+        b, _ = fp_batch(1, integrator=integ, dt=dt)
+        y = run(b, x, cmd, int(round(T / dt)))
+        errs.append(float((y[0:13] - ref[0:13]).abs().max()))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 0.75 * ratio < r1 < 1.3 * ratio and 0.75 * ratio < r2 < 1.3 * ratio, errs
+
+
+# ---- identified model -----------------------------------------------------------------------
+
+def test_identified_attitude_lti_discrete_closed_form():
+    """Per axis z = [Psi, Psi'] obeys z' = A z + b Psi_c with A = [[0,1],[c1,c2]];
+    RK4 on an affine system is exactly z+ = R(hA) z + h S(hA) b Psi_c with
+    R(X) = I+X+X^2/2+X^3/6+X^4/24, S(X) = I+X/2+X^2/6+X^3/24. The thrust state
+    follows f_c + (f0 - f_c) P(c_tau dt)^n; the continuous solution (matrix
+    exponential) is approached at O(dt^4); steady state is k Psi_c."""
+    dt, n = 0.002, 400
+    gain, tau = np.array([1.1, 0.9, 1.2]), np.array([0.07, 0.05, 0.11])
+    b, P = id_batch(1, dt=dt, gain=gain, tau=tau)
+    x = torch.zeros(13, 1, dtype=F64)
+    x[3:6, 0] = torch.tensor([0.05, -0.1, 0.2], dtype=F64)
+    x[9:12, 0] = torch.tensor([0.3, 0.0, -0.5], dtype=F64)
+    x[12, 0] = 0.2
+    u = torch.tensor([[0.15], [-0.05], [0.4], [0.3]], dtype=F64)
+    y = run(b, x, u, n)
+    I2 = np.eye(2)
+    for ax in range(3):
+        c1, c2, c3 = P["c_psi1"][0, ax], P["c_psi2"][0, ax], P["c_psi3"][0, ax]
+        A = np.array([[0.0, 1.0], [c1, c2]])
+        X = dt * A
+        R = I2 + X + X @ X / 2 + X @ X @ X / 6 + X @ X @ X @ X / 24
+        S = I2 + X / 2 + X @ X / 6 + X @ X @ X / 24
+        bvec = np.array([0.0, c3 * float(u[ax, 0])])
+        z = np.array([float(x[3 + ax, 0]), float(x[9 + ax, 0])])
+        for _ in range(n):
+            z = R @ z + dt * S @ bvec
+        assert abs(z[0] - float(y[3 + ax, 0])) < 1e-12 and abs(z[1] - float(y[9 + ax, 0])) < 1e-11
+        # continuous solution (augmented matrix exponential)
+        Aug = np.zeros((3, 3))
+        Aug[0:2, 0:2] = A
+        Aug[0:2, 2] = bvec
+        zc = (expm(Aug * n * dt) @ np.array([float(x[3 + ax, 0]), float(x[9 + ax, 0]), 1.0]))[0:2]
+        assert abs(zc[0] - z[0]) < 1e-7
+    ct = P["c_tau"][0, 0]
+    zt = ct * dt
+    amp = 1 - zt + zt ** 2 / 2 - zt ** 3 / 6 + zt ** 4 / 24
+    assert abs(float(y[12, 0]) - (0.3 + (0.2 - 0.3) * amp ** n)) < 1e-12
+    # steady state: Psi -> k Psi_c
+    y2 = run(b, x, u, 5000)
+    assert np.allclose(y2[3:6, 0].numpy(), gain * u[0:3, 0].numpy(), atol=1e-9)
+
+
+# ---- symmetries --------------------------------------------------------------------------
+
+def _yaw_quat(beta):
+    return torch.tensor([0.0, 0.0, math.sin(beta / 2), math.cos(beta / 2)], dtype=F64)
+
+
+def _rotz(beta):
+    c, s = math.cos(beta), math.sin(beta)
+    return torch.tensor([[c, -s, 0], [s, c, 0], [0, 0, 1]], dtype=F64)
+
+
+@pytest.mark.parametrize("control", [O.CTRL_ROTOR, O.CTRL_ATT_PID])
+def test_yaw_equivariance_first_principles(control):
+    """Rotating the initial position, velocity and attitude about world z rotates
+    the whole trajectory (gravity is along z; body quantities are unchanged)."""
+    rng = np.random.default_rng(5)
+    beta = 0.7
+    S = 25 if control == O.CTRL_ATT_PID else 17
+    b, _ = fp_batch(2, control=control)
+    wh = math.sqrt(W.MASS * W.GRAVITY / (4 * W.K_THRUST))
+    x = torch.zeros(S, 2, dtype=F64)
+    x[0:3] = torch.as_tensor(rng.normal(size=(3, 2)))
+    x[3:7] = torch.as_tensor(unit_quats(rng, 2))
+    x[7:10] = torch.as_tensor(rng.normal(size=(3, 2)))
+    x[10:13] = torch.as_tensor(rng.normal(0, 0.5, size=(3, 2)))
+    x[13:17] = wh
+    if control == O.CTRL_ATT_PID:
+        x[22:25] = x[10:13]
+        u = torch.tensor([[0.1, -0.2], [0.05, 0.2], [0.3, -0.1], [0.3, 0.25]], dtype=F64)
+    else:
+        u = torch.as_tensor(wh * (1 + 0.05 * rng.normal(size=(4, 2))))
+    Rz = _rotz(beta)
+    xr = x.clone()
+    xr[0:3] = Rz @ x[0:3]
+    xr[7:10] = Rz @ x[7:10]
+    xr[3:7] = O.quat_mul(_yaw_quat(beta)[:, None].expand(4, 2), x[3:7])
+    y = run(b, x, u, 300)
+    yr = run(b, xr, u, 300)
+    assert torch.allclose(yr[0:3], Rz @ y[0:3], atol=1e-10)
+    assert torch.allclose(yr[7:10], Rz @ y[7:10], atol=1e-10)
+    assert torch.allclose(yr[10:], y[10:], atol=1e-9 * wh)
+    qy = O.quat_mul(_yaw_quat(beta)[:, None].expand(4, 2), y[3:7])
+    assert torch.allclose(yr[3:7], qy, atol=1e-10)
+
+
+def test_yaw_equivariance_and_translation_identified():
+    b, _ = id_batch(1)
+    beta = -0.9
+    x = torch.zeros(13, 1, dtype=F64)
+    x[0:3, 0] = torch.tensor([1.0, 2.0, 3.0], dtype=F64)
+    x[3:6, 0] = torch.tensor([0.1, -0.05, 0.3], dtype=F64)
+    x[6:9, 0] = torch.tensor([0.5, -1.0, 0.2], dtype=F64)
+    x[12, 0] = 0.3
+    u = torch.tensor([[0.05], [0.1], [0.2], [0.28]], dtype=F64)
+    y = run(b, x, u, 400)
+    xr, ur = x.clone(), u.clone()
+    xr[0:3] = _rotz(beta) @ x[0:3] + torch.tensor([[5.0], [-3.0], [1.0]], dtype=F64)
+    xr[6:9] = _rotz(beta) @ x[6:9]
+    xr[5] += beta
+    ur[2] += beta          # yaw is commanded as an absolute angle (DC gain 1 here)
+    yr = run(b, xr, ur, 400)
+    assert torch.allclose(yr[0:3], _rotz(beta) @ y[0:3] + torch.tensor([[5.0], [-3.0], [1.0]], dtype=F64), atol=1e-10)
+    assert torch.allclose(yr[6:9], _rotz(beta) @ y[6:9], atol=1e-10)
+
+
+# ---- mixing and controller -------------------------------------------------------------------
+
+def test_single_rotor_torque_matches_cross_product():
+    """Torque of one rotor's thrust equals r_i x (f e_z) for the x-airframe motor
+    positions M1(+a,-a) M2(-a,-a) M3(-a,+a) M4(+a,+a); the reaction torque about
+    z follows the spin signs -,+,-,+ at the torque/thrust ratio."""
+    _, P = fp_batch(1)
+    Pd = O.per_drone_params(P, [1])
+    a = W.ARM / math.sqrt(2)
+    pos = np.array([[a, -a, 0], [-a, -a, 0], [-a, a, 0], [a, a, 0]])
+    for i in range(4):
+        rot = torch.zeros(4, 1, dtype=F64)
+        rot[i] = 15000.0
+        thrust, torque = O.rotor_wrench(rot, Pd)
+        f = W.K_THRUST * 15000.0 ** 2
+        assert abs(float(thrust[0]) - f) < 1e-15
+        expect = np.cross(pos[i], [0, 0, f])
+        assert np.allclose(torque[0:2, 0].numpy(), expect[0:2], atol=1e-18)
+        assert abs(float(torque[2, 0]) - (-1) ** (i + 1) * W.TORQUE_RATIO * f) < 1e-18
+
+
+def test_allocation_inverts_mixing():
+    _, P = fp_batch(1)
+    a = W.ARM / math.sqrt(2)
+    mix = np.stack([np.ones(4), P["mix_tx"][0], P["mix_ty"][0], W.TORQUE_RATIO * P["mix_yaw"][0]])
+    assert np.allclose(P["alloc"][0].reshape(4, 4) @ mix, np.eye(4), atol=1e-12)
+    assert np.allclose(mix[1], a * np.array([-1, -1, 1, 1]))
+
+
+def test_pid_closed_loop_linearisation_is_stable():
+    """Jacobian of the closed-loop discrete map at hover: every mode that the loop
+    controls lies strictly inside the unit circle; the only unit modes are the
+    uncontrolled ones (position 3, velocity 3, yaw angle 1)."""
+    b, _ = fp_batch(1, control=O.CTRL_ATT_PID)
+    wh = math.sqrt(W.MASS * W.GRAVITY / (4 * W.K_THRUST))
+    x = torch.zeros(25, 1, dtype=F64)
+    x[6] = 1.0
+    x[13:17] = wh
+    u = torch.tensor([[0.0], [0.0], [0.0], [W.MASS * W.GRAVITY]], dtype=F64)
+    scale = torch.ones(25, dtype=F64)
+    scale[13:17] = wh
+    Jm = torch.zeros(25, 25, dtype=F64)
+    for j in range(25):
+        h = 1e-6 * scale[j]
+        xp, xm = x.clone(), x.clone()
+        xp[j] += h
+        xm[j] -= h
+        Jm[:, j] = (b.step(xp, u) - b.step(xm, u))[:, 0] / (2 * h)
+    # quaternion: drop w (renormalisation removes the radial direction)
+    keep = [i for i in range(25) if i != 6]
+    ev = np.linalg.eigvals(Jm[keep][:, keep].numpy())
+    mag = np.sort(np.abs(ev))[::-1]
+    assert mag[0] < 1 + 1e-7
+    assert np.sum(mag > 1 - 1e-7) == 7
+    assert mag[7] < 1 - 1e-5
+
+
+def test_pid_tracks_held_attitude():
+    b, _ = fp_batch(1, control=O.CTRL_ATT_PID)
+    wh = math.sqrt(W.MASS * W.GRAVITY / (4 * W.K_THRUST))
+    x = torch.zeros(25, 1, dtype=F64)
+    x[6] = 1.0
+    x[13:17] = wh
+    u = torch.tensor([[0.2], [-0.1], [0.3], [W.MASS * W.GRAVITY]], dtype=F64)
+    y = run(b, x, u, 15000)
+    roll, pitch = O.roll_pitch_from_quat(y[3:7])
+    assert abs(float(roll[0]) - 0.2) < 2e-3 and abs(float(pitch[0]) + 0.1) < 2e-3
+    assert abs(float(y[12, 0]) - 0.3) < 2e-3
+
+
+# ---- gradients -------------------------------------------------------------------------------
+
+def _fd_check(w, n_dirs=4, h=1e-4, seed=0):
+    """Central differences of the FP64 oracle loss along random directions of the
+    per-step commands, the initial state and the gain vs the autograd gradient."""
+    b = O.Batch.from_workload(w)
+    kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u,
+              ref_offset=None if w.ref_offset is None else O.t64(w.ref_offset))
+    x0, cmds = O.t64(w.x0), O.t64(w.cmds)
+    gain = None if w.gain is None else O.t64(w.gain)
+    g = O.rollout_grad(b, x0, cmds, w.steps, gain=gain, gain_index=w.gain_index, dloss=w.dloss, **kw)
+    seed_w = O.t64(w.dloss)
+
+    def L(x0_, c_, g_):
+        with torch.no_grad():
+            out = O.rollout(b, x0_, c_, w.steps, gain=g_, gain_index=w.gain_index, **kw)
+        return float((seed_w * out["loss"]).sum())
+
+    rng = np.random.default_rng(seed)
+    scale_x = torch.ones_like(x0)
+    if x0.shape[0] >= 17:
+        scale_x[13:17] = 1e3
+    for _ in range(n_dirs):
+        dx = torch.as_tensor(rng.normal(size=x0.shape)) * scale_x
+        if x0.shape[0] >= 17:
+            dx[3:7] = 0          # keep the attitude direction out (renormalised)
+        dc = torch.as_tensor(rng.normal(size=cmds.shape))
+        if x0.shape[0] >= 17 and w.control == O.CTRL_ROTOR:
+            dc *= 1e3
+        dg = None if gain is None else torch.as_tensor(rng.normal(size=gain.shape))
+        fp = L(x0 + h * dx, cmds + h * dc, None if gain is None else gain + h * dg)
+        fm = L(x0 - h * dx, cmds - h * dc, None if gain is None else gain - h * dg)
+        fd = (fp - fm) / (2 * h)
+        ad = float((g["g_x0"] * dx).sum() + (g["g_cmds"] * dc).sum())
+        if gain is not None:
+            ad += float((g["g_gain"] * dg).sum())
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-3), (fd, ad)
+    return g
+
+
+def test_gradient_fd_identified_with_feedback():
+    w = W.config4(seed=11, n_worlds=3, steps=40, gain_std=0.05)
+    _fd_check(w)
+
+
+def test_gradient_fd_first_principles_pid():
+    w = W.config5_adjoint(seed=12, n_worlds=6, n_subset=4, steps=30, n_max=3)
+    _fd_check(w)
+
+
+def test_gradient_fd_first_principles_rotor():
+    w = W.config1(seed=13, n_worlds=2, steps=30)
+    w.ref_offset = w.x0[0:3].copy()
+    w.dloss = np.ones(2, np.float32)
+    w.w_u = 1e-9
+    _fd_check(w, h=1e-3)
+
+
+def test_gain_gradient_identity():
+    """u_t = ubar_t + G e_t gives dL/dG = sum_t (dL/du_t) e_t^T exactly."""
+    w = W.config4(seed=14, n_worlds=4, steps=25, gain_std=0.05)
+    b = O.Batch.from_workload(w)
+    kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u)
+    g = O.rollout_grad(b, w.x0, w.cmds, w.steps, gain=O.t64(w.gain), dloss=w.dloss, **kw)
+    out = O.rollout(b, O.t64(w.x0), O.t64(w.cmds), w.steps, gain=O.t64(w.gain), keep_traj=True, **kw)
+    traj = out["traj"].detach()
+    acc = torch.zeros(4, 13, dtype=F64)
+    for n in range(w.steps):
+        p, v = b.figure_eight(n * b.dt, w.ref_amp, w.ref_period, None)
+        e = traj[n, 0:13] - b.reference_state(p, v)
+        acc += g["g_cmds"][n] @ e.T
+    assert torch.allclose(acc, g["g_gain"][0], rtol=1e-10, atol=1e-14)

@@ -1,0 +1,410 @@
+"""Seeded synthetic workloads for the batched drone step.
+
+This module only draws random numbers and lays them out. It contains none of the
+simulation arithmetic (no derivative, controller, integrator or loss); both the
+FP64 oracle and the GPU path consume what it returns.
+
+Every array is rounded to float32 before it is handed out, so both sides start
+from the same FP32 values (the oracle promotes them to FP64).
+
+Shapes follow the structure-of-arrays convention of the C interface:
+state ``[S][D]``, held commands ``[4][D]``, per-step commands ``[T][4][D]``,
+per-world parameters as named ``[M, k]`` arrays. ``D`` is the total drone count,
+worlds are concatenated in world order.
+
+Random streams are ``numpy.random.Generator(numpy.random.Philox(seed))``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, Optional
+
+import numpy as np
+
+# ---- enum values of the C interface (include/cfsim.h) -----------------------
+MODEL_FP = 0          # first-principles rigid body + rotor dynamics
+MODEL_ID = 1          # identified (abstracted) attitude-command model
+CTRL_ROTOR = 0        # first-principles worlds take rotor-speed commands
+CTRL_ATT_PID = 1      # first-principles worlds take [roll, pitch, yaw-rate, thrust]
+INTEG_EULER = 0
+INTEG_RK4 = 1
+
+S_FP_ROTOR = 17       # p(3) q(4, scalar last) v(3) w_body(3) Omega(4)
+S_FP_PID = 25         # + angle integrals(2) rate integrals(3) previous body rate(3)
+S_ID = 13             # p(3) Psi(3) v(3) dPsi(3) f_sum(1)
+
+# Named per-world parameter fields and their widths, in record order.
+PARAM_FIELDS = (
+    ("mass", 1), ("gravity", 1), ("J", 3),
+    ("thrust_poly", 3), ("torque_poly", 3),
+    ("mix_tx", 4), ("mix_ty", 4), ("mix_yaw", 4),
+    ("motor_up", 2), ("motor_down", 2),
+    ("Jp", 1), ("drag", 3),
+    ("ang_kp", 2), ("ang_ki", 2), ("rate_kp", 3), ("rate_ki", 3), ("rate_kd", 3),
+    ("J_ctrl", 3), ("f_max", 1), ("alloc", 16),
+    ("c_f", 1), ("c_tau", 1), ("c_psi1", 3), ("c_psi2", 3), ("c_psi3", 3),
+)
+
+# ---- nominal Crazyflie-class airframe (synthetic values) --------------------
+MASS = 0.027
+GRAVITY = 9.81
+INERTIA = (1.4e-5, 1.4e-5, 2.2e-5)
+K_THRUST = 3e-10            # f = K_THRUST * Omega^2
+TORQUE_RATIO = 0.006        # rotor drag torque = TORQUE_RATIO * f
+ARM = 0.046                 # motor distance from the centre
+MOTOR_TAU = 0.03            # rotor-speed time constant [s]
+THRUST_TO_WEIGHT = 1.9
+# attitude PID gains (own design, normalised by the nominal inertia)
+ANG_KP, ANG_KI = 6.0, 1.0
+RATE_KP, RATE_KI, RATE_KD = 17.0, 5.0, 0.1
+# identified model nominal response
+ID_TAU = (0.06, 0.06, 0.12)
+ID_GAIN = (1.0, 1.0, 1.0)
+ID_CF = 1.0
+ID_CTAU = 1.0 / 0.03
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    n_worlds: int
+    drones_per_world: np.ndarray          # int32 [M]
+    model_per_world: np.ndarray           # uint8 [M]
+    control: int
+    integrator: int
+    dt: float
+    renorm_q: int
+    params: Dict[str, np.ndarray]         # name -> float32 [M, k]
+    x0: np.ndarray                        # float32 [S, D]
+    steps: int
+    cmds: np.ndarray                      # float32 [4, D] (held) or [T, 4, D]
+    gain: Optional[np.ndarray] = None     # float32 [G, 4, 13]
+    gain_index: Optional[np.ndarray] = None   # int32 [M]
+    ref_amp: float = 1.0
+    ref_period: float = 4.0
+    ref_offset: Optional[np.ndarray] = None   # float32 [3, D]
+    w_u: float = 1e-3
+    dloss: Optional[np.ndarray] = None    # float32 [D]
+
+    @property
+    def n_drones_total(self) -> int:
+        return int(self.drones_per_world.sum())
+
+    @property
+    def state_dim(self) -> int:
+        return int(self.x0.shape[0])
+
+    def world_offsets(self) -> np.ndarray:
+        off = np.zeros(self.n_worlds + 1, dtype=np.int64)
+        off[1:] = np.cumsum(self.drones_per_world)
+        return off
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(seed))
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
+
+
+def empty_params(n_worlds: int) -> Dict[str, np.ndarray]:
+    return {name: np.zeros((n_worlds, k), dtype=np.float64) for name, k in PARAM_FIELDS}
+
+
+def fill_fp_airframe(P: Dict[str, np.ndarray], worlds, mass, inertia) -> None:
+    """Crazyflie-class first-principles parameters for the given worlds.
+
+    ``mass`` [n], ``inertia`` [n, 3] are the (possibly perturbed) physical values;
+    the controller keeps the nominal inertia and motor limits.
+    """
+    worlds = np.asarray(worlds)
+    a = ARM / math.sqrt(2.0)
+    P["mass"][worlds, 0] = mass
+    P["gravity"][worlds, 0] = GRAVITY
+    P["J"][worlds] = inertia
+    P["thrust_poly"][worlds] = (0.0, 0.0, K_THRUST)
+    P["torque_poly"][worlds] = (0.0, 0.0, TORQUE_RATIO * K_THRUST)
+    # motors 1..4 at (+a,-a), (-a,-a), (-a,+a), (+a,+a); yaw reaction signs -,+,-,+
+    P["mix_tx"][worlds] = (-a, -a, a, a)
+    P["mix_ty"][worlds] = (-a, a, a, -a)
+    P["mix_yaw"][worlds] = (-1.0, 1.0, -1.0, 1.0)
+    P["motor_up"][worlds] = (1.0 / MOTOR_TAU, 0.0)
+    P["motor_down"][worlds] = (1.0 / MOTOR_TAU, 0.0)
+    P["ang_kp"][worlds] = ANG_KP
+    P["ang_ki"][worlds] = ANG_KI
+    P["rate_kp"][worlds] = RATE_KP
+    P["rate_ki"][worlds] = RATE_KI
+    P["rate_kd"][worlds] = RATE_KD
+    P["J_ctrl"][worlds] = INERTIA
+    P["f_max"][worlds, 0] = THRUST_TO_WEIGHT * MASS * GRAVITY / 4.0
+    # Allocation (controller mixer) of the x airframe: per-motor thrust from
+    # [collective thrust, tau_x, tau_y, tau_z]; row i = motor i.
+    sx = (-1.0, -1.0, 1.0, 1.0)
+    sy = (-1.0, 1.0, 1.0, -1.0)
+    sz = (-1.0, 1.0, -1.0, 1.0)
+    alloc = np.zeros((4, 4))
+    for i in range(4):
+        alloc[i] = (0.25, sx[i] / (4 * a), sy[i] / (4 * a), sz[i] / (4 * TORQUE_RATIO))
+    P["alloc"][worlds] = alloc.reshape(16)
+
+
+def fill_id_model(P: Dict[str, np.ndarray], worlds, gain, tau) -> None:
+    """Identified attitude model with a critically damped second-order response
+    per axis: DC gain ``gain`` [n,3] and time constant ``tau`` [n,3]."""
+    worlds = np.asarray(worlds)
+    P["mass"][worlds, 0] = MASS
+    P["gravity"][worlds, 0] = GRAVITY
+    P["c_f"][worlds, 0] = ID_CF
+    P["c_tau"][worlds, 0] = ID_CTAU
+    P["c_psi1"][worlds] = -1.0 / tau ** 2
+    P["c_psi2"][worlds] = -2.0 / tau
+    P["c_psi3"][worlds] = gain / tau ** 2
+
+
+def hover_speed(mass) -> np.ndarray:
+    return np.sqrt(np.asarray(mass) * GRAVITY / (4.0 * K_THRUST))
+
+
+def _finish_params(P) -> Dict[str, np.ndarray]:
+    return {k: _f32(v) for k, v in P.items()}
+
+
+def _random_attitude(rng, n, max_angle):
+    axis = rng.normal(size=(3, n))
+    axis /= np.linalg.norm(axis, axis=0, keepdims=True)
+    ang = rng.uniform(0.0, max_angle, size=n)
+    return np.concatenate([axis * np.sin(ang / 2), np.cos(ang / 2)[None]], axis=0)
+
+
+def _grid_positions(rng, n, dims=None, spacing=0.3, jitter=0.03):
+    """First ``n`` points of a jittered grid. ``dims`` = (nx, ny, nz) or a cube."""
+    if dims is None:
+        side = max(1, int(math.ceil(round(n ** (1.0 / 3.0), 9))))
+        while side ** 3 < n:
+            side += 1
+        dims = (side, side, side)
+    nx, ny, nz = dims
+    idx = np.arange(n)
+    ix, iy, iz = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    pos = np.stack([ix, iy, iz]).astype(np.float64) * spacing
+    pos += rng.uniform(-jitter, jitter, size=(3, n))
+    return pos
+
+
+# ---- the five workloads ------------------------------------------------------
+
+def config1(seed: int = 1001, n_worlds: int = 16, steps: int = 500,
+            integrator: int = INTEG_RK4, dt: float = 0.002) -> Workload:
+    """Plain forward, first-principles rotor-speed interface, 1 drone per world."""
+    rng = _rng(seed)
+    M = D = n_worlds
+    P = empty_params(M)
+    fill_fp_airframe(P, np.arange(M), np.full(M, MASS), np.tile(INERTIA, (M, 1)))
+    wh = hover_speed(MASS)
+    x0 = np.zeros((S_FP_ROTOR, D))
+    x0[0:3] = rng.uniform(-1.0, 1.0, size=(3, D))
+    x0[7:10] = rng.normal(0.0, 0.1, size=(3, D))
+    x0[3:7] = _random_attitude(rng, D, 0.3)
+    x0[13:17] = wh
+    cmds = wh * (1.0 + 0.05 * rng.normal(size=(steps, 4, D)))
+    return Workload("fp_rotor_open_loop", M, np.ones(M, np.int32),
+                    np.full(M, MODEL_FP, np.uint8), CTRL_ROTOR, integrator,
+                    float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps, _f32(cmds))
+
+
+def _fp_pid_x0(D, mass_per_drone, pos=None):
+    x0 = np.zeros((S_FP_PID, D))
+    if pos is not None:
+        x0[0:3] = pos
+    x0[6] = 1.0
+    x0[13:17] = hover_speed(mass_per_drone)
+    return x0
+
+
+def _attitude_cmds(rng, D):
+    c = np.empty((4, D))
+    c[0:2] = rng.uniform(-0.3, 0.3, size=(2, D))
+    c[2] = rng.uniform(-0.3, 0.3, size=D)
+    c[3] = rng.uniform(0.2, 0.5, size=D)
+    return c
+
+
+def config2(seed: int = 1002, n_worlds: int = 4096, steps: int = 1000,
+            dt: float = 0.002) -> Workload:
+    """Closed loop: attitude commands -> cascaded PID -> mixer -> first-principles model."""
+    rng = _rng(seed)
+    M = D = n_worlds
+    P = empty_params(M)
+    mass = MASS * rng.uniform(0.9, 1.1, size=M)
+    inertia = np.asarray(INERTIA)[None, :] * rng.uniform(0.9, 1.1, size=(M, 3))
+    fill_fp_airframe(P, np.arange(M), mass, inertia)
+    cmds = _attitude_cmds(rng, D)
+    x0 = _fp_pid_x0(D, mass)
+    return Workload("fp_pid_closed_loop", M, np.ones(M, np.int32),
+                    np.full(M, MODEL_FP, np.uint8), CTRL_ATT_PID, INTEG_RK4,
+                    float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps, _f32(cmds))
+
+
+def _id_world_response(rng, n):
+    gain = np.asarray(ID_GAIN)[None, :] * rng.uniform(0.8, 1.2, size=(n, 3))
+    tau = np.asarray(ID_TAU)[None, :] * rng.uniform(0.8, 1.2, size=(n, 3))
+    return gain, tau
+
+
+def _id_cmds(rng, D):
+    c = np.empty((4, D))
+    c[0:3] = rng.uniform(-0.1, 0.1, size=(3, D))
+    c[3] = (MASS * GRAVITY / ID_CF) * rng.uniform(0.95, 1.05, size=D)
+    return c
+
+
+def _id_x0(D, pos):
+    x0 = np.zeros((S_ID, D))
+    x0[0:3] = pos
+    x0[12] = MASS * GRAVITY / ID_CF
+    return x0
+
+
+def config3(seed: int = 1003, n_worlds: int = 64, n_drones: int = 4000,
+            steps: int = 1000, dt: float = 0.002, integrator: int = INTEG_RK4) -> Workload:
+    """Swarm: identified attitude-command model, jittered 20x20x10 grid per world."""
+    rng = _rng(seed)
+    M, N = n_worlds, n_drones
+    D = M * N
+    P = empty_params(M)
+    gain, tau = _id_world_response(rng, M)
+    fill_id_model(P, np.arange(M), gain, tau)
+    dims = (20, 20, 10) if N <= 4000 else None
+    pos = np.concatenate([_grid_positions(rng, N, dims) for _ in range(M)], axis=1)
+    x0 = _id_x0(D, pos)
+    cmds = _id_cmds(rng, D)
+    return Workload("id_swarm", M, np.full(M, N, np.int32),
+                    np.full(M, MODEL_ID, np.uint8), CTRL_ATT_PID, integrator,
+                    float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps, _f32(cmds))
+
+
+def config4(seed: int = 1004, n_worlds: int = 1024, steps: int = 500,
+            dt: float = 0.002, gain_std: float = 0.01) -> Workload:
+    """Differentiable rollout of the identified model with a shared 4x13 feedback gain,
+    tracking a figure-eight (amplitude 1 m, period 4 s)."""
+    rng = _rng(seed)
+    M = D = n_worlds
+    P = empty_params(M)
+    fill_id_model(P, np.arange(M), np.tile(ID_GAIN, (M, 1)), np.tile(ID_TAU, (M, 1)))
+    f_hover = MASS * GRAVITY / ID_CF
+    x0 = _id_x0(D, rng.normal(0.0, 0.05, size=(3, D)))
+    # velocity of the figure-eight at t = 0 is (2*pi*A/P, 2*pi*A/P, 0) = (pi/2, pi/2, 0)
+    x0[6:9] = np.array([math.pi / 2, math.pi / 2, 0.0])[:, None] + rng.normal(0.0, 0.05, size=(3, D))
+    ubar = np.zeros((steps, 4, D))
+    ubar[:, 3] = f_hover
+    ubar += rng.normal(0.0, 0.02, size=ubar.shape)
+    gain = rng.normal(0.0, gain_std, size=(1, 4, 13))
+    return Workload("id_rollout_grad", M, np.ones(M, np.int32),
+                    np.full(M, MODEL_ID, np.uint8), CTRL_ATT_PID, INTEG_RK4,
+                    float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps, _f32(ubar),
+                    gain=_f32(gain), gain_index=None, ref_amp=1.0, ref_period=4.0,
+                    ref_offset=None, w_u=1e-3, dloss=np.ones(D, np.float32))
+
+
+def uneven_counts(rng, n_worlds, n_max=4000):
+    n = np.round(np.exp(rng.uniform(0.0, math.log(n_max), size=n_worlds)))
+    return np.clip(n, 1, n_max).astype(np.int32)
+
+
+def config5(seed: int = 1005, n_worlds: int = 2048, steps: int = 1000, dt: float = 0.002,
+            n_max: int = 4000) -> Workload:
+    """Uneven batch: log-uniform drones per world, half first-principles closed loop,
+    half identified model, held commands."""
+    rng = _rng(seed)
+    M = n_worlds
+    counts = uneven_counts(rng, M, n_max)
+    models = np.zeros(M, np.uint8)
+    models[rng.permutation(M)[: M // 2]] = MODEL_ID
+    fp = np.nonzero(models == MODEL_FP)[0]
+    idw = np.nonzero(models == MODEL_ID)[0]
+    P = empty_params(M)
+    mass = MASS * rng.uniform(0.9, 1.1, size=len(fp))
+    inertia = np.asarray(INERTIA)[None, :] * rng.uniform(0.9, 1.1, size=(len(fp), 3))
+    fill_fp_airframe(P, fp, mass, inertia)
+    gain, tau = _id_world_response(rng, len(idw))
+    fill_id_model(P, idw, gain, tau)
+    D = int(counts.sum())
+    off = np.zeros(M + 1, np.int64)
+    off[1:] = np.cumsum(counts)
+    x0 = np.zeros((S_FP_PID, D))
+    cmds = np.zeros((4, D))
+    world_mass = P["mass"][:, 0]
+    for w in range(M):
+        n = int(counts[w])
+        s = slice(off[w], off[w + 1])
+        pos = _grid_positions(rng, n)
+        if models[w] == MODEL_FP:
+            x0[:, s] = _fp_pid_x0(n, np.full(n, world_mass[w]), pos)
+            cmds[:, s] = _attitude_cmds(rng, n)
+        else:
+            x0[:S_ID, s] = _id_x0(n, pos)
+            cmds[:, s] = _id_cmds(rng, n)
+    return Workload("uneven_mixed", M, counts, models, CTRL_ATT_PID, INTEG_RK4,
+                    float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps, _f32(cmds))
+
+
+def subset(w: Workload, worlds) -> Workload:
+    """The workload restricted to the given worlds (in the given order)."""
+    worlds = np.asarray(worlds)
+    off = w.world_offsets()
+    cols = np.concatenate([np.arange(off[i], off[i + 1]) for i in worlds]) if len(worlds) else np.zeros(0, np.int64)
+    cmds = w.cmds[..., cols]
+    return dataclasses.replace(
+        w, n_worlds=len(worlds), drones_per_world=w.drones_per_world[worlds].copy(),
+        model_per_world=w.model_per_world[worlds].copy(),
+        params={k: v[worlds].copy() for k, v in w.params.items()},
+        x0=np.ascontiguousarray(w.x0[:, cols]), cmds=np.ascontiguousarray(cmds),
+        gain_index=None if w.gain_index is None else w.gain_index[worlds].copy(),
+        ref_offset=None if w.ref_offset is None else np.ascontiguousarray(w.ref_offset[:, cols]),
+        dloss=None if w.dloss is None else w.dloss[cols].copy())
+
+
+def config5_adjoint(seed: int = 1005, n_worlds: int = 2048, n_subset: int = 256,
+                    steps: int = 1000, dt: float = 0.002, n_max: int = 4000,
+                    gain_std: float = 0.01) -> Workload:
+    """The seeded world subset of the uneven batch that is differentiated: per-step
+    commands (hover + noise), per-drone figure-eight offsets at the drones' start
+    positions, one feedback gain per model (index 0 first-principles, 1 identified)."""
+    base = config5(seed, n_worlds, 1, dt, n_max)
+    rng = _rng(seed + 7919)
+    pick = np.sort(rng.permutation(n_worlds)[:n_subset])
+    w = subset(base, pick)
+    D = w.n_drones_total
+    off = w.world_offsets()
+    ubar = np.zeros((steps, 4, D))
+    for i in range(w.n_worlds):
+        s = slice(off[i], off[i + 1])
+        if w.model_per_world[i] == MODEL_FP:
+            ubar[:, 3, s] = float(w.params["mass"][i, 0]) * GRAVITY
+        else:
+            ubar[:, 3, s] = MASS * GRAVITY / ID_CF
+    ubar += rng.normal(0.0, 0.02, size=ubar.shape)
+    gain = rng.normal(0.0, gain_std, size=(2, 4, 13))
+    gidx = np.where(w.model_per_world == MODEL_FP, 0, 1).astype(np.int32)
+    return dataclasses.replace(
+        w, name="uneven_mixed_adjoint", steps=steps, cmds=_f32(ubar), gain=_f32(gain),
+        gain_index=gidx, ref_amp=1.0, ref_period=4.0, ref_offset=_f32(w.x0[0:3]),
+        w_u=1e-3, dloss=np.ones(D, np.float32))
+
+
+def small(cfg: int, seed: int) -> Workload:
+    """Reduced versions of the five workloads that the oracle finishes in seconds but
+    that still span several 64-lane waves and a ragged tail."""
+    if cfg == 1:
+        return config1(seed, n_worlds=16, steps=500)
+    if cfg == 2:
+        return config2(seed, n_worlds=200, steps=1000)
+    if cfg == 3:
+        return config3(seed, n_worlds=3, n_drones=150, steps=1000)
+    if cfg == 4:
+        return config4(seed, n_worlds=100, steps=100)
+    if cfg == 5:
+        return config5(seed, n_worlds=24, steps=300, n_max=120)
+    raise ValueError(cfg)
