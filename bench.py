@@ -1,0 +1,221 @@
+"""Throughput of the batched drone step on one MI355X.
+
+One bench step is one pass of the whole hot path over the uneven mixed batch
+(2048 worlds, log-uniform 1..4000 drones each, half first-principles with the
+attitude PID, half identified model, RK4 at dt = 2 ms):
+  1. masked reset of every world to its initial state;
+  2. 1000 held-command steps of all drones in one launch sequence (fused
+     kernel, per-world tiles or the persistent work queue, autotuned);
+  3. forward rollout (per-step commands, linear feedback, figure-eight
+     tracking loss, checkpoints) and the hand-written adjoint on the seeded
+     256-world subset, 1000 steps.
+value = (D * T + D_sub * T) / wall time of the step (drone-steps/s), inputs
+resident in HBM. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# algorithmic FP32 operations per drone-step (add/sub/mul = 1, FMA = 2, each
+# sqrt/div/sin/cos/atan2/asin = 1), counted from the step's formulas
+FLOPS_PER_DS = {"fp_pid_rk4": 943.0, "fp_rotor_rk4": 802.0, "id_rk4": 317.0}
+SPEC_FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
+SPEC_HBM_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--seed", type=int, default=1005)
+    p.add_argument("--horizon", type=int, default=1000)
+    p.add_argument("--ckpt", type=int, default=50)
+    p.add_argument("--autotune-ms", type=int, default=3000)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-comparators", action="store_true")
+    p.add_argument("--copy-probe", action="store_true", help="also run a 256 MiB device copy (profile scale)")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import workloads as W
+    from paper_2606_01478_amd import binding as B
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    T = args.horizon
+    w = W.config5(seed=args.seed, steps=T)
+    ws = W.config5_adjoint(seed=args.seed, steps=T)
+    D, Ds = w.n_drones_total, ws.n_drones_total
+    t2d = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt)
+
+    sim = B.Sim.from_workload(w)
+    init = t2d(w.x0)
+    state = init.clone()
+    cmd = t2d(w.cmds)
+    mask = torch.ones(w.n_worlds, dtype=torch.uint8, device=dev)
+    sim.autotune(state, cmd, T, args.autotune_ms)
+    cfg = sim.launch_config()
+
+    simA = B.Sim.from_workload(ws)
+    x0s, cmds_s = t2d(ws.x0), t2d(ws.cmds)
+    gain, off = t2d(ws.gain), t2d(ws.ref_offset)
+    obj = B.Sim.objective(gain=gain, ref_amp=ws.ref_amp, ref_period=ws.ref_period, ref_offset=off, w_u=ws.w_u)
+    K = args.ckpt
+    nseg = (T + K - 1) // K
+    ckpt = torch.empty((nseg, simA.S, Ds), device=dev)
+    loss = torch.empty(Ds, device=dev)
+    loss_w = torch.empty(ws.n_worlds, device=dev)
+    dloss = t2d(ws.dloss)
+    g_cmds, g_x0, g_gain = torch.empty_like(cmds_s), torch.empty_like(x0s), torch.empty_like(gain)
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def one_step(record=None):
+        e = [ev() for _ in range(5)]
+        e[0].record()
+        sim.reset(state, init, mask)
+        e[1].record()
+        sim.step_k(state, cmd, T)
+        e[2].record()
+        simA.rollout(x0s, cmds_s, T, obj, K, ckpt=ckpt, loss=loss, loss_world=loss_w)
+        e[3].record()
+        simA.rollout_backward(x0s, cmds_s, T, obj, K, ckpt, dloss=dloss, g_cmds=g_cmds, g_x0=g_x0, g_gain=g_gain)
+        e[4].record()
+        if record is not None:
+            record.append(e)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(recs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if sim.last_error() != 0 or simA.last_error() != 0:
+        raise RuntimeError("device error during the timed region")
+    ph = np.array([[r[i].elapsed_time(r[i + 1]) for i in range(4)] for r in recs])  # ms
+    step_ms = wall * 1e3 / args.steps
+    fwd_ms = float(ph[:, 1].mean())
+    rf_ms, rb_ms = float(ph[:, 2].mean()), float(ph[:, 3].mean())
+
+    # algorithmic work of the dominant kernel (held-command step over the whole batch)
+    world = np.repeat(np.arange(w.n_worlds), w.drones_per_world)
+    n_fp = int((w.model_per_world[world] == W.MODEL_FP).sum())
+    n_id = D - n_fp
+    flops = (n_fp * FLOPS_PER_DS["fp_pid_rk4"] + n_id * FLOPS_PER_DS["id_rk4"]) * T
+    achieved = flops / (fwd_ms * 1e-3) / 1e12
+    value = (D * T + Ds * T) / (step_ms * 1e-3)
+    out = {
+        "metric": "drone-steps/s fwd & fwd+bwd on 1 MI355X vs plain kernel; % of VALU/HBM roofline",
+        "value": value, "unit": "drone-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded Philox, Crazyflie-class parameters)",
+        "config": {"workload": "uneven_mixed_2048w_logu1-4000_T1000_plus_adjoint_256w",
+                   "worlds": w.n_worlds, "drones": D, "horizon": T, "adjoint_worlds": ws.n_worlds,
+                   "adjoint_drones": Ds, "ckpt_every": K, "integrator": "rk4", "dt": w.dt,
+                   "launch": cfg},
+        "fwd_drone_steps_per_s": D * T / (fwd_ms * 1e-3),
+        "fwdbwd_drone_steps_per_s": Ds * T / ((rf_ms + rb_ms) * 1e-3),
+        "phase_ms": {"reset": float(ph[:, 0].mean()), "forward": fwd_ms, "rollout_fwd": rf_ms,
+                     "rollout_bwd": rb_ms, "forward_std": float(ph[:, 1].std())},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": SPEC_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / SPEC_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "kernel": "k_step_wq/k_step_tile (held-command RK4 step, whole batch)",
+                     "flops_per_launch": flops},
+    }
+
+    if not args.no_comparators:
+        # plain single-step kernel over the whole batch (one launch per step)
+        simP = B.Sim.from_workload(w, flags=B.F_PLAIN_KERNEL | B.F_NO_AUTOTUNE_CACHE)
+        xs = init.clone()
+        n_plain = 50
+        simP.step_k(xs, cmd, 5)
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        simP.step_k(xs, cmd, n_plain)
+        b.record()
+        torch.cuda.synchronize()
+        plain_ms = a.elapsed_time(b) / n_plain
+        out["plain_kernel_drone_steps_per_s"] = D / (plain_ms * 1e-3)
+        out["plain_kernel_hbm_gbs"] = D * (2 * 25 * 4 + 16) / (plain_ms * 1e-3) / 1e9
+        # per-world loop of plain launches (one handle per world), a few steps
+        handles = []
+        offs = w.world_offsets()
+        for i in range(w.n_worlds):
+            sub = W.subset(w, [i])
+            handles.append((B.Sim.from_workload(sub, flags=B.F_PLAIN_KERNEL | B.F_NO_AUTOTUNE_CACHE),
+                            state[:, offs[i]:offs[i + 1]].clone(), cmd[:, offs[i]:offs[i + 1]].contiguous()))
+        n_loop = 5
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for h, xs_i, u_i in handles:
+            h.step_k(xs_i, u_i, n_loop)
+        b.record()
+        torch.cuda.synchronize()
+        out["per_world_loop_drone_steps_per_s"] = D * n_loop / (a.elapsed_time(b) * 1e-3)
+        for h, _, _ in handles:
+            h.close()
+
+    if args.copy_probe:
+        src = torch.empty(64 * 1024 * 1024, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, seconds):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
+    every 16th world for as many steps as fit in about ``seconds``."""
+    import torch
+
+    import oracle as O
+    import workloads as W
+    pick = np.arange(0, w.n_worlds, 16)
+    sub = W.subset(w, pick)
+    b = O.Batch.from_workload(sub)
+    x = O.t64(sub.x0)
+    u = O.t64(sub.cmds)
+    threads = torch.get_num_threads()
+    n = 0
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        while time.perf_counter() - t0 < seconds and n < w.steps:
+            x = b.step(x, u)
+            n += 1
+    el = time.perf_counter() - t0
+    return {"value": sub.n_drones_total * n / el, "unit": "drone-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"worlds 0,16,32,... ({len(pick)} worlds, {sub.n_drones_total} drones), {n} steps, "
+                      f"FP64 PyTorch CPU, {el:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,244 @@
+/*
+ * cfsim -- batched drone simulation step for AMD MI355X (gfx950), C interface.
+ *
+ * The library advances M worlds of N_w drones each (D = sum N_w drones in
+ * total) with the two dynamics models of Crazyflow (arXiv 2606.01478,
+ * Methods):
+ *   - CF_MODEL_FP: first-principles rigid body (Eq. 1) with second-order
+ *     thrust / rotor-drag polynomials, the x-airframe mixing matrix and the
+ *     adapted, direction-dependent rotor-speed dynamics (Eq. rotor_adapted);
+ *     section "First Principles Modeling";
+ *   - CF_MODEL_ID: identified attitude-command model (point mass, first-order
+ *     collective thrust, second-order attitude response; Eqs. 3_simplified_*);
+ *     section "Abstracted Physics Modeling".
+ * Control interfaces (section "First Principles Modeling", last paragraphs):
+ * rotor speeds, or attitude + collective thrust through a cascaded PID and
+ * the motor allocation. Explicit Euler or classical RK4 with the command held
+ * over a step (the equations are integrated directly, section "Architecture").
+ *
+ * Conventions shared by every call
+ *   - Memory: every state, command, loss and gradient buffer is caller-owned
+ *     device memory, float32, contiguous, structure of arrays: component-major
+ *     [component][drone], drones of world 0 first, then world 1, ...
+ *     (cf_world_offsets gives the first drone of each world). Buffers passed
+ *     to one call must not overlap unless stated.
+ *   - Streams: all device work is enqueued on the handle's HIP stream and is
+ *     asynchronous; only cf_create, cf_destroy and cf_autotune synchronise.
+ *   - Errors: every call returns a cf_status. Argument validation happens on
+ *     the host before anything is enqueued; a call that fails validation
+ *     writes no output. Asynchronous device faults are reported as
+ *     CF_EDEVICE by a later call (sticky) or by cf_last_error.
+ *   - Threading: a handle is not thread-safe; distinct handles are
+ *     independent.
+ */
+#ifndef CFSIM_H
+#define CFSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cf_status;
+#define CF_OK            0
+#define CF_EINVAL       (-1)  /* invalid argument (NULL, size, enum, range) */
+#define CF_ENODEV       (-2)  /* no usable HIP device */
+#define CF_ENOMEM       (-3)  /* device or host allocation failed */
+#define CF_EDEVICE      (-4)  /* a HIP runtime call or kernel failed */
+#define CF_ESTATE       (-5)  /* call sequence violated (e.g. checkpoint mismatch) */
+#define CF_EUNSUPPORTED (-6)  /* valid request that this build does not implement */
+
+/* models, control interfaces, integrators */
+#define CF_MODEL_FP      0
+#define CF_MODEL_ID      1
+#define CF_CTRL_ROTOR    0   /* FP command = rotor-speed setpoints Omega_cmd[4] */
+#define CF_CTRL_ATT_PID  1   /* FP command = [roll, pitch, yaw rate, thrust]    */
+#define CF_INTEG_EULER   0
+#define CF_INTEG_RK4     1
+
+/* cf_desc.flags */
+#define CF_F_PLAIN_KERNEL    0x1u  /* cf_step_k: one single-step launch per step   */
+#define CF_F_NONFINITE_CHECK 0x2u  /* cf_step_k / cf_rollout: flag non-finite states */
+#define CF_F_GRAPH           0x4u  /* replay launch sequences from captured hipGraphs */
+#define CF_F_WORKQUEUE       0x8u  /* cf_step_k: persistent work-queue kernel (one launch) */
+#define CF_F_NO_AUTOTUNE_CACHE 0x10u /* do not read the autotune cache at create */
+
+/*
+ * State layout (rows of the [S][D] state):
+ *   FP:  0-2 position p [m] (world, z up), 3-6 attitude quaternion (x,y,z,w),
+ *        body->world, scalar last; 7-9 velocity v [m/s] (world);
+ *        10-12 body rate [rad/s]; 13-16 rotor speeds Omega_1..4.
+ *        With CF_CTRL_ATT_PID: 17-18 roll/pitch angle-error integrals,
+ *        19-21 body-rate-error integrals, 22-24 body rate of the previous step.
+ *   ID:  0-2 p, 3-5 Euler angles (roll, pitch, yaw; R = Rz Ry Rx), 6-8 v,
+ *        9-11 Euler-angle rates, 12 collective thrust state f_sum [N].
+ * S = 17 (FP rotor), 25 (FP attitude), 13 (ID). A handle holding both models
+ * uses S = max; identified drones use rows 0..12 and leave the rest untouched.
+ * Commands are [4][D]: FP rotor: Omega_cmd; FP attitude: [roll, pitch,
+ * yaw rate, thrust]; ID: [roll, pitch, yaw, thrust].
+ */
+#define CF_S_FP_ROTOR 17
+#define CF_S_FP_PID   25
+#define CF_S_ID       13
+
+/*
+ * Per-world parameter record: CF_NPARAM floats, in this order (unused entries
+ * must be 0). Units SI. "FP" = read by first-principles worlds, "ID" = by
+ * identified worlds, "PID" = by the attitude controller.
+ */
+#define CF_NPARAM 96
+#define CF_P_MASS        0   /* FP,ID  m [kg]                                      */
+#define CF_P_GRAVITY     1   /* FP,ID  g [m/s^2], acts along -z                    */
+#define CF_P_J           2   /* FP     Jxx, Jyy, Jzz (diagonal inertia) [3]        */
+#define CF_P_THRUST      5   /* FP     k0, k1, k2: f_i = k0 + k1 W + k2 W^2 [3]    */
+#define CF_P_TORQUE      8   /* FP     t0, t1, t2: drag torque polynomial [3]      */
+#define CF_P_MIX_TX     11   /* FP     tau_x = sum mix_tx[i] f_i [4]               */
+#define CF_P_MIX_TY     15   /* FP     tau_y = sum mix_ty[i] f_i [4]               */
+#define CF_P_MIX_YAW    19   /* FP     tau_z = sum mix_yaw[i] torque_i [4]         */
+#define CF_P_MOTOR_UP   23   /* FP     c_v, c_d when Omega_cmd >= Omega [2]        */
+#define CF_P_MOTOR_DOWN 25   /* FP     c_v, c_d when Omega_cmd <  Omega [2]        */
+#define CF_P_JP         27   /* FP     propeller inertia J_p: must be 0 (see errors) */
+#define CF_P_DRAG       28   /* FP,ID  linear drag C_a diagonal: must be 0 [3]     */
+#define CF_P_ANG_KP     31   /* PID    roll/pitch angle P gain [1/s] [2]           */
+#define CF_P_ANG_KI     33   /* PID    roll/pitch angle I gain [1/s^2] [2]         */
+#define CF_P_RATE_KP    35   /* PID    body-rate P gain [1/s] [3]                  */
+#define CF_P_RATE_KI    38   /* PID    body-rate I gain [1/s^2] [3]                */
+#define CF_P_RATE_KD    41   /* PID    body-rate D gain [-] [3]                    */
+#define CF_P_J_CTRL     44   /* PID    inertia used by the controller [3]          */
+#define CF_P_F_MAX      47   /* PID    per-rotor thrust limit [N]                  */
+#define CF_P_ALLOC      48   /* PID    4x4 row-major: f = alloc [T, tau_x, tau_y, tau_z] */
+#define CF_P_CF         64   /* ID     thrust scaling c_f                          */
+#define CF_P_CTAU       65   /* ID     thrust time coefficient c_tau [1/s]         */
+#define CF_P_CPSI1      66   /* ID     attitude coefficient c1 per axis [3]        */
+#define CF_P_CPSI2      69   /* ID     c2 per axis [3]                             */
+#define CF_P_CPSI3      72   /* ID     c3 per axis [3]                             */
+
+typedef struct cf_desc {
+    int32_t n_worlds;                 /* M >= 1                                       */
+    int32_t n_drones;                 /* drones per world when drones_per_world NULL  */
+    const int32_t* drones_per_world;  /* host [M], each >= 0, or NULL                 */
+    int32_t model;                    /* CF_MODEL_* of every world when model_per_world NULL */
+    const uint8_t* model_per_world;   /* host [M] or NULL                             */
+    int32_t control;                  /* CF_CTRL_* for first-principles worlds        */
+    int32_t integrator;               /* CF_INTEG_*                                   */
+    float dt;                         /* step [s], finite, > 0                        */
+    int32_t renorm_q;                 /* 1: normalise the quaternion after each step  */
+    const float* params;              /* host [M][CF_NPARAM]; copied at create        */
+    int32_t n_gains;                  /* feedback gains available to cf_rollout (>= 0) */
+    const int32_t* gain_index;        /* host [M] in [0, n_gains) or NULL (all 0)     */
+    void* stream;                     /* hipStream_t, NULL = default stream           */
+    uint32_t flags;                   /* CF_F_*                                       */
+    int32_t device;                   /* HIP device ordinal, -1 = current device      */
+} cf_desc;
+
+typedef struct cf_handle cf_handle;
+
+/*
+ * Tracking objective and linear feedback of cf_rollout / cf_rollout_backward.
+ * Applied command u_t = ubar_t + G_w (x_t[0:13] - x_ref(t)) when gain != NULL.
+ * Loss per drone: sum_{t=1..T} |p_t - p_ref(t)|^2 + w_u sum_{t=0..T-1} |u_t|^2,
+ * t_n = n dt. Reference (ref_table == NULL): figure-eight
+ * p_ref = [A sin(2 pi t/P), (A/2) sin(4 pi t/P), 0] + offset_d and its
+ * derivative; x_ref = [p_ref, (0,0,0,1), v_ref, 0] (FP) or
+ * [p_ref, 0, v_ref, 0, m g / c_f] (ID). With ref_table, x_ref(t) is row t
+ * (offset added to its position).
+ */
+typedef struct cf_objective {
+    const float* gain;        /* device [n_gains][4][13] or NULL (no feedback)   */
+    const float* ref_table;   /* device [T+1][13] or NULL (figure-eight)         */
+    float ref_amp;            /* A [m]                                           */
+    float ref_period;         /* P [s], > 0                                      */
+    const float* ref_offset;  /* device [3][D] or NULL                           */
+    float w_u;                /* command weight, >= 0                            */
+} cf_objective;
+
+/*
+ * cf_create: validate *desc, copy the parameter records and the world layout
+ * to the device, choose kernel variants (autotune cache unless
+ * CF_F_NO_AUTOTUNE_CACHE) and return a handle in *out (NULL on failure).
+ * Errors: CF_EINVAL (NULL pointers, M < 1, negative drone counts, D > 2^31-1,
+ * unknown enum, dt not finite or <= 0, mass/inertia/k2/c_f not > 0, gain
+ * index out of range), CF_EUNSUPPORTED (non-zero J_p or drag), CF_ENODEV (no
+ * device), CF_ENOMEM, CF_EDEVICE.
+ */
+cf_status cf_create(const cf_desc* desc, cf_handle** out);
+
+/* cf_destroy: synchronise the stream and free everything the library owns. NULL is a no-op. */
+cf_status cf_destroy(cf_handle* h);
+
+/* Queries (host only). */
+cf_status cf_state_dim(const cf_handle* h, int32_t* S);
+cf_status cf_total_drones(const cf_handle* h, int64_t* D);
+cf_status cf_world_offsets(const cf_handle* h, int64_t* offsets_host /* [M+1] */);
+cf_status cf_set_stream(cf_handle* h, void* stream);
+
+/*
+ * cf_reset (continuous/masked resets, section "Architecture"): for every world w
+ * with world_mask[w] != 0 (all worlds when world_mask is NULL), copy the S rows
+ * of init into state for that world's drones. state, init: device [S][D];
+ * world_mask: device uint8 [M] or NULL. state and init must not overlap.
+ */
+cf_status cf_reset(cf_handle* h, float* state, const float* init, const uint8_t* world_mask);
+
+/*
+ * cf_step_k: advance every drone k >= 1 steps with the command held (zero-order
+ * hold). state: device [S][D], updated in place; cmd: device [4][D].
+ * nonfinite_world: device uint32 [M] or NULL; with CF_F_NONFINITE_CHECK the
+ * entry of a world is OR-ed with 1 when any of its drones ends with a
+ * non-finite state component (the buffer is not cleared by the library).
+ * Kernel: fused k-step kernel that keeps the state in registers (chunked by
+ * the autotuned K), or k single-step launches with CF_F_PLAIN_KERNEL, or the
+ * persistent work-queue kernel (CF_F_WORKQUEUE or autotune choice).
+ */
+cf_status cf_step_k(cf_handle* h, float* state, const float* cmd, int32_t k,
+                    uint32_t* nonfinite_world);
+
+/*
+ * cf_rollout: T >= 1 steps from x0 (device [S][D]) with per-step commands
+ * cmds (device [T][4][D], the ubar_t of cf_objective). obj may be NULL (no
+ * feedback, no loss: loss and loss_world must then be NULL).
+ * ckpt_every K >= 1; ckpt (device [ceil(T/K)][S][D] or NULL) receives the
+ * states at t = 0, K, 2K, ... and is required by cf_rollout_backward.
+ * x_T (device [S][D]), traj (device [T+1][S][D]), loss (device [D]) and
+ * loss_world (device [M], per-world sums in a fixed order) may each be NULL.
+ */
+cf_status cf_rollout(cf_handle* h, const float* x0, const float* cmds, int32_t T,
+                     const cf_objective* obj, int32_t ckpt_every, float* ckpt,
+                     float* x_T, float* traj, float* loss, float* loss_world);
+
+/*
+ * cf_rollout_backward: gradient of sum_d dloss[d] * loss_d (dloss: device [D])
+ * through the whole rollout, by a hand-written discrete adjoint that
+ * recomputes each K-step segment from its checkpoint. The arguments x0, cmds,
+ * T, obj, ckpt_every must be those of the cf_rollout that filled ckpt on this
+ * handle; a different T, K or ckpt pointer returns CF_ESTATE. Outputs
+ * (overwritten, each may be NULL): g_cmds device [T][4][D] (d/d ubar_t),
+ * g_x0 device [S][D], g_gain device [n_gains][4][13] (sum over drones in a
+ * fixed order; requires obj->gain).
+ */
+cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, int32_t T,
+                              const cf_objective* obj, int32_t ckpt_every, const float* ckpt,
+                              const float* dloss, float* g_cmds, float* g_x0, float* g_gain);
+
+/*
+ * cf_autotune: time candidate launch shapes of cf_step_k (fused grid vs
+ * persistent work queue, tile size, steps per launch K) on copies of state and
+ * cmd (device [S][D], [4][D], not modified) for about budget_ms, keep the
+ * fastest for this handle and store it in the autotune cache file
+ * ($CFSIM_AUTOTUNE_CACHE, default $HOME/.cache/cfsim_autotune.json). Synchronises.
+ */
+cf_status cf_autotune(cf_handle* h, const float* state, const float* cmd, int32_t k, int32_t budget_ms);
+
+/* Current launch choice (host): use_workqueue (0/1), tile (lanes per work item), chunk K. */
+cf_status cf_launch_config(const cf_handle* h, int32_t* use_workqueue, int32_t* tile, int32_t* chunk);
+
+const char* cf_strerror(cf_status status);
+
+/* cf_last_error: synchronise the stream and return the sticky device error (or CF_OK). */
+cf_status cf_last_error(cf_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFSIM_H */

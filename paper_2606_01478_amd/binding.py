@@ -1,0 +1,345 @@
+"""ctypes binding of libcfsim.so (include/cfsim.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+library. PyTorch supplies device memory (CUDA/HIP tensors) and the stream.
+Loading fails loudly when the library has not been built; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_float, c_int32, c_int64, c_uint8, c_uint32, c_void_p
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcfsim.so")
+
+CF_OK, CF_EINVAL, CF_ENODEV, CF_ENOMEM, CF_EDEVICE, CF_ESTATE, CF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+MODEL_FP, MODEL_ID = 0, 1
+CTRL_ROTOR, CTRL_ATT_PID = 0, 1
+INTEG_EULER, INTEG_RK4 = 0, 1
+F_PLAIN_KERNEL, F_NONFINITE_CHECK, F_GRAPH, F_WORKQUEUE, F_NO_AUTOTUNE_CACHE = 0x1, 0x2, 0x4, 0x8, 0x10
+S_FP_ROTOR, S_FP_PID, S_ID = 17, 25, 13
+NPARAM = 96
+NGAIN = 52
+
+# offsets of the named parameter fields in the CF_NPARAM record (CF_P_* in the header)
+PARAM_OFFSETS = {
+    "mass": (0, 1), "gravity": (1, 1), "J": (2, 3), "thrust_poly": (5, 3), "torque_poly": (8, 3),
+    "mix_tx": (11, 4), "mix_ty": (15, 4), "mix_yaw": (19, 4), "motor_up": (23, 2), "motor_down": (25, 2),
+    "Jp": (27, 1), "drag": (28, 3), "ang_kp": (31, 2), "ang_ki": (33, 2), "rate_kp": (35, 3),
+    "rate_ki": (38, 3), "rate_kd": (41, 3), "J_ctrl": (44, 3), "f_max": (47, 1), "alloc": (48, 16),
+    "c_f": (64, 1), "c_tau": (65, 1), "c_psi1": (66, 3), "c_psi2": (69, 3), "c_psi3": (72, 3),
+}
+
+EXPORTS = ("cf_create", "cf_destroy", "cf_state_dim", "cf_total_drones", "cf_world_offsets", "cf_set_stream",
+           "cf_reset", "cf_step_k", "cf_rollout", "cf_rollout_backward", "cf_autotune", "cf_launch_config",
+           "cf_strerror", "cf_last_error")
+
+
+class CfError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {_LIB.cf_strerror(status).decode() if _LIB else status} ({status})")
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("n_worlds", c_int32), ("n_drones", c_int32), ("drones_per_world", POINTER(c_int32)),
+                ("model", c_int32), ("model_per_world", POINTER(c_uint8)), ("control", c_int32),
+                ("integrator", c_int32), ("dt", c_float), ("renorm_q", c_int32), ("params", POINTER(c_float)),
+                ("n_gains", c_int32), ("gain_index", POINTER(c_int32)), ("stream", c_void_p),
+                ("flags", c_uint32), ("device", c_int32)]
+
+
+class _Objective(ctypes.Structure):
+    _fields_ = [("gain", c_void_p), ("ref_table", c_void_p), ("ref_amp", c_float), ("ref_period", c_float),
+                ("ref_offset", c_void_p), ("w_u", c_float)]
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2606_01478_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    H = c_void_p
+    P = c_void_p
+    sig = {
+        "cf_create": ([POINTER(_Desc), POINTER(c_void_p)], c_int32),
+        "cf_destroy": ([H], c_int32),
+        "cf_state_dim": ([H, POINTER(c_int32)], c_int32),
+        "cf_total_drones": ([H, POINTER(c_int64)], c_int32),
+        "cf_world_offsets": ([H, POINTER(c_int64)], c_int32),
+        "cf_set_stream": ([H, c_void_p], c_int32),
+        "cf_reset": ([H, P, P, P], c_int32),
+        "cf_step_k": ([H, P, P, c_int32, P], c_int32),
+        "cf_rollout": ([H, P, P, c_int32, POINTER(_Objective), c_int32, P, P, P, P, P], c_int32),
+        "cf_rollout_backward": ([H, P, P, c_int32, POINTER(_Objective), c_int32, P, P, P, P, P], c_int32),
+        "cf_autotune": ([H, P, P, c_int32, c_int32], c_int32),
+        "cf_launch_config": ([H, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)], c_int32),
+        "cf_strerror": ([c_int32], ctypes.c_char_p),
+        "cf_last_error": ([H], c_int32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _LIB = lib
+    return lib
+
+
+def _check(status: int, what: str) -> None:
+    if status != CF_OK:
+        raise CfError(status, what)
+
+
+def pack_params(params: Dict[str, np.ndarray], n_worlds: int) -> np.ndarray:
+    """Named per-world fields ``[M, k]`` -> the flat ``[M][CF_NPARAM]`` float32 record."""
+    out = np.zeros((n_worlds, NPARAM), np.float32)
+    for name, arr in params.items():
+        off, k = PARAM_OFFSETS[name]
+        a = np.asarray(arr, np.float32).reshape(n_worlds, k)
+        out[:, off:off + k] = a
+    return out
+
+
+def _ptr(t) -> Optional[int]:
+    """Device address of a contiguous float32/uint8/uint32 CUDA tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Sim:
+    """A batch of worlds on one GPU (handle of the C library)."""
+
+    def __init__(self, n_worlds: int, drones_per_world, model_per_world, control: int, integrator: int,
+                 dt: float, params, *, renorm_q: int = 1, n_gains: int = 0, gain_index=None, flags: int = 0,
+                 device: int = -1):
+        import torch
+        lib = load()
+        self._lib = lib
+        self._h = c_void_p()
+        M = int(n_worlds)
+        self.n_worlds = M
+        counts = np.ascontiguousarray(np.broadcast_to(np.asarray(drones_per_world, np.int32), (M,)))
+        models = np.ascontiguousarray(np.broadcast_to(np.asarray(model_per_world, np.uint8), (M,)))
+        flat = pack_params(params, M) if isinstance(params, dict) else np.ascontiguousarray(params, np.float32)
+        if flat.shape != (M, NPARAM):
+            raise ValueError(f"params must be [{M}, {NPARAM}]")
+        self._keep = [counts, models, flat]
+        d = _Desc()
+        d.n_worlds = M
+        d.n_drones = 0
+        d.drones_per_world = counts.ctypes.data_as(POINTER(c_int32))
+        d.model = int(models[0]) if M else 0
+        d.model_per_world = models.ctypes.data_as(POINTER(c_uint8))
+        d.control = int(control)
+        d.integrator = int(integrator)
+        d.dt = float(dt)
+        d.renorm_q = int(renorm_q)
+        d.params = flat.ctypes.data_as(POINTER(c_float))
+        d.n_gains = int(n_gains)
+        if gain_index is not None:
+            gi = np.ascontiguousarray(np.asarray(gain_index, np.int32).reshape(M))
+            self._keep.append(gi)
+            d.gain_index = gi.ctypes.data_as(POINTER(c_int32))
+        d.stream = c_void_p(_stream() if torch.cuda.is_available() else 0)
+        d.flags = int(flags)
+        d.device = int(device)
+        _check(lib.cf_create(ctypes.byref(d), ctypes.byref(self._h)), "cf_create")
+        S = c_int32()
+        D = c_int64()
+        _check(lib.cf_state_dim(self._h, ctypes.byref(S)), "cf_state_dim")
+        _check(lib.cf_total_drones(self._h, ctypes.byref(D)), "cf_total_drones")
+        self.S, self.D = int(S.value), int(D.value)
+        off = np.zeros(M + 1, np.int64)
+        _check(lib.cf_world_offsets(self._h, off.ctypes.data_as(POINTER(c_int64))), "cf_world_offsets")
+        self.offsets = off
+        self.n_gains = int(n_gains)
+        self.flags = int(flags)
+
+    @classmethod
+    def from_workload(cls, w, flags: int = 0, **kw):
+        n_gains = 0 if w.gain is None else int(w.gain.shape[0])
+        return cls(w.n_worlds, w.drones_per_world, w.model_per_world, w.control, w.integrator, w.dt,
+                   w.params, renorm_q=w.renorm_q, n_gains=n_gains, gain_index=w.gain_index, flags=flags, **kw)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.cf_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _need(self, t, shape, name, dtypes=("float32",)) -> None:
+        if t is None:
+            return
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+        if str(t.dtype).replace("torch.", "") not in dtypes:
+            raise ValueError(f"{name}: expected dtype {dtypes}, got {t.dtype}")
+
+    def _need_obj(self, obj, T) -> None:
+        if obj is None:
+            return
+        g, rt, ro = getattr(obj, "_tensors", (None, None, None))
+        self._need(g, (self.n_gains, 4, 13), "gain")
+        self._need(rt, (T + 1, 13), "ref_table")
+        self._need(ro, (3, self.D), "ref_offset")
+
+    def _sync_stream(self) -> None:
+        _check(self._lib.cf_set_stream(self._h, c_void_p(_stream())), "cf_set_stream")
+
+    # -- calls -------------------------------------------------------------------
+    def reset(self, state, init, world_mask=None) -> None:
+        self._need(state, (self.S, self.D), "state")
+        self._need(init, (self.S, self.D), "init")
+        self._need(world_mask, (self.n_worlds,), "world_mask", ("uint8", "bool"))
+        self._sync_stream()
+        _check(self._lib.cf_reset(self._h, _ptr(state), _ptr(init), _ptr(world_mask)), "cf_reset")
+
+    def step_k(self, state, cmd, k: int, nonfinite=None) -> None:
+        self._need(state, (self.S, self.D), "state")
+        self._need(cmd, (4, self.D), "cmd")
+        self._need(nonfinite, (self.n_worlds,), "nonfinite", ("int32", "uint32"))
+        self._sync_stream()
+        _check(self._lib.cf_step_k(self._h, _ptr(state), _ptr(cmd), int(k), _ptr(nonfinite)), "cf_step_k")
+
+    @staticmethod
+    def objective(gain=None, ref_table=None, ref_amp=1.0, ref_period=4.0, ref_offset=None, w_u=1e-3):
+        o = _Objective()
+        o.gain = _ptr(gain)
+        o.ref_table = _ptr(ref_table)
+        o.ref_amp = float(ref_amp)
+        o.ref_period = float(ref_period)
+        o.ref_offset = _ptr(ref_offset)
+        o.w_u = float(w_u)
+        o._tensors = (gain, ref_table, ref_offset)
+        return o
+
+    def rollout(self, x0, cmds, T: int, obj=None, ckpt_every: int = 50, ckpt=None, x_T=None, traj=None,
+                loss=None, loss_world=None) -> None:
+        T = int(T)
+        nseg = (T + int(ckpt_every) - 1) // int(ckpt_every) if ckpt_every > 0 else 0
+        self._need(x0, (self.S, self.D), "x0")
+        self._need(cmds, (T, 4, self.D), "cmds")
+        self._need(ckpt, (nseg, self.S, self.D), "ckpt")
+        self._need(x_T, (self.S, self.D), "x_T")
+        self._need(traj, (T + 1, self.S, self.D), "traj")
+        self._need(loss, (self.D,), "loss")
+        self._need(loss_world, (self.n_worlds,), "loss_world")
+        self._need_obj(obj, T)
+        self._sync_stream()
+        o = ctypes.byref(obj) if obj is not None else None
+        _check(self._lib.cf_rollout(self._h, _ptr(x0), _ptr(cmds), int(T), o, int(ckpt_every), _ptr(ckpt),
+                                    _ptr(x_T), _ptr(traj), _ptr(loss), _ptr(loss_world)), "cf_rollout")
+
+    def rollout_backward(self, x0, cmds, T: int, obj, ckpt_every: int, ckpt, dloss=None, g_cmds=None,
+                         g_x0=None, g_gain=None) -> None:
+        T = int(T)
+        nseg = (T + int(ckpt_every) - 1) // int(ckpt_every) if ckpt_every > 0 else 0
+        self._need(cmds, (T, 4, self.D), "cmds")
+        self._need(ckpt, (nseg, self.S, self.D), "ckpt")
+        self._need(dloss, (self.D,), "dloss")
+        self._need(g_cmds, (T, 4, self.D), "g_cmds")
+        self._need(g_x0, (self.S, self.D), "g_x0")
+        self._need(g_gain, (self.n_gains, 4, 13), "g_gain")
+        self._need_obj(obj, T)
+        self._sync_stream()
+        o = ctypes.byref(obj) if obj is not None else None
+        _check(self._lib.cf_rollout_backward(self._h, _ptr(x0), _ptr(cmds), int(T), o, int(ckpt_every),
+                                             _ptr(ckpt), _ptr(dloss), _ptr(g_cmds), _ptr(g_x0), _ptr(g_gain)),
+               "cf_rollout_backward")
+
+    def autotune(self, state, cmd, k: int, budget_ms: int = 2000) -> None:
+        self._need(state, (self.S, self.D), "state")
+        self._need(cmd, (4, self.D), "cmd")
+        self._sync_stream()
+        _check(self._lib.cf_autotune(self._h, _ptr(state), _ptr(cmd), int(k), int(budget_ms)), "cf_autotune")
+
+    def launch_config(self):
+        a, b, c = c_int32(), c_int32(), c_int32()
+        _check(self._lib.cf_launch_config(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "cf_launch_config")
+        return {"workqueue": a.value, "tile": b.value, "chunk": c.value}
+
+    def last_error(self) -> int:
+        return int(self._lib.cf_last_error(self._h))
+
+
+def _rollout_loss_apply(sim: Sim, x0, cmds, gain, T, ckpt_every, obj_kw):
+    import torch
+    dev = x0.device
+    nseg = (T + ckpt_every - 1) // ckpt_every
+    ckpt = torch.empty((nseg, sim.S, sim.D), device=dev, dtype=torch.float32)
+    loss = torch.empty(sim.D, device=dev, dtype=torch.float32)
+    obj = Sim.objective(gain=gain, **obj_kw)
+    sim.rollout(x0, cmds, T, obj, ckpt_every, ckpt=ckpt, loss=loss)
+    return loss, ckpt, obj
+
+
+class RolloutLoss:
+    """``loss = RolloutLoss.apply(x0, cmds, gain, sim, T, ckpt_every, obj_kw)``: per-drone
+    tracking loss ``[D]`` of a rollout; backward runs the library's discrete adjoint and
+    returns gradients for ``x0`` ``[S][D]``, ``cmds`` ``[T][4][D]`` and ``gain``."""
+
+    @staticmethod
+    def _fn():
+        import torch
+
+        class _F(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, x0, cmds, gain, sim, T, ckpt_every, obj_kw):
+                x0c, cmdsc = x0.detach().contiguous(), cmds.detach().contiguous()
+                gc = None if gain is None else gain.detach().contiguous()
+                loss, ckpt, _ = _rollout_loss_apply(sim, x0c, cmdsc, gc, T, ckpt_every, obj_kw)
+                ctx.sim, ctx.T, ctx.K, ctx.obj_kw = sim, T, ckpt_every, obj_kw
+                ctx.save_for_backward(x0c, cmdsc, ckpt, *( [gc] if gc is not None else []))
+                ctx.has_gain = gc is not None
+                return loss
+
+            @staticmethod
+            def backward(ctx, dloss):
+                saved = ctx.saved_tensors
+                x0, cmds, ckpt = saved[0], saved[1], saved[2]
+                gain = saved[3] if ctx.has_gain else None
+                sim = ctx.sim
+                g_cmds = torch.empty_like(cmds)
+                g_x0 = torch.empty_like(x0)
+                g_gain = torch.empty_like(gain) if gain is not None else None
+                obj = Sim.objective(gain=gain, **ctx.obj_kw)
+                sim.rollout_backward(x0, cmds, ctx.T, obj, ctx.K, ckpt, dloss=dloss.contiguous(),
+                                     g_cmds=g_cmds, g_x0=g_x0, g_gain=g_gain)
+                return g_x0, g_cmds, g_gain, None, None, None, None
+
+        return _F
+
+    _cached = None
+
+    @classmethod
+    def apply(cls, x0, cmds, gain, sim, T, ckpt_every=50, obj_kw=None):
+        if cls._cached is None:
+            cls._cached = cls._fn()
+        return cls._cached.apply(x0, cmds, gain, sim, T, ckpt_every, obj_kw or {})

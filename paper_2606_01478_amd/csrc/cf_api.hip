@@ -1,0 +1,875 @@
+// Host runtime of the C interface declared in include/cfsim.h: argument
+// validation, device-side world layout, tile lists for uneven worlds, launch
+// selection, hipGraph replay of launch sequences, the autotuner, and the small
+// utility kernels (reset, reference table, deterministic reductions).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <sys/stat.h>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/cfsim.h"
+#include "cf_device.hpp"
+#include "cf_internal.hpp"
+
+using namespace cfk;
+
+// ---------------------------------------------------------------------------
+// utility kernels
+
+__global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// state[:, d] = init[:, d] for drones of masked worlds
+__global__ void k_reset(float* __restrict__ st, const float* __restrict__ init, int S, int64_t D,
+                        const int32_t* __restrict__ drone_world, const uint8_t* __restrict__ mask) {
+    const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= (size_t)D) return;
+    if (mask && !mask[drone_world[d]]) return;
+    for (int i = 0; i < S; ++i) st[(size_t)i * D + d] = init[(size_t)i * D + d];
+}
+
+// figure-eight (lemniscate of Gerono) rows [p(3), v(3)] for t = 0..T
+__global__ void k_eight_table(float* tab, int T, float dt, float amp, float period) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > T) return;
+    const double w0 = 2.0 * 3.14159265358979323846 / (double)period;
+    const double tt = (double)t * (double)dt;
+    const double A = amp;
+    float* r = tab + (size_t)t * 6;
+    r[0] = (float)(A * sin(w0 * tt));
+    r[1] = (float)(0.5 * A * sin(2.0 * w0 * tt));
+    r[2] = 0.f;
+    r[3] = (float)(A * w0 * cos(w0 * tt));
+    r[4] = (float)(A * w0 * cos(2.0 * w0 * tt));
+    r[5] = 0.f;
+}
+
+// out[w][c] = sum over the drones of world w of v[c][d], in a fixed order:
+// each thread sums a strided subset, then a fixed LDS tree.
+__global__ __launch_bounds__(256) void k_reduce_world(const float* __restrict__ v, int ncomp, int64_t D,
+                                                      const int64_t* __restrict__ off, float* __restrict__ out) {
+    __shared__ float sh[256];
+    const int w = blockIdx.x;
+    const int64_t a = off[w], b = off[w + 1];
+    for (int c = 0; c < ncomp; ++c) {
+        float s = 0.f;
+        for (int64_t d = a + threadIdx.x; d < b; d += blockDim.x) s += v[(size_t)c * D + d];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[(size_t)w * ncomp + c] = sh[0];
+        __syncthreads();
+    }
+}
+
+// g[k][c] = sum over worlds w (in order) with gidx[w] == k of ws[w][c]
+__global__ void k_reduce_gain(const float* __restrict__ ws, const int32_t* __restrict__ gidx, int M,
+                              int n_gains, int ncomp, float* __restrict__ g) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_gains * ncomp) return;
+    const int k = i / ncomp, c = i % ncomp;
+    float s = 0.f;
+    for (int w = 0; w < M; ++w)
+        if (gidx[w] == k) s += ws[(size_t)w * ncomp + c];
+    g[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// handle
+
+namespace {
+
+struct GraphKey {
+    const void* st; const void* cmd; const void* nf; int k; int wq; int tile; int chunk; int plain;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(st, cmd, nf, k, wq, tile, chunk, plain) <
+               std::tie(o.st, o.cmd, o.nf, o.k, o.wq, o.tile, o.chunk, o.plain);
+    }
+};
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct cf_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int M = 0;
+    int64_t D = 0;
+    int S = 0;
+    int models = 0;  // MS_*
+    int control = 0, integ = 0, renorm = 1;
+    float dt = 0.f;
+    uint32_t flags = 0;
+    int n_gains = 0;
+    std::vector<int32_t> counts;
+    std::vector<int64_t> offsets;
+    std::vector<uint8_t> model_of_world;
+    int cus = 256;
+    std::string arch;
+    // device copies
+    float* par_aos = nullptr;
+    float* par_soa = nullptr;
+    int32_t* drone_world = nullptr;
+    int64_t* d_offsets = nullptr;
+    int32_t* d_gidx = nullptr;
+    // tiles for the current tile size
+    int4* tiles = nullptr;
+    int n_tiles = 0;
+    int tiles_for = 0;
+    unsigned* counters = nullptr;
+    int n_counters = 0;
+    // launch choice
+    int lane_ok = 0;     // all worlds one model: per-lane mapping possible
+    int use_wq = 0;
+    int tile = 64;
+    int chunk = 0;       // 0 = all k steps in one launch
+    int mode = LM_TILE;
+    // scratch
+    DevBuf ref_tab, seg, ggc, wsum, loss_tmp;
+    // last rollout (for the backward's consistency check)
+    const float* last_ckpt = nullptr;
+    int last_T = -1, last_K = -1;
+    cf_status sticky = CF_OK;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+cf_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return CF_OK;
+    if (e == hipErrorOutOfMemory) return CF_ENOMEM;
+    if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return CF_ENODEV;
+    return CF_EDEVICE;
+}
+
+cf_status note(cf_handle* h, hipError_t e) {
+    cf_status s = from_hip(e);
+    if (s == CF_EDEVICE && h->sticky == CF_OK) h->sticky = s;
+    return s;
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    return hipMalloc((void**)p, n * sizeof(T));
+}
+
+hipError_t ensure(DevBuf& b, size_t bytes) {
+    if (b.n >= bytes && b.p) return hipSuccess;
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+    hipError_t e = hipMalloc(&b.p, bytes ? bytes : 1);
+    if (e == hipSuccess) b.n = bytes;
+    return e;
+}
+
+// caller buffer check: ptr must be device memory holding at least `bytes`
+cf_status check_dev(const void* ptr, size_t bytes) {
+    if (!ptr) return CF_EINVAL;
+    if (bytes == 0) return CF_OK;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return CF_EINVAL;
+    }
+    const char* b = (const char*)base;
+    const char* p = (const char*)ptr;
+    if (p < b || (size_t)(p - b) + bytes > size) return CF_EINVAL;
+    return CF_OK;
+}
+
+int model_cost(int model, int ctrl) {
+    if (model == MODEL_ID) return 2;
+    return ctrl == CTRL_PID ? 5 : 4;
+}
+
+hipError_t build_tiles(cf_handle* h, int tile) {
+    if (h->tiles && h->tiles_for == tile) return hipSuccess;
+    struct T { int4 v; int cost; };
+    std::vector<T> ts;
+    for (int w = 0; w < h->M; ++w) {
+        const int n = h->counts[w];
+        for (int s = 0; s < n; s += tile) {
+            const int c = std::min(tile, n - s);
+            const int waves = (c + 63) / 64;
+            ts.push_back({make_int4(w, (int)(h->offsets[w] + s), c, h->model_of_world[w]),
+                          waves * model_cost(h->model_of_world[w], h->control)});
+        }
+    }
+    // most expensive first (longest-processing-time order), ties by position
+    std::stable_sort(ts.begin(), ts.end(), [](const T& a, const T& b) { return a.cost > b.cost; });
+    std::vector<int4> v(ts.size());
+    for (size_t i = 0; i < ts.size(); ++i) v[i] = ts[i].v;
+    if (h->tiles) hipFree(h->tiles);
+    h->tiles = nullptr;
+    h->n_tiles = (int)v.size();
+    hipError_t e = dalloc(&h->tiles, v.size());
+    if (e != hipSuccess) return e;
+    if (!v.empty()) e = hipMemcpy(h->tiles, v.data(), v.size() * sizeof(int4), hipMemcpyHostToDevice);
+    h->tiles_for = tile;
+    return e;
+}
+
+void clear_graphs(cf_handle* h) {
+    for (auto& kv : h->graphs) hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+}
+
+KernelSel selection(const cf_handle* h, int mode, int tile) {
+    KernelSel ks;
+    ks.models = h->models;
+    ks.ctrl = h->control;
+    ks.integ = h->integ;
+    ks.mode = mode;
+    ks.tile = tile;
+    return ks;
+}
+
+StepArgs step_args(const cf_handle* h, float* st, const float* cmd, int K, uint32_t* nf) {
+    StepArgs a;
+    a.st = st;
+    a.cmd = cmd;
+    a.D = h->D;
+    a.M = h->M;
+    a.par_aos = h->par_aos;
+    a.par_soa = h->par_soa;
+    a.drone_world = h->drone_world;
+    a.dt = h->dt;
+    a.inv_dt = 1.0f / h->dt;
+    a.renorm = h->renorm;
+    a.K = K;
+    a.nonfinite = (h->flags & CF_F_NONFINITE_CHECK) ? nf : nullptr;
+    return a;
+}
+
+std::string cache_path() {
+    const char* p = std::getenv("CFSIM_AUTOTUNE_CACHE");
+    if (p && *p) return p;
+    const char* home = std::getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/cfsim_autotune.txt";
+}
+
+std::string signature(const cf_handle* h) {
+    char buf[256];
+    int nfp = 0;
+    for (auto m : h->model_of_world) nfp += (m == MODEL_FP);
+    std::snprintf(buf, sizeof buf, "%s|M%d|D%lld|fp%d|c%d|i%d", h->arch.c_str(), h->M, (long long)h->D, nfp,
+                  h->control, h->integ);
+    return buf;
+}
+
+bool cache_lookup(const std::string& key, int* wq, int* tile, int* chunk) {
+    FILE* f = std::fopen(cache_path().c_str(), "r");
+    if (!f) return false;
+    char k[256];
+    int a, b, c;
+    float ms;
+    bool found = false;
+    while (std::fscanf(f, "%255s %d %d %d %f", k, &a, &b, &c, &ms) == 5) {
+        if (key == k) { *wq = a; *tile = b; *chunk = c; found = true; }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const std::string& key, int wq, int tile, int chunk, float ms) {
+    const std::string path = cache_path();
+    std::vector<std::string> lines;
+    if (FILE* f = std::fopen(path.c_str(), "r")) {
+        char line[512];
+        while (std::fgets(line, sizeof line, f)) {
+            char k[256];
+            if (std::sscanf(line, "%255s", k) == 1 && key != k) lines.push_back(line);
+        }
+        std::fclose(f);
+    }
+    const size_t slash = path.find_last_of('/');
+    if (slash != std::string::npos && slash > 0) mkdir(path.substr(0, slash).c_str(), 0755);
+    FILE* f = std::fopen(path.c_str(), "w");
+    if (!f) return;
+    for (auto& l : lines) std::fputs(l.c_str(), f);
+    std::fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), wq, tile, chunk, ms);
+    std::fclose(f);
+}
+
+void apply_choice(cf_handle* h, int wq, int tile, int chunk) {
+    if (tile != 64 && tile != 128 && tile != 256) tile = 64;
+    h->use_wq = wq ? 1 : 0;
+    h->tile = tile;
+    h->chunk = chunk > 0 ? chunk : 0;
+    h->mode = (h->lane_ok && !h->use_wq && h->D > 0 && (double)h->D / h->M < 32.0) ? LM_LANE : LM_TILE;
+    clear_graphs(h);
+}
+
+cf_status validate_desc(const cf_desc* d, std::vector<int32_t>& counts, std::vector<uint8_t>& models,
+                        std::vector<int32_t>& gidx, int64_t* D_out) {
+    if (!d) return CF_EINVAL;
+    if (d->n_worlds < 1) return CF_EINVAL;
+    const int M = d->n_worlds;
+    counts.assign(M, 0);
+    models.assign(M, 0);
+    int64_t D = 0;
+    for (int w = 0; w < M; ++w) {
+        const int n = d->drones_per_world ? d->drones_per_world[w] : d->n_drones;
+        if (n < 0) return CF_EINVAL;
+        counts[w] = n;
+        D += n;
+        if (D > 2147483647LL) return CF_EINVAL;
+        const int m = d->model_per_world ? d->model_per_world[w] : d->model;
+        if (m != CF_MODEL_FP && m != CF_MODEL_ID) return CF_EINVAL;
+        models[w] = (uint8_t)m;
+    }
+    if (d->control != CF_CTRL_ROTOR && d->control != CF_CTRL_ATT_PID) return CF_EINVAL;
+    if (d->integrator != CF_INTEG_EULER && d->integrator != CF_INTEG_RK4) return CF_EINVAL;
+    if (!(std::isfinite(d->dt) && d->dt > 0.f)) return CF_EINVAL;
+    if (d->renorm_q != 0 && d->renorm_q != 1) return CF_EINVAL;
+    if (!d->params) return CF_EINVAL;
+    if (d->n_gains < 0) return CF_EINVAL;
+    gidx.assign(M, 0);
+    if (d->gain_index) {
+        for (int w = 0; w < M; ++w) {
+            if (d->gain_index[w] < 0 || d->gain_index[w] >= std::max(d->n_gains, 1)) return CF_EINVAL;
+            gidx[w] = d->gain_index[w];
+        }
+    }
+    bool unsupported = false;
+    for (int w = 0; w < M; ++w) {
+        const float* r = d->params + (size_t)w * CF_NPARAM;
+        for (int i = 0; i < CF_NPARAM; ++i)
+            if (!std::isfinite(r[i])) return CF_EINVAL;
+        if (!(r[CF_P_MASS] > 0.f)) return CF_EINVAL;
+        if (r[CF_P_DRAG] != 0.f || r[CF_P_DRAG + 1] != 0.f || r[CF_P_DRAG + 2] != 0.f) unsupported = true;
+        if (models[w] == CF_MODEL_FP) {
+            for (int i = 0; i < 3; ++i)
+                if (!(r[CF_P_J + i] > 0.f)) return CF_EINVAL;
+            if (d->control == CF_CTRL_ATT_PID && !(r[CF_P_THRUST + 2] > 0.f)) return CF_EINVAL;
+            if (r[CF_P_JP] != 0.f) unsupported = true;
+        } else {
+            if (!(r[CF_P_CF] > 0.f)) return CF_EINVAL;
+        }
+    }
+    if (unsupported) return CF_EUNSUPPORTED;
+    *D_out = D;
+    return CF_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C interface
+
+extern "C" {
+
+const char* cf_strerror(cf_status s) {
+    switch (s) {
+        case CF_OK: return "success";
+        case CF_EINVAL: return "invalid argument";
+        case CF_ENODEV: return "no usable HIP device";
+        case CF_ENOMEM: return "out of memory";
+        case CF_EDEVICE: return "HIP device or runtime error";
+        case CF_ESTATE: return "call sequence or checkpoint mismatch";
+        case CF_EUNSUPPORTED: return "unsupported by this build";
+        default: return "unknown status";
+    }
+}
+
+cf_status cf_create(const cf_desc* d, cf_handle** out) {
+    if (!out) return CF_EINVAL;
+    *out = nullptr;
+    std::vector<int32_t> counts, gidx;
+    std::vector<uint8_t> models;
+    int64_t D = 0;
+    cf_status st = validate_desc(d, counts, models, gidx, &D);
+    if (st != CF_OK) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return CF_ENODEV;
+    }
+    int dev = d->device;
+    if (dev < 0) {
+        if (hipGetDevice(&dev) != hipSuccess) return CF_ENODEV;
+    }
+    if (dev >= ndev) return CF_ENODEV;
+    if (hipSetDevice(dev) != hipSuccess) return CF_ENODEV;
+
+    cf_handle* h = new (std::nothrow) cf_handle();
+    if (!h) return CF_ENOMEM;
+    h->device = dev;
+    h->stream = (hipStream_t)d->stream;
+    h->M = d->n_worlds;
+    h->D = D;
+    h->control = d->control;
+    h->integ = d->integrator;
+    h->renorm = d->renorm_q;
+    h->dt = d->dt;
+    h->flags = d->flags;
+    h->n_gains = d->n_gains;
+    h->counts = counts;
+    h->model_of_world = models;
+    h->offsets.assign(h->M + 1, 0);
+    for (int w = 0; w < h->M; ++w) h->offsets[w + 1] = h->offsets[w] + counts[w];
+    int has_fp = 0, has_id = 0;
+    for (auto m : models) (m == CF_MODEL_FP ? has_fp : has_id) = 1;
+    h->models = (has_fp ? MS_FP : 0) | (has_id ? MS_ID : 0);
+    h->S = has_fp ? (h->control == CF_CTRL_ATT_PID ? CF_S_FP_PID : CF_S_FP_ROTOR) : CF_S_ID;
+    h->lane_ok = (h->models != MS_BOTH);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        h->cus = prop.multiProcessorCount;
+        h->arch = prop.gcnArchName;
+        for (auto& c : h->arch)
+            if (c == ':' || c == ' ') c = '_';
+    }
+
+    auto fail = [&](hipError_t e) {
+        cf_status s = from_hip(e);
+        cf_destroy(h);
+        return s == CF_OK ? CF_EDEVICE : s;
+    };
+    hipError_t e;
+    const size_t M = (size_t)h->M;
+    std::vector<float> soa((size_t)CF_NPARAM * M);
+    for (size_t w = 0; w < M; ++w)
+        for (int i = 0; i < CF_NPARAM; ++i) soa[(size_t)i * M + w] = d->params[w * CF_NPARAM + i];
+    std::vector<int32_t> dw((size_t)std::max<int64_t>(D, 1));
+    for (int w = 0; w < h->M; ++w)
+        for (int64_t k = h->offsets[w]; k < h->offsets[w + 1]; ++k) dw[k] = w;
+    if ((e = dalloc(&h->par_aos, M * CF_NPARAM)) != hipSuccess) return fail(e);
+    if ((e = dalloc(&h->par_soa, M * CF_NPARAM)) != hipSuccess) return fail(e);
+    if ((e = dalloc(&h->drone_world, (size_t)std::max<int64_t>(D, 1))) != hipSuccess) return fail(e);
+    if ((e = dalloc(&h->d_offsets, M + 1)) != hipSuccess) return fail(e);
+    if ((e = dalloc(&h->d_gidx, M)) != hipSuccess) return fail(e);
+    h->n_counters = 4096;
+    if ((e = dalloc(&h->counters, (size_t)h->n_counters)) != hipSuccess) return fail(e);
+    if ((e = hipMemcpy(h->par_aos, d->params, M * CF_NPARAM * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    if ((e = hipMemcpy(h->par_soa, soa.data(), soa.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    if ((e = hipMemcpy(h->drone_world, dw.data(), dw.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    if ((e = hipMemcpy(h->d_offsets, h->offsets.data(), (M + 1) * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    if ((e = hipMemcpy(h->d_gidx, gidx.data(), M * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    if ((e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking)) != hipSuccess) return fail(e);
+
+    int wq = (h->flags & CF_F_WORKQUEUE) ? 1 : 0, tile = 64, chunk = 0;
+    if (!(h->flags & CF_F_NO_AUTOTUNE_CACHE) && !(h->flags & CF_F_WORKQUEUE)) {
+        int a, b, c;
+        if (cache_lookup(signature(h), &a, &b, &c)) { wq = a; tile = b; chunk = c; }
+    }
+    apply_choice(h, wq, tile, chunk);
+    if ((e = build_tiles(h, h->tile)) != hipSuccess) return fail(e);
+    *out = h;
+    return CF_OK;
+}
+
+cf_status cf_destroy(cf_handle* h) {
+    if (!h) return CF_OK;
+    hipSetDevice(h->device);
+    if (h->stream) hipStreamSynchronize(h->stream);
+    else hipDeviceSynchronize();
+    clear_graphs(h);
+    hipFree(h->par_aos);
+    hipFree(h->par_soa);
+    hipFree(h->drone_world);
+    hipFree(h->d_offsets);
+    hipFree(h->d_gidx);
+    hipFree(h->tiles);
+    hipFree(h->counters);
+    for (DevBuf* b : {&h->ref_tab, &h->seg, &h->ggc, &h->wsum, &h->loss_tmp})
+        if (b->p) hipFree(b->p);
+    if (h->capture_stream) hipStreamDestroy(h->capture_stream);
+    delete h;
+    return CF_OK;
+}
+
+cf_status cf_state_dim(const cf_handle* h, int32_t* S) {
+    if (!h || !S) return CF_EINVAL;
+    *S = h->S;
+    return CF_OK;
+}
+
+cf_status cf_total_drones(const cf_handle* h, int64_t* D) {
+    if (!h || !D) return CF_EINVAL;
+    *D = h->D;
+    return CF_OK;
+}
+
+cf_status cf_world_offsets(const cf_handle* h, int64_t* off) {
+    if (!h || !off) return CF_EINVAL;
+    std::memcpy(off, h->offsets.data(), (h->M + 1) * sizeof(int64_t));
+    return CF_OK;
+}
+
+cf_status cf_set_stream(cf_handle* h, void* stream) {
+    if (!h) return CF_EINVAL;
+    h->stream = (hipStream_t)stream;
+    return CF_OK;
+}
+
+cf_status cf_launch_config(const cf_handle* h, int32_t* use_wq, int32_t* tile, int32_t* chunk) {
+    if (!h || !use_wq || !tile || !chunk) return CF_EINVAL;
+    *use_wq = h->use_wq;
+    *tile = h->tile;
+    *chunk = h->chunk;
+    return CF_OK;
+}
+
+cf_status cf_last_error(cf_handle* h) {
+    if (!h) return CF_EINVAL;
+    hipSetDevice(h->device);
+    hipError_t e = h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize();
+    if (e != hipSuccess) note(h, e);
+    hipError_t e2 = hipGetLastError();
+    if (e2 != hipSuccess) note(h, e2);
+    return h->sticky;
+}
+
+cf_status cf_reset(cf_handle* h, float* state, const float* init, const uint8_t* world_mask) {
+    if (!h) return CF_EINVAL;
+    if (h->sticky != CF_OK) return h->sticky;
+    if (h->D == 0) return CF_OK;
+    const size_t bytes = (size_t)h->S * h->D * sizeof(float);
+    if (check_dev(state, bytes) || check_dev(init, bytes)) return CF_EINVAL;
+    if (world_mask && check_dev(world_mask, (size_t)h->M)) return CF_EINVAL;
+    const char* s0 = (const char*)state;
+    const char* i0 = (const char*)init;
+    if (s0 < i0 + bytes && i0 < s0 + bytes) return CF_EINVAL;
+    hipSetDevice(h->device);
+    const unsigned grid = (unsigned)((h->D + 255) / 256);
+    hipLaunchKernelGGL(k_reset, dim3(grid), dim3(256), 0, h->stream, state, init, h->S, h->D, h->drone_world,
+                       world_mask);
+    return note(h, hipGetLastError());
+}
+
+// enqueue k held-command steps with the current launch choice on stream s
+static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int k, uint32_t* nf, hipStream_t s,
+                               int plain) {
+    hipError_t e = hipSuccess;
+    if (plain) {
+        const KernelSel ks = selection(h, h->mode == LM_LANE ? LM_LANE : LM_TILE, h->tile);
+        const StepArgs a = step_args(h, state, cmd, 1, nf);
+        for (int i = 0; i < k && e == hipSuccess; ++i) e = launch_step(ks, a, h->tiles, h->n_tiles, nullptr, 0, s);
+        return note(h, e);
+    }
+    const int chunk = (h->chunk > 0 && h->chunk < k) ? h->chunk : k;
+    const int n_launch = (k + chunk - 1) / chunk;
+    if (h->use_wq) {
+        if (n_launch > h->n_counters) return CF_EINVAL;
+        const KernelSel ks = selection(h, LM_WQ, h->tile);
+        const int per_cu = step_wq_blocks_per_cu(ks);
+        const int blocks = std::max(1, std::min(h->n_tiles, per_cu * h->cus));
+        hipLaunchKernelGGL(k_fill_u32, dim3((n_launch + 255) / 256), dim3(256), 0, s, h->counters, n_launch, 0u);
+        e = hipGetLastError();
+        for (int c = 0; c < n_launch && e == hipSuccess; ++c) {
+            const int kk = std::min(chunk, k - c * chunk);
+            const StepArgs a = step_args(h, state, cmd, kk, nf);
+            e = launch_step(ks, a, h->tiles, h->n_tiles, h->counters + c, blocks, s);
+        }
+    } else {
+        const KernelSel ks = selection(h, h->mode, h->tile);
+        for (int c = 0; c < n_launch && e == hipSuccess; ++c) {
+            const int kk = std::min(chunk, k - c * chunk);
+            const StepArgs a = step_args(h, state, cmd, kk, nf);
+            e = launch_step(ks, a, h->tiles, h->n_tiles, nullptr, 0, s);
+        }
+    }
+    return note(h, e);
+}
+
+cf_status cf_step_k(cf_handle* h, float* state, const float* cmd, int32_t k, uint32_t* nf) {
+    if (!h || k < 1) return CF_EINVAL;
+    if (h->sticky != CF_OK) return h->sticky;
+    if (h->D == 0) return CF_OK;
+    if (check_dev(state, (size_t)h->S * h->D * sizeof(float)) ||
+        check_dev(cmd, (size_t)4 * h->D * sizeof(float)))
+        return CF_EINVAL;
+    if (nf && check_dev(nf, (size_t)h->M * sizeof(uint32_t))) return CF_EINVAL;
+    hipSetDevice(h->device);
+    hipError_t e = build_tiles(h, h->tile);
+    if (e != hipSuccess) return note(h, e);
+    const int plain = (h->flags & CF_F_PLAIN_KERNEL) ? 1 : 0;
+    if (!(h->flags & CF_F_GRAPH)) return enqueue_steps(h, state, cmd, k, nf, h->stream, plain);
+
+    const GraphKey key{state, cmd, nf, k, h->use_wq, h->tile, h->chunk, plain};
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+        if (h->graphs.size() >= 64) clear_graphs(h);
+        hipStream_t cs = h->capture_stream;
+        if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return note(h, e);
+        cf_status st = enqueue_steps(h, state, cmd, k, nf, cs, plain);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (st != CF_OK) {
+            if (g) hipGraphDestroy(g);
+            return st;
+        }
+        if (e2 != hipSuccess) return note(h, e2);
+        hipGraphExec_t ge = nullptr;
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return note(h, e);
+        it = h->graphs.emplace(key, ge).first;
+    }
+    return note(h, hipGraphLaunch(it->second, h->stream));
+}
+
+// ---------------------------------------------------------------------------
+// rollout
+
+static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T, RollArgs& a) {
+    a.has_obj = obj ? 1 : 0;
+    a.gain = nullptr;
+    a.gidx = h->d_gidx;
+    a.ref_tab = nullptr;
+    a.ref_user = 0;
+    a.ref_off = nullptr;
+    a.w_u = 0.f;
+    if (!obj) return CF_OK;
+    if (!(std::isfinite(obj->w_u) && obj->w_u >= 0.f)) return CF_EINVAL;
+    if (obj->gain) {
+        if (h->n_gains < 1) return CF_EINVAL;
+        if (check_dev(obj->gain, (size_t)h->n_gains * 52 * sizeof(float))) return CF_EINVAL;
+        a.gain = obj->gain;
+    }
+    if (obj->ref_offset) {
+        if (check_dev(obj->ref_offset, (size_t)3 * h->D * sizeof(float))) return CF_EINVAL;
+        a.ref_off = obj->ref_offset;
+    }
+    a.w_u = obj->w_u;
+    if (obj->ref_table) {
+        if (check_dev(obj->ref_table, (size_t)(T + 1) * 13 * sizeof(float))) return CF_EINVAL;
+        a.ref_tab = obj->ref_table;
+        a.ref_user = 1;
+    } else {
+        if (!(std::isfinite(obj->ref_period) && obj->ref_period > 0.f) || !std::isfinite(obj->ref_amp))
+            return CF_EINVAL;
+        hipError_t e = ensure(h->ref_tab, (size_t)(T + 1) * 6 * sizeof(float));
+        if (e != hipSuccess) return note(h, e);
+        hipLaunchKernelGGL(k_eight_table, dim3((T + 1 + 255) / 256), dim3(256), 0, h->stream, (float*)h->ref_tab.p,
+                           T, h->dt, obj->ref_amp, obj->ref_period);
+        if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
+        a.ref_tab = (const float*)h->ref_tab.p;
+    }
+    return CF_OK;
+}
+
+static RollArgs roll_args(const cf_handle* h, const float* x0, const float* cmds, int T, int K) {
+    RollArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.x0 = x0;
+    a.cmds = cmds;
+    a.T = T;
+    a.D = h->D;
+    a.M = h->M;
+    a.par_aos = h->par_aos;
+    a.par_soa = h->par_soa;
+    a.drone_world = h->drone_world;
+    a.dt = h->dt;
+    a.inv_dt = 1.0f / h->dt;
+    a.renorm = h->renorm;
+    a.K = K;
+    return a;
+}
+
+static int roll_mode(const cf_handle* h) {
+    return (h->lane_ok && h->D > 0 && (double)h->D / h->M < 32.0) ? LM_LANE : LM_TILE;
+}
+
+cf_status cf_rollout(cf_handle* h, const float* x0, const float* cmds, int32_t T, const cf_objective* obj,
+                     int32_t K, float* ckpt, float* x_T, float* traj, float* loss, float* loss_world) {
+    if (!h || T < 1 || K < 1) return CF_EINVAL;
+    if (h->sticky != CF_OK) return h->sticky;
+    if (!obj && (loss || loss_world)) return CF_EINVAL;
+    const size_t SD = (size_t)h->S * h->D * sizeof(float);
+    const int nseg = (T + K - 1) / K;
+    if (h->D > 0) {
+        if (check_dev(x0, SD) || check_dev(cmds, (size_t)T * 4 * h->D * sizeof(float))) return CF_EINVAL;
+        if (ckpt && check_dev(ckpt, (size_t)nseg * SD)) return CF_EINVAL;
+        if (x_T && check_dev(x_T, SD)) return CF_EINVAL;
+        if (traj && check_dev(traj, (size_t)(T + 1) * SD)) return CF_EINVAL;
+        if (loss && check_dev(loss, (size_t)h->D * sizeof(float))) return CF_EINVAL;
+    }
+    if (loss_world && check_dev(loss_world, (size_t)h->M * sizeof(float))) return CF_EINVAL;
+    hipSetDevice(h->device);
+    RollArgs a = roll_args(h, x0, cmds, T, K);
+    cf_status st = prepare_objective(h, obj, T, a);
+    if (st != CF_OK) return st;
+    a.ckpt = ckpt;
+    a.xT = x_T;
+    a.traj = traj;
+    a.loss = loss;
+    a.nonfinite = nullptr;
+    hipError_t e = hipSuccess;
+    if (loss_world && !loss) {
+        if ((e = ensure(h->loss_tmp, (size_t)std::max<int64_t>(h->D, 1) * sizeof(float))) != hipSuccess)
+            return note(h, e);
+        a.loss = (float*)h->loss_tmp.p;
+    }
+    if (h->D > 0) {
+        const int mode = roll_mode(h);
+        const int tile = 64;
+        if (mode == LM_TILE && (e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
+        const KernelSel ks = selection(h, mode, mode == LM_LANE ? 64 : h->tile);
+        (void)tile;
+        if ((e = launch_rollout_fwd(ks, a, h->tiles, h->n_tiles, h->stream)) != hipSuccess) return note(h, e);
+    }
+    if (loss_world) {
+        hipLaunchKernelGGL(k_reduce_world, dim3(h->M), dim3(256), 0, h->stream, a.loss, 1, h->D, h->d_offsets,
+                           loss_world);
+        if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
+    }
+    h->last_ckpt = ckpt;
+    h->last_T = T;
+    h->last_K = K;
+    return CF_OK;
+}
+
+cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, int32_t T, const cf_objective* obj,
+                              int32_t K, const float* ckpt, const float* dloss, float* g_cmds, float* g_x0,
+                              float* g_gain) {
+    if (!h || T < 1 || K < 1 || !ckpt) return CF_EINVAL;
+    if (h->sticky != CF_OK) return h->sticky;
+    if (ckpt != h->last_ckpt || T != h->last_T || K != h->last_K) return CF_ESTATE;
+    if (g_gain && (!obj || !obj->gain)) return CF_EINVAL;
+    const size_t SD = (size_t)h->S * h->D * sizeof(float);
+    const int nseg = (T + K - 1) / K;
+    if (h->D > 0) {
+        if (check_dev(cmds, (size_t)T * 4 * h->D * sizeof(float))) return CF_EINVAL;
+        if (check_dev(ckpt, (size_t)nseg * SD)) return CF_EINVAL;
+        if (dloss && check_dev(dloss, (size_t)h->D * sizeof(float))) return CF_EINVAL;
+        if (g_cmds && check_dev(g_cmds, (size_t)T * 4 * h->D * sizeof(float))) return CF_EINVAL;
+        if (g_x0 && check_dev(g_x0, SD)) return CF_EINVAL;
+    }
+    if (g_gain && check_dev(g_gain, (size_t)h->n_gains * 52 * sizeof(float))) return CF_EINVAL;
+    (void)x0;
+    hipSetDevice(h->device);
+    RollArgs a = roll_args(h, x0, cmds, T, K);
+    cf_status st = prepare_objective(h, obj, T, a);
+    if (st != CF_OK) return st;
+    hipError_t e;
+    a.ckpt_in = ckpt;
+    a.dloss = dloss;
+    a.g_cmds = g_cmds;
+    a.g_x0 = g_x0;
+    const int64_t Dm = std::max<int64_t>(h->D, 1);
+    if ((e = ensure(h->seg, (size_t)std::min(K, T) * h->S * Dm * sizeof(float))) != hipSuccess) return note(h, e);
+    a.seg = (float*)h->seg.p;
+    if (g_gain) {
+        if ((e = ensure(h->ggc, (size_t)52 * Dm * sizeof(float))) != hipSuccess) return note(h, e);
+        if ((e = ensure(h->wsum, (size_t)h->M * 52 * sizeof(float))) != hipSuccess) return note(h, e);
+        a.ggc = (float*)h->ggc.p;
+    }
+    if (h->D > 0) {
+        const int mode = roll_mode(h);
+        if (mode == LM_TILE && (e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
+        const KernelSel ks = selection(h, mode, mode == LM_LANE ? 64 : h->tile);
+        if ((e = launch_rollout_bwd(ks, a, h->tiles, h->n_tiles, h->stream)) != hipSuccess) return note(h, e);
+    }
+    if (g_gain) {
+        if (h->D > 0) {
+            hipLaunchKernelGGL(k_reduce_world, dim3(h->M), dim3(256), 0, h->stream, (const float*)h->ggc.p, 52,
+                               h->D, h->d_offsets, (float*)h->wsum.p);
+        } else {
+            hipLaunchKernelGGL(k_fill_u32, dim3((h->M * 52 + 255) / 256), dim3(256), 0, h->stream,
+                               (unsigned*)h->wsum.p, h->M * 52, 0u);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
+        const int n = h->n_gains * 52;
+        hipLaunchKernelGGL(k_reduce_gain, dim3((n + 255) / 256), dim3(256), 0, h->stream, (const float*)h->wsum.p,
+                           h->d_gidx, h->M, h->n_gains, 52, g_gain);
+        if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
+    }
+    return CF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotune
+
+cf_status cf_autotune(cf_handle* h, const float* state, const float* cmd, int32_t k, int32_t budget_ms) {
+    if (!h || k < 1 || budget_ms < 1) return CF_EINVAL;
+    if (h->sticky != CF_OK) return h->sticky;
+    if (h->D == 0) return CF_OK;
+    const size_t SD = (size_t)h->S * h->D * sizeof(float);
+    if (check_dev(state, SD) || check_dev(cmd, (size_t)4 * h->D * sizeof(float))) return CF_EINVAL;
+    hipSetDevice(h->device);
+    float* work = nullptr;
+    hipError_t e = hipMalloc(&work, SD);
+    if (e != hipSuccess) return note(h, e);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    struct Cand { int wq, tile, chunk; };
+    std::vector<Cand> cands;
+    for (int wq = 0; wq < 2; ++wq)
+        for (int tile : {64, 128, 256})
+            for (int chunk : {0, 100, 25}) {
+                if (chunk && chunk >= k) continue;
+                cands.push_back({wq, tile, chunk});
+            }
+    const int save_wq = h->use_wq, save_tile = h->tile, save_chunk = h->chunk;
+    const uint32_t save_flags = h->flags;
+    h->flags &= ~(CF_F_PLAIN_KERNEL | CF_F_GRAPH);
+    float best = 1e30f;
+    Cand bc{save_wq, save_tile, save_chunk};
+    double spent = 0.0;
+    cf_status st = CF_OK;
+    for (const Cand& c : cands) {
+        if (spent > budget_ms && best < 1e30f) break;
+        apply_choice(h, c.wq, c.tile, c.chunk);
+        if ((e = build_tiles(h, h->tile)) != hipSuccess) { st = note(h, e); break; }
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            hipMemcpyAsync(work, state, SD, hipMemcpyDeviceToDevice, h->stream);
+            hipEventRecord(e0, h->stream);
+            st = enqueue_steps(h, work, cmd, k, nullptr, h->stream, 0);
+            hipEventRecord(e1, h->stream);
+            if (st != CF_OK) break;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) { st = note(h, e); break; }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            spent += ms;
+            ms_best = std::min(ms_best, ms);
+        }
+        if (st != CF_OK) break;
+        if (ms_best < best) { best = ms_best; bc = c; }
+    }
+    h->flags = save_flags;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(work);
+    if (st != CF_OK) {
+        apply_choice(h, save_wq, save_tile, save_chunk);
+        return st;
+    }
+    apply_choice(h, bc.wq, bc.tile, bc.chunk);
+    if ((e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
+    cache_store(signature(h), bc.wq, bc.tile, bc.chunk, best);
+    return CF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal interface between the host runtime and the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cfk {
+
+// bit set of models present in a launch
+enum : int { MS_FP = 1, MS_ID = 2, MS_BOTH = 3 };
+// how lanes are mapped to drones
+//   LM_LANE: lane = drone, world looked up per lane, parameters from the
+//            transposed [NPARAM][M] copy (worlds of a handful of drones);
+//   LM_TILE: one workgroup per tile {world, first drone, count, model}, all
+//            lanes of a tile share one world (parameters are uniform loads);
+//   LM_WQ:   persistent workgroups pop tiles from an atomic queue head.
+enum : int { LM_LANE = 0, LM_TILE = 1, LM_WQ = 2 };
+
+struct KernelSel {
+    int models;  // MS_*
+    int ctrl;    // CTRL_ROTOR / CTRL_PID
+    int integ;   // EULER / RK4
+    int mode;    // LM_*
+    int tile;    // lanes per workgroup (64, 128, 256)
+};
+
+struct StepArgs {
+    float* st;              // [S][D]
+    const float* cmd;       // [4][D]
+    int64_t D;
+    int M;
+    const float* par_aos;   // [M][NPARAM]
+    const float* par_soa;   // [NPARAM][M]
+    const int32_t* drone_world;  // [D]
+    float dt, inv_dt;
+    int renorm;
+    int K;                  // steps per launch
+    uint32_t* nonfinite;    // [M] or null
+};
+
+struct RollArgs {
+    const float* x0;        // [S][D]
+    const float* cmds;      // [T][4][D]
+    int T;
+    int64_t D;
+    int M;
+    const float* par_aos;
+    const float* par_soa;
+    const int32_t* drone_world;
+    float dt, inv_dt;
+    int renorm;
+    // objective
+    int has_obj;
+    const float* gain;      // [G][4][13] or null
+    const int32_t* gidx;    // [M] device
+    const float* ref_tab;   // [T+1][6] figure-eight (p, v) or [T+1][13] user table
+    int ref_user;
+    const float* ref_off;   // [3][D] or null
+    float w_u;
+    // forward outputs
+    int K;                  // checkpoint interval
+    float* ckpt;            // [ceil(T/K)][S][D] or null
+    float* xT;
+    float* traj;            // [T+1][S][D] or null
+    float* loss;            // [D] or null
+    uint32_t* nonfinite;
+    // backward
+    const float* ckpt_in;
+    const float* dloss;     // [D] or null (ones)
+    float* g_cmds;          // [T][4][D] or null
+    float* g_x0;            // [S][D] or null
+    float* ggc;             // [52][D] per-drone gain-gradient contributions or null
+    float* seg;             // [K][S][D] segment scratch
+};
+
+hipError_t launch_step(const KernelSel& ks, const StepArgs& a, const int4* tiles, int n_tiles,
+                       unsigned* counter, int wq_blocks, hipStream_t s);
+hipError_t launch_rollout_fwd(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
+                              hipStream_t s);
+hipError_t launch_rollout_bwd(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
+                              hipStream_t s);
+// resident workgroups per CU of the work-queue kernel for this selection
+int step_wq_blocks_per_cu(const KernelSel& ks);
+
+}  // namespace cfk

@@ -1,0 +1,362 @@
+// Rollout kernels: the forward pass with per-step commands, linear feedback,
+// tracking loss and checkpoints; and the hand-written discrete adjoint that
+// recomputes every checkpoint segment and sweeps it in reverse.
+//
+// Objective (per drone d, t_n = n dt):
+//   u_t  = ubar_t + G_w (x_t[0:13] - x_ref(t))                (feedback, optional)
+//   loss = sum_{t=1..T} |p_t - p_ref(t)|^2 + w_u sum_{t=0..T-1} |u_t|^2
+// Adjoint: lambda_T = 0; for t = T-1..0:
+//   lambda_{t+1} += 2 dloss (p_{t+1} - p_ref(t+1))
+//   (xbar, ubar) = VJP of the step at (x_t, u_t) applied to lambda_{t+1}
+//   ubar += 2 dloss w_u u_t;  g_cmds[t] = ubar;  xbar[0:13] += G^T ubar;
+//   dL/dG += ubar e_t^T;  lambda_t = xbar.
+#include "cf_device.hpp"
+#include "cf_internal.hpp"
+
+namespace cfk {
+
+constexpr int NG = 52;  // 4 x 13 gain entries
+
+// position reference at step t (figure-eight table rows are [p(3), v(3)])
+__device__ __forceinline__ void ref_pos(const RollArgs& a, int t, const float* off, float* pr) {
+    const int stride = a.ref_user ? 13 : 6;
+    const float* row = a.ref_tab + (size_t)t * stride;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) pr[j] = row[j] + off[j];
+}
+
+// 13-component reference state of a drone of model MODEL
+template <int MODEL>
+__device__ __forceinline__ void ref_state(const RollArgs& a, int t, const float* off, float f_hover, float* xr) {
+    if (a.ref_user) {
+        const float* row = a.ref_tab + (size_t)t * 13;
+#pragma unroll
+        for (int j = 0; j < 13; ++j) xr[j] = row[j];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) xr[j] += off[j];
+        return;
+    }
+    const float* row = a.ref_tab + (size_t)t * 6;
+#pragma unroll
+    for (int j = 0; j < 13; ++j) xr[j] = 0.f;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) xr[j] = row[j] + off[j];
+    if constexpr (MODEL == MODEL_FP) {
+        xr[6] = 1.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) xr[7 + j] = row[3 + j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) xr[6 + j] = row[3 + j];
+        xr[12] = f_hover;
+    }
+}
+
+// applied command u = ubar + G e, e = x[0:13] - x_ref(t); returns e in ev
+template <int MODEL>
+__device__ __forceinline__ void applied_command(const RollArgs& a, const float* G, const float* x, int t,
+                                                const float* off, float f_hover, size_t d, float* u, float* ev) {
+    const size_t D = (size_t)a.D;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] = a.cmds[((size_t)t * 4 + i) * D + d];
+    if (G) {
+        float xr[13];
+        ref_state<MODEL>(a, t, off, f_hover, xr);
+#pragma unroll
+        for (int j = 0; j < 13; ++j) ev[j] = x[j] - xr[j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < 13; ++j) s += G[i * 13 + j] * ev[j];
+            u[i] += s;
+        }
+    }
+}
+
+template <int MODEL, int CTRL>
+struct ModelTraits {
+    static constexpr int S = MODEL == MODEL_ID ? S_ID : (CTRL == CTRL_PID ? S_PID : S_FP);
+};
+
+// per-drone parameters of either model
+struct DroneParams {
+    FpParams fp;
+    PidParams pid;
+    IdParams id;
+};
+
+template <int MODEL, int CTRL, class R>
+__device__ __forceinline__ void load_params(const R& rec, DroneParams& p) {
+    if constexpr (MODEL == MODEL_FP) {
+        p.fp = load_fp(rec);
+        if constexpr (CTRL == CTRL_PID) p.pid = load_pid(rec);
+    } else {
+        p.id = load_id(rec);
+    }
+}
+
+template <int MODEL, int CTRL, int INTEG>
+__device__ __forceinline__ void model_step(float* x, const float* u, const DroneParams& p, const RollArgs& a) {
+    if constexpr (MODEL == MODEL_FP) fp_step<CTRL, INTEG>(x, u, p.fp, p.pid, a.dt, a.inv_dt, a.renorm);
+    else id_step<INTEG>(x, u, p.id, a.dt);
+}
+
+template <int MODEL, int CTRL, int INTEG>
+__device__ __forceinline__ void model_step_vjp(const float* x, const float* u, const DroneParams& p,
+                                               const RollArgs& a, const float* yb, float* xb, float* ub) {
+    if constexpr (MODEL == MODEL_FP)
+        fp_step_vjp<CTRL, INTEG>(x, u, p.fp, p.pid, a.dt, a.inv_dt, a.renorm, yb, xb, ub);
+    else
+        id_step_vjp<INTEG>(x, u, p.id, a.dt, yb, xb, ub);
+}
+
+template <int N>
+__device__ __forceinline__ void store_rows(float* dst, size_t D, size_t d, const float* x) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) dst[i * D + d] = x[i];
+}
+template <int N>
+__device__ __forceinline__ void load_rows(const float* src, size_t D, size_t d, float* x) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = src[i * D + d];
+}
+
+// ---------------------------------------------------------------------------
+// forward rollout of one drone
+template <int MODEL, int CTRL, int INTEG, class R>
+__device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
+    constexpr int S = ModelTraits<MODEL, CTRL>::S;
+    const size_t D = (size_t)a.D;
+    const size_t SD = (size_t)S_h * D;
+    DroneParams p;
+    load_params<MODEL, CTRL>(rec, p);
+    const float f_hover = (MODEL == MODEL_ID) ? p.id.f_hover : 0.f;
+    float x[S];
+    load_rows<S>(a.x0, D, d, x);
+    float off[3] = {0.f, 0.f, 0.f};
+    if (a.has_obj && a.ref_off) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) off[j] = a.ref_off[j * D + d];
+    }
+    const float* G = (a.has_obj && a.gain) ? a.gain + (size_t)a.gidx[w] * NG : nullptr;
+    if (a.ckpt) store_rows<S>(a.ckpt, D, d, x);
+    if (a.traj) store_rows<S>(a.traj, D, d, x);
+    float loss = 0.f;
+    for (int t = 0; t < a.T; ++t) {
+        float u[4], ev[13];
+        applied_command<MODEL>(a, G, x, t, off, f_hover, d, u, ev);
+        if (a.has_obj) loss += a.w_u * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3]);
+        model_step<MODEL, CTRL, INTEG>(x, u, p, a);
+        if (a.has_obj) {
+            float pr[3];
+            ref_pos(a, t + 1, off, pr);
+            const float e0 = x[0] - pr[0], e1 = x[1] - pr[1], e2 = x[2] - pr[2];
+            loss += e0 * e0 + e1 * e1 + e2 * e2;
+        }
+        const int tn = t + 1;
+        if (a.ckpt && tn < a.T && (tn % a.K) == 0) store_rows<S>(a.ckpt + (size_t)(tn / a.K) * SD, D, d, x);
+        if (a.traj) store_rows<S>(a.traj + (size_t)tn * SD, D, d, x);
+    }
+    if (a.xT) store_rows<S>(a.xT, D, d, x);
+    if (a.loss) a.loss[d] = loss;
+    if (a.nonfinite) {
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < S; ++i) bad |= !isfinite(x[i]);
+        if (bad) atomicOr(a.nonfinite + w, 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of one drone's rollout
+template <int MODEL, int CTRL, int INTEG, class R>
+__device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
+    constexpr int S = ModelTraits<MODEL, CTRL>::S;
+    const size_t D = (size_t)a.D;
+    const size_t SD = (size_t)S_h * D;
+    DroneParams p;
+    load_params<MODEL, CTRL>(rec, p);
+    const float f_hover = (MODEL == MODEL_ID) ? p.id.f_hover : 0.f;
+    float off[3] = {0.f, 0.f, 0.f};
+    if (a.has_obj && a.ref_off) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) off[j] = a.ref_off[j * D + d];
+    }
+    const float* G = (a.has_obj && a.gain) ? a.gain + (size_t)a.gidx[w] * NG : nullptr;
+    const float seed = a.dloss ? a.dloss[d] : 1.f;
+    const float two_seed = 2.f * seed;
+    float lam[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) lam[i] = 0.f;
+    float gG[NG];
+    if (G) {
+#pragma unroll
+        for (int i = 0; i < NG; ++i) gG[i] = 0.f;
+    }
+    const int nseg = (a.T + a.K - 1) / a.K;
+    for (int s = nseg - 1; s >= 0; --s) {
+        const int t0 = s * a.K;
+        const int t1 = min(a.T, t0 + a.K);
+        float x[S];
+        load_rows<S>(a.ckpt_in + (size_t)s * SD, D, d, x);
+        // recompute the segment, keeping x_t for t in [t0, t1)
+        for (int t = t0; t < t1; ++t) {
+            store_rows<S>(a.seg + (size_t)(t - t0) * SD, D, d, x);
+            float u[4], ev[13];
+            applied_command<MODEL>(a, G, x, t, off, f_hover, d, u, ev);
+            model_step<MODEL, CTRL, INTEG>(x, u, p, a);
+        }
+        float pn[3] = {x[0], x[1], x[2]};  // position of x_{t+1}
+        for (int t = t1 - 1; t >= t0; --t) {
+            if (a.has_obj) {
+                float pr[3];
+                ref_pos(a, t + 1, off, pr);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) lam[j] += two_seed * (pn[j] - pr[j]);
+            }
+            load_rows<S>(a.seg + (size_t)(t - t0) * SD, D, d, x);
+            float u[4], ev[13];
+            applied_command<MODEL>(a, G, x, t, off, f_hover, d, u, ev);
+            float xb[S];
+            float ub[4] = {0.f, 0.f, 0.f, 0.f};
+            model_step_vjp<MODEL, CTRL, INTEG>(x, u, p, a, lam, xb, ub);
+            if (a.has_obj) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ub[i] += two_seed * a.w_u * u[i];
+            }
+            if (a.g_cmds) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a.g_cmds[((size_t)t * 4 + i) * D + d] = ub[i];
+            }
+            if (G) {
+#pragma unroll
+                for (int j = 0; j < 13; ++j) {
+                    float s2 = 0.f;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) s2 += G[i * 13 + j] * ub[i];
+                    xb[j] += s2;
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                    for (int j = 0; j < 13; ++j) gG[i * 13 + j] += ub[i] * ev[j];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < S; ++i) lam[i] = xb[i];
+            pn[0] = x[0]; pn[1] = x[1]; pn[2] = x[2];
+        }
+    }
+    if (a.g_x0) store_rows<S>(a.g_x0, D, d, lam);
+    if (a.ggc) {
+        if (G) store_rows<NG>(a.ggc, D, d, gG);
+        else {
+#pragma unroll
+            for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = 0.f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+
+template <bool BWD, int MODEL, int CTRL, int INTEG, class R>
+__device__ __forceinline__ void rollout_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
+    if constexpr (BWD) rollout_bwd_drone<MODEL, CTRL, INTEG>(rec, a, d, w, S_h);
+    else rollout_fwd_drone<MODEL, CTRL, INTEG>(rec, a, d, w, S_h);
+}
+
+template <bool BWD, int MODELS, int CTRL, int INTEG>
+__global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
+    const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= (size_t)a.D) return;
+    const int w = a.drone_world[d];
+    const SoaRec rec{a.par_soa, a.M, w};
+    if constexpr (MODELS == MS_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG>(rec, a, d, w, S_h);
+    else rollout_drone<BWD, MODEL_ID, CTRL, INTEG>(rec, a, d, w, S_h);
+}
+
+template <bool BWD, int MODELS, int CTRL, int INTEG>
+__global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __restrict__ tiles, int S_h) {
+    const int4 td = tiles[blockIdx.x];
+    const int w = __builtin_amdgcn_readfirstlane(td.x);
+    const int d0 = __builtin_amdgcn_readfirstlane(td.y);
+    const int cnt = __builtin_amdgcn_readfirstlane(td.z);
+    const int model = __builtin_amdgcn_readfirstlane(td.w);
+    if ((int)threadIdx.x >= cnt) return;
+    const AosRec rec{a.par_aos + (size_t)w * NPARAM};
+    const size_t d = (size_t)d0 + threadIdx.x;
+    if constexpr (MODELS == MS_FP) {
+        rollout_drone<BWD, MODEL_FP, CTRL, INTEG>(rec, a, d, w, S_h);
+    } else if constexpr (MODELS == MS_ID) {
+        rollout_drone<BWD, MODEL_ID, CTRL, INTEG>(rec, a, d, w, S_h);
+    } else {
+        if (model == MODEL_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG>(rec, a, d, w, S_h);
+        else rollout_drone<BWD, MODEL_ID, CTRL, INTEG>(rec, a, d, w, S_h);
+    }
+}
+
+static int handle_rows(int models, int ctrl) {
+    if (models & MS_FP) return ctrl == CTRL_PID ? S_PID : S_FP;
+    return S_ID;
+}
+
+template <bool BWD, int MODELS, int CTRL, int INTEG>
+static hipError_t launch_roll_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
+                                hipStream_t s) {
+    const int S_h = handle_rows(MODELS, CTRL);
+    if (ks.mode == LM_LANE) {
+        if constexpr (MODELS != MS_BOTH) {
+            const int bs = ks.tile;
+            const unsigned grid = (unsigned)((a.D + bs - 1) / bs);
+            hipLaunchKernelGGL((k_rollout_lane<BWD, MODELS, CTRL, INTEG>), dim3(grid), dim3(bs), 0, s, a, S_h);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        hipLaunchKernelGGL((k_rollout_tile<BWD, MODELS, CTRL, INTEG>), dim3(n_tiles), dim3(ks.tile), 0, s, a,
+                           tiles, S_h);
+    }
+    return hipGetLastError();
+}
+
+template <int MODELS, int CTRL, int INTEG>
+static hipError_t launch_fwd_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
+                               hipStream_t s) {
+    return launch_roll_t<false, MODELS, CTRL, INTEG>(ks, a, tiles, n_tiles, s);
+}
+template <int MODELS, int CTRL, int INTEG>
+static hipError_t launch_bwd_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
+                               hipStream_t s) {
+    return launch_roll_t<true, MODELS, CTRL, INTEG>(ks, a, tiles, n_tiles, s);
+}
+
+#define CF_DISPATCH(FN, ...)                                                             \
+    switch (ks.models * 4 + ks.ctrl * 2 + ks.integ) {                                    \
+        case MS_FP * 4 + 0: return FN<MS_FP, CTRL_ROTOR, EULER>(__VA_ARGS__);            \
+        case MS_FP * 4 + 1: return FN<MS_FP, CTRL_ROTOR, RK4>(__VA_ARGS__);              \
+        case MS_FP * 4 + 2: return FN<MS_FP, CTRL_PID, EULER>(__VA_ARGS__);              \
+        case MS_FP * 4 + 3: return FN<MS_FP, CTRL_PID, RK4>(__VA_ARGS__);                \
+        case MS_ID * 4 + 0: case MS_ID * 4 + 2: return FN<MS_ID, CTRL_ROTOR, EULER>(__VA_ARGS__); \
+        case MS_ID * 4 + 1: case MS_ID * 4 + 3: return FN<MS_ID, CTRL_ROTOR, RK4>(__VA_ARGS__);   \
+        case MS_BOTH * 4 + 0: return FN<MS_BOTH, CTRL_ROTOR, EULER>(__VA_ARGS__);        \
+        case MS_BOTH * 4 + 1: return FN<MS_BOTH, CTRL_ROTOR, RK4>(__VA_ARGS__);          \
+        case MS_BOTH * 4 + 2: return FN<MS_BOTH, CTRL_PID, EULER>(__VA_ARGS__);          \
+        case MS_BOTH * 4 + 3: return FN<MS_BOTH, CTRL_PID, RK4>(__VA_ARGS__);            \
+        default: break;                                                                  \
+    }
+
+hipError_t launch_rollout_fwd(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
+                              hipStream_t s) {
+    CF_DISPATCH(launch_fwd_t, ks, a, tiles, n_tiles, s)
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rollout_bwd(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
+                              hipStream_t s) {
+    CF_DISPATCH(launch_bwd_t, ks, a, tiles, n_tiles, s)
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cfk

@@ -1,0 +1,150 @@
+// Held-command step kernels: K steps per launch with each drone's state in
+// registers (K = 1 is the plain single-step kernel), in three lane mappings
+// (per-lane world, one world per tile, persistent work queue over tiles).
+#include "cf_device.hpp"
+#include "cf_internal.hpp"
+
+namespace cfk {
+
+// One drone, K steps with a held command; state rows st[i*D + d].
+template <int MODEL, int CTRL, int INTEG, class R>
+__device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t d, int w) {
+    const size_t D = (size_t)a.D;
+    bool bad = false;
+    if constexpr (MODEL == MODEL_FP) {
+        constexpr int S = (CTRL == CTRL_PID) ? S_PID : S_FP;
+        const FpParams P = load_fp(rec);
+        PidParams C;
+        if constexpr (CTRL == CTRL_PID) C = load_pid(rec);
+        float x[S], u[4];
+#pragma unroll
+        for (int i = 0; i < S; ++i) x[i] = a.st[i * D + d];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) u[i] = a.cmd[i * D + d];
+        for (int k = 0; k < a.K; ++k) fp_step<CTRL, INTEG>(x, u, P, C, a.dt, a.inv_dt, a.renorm);
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            a.st[i * D + d] = x[i];
+            bad |= !isfinite(x[i]);
+        }
+    } else {
+        const IdParams P = load_id(rec);
+        float x[S_ID], u[4];
+#pragma unroll
+        for (int i = 0; i < S_ID; ++i) x[i] = a.st[i * D + d];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) u[i] = a.cmd[i * D + d];
+        for (int k = 0; k < a.K; ++k) id_step<INTEG>(x, u, P, a.dt);
+#pragma unroll
+        for (int i = 0; i < S_ID; ++i) {
+            a.st[i * D + d] = x[i];
+            bad |= !isfinite(x[i]);
+        }
+    }
+    if (a.nonfinite && bad) atomicOr(a.nonfinite + w, 1u);
+}
+
+template <int MODELS, int CTRL, int INTEG>
+__device__ __forceinline__ void run_tile(const StepArgs& a, int4 td) {
+    // td = {world, first drone, drone count, model}, uniform over the workgroup
+    const int w = __builtin_amdgcn_readfirstlane(td.x);
+    const int d0 = __builtin_amdgcn_readfirstlane(td.y);
+    const int cnt = __builtin_amdgcn_readfirstlane(td.z);
+    const int model = __builtin_amdgcn_readfirstlane(td.w);
+    const int lane = threadIdx.x;
+    if (lane >= cnt) return;
+    const AosRec rec{a.par_aos + (size_t)w * NPARAM};
+    const size_t d = (size_t)d0 + lane;
+    if constexpr (MODELS == MS_FP) {
+        run_held<MODEL_FP, CTRL, INTEG>(rec, a, d, w);
+    } else if constexpr (MODELS == MS_ID) {
+        run_held<MODEL_ID, CTRL, INTEG>(rec, a, d, w);
+    } else {
+        if (model == MODEL_FP) run_held<MODEL_FP, CTRL, INTEG>(rec, a, d, w);
+        else run_held<MODEL_ID, CTRL, INTEG>(rec, a, d, w);
+    }
+}
+
+template <int MODELS, int CTRL, int INTEG>
+__global__ __launch_bounds__(256) void k_step_lane(StepArgs a) {
+    const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= (size_t)a.D) return;
+    const int w = a.drone_world[d];
+    const SoaRec rec{a.par_soa, a.M, w};
+    if constexpr (MODELS == MS_FP) run_held<MODEL_FP, CTRL, INTEG>(rec, a, d, w);
+    else run_held<MODEL_ID, CTRL, INTEG>(rec, a, d, w);
+}
+
+template <int MODELS, int CTRL, int INTEG>
+__global__ __launch_bounds__(256) void k_step_tile(StepArgs a, const int4* __restrict__ tiles) {
+    run_tile<MODELS, CTRL, INTEG>(a, tiles[blockIdx.x]);
+}
+
+// Persistent work queue: each workgroup pops the next tile index from *counter
+// until the tiles run out; every workgroup exits after one failed pop.
+template <int MODELS, int CTRL, int INTEG>
+__global__ __launch_bounds__(256) void k_step_wq(StepArgs a, const int4* __restrict__ tiles, int n_tiles,
+                                                 unsigned* counter) {
+    __shared__ int s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_next);
+        __syncthreads();
+        if (t >= n_tiles) break;
+        run_tile<MODELS, CTRL, INTEG>(a, tiles[t]);
+    }
+}
+
+template <int MODELS, int CTRL, int INTEG>
+static hipError_t launch_step_t(const KernelSel& ks, const StepArgs& a, const int4* tiles, int n_tiles,
+                                unsigned* counter, int wq_blocks, hipStream_t s) {
+    if (ks.mode == LM_LANE) {
+        if constexpr (MODELS == MS_BOTH) return hipErrorInvalidValue;
+        const int bs = ks.tile;
+        const unsigned grid = (unsigned)((a.D + bs - 1) / bs);
+        hipLaunchKernelGGL((k_step_lane<MODELS, CTRL, INTEG>), dim3(grid), dim3(bs), 0, s, a);
+    } else if (ks.mode == LM_TILE) {
+        hipLaunchKernelGGL((k_step_tile<MODELS, CTRL, INTEG>), dim3(n_tiles), dim3(ks.tile), 0, s, a, tiles);
+    } else {
+        hipLaunchKernelGGL((k_step_wq<MODELS, CTRL, INTEG>), dim3(wq_blocks), dim3(ks.tile), 0, s, a, tiles,
+                           n_tiles, counter);
+    }
+    return hipGetLastError();
+}
+
+template <int MODELS, int CTRL, int INTEG>
+static int wq_blocks_t(int tile) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq<MODELS, CTRL, INTEG>, tile, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+#define CF_DISPATCH(FN, ...)                                                             \
+    switch (ks.models * 4 + ks.ctrl * 2 + ks.integ) {                                    \
+        case MS_FP * 4 + 0: return FN<MS_FP, CTRL_ROTOR, EULER>(__VA_ARGS__);            \
+        case MS_FP * 4 + 1: return FN<MS_FP, CTRL_ROTOR, RK4>(__VA_ARGS__);              \
+        case MS_FP * 4 + 2: return FN<MS_FP, CTRL_PID, EULER>(__VA_ARGS__);              \
+        case MS_FP * 4 + 3: return FN<MS_FP, CTRL_PID, RK4>(__VA_ARGS__);                \
+        case MS_ID * 4 + 0: case MS_ID * 4 + 2: return FN<MS_ID, CTRL_ROTOR, EULER>(__VA_ARGS__); \
+        case MS_ID * 4 + 1: case MS_ID * 4 + 3: return FN<MS_ID, CTRL_ROTOR, RK4>(__VA_ARGS__);   \
+        case MS_BOTH * 4 + 0: return FN<MS_BOTH, CTRL_ROTOR, EULER>(__VA_ARGS__);        \
+        case MS_BOTH * 4 + 1: return FN<MS_BOTH, CTRL_ROTOR, RK4>(__VA_ARGS__);          \
+        case MS_BOTH * 4 + 2: return FN<MS_BOTH, CTRL_PID, EULER>(__VA_ARGS__);          \
+        case MS_BOTH * 4 + 3: return FN<MS_BOTH, CTRL_PID, RK4>(__VA_ARGS__);            \
+        default: break;                                                                  \
+    }
+
+hipError_t launch_step(const KernelSel& ks, const StepArgs& a, const int4* tiles, int n_tiles,
+                       unsigned* counter, int wq_blocks, hipStream_t s) {
+    CF_DISPATCH(launch_step_t, ks, a, tiles, n_tiles, counter, wq_blocks, s)
+    return hipErrorInvalidValue;
+}
+
+int step_wq_blocks_per_cu(const KernelSel& ks) {
+    CF_DISPATCH(wq_blocks_t, ks.tile)
+    return 1;
+}
+
+}  // namespace cfk

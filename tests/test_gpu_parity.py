@@ -1,0 +1,304 @@
+"""GPU (HIP, FP32) vs FP64 oracle parity through the C ABI, on reduced versions of
+the five workloads that span several waves and a ragged tail, plus the edge
+cases of the interface."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from gpu_helpers import assert_grad_close, assert_states_close, dev, sample_drones
+from paper_2606_01478_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(w, flags=B.F_NO_AUTOTUNE_CACHE, **kw):
+    return B.Sim.from_workload(w, flags=flags | B.F_NO_AUTOTUNE_CACHE, **kw)
+
+
+def _oracle_traj(w):
+    return O.rollout_workload(w, keep_traj=True)
+
+
+@pytest.mark.parametrize("integ", [W.INTEG_RK4, W.INTEG_EULER])
+def test_fp_rotor_open_loop_rollout(gpu_lib, integ):
+    """Per-step rotor commands, 16 worlds x 1 drone, 500 steps."""
+    w = W.config1(seed=1, integrator=integ)
+    sim = _sim(w)
+    T = w.steps
+    x0, cmds = dev(w.x0), dev(w.cmds)
+    xT = torch.empty_like(x0)
+    traj = torch.empty((T + 1, sim.S, sim.D), device="cuda")
+    sim.rollout(x0, cmds, T, None, 50, x_T=xT, traj=traj)
+    torch.cuda.synchronize()
+    with torch.no_grad():
+        ref = O.rollout(O.Batch.from_workload(w), O.t64(w.x0), O.t64(w.cmds), T, with_loss=False, keep_traj=True)
+    assert_states_close(xT, ref["x"], w, what="x_T")
+    for t in (1, 10, 100, 250, T):
+        assert_states_close(traj[t], ref["traj"][t], w, what=f"traj[{t}]")
+    assert torch.equal(traj[T], xT)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_fp_pid_closed_loop_held(gpu_lib, plain):
+    """Attitude commands through the PID, 200 single-drone worlds, 1000 steps."""
+    w = W.small(2, seed=2)
+    sim = _sim(w, flags=B.F_PLAIN_KERNEL if plain else 0)
+    x = dev(w.x0)
+    sim.step_k(x, dev(w.cmds), w.steps)
+    torch.cuda.synchronize()
+    ref = O.simulate_held(w)
+    assert_states_close(x, ref, w)
+
+
+def test_plain_and_fused_agree(gpu_lib):
+    w = W.small(2, seed=3)
+    a, b = dev(w.x0), dev(w.x0)
+    _sim(w).step_k(a, dev(w.cmds), 300)
+    _sim(w, flags=B.F_PLAIN_KERNEL).step_k(b, dev(w.cmds), 300)
+    torch.cuda.synchronize()
+    rel = ((a - b).abs() / b.abs().clamp_min(1.0)).max().item()
+    assert rel <= 1e-6, rel
+
+
+@pytest.mark.parametrize("k_launch", [1, 10, 100])
+def test_id_swarm_chunks(gpu_lib, k_launch):
+    """Identified model, 3 worlds x 150 drones (tiles with a ragged tail), 1000
+    steps as 1000/k_launch fused launches of k_launch steps."""
+    w = W.small(3, seed=4)
+    sim = _sim(w)
+    x, u = dev(w.x0), dev(w.cmds)
+    for _ in range(w.steps // k_launch):
+        sim.step_k(x, u, k_launch)
+    torch.cuda.synchronize()
+    assert_states_close(x, O.simulate_held(w), w)
+
+
+@pytest.mark.parametrize("wq", [False, True])
+def test_uneven_mixed_models(gpu_lib, wq):
+    """Uneven drones per world, first-principles (PID) and identified worlds in one
+    handle, grid of per-world tiles or the persistent work queue."""
+    w = W.small(5, seed=5)
+    sim = _sim(w, flags=B.F_WORKQUEUE if wq else 0)
+    x = dev(w.x0)
+    sim.step_k(x, dev(w.cmds), w.steps)
+    torch.cuda.synchronize()
+    assert_states_close(x, O.simulate_held(w), w)
+
+
+def test_batch_composition_invariance(gpu_lib):
+    """A world gives bit-identical results alone or inside a larger batch."""
+    w = W.small(3, seed=6)
+    full = dev(w.x0)
+    _sim(w).step_k(full, dev(w.cmds), 200)
+    sub = W.subset(w, [1])
+    part = dev(sub.x0)
+    _sim(sub).step_k(part, dev(sub.cmds), 200)
+    torch.cuda.synchronize()
+    off = w.world_offsets()
+    assert torch.equal(full[:, off[1]:off[2]], part)
+
+
+def test_workqueue_deterministic_and_equal_to_grid(gpu_lib):
+    w = W.small(5, seed=7)
+    outs = []
+    for flags in (0, B.F_WORKQUEUE, B.F_WORKQUEUE):
+        x = dev(w.x0)
+        _sim(w, flags=flags).step_k(x, dev(w.cmds), 100)
+        outs.append(x)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[1], outs[2])
+
+
+def _rollout_grads(w, K, sim=None):
+    sim = sim or _sim(w)
+    T = w.steps
+    x0, cmds = dev(w.x0), dev(w.cmds)
+    gain = None if w.gain is None else dev(w.gain)
+    off = None if w.ref_offset is None else dev(w.ref_offset)
+    obj = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, ref_offset=off, w_u=w.w_u)
+    nseg = (T + K - 1) // K
+    ckpt = torch.empty((nseg, sim.S, sim.D), device="cuda")
+    loss = torch.empty(sim.D, device="cuda")
+    lw = torch.empty(sim.n_worlds, device="cuda")
+    xT = torch.empty_like(x0)
+    sim.rollout(x0, cmds, T, obj, K, ckpt=ckpt, x_T=xT, loss=loss, loss_world=lw)
+    g_cmds, g_x0 = torch.empty_like(cmds), torch.empty_like(x0)
+    g_gain = None if gain is None else torch.empty_like(gain)
+    sim.rollout_backward(x0, cmds, T, obj, K, ckpt, dloss=dev(w.dloss), g_cmds=g_cmds, g_x0=g_x0, g_gain=g_gain)
+    torch.cuda.synchronize()
+    return dict(loss=loss, loss_world=lw, x=xT, g_cmds=g_cmds, g_x0=g_x0, g_gain=g_gain, ckpt=ckpt)
+
+
+def _check_against_oracle(w, got):
+    ref = O.rollout_workload(w, with_grad=True)
+    lg, lr = got["loss"].double().cpu(), ref["loss"]
+    assert torch.all((lg - lr).abs() <= 1e-4 * lr.abs().clamp_min(1e-2)), (lg - lr).abs().max()
+    off = w.world_offsets()
+    lw = torch.tensor([float(lr[off[i]:off[i + 1]].sum()) for i in range(w.n_worlds)], dtype=torch.float64)
+    assert torch.all((got["loss_world"].double().cpu() - lw).abs() <= 1e-4 * lw.abs().clamp_min(1e-2))
+    assert_states_close(got["x"], ref["x"], w, what="x_T")
+    assert_grad_close(got["g_cmds"], ref["g_cmds"], "g_cmds")
+    S = w.x0.shape[0]
+    gx = got["g_x0"].double().cpu()
+    rx = ref["g_x0"]
+    if S > W.S_ID:
+        world = np.repeat(np.arange(w.n_worlds), w.drones_per_world)
+        idm = torch.as_tensor(w.model_per_world[world] == W.MODEL_ID)
+        gx[W.S_ID:, idm] = 0.0
+        rx = rx.clone()
+        rx[W.S_ID:, idm] = 0.0
+    assert_grad_close(gx, rx, "g_x0")
+    if w.gain is not None:
+        gg, rg = got["g_gain"].double().cpu(), ref["g_gain"]
+        for k in range(gg.shape[0]):
+            assert (gg[k] - rg[k]).norm() <= 1e-3 * rg[k].norm(), (k, (gg[k] - rg[k]).norm() / rg[k].norm())
+
+
+def test_identified_rollout_gradients(gpu_lib):
+    """Figure-eight tracking with a shared 4x13 gain: loss, per-world loss, x_T and
+    gradients w.r.t. commands, initial state and gain vs the oracle's autograd."""
+    w = W.small(4, seed=8)
+    _check_against_oracle(w, _rollout_grads(w, 25))
+
+
+def test_mixed_rollout_gradients(gpu_lib):
+    """First-principles (PID, S=25) and identified worlds, uneven sizes, one gain
+    per model, per-drone figure-eight offsets."""
+    w = W.config5_adjoint(seed=9, n_worlds=12, n_subset=8, steps=120, n_max=70)
+    _check_against_oracle(w, _rollout_grads(w, 40))
+
+
+def test_fp_rotor_rollout_gradients(gpu_lib):
+    w = W.config1(seed=10, n_worlds=70, steps=60)
+    w.ref_offset = w.x0[0:3].copy()
+    w.dloss = np.linspace(0.5, 1.5, 70).astype(np.float32)
+    w.w_u = 1e-9
+    _check_against_oracle(w, _rollout_grads(w, 16))
+
+
+def test_checkpoint_interval_invariance(gpu_lib):
+    w = W.small(4, seed=11)
+    base = _rollout_grads(w, 100)
+    for K in (25, 50, 7):
+        g = _rollout_grads(w, K)
+        for k in ("loss", "g_cmds", "g_x0", "g_gain"):
+            a, b = g[k], base[k]
+            assert ((a - b).abs().max() <= 1e-6 * b.abs().max()).item(), (K, k)
+
+
+def test_autograd_function(gpu_lib):
+    w = W.small(4, seed=12)
+    sim = _sim(w)
+    x0 = dev(w.x0).requires_grad_(True)
+    cmds = dev(w.cmds).requires_grad_(True)
+    gain = dev(w.gain).requires_grad_(True)
+    loss = B.RolloutLoss.apply(x0, cmds, gain, sim, w.steps, 25,
+                               dict(ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u))
+    (loss * dev(w.dloss)).sum().backward()
+    ref = O.rollout_workload(w, with_grad=True)
+    assert_grad_close(cmds.grad, ref["g_cmds"], "g_cmds")
+    assert_grad_close(x0.grad, ref["g_x0"], "g_x0")
+    assert (gain.grad.double().cpu() - ref["g_gain"]).norm() <= 1e-3 * ref["g_gain"].norm()
+
+
+def test_backward_rejects_foreign_checkpoints(gpu_lib):
+    w = W.small(4, seed=13)
+    sim = _sim(w)
+    g = _rollout_grads(w, 25, sim=sim)
+    x0, cmds = dev(w.x0), dev(w.cmds)
+    obj = B.Sim.objective(gain=dev(w.gain), w_u=w.w_u)
+    other = torch.empty_like(g["ckpt"])
+    with pytest.raises(B.CfError) as ei:
+        sim.rollout_backward(x0, cmds, w.steps, obj, 25, other, g_cmds=torch.empty_like(cmds))
+    assert ei.value.status == B.CF_ESTATE
+    # same buffer, different checkpoint interval: refused by the library itself
+    gc = torch.empty_like(cmds)
+    st = sim._lib.cf_rollout_backward(sim._h, x0.data_ptr(), cmds.data_ptr(), w.steps, ctypes.byref(obj), 50,
+                                      g["ckpt"].data_ptr(), None, gc.data_ptr(), None, None)
+    assert st == B.CF_ESTATE
+
+
+def test_masked_reset(gpu_lib):
+    w = W.small(5, seed=14)
+    sim = _sim(w)
+    x = dev(w.x0)
+    init = x.clone()
+    sim.step_k(x, dev(w.cmds), 20)
+    moved = x.clone()
+    mask = torch.zeros(w.n_worlds, dtype=torch.uint8, device="cuda")
+    mask[[1, 4, 7]] = 1
+    sim.reset(x, init, mask)
+    torch.cuda.synchronize()
+    off = w.world_offsets()
+    for i in range(w.n_worlds):
+        sl = slice(off[i], off[i + 1])
+        expect = init[:, sl] if i in (1, 4, 7) else moved[:, sl]
+        assert torch.equal(x[:, sl], expect), i
+    sim.reset(x, init)
+    assert torch.equal(x, init)
+
+
+def test_nonfinite_flag(gpu_lib):
+    w = W.small(5, seed=15)
+    sim = _sim(w, flags=B.F_NONFINITE_CHECK)
+    x = dev(w.x0)
+    off = w.world_offsets()
+    x[7, off[3]] = float("nan")
+    flag = torch.zeros(w.n_worlds, dtype=torch.int32, device="cuda")
+    sim.step_k(x, dev(w.cmds), 5, nonfinite=flag)
+    torch.cuda.synchronize()
+    f = flag.cpu().numpy()
+    assert f[3] == 1 and f.sum() == 1
+
+
+def test_graph_replay_matches_eager(gpu_lib):
+    """hipGraph replays of a captured 30-step sequence, with eager work and
+    synchronisation between replays, give the eager result every time."""
+    w = W.small(5, seed=16)
+    eager = _sim(w)
+    graph = _sim(w, flags=B.F_GRAPH | B.F_WORKQUEUE)
+    xe, xg, u = dev(w.x0), dev(w.x0), dev(w.cmds)
+    for r in range(4):
+        eager.step_k(xe, u, 30)
+        graph.step_k(xg, u, 30)
+        torch.cuda.synchronize()
+        _ = (xe * 2).sum().item()
+        assert torch.equal(xe, xg), r
+
+
+def test_empty_worlds_and_ragged_counts(gpu_lib):
+    w = W.small(5, seed=17)
+    counts = w.drones_per_world.copy()
+    counts[[0, 5]] = 0
+    keep = np.concatenate([np.arange(o, o + c) for o, c in zip(w.world_offsets()[:-1], counts)])
+    w2 = W.subset(w, np.arange(w.n_worlds))
+    w2.drones_per_world = counts
+    w2.x0 = np.ascontiguousarray(w.x0[:, keep])
+    w2.cmds = np.ascontiguousarray(w.cmds[:, keep])
+    sim = _sim(w2)
+    x = dev(w2.x0)
+    sim.step_k(x, dev(w2.cmds), 50)
+    torch.cuda.synchronize()
+    assert_states_close(x, O.simulate_held(w2, steps=50), w2)
+
+
+def test_invalid_device_arguments_are_rejected(gpu_lib):
+    w = W.small(2, seed=18)
+    sim = _sim(w)
+    x = dev(w.x0)
+    short = torch.empty((sim.S, sim.D - 1), device="cuda")
+    with pytest.raises(ValueError):
+        sim.step_k(short, dev(w.cmds), 1)
+    # a host pointer is not device memory: the library refuses it before launching
+    host = np.zeros((sim.S, sim.D), np.float32)
+    st = sim._lib.cf_step_k(sim._h, host.ctypes.data, dev(w.cmds).data_ptr(), 1, None)
+    assert st == B.CF_EINVAL
+    with pytest.raises(B.CfError):
+        sim.step_k(x, dev(w.cmds), 0)
+    with pytest.raises(B.CfError):
+        sim.reset(x, x)
+    assert sim.last_error() == B.CF_OK
