@@ -167,8 +167,8 @@ def main():
         offs = w.world_offsets()
         for i in range(w.n_worlds):
             sub = W.subset(w, [i])
-            handles.append((B.Sim.from_workload(sub, flags=B.F_PLAIN_KERNEL | B.F_NO_AUTOTUNE_CACHE),
-                            state[:, offs[i]:offs[i + 1]].clone(), cmd[:, offs[i]:offs[i + 1]].contiguous()))
+            h = B.Sim.from_workload(sub, flags=B.F_PLAIN_KERNEL | B.F_NO_AUTOTUNE_CACHE)
+            handles.append((h, state[:h.S, offs[i]:offs[i + 1]].clone(), cmd[:, offs[i]:offs[i + 1]].contiguous()))
         n_loop = 5
         torch.cuda.synchronize()
         a, b = ev(), ev()

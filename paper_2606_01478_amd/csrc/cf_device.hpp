@@ -343,16 +343,20 @@ __device__ __forceinline__ void pid_vjp(const float* x, const FpParams& P, const
 }
 
 // ---------------------------------------------------------------------------
-// integrators over an N-component state with a rates functor rates(xin, xdot)
-template <int N, int INTEG, class Rates>
-__device__ __forceinline__ void integrate(float* x, float h, const Rates& rates) {
+// integrators over an N-component state with a rates functor rates(xin, xdot).
+// Rows set in MASK take the final update x += d with compensated (Kahan)
+// summation; c[] carries each row's lost low-order part from step to step while
+// the state stays in registers (rotor speeds ~1e4 and growing positions and
+// velocities would otherwise drop increments below half an FP32 ulp).
+template <int N, int INTEG, uint32_t MASK, class Rates>
+__device__ __forceinline__ void integrate(float* x, float* c, float h, const Rates& rates) {
+    float k[N], d[N];
     if constexpr (INTEG == EULER) {
-        float k[N];
         rates(x, k);
 #pragma unroll
-        for (int i = 0; i < N; ++i) x[i] += h * k[i];
+        for (int i = 0; i < N; ++i) d[i] = h * k[i];
     } else {
-        float k[N], acc[N], xs[N];
+        float acc[N], xs[N];
         const float h2 = 0.5f * h, h6 = h * (1.0f / 6.0f);
         rates(x, k);
 #pragma unroll
@@ -365,9 +369,26 @@ __device__ __forceinline__ void integrate(float* x, float h, const Rates& rates)
         for (int i = 0; i < N; ++i) { acc[i] += 2.f * k[i]; xs[i] = x[i] + h * k[i]; }
         rates(xs, k);
 #pragma unroll
-        for (int i = 0; i < N; ++i) x[i] += h6 * (acc[i] + k[i]);
+        for (int i = 0; i < N; ++i) d[i] = h6 * (acc[i] + k[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if ((MASK >> i) & 1u) {
+            const float y = d[i] - c[i];
+            const float t = x[i] + y;
+            c[i] = (t - x[i]) - y;
+            x[i] = t;
+        } else {
+            x[i] += d[i];
+        }
     }
 }
+
+// rows with compensated updates: position, velocity, rotor speeds (first
+// principles); position, velocity (identified)
+constexpr uint32_t COMP_FP = 0x7u | (0x7u << 7) | (0xFu << 13);
+constexpr uint32_t COMP_ID = 0x7u | (0x7u << 6);
+constexpr uint32_t COMP_NONE = 0u;
 
 // VJP of one integration step y = Phi(x) with the command held.
 // yb: adjoint of y (N). Writes xb = (dPhi/dx)^T yb; the command adjoint is
@@ -419,8 +440,8 @@ __device__ __forceinline__ void integrate_vjp(const float* x, float h, const flo
 
 // first-principles step; S = 17 (rotor interface) or 25 (attitude PID)
 template <int CTRL, int INTEG>
-__device__ __forceinline__ void fp_step(float* x, const float* u, const FpParams& P, const PidParams& C,
-                                        float dt, float inv_dt, int renorm) {
+__device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, const FpParams& P,
+                                        const PidParams& C, float dt, float inv_dt, int renorm) {
     float rc[4];
     float cs[8];
     if constexpr (CTRL == CTRL_PID) {
@@ -430,7 +451,7 @@ __device__ __forceinline__ void fp_step(float* x, const float* u, const FpParams
 #pragma unroll
         for (int i = 0; i < 4; ++i) rc[i] = u[i];
     }
-    integrate<S_FP, INTEG>(x, dt, [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
+    integrate<S_FP, INTEG, COMP_FP>(x, comp, dt, [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
     if (renorm) {
         const float n2 = x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6];
         const float inv = 1.0f / sqrtf(n2);
@@ -443,8 +464,8 @@ __device__ __forceinline__ void fp_step(float* x, const float* u, const FpParams
 }
 
 template <int INTEG>
-__device__ __forceinline__ void id_step(float* x, const float* u, const IdParams& P, float dt) {
-    integrate<S_ID, INTEG>(x, dt, [&](const float* xi, float* xd) { id_rates(xi, u, P, xd); });
+__device__ __forceinline__ void id_step(float* x, float* comp, const float* u, const IdParams& P, float dt) {
+    integrate<S_ID, INTEG, COMP_ID>(x, comp, dt, [&](const float* xi, float* xd) { id_rates(xi, u, P, xd); });
 }
 
 // VJP of fp_step at (x, u): yb = adjoint of the new state (S components),
@@ -466,10 +487,10 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
     for (int i = 0; i < S_FP; ++i) yb17[i] = yb[i];
     if (renorm) {
         // forward once more to get the unnormalised quaternion
-        float y[S_FP];
+        float y[S_FP], c0[S_FP];
 #pragma unroll
-        for (int i = 0; i < S_FP; ++i) y[i] = x[i];
-        integrate<S_FP, INTEG>(y, dt, [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
+        for (int i = 0; i < S_FP; ++i) { y[i] = x[i]; c0[i] = 0.f; }
+        integrate<S_FP, INTEG, COMP_NONE>(y, c0, dt, [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
         const float n2 = y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6];
         const float inv = 1.0f / sqrtf(n2);
         const float q0 = y[3] * inv, q1 = y[4] * inv, q2 = y[5] * inv, q3 = y[6] * inv;

@@ -97,9 +97,10 @@ __device__ __forceinline__ void load_params(const R& rec, DroneParams& p) {
 }
 
 template <int MODEL, int CTRL, int INTEG>
-__device__ __forceinline__ void model_step(float* x, const float* u, const DroneParams& p, const RollArgs& a) {
-    if constexpr (MODEL == MODEL_FP) fp_step<CTRL, INTEG>(x, u, p.fp, p.pid, a.dt, a.inv_dt, a.renorm);
-    else id_step<INTEG>(x, u, p.id, a.dt);
+__device__ __forceinline__ void model_step(float* x, float* comp, const float* u, const DroneParams& p,
+                                           const RollArgs& a) {
+    if constexpr (MODEL == MODEL_FP) fp_step<CTRL, INTEG>(x, comp, u, p.fp, p.pid, a.dt, a.inv_dt, a.renorm);
+    else id_step<INTEG>(x, comp, u, p.id, a.dt);
 }
 
 template <int MODEL, int CTRL, int INTEG>
@@ -132,8 +133,10 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
     DroneParams p;
     load_params<MODEL, CTRL>(rec, p);
     const float f_hover = (MODEL == MODEL_ID) ? p.id.f_hover : 0.f;
-    float x[S];
+    float x[S], comp[S];
     load_rows<S>(a.x0, D, d, x);
+#pragma unroll
+    for (int i = 0; i < S; ++i) comp[i] = 0.f;
     float off[3] = {0.f, 0.f, 0.f};
     if (a.has_obj && a.ref_off) {
 #pragma unroll
@@ -147,7 +150,7 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
         float u[4], ev[13];
         applied_command<MODEL>(a, G, x, t, off, f_hover, d, u, ev);
         if (a.has_obj) loss += a.w_u * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3]);
-        model_step<MODEL, CTRL, INTEG>(x, u, p, a);
+        model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a);
         if (a.has_obj) {
             float pr[3];
             ref_pos(a, t + 1, off, pr);
@@ -198,14 +201,16 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
     for (int s = nseg - 1; s >= 0; --s) {
         const int t0 = s * a.K;
         const int t1 = min(a.T, t0 + a.K);
-        float x[S];
+        float x[S], comp[S];
         load_rows<S>(a.ckpt_in + (size_t)s * SD, D, d, x);
+#pragma unroll
+        for (int i = 0; i < S; ++i) comp[i] = 0.f;
         // recompute the segment, keeping x_t for t in [t0, t1)
         for (int t = t0; t < t1; ++t) {
             store_rows<S>(a.seg + (size_t)(t - t0) * SD, D, d, x);
             float u[4], ev[13];
             applied_command<MODEL>(a, G, x, t, off, f_hover, d, u, ev);
-            model_step<MODEL, CTRL, INTEG>(x, u, p, a);
+            model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a);
         }
         float pn[3] = {x[0], x[1], x[2]};  // position of x_{t+1}
         for (int t = t1 - 1; t >= t0; --t) {

@@ -16,12 +16,14 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
         const FpParams P = load_fp(rec);
         PidParams C;
         if constexpr (CTRL == CTRL_PID) C = load_pid(rec);
-        float x[S], u[4];
+        float x[S], u[4], comp[S_FP];
 #pragma unroll
         for (int i = 0; i < S; ++i) x[i] = a.st[i * D + d];
 #pragma unroll
+        for (int i = 0; i < S_FP; ++i) comp[i] = 0.f;
+#pragma unroll
         for (int i = 0; i < 4; ++i) u[i] = a.cmd[i * D + d];
-        for (int k = 0; k < a.K; ++k) fp_step<CTRL, INTEG>(x, u, P, C, a.dt, a.inv_dt, a.renorm);
+        for (int k = 0; k < a.K; ++k) fp_step<CTRL, INTEG>(x, comp, u, P, C, a.dt, a.inv_dt, a.renorm);
 #pragma unroll
         for (int i = 0; i < S; ++i) {
             a.st[i * D + d] = x[i];
@@ -29,12 +31,12 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
         }
     } else {
         const IdParams P = load_id(rec);
-        float x[S_ID], u[4];
+        float x[S_ID], u[4], comp[S_ID];
 #pragma unroll
-        for (int i = 0; i < S_ID; ++i) x[i] = a.st[i * D + d];
+        for (int i = 0; i < S_ID; ++i) { x[i] = a.st[i * D + d]; comp[i] = 0.f; }
 #pragma unroll
         for (int i = 0; i < 4; ++i) u[i] = a.cmd[i * D + d];
-        for (int k = 0; k < a.K; ++k) id_step<INTEG>(x, u, P, a.dt);
+        for (int k = 0; k < a.K; ++k) id_step<INTEG>(x, comp, u, P, a.dt);
 #pragma unroll
         for (int i = 0; i < S_ID; ++i) {
             a.st[i * D + d] = x[i];

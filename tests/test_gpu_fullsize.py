@@ -1,0 +1,164 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times:
+every drone where the oracle finishes in seconds, otherwise drones sampled one
+by one (drones never interact) plus properties that hold at any size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from gpu_helpers import assert_grad_close, assert_states_close, dev, sample_drones
+from paper_2606_01478_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+
+def test_closed_loop_4096_worlds_all_drones(gpu_lib):
+    w = W.config2()
+    sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
+    x = dev(w.x0)
+    sim.step_k(x, dev(w.cmds), w.steps)
+    torch.cuda.synchronize()
+    assert_states_close(x, O.simulate_held(w), w, what="config2 x_1000")
+
+
+def test_swarm_64x4000_chunkings_and_samples(gpu_lib):
+    w = W.config3()
+    sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
+    u = dev(w.cmds)
+    outs = {}
+    for k in (1, 10, 100, 1000):
+        x = dev(w.x0)
+        for _ in range(w.steps // k):
+            sim.step_k(x, u, k)
+        outs[k] = x
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(0).choice(w.n_drones_total, 256, replace=False)
+    ws = sample_drones(w, idx)
+    ref = O.simulate_held(ws)
+    ii = torch.as_tensor(idx, device="cuda")
+    for k in (1, 10, 100, 1000):
+        assert_states_close(outs[k][:, ii], ref, ws, what=f"config3 sampled, {k} steps per launch")
+        assert_states_close(outs[k], outs[1000], w, what=f"config3 all drones, {k} vs 1000 steps per launch")
+
+
+@pytest.mark.parametrize("K", [25, 50, 100])
+def test_differentiable_1024_worlds(gpu_lib, K):
+    w = W.config4()
+    sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
+    T = w.steps
+    x0, cmds, gain = dev(w.x0), dev(w.cmds), dev(w.gain)
+    obj = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u)
+    ckpt = torch.empty(((T + K - 1) // K, sim.S, sim.D), device="cuda")
+    loss = torch.empty(sim.D, device="cuda")
+    sim.rollout(x0, cmds, T, obj, K, ckpt=ckpt, loss=loss)
+    g_cmds, g_x0, g_gain = torch.empty_like(cmds), torch.empty_like(x0), torch.empty_like(gain)
+    sim.rollout_backward(x0, cmds, T, obj, K, ckpt, dloss=dev(w.dloss), g_cmds=g_cmds, g_x0=g_x0, g_gain=g_gain)
+    torch.cuda.synchronize()
+    if K != 50:
+        return  # the oracle comparison is done once; other K are checked against K = 50 below
+    ref = O.rollout_workload(w, with_grad=True)
+    lr = ref["loss"]
+    assert torch.all((loss.double().cpu() - lr).abs() <= 1e-4 * lr.abs().clamp_min(1e-2))
+    assert_grad_close(g_cmds, ref["g_cmds"], "config4 g_cmds")
+    assert_grad_close(g_x0, ref["g_x0"], "config4 g_x0")
+    assert (g_gain.double().cpu() - ref["g_gain"]).norm() <= 1e-3 * ref["g_gain"].norm()
+
+
+def test_differentiable_checkpoint_invariance_full(gpu_lib):
+    w = W.config4()
+    sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
+    T = w.steps
+    x0, cmds, gain = dev(w.x0), dev(w.cmds), dev(w.gain)
+    obj = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u)
+    res = {}
+    for K in (25, 50, 100):
+        ckpt = torch.empty(((T + K - 1) // K, sim.S, sim.D), device="cuda")
+        sim.rollout(x0, cmds, T, obj, K, ckpt=ckpt)
+        g = [torch.empty_like(cmds), torch.empty_like(x0), torch.empty_like(gain)]
+        sim.rollout_backward(x0, cmds, T, obj, K, ckpt, g_cmds=g[0], g_x0=g[1], g_gain=g[2])
+        res[K] = g
+    torch.cuda.synchronize()
+    # the forward kernel and the adjoint's recompute loop are compiled separately,
+    # so states at segment boundaries may differ in the last bit between intervals
+    for K in (25, 100):
+        for a, b in zip(res[K], res[50]):
+            assert ((a - b).abs().max() <= 1e-6 * b.abs().max()).item(), K
+
+
+def test_uneven_2048_worlds_autotuned_launch(gpu_lib):
+    """Full uneven mixed batch (~1M drones) in the autotuned launch configuration,
+    512 drones sampled against the oracle; grid and work queue give the same bits."""
+    w = W.config5()
+    sim = B.Sim.from_workload(w)
+    x = dev(w.x0)
+    u = dev(w.cmds)
+    sim.autotune(x, u, w.steps, 1500)
+    sim.step_k(x, u, w.steps)
+    xq = dev(w.x0)
+    B.Sim.from_workload(w, flags=B.F_WORKQUEUE | B.F_NO_AUTOTUNE_CACHE).step_k(xq, u, w.steps)
+    torch.cuda.synchronize()
+    assert torch.equal(x, xq)
+    idx = np.random.default_rng(1).choice(w.n_drones_total, 512, replace=False)
+    ws = sample_drones(w, idx)
+    assert_states_close(x[:, torch.as_tensor(idx, device="cuda")], O.simulate_held(ws), ws, what="config5 sampled")
+
+
+def test_uneven_adjoint_subset_full(gpu_lib):
+    """256-world subset, T = 1000: per-drone gradients on sampled drones vs the
+    oracle; the gain gradient against sum_t sum_d g_cmds[t] e_t^T computed from
+    the full trajectory (an identity that holds at any size)."""
+    w = W.config5_adjoint()
+    sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
+    T, K = w.steps, 50
+    x0, cmds, gain, off = dev(w.x0), dev(w.cmds), dev(w.gain), dev(w.ref_offset)
+    obj = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, ref_offset=off, w_u=w.w_u)
+    ckpt = torch.empty(((T + K - 1) // K, sim.S, sim.D), device="cuda")
+    traj = torch.empty((T + 1, sim.S, sim.D), device="cuda")
+    loss = torch.empty(sim.D, device="cuda")
+    sim.rollout(x0, cmds, T, obj, K, ckpt=ckpt, traj=traj, loss=loss)
+    g_cmds, g_x0, g_gain = torch.empty_like(cmds), torch.empty_like(x0), torch.empty_like(gain)
+    sim.rollout_backward(x0, cmds, T, obj, K, ckpt, dloss=dev(w.dloss), g_cmds=g_cmds, g_x0=g_x0, g_gain=g_gain)
+    torch.cuda.synchronize()
+    # sampled drones vs the oracle
+    idx = np.random.default_rng(2).choice(w.n_drones_total, 48, replace=False)
+    ws = sample_drones(w, idx)
+    ref = O.rollout_workload(ws, with_grad=True)
+    ii = torch.as_tensor(idx, device="cuda")
+    lr = ref["loss"]
+    assert torch.all((loss[ii].double().cpu() - lr).abs() <= 1e-4 * lr.abs().clamp_min(1e-2))
+    assert_grad_close(g_cmds[:, :, ii], ref["g_cmds"], "config5 subset g_cmds")
+    gx, rx = g_x0[:, ii].double().cpu(), ref["g_x0"].clone()
+    idm = torch.as_tensor(ws.model_per_world == W.MODEL_ID)
+    gx[13:, idm] = 0
+    rx[13:, idm] = 0
+    assert_grad_close(gx, rx, "config5 subset g_x0")
+    # gain gradient identity on the full subset
+    world = np.repeat(np.arange(w.n_worlds), w.drones_per_world)
+    models = torch.as_tensor(w.model_per_world[world], device="cuda")
+    D = w.n_drones_total
+    t = torch.arange(T, device="cuda", dtype=torch.float64) * np.float32(w.dt)
+    w0 = 2 * np.pi / w.ref_period
+    xr = torch.zeros((T, 13, D), device="cuda", dtype=torch.float64)
+    xr[:, 0] = (w.ref_amp * torch.sin(w0 * t))[:, None]
+    xr[:, 1] = (0.5 * w.ref_amp * torch.sin(2 * w0 * t))[:, None]
+    xr[:, 0:3] += off.double()[None]
+    vx = (w.ref_amp * w0 * torch.cos(w0 * t))[:, None]
+    vy = (w.ref_amp * w0 * torch.cos(2 * w0 * t))[:, None]
+    fp = models == W.MODEL_FP
+    xr[:, 6] = torch.where(fp, 1.0, 0.0)
+    xr[:, 7] = torch.where(fp, vx, 0.0)
+    xr[:, 8] = torch.where(fp, vy, 0.0)
+    xr[:, 6] = torch.where(fp, xr[:, 6], vx)
+    xr[:, 7] = torch.where(fp, xr[:, 7], vy)
+    mg = torch.as_tensor(w.params["mass"][world, 0] * w.params["gravity"][world, 0] / np.where(
+        w.params["c_f"][world, 0] > 0, w.params["c_f"][world, 0], 1.0), device="cuda", dtype=torch.float64)
+    xr[:, 12] = torch.where(fp, xr[:, 12], mg[None])
+    e = traj[:T, 0:13].double() - xr
+    gidx = torch.as_tensor(w.gain_index[world], device="cuda")
+    for k in range(gain.shape[0]):
+        sel = gidx == k
+        gk = g_cmds[:, :, sel].double().permute(1, 0, 2).reshape(4, -1)
+        ek = e[:, :, sel].permute(1, 0, 2).reshape(13, -1).t().contiguous()
+        expect = gk @ ek
+        assert (g_gain[k].double() - expect).norm() <= 1e-3 * expect.norm(), k

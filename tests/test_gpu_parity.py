@@ -55,13 +55,15 @@ def test_fp_pid_closed_loop_held(gpu_lib, plain):
 
 
 def test_plain_and_fused_agree(gpu_lib):
+    """The fused kernel carries its compensated-summation terms across the steps it
+    keeps in registers; the plain kernel restarts them every launch. Both follow
+    the same discrete map, so they agree to the parity bar."""
     w = W.small(2, seed=3)
     a, b = dev(w.x0), dev(w.x0)
     _sim(w).step_k(a, dev(w.cmds), 300)
     _sim(w, flags=B.F_PLAIN_KERNEL).step_k(b, dev(w.cmds), 300)
     torch.cuda.synchronize()
-    rel = ((a - b).abs() / b.abs().clamp_min(1.0)).max().item()
-    assert rel <= 1e-6, rel
+    assert_states_close(b, a, w, what="plain vs fused")
 
 
 @pytest.mark.parametrize("k_launch", [1, 10, 100])
