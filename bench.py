@@ -9,8 +9,10 @@ attitude PID, half identified model, RK4 at dt = 2 ms):
   3. forward rollout (per-step commands, linear feedback, figure-eight
      tracking loss, checkpoints) and the hand-written adjoint on the seeded
      256-world subset, 1000 steps.
-value = (D * T + D_sub * T) / wall time of the step (drone-steps/s), inputs
-resident in HBM. Prints one JSON line.
+Part 3 is independent of parts 1-2 and runs on a second stream (default
+priority) so that its latency-bound adjoint fills SIMD slots the forward leaves
+idle. value = (D * T + D_sub * T) / wall time of the step (drone-steps/s),
+inputs resident in HBM. Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -29,8 +31,27 @@ import numpy as np  # noqa: E402
 # algorithmic FP32 operations per drone-step (add/sub/mul = 1, FMA = 2, each
 # sqrt/div/sin/cos/atan2/asin = 1), counted from the step's formulas
 FLOPS_PER_DS = {"fp_pid_rk4": 943.0, "fp_rotor_rk4": 802.0, "id_rk4": 317.0}
-SPEC_FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
+SPEC_FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak
 SPEC_HBM_GBS = 8000.0
+
+# HBM traffic of one held-command step launch over the whole batch, from two
+# rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
+# 256 MiB device copy gives), recorded in
+# profiles/k_step_tile_uneven_mixed_2048w_T1000.md; valid only for the kernel
+# sources it was measured on (SHA-256 below), reported as null otherwise.
+PROFILED_TRAFFIC = {"sources_sha256": "2c08b40cc11119eac640979451237c20e7f98a27703f156736d1e87e918c24d7",
+                    "bytes_per_launch": 220.5e6}
+
+
+def kernel_sources_sha256() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2606_01478_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -40,7 +61,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--seed", type=int, default=1005)
     p.add_argument("--horizon", type=int, default=1000)
-    p.add_argument("--ckpt", type=int, default=50)
+    p.add_argument("--ckpt", type=int, default=0, help="checkpoint interval; 0 = time 1, 10, 50, 100")
+    p.add_argument("--serial", action="store_true", help="run the subset adjoint after the forward")
     p.add_argument("--autotune-ms", type=int, default=3000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -73,34 +95,87 @@ def main():
     state = init.clone()
     cmd = t2d(w.cmds)
     mask = torch.ones(w.n_worlds, dtype=torch.uint8, device=dev)
-    sim.autotune(state, cmd, T, args.autotune_ms)
+    if args.autotune_ms > 0:
+        sim.autotune(state, cmd, T, args.autotune_ms)
     cfg = sim.launch_config()
 
     simA = B.Sim.from_workload(ws)
     x0s, cmds_s = t2d(ws.x0), t2d(ws.cmds)
     gain, off = t2d(ws.gain), t2d(ws.ref_offset)
     obj = B.Sim.objective(gain=gain, ref_amp=ws.ref_amp, ref_period=ws.ref_period, ref_offset=off, w_u=ws.w_u)
-    K = args.ckpt
-    nseg = (T + K - 1) // K
-    ckpt = torch.empty((nseg, simA.S, Ds), device=dev)
-    loss = torch.empty(Ds, device=dev)
-    loss_w = torch.empty(ws.n_worlds, device=dev)
     dloss = t2d(ws.dloss)
     g_cmds, g_x0, g_gain = torch.empty_like(cmds_s), torch.empty_like(x0s), torch.empty_like(gain)
-
+    loss = torch.empty(Ds, device=dev)
+    loss_w = torch.empty(ws.n_worlds, device=dev)
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
-    def one_step(record=None):
-        e = [ev() for _ in range(5)]
-        e[0].record()
-        sim.reset(state, init, mask)
-        e[1].record()
-        sim.step_k(state, cmd, T)
-        e[2].record()
+    def adjoint_buffers(K):
+        return torch.empty(((T + K - 1) // K, simA.S, Ds), device=dev)
+
+    def adjoint(K, ckpt):
         simA.rollout(x0s, cmds_s, T, obj, K, ckpt=ckpt, loss=loss, loss_world=loss_w)
-        e[3].record()
         simA.rollout_backward(x0s, cmds_s, T, obj, K, ckpt, dloss=dloss, g_cmds=g_cmds, g_x0=g_x0, g_gain=g_gain)
-        e[4].record()
+
+    # checkpoint interval: the caller's choice; here the fastest of a few
+    if args.ckpt > 0:
+        K = args.ckpt
+    else:
+        best = None
+        for Kc in (1, 10, 50, 100):
+            ck = adjoint_buffers(Kc)
+            adjoint(Kc, ck)
+            a, b = ev(), ev()
+            a.record()
+            adjoint(Kc, ck)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            if best is None or ms < best[1]:
+                best = (Kc, ms)
+            del ck
+        K = best[0]
+    ckpt = adjoint_buffers(K)
+    adjoint(K, ckpt)
+    a, b = ev(), ev()
+    a.record()
+    adjoint(K, ckpt)
+    b.record()
+    sim.step_k(state, cmd, T)
+    c = ev()
+    c.record()
+    torch.cuda.synchronize()
+    standalone = {"adjoint_fwd_bwd": a.elapsed_time(b), "forward": b.elapsed_time(c)}
+    side = torch.cuda.Stream(device=dev)   # default priority
+
+    def one_step(record=None):
+        e = [ev() for _ in range(6)]
+        main = torch.cuda.current_stream()
+        e[0].record(main)
+        if args.serial:
+            sim.reset(state, init, mask)
+            e[1].record(main)
+            sim.step_k(state, cmd, T)
+            e[2].record(main)
+            simA.rollout(x0s, cmds_s, T, obj, K, ckpt=ckpt, loss=loss, loss_world=loss_w)
+            e[3].record(main)
+            simA.rollout_backward(x0s, cmds_s, T, obj, K, ckpt, dloss=dloss, g_cmds=g_cmds, g_x0=g_x0,
+                                  g_gain=g_gain)
+            e[4].record(main)
+            e[5].record(main)
+        else:
+            side.wait_event(e[0])
+            with torch.cuda.stream(side):
+                e[2].record(side)
+                simA.rollout(x0s, cmds_s, T, obj, K, ckpt=ckpt, loss=loss, loss_world=loss_w)
+                e[3].record(side)
+                simA.rollout_backward(x0s, cmds_s, T, obj, K, ckpt, dloss=dloss, g_cmds=g_cmds, g_x0=g_x0,
+                                      g_gain=g_gain)
+                e[4].record(side)
+            sim.reset(state, init, mask)
+            e[1].record(main)
+            sim.step_k(state, cmd, T)
+            e[5].record(main)
+            main.wait_event(e[4])
         if record is not None:
             record.append(e)
 
@@ -116,7 +191,14 @@ def main():
     wall = time.perf_counter() - t0
     if sim.last_error() != 0 or simA.last_error() != 0:
         raise RuntimeError("device error during the timed region")
-    ph = np.array([[r[i].elapsed_time(r[i + 1]) for i in range(4)] for r in recs])  # ms
+    # per-phase durations from the events (ms); with overlap the forward is
+    # e[1]->e[5] on the main stream and the adjoint e[2]->e[4] on the side stream
+    if args.serial:
+        ph = np.array([[r[0].elapsed_time(r[1]), r[1].elapsed_time(r[2]), r[2].elapsed_time(r[3]),
+                        r[3].elapsed_time(r[4])] for r in recs])
+    else:
+        ph = np.array([[r[0].elapsed_time(r[1]), r[1].elapsed_time(r[5]), r[2].elapsed_time(r[3]),
+                        r[3].elapsed_time(r[4])] for r in recs])
     step_ms = wall * 1e3 / args.steps
     fwd_ms = float(ph[:, 1].mean())
     rf_ms, rb_ms = float(ph[:, 2].mean()), float(ph[:, 3].mean())
@@ -136,13 +218,17 @@ def main():
         "config": {"workload": "uneven_mixed_2048w_logu1-4000_T1000_plus_adjoint_256w",
                    "worlds": w.n_worlds, "drones": D, "horizon": T, "adjoint_worlds": ws.n_worlds,
                    "adjoint_drones": Ds, "ckpt_every": K, "integrator": "rk4", "dt": w.dt,
-                   "launch": cfg},
+                   "launch": cfg, "adjoint_overlapped": not args.serial},
         "fwd_drone_steps_per_s": D * T / (fwd_ms * 1e-3),
         "fwdbwd_drone_steps_per_s": Ds * T / ((rf_ms + rb_ms) * 1e-3),
         "phase_ms": {"reset": float(ph[:, 0].mean()), "forward": fwd_ms, "rollout_fwd": rf_ms,
                      "rollout_bwd": rb_ms, "forward_std": float(ph[:, 1].std())},
+        "standalone_ms": standalone,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": SPEC_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / SPEC_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "frac": achieved / SPEC_FP32_VECTOR_TFLOPS,
+                     "traffic": (PROFILED_TRAFFIC["bytes_per_launch"]
+                                 if kernel_sources_sha256() == PROFILED_TRAFFIC["sources_sha256"] else None),
+                     "algorithmic_bytes_per_launch": float(n_fp * (2 * W.S_FP_PID * 4 + 16) + n_id * (2 * W.S_ID * 4 + 16)),
                      "kernel": "k_step_wq/k_step_tile (held-command RK4 step, whole batch)",
                      "flops_per_launch": flops},
     }
@@ -161,7 +247,10 @@ def main():
         torch.cuda.synchronize()
         plain_ms = a.elapsed_time(b) / n_plain
         out["plain_kernel_drone_steps_per_s"] = D / (plain_ms * 1e-3)
-        out["plain_kernel_hbm_gbs"] = D * (2 * 25 * 4 + 16) / (plain_ms * 1e-3) / 1e9
+        # algorithmic bytes per drone-step: state in + out + held command
+        plain_bytes = n_fp * (2 * W.S_FP_PID * 4 + 16) + n_id * (2 * W.S_ID * 4 + 16)
+        out["plain_kernel_bytes_per_step"] = plain_bytes
+        out["plain_kernel_gbs"] = plain_bytes / (plain_ms * 1e-3) / 1e9
         # per-world loop of plain launches (one handle per world), a few steps
         handles = []
         offs = w.world_offsets()

@@ -777,8 +777,14 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
     a.g_cmds = g_cmds;
     a.g_x0 = g_x0;
     const int64_t Dm = std::max<int64_t>(h->D, 1);
-    if ((e = ensure(h->seg, (size_t)std::min(K, T) * h->S * Dm * sizeof(float))) != hipSuccess) return note(h, e);
-    a.seg = (float*)h->seg.p;
+    // segment slots 1..K-1 hold recomputed states (slot 0 is the checkpoint itself)
+    if (std::min(K, T) > 1) {
+        if ((e = ensure(h->seg, (size_t)std::min(K, T) * h->S * Dm * sizeof(float))) != hipSuccess)
+            return note(h, e);
+        a.seg = (float*)h->seg.p;
+    } else {
+        a.seg = nullptr;
+    }
     if (g_gain) {
         if ((e = ensure(h->ggc, (size_t)52 * Dm * sizeof(float))) != hipSuccess) return note(h, e);
         if ((e = ensure(h->wsum, (size_t)h->M * 52 * sizeof(float))) != hipSuccess) return note(h, e);

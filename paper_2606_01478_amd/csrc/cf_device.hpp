@@ -42,7 +42,7 @@ struct SoaRec {
 struct FpParams {
     float inv_m, g;
     float iJx, iJy, iJz, dJx, dJy, dJz;  // dJx = Jz - Jy, dJy = Jx - Jz, dJz = Jy - Jx
-    float k0, k1, k2, t0, t1, t2;
+    float k0, k1, k2, t0, t1, t2, inv_2k2;
     float tx[4], ty[4], tz[4];
     float cvu, cdu, cvd, cdd;
 };
@@ -64,6 +64,7 @@ __device__ __forceinline__ FpParams load_fp(const R& rec) {
     P.iJx = 1.0f / Jx; P.iJy = 1.0f / Jy; P.iJz = 1.0f / Jz;
     P.dJx = Jz - Jy; P.dJy = Jx - Jz; P.dJz = Jy - Jx;
     P.k0 = rec(P_THRUST); P.k1 = rec(P_THRUST + 1); P.k2 = rec(P_THRUST + 2);
+    P.inv_2k2 = 0.5f / P.k2;
     P.t0 = rec(P_TORQUE); P.t1 = rec(P_TORQUE + 1); P.t2 = rec(P_TORQUE + 2);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -104,6 +105,53 @@ __device__ __forceinline__ IdParams load_id(const R& rec) {
     }
     return P;
 }
+
+// ---------------------------------------------------------------------------
+// elementary functions
+
+// sin and cos of x together: Cody and Waite's argument reduction by pi/2 with a
+// three-part constant (r = x - k pi/2, |r| <= pi/4), Taylor polynomials of
+// degree 9 (sin) and 10 (cos) in r (truncation below 2e-9), and the quadrant
+// of k. About 1.4 ulp for |x| <= 2^15.
+__device__ __forceinline__ void sincos_cw(float x, float* s, float* c) {
+    const float k = __builtin_rintf(x * 0x1.45f306p-1f);          // x * 2/pi
+    float r = __builtin_fmaf(-k, 0x1.921fb6p+0f, x);              // pi/2, leading part
+    r = __builtin_fmaf(-k, -0x1.777a5cp-25f, r);                  // second part
+    r = __builtin_fmaf(-k, -0x1.0p-49f, r);                       // third part
+    const float z = r * r;
+    float ps = __builtin_fmaf(z, 0x1.71de3ap-19f, -0x1.a01a02p-13f);  // 1/9!, -1/7!
+    ps = __builtin_fmaf(z, ps, 0x1.111112p-7f);                        // 1/5!
+    ps = __builtin_fmaf(z, ps, -0x1.555556p-3f);                       // -1/3!
+    const float sv = __builtin_fmaf(r * z, ps, r);
+    float pc = __builtin_fmaf(z, -0x1.27e4fcp-22f, 0x1.a01a02p-16f);  // -1/10!, 1/8!
+    pc = __builtin_fmaf(z, pc, -0x1.6c16c2p-10f);                      // -1/6!
+    pc = __builtin_fmaf(z, pc, 0x1.555556p-5f);                        // 1/4!
+    pc = __builtin_fmaf(z, pc, -0.5f);
+    const float cv = __builtin_fmaf(z, pc, 1.0f);
+    const int q = (int)k;
+    float sr = (q & 1) ? cv : sv;
+    float cr = (q & 1) ? sv : cv;
+    *s = (q & 2) ? -sr : sr;
+    *c = ((q + 1) & 2) ? -cr : cr;
+}
+
+// sines and cosines of the three Euler angles; arguments beyond 2^15 rad (never
+// reached by the workloads) take the library routine for all three
+__device__ __forceinline__ void sincos3(const float* a, float* s, float* c) {
+    const float m = fmaxf(fabsf(a[0]), fmaxf(fabsf(a[1]), fabsf(a[2])));
+    if (__builtin_expect(m > 32768.f, 0)) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) sincosf(a[i], s + i, c + i);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) sincos_cw(a[i], s + i, c + i);
+    }
+}
+
+// hardware square root and reciprocal square root (within 1 ulp on gfx950)
+__device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float rsqrt_hw(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------------------
 // first-principles right-hand side, 17 components [p q v w Omega]
@@ -197,10 +245,9 @@ __device__ __forceinline__ void fp_rates_vjp(const float* x, const float* rc, co
 // ---------------------------------------------------------------------------
 // identified model right-hand side, 13 components [p Psi v dPsi f]
 __device__ __forceinline__ void id_rates(const float* x, const float* u, const IdParams& P, float* xd) {
-    float sph, cph, sth, cth, sps, cps;
-    sincosf(x[3], &sph, &cph);
-    sincosf(x[4], &sth, &cth);
-    sincosf(x[5], &sps, &cps);
+    float sn[3], cs[3];
+    sincos3(x + 3, sn, cs);
+    const float sph = sn[0], cph = cs[0], sth = sn[1], cth = cs[1], sps = sn[2], cps = cs[2];
     const float a = P.cf_m * x[12];
     xd[0] = x[6]; xd[1] = x[7]; xd[2] = x[8];
     xd[3] = x[9]; xd[4] = x[10]; xd[5] = x[11];
@@ -214,10 +261,9 @@ __device__ __forceinline__ void id_rates(const float* x, const float* u, const I
 
 __device__ __forceinline__ void id_rates_vjp(const float* x, const float* u, const IdParams& P,
                                              const float* gb, float* xb, float* ub) {
-    float sph, cph, sth, cth, sps, cps;
-    sincosf(x[3], &sph, &cph);
-    sincosf(x[4], &sth, &cth);
-    sincosf(x[5], &sps, &cps);
+    float sn[3], cs[3];
+    sincos3(x + 3, sn, cs);
+    const float sph = sn[0], cph = cs[0], sth = sn[1], cth = cs[1], sps = sn[2], cps = cs[2];
     const float a = P.cf_m * x[12];
     const float rz0 = cps * sth * cph + sps * sph;
     const float rz1 = sps * sth * cph - cps * sph;
@@ -251,7 +297,7 @@ struct PidTrace {
 };
 
 __device__ __forceinline__ float rotor_root(float f, float disc, const FpParams& P) {
-    return disc > 0.f ? (sqrtf(disc) - P.k1) / (2.f * P.k2) : -P.k1 / (2.f * P.k2);
+    return disc > 0.f ? (sqrt_hw(disc) - P.k1) * P.inv_2k2 : -P.k1 * P.inv_2k2;
 }
 
 // x: 25-component state; u: [roll, pitch, yawrate, thrust]. Writes rotor
@@ -302,7 +348,7 @@ __device__ __forceinline__ void pid_vjp(const float* x, const FpParams& P, const
     for (int j = 0; j < 4; ++j) {
         const float fr = tr.fraw[j];
         const bool pass = (fr >= 0.f) && (fr <= C.fmax) && (tr.disc[j] > 0.f);
-        const float fb = pass ? rcb[j] * (1.0f / sqrtf(tr.disc[j])) : 0.f;
+        const float fb = pass ? rcb[j] * rsqrt_hw(tr.disc[j]) : 0.f;
         ub[3] += C.A[4 * j] * fb;
         tqb[0] += C.A[4 * j + 1] * fb;
         tqb[1] += C.A[4 * j + 2] * fb;
@@ -331,10 +377,10 @@ __device__ __forceinline__ void pid_vjp(const float* x, const FpParams& P, const
     ub[0] += eab[0];
     ub[1] += eab[1];
     const float rollb = -eab[0], pitchb = -eab[1];
-    const float den = tr.s1 * tr.s1 + tr.c1 * tr.c1;
-    const float s1b = rollb * tr.c1 / den;
-    const float c1b = -rollb * tr.s1 / den;
-    const float s2b = (tr.s2 >= -1.f && tr.s2 <= 1.f) ? pitchb / sqrtf(1.f - tr.s2 * tr.s2) : 0.f;
+    const float iden = rcp_hw(tr.s1 * tr.s1 + tr.c1 * tr.c1);
+    const float s1b = rollb * tr.c1 * iden;
+    const float c1b = -rollb * tr.s1 * iden;
+    const float s2b = (tr.s2 >= -1.f && tr.s2 <= 1.f) ? pitchb * rsqrt_hw(1.f - tr.s2 * tr.s2) : 0.f;
     const float qx = x[3], qy = x[4], qz = x[5], qw = x[6];
     xb[3] += 2.f * qw * s1b - 4.f * qx * c1b - 2.f * qz * s2b;
     xb[4] += 2.f * qz * s1b - 4.f * qy * c1b + 2.f * qw * s2b;
@@ -391,13 +437,25 @@ constexpr uint32_t COMP_ID = 0x7u | (0x7u << 6);
 constexpr uint32_t COMP_NONE = 0u;
 
 // VJP of one integration step y = Phi(x) with the command held.
-// yb: adjoint of y (N). Writes xb = (dPhi/dx)^T yb; the command adjoint is
-// accumulated by vjp(xs, gb, xb_stage) into its own accumulator.
-// rates(xin, xdot); vjp(xin, gb, xb_add) adds (d rates/d xin)^T gb into xb_add.
-template <int N, int INTEG, class Rates, class Vjp>
-__device__ __forceinline__ void integrate_vjp(const float* x, float h, const float* yb, float* xb,
-                                              const Rates& rates, const Vjp& vjp) {
+// yb: adjoint of the step's output. post(y, yb) may rewrite yb using the
+// integrator output y before the reverse sweep (the renormalisation that
+// follows the step); it receives y only when NEED_Y. Writes
+// xb = (dPhi/dx)^T yb; vjp(xin, gb, xa) adds (d rates/d xin)^T gb into xa and
+// accumulates the command adjoint itself.
+template <int N, int INTEG, bool NEED_Y, class Rates, class Vjp, class Post>
+__device__ __forceinline__ void integrate_vjp(const float* x, float h, const float* yb_in, float* xb,
+                                              const Rates& rates, const Vjp& vjp, const Post& post) {
+    float yb[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) yb[i] = yb_in[i];
     if constexpr (INTEG == EULER) {
+        if constexpr (NEED_Y) {
+            float k[N], y[N];
+            rates(x, k);
+#pragma unroll
+            for (int i = 0; i < N; ++i) y[i] = x[i] + h * k[i];
+            post(y, yb);
+        }
         float gb[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) { xb[i] = yb[i]; gb[i] = h * yb[i]; }
@@ -406,17 +464,25 @@ __device__ __forceinline__ void integrate_vjp(const float* x, float h, const flo
         const float h2 = 0.5f * h;
         float x2[N], x3[N], x4[N], k[N];
         rates(x, k);
+        float acc[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) x2[i] = x[i] + h2 * k[i];
+        for (int i = 0; i < N; ++i) { x2[i] = x[i] + h2 * k[i]; acc[i] = k[i]; }
         rates(x2, k);
 #pragma unroll
-        for (int i = 0; i < N; ++i) x3[i] = x[i] + h2 * k[i];
+        for (int i = 0; i < N; ++i) { x3[i] = x[i] + h2 * k[i]; acc[i] += 2.f * k[i]; }
         rates(x3, k);
 #pragma unroll
-        for (int i = 0; i < N; ++i) x4[i] = x[i] + h * k[i];
+        for (int i = 0; i < N; ++i) { x4[i] = x[i] + h * k[i]; acc[i] += 2.f * k[i]; }
+        const float h6 = h * (1.0f / 6.0f), h3 = h * (1.0f / 3.0f);
+        if constexpr (NEED_Y) {
+            rates(x4, k);
+            float y[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) y[i] = x[i] + h6 * (acc[i] + k[i]);
+            post(y, yb);
+        }
         // reverse sweep: kb4 = h/6 yb, kb3 = h/3 yb + h a4, kb2 = h/3 yb + h/2 a3,
         // kb1 = h/6 yb + h/2 a2, with a_s = (d k_s / d x_s)^T kb_s
-        const float h6 = h * (1.0f / 6.0f), h3 = h * (1.0f / 3.0f);
         float gb[N], a[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) { xb[i] = yb[i]; gb[i] = h6 * yb[i]; a[i] = 0.f; }
@@ -454,7 +520,7 @@ __device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, c
     integrate<S_FP, INTEG, COMP_FP>(x, comp, dt, [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
     if (renorm) {
         const float n2 = x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6];
-        const float inv = 1.0f / sqrtf(n2);
+        const float inv = rsqrt_hw(n2);
         x[3] *= inv; x[4] *= inv; x[5] *= inv; x[6] *= inv;
     }
     if constexpr (CTRL == CTRL_PID) {
@@ -482,29 +548,24 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
 #pragma unroll
         for (int i = 0; i < 4; ++i) rc[i] = u[i];
     }
-    float yb17[S_FP];
-#pragma unroll
-    for (int i = 0; i < S_FP; ++i) yb17[i] = yb[i];
-    if (renorm) {
-        // forward once more to get the unnormalised quaternion
-        float y[S_FP], c0[S_FP];
-#pragma unroll
-        for (int i = 0; i < S_FP; ++i) { y[i] = x[i]; c0[i] = 0.f; }
-        integrate<S_FP, INTEG, COMP_NONE>(y, c0, dt, [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
-        const float n2 = y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6];
-        const float inv = 1.0f / sqrtf(n2);
-        const float q0 = y[3] * inv, q1 = y[4] * inv, q2 = y[5] * inv, q3 = y[6] * inv;
-        const float dot = q0 * yb[3] + q1 * yb[4] + q2 * yb[5] + q3 * yb[6];
-        yb17[3] = (yb[3] - q0 * dot) * inv;
-        yb17[4] = (yb[4] - q1 * dot) * inv;
-        yb17[5] = (yb[5] - q2 * dot) * inv;
-        yb17[6] = (yb[6] - q3 * dot) * inv;
-    }
     float rcb[4] = {0.f, 0.f, 0.f, 0.f};
-    integrate_vjp<S_FP, INTEG>(
-        x, dt, yb17, xb,
-        [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); },
-        [&](const float* xi, const float* gb, float* xa) { fp_rates_vjp(xi, rc, P, gb, xa, rcb); });
+    const auto rates = [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); };
+    const auto vjp = [&](const float* xi, const float* gb, float* xa) { fp_rates_vjp(xi, rc, P, gb, xa, rcb); };
+    if (renorm) {
+        // q_out = q / |q| after the step: qb <- (qb_out - q_out (q_out . qb_out)) / |q|
+        const auto post = [&](const float* y, float* ybr) {
+            const float inv = rsqrt_hw(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]);
+            const float q0 = y[3] * inv, q1 = y[4] * inv, q2 = y[5] * inv, q3 = y[6] * inv;
+            const float dot = q0 * ybr[3] + q1 * ybr[4] + q2 * ybr[5] + q3 * ybr[6];
+            ybr[3] = (ybr[3] - q0 * dot) * inv;
+            ybr[4] = (ybr[4] - q1 * dot) * inv;
+            ybr[5] = (ybr[5] - q2 * dot) * inv;
+            ybr[6] = (ybr[6] - q3 * dot) * inv;
+        };
+        integrate_vjp<S_FP, INTEG, true>(x, dt, yb, xb, rates, vjp, post);
+    } else {
+        integrate_vjp<S_FP, INTEG, false>(x, dt, yb, xb, rates, vjp, [](const float*, float*) {});
+    }
     if constexpr (CTRL == CTRL_PID) {
 #pragma unroll
         for (int i = S_FP; i < S_PID; ++i) xb[i] = 0.f;
@@ -518,10 +579,11 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
 template <int INTEG>
 __device__ __forceinline__ void id_step_vjp(const float* x, const float* u, const IdParams& P, float dt,
                                             const float* yb, float* xb, float* ub) {
-    integrate_vjp<S_ID, INTEG>(
+    integrate_vjp<S_ID, INTEG, false>(
         x, dt, yb, xb,
         [&](const float* xi, float* xd) { id_rates(xi, u, P, xd); },
-        [&](const float* xi, const float* gb, float* xa) { id_rates_vjp(xi, u, P, gb, xa, ub); });
+        [&](const float* xi, const float* gb, float* xa) { id_rates_vjp(xi, u, P, gb, xa, ub); },
+        [](const float*, float*) {});
 }
 
 }  // namespace cfk

@@ -201,18 +201,28 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
     for (int s = nseg - 1; s >= 0; --s) {
         const int t0 = s * a.K;
         const int t1 = min(a.T, t0 + a.K);
+        // recompute x_{t0+1} .. x_{t1-1} into segment slots 1..; slot 0 is the
+        // checkpoint itself. The state after the segment is the next checkpoint
+        // (only its position is needed); the last segment steps once more.
         float x[S], comp[S];
         load_rows<S>(a.ckpt_in + (size_t)s * SD, D, d, x);
 #pragma unroll
         for (int i = 0; i < S; ++i) comp[i] = 0.f;
-        // recompute the segment, keeping x_t for t in [t0, t1)
-        for (int t = t0; t < t1; ++t) {
-            store_rows<S>(a.seg + (size_t)(t - t0) * SD, D, d, x);
+        const int n_re = (s == nseg - 1) ? (t1 - t0) : (t1 - t0 - 1);
+        for (int j = 0; j < n_re; ++j) {
             float u[4], ev[13];
-            applied_command<MODEL>(a, G, x, t, off, f_hover, d, u, ev);
+            applied_command<MODEL>(a, G, x, t0 + j, off, f_hover, d, u, ev);
             model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a);
+            if (j + 1 < t1 - t0) store_rows<S>(a.seg + (size_t)(j + 1) * SD, D, d, x);
         }
-        float pn[3] = {x[0], x[1], x[2]};  // position of x_{t+1}
+        float pn[3];  // position of x_{t+1}
+        if (s == nseg - 1) {
+            pn[0] = x[0]; pn[1] = x[1]; pn[2] = x[2];
+        } else {
+            const float* nxt = a.ckpt_in + (size_t)(s + 1) * SD;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) pn[j] = nxt[j * D + d];
+        }
         for (int t = t1 - 1; t >= t0; --t) {
             if (a.has_obj) {
                 float pr[3];
@@ -220,7 +230,8 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
                 for (int j = 0; j < 3; ++j) lam[j] += two_seed * (pn[j] - pr[j]);
             }
-            load_rows<S>(a.seg + (size_t)(t - t0) * SD, D, d, x);
+            const float* src = (t > t0) ? a.seg + (size_t)(t - t0) * SD : a.ckpt_in + (size_t)s * SD;
+            load_rows<S>(src, D, d, x);
             float u[4], ev[13];
             applied_command<MODEL>(a, G, x, t, off, f_hover, d, u, ev);
             float xb[S];
