@@ -68,6 +68,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-comparators", action="store_true")
     p.add_argument("--copy-probe", action="store_true", help="also run a 256 MiB device copy (profile scale)")
+    p.add_argument("--no-mppi", action="store_true",
+                   help="skip the sampled-rollout controller measurement (5 x 100k samples x 25 steps)")
+    p.add_argument("--no-grad-bench", action="store_true",
+                   help="skip the gradient-throughput measurement (2^20 worlds, 10 steps)")
     return p.parse_args()
 
 
@@ -270,6 +274,11 @@ def main():
         for h, _, _ in handles:
             h.close()
 
+    if not args.no_grad_bench:
+        out["gradient_benchmark"] = gradient_benchmark(B, W, dev, t2d, ev)
+    if not args.no_mppi:
+        out["mppi"] = mppi_benchmark(B, W, dev, t2d, ev)
+
     if args.copy_probe:
         src = torch.empty(64 * 1024 * 1024, device=dev)
         dst = torch.empty_like(src)
@@ -279,6 +288,76 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def gradient_benchmark(B, W, dev, t2d, ev, reps=10):
+    """Gradients of a 10-step goal-distance loss w.r.t. the per-step commands and
+    the initial state for 2^20 single-drone closed-loop worlds: forward with one
+    checkpoint, then the adjoint; gradients/s = worlds / (forward + backward)."""
+    import torch
+    wg = W.gradient_goal()
+    T = wg.steps
+    sim = B.Sim.from_workload(wg)
+    x0, cmds, goal = t2d(wg.x0), t2d(wg.cmds), t2d(wg.ref_offset)
+    obj = B.Sim.objective(ref_amp=wg.ref_amp, ref_period=wg.ref_period, ref_offset=goal, w_u=wg.w_u)
+    ckpt = torch.empty((1, sim.S, sim.D), device=dev)
+    loss = torch.empty(sim.D, device=dev)
+    g_cmds, g_x0 = torch.empty_like(cmds), torch.empty_like(x0)
+
+    def once():
+        sim.rollout(x0, cmds, T, obj, T, ckpt=ckpt, loss=loss)
+        sim.rollout_backward(x0, cmds, T, obj, T, ckpt, g_cmds=g_cmds, g_x0=g_x0)
+
+    once()
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record()
+    for _ in range(reps):
+        once()
+    b.record()
+    torch.cuda.synchronize()
+    if sim.last_error() != 0:
+        raise RuntimeError("device error in the gradient benchmark")
+    ms = a.elapsed_time(b) / reps
+    sim.close()
+    return {"workload": "fp_pid_goal_gradient_2^20w_T10", "worlds": wg.n_worlds, "steps": T,
+            "ms_fwd_bwd": ms, "gradients_per_s": wg.n_worlds / (ms * 1e-3),
+            "drone_steps_per_s": wg.n_worlds * T / (ms * 1e-3), "reps": reps,
+            "paper_context": "9e6 gradients/s at 1e6 environments x 10 steps (other hardware)"}
+
+
+def mppi_benchmark(B, W, dev, t2d, ev, reps=20):
+    """Control steps of 5 sampled-rollout controllers x 100 000 samples x 25 steps
+    of the closed-loop first-principles model at 50 Hz (dt = 20 ms): sampling,
+    rollouts, costs, elite selection, weighted means and the command, with the
+    warm start shifted by one step per call."""
+    import torch
+    w, P, mean0 = W.mppi_task()
+    sim = B.Sim.from_workload(w)
+    mp = B.Mppi(sim, P)
+    x_now, mean = t2d(w.x0[:, 0]), t2d(mean0)
+    u = torch.empty(4, device=dev)
+    best = torch.empty(1, dtype=torch.int32, device=dev)
+    mp.step(x_now, mean, 0, 0, u_apply=u, best=best)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record()
+    for it in range(reps):
+        mp.step(x_now, mean, 1, it + 1, u_apply=u, best=best)
+    b.record()
+    torch.cuda.synchronize()
+    if sim.last_error() != 0:
+        raise RuntimeError("device error in the sampled-rollout controller")
+    ms = a.elapsed_time(b) / reps
+    n = P["n_controllers"] * P["n_samples"]
+    steps = n * P["horizon"] * P["substeps"]
+    mp.close()
+    sim.close()
+    return {"workload": "mppi_5x100k_H25_fp_pid_50Hz", "controllers": P["n_controllers"],
+            "samples": n, "horizon": P["horizon"], "elites_per_controller": P["n_elite"],
+            "ms_per_control_step": ms, "sim_steps_per_s": steps / (ms * 1e-3),
+            "max_rate_hz": 1e3 / ms, "reps": reps,
+            "paper_context": "500k samples x 25 steps at 50 Hz, > 0.5e9 steps/s (other hardware)"}
 
 
 def cpu_baseline(w, seconds):

@@ -54,6 +54,8 @@ typedef int32_t cf_status;
 #define CF_MODEL_ID      1
 #define CF_CTRL_ROTOR    0   /* FP command = rotor-speed setpoints Omega_cmd[4] */
 #define CF_CTRL_ATT_PID  1   /* FP command = [roll, pitch, yaw rate, thrust]    */
+#define CF_CTRL_TORQUE   2   /* FP command = [thrust, tau_x, tau_y, tau_z] through the
+                                motor allocation (CF_P_ALLOC, CF_P_F_MAX)       */
 #define CF_INTEG_EULER   0
 #define CF_INTEG_RK4     1
 
@@ -63,6 +65,9 @@ typedef int32_t cf_status;
 #define CF_F_GRAPH           0x4u  /* replay launch sequences from captured hipGraphs */
 #define CF_F_WORKQUEUE       0x8u  /* cf_step_k: persistent work-queue kernel (one launch) */
 #define CF_F_NO_AUTOTUNE_CACHE 0x10u /* do not read the autotune cache at create */
+#define CF_F_SINGLE_LAUNCH   0x20u  /* mixed-model handles: one launch for both models
+                                       (default: one launch per model, forked onto a
+                                       second stream and joined with events) */
 
 /*
  * State layout (rows of the [S][D] state):
@@ -73,10 +78,11 @@ typedef int32_t cf_status;
  *        19-21 body-rate-error integrals, 22-24 body rate of the previous step.
  *   ID:  0-2 p, 3-5 Euler angles (roll, pitch, yaw; R = Rz Ry Rx), 6-8 v,
  *        9-11 Euler-angle rates, 12 collective thrust state f_sum [N].
- * S = 17 (FP rotor), 25 (FP attitude), 13 (ID). A handle holding both models
+ * S = 17 (FP rotor or torque interface), 25 (FP attitude), 13 (ID). A handle holding both models
  * uses S = max; identified drones use rows 0..12 and leave the rest untouched.
  * Commands are [4][D]: FP rotor: Omega_cmd; FP attitude: [roll, pitch,
- * yaw rate, thrust]; ID: [roll, pitch, yaw, thrust].
+ * yaw rate, thrust]; FP torque: [thrust, tau_x, tau_y, tau_z]; ID: [roll,
+ * pitch, yaw, thrust].
  */
 #define CF_S_FP_ROTOR 17
 #define CF_S_FP_PID   25
@@ -98,8 +104,10 @@ typedef int32_t cf_status;
 #define CF_P_MIX_YAW    19   /* FP     tau_z = sum mix_yaw[i] torque_i [4]         */
 #define CF_P_MOTOR_UP   23   /* FP     c_v, c_d when Omega_cmd >= Omega [2]        */
 #define CF_P_MOTOR_DOWN 25   /* FP     c_v, c_d when Omega_cmd <  Omega [2]        */
-#define CF_P_JP         27   /* FP     propeller inertia J_p: must be 0 (see errors) */
-#define CF_P_DRAG       28   /* FP,ID  linear drag C_a diagonal: must be 0 [3]     */
+#define CF_P_JP         27   /* FP     propeller+motor inertia J_p >= 0 (gyroscopic and
+                                      reaction torques; spin directions are -sign(mix_yaw)) */
+#define CF_P_DRAG       28   /* FP,ID  linear body-frame drag C_a diagonal [3]: the force is
+                                      R C_a R^T v (entries <= 0 damp)               */
 #define CF_P_ANG_KP     31   /* PID    roll/pitch angle P gain [1/s] [2]           */
 #define CF_P_ANG_KI     33   /* PID    roll/pitch angle I gain [1/s^2] [2]         */
 #define CF_P_RATE_KP    35   /* PID    body-rate P gain [1/s] [3]                  */
@@ -158,9 +166,9 @@ typedef struct cf_objective {
  * to the device, choose kernel variants (autotune cache unless
  * CF_F_NO_AUTOTUNE_CACHE) and return a handle in *out (NULL on failure).
  * Errors: CF_EINVAL (NULL pointers, M < 1, negative drone counts, D > 2^31-1,
- * unknown enum, dt not finite or <= 0, mass/inertia/k2/c_f not > 0, gain
- * index out of range), CF_EUNSUPPORTED (non-zero J_p or drag), CF_ENODEV (no
- * device), CF_ENOMEM, CF_EDEVICE.
+ * unknown enum, dt not finite or <= 0, a non-finite parameter, mass/inertia/
+ * k2/c_f not > 0, J_p < 0, gain index out of range), CF_ENODEV (no device),
+ * CF_ENOMEM, CF_EDEVICE.
  */
 cf_status cf_create(const cf_desc* desc, cf_handle** out);
 
@@ -226,17 +234,98 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
  * persistent work queue, tile size, steps per launch K) on copies of state and
  * cmd (device [S][D], [4][D], not modified) for about budget_ms, keep the
  * fastest for this handle and store it in the autotune cache file
- * ($CFSIM_AUTOTUNE_CACHE, default $HOME/.cache/cfsim_autotune.json). Synchronises.
+ * ($CFSIM_AUTOTUNE_CACHE, default $HOME/.cache/cfsim_autotune.txt: one line per
+ * handle signature with the chosen shape and its time). Synchronises.
  */
 cf_status cf_autotune(cf_handle* h, const float* state, const float* cmd, int32_t k, int32_t budget_ms);
 
-/* Current launch choice (host): use_workqueue (0/1), tile (lanes per work item), chunk K. */
+/* Current launch choice (host): use_workqueue (bit 0: work queue; bit 1: one launch per
+   model on two streams), tile (lanes per work item), chunk K (0 = all k steps per launch). */
 cf_status cf_launch_config(const cf_handle* h, int32_t* use_workqueue, int32_t* tile, int32_t* chunk);
 
 const char* cf_strerror(cf_status status);
 
 /* cf_last_error: synchronise the stream and return the sticky device error (or CF_OK). */
 cf_status cf_last_error(cf_handle* h);
+
+/* ---- sampled-rollout controller ---------------------------------------------
+ * The iCEM/MPPI hybrid of the obstacle-avoidance showcase (Methods, section
+ * "Model Predictive Path Integral"; Results, MPPI paragraph): C independent
+ * controllers, each samples N command sequences of H steps around its previous
+ * mean with temporally correlated noise, rolls every sample through the
+ * simulator from the current state, keeps its n_e lowest-cost samples (the
+ * paper keeps the best 1 %) and replaces its mean by their exponentially
+ * weighted average; the controller with the lowest elite cost supplies the
+ * command. Per sample k of controller c at call `iteration`:
+ *   xi_t    standard normals: Philox4x64-10 with counter (t/2, k, c, iteration)
+ *           and key (seed, 0); each 64-bit output word w gives one Box-Muller
+ *           pair from u1 = ((lo32(w) >> 9) + 1/2) 2^-23, u2 = ((hi32(w) >> 9) +
+ *           1/2) 2^-23; words 0..3 give components 0..3 of step 2b and then of
+ *           step 2b+1 (in the order cos, sin of each pair);
+ *   eps_0 = xi_0, eps_t = beta eps_{t-1} + sqrt(1 - beta^2) xi_t; eps = 0 for k = 0;
+ *   u_t = clip(mean[c][min(t + shift, H - 1)] + sigma * eps_t, u_lo, u_hi);
+ *   x advanced `substeps` simulator steps per u_t (the handle's model,
+ *   interface, integrator and dt); cost
+ *   J = sum_t sum_i r_u[i] (u_t,i - u_ref[i])^2 + sum_{t=1..H} q_p |p_t - goal|^2
+ *       + q_v |v_t|^2 + w_obs sum_o max(0, 1 - |p_t - c_o|^2 / r_o^2)^2,
+ *   a non-finite J counted as +inf.
+ * Elites: the n_e smallest (J, k) pairs; new mean = sum w_k u_k / sum w_k with
+ * w_k = exp(-(J_k - J_min) / lambda). best = argmin_c J_min,c (lowest c on ties),
+ * u_apply = new mean[best][0].
+ */
+#define CF_MPPI_MAX_OBSTACLES 16
+#define CF_MPPI_MAX_ELITE 4096
+
+typedef struct cf_mppi cf_mppi;
+
+typedef struct cf_mppi_desc {
+    int32_t n_controllers;   /* 1 <= C <= 65535                                       */
+    int32_t n_samples;       /* N >= 1 per controller, C*N <= 2^31-1                  */
+    int32_t horizon;         /* H >= 1                                                */
+    int32_t substeps;        /* simulator steps per horizon step, >= 1               */
+    int32_t n_elite;         /* 1 <= n_e <= min(N, CF_MPPI_MAX_ELITE)                 */
+    float sigma[4];          /* noise scale per command component, >= 0               */
+    float beta;              /* temporal correlation, 0 <= beta < 1                   */
+    float lambda;            /* temperature of the elite weights, > 0                 */
+    float u_lo[4], u_hi[4];  /* command bounds, u_lo <= u_hi                          */
+    float u_ref[4], r_u[4];  /* command cost: reference and weight (>= 0)             */
+    float goal[3];           /* position goal [m]                                     */
+    float q_p, q_v, w_obs;   /* position, velocity and obstacle weights, >= 0         */
+    int32_t n_obstacles;     /* 0 .. CF_MPPI_MAX_OBSTACLES                            */
+    float obstacles[CF_MPPI_MAX_OBSTACLES][4];  /* centre [m], radius [m] (> 0)       */
+    uint64_t seed;           /* generator key                                         */
+} cf_mppi_desc;
+
+/*
+ * cf_mppi_create: a controller set for the single world of handle h (h must
+ * have n_worlds = 1; its parameters, model, interface, integrator and dt are
+ * used; h must outlive the controller set and its stream is used). Allocates
+ * device scratch of about C*N*4 + C*n_e*(16*H + 8) bytes.
+ * Errors: CF_EINVAL (h has more than one world, a field out of range or not
+ * finite), CF_ENOMEM; *out is NULL on failure.
+ */
+cf_status cf_mppi_create(cf_handle* h, const cf_mppi_desc* desc, cf_mppi** out);
+
+/* cf_mppi_destroy: synchronise the stream and free the scratch. NULL is a no-op. */
+cf_status cf_mppi_destroy(cf_mppi* m);
+
+/*
+ * cf_mppi_step: one control step of all controllers, asynchronous on the
+ * handle's stream. x_now device [S] (the handle's state layout); mean device
+ * [C][H][4], in: the previous plans (read shifted by `shift` >= 0 steps), out:
+ * the new plans. Optional device outputs (NULL to skip): u_apply [4], best [1],
+ * cost [C][N], elite_idx [C][n_e] (ordered by cost, then index), cost_min [C].
+ * The same (seed, iteration) gives the same samples. Calls on one controller
+ * set share its scratch and must not overlap on different streams.
+ * Errors: CF_EINVAL (NULL or too-small device buffers, shift < 0), sticky
+ * CF_EDEVICE.
+ */
+cf_status cf_mppi_step(cf_mppi* m, const float* x_now, float* mean, int32_t shift, uint64_t iteration,
+                       float* u_apply, int32_t* best, float* cost, int32_t* elite_idx, float* cost_min);
+
+/* cf_mppi_noise: the correlated noise eps (before sigma and clipping) of call
+   `iteration`, device [C][N][H][4]; zero for sample 0. */
+cf_status cf_mppi_noise(cf_mppi* m, uint64_t iteration, float* eps);
 
 #ifdef __cplusplus
 }

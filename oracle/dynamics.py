@@ -42,7 +42,7 @@ F64 = torch.float64
 
 # enum values of the public interface
 MODEL_FP, MODEL_ID = 0, 1
-CTRL_ROTOR, CTRL_ATT_PID = 0, 1
+CTRL_ROTOR, CTRL_ATT_PID, CTRL_TORQUE = 0, 1, 2
 EULER, RK4 = 0, 1
 
 
@@ -77,6 +77,35 @@ def body_z_in_world(q: torch.Tensor) -> torch.Tensor:
     return torch.stack([2 * (qx * qz + qw * qy),
                         2 * (qy * qz - qw * qx),
                         1 - 2 * (qx * qx + qy * qy)])
+
+
+def rotation_matrix(q: torch.Tensor) -> torch.Tensor:
+    """Body->world rotation matrix [3, 3, D] of a unit quaternion (x, y, z, w),
+    applied (like body_z_in_world) to the stage quaternion as is."""
+    qx, qy, qz, qw = q[0], q[1], q[2], q[3]
+    return torch.stack([
+        torch.stack([1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)]),
+        torch.stack([2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)]),
+        torch.stack([2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)]),
+    ])
+
+
+def euler_zyx_matrix(psi: torch.Tensor) -> torch.Tensor:
+    """R = Rz(yaw) Ry(pitch) Rx(roll) as [3, 3, D]."""
+    phi, th, ps = psi[0], psi[1], psi[2]
+    cf, sf, ct, st, cp, sp = torch.cos(phi), torch.sin(phi), torch.cos(th), torch.sin(th), torch.cos(ps), torch.sin(ps)
+    return torch.stack([
+        torch.stack([cp * ct, cp * st * sf - sp * cf, cp * st * cf + sp * sf]),
+        torch.stack([sp * ct, sp * st * sf + cp * cf, sp * st * cf - cp * sf]),
+        torch.stack([-st, ct * sf, ct * cf]),
+    ])
+
+
+def drag_acceleration(R: torch.Tensor, v: torch.Tensor, P) -> torch.Tensor:
+    """R C_a R^T v / m: linear drag C_a v_body in the body frame, rotated to the world."""
+    vb = (R * v[:, None, :]).sum(0)               # R^T v
+    fb = P["drag"] * vb
+    return (R * fb[None, :, :]).sum(1) / P["mass"][0]
 
 
 def euler_zyx_body_z(psi: torch.Tensor) -> torch.Tensor:
@@ -119,9 +148,16 @@ def fp_rates(x: torch.Tensor, rot_cmd: torch.Tensor, P) -> torch.Tensor:
     [p, q(x,y,z,w), v, w_body, Omega(4)] under rotor-speed command ``rot_cmd``.
 
     Eq. (1): p' = v; q' = 1/2 q (x) [w; 0]; m v' = f_sum; J w' = t_sum - w x J w,
-    with f_sum = R(q) [0, 0, sum f_i] - m g e_z (gravity along -z, g from the
-    record). Gyroscopic/reaction torques (J_p) and linear drag (C_a) are not
-    part of this oracle: the interface rejects non-zero values of both.
+    with f_sum = R(q) [0, 0, sum f_i] + R(q) C_a R(q)^T v - m g e_z (gravity along
+    -z, g from the record; linear body-frame drag f_a = C_a v_body, C_a diagonal)
+    and t_sum = mixed rotor torques + gyroscopic/reaction torques of the rotors.
+
+    Reading of the garbled gyroscopic rows: rotor i spins with direction
+    sigma_i = -sign(mix_yaw_i) (+,-,+,- for the x airframe), so the rotors carry
+    angular momentum h = J_p Omega_s e_z, Omega_s = sum sigma_i Omega_i, and
+    Euler's equation with internal rotors adds -w x h - h' =
+    J_p [-w_y Omega_s, w_x Omega_s, -sum sigma_i Omega_i'] to the torques; the
+    third row is the reaction torque exactly as printed.
     """
     q, v, w, rot = x[3:7], x[7:10], x[10:13], x[13:17]
     rot_dot = rotor_rates(rot, rot_cmd, P)
@@ -129,6 +165,11 @@ def fp_rates(x: torch.Tensor, rot_cmd: torch.Tensor, P) -> torch.Tensor:
     m, g = P["mass"][0], P["gravity"][0]
     acc = (thrust / m) * body_z_in_world(q)
     acc = acc - torch.stack([torch.zeros_like(g), torch.zeros_like(g), g])
+    acc = acc + drag_acceleration(rotation_matrix(q), v, P)
+    sigma = -torch.sign(P["mix_yaw"])
+    jp = P["Jp"][0]
+    om_s = (sigma * rot).sum(0)
+    torque = torque + jp * torch.stack([-w[1] * om_s, w[0] * om_s, -(sigma * rot_dot).sum(0)])
     q_dot = 0.5 * quat_mul(q, torch.cat([w, torch.zeros_like(w[0:1])], 0))
     J = P["J"]
     w_dot = (torque - torch.linalg.cross(w, J * w, dim=0)) / J
@@ -179,11 +220,18 @@ def attitude_pid(x: torch.Tensor, u: torch.Tensor, P, dt: float):
     i_rate = i_rate + e_rate * dt
     alpha = P["rate_kp"] * e_rate + P["rate_ki"] * i_rate - P["rate_kd"] * (w - w_prev) / dt
     wrench = torch.cat([u[3:4], P["J_ctrl"] * alpha], 0)
+    return allocate(wrench, P), torch.cat([i_ang, i_rate, w], 0)
+
+
+def allocate(wrench: torch.Tensor, P) -> torch.Tensor:
+    """Motor allocation: per-rotor thrusts f = alloc [T, tau_x, tau_y, tau_z],
+    clamped to [0, f_max], turned into rotor-speed commands on the thrust curve.
+    It is also the torque interface of the first-principles model (command =
+    collective thrust and body torques)."""
     A = P["alloc"].reshape(4, 4, -1)
     f = (A * wrench[None, :, :]).sum(1)
     f = torch.clamp(f, min=torch.zeros_like(f), max=P["f_max"][0:1].expand_as(f))
-    rot_cmd = rotor_speed_for_thrust(f, P)
-    return rot_cmd, torch.cat([i_ang, i_rate, w], 0)
+    return rotor_speed_for_thrust(f, P)
 
 
 # ---- identified model -----------------------------------------------------------
@@ -193,11 +241,13 @@ def id_rates(x: torch.Tensor, u: torch.Tensor, P) -> torch.Tensor:
     under u = [Psi_cmd, f_cmd] (Eqs. 3_simplified_*): p' = v;
     m v' = -m g e_z + R(Psi) e_z c_f f; f' = c_tau (f_cmd - f);
     Psi'' = c1 Psi + c2 Psi' + c3 Psi_cmd (per axis; reading of the garbled
-    coefficient labels as three distinct 3-vectors). Drag is not included."""
+    coefficient labels as three distinct 3-vectors); the drag term R f_a with
+    f_a = C_a R^T v as in the first-principles model."""
     psi, v, dpsi, fs = x[3:6], x[6:9], x[9:12], x[12]
     m, g = P["mass"][0], P["gravity"][0]
     acc = (P["c_f"][0] * fs / m) * euler_zyx_body_z(psi)
     acc = acc - torch.stack([torch.zeros_like(g), torch.zeros_like(g), g])
+    acc = acc + drag_acceleration(euler_zyx_matrix(psi), v, P)
     ddpsi = P["c_psi1"] * psi + P["c_psi2"] * dpsi + P["c_psi3"] * u[0:3]
     dfs = P["c_tau"][0] * (u[3] - fs)
     return torch.cat([v, dpsi, acc, ddpsi, dfs[None]], 0)
@@ -220,6 +270,8 @@ def step_fp(x, u, P, control: int, integrator: int, dt: float, renorm: bool = Tr
     """One step of a first-principles drone (state 17, or 25 with the PID)."""
     if control == CTRL_ATT_PID:
         rot_cmd, ctrl = attitude_pid(x, u, P, dt)
+    elif control == CTRL_TORQUE:
+        rot_cmd, ctrl = allocate(u, P), None
     else:
         rot_cmd, ctrl = u, None
     body = integrate(lambda s: fp_rates(s, rot_cmd, P), x[0:17], dt, integrator)

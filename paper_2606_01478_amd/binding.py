@@ -19,9 +19,10 @@ LIB_PATH = os.path.join(HERE, "libcfsim.so")
 
 CF_OK, CF_EINVAL, CF_ENODEV, CF_ENOMEM, CF_EDEVICE, CF_ESTATE, CF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MODEL_FP, MODEL_ID = 0, 1
-CTRL_ROTOR, CTRL_ATT_PID = 0, 1
+CTRL_ROTOR, CTRL_ATT_PID, CTRL_TORQUE = 0, 1, 2
 INTEG_EULER, INTEG_RK4 = 0, 1
 F_PLAIN_KERNEL, F_NONFINITE_CHECK, F_GRAPH, F_WORKQUEUE, F_NO_AUTOTUNE_CACHE = 0x1, 0x2, 0x4, 0x8, 0x10
+F_SINGLE_LAUNCH = 0x20
 S_FP_ROTOR, S_FP_PID, S_ID = 17, 25, 13
 NPARAM = 96
 NGAIN = 52
@@ -37,7 +38,10 @@ PARAM_OFFSETS = {
 
 EXPORTS = ("cf_create", "cf_destroy", "cf_state_dim", "cf_total_drones", "cf_world_offsets", "cf_set_stream",
            "cf_reset", "cf_step_k", "cf_rollout", "cf_rollout_backward", "cf_autotune", "cf_launch_config",
-           "cf_strerror", "cf_last_error")
+           "cf_strerror", "cf_last_error", "cf_mppi_create", "cf_mppi_destroy", "cf_mppi_step", "cf_mppi_noise")
+
+MPPI_MAX_OBSTACLES = 16
+MPPI_MAX_ELITE = 4096
 
 
 class CfError(RuntimeError):
@@ -57,6 +61,15 @@ class _Desc(ctypes.Structure):
 class _Objective(ctypes.Structure):
     _fields_ = [("gain", c_void_p), ("ref_table", c_void_p), ("ref_amp", c_float), ("ref_period", c_float),
                 ("ref_offset", c_void_p), ("w_u", c_float)]
+
+
+class _MppiDesc(ctypes.Structure):
+    _fields_ = [("n_controllers", c_int32), ("n_samples", c_int32), ("horizon", c_int32), ("substeps", c_int32),
+                ("n_elite", c_int32), ("sigma", c_float * 4), ("beta", c_float), ("lambda_", c_float),
+                ("u_lo", c_float * 4), ("u_hi", c_float * 4), ("u_ref", c_float * 4), ("r_u", c_float * 4),
+                ("goal", c_float * 3), ("q_p", c_float), ("q_v", c_float), ("w_obs", c_float),
+                ("n_obstacles", c_int32), ("obstacles", (c_float * 4) * MPPI_MAX_OBSTACLES),
+                ("seed", ctypes.c_uint64)]
 
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -87,6 +100,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "cf_launch_config": ([H, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)], c_int32),
         "cf_strerror": ([c_int32], ctypes.c_char_p),
         "cf_last_error": ([H], c_int32),
+        "cf_mppi_create": ([H, POINTER(_MppiDesc), POINTER(c_void_p)], c_int32),
+        "cf_mppi_destroy": ([H], c_int32),
+        "cf_mppi_step": ([H, P, P, c_int32, ctypes.c_uint64, P, P, P, P, P], c_int32),
+        "cf_mppi_noise": ([H, ctypes.c_uint64, P], c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -283,7 +300,7 @@ class Sim:
         a, b, c = c_int32(), c_int32(), c_int32()
         _check(self._lib.cf_launch_config(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "cf_launch_config")
-        return {"workqueue": a.value, "tile": b.value, "chunk": c.value}
+        return {"workqueue": a.value & 1, "per_model_launches": (a.value >> 1) & 1, "tile": b.value, "chunk": c.value}
 
     def last_error(self) -> int:
         return int(self._lib.cf_last_error(self._h))
@@ -343,3 +360,65 @@ class RolloutLoss:
         if cls._cached is None:
             cls._cached = cls._fn()
         return cls._cached.apply(x0, cmds, gain, sim, T, ckpt_every, obj_kw or {})
+
+
+class Mppi:
+    """Sampled-rollout controllers (iCEM/MPPI hybrid) on the single world of ``sim``.
+    ``params`` holds n_controllers, n_samples, horizon, substeps, n_elite, sigma,
+    beta, lambda, u_lo, u_hi, u_ref, r_u, goal, q_p, q_v, w_obs, obstacles
+    ``[n][4]`` (centre, radius) and seed."""
+
+    def __init__(self, sim: Sim, params: Dict):
+        self._lib = sim._lib
+        self.sim = sim
+        d = _MppiDesc()
+        d.n_controllers = int(params["n_controllers"])
+        d.n_samples = int(params["n_samples"])
+        d.horizon = int(params["horizon"])
+        d.substeps = int(params.get("substeps", 1))
+        d.n_elite = int(params["n_elite"])
+        for name in ("sigma", "u_lo", "u_hi", "u_ref", "r_u"):
+            getattr(d, name)[:] = [float(v) for v in params[name]]
+        d.goal[:] = [float(v) for v in params["goal"]]
+        d.beta = float(params["beta"])
+        d.lambda_ = float(params["lambda"])
+        d.q_p, d.q_v, d.w_obs = float(params["q_p"]), float(params["q_v"]), float(params["w_obs"])
+        obs = np.asarray(params.get("obstacles", np.zeros((0, 4))), np.float32).reshape(-1, 4)
+        if len(obs) > MPPI_MAX_OBSTACLES:
+            raise ValueError(f"at most {MPPI_MAX_OBSTACLES} obstacles")
+        d.n_obstacles = len(obs)
+        for o in range(len(obs)):
+            d.obstacles[o][:] = [float(v) for v in obs[o]]
+        d.seed = int(params["seed"]) & 0xFFFFFFFFFFFFFFFF
+        self.C, self.N, self.H, self.n_elite = d.n_controllers, d.n_samples, d.horizon, d.n_elite
+        self._m = c_void_p()
+        _check(self._lib.cf_mppi_create(sim._h, ctypes.byref(d), ctypes.byref(self._m)), "cf_mppi_create")
+
+    def close(self) -> None:
+        if getattr(self, "_m", None) is not None and self._m.value:
+            self._lib.cf_mppi_destroy(self._m)
+            self._m = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, x_now, mean, shift: int, iteration: int, u_apply=None, best=None, cost=None, elite_idx=None,
+             cost_min=None) -> None:
+        """One control step; ``mean`` ``[C][H][4]`` is updated in place."""
+        sim = self.sim
+        sim._need(x_now, (sim.S,), "x_now")
+        sim._need(mean, (self.C, self.H, 4), "mean")
+        sim._need(u_apply, (4,), "u_apply")
+        sim._need(best, (1,), "best", ("int32",))
+        sim._need(cost, (self.C, self.N), "cost")
+        sim._need(elite_idx, (self.C, self.n_elite), "elite_idx", ("int32",))
+        sim._need(cost_min, (self.C,), "cost_min")
+        _check(self._lib.cf_mppi_step(self._m, _ptr(x_now), _ptr(mean), int(shift), int(iteration), _ptr(u_apply),
+                                      _ptr(best), _ptr(cost), _ptr(elite_idx), _ptr(cost_min)), "cf_mppi_step")
+
+    def noise(self, iteration: int, eps) -> None:
+        self.sim._need(eps, (self.C, self.N, self.H, 4), "eps")
+        _check(self._lib.cf_mppi_noise(self._m, int(iteration), _ptr(eps)), "cf_mppi_noise")

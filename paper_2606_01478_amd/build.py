@@ -1,7 +1,11 @@
 """Build libcfsim.so (HIP for gfx950) in-tree with hipcc.
 
 Packed FP32 instructions are disabled (``-packed-fp32-ops``); every kernel is
-plain FP32 VALU code.
+plain FP32 VALU code. Multiply-add contraction is decided per source expression
+(``-ffp-contract=on``), never across statements by the backend, so a drone's
+arithmetic is the same in every kernel instantiation (lane, tile, work-queue,
+mixed or per-model launches, forward and adjoint recompute) and the results do
+not depend on the launch configuration.
 """
 from __future__ import annotations
 
@@ -12,11 +16,11 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["cf_api.hip", "cf_step.hip", "cf_rollout.hip"]
+SOURCES = ["cf_api.hip", "cf_step.hip", "cf_rollout.hip", "cf_mppi.hip"]
 LIB = os.path.join(HERE, "libcfsim.so")
 ARCH = os.environ.get("CFSIM_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on",
          "-I", os.path.join(ROOT, "include")]
 
 

@@ -112,6 +112,8 @@ struct cf_handle {
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
+    hipStream_t aux_stream = nullptr;      // second stream for per-model launches (default priority)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int M = 0;
     int64_t D = 0;
     int S = 0;
@@ -134,14 +136,17 @@ struct cf_handle {
     // tiles for the current tile size
     int4* tiles = nullptr;
     int n_tiles = 0;
+    int n_tiles_fp = 0;  // tiles of first-principles worlds come first
     int tiles_for = 0;
     unsigned* counters = nullptr;
     int n_counters = 0;
     // launch choice
     int lane_ok = 0;     // all worlds one model: per-lane mapping possible
+    int aero = 0;        // some world has propeller inertia or drag
     int use_wq = 0;
     int tile = 64;
     int chunk = 0;       // 0 = all k steps in one launch
+    int split = 1;       // mixed handles: one launch per model on two streams
     int mode = LM_TILE;
     // scratch
     DevBuf ref_tab, seg, ggc, wsum, loss_tmp;
@@ -150,6 +155,17 @@ struct cf_handle {
     int last_T = -1, last_K = -1;
     cf_status sticky = CF_OK;
     std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+struct cf_mppi {
+    cf_handle* h = nullptr;
+    cfk::MppiArgs base{};
+    cfk::KernelSel ks{};
+    float* cost = nullptr;        // [C][N]
+    float* elite_u = nullptr;     // [C][H*4][n_e]
+    int32_t* elite_idx = nullptr; // [C][n_e]
+    float* elite_cost = nullptr;  // [C][n_e]
+    float* cost_min = nullptr;    // [C]
 };
 
 namespace {
@@ -202,7 +218,7 @@ cf_status check_dev(const void* ptr, size_t bytes) {
 
 int model_cost(int model, int ctrl) {
     if (model == MODEL_ID) return 2;
-    return ctrl == CTRL_PID ? 5 : 4;
+    return ctrl == CTRL_ROTOR ? 4 : 5;
 }
 
 hipError_t build_tiles(cf_handle* h, int tile) {
@@ -218,13 +234,22 @@ hipError_t build_tiles(cf_handle* h, int tile) {
                           waves * model_cost(h->model_of_world[w], h->control)});
         }
     }
-    // most expensive first (longest-processing-time order), ties by position
-    std::stable_sort(ts.begin(), ts.end(), [](const T& a, const T& b) { return a.cost > b.cost; });
+    // first-principles tiles first; within a model the most expensive first
+    // (longest-processing-time order), ties by position
+    std::stable_sort(ts.begin(), ts.end(), [](const T& a, const T& b) {
+        if (a.v.w != b.v.w) return a.v.w < b.v.w;
+        return a.cost > b.cost;
+    });
     std::vector<int4> v(ts.size());
-    for (size_t i = 0; i < ts.size(); ++i) v[i] = ts[i].v;
+    int nfp = 0;
+    for (size_t i = 0; i < ts.size(); ++i) {
+        v[i] = ts[i].v;
+        nfp += (ts[i].v.w == MODEL_FP);
+    }
     if (h->tiles) hipFree(h->tiles);
     h->tiles = nullptr;
     h->n_tiles = (int)v.size();
+    h->n_tiles_fp = nfp;
     hipError_t e = dalloc(&h->tiles, v.size());
     if (e != hipSuccess) return e;
     if (!v.empty()) e = hipMemcpy(h->tiles, v.data(), v.size() * sizeof(int4), hipMemcpyHostToDevice);
@@ -237,6 +262,23 @@ void clear_graphs(cf_handle* h) {
     h->graphs.clear();
 }
 
+// Runs fn(models, tiles, n_tiles, stream, slot) over the tile list: once for
+// all tiles (uniform-model handles, or a single mixed launch), or once per
+// model with the identified-model launch forked onto the auxiliary stream and
+// joined back with events (also valid while capturing a graph).
+template <class F>
+hipError_t per_model(cf_handle* h, hipStream_t s, F&& fn) {
+    if (!(h->models == MS_BOTH && h->split)) return fn(h->models, h->tiles, h->n_tiles, s, 0);
+    hipError_t e;
+    const int n_fp = h->n_tiles_fp, n_id = h->n_tiles - h->n_tiles_fp;
+    if ((e = hipEventRecord(h->ev_fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(h->aux_stream, h->ev_fork, 0)) != hipSuccess) return e;
+    if (n_fp > 0 && (e = fn(MS_FP, h->tiles, n_fp, s, 0)) != hipSuccess) return e;
+    if (n_id > 0 && (e = fn(MS_ID, h->tiles + n_fp, n_id, h->aux_stream, 1)) != hipSuccess) return e;
+    if ((e = hipEventRecord(h->ev_join, h->aux_stream)) != hipSuccess) return e;
+    return hipStreamWaitEvent(s, h->ev_join, 0);
+}
+
 KernelSel selection(const cf_handle* h, int mode, int tile) {
     KernelSel ks;
     ks.models = h->models;
@@ -244,6 +286,7 @@ KernelSel selection(const cf_handle* h, int mode, int tile) {
     ks.integ = h->integ;
     ks.mode = mode;
     ks.tile = tile;
+    ks.aero = h->aero;
     return ks;
 }
 
@@ -275,26 +318,26 @@ std::string signature(const cf_handle* h) {
     char buf[256];
     int nfp = 0;
     for (auto m : h->model_of_world) nfp += (m == MODEL_FP);
-    std::snprintf(buf, sizeof buf, "%s|M%d|D%lld|fp%d|c%d|i%d", h->arch.c_str(), h->M, (long long)h->D, nfp,
+    std::snprintf(buf, sizeof buf, "v2|%s|M%d|D%lld|fp%d|c%d|i%d", h->arch.c_str(), h->M, (long long)h->D, nfp,
                   h->control, h->integ);
     return buf;
 }
 
-bool cache_lookup(const std::string& key, int* wq, int* tile, int* chunk) {
+bool cache_lookup(const std::string& key, int* wq, int* tile, int* chunk, int* split) {
     FILE* f = std::fopen(cache_path().c_str(), "r");
     if (!f) return false;
     char k[256];
-    int a, b, c;
+    int a, b, c, sp;
     float ms;
     bool found = false;
-    while (std::fscanf(f, "%255s %d %d %d %f", k, &a, &b, &c, &ms) == 5) {
-        if (key == k) { *wq = a; *tile = b; *chunk = c; found = true; }
+    while (std::fscanf(f, "%255s %d %d %d %d %f", k, &a, &b, &c, &sp, &ms) == 6) {
+        if (key == k) { *wq = a; *tile = b; *chunk = c; *split = sp; found = true; }
     }
     std::fclose(f);
     return found;
 }
 
-void cache_store(const std::string& key, int wq, int tile, int chunk, float ms) {
+void cache_store(const std::string& key, int wq, int tile, int chunk, int split, float ms) {
     const std::string path = cache_path();
     std::vector<std::string> lines;
     if (FILE* f = std::fopen(path.c_str(), "r")) {
@@ -310,12 +353,13 @@ void cache_store(const std::string& key, int wq, int tile, int chunk, float ms) 
     FILE* f = std::fopen(path.c_str(), "w");
     if (!f) return;
     for (auto& l : lines) std::fputs(l.c_str(), f);
-    std::fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), wq, tile, chunk, ms);
+    std::fprintf(f, "%s %d %d %d %d %.6f\n", key.c_str(), wq, tile, chunk, split, ms);
     std::fclose(f);
 }
 
-void apply_choice(cf_handle* h, int wq, int tile, int chunk) {
+void apply_choice(cf_handle* h, int wq, int tile, int chunk, int split) {
     if (tile != 64 && tile != 128 && tile != 256) tile = 64;
+    h->split = split ? 1 : 0;
     h->use_wq = wq ? 1 : 0;
     h->tile = tile;
     h->chunk = chunk > 0 ? chunk : 0;
@@ -341,7 +385,8 @@ cf_status validate_desc(const cf_desc* d, std::vector<int32_t>& counts, std::vec
         if (m != CF_MODEL_FP && m != CF_MODEL_ID) return CF_EINVAL;
         models[w] = (uint8_t)m;
     }
-    if (d->control != CF_CTRL_ROTOR && d->control != CF_CTRL_ATT_PID) return CF_EINVAL;
+    if (d->control != CF_CTRL_ROTOR && d->control != CF_CTRL_ATT_PID && d->control != CF_CTRL_TORQUE)
+        return CF_EINVAL;
     if (d->integrator != CF_INTEG_EULER && d->integrator != CF_INTEG_RK4) return CF_EINVAL;
     if (!(std::isfinite(d->dt) && d->dt > 0.f)) return CF_EINVAL;
     if (d->renorm_q != 0 && d->renorm_q != 1) return CF_EINVAL;
@@ -354,23 +399,20 @@ cf_status validate_desc(const cf_desc* d, std::vector<int32_t>& counts, std::vec
             gidx[w] = d->gain_index[w];
         }
     }
-    bool unsupported = false;
     for (int w = 0; w < M; ++w) {
         const float* r = d->params + (size_t)w * CF_NPARAM;
         for (int i = 0; i < CF_NPARAM; ++i)
             if (!std::isfinite(r[i])) return CF_EINVAL;
         if (!(r[CF_P_MASS] > 0.f)) return CF_EINVAL;
-        if (r[CF_P_DRAG] != 0.f || r[CF_P_DRAG + 1] != 0.f || r[CF_P_DRAG + 2] != 0.f) unsupported = true;
         if (models[w] == CF_MODEL_FP) {
             for (int i = 0; i < 3; ++i)
                 if (!(r[CF_P_J + i] > 0.f)) return CF_EINVAL;
-            if (d->control == CF_CTRL_ATT_PID && !(r[CF_P_THRUST + 2] > 0.f)) return CF_EINVAL;
-            if (r[CF_P_JP] != 0.f) unsupported = true;
+            if (d->control != CF_CTRL_ROTOR && !(r[CF_P_THRUST + 2] > 0.f)) return CF_EINVAL;
+            if (r[CF_P_JP] < 0.f) return CF_EINVAL;
         } else {
             if (!(r[CF_P_CF] > 0.f)) return CF_EINVAL;
         }
     }
-    if (unsupported) return CF_EUNSUPPORTED;
     *D_out = D;
     return CF_OK;
 }
@@ -436,6 +478,12 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
     h->models = (has_fp ? MS_FP : 0) | (has_id ? MS_ID : 0);
     h->S = has_fp ? (h->control == CF_CTRL_ATT_PID ? CF_S_FP_PID : CF_S_FP_ROTOR) : CF_S_ID;
     h->lane_ok = (h->models != MS_BOTH);
+    for (int w = 0; w < h->M; ++w) {
+        const float* r = d->params + (size_t)w * CF_NPARAM;
+        if (r[CF_P_DRAG] != 0.f || r[CF_P_DRAG + 1] != 0.f || r[CF_P_DRAG + 2] != 0.f ||
+            (models[w] == CF_MODEL_FP && r[CF_P_JP] != 0.f))
+            h->aero = 1;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
         h->cus = prop.multiProcessorCount;
@@ -475,13 +523,17 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
     if ((e = hipMemcpy(h->d_gidx, gidx.data(), M * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e);
     if ((e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking)) != hipSuccess) return fail(e);
+    if ((e = hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking)) != hipSuccess) return fail(e);
+    if ((e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming)) != hipSuccess) return fail(e);
+    if ((e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming)) != hipSuccess) return fail(e);
 
-    int wq = (h->flags & CF_F_WORKQUEUE) ? 1 : 0, tile = 64, chunk = 0;
+    int wq = (h->flags & CF_F_WORKQUEUE) ? 1 : 0, tile = 64, chunk = 0, split = 1;
     if (!(h->flags & CF_F_NO_AUTOTUNE_CACHE) && !(h->flags & CF_F_WORKQUEUE)) {
-        int a, b, c;
-        if (cache_lookup(signature(h), &a, &b, &c)) { wq = a; tile = b; chunk = c; }
+        int a, b, c, sp;
+        if (cache_lookup(signature(h), &a, &b, &c, &sp)) { wq = a; tile = b; chunk = c; split = sp; }
     }
-    apply_choice(h, wq, tile, chunk);
+    if (h->flags & CF_F_SINGLE_LAUNCH) split = 0;
+    apply_choice(h, wq, tile, chunk, split);
     if ((e = build_tiles(h, h->tile)) != hipSuccess) return fail(e);
     *out = h;
     return CF_OK;
@@ -503,6 +555,12 @@ cf_status cf_destroy(cf_handle* h) {
     for (DevBuf* b : {&h->ref_tab, &h->seg, &h->ggc, &h->wsum, &h->loss_tmp})
         if (b->p) hipFree(b->p);
     if (h->capture_stream) hipStreamDestroy(h->capture_stream);
+    if (h->aux_stream) {
+        hipStreamSynchronize(h->aux_stream);
+        hipStreamDestroy(h->aux_stream);
+    }
+    if (h->ev_fork) hipEventDestroy(h->ev_fork);
+    if (h->ev_join) hipEventDestroy(h->ev_join);
     delete h;
     return CF_OK;
 }
@@ -533,7 +591,7 @@ cf_status cf_set_stream(cf_handle* h, void* stream) {
 
 cf_status cf_launch_config(const cf_handle* h, int32_t* use_wq, int32_t* tile, int32_t* chunk) {
     if (!h || !use_wq || !tile || !chunk) return CF_EINVAL;
-    *use_wq = h->use_wq;
+    *use_wq = h->use_wq | (h->split && h->models == MS_BOTH ? 2 : 0);
     *tile = h->tile;
     *chunk = h->chunk;
     return CF_OK;
@@ -571,33 +629,38 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
                                int plain) {
     hipError_t e = hipSuccess;
     if (plain) {
-        const KernelSel ks = selection(h, h->mode == LM_LANE ? LM_LANE : LM_TILE, h->tile);
+        const int mode = h->mode == LM_LANE ? LM_LANE : LM_TILE;
         const StepArgs a = step_args(h, state, cmd, 1, nf);
-        for (int i = 0; i < k && e == hipSuccess; ++i) e = launch_step(ks, a, h->tiles, h->n_tiles, nullptr, 0, s);
+        e = per_model(h, s, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
+            KernelSel ks = selection(h, mode, h->tile);
+            ks.models = models;
+            hipError_t r = hipSuccess;
+            for (int i = 0; i < k && r == hipSuccess; ++i) r = launch_step(ks, a, tiles, nt, nullptr, 0, st);
+            return r;
+        });
         return note(h, e);
     }
     const int chunk = (h->chunk > 0 && h->chunk < k) ? h->chunk : k;
     const int n_launch = (k + chunk - 1) / chunk;
     if (h->use_wq) {
-        if (n_launch > h->n_counters) return CF_EINVAL;
-        const KernelSel ks = selection(h, LM_WQ, h->tile);
-        const int per_cu = step_wq_blocks_per_cu(ks);
-        const int blocks = std::max(1, std::min(h->n_tiles, per_cu * h->cus));
-        hipLaunchKernelGGL(k_fill_u32, dim3((n_launch + 255) / 256), dim3(256), 0, s, h->counters, n_launch, 0u);
-        e = hipGetLastError();
-        for (int c = 0; c < n_launch && e == hipSuccess; ++c) {
-            const int kk = std::min(chunk, k - c * chunk);
-            const StepArgs a = step_args(h, state, cmd, kk, nf);
-            e = launch_step(ks, a, h->tiles, h->n_tiles, h->counters + c, blocks, s);
-        }
-    } else {
-        const KernelSel ks = selection(h, h->mode, h->tile);
-        for (int c = 0; c < n_launch && e == hipSuccess; ++c) {
-            const int kk = std::min(chunk, k - c * chunk);
-            const StepArgs a = step_args(h, state, cmd, kk, nf);
-            e = launch_step(ks, a, h->tiles, h->n_tiles, nullptr, 0, s);
-        }
+        if (2 * n_launch > h->n_counters) return CF_EINVAL;
+        hipLaunchKernelGGL(k_fill_u32, dim3((2 * n_launch + 255) / 256), dim3(256), 0, s, h->counters, 2 * n_launch,
+                           0u);
+        if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
     }
+    e = per_model(h, s, [&](int models, const int4* tiles, int nt, hipStream_t st, int slot) {
+        KernelSel ks = selection(h, h->use_wq ? LM_WQ : h->mode, h->tile);
+        ks.models = models;
+        int blocks = 0;
+        if (h->use_wq) blocks = std::max(1, std::min(nt, step_wq_blocks_per_cu(ks) * h->cus));
+        hipError_t r = hipSuccess;
+        for (int c = 0; c < n_launch && r == hipSuccess; ++c) {
+            const int kk = std::min(chunk, k - c * chunk);
+            const StepArgs a = step_args(h, state, cmd, kk, nf);
+            r = launch_step(ks, a, tiles, nt, h->use_wq ? h->counters + 2 * c + slot : nullptr, blocks, st);
+        }
+        return r;
+    });
     return note(h, e);
 }
 
@@ -615,7 +678,7 @@ cf_status cf_step_k(cf_handle* h, float* state, const float* cmd, int32_t k, uin
     const int plain = (h->flags & CF_F_PLAIN_KERNEL) ? 1 : 0;
     if (!(h->flags & CF_F_GRAPH)) return enqueue_steps(h, state, cmd, k, nf, h->stream, plain);
 
-    const GraphKey key{state, cmd, nf, k, h->use_wq, h->tile, h->chunk, plain};
+    const GraphKey key{state, cmd, nf, k, h->use_wq * 2 + h->split, h->tile, h->chunk, plain};
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         if (h->graphs.size() >= 64) clear_graphs(h);
@@ -682,6 +745,7 @@ static RollArgs roll_args(const cf_handle* h, const float* x0, const float* cmds
     RollArgs a;
     std::memset(&a, 0, sizeof a);
     a.x0 = x0;
+    a.S_h = h->S;
     a.cmds = cmds;
     a.T = T;
     a.D = h->D;
@@ -732,11 +796,13 @@ cf_status cf_rollout(cf_handle* h, const float* x0, const float* cmds, int32_t T
     }
     if (h->D > 0) {
         const int mode = roll_mode(h);
-        const int tile = 64;
         if (mode == LM_TILE && (e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
-        const KernelSel ks = selection(h, mode, mode == LM_LANE ? 64 : h->tile);
-        (void)tile;
-        if ((e = launch_rollout_fwd(ks, a, h->tiles, h->n_tiles, h->stream)) != hipSuccess) return note(h, e);
+        e = per_model(h, h->stream, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
+            KernelSel ks = selection(h, mode, mode == LM_LANE ? 64 : h->tile);
+            ks.models = models;
+            return launch_rollout_fwd(ks, a, tiles, nt, st);
+        });
+        if (e != hipSuccess) return note(h, e);
     }
     if (loss_world) {
         hipLaunchKernelGGL(k_reduce_world, dim3(h->M), dim3(256), 0, h->stream, a.loss, 1, h->D, h->d_offsets,
@@ -793,8 +859,12 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
     if (h->D > 0) {
         const int mode = roll_mode(h);
         if (mode == LM_TILE && (e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
-        const KernelSel ks = selection(h, mode, mode == LM_LANE ? 64 : h->tile);
-        if ((e = launch_rollout_bwd(ks, a, h->tiles, h->n_tiles, h->stream)) != hipSuccess) return note(h, e);
+        e = per_model(h, h->stream, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
+            KernelSel ks = selection(h, mode, mode == LM_LANE ? 64 : h->tile);
+            ks.models = models;
+            return launch_rollout_bwd(ks, a, tiles, nt, st);
+        });
+        if (e != hipSuccess) return note(h, e);
     }
     if (g_gain) {
         if (h->D > 0) {
@@ -829,24 +899,25 @@ cf_status cf_autotune(cf_handle* h, const float* state, const float* cmd, int32_
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
-    struct Cand { int wq, tile, chunk; };
+    struct Cand { int wq, tile, chunk, split; };
     std::vector<Cand> cands;
-    for (int wq = 0; wq < 2; ++wq)
-        for (int tile : {64, 128, 256})
-            for (int chunk : {0, 100, 25}) {
-                if (chunk && chunk >= k) continue;
-                cands.push_back({wq, tile, chunk});
-            }
-    const int save_wq = h->use_wq, save_tile = h->tile, save_chunk = h->chunk;
+    for (int split = 1; split >= (h->models == MS_BOTH ? 0 : 1); --split)
+        for (int wq = 0; wq < 2; ++wq)
+            for (int tile : {64, 128, 256})
+                for (int chunk : {0, 100, 25}) {
+                    if (chunk && chunk >= k) continue;
+                    cands.push_back({wq, tile, chunk, split});
+                }
+    const int save_wq = h->use_wq, save_tile = h->tile, save_chunk = h->chunk, save_split = h->split;
     const uint32_t save_flags = h->flags;
     h->flags &= ~(CF_F_PLAIN_KERNEL | CF_F_GRAPH);
     float best = 1e30f;
-    Cand bc{save_wq, save_tile, save_chunk};
+    Cand bc{save_wq, save_tile, save_chunk, save_split};
     double spent = 0.0;
     cf_status st = CF_OK;
     for (const Cand& c : cands) {
         if (spent > budget_ms && best < 1e30f) break;
-        apply_choice(h, c.wq, c.tile, c.chunk);
+        apply_choice(h, c.wq, c.tile, c.chunk, c.split);
         if ((e = build_tiles(h, h->tile)) != hipSuccess) { st = note(h, e); break; }
         float ms_best = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
@@ -869,13 +940,161 @@ cf_status cf_autotune(cf_handle* h, const float* state, const float* cmd, int32_
     hipEventDestroy(e1);
     hipFree(work);
     if (st != CF_OK) {
-        apply_choice(h, save_wq, save_tile, save_chunk);
+        apply_choice(h, save_wq, save_tile, save_chunk, save_split);
         return st;
     }
-    apply_choice(h, bc.wq, bc.tile, bc.chunk);
+    apply_choice(h, bc.wq, bc.tile, bc.chunk, bc.split);
     if ((e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
-    cache_store(signature(h), bc.wq, bc.tile, bc.chunk, best);
+    cache_store(signature(h), bc.wq, bc.tile, bc.chunk, bc.split, best);
     return CF_OK;
+}
+
+// ---- sampled-rollout controller -------------------------------------------------
+
+static void mppi_free(cf_mppi* m) {
+    hipFree(m->cost);
+    hipFree(m->elite_u);
+    hipFree(m->elite_idx);
+    hipFree(m->elite_cost);
+    hipFree(m->cost_min);
+}
+
+cf_status cf_mppi_create(cf_handle* h, const cf_mppi_desc* d, cf_mppi** out) {
+    if (!out) return CF_EINVAL;
+    *out = nullptr;
+    if (!h || !d) return CF_EINVAL;
+    if (h->M != 1) return CF_EINVAL;
+    if (d->n_controllers < 1 || d->n_samples < 1 || d->horizon < 1 || d->substeps < 1) return CF_EINVAL;
+    if (d->n_controllers > 65535) return CF_EINVAL;  // grid y dimension of the rollout
+    if ((int64_t)d->n_controllers * d->n_samples > 2147483647LL) return CF_EINVAL;
+    if ((int64_t)d->n_controllers * d->horizon * 4 > 2147483647LL) return CF_EINVAL;
+    if (d->n_elite < 1 || d->n_elite > d->n_samples || d->n_elite > cfk::MPPI_MAX_ELITE) return CF_EINVAL;
+    if (!(std::isfinite(d->beta) && d->beta >= 0.f && d->beta < 1.f)) return CF_EINVAL;
+    if (!(std::isfinite(d->lambda) && d->lambda > 0.f)) return CF_EINVAL;
+    for (int i = 0; i < 4; ++i) {
+        if (!(std::isfinite(d->sigma[i]) && d->sigma[i] >= 0.f)) return CF_EINVAL;
+        if (!(std::isfinite(d->u_lo[i]) && std::isfinite(d->u_hi[i]) && d->u_lo[i] <= d->u_hi[i])) return CF_EINVAL;
+        if (!(std::isfinite(d->u_ref[i]) && std::isfinite(d->r_u[i]) && d->r_u[i] >= 0.f)) return CF_EINVAL;
+    }
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(d->goal[i])) return CF_EINVAL;
+    if (!(std::isfinite(d->q_p) && d->q_p >= 0.f && std::isfinite(d->q_v) && d->q_v >= 0.f &&
+          std::isfinite(d->w_obs) && d->w_obs >= 0.f))
+        return CF_EINVAL;
+    if (d->n_obstacles < 0 || d->n_obstacles > CF_MPPI_MAX_OBSTACLES) return CF_EINVAL;
+    for (int o = 0; o < d->n_obstacles; ++o) {
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(d->obstacles[o][i])) return CF_EINVAL;
+        if (!(std::isfinite(d->obstacles[o][3]) && d->obstacles[o][3] > 0.f)) return CF_EINVAL;
+    }
+    if (h->sticky != CF_OK) return h->sticky;
+    hipSetDevice(h->device);
+    cf_mppi* m = new (std::nothrow) cf_mppi();
+    if (!m) return CF_ENOMEM;
+    m->h = h;
+    cfk::MppiArgs& a = m->base;
+    a.par = h->par_aos;
+    a.C = d->n_controllers;
+    a.N = d->n_samples;
+    a.H = d->horizon;
+    a.sub = d->substeps;
+    a.n_e = d->n_elite;
+    a.dt = h->dt;
+    a.inv_dt = 1.0f / h->dt;
+    a.renorm = h->renorm;
+    for (int i = 0; i < 4; ++i) {
+        a.sigma[i] = d->sigma[i];
+        a.u_lo[i] = d->u_lo[i];
+        a.u_hi[i] = d->u_hi[i];
+        a.u_ref[i] = d->u_ref[i];
+        a.r_u[i] = d->r_u[i];
+    }
+    a.beta = d->beta;
+    a.beta_c = (float)std::sqrt(1.0 - (double)d->beta * (double)d->beta);
+    a.inv_lambda = (float)(1.0 / (double)d->lambda);
+    for (int i = 0; i < 3; ++i) a.goal[i] = d->goal[i];
+    a.q_p = d->q_p;
+    a.q_v = d->q_v;
+    a.w_obs = d->w_obs;
+    a.n_obs = d->n_obstacles;
+    for (int o = 0; o < d->n_obstacles; ++o) {
+        for (int i = 0; i < 3; ++i) a.obs[o][i] = d->obstacles[o][i];
+        const double r = d->obstacles[o][3];
+        a.obs[o][3] = (float)(1.0 / (r * r));
+    }
+    a.seed = d->seed;
+    m->ks = selection(h, LM_LANE, 256);
+    const size_t CN = (size_t)a.C * a.N, CE = (size_t)a.C * a.n_e;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = dalloc(&m->cost, CN);
+    if (e == hipSuccess) e = dalloc(&m->elite_u, CE * a.H * 4);
+    if (e == hipSuccess) e = dalloc(&m->elite_idx, CE);
+    if (e == hipSuccess) e = dalloc(&m->elite_cost, CE);
+    if (e == hipSuccess) e = dalloc(&m->cost_min, (size_t)a.C);
+    if (e != hipSuccess) {
+        mppi_free(m);
+        delete m;
+        return from_hip(e);
+    }
+    *out = m;
+    return CF_OK;
+}
+
+cf_status cf_mppi_destroy(cf_mppi* m) {
+    if (!m) return CF_OK;
+    hipSetDevice(m->h->device);
+    if (m->h->stream) hipStreamSynchronize(m->h->stream);
+    else hipDeviceSynchronize();
+    mppi_free(m);
+    delete m;
+    return CF_OK;
+}
+
+cf_status cf_mppi_step(cf_mppi* m, const float* x_now, float* mean, int32_t shift, uint64_t iteration,
+                       float* u_apply, int32_t* best, float* cost, int32_t* elite_idx, float* cost_min) {
+    if (!m || shift < 0) return CF_EINVAL;
+    cf_handle* h = m->h;
+    if (h->sticky != CF_OK) return h->sticky;
+    const cfk::MppiArgs& b = m->base;
+    const size_t CN = (size_t)b.C * b.N, CE = (size_t)b.C * b.n_e;
+    if (check_dev(x_now, (size_t)h->S * sizeof(float)) ||
+        check_dev(mean, (size_t)b.C * b.H * 4 * sizeof(float)))
+        return CF_EINVAL;
+    if ((u_apply && check_dev(u_apply, 4 * sizeof(float))) || (best && check_dev(best, sizeof(int32_t))) ||
+        (cost && check_dev(cost, CN * sizeof(float))) || (elite_idx && check_dev(elite_idx, CE * sizeof(int32_t))) ||
+        (cost_min && check_dev(cost_min, (size_t)b.C * sizeof(float))))
+        return CF_EINVAL;
+    hipSetDevice(h->device);
+    cfk::MppiArgs a = b;
+    a.x_now = x_now;
+    a.mean = mean;
+    a.mean_out = mean;
+    a.shift = shift;
+    a.iter = iteration;
+    a.cost = cost ? cost : m->cost;
+    a.elite_u = m->elite_u;
+    a.elite_idx = elite_idx ? elite_idx : m->elite_idx;
+    a.elite_cost = m->elite_cost;
+    a.cost_min = cost_min ? cost_min : m->cost_min;
+    a.u_apply = u_apply;
+    a.best = best;
+    hipError_t e = cfk::launch_mppi_rollout(m->ks, a, h->stream);
+    if (e == hipSuccess) e = cfk::launch_mppi_select(a, h->stream);
+    return e == hipSuccess ? CF_OK : note(h, e);
+}
+
+cf_status cf_mppi_noise(cf_mppi* m, uint64_t iteration, float* eps) {
+    if (!m) return CF_EINVAL;
+    cf_handle* h = m->h;
+    if (h->sticky != CF_OK) return h->sticky;
+    const cfk::MppiArgs& b = m->base;
+    if (check_dev(eps, (size_t)b.C * b.N * b.H * 4 * sizeof(float))) return CF_EINVAL;
+    hipSetDevice(h->device);
+    cfk::MppiArgs a = b;
+    a.iter = iteration;
+    a.eps_out = eps;
+    hipError_t e = cfk::launch_mppi_noise(a, h->stream);
+    return e == hipSuccess ? CF_OK : note(h, e);
 }
 
 }  // extern "C"

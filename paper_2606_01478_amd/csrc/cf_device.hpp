@@ -24,7 +24,7 @@ enum : int {
     P_CPSI1 = 66, P_CPSI2 = 69, P_CPSI3 = 72, NPARAM = 96
 };
 enum : int { MODEL_FP = 0, MODEL_ID = 1 };
-enum : int { CTRL_ROTOR = 0, CTRL_PID = 1 };
+enum : int { CTRL_ROTOR = 0, CTRL_PID = 1, CTRL_TORQUE = 2 };
 enum : int { EULER = 0, RK4 = 1 };
 constexpr int S_FP = 17, S_PID = 25, S_ID = 13;
 
@@ -45,17 +45,24 @@ struct FpParams {
     float k0, k1, k2, t0, t1, t2, inv_2k2;
     float tx[4], ty[4], tz[4];
     float cvu, cdu, cvd, cdd;
+    float jp, sg[4];          // propeller inertia, rotor spin directions (-sign of the yaw mixing)
+    float cd[3];              // linear drag C_a diagonal
+    bool gyro, drag;          // J_p != 0, C_a != 0
 };
 struct PidParams {
     float akp[2], aki[2], rkp[3], rki[3], rkd[3], jc[3], fmax;
     float A[16];
 };
 struct IdParams {
-    float cf_m, g, ctau, f_hover;
+    float cf_m, g, ctau, f_hover, inv_m;
     float c1[3], c2[3], c3[3];
+    float cd[3];
+    bool drag;
 };
 
-template <class R>
+// AERO = false: the gyroscopic/reaction torques and drag are compiled out (the
+// flags below become constants and their branches fold away)
+template <bool AERO, class R>
 __device__ __forceinline__ FpParams load_fp(const R& rec) {
     FpParams P;
     P.inv_m = 1.0f / rec(P_MASS);
@@ -72,6 +79,23 @@ __device__ __forceinline__ FpParams load_fp(const R& rec) {
     }
     P.cvu = rec(P_MOTOR_UP); P.cdu = rec(P_MOTOR_UP + 1);
     P.cvd = rec(P_MOTOR_DOWN); P.cdd = rec(P_MOTOR_DOWN + 1);
+    if constexpr (AERO) {
+        P.jp = rec(P_JP);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) P.sg[i] = P.tz[i] > 0.f ? -1.f : (P.tz[i] < 0.f ? 1.f : 0.f);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) P.cd[i] = rec(P_DRAG + i);
+        P.gyro = P.jp != 0.f;
+        P.drag = (P.cd[0] != 0.f) || (P.cd[1] != 0.f) || (P.cd[2] != 0.f);
+    } else {
+        P.jp = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) P.sg[i] = 0.f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) P.cd[i] = 0.f;
+        P.gyro = false;
+        P.drag = false;
+    }
     return P;
 }
 
@@ -91,7 +115,7 @@ __device__ __forceinline__ PidParams load_pid(const R& rec) {
     return C;
 }
 
-template <class R>
+template <bool AERO, class R>
 __device__ __forceinline__ IdParams load_id(const R& rec) {
     IdParams P;
     const float m = rec(P_MASS), cf = rec(P_CF);
@@ -99,10 +123,13 @@ __device__ __forceinline__ IdParams load_id(const R& rec) {
     P.g = rec(P_GRAVITY);
     P.ctau = rec(P_CTAU);
     P.f_hover = m * P.g / cf;
+    P.inv_m = 1.0f / m;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         P.c1[i] = rec(P_CPSI1 + i); P.c2[i] = rec(P_CPSI2 + i); P.c3[i] = rec(P_CPSI3 + i);
+        P.cd[i] = AERO ? rec(P_DRAG + i) : 0.f;
     }
+    P.drag = AERO && ((P.cd[0] != 0.f) || (P.cd[1] != 0.f) || (P.cd[2] != 0.f));
     return P;
 }
 
@@ -154,6 +181,73 @@ __device__ __forceinline__ float rsqrt_hw(float x) { return __builtin_amdgcn_rsq
 __device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------------------
+// rotation matrices (row-major 3x3) and the linear drag term R C_a R^T v / m
+
+// body->world matrix of a unit quaternion (x, y, z, w), used on stage
+// quaternions as they are
+__device__ __forceinline__ void quat_matrix(float x, float y, float z, float w, float* R) {
+    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
+    R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+    R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+// qb += (dR/dq)^T Rb
+__device__ __forceinline__ void quat_matrix_vjp(float x, float y, float z, float w, const float* Rb, float* qb) {
+    qb[0] += 2.f * (y * Rb[1] + z * Rb[2] + y * Rb[3] - w * Rb[5] + z * Rb[6] + w * Rb[7]) - 4.f * x * (Rb[4] + Rb[8]);
+    qb[1] += 2.f * (x * Rb[1] + w * Rb[2] + x * Rb[3] + z * Rb[5] - w * Rb[6] + z * Rb[7]) - 4.f * y * (Rb[0] + Rb[8]);
+    qb[2] += 2.f * (-w * Rb[1] + x * Rb[2] + w * Rb[3] + y * Rb[5] + x * Rb[6] + y * Rb[7]) - 4.f * z * (Rb[0] + Rb[4]);
+    qb[3] += 2.f * (-z * Rb[1] + y * Rb[2] + z * Rb[3] - x * Rb[5] - y * Rb[6] + x * Rb[7]);
+}
+
+// R = Rz(yaw) Ry(pitch) Rx(roll) from the sines/cosines of (roll, pitch, yaw)
+__device__ __forceinline__ void euler_matrix(const float* sn, const float* cs, float* R) {
+    const float sf = sn[0], cf = cs[0], st = sn[1], ct = cs[1], sp = sn[2], cp = cs[2];
+    R[0] = cp * ct; R[1] = cp * st * sf - sp * cf; R[2] = cp * st * cf + sp * sf;
+    R[3] = sp * ct; R[4] = sp * st * sf + cp * cf; R[5] = sp * st * cf - cp * sf;
+    R[6] = -st;     R[7] = ct * sf;                R[8] = ct * cf;
+}
+
+// psib += (dR/dPsi)^T Rb
+__device__ __forceinline__ void euler_matrix_vjp(const float* sn, const float* cs, const float* Rb, float* psib) {
+    const float sf = sn[0], cf = cs[0], st = sn[1], ct = cs[1], sp = sn[2], cp = cs[2];
+    psib[0] += Rb[1] * (cp * st * cf + sp * sf) + Rb[2] * (-cp * st * sf + sp * cf) +
+               Rb[4] * (sp * st * cf - cp * sf) + Rb[5] * (-sp * st * sf - cp * cf) + Rb[7] * (ct * cf) -
+               Rb[8] * (ct * sf);
+    psib[1] += -Rb[0] * (cp * st) + Rb[1] * (cp * ct * sf) + Rb[2] * (cp * ct * cf) - Rb[3] * (sp * st) +
+               Rb[4] * (sp * ct * sf) + Rb[5] * (sp * ct * cf) - Rb[6] * ct - Rb[7] * (st * sf) - Rb[8] * (st * cf);
+    psib[2] += -Rb[0] * (sp * ct) + Rb[1] * (-sp * st * sf - cp * cf) + Rb[2] * (-sp * st * cf + cp * sf) +
+               Rb[3] * (cp * ct) + Rb[4] * (cp * st * sf - sp * cf) + Rb[5] * (cp * st * cf + sp * sf);
+}
+
+// acc += R diag(cd) R^T v / m
+__device__ __forceinline__ void drag_acc(const float* R, const float* v, const float* cd, float inv_m, float* acc) {
+    float fb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) fb[j] = cd[j] * (R[j] * v[0] + R[3 + j] * v[1] + R[6 + j] * v[2]) * inv_m;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc[i] += R[3 * i] * fb[0] + R[3 * i + 1] * fb[1] + R[3 * i + 2] * fb[2];
+}
+
+// VJP of drag_acc w.r.t. v (vb +=) and R (Rb +=), given the adjoint ga of acc
+__device__ __forceinline__ void drag_acc_vjp(const float* R, const float* v, const float* cd, float inv_m,
+                                             const float* ga, float* vb, float* Rb) {
+    float vbody[3], fb[3], fbb[3], vbb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        vbody[j] = R[j] * v[0] + R[3 + j] * v[1] + R[6 + j] * v[2];
+        fb[j] = cd[j] * vbody[j] * inv_m;
+        fbb[j] = R[j] * ga[0] + R[3 + j] * ga[1] + R[6 + j] * ga[2];   // R^T ga
+        vbb[j] = cd[j] * inv_m * fbb[j];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        vb[i] += R[3 * i] * vbb[0] + R[3 * i + 1] * vbb[1] + R[3 * i + 2] * vbb[2];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Rb[3 * i + j] += ga[i] * fb[j] + v[i] * vbb[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // first-principles right-hand side, 17 components [p q v w Omega]
 __device__ __forceinline__ void fp_rates(const float* x, const float* rc, const FpParams& P, float* xd) {
     const float qx = x[3], qy = x[4], qz = x[5], qw = x[6];
@@ -182,6 +276,23 @@ __device__ __forceinline__ void fp_rates(const float* x, const float* rc, const 
     xd[7] = a * (2.f * (qx * qz + qw * qy));
     xd[8] = a * (2.f * (qy * qz - qw * qx));
     xd[9] = a * (1.f - 2.f * (qx * qx + qy * qy)) - P.g;
+    if (P.drag) {
+        float R[9];
+        quat_matrix(qx, qy, qz, qw, R);
+        drag_acc(R, x + 7, P.cd, P.inv_m, xd + 7);
+    }
+    if (P.gyro) {
+        // -w x h - h', h = J_p Omega_s e_z, Omega_s = sum sigma_i Omega_i
+        float om_s = 0.f, dom_s = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            om_s += P.sg[i] * x[13 + i];
+            dom_s += P.sg[i] * xd[13 + i];
+        }
+        tx -= P.jp * wy * om_s;
+        ty += P.jp * wx * om_s;
+        tz -= P.jp * dom_s;
+    }
     xd[10] = (tx - P.dJx * wy * wz) * P.iJx;
     xd[11] = (ty - P.dJy * wz * wx) * P.iJy;
     xd[12] = (tz - P.dJz * wx * wy) * P.iJz;
@@ -222,11 +333,26 @@ __device__ __forceinline__ void fp_rates_vjp(const float* x, const float* rc, co
     xb[4] += 2.f * (qw * r0b + qz * r1b) - 4.f * qy * r2b;
     xb[5] += 2.f * (qx * r0b + qy * r1b);
     xb[6] += 2.f * (qy * r0b - qx * r1b);
+    if (P.drag) {
+        float R[9], Rb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        quat_matrix(qx, qy, qz, qw, R);
+        drag_acc_vjp(R, x + 7, P.cd, P.inv_m, gb + 7, xb + 7, Rb);
+        quat_matrix_vjp(qx, qy, qz, qw, Rb, xb + 3);
+    }
     // w' = (tau - w x J w) / J
     const float hx = gb[10] * P.iJx, hy = gb[11] * P.iJy, hz = gb[12] * P.iJz;
     xb[10] -= hy * P.dJy * wz + hz * P.dJz * wy;
     xb[11] -= hx * P.dJx * wz + hz * P.dJz * wx;
     xb[12] -= hx * P.dJx * wy + hy * P.dJy * wx;
+    float om_sb = 0.f;
+    if (P.gyro) {
+        float om_s = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) om_s += P.sg[i] * x[13 + i];
+        xb[11] -= P.jp * om_s * hx;
+        xb[10] += P.jp * om_s * hy;
+        om_sb = P.jp * (wx * hy - wy * hx);
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float r = x[13 + i];
@@ -235,7 +361,9 @@ __device__ __forceinline__ void fp_rates_vjp(const float* x, const float* rc, co
         const bool up = rc[i] >= r;
         const float cv = up ? P.cvu : P.cvd;
         const float cd = up ? P.cdu : P.cdd;
-        const float gr = gb[13 + i];
+        // adjoint of the rotor acceleration: the state derivative, plus the reaction torque
+        const float gr = gb[13 + i] - (P.gyro ? P.jp * P.sg[i] * hz : 0.f);
+        if (P.gyro) xb[13 + i] += P.sg[i] * om_sb;
         xb[13 + i] += fb * (P.k1 + 2.f * P.k2 * r) + tqb * (P.t1 + 2.f * P.t2 * r)
                       - gr * (cv + 2.f * cd * r);
         rcb[i] += gr * (cv + 2.f * cd * rc[i]);
@@ -254,6 +382,11 @@ __device__ __forceinline__ void id_rates(const float* x, const float* u, const I
     xd[6] = a * (cps * sth * cph + sps * sph);
     xd[7] = a * (sps * sth * cph - cps * sph);
     xd[8] = a * (cth * cph) - P.g;
+    if (P.drag) {
+        float R[9];
+        euler_matrix(sn, cs, R);
+        drag_acc(R, x + 6, P.cd, P.inv_m, xd + 6);
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) xd[9 + i] = P.c1[i] * x[3 + i] + P.c2[i] * x[9 + i] + P.c3[i] * u[i];
     xd[12] = P.ctau * (u[3] - x[12]);
@@ -277,6 +410,12 @@ __device__ __forceinline__ void id_rates_vjp(const float* x, const float* u, con
     xb[3] += b0 * (sps * cph - cps * sth * sph) + b1 * (-sps * sth * sph - cps * cph) + b2 * (-cth * sph);
     xb[4] += b0 * (cps * cth * cph) + b1 * (sps * cth * cph) + b2 * (-sth * cph);
     xb[5] += b0 * (cps * sph - sps * sth * cph) + b1 * (cps * sth * cph + sps * sph);
+    if (P.drag) {
+        float R[9], Rb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        euler_matrix(sn, cs, R);
+        drag_acc_vjp(R, x + 6, P.cd, P.inv_m, gb + 6, xb + 6, Rb);
+        euler_matrix_vjp(sn, cs, Rb, xb + 3);
+    }
     // Psi'' = c1 Psi + c2 dPsi + c3 Psi_cmd
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -298,6 +437,33 @@ struct PidTrace {
 
 __device__ __forceinline__ float rotor_root(float f, float disc, const FpParams& P) {
     return disc > 0.f ? (sqrt_hw(disc) - P.k1) * P.inv_2k2 : -P.k1 * P.inv_2k2;
+}
+
+// Motor allocation: f = alloc [T, tau_x, tau_y, tau_z], clamped to [0, f_max],
+// rotor-speed commands from the thrust curve. Also the torque interface.
+__device__ __forceinline__ void allocate(const float* wrench, const FpParams& P, const PidParams& C, float* rc,
+                                         PidTrace& tr) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float fr = C.A[4 * j] * wrench[0] + C.A[4 * j + 1] * wrench[1] + C.A[4 * j + 2] * wrench[2] +
+                         C.A[4 * j + 3] * wrench[3];
+        tr.fraw[j] = fr;
+        const float f = fminf(fmaxf(fr, 0.f), C.fmax);
+        tr.disc[j] = P.k1 * P.k1 - 4.f * P.k2 * (P.k0 - f);
+        rc[j] = rotor_root(f, tr.disc[j], P);
+    }
+}
+
+// VJP of allocate: wb += (d rc / d wrench)^T rcb
+__device__ __forceinline__ void allocate_vjp(const PidParams& C, const PidTrace& tr, const float* rcb, float* wb) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float fr = tr.fraw[j];
+        const bool pass = (fr >= 0.f) && (fr <= C.fmax) && (tr.disc[j] > 0.f);
+        const float fb = pass ? rcb[j] * rsqrt_hw(tr.disc[j]) : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wb[i] += C.A[4 * j + i] * fb;
+    }
 }
 
 // x: 25-component state; u: [roll, pitch, yawrate, thrust]. Writes rotor
@@ -328,14 +494,8 @@ __device__ __forceinline__ void pid_forward(const float* x, const float* u, cons
         tq[i] = C.jc[i] * al;
         cs[5 + i] = w;
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const float fr = C.A[4 * j] * u[3] + C.A[4 * j + 1] * tq[0] + C.A[4 * j + 2] * tq[1] + C.A[4 * j + 3] * tq[2];
-        tr.fraw[j] = fr;
-        const float f = fminf(fmaxf(fr, 0.f), C.fmax);
-        tr.disc[j] = P.k1 * P.k1 - 4.f * P.k2 * (P.k0 - f);
-        rc[j] = rotor_root(f, tr.disc[j], P);
-    }
+    const float wrench[4] = {u[3], tq[0], tq[1], tq[2]};
+    allocate(wrench, P, C, rc, tr);
 }
 
 // VJP of pid_forward. rcb: adjoint of rc; csb: adjoint of the new controller state.
@@ -343,17 +503,10 @@ __device__ __forceinline__ void pid_forward(const float* x, const float* u, cons
 __device__ __forceinline__ void pid_vjp(const float* x, const FpParams& P, const PidParams& C,
                                         float dt, float inv_dt, const PidTrace& tr,
                                         const float* rcb, const float* csb, float* xb, float* ub) {
-    float tqb[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const float fr = tr.fraw[j];
-        const bool pass = (fr >= 0.f) && (fr <= C.fmax) && (tr.disc[j] > 0.f);
-        const float fb = pass ? rcb[j] * rsqrt_hw(tr.disc[j]) : 0.f;
-        ub[3] += C.A[4 * j] * fb;
-        tqb[0] += C.A[4 * j + 1] * fb;
-        tqb[1] += C.A[4 * j + 2] * fb;
-        tqb[2] += C.A[4 * j + 3] * fb;
-    }
+    float wb[4] = {0.f, 0.f, 0.f, 0.f};
+    allocate_vjp(C, tr, rcb, wb);
+    ub[3] += wb[0];
+    const float tqb[3] = {wb[1], wb[2], wb[3]};
     float rsb[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -442,9 +595,40 @@ constexpr uint32_t COMP_NONE = 0u;
 // follows the step); it receives y only when NEED_Y. Writes
 // xb = (dPhi/dx)^T yb; vjp(xin, gb, xa) adds (d rates/d xin)^T gb into xa and
 // accumulates the command adjoint itself.
-template <int N, int INTEG, bool NEED_Y, class Rates, class Vjp, class Post>
+// Stage states of RK4 kept in registers, or (IN_LDS) in this lane's LDS slots
+// (stride `sstride`, three stages of N values).
+template <int N, bool IN_LDS>
+struct StageStore;
+template <int N>
+struct StageStore<N, false> {
+    float reg[3][N];
+    __device__ __forceinline__ void put(int st, const float* v) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) reg[st][i] = v[i];
+    }
+    __device__ __forceinline__ void get(int st, float* v) const {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = reg[st][i];
+    }
+};
+template <int N>
+struct StageStore<N, true> {
+    volatile float* stage;
+    int sstride;
+    __device__ __forceinline__ void put(int st, const float* v) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) stage[(st * N + i) * sstride] = v[i];
+    }
+    __device__ __forceinline__ void get(int st, float* v) const {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = stage[(st * N + i) * sstride];
+    }
+};
+
+template <int N, int INTEG, bool NEED_Y, bool LDS_STAGES, class Rates, class Vjp, class Post>
 __device__ __forceinline__ void integrate_vjp(const float* x, float h, const float* yb_in, float* xb,
-                                              const Rates& rates, const Vjp& vjp, const Post& post) {
+                                              const Rates& rates, const Vjp& vjp, const Post& post,
+                                              float* stage_lds = nullptr, int sstride = 0) {
     float yb[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) yb[i] = yb_in[i];
@@ -462,20 +646,26 @@ __device__ __forceinline__ void integrate_vjp(const float* x, float h, const flo
         vjp(x, gb, xb);
     } else {
         const float h2 = 0.5f * h;
-        float x2[N], x3[N], x4[N], k[N];
+        StageStore<N, LDS_STAGES> ss;
+        if constexpr (LDS_STAGES) {
+            ss.stage = stage_lds;
+            ss.sstride = sstride;
+        }
+        float xs[N], k[N], acc[N];
         rates(x, k);
-        float acc[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) { x2[i] = x[i] + h2 * k[i]; acc[i] = k[i]; }
-        rates(x2, k);
+        for (int i = 0; i < N; ++i) { xs[i] = x[i] + h2 * k[i]; acc[i] = k[i]; }
+        ss.put(0, xs);
+        rates(xs, k);
 #pragma unroll
-        for (int i = 0; i < N; ++i) { x3[i] = x[i] + h2 * k[i]; acc[i] += 2.f * k[i]; }
-        rates(x3, k);
+        for (int i = 0; i < N; ++i) { xs[i] = x[i] + h2 * k[i]; acc[i] += 2.f * k[i]; }
+        ss.put(1, xs);
+        rates(xs, k);
 #pragma unroll
-        for (int i = 0; i < N; ++i) { x4[i] = x[i] + h * k[i]; acc[i] += 2.f * k[i]; }
+        for (int i = 0; i < N; ++i) { xs[i] = x[i] + h * k[i]; acc[i] += 2.f * k[i]; }
         const float h6 = h * (1.0f / 6.0f), h3 = h * (1.0f / 3.0f);
         if constexpr (NEED_Y) {
-            rates(x4, k);
+            rates(xs, k);
             float y[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) y[i] = x[i] + h6 * (acc[i] + k[i]);
@@ -486,16 +676,18 @@ __device__ __forceinline__ void integrate_vjp(const float* x, float h, const flo
         float gb[N], a[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) { xb[i] = yb[i]; gb[i] = h6 * yb[i]; a[i] = 0.f; }
-        vjp(x4, gb, a);
+        vjp(xs, gb, a);                       // stage 4 at x + h k3
 #pragma unroll
         for (int i = 0; i < N; ++i) { xb[i] += a[i]; gb[i] = h3 * yb[i] + h * a[i]; a[i] = 0.f; }
-        vjp(x3, gb, a);
+        ss.get(1, xs);
+        vjp(xs, gb, a);                       // stage 3
 #pragma unroll
         for (int i = 0; i < N; ++i) { xb[i] += a[i]; gb[i] = h3 * yb[i] + h2 * a[i]; a[i] = 0.f; }
-        vjp(x2, gb, a);
+        ss.get(0, xs);
+        vjp(xs, gb, a);                       // stage 2
 #pragma unroll
         for (int i = 0; i < N; ++i) { xb[i] += a[i]; gb[i] = h6 * yb[i] + h2 * a[i]; a[i] = 0.f; }
-        vjp(x, gb, a);
+        vjp(x, gb, a);                        // stage 1
 #pragma unroll
         for (int i = 0; i < N; ++i) xb[i] += a[i];
     }
@@ -513,6 +705,9 @@ __device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, c
     if constexpr (CTRL == CTRL_PID) {
         PidTrace tr;
         pid_forward(x, u, P, C, dt, inv_dt, rc, cs, tr);
+    } else if constexpr (CTRL == CTRL_TORQUE) {
+        PidTrace tr;
+        allocate(u, P, C, rc, tr);
     } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) rc[i] = u[i];
@@ -539,11 +734,14 @@ __device__ __forceinline__ void id_step(float* x, float* comp, const float* u, c
 template <int CTRL, int INTEG>
 __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, const FpParams& P,
                                             const PidParams& C, float dt, float inv_dt, int renorm,
-                                            const float* yb, float* xb, float* ub) {
+                                            const float* yb, float* xb, float* ub,
+                                            float* stage_lds = nullptr, int sstride = 0) {
     float rc[4], cs[8];
     PidTrace tr;
     if constexpr (CTRL == CTRL_PID) {
         pid_forward(x, u, P, C, dt, inv_dt, rc, cs, tr);
+    } else if constexpr (CTRL == CTRL_TORQUE) {
+        allocate(u, P, C, rc, tr);
     } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) rc[i] = u[i];
@@ -562,14 +760,19 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
             ybr[5] = (ybr[5] - q2 * dot) * inv;
             ybr[6] = (ybr[6] - q3 * dot) * inv;
         };
-        integrate_vjp<S_FP, INTEG, true>(x, dt, yb, xb, rates, vjp, post);
+        if (stage_lds) integrate_vjp<S_FP, INTEG, true, true>(x, dt, yb, xb, rates, vjp, post, stage_lds, sstride);
+        else integrate_vjp<S_FP, INTEG, true, false>(x, dt, yb, xb, rates, vjp, post);
     } else {
-        integrate_vjp<S_FP, INTEG, false>(x, dt, yb, xb, rates, vjp, [](const float*, float*) {});
+        const auto none = [](const float*, float*) {};
+        if (stage_lds) integrate_vjp<S_FP, INTEG, false, true>(x, dt, yb, xb, rates, vjp, none, stage_lds, sstride);
+        else integrate_vjp<S_FP, INTEG, false, false>(x, dt, yb, xb, rates, vjp, none);
     }
     if constexpr (CTRL == CTRL_PID) {
 #pragma unroll
         for (int i = S_FP; i < S_PID; ++i) xb[i] = 0.f;
         pid_vjp(x, P, C, dt, inv_dt, tr, rcb, yb + S_FP, xb, ub);
+    } else if constexpr (CTRL == CTRL_TORQUE) {
+        allocate_vjp(C, tr, rcb, ub);
     } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) ub[i] += rcb[i];
@@ -579,7 +782,7 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
 template <int INTEG>
 __device__ __forceinline__ void id_step_vjp(const float* x, const float* u, const IdParams& P, float dt,
                                             const float* yb, float* xb, float* ub) {
-    integrate_vjp<S_ID, INTEG, false>(
+    integrate_vjp<S_ID, INTEG, false, false>(
         x, dt, yb, xb,
         [&](const float* xi, float* xd) { id_rates(xi, u, P, xd); },
         [&](const float* xi, const float* gb, float* xa) { id_rates_vjp(xi, u, P, gb, xa, ub); },

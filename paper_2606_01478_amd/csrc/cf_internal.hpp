@@ -21,6 +21,7 @@ struct KernelSel {
     int integ;   // EULER / RK4
     int mode;    // LM_*
     int tile;    // lanes per workgroup (64, 128, 256)
+    int aero;    // kernels with gyroscopic/reaction torques and drag compiled in
 };
 
 struct StepArgs {
@@ -39,6 +40,7 @@ struct StepArgs {
 
 struct RollArgs {
     const float* x0;        // [S][D]
+    int S_h;                // rows of the handle's state (stride between checkpoints)
     const float* cmds;      // [T][4][D]
     int T;
     int64_t D;
@@ -71,6 +73,37 @@ struct RollArgs {
     float* ggc;             // [52][D] per-drone gain-gradient contributions or null
     float* seg;             // [K][S][D] segment scratch
 };
+
+// sampled-rollout controller (one world's model, C controllers x N samples)
+constexpr int MPPI_MAX_OBS = 16;
+constexpr int MPPI_MAX_ELITE = 4096;
+constexpr int MPPI_SELECT_THREADS = 1024;
+struct MppiArgs {
+    const float* par;        // the world's record [NPARAM]
+    const float* x_now;      // [S]
+    const float* mean;       // [C][H][4] previous plan (read at min(t + shift, H - 1))
+    float* mean_out;         // [C][H][4] new plan (may alias mean)
+    int C, N, H, sub, n_e, shift;
+    float dt, inv_dt;
+    int renorm;
+    float sigma[4], beta, beta_c, inv_lambda;
+    float u_lo[4], u_hi[4], u_ref[4], r_u[4];
+    float goal[3], q_p, q_v, w_obs;
+    int n_obs;
+    float obs[MPPI_MAX_OBS][4];  // centre, 1 / r^2
+    uint64_t seed, iter;
+    float* cost;             // [C][N]
+    float* eps_out;          // [C][N][H][4] (noise kernel only)
+    float* elite_u;          // scratch [C][H*4][n_e]
+    int32_t* elite_idx;      // [C][n_e]
+    float* elite_cost;       // [C][n_e]
+    float* cost_min;         // [C]
+    float* u_apply;          // [4] or null
+    int32_t* best;           // [1] or null
+};
+hipError_t launch_mppi_rollout(const KernelSel& ks, const MppiArgs& a, hipStream_t s);
+hipError_t launch_mppi_noise(const MppiArgs& a, hipStream_t s);
+hipError_t launch_mppi_select(const MppiArgs& a, hipStream_t s);
 
 hipError_t launch_step(const KernelSel& ks, const StepArgs& a, const int4* tiles, int n_tiles,
                        unsigned* counter, int wq_blocks, hipStream_t s);

@@ -52,13 +52,19 @@ __device__ __forceinline__ void ref_state(const RollArgs& a, int t, const float*
     }
 }
 
-// applied command u = ubar + G e, e = x[0:13] - x_ref(t); returns e in ev
-template <int MODEL>
-__device__ __forceinline__ void applied_command(const RollArgs& a, const float* G, const float* x, int t,
-                                                const float* off, float f_hover, size_t d, float* u, float* ev) {
+// per-step command ubar_t of drone d
+__device__ __forceinline__ void load_cmd(const RollArgs& a, int t, size_t d, float* ub) {
     const size_t D = (size_t)a.D;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) u[i] = a.cmds[((size_t)t * 4 + i) * D + d];
+    for (int i = 0; i < 4; ++i) ub[i] = a.cmds[((size_t)t * 4 + i) * D + d];
+}
+
+// applied command u = ubar + G e, e = x[0:13] - x_ref(t); returns e in ev
+template <int MODEL>
+__device__ __forceinline__ void feedback(const RollArgs& a, const float* G, const float* x, int t, const float* off,
+                                         float f_hover, const float* ubar, float* u, float* ev) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] = ubar[i];
     if (G) {
         float xr[13];
         ref_state<MODEL>(a, t, off, f_hover, xr);
@@ -86,13 +92,13 @@ struct DroneParams {
     IdParams id;
 };
 
-template <int MODEL, int CTRL, class R>
+template <int MODEL, int CTRL, bool AERO, class R>
 __device__ __forceinline__ void load_params(const R& rec, DroneParams& p) {
     if constexpr (MODEL == MODEL_FP) {
-        p.fp = load_fp(rec);
-        if constexpr (CTRL == CTRL_PID) p.pid = load_pid(rec);
+        p.fp = load_fp<AERO>(rec);
+        if constexpr (CTRL != CTRL_ROTOR) p.pid = load_pid(rec);
     } else {
-        p.id = load_id(rec);
+        p.id = load_id<AERO>(rec);
     }
 }
 
@@ -105,9 +111,10 @@ __device__ __forceinline__ void model_step(float* x, float* comp, const float* u
 
 template <int MODEL, int CTRL, int INTEG>
 __device__ __forceinline__ void model_step_vjp(const float* x, const float* u, const DroneParams& p,
-                                               const RollArgs& a, const float* yb, float* xb, float* ub) {
+                                               const RollArgs& a, const float* yb, float* xb, float* ub,
+                                               float* stage_lds, int sstride) {
     if constexpr (MODEL == MODEL_FP)
-        fp_step_vjp<CTRL, INTEG>(x, u, p.fp, p.pid, a.dt, a.inv_dt, a.renorm, yb, xb, ub);
+        fp_step_vjp<CTRL, INTEG>(x, u, p.fp, p.pid, a.dt, a.inv_dt, a.renorm, yb, xb, ub, stage_lds, sstride);
     else
         id_step_vjp<INTEG>(x, u, p.id, a.dt, yb, xb, ub);
 }
@@ -125,13 +132,13 @@ __device__ __forceinline__ void load_rows(const float* src, size_t D, size_t d, 
 
 // ---------------------------------------------------------------------------
 // forward rollout of one drone
-template <int MODEL, int CTRL, int INTEG, class R>
+template <int MODEL, int CTRL, int INTEG, bool AERO, class R>
 __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
     constexpr int S = ModelTraits<MODEL, CTRL>::S;
     const size_t D = (size_t)a.D;
     const size_t SD = (size_t)S_h * D;
     DroneParams p;
-    load_params<MODEL, CTRL>(rec, p);
+    load_params<MODEL, CTRL, AERO>(rec, p);
     const float f_hover = (MODEL == MODEL_ID) ? p.id.f_hover : 0.f;
     float x[S], comp[S];
     load_rows<S>(a.x0, D, d, x);
@@ -146,9 +153,12 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
     if (a.ckpt) store_rows<S>(a.ckpt, D, d, x);
     if (a.traj) store_rows<S>(a.traj, D, d, x);
     float loss = 0.f;
+    float ubar[4];
+    load_cmd(a, 0, d, ubar);
     for (int t = 0; t < a.T; ++t) {
-        float u[4], ev[13];
-        applied_command<MODEL>(a, G, x, t, off, f_hover, d, u, ev);
+        float u[4], ev[13], unext[4];
+        if (t + 1 < a.T) load_cmd(a, t + 1, d, unext);   // issued early, used next step
+        feedback<MODEL>(a, G, x, t, off, f_hover, ubar, u, ev);
         if (a.has_obj) loss += a.w_u * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3]);
         model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a);
         if (a.has_obj) {
@@ -160,6 +170,8 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
         const int tn = t + 1;
         if (a.ckpt && tn < a.T && (tn % a.K) == 0) store_rows<S>(a.ckpt + (size_t)(tn / a.K) * SD, D, d, x);
         if (a.traj) store_rows<S>(a.traj + (size_t)tn * SD, D, d, x);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ubar[i] = unext[i];
     }
     if (a.xT) store_rows<S>(a.xT, D, d, x);
     if (a.loss) a.loss[d] = loss;
@@ -173,13 +185,17 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
 
 // ---------------------------------------------------------------------------
 // adjoint of one drone's rollout
-template <int MODEL, int CTRL, int INTEG, class R>
-__device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
+// gacc: this lane's 52 gain-gradient accumulators in LDS, stride `gstride`
+// (one writer per slot, so the sums keep a fixed order); stage: this lane's
+// LDS slots for the RK4 stage states of the first-principles model
+template <int MODEL, int CTRL, int INTEG, bool AERO, class R>
+__device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
+                                                  float* gacc, float* stage, int gstride) {
     constexpr int S = ModelTraits<MODEL, CTRL>::S;
     const size_t D = (size_t)a.D;
     const size_t SD = (size_t)S_h * D;
     DroneParams p;
-    load_params<MODEL, CTRL>(rec, p);
+    load_params<MODEL, CTRL, AERO>(rec, p);
     const float f_hover = (MODEL == MODEL_ID) ? p.id.f_hover : 0.f;
     float off[3] = {0.f, 0.f, 0.f};
     if (a.has_obj && a.ref_off) {
@@ -192,10 +208,9 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
     float lam[S];
 #pragma unroll
     for (int i = 0; i < S; ++i) lam[i] = 0.f;
-    float gG[NG];
     if (G) {
 #pragma unroll
-        for (int i = 0; i < NG; ++i) gG[i] = 0.f;
+        for (int i = 0; i < NG; ++i) gacc[i * gstride] = 0.f;
     }
     const int nseg = (a.T + a.K - 1) / a.K;
     for (int s = nseg - 1; s >= 0; --s) {
@@ -210,8 +225,9 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
         for (int i = 0; i < S; ++i) comp[i] = 0.f;
         const int n_re = (s == nseg - 1) ? (t1 - t0) : (t1 - t0 - 1);
         for (int j = 0; j < n_re; ++j) {
-            float u[4], ev[13];
-            applied_command<MODEL>(a, G, x, t0 + j, off, f_hover, d, u, ev);
+            float u[4], ev[13], ubar[4];
+            load_cmd(a, t0 + j, d, ubar);
+            feedback<MODEL>(a, G, x, t0 + j, off, f_hover, ubar, u, ev);
             model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a);
             if (j + 1 < t1 - t0) store_rows<S>(a.seg + (size_t)(j + 1) * SD, D, d, x);
         }
@@ -223,20 +239,29 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
             for (int j = 0; j < 3; ++j) pn[j] = nxt[j * D + d];
         }
+        // x_t and ubar_t of the step being differentiated are loaded one
+        // iteration ahead, so the loads overlap the previous step's VJP
+        const float* ck = a.ckpt_in + (size_t)s * SD;
+        float xc[S], uc[4];
+        load_rows<S>((t1 - 1 > t0) ? a.seg + (size_t)(t1 - 1 - t0) * SD : ck, D, d, xc);
+        load_cmd(a, t1 - 1, d, uc);
         for (int t = t1 - 1; t >= t0; --t) {
+            float xn[S], un[4];
+            if (t > t0) {
+                load_rows<S>((t - 1 > t0) ? a.seg + (size_t)(t - 1 - t0) * SD : ck, D, d, xn);
+                load_cmd(a, t - 1, d, un);
+            }
             if (a.has_obj) {
                 float pr[3];
                 ref_pos(a, t + 1, off, pr);
 #pragma unroll
                 for (int j = 0; j < 3; ++j) lam[j] += two_seed * (pn[j] - pr[j]);
             }
-            const float* src = (t > t0) ? a.seg + (size_t)(t - t0) * SD : a.ckpt_in + (size_t)s * SD;
-            load_rows<S>(src, D, d, x);
             float u[4], ev[13];
-            applied_command<MODEL>(a, G, x, t, off, f_hover, d, u, ev);
+            feedback<MODEL>(a, G, xc, t, off, f_hover, uc, u, ev);
             float xb[S];
             float ub[4] = {0.f, 0.f, 0.f, 0.f};
-            model_step_vjp<MODEL, CTRL, INTEG>(x, u, p, a, lam, xb, ub);
+            model_step_vjp<MODEL, CTRL, INTEG>(xc, u, p, a, lam, xb, ub, stage, gstride);
             if (a.has_obj) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) ub[i] += two_seed * a.w_u * u[i];
@@ -256,18 +281,26 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
 #pragma unroll
-                    for (int j = 0; j < 13; ++j) gG[i * 13 + j] += ub[i] * ev[j];
+                    for (int j = 0; j < 13; ++j) atomicAdd(gacc + (i * 13 + j) * gstride, ub[i] * ev[j]);
                 }
             }
 #pragma unroll
             for (int i = 0; i < S; ++i) lam[i] = xb[i];
-            pn[0] = x[0]; pn[1] = x[1]; pn[2] = x[2];
+            pn[0] = xc[0]; pn[1] = xc[1]; pn[2] = xc[2];
+            if (t > t0) {
+#pragma unroll
+                for (int i = 0; i < S; ++i) xc[i] = xn[i];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) uc[i] = un[i];
+            }
         }
     }
     if (a.g_x0) store_rows<S>(a.g_x0, D, d, lam);
     if (a.ggc) {
-        if (G) store_rows<NG>(a.ggc, D, d, gG);
-        else {
+        if (G) {
+#pragma unroll
+            for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = gacc[i * gstride];
+        } else {
 #pragma unroll
             for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = 0.f;
         }
@@ -277,23 +310,30 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 // ---------------------------------------------------------------------------
 // kernels
 
-template <bool BWD, int MODEL, int CTRL, int INTEG, class R>
+template <bool BWD, int MODEL, int CTRL, int INTEG, bool AERO, class R>
 __device__ __forceinline__ void rollout_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
-    if constexpr (BWD) rollout_bwd_drone<MODEL, CTRL, INTEG>(rec, a, d, w, S_h);
-    else rollout_fwd_drone<MODEL, CTRL, INTEG>(rec, a, d, w, S_h);
+    if constexpr (BWD) {
+        // dynamic LDS: [52][blockDim] gain accumulators, then [3*17][blockDim] RK4 stage states
+        extern __shared__ float bwd_lds[];
+        float* gacc = bwd_lds + threadIdx.x;
+        float* stage = (MODEL == MODEL_FP && INTEG == RK4) ? bwd_lds + NG * blockDim.x + threadIdx.x : nullptr;
+        rollout_bwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h, gacc, stage, (int)blockDim.x);
+    } else {
+        rollout_fwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
+    }
 }
 
-template <bool BWD, int MODELS, int CTRL, int INTEG>
+template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
 __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
     const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= (size_t)a.D) return;
     const int w = a.drone_world[d];
     const SoaRec rec{a.par_soa, a.M, w};
-    if constexpr (MODELS == MS_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG>(rec, a, d, w, S_h);
-    else rollout_drone<BWD, MODEL_ID, CTRL, INTEG>(rec, a, d, w, S_h);
+    if constexpr (MODELS == MS_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
+    else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
 }
 
-template <bool BWD, int MODELS, int CTRL, int INTEG>
+template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
 __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __restrict__ tiles, int S_h) {
     const int4 td = tiles[blockIdx.x];
     const int w = __builtin_amdgcn_readfirstlane(td.x);
@@ -304,63 +344,74 @@ __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __
     const AosRec rec{a.par_aos + (size_t)w * NPARAM};
     const size_t d = (size_t)d0 + threadIdx.x;
     if constexpr (MODELS == MS_FP) {
-        rollout_drone<BWD, MODEL_FP, CTRL, INTEG>(rec, a, d, w, S_h);
+        rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
     } else if constexpr (MODELS == MS_ID) {
-        rollout_drone<BWD, MODEL_ID, CTRL, INTEG>(rec, a, d, w, S_h);
+        rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
     } else {
-        if (model == MODEL_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG>(rec, a, d, w, S_h);
-        else rollout_drone<BWD, MODEL_ID, CTRL, INTEG>(rec, a, d, w, S_h);
+        if (model == MODEL_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
+        else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
     }
 }
 
-static int handle_rows(int models, int ctrl) {
-    if (models & MS_FP) return ctrl == CTRL_PID ? S_PID : S_FP;
-    return S_ID;
-}
-
-template <bool BWD, int MODELS, int CTRL, int INTEG>
+template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
 static hipError_t launch_roll_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                 hipStream_t s) {
-    const int S_h = handle_rows(MODELS, CTRL);
+    const int S_h = a.S_h;
+    // adjoint LDS per lane: gain-gradient accumulators and first-principles RK4 stage states
+    const size_t shmem = BWD ? (size_t)(NG + ((MODELS & MS_FP) && INTEG == RK4 ? 3 * S_FP : 0)) * ks.tile *
+                                   sizeof(float)
+                             : 0;
     if (ks.mode == LM_LANE) {
         if constexpr (MODELS != MS_BOTH) {
             const int bs = ks.tile;
             const unsigned grid = (unsigned)((a.D + bs - 1) / bs);
-            hipLaunchKernelGGL((k_rollout_lane<BWD, MODELS, CTRL, INTEG>), dim3(grid), dim3(bs), 0, s, a, S_h);
+            hipLaunchKernelGGL((k_rollout_lane<BWD, MODELS, CTRL, INTEG, AERO>), dim3(grid), dim3(bs), shmem, s, a, S_h);
         } else {
             return hipErrorInvalidValue;
         }
     } else {
-        hipLaunchKernelGGL((k_rollout_tile<BWD, MODELS, CTRL, INTEG>), dim3(n_tiles), dim3(ks.tile), 0, s, a,
+        hipLaunchKernelGGL((k_rollout_tile<BWD, MODELS, CTRL, INTEG, AERO>), dim3(n_tiles), dim3(ks.tile), shmem, s, a,
                            tiles, S_h);
     }
     return hipGetLastError();
 }
 
-template <int MODELS, int CTRL, int INTEG>
+template <int MODELS, int CTRL, int INTEG, bool AERO>
 static hipError_t launch_fwd_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                hipStream_t s) {
-    return launch_roll_t<false, MODELS, CTRL, INTEG>(ks, a, tiles, n_tiles, s);
+    return launch_roll_t<false, MODELS, CTRL, INTEG, AERO>(ks, a, tiles, n_tiles, s);
 }
-template <int MODELS, int CTRL, int INTEG>
+template <int MODELS, int CTRL, int INTEG, bool AERO>
 static hipError_t launch_bwd_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                hipStream_t s) {
-    return launch_roll_t<true, MODELS, CTRL, INTEG>(ks, a, tiles, n_tiles, s);
+    return launch_roll_t<true, MODELS, CTRL, INTEG, AERO>(ks, a, tiles, n_tiles, s);
 }
 
-#define CF_DISPATCH(FN, ...)                                                             \
-    switch (ks.models * 4 + ks.ctrl * 2 + ks.integ) {                                    \
-        case MS_FP * 4 + 0: return FN<MS_FP, CTRL_ROTOR, EULER>(__VA_ARGS__);            \
-        case MS_FP * 4 + 1: return FN<MS_FP, CTRL_ROTOR, RK4>(__VA_ARGS__);              \
-        case MS_FP * 4 + 2: return FN<MS_FP, CTRL_PID, EULER>(__VA_ARGS__);              \
-        case MS_FP * 4 + 3: return FN<MS_FP, CTRL_PID, RK4>(__VA_ARGS__);                \
-        case MS_ID * 4 + 0: case MS_ID * 4 + 2: return FN<MS_ID, CTRL_ROTOR, EULER>(__VA_ARGS__); \
-        case MS_ID * 4 + 1: case MS_ID * 4 + 3: return FN<MS_ID, CTRL_ROTOR, RK4>(__VA_ARGS__);   \
-        case MS_BOTH * 4 + 0: return FN<MS_BOTH, CTRL_ROTOR, EULER>(__VA_ARGS__);        \
-        case MS_BOTH * 4 + 1: return FN<MS_BOTH, CTRL_ROTOR, RK4>(__VA_ARGS__);          \
-        case MS_BOTH * 4 + 2: return FN<MS_BOTH, CTRL_PID, EULER>(__VA_ARGS__);          \
-        case MS_BOTH * 4 + 3: return FN<MS_BOTH, CTRL_PID, RK4>(__VA_ARGS__);            \
+#define CF_DISPATCH_A(FN, A, ...)                                                        \
+    switch (ks.models * 8 + ks.ctrl * 2 + ks.integ) {                                    \
+        case MS_FP * 8 + 0: return FN<MS_FP, CTRL_ROTOR, EULER, A>(__VA_ARGS__);         \
+        case MS_FP * 8 + 1: return FN<MS_FP, CTRL_ROTOR, RK4, A>(__VA_ARGS__);           \
+        case MS_FP * 8 + 2: return FN<MS_FP, CTRL_PID, EULER, A>(__VA_ARGS__);           \
+        case MS_FP * 8 + 3: return FN<MS_FP, CTRL_PID, RK4, A>(__VA_ARGS__);             \
+        case MS_FP * 8 + 4: return FN<MS_FP, CTRL_TORQUE, EULER, A>(__VA_ARGS__);        \
+        case MS_FP * 8 + 5: return FN<MS_FP, CTRL_TORQUE, RK4, A>(__VA_ARGS__);          \
+        case MS_ID * 8 + 0: case MS_ID * 8 + 2: case MS_ID * 8 + 4:                      \
+            return FN<MS_ID, CTRL_ROTOR, EULER, A>(__VA_ARGS__);                         \
+        case MS_ID * 8 + 1: case MS_ID * 8 + 3: case MS_ID * 8 + 5:                      \
+            return FN<MS_ID, CTRL_ROTOR, RK4, A>(__VA_ARGS__);                           \
+        case MS_BOTH * 8 + 0: return FN<MS_BOTH, CTRL_ROTOR, EULER, A>(__VA_ARGS__);     \
+        case MS_BOTH * 8 + 1: return FN<MS_BOTH, CTRL_ROTOR, RK4, A>(__VA_ARGS__);       \
+        case MS_BOTH * 8 + 2: return FN<MS_BOTH, CTRL_PID, EULER, A>(__VA_ARGS__);       \
+        case MS_BOTH * 8 + 3: return FN<MS_BOTH, CTRL_PID, RK4, A>(__VA_ARGS__);         \
+        case MS_BOTH * 8 + 4: return FN<MS_BOTH, CTRL_TORQUE, EULER, A>(__VA_ARGS__);    \
+        case MS_BOTH * 8 + 5: return FN<MS_BOTH, CTRL_TORQUE, RK4, A>(__VA_ARGS__);      \
         default: break;                                                                  \
+    }
+#define CF_DISPATCH(FN, ...)                                                             \
+    if (ks.aero) {                                                                       \
+        CF_DISPATCH_A(FN, true, __VA_ARGS__)                                             \
+    } else {                                                                             \
+        CF_DISPATCH_A(FN, false, __VA_ARGS__)                                            \
     }
 
 hipError_t launch_rollout_fwd(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,

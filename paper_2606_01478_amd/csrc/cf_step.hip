@@ -7,15 +7,15 @@
 namespace cfk {
 
 // One drone, K steps with a held command; state rows st[i*D + d].
-template <int MODEL, int CTRL, int INTEG, class R>
+template <int MODEL, int CTRL, int INTEG, bool AERO, class R>
 __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t d, int w) {
     const size_t D = (size_t)a.D;
     bool bad = false;
     if constexpr (MODEL == MODEL_FP) {
         constexpr int S = (CTRL == CTRL_PID) ? S_PID : S_FP;
-        const FpParams P = load_fp(rec);
+        const FpParams P = load_fp<AERO>(rec);
         PidParams C;
-        if constexpr (CTRL == CTRL_PID) C = load_pid(rec);
+        if constexpr (CTRL != CTRL_ROTOR) C = load_pid(rec);
         float x[S], u[4], comp[S_FP];
 #pragma unroll
         for (int i = 0; i < S; ++i) x[i] = a.st[i * D + d];
@@ -30,7 +30,7 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
             bad |= !isfinite(x[i]);
         }
     } else {
-        const IdParams P = load_id(rec);
+        const IdParams P = load_id<AERO>(rec);
         float x[S_ID], u[4], comp[S_ID];
 #pragma unroll
         for (int i = 0; i < S_ID; ++i) { x[i] = a.st[i * D + d]; comp[i] = 0.f; }
@@ -46,7 +46,7 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
     if (a.nonfinite && bad) atomicOr(a.nonfinite + w, 1u);
 }
 
-template <int MODELS, int CTRL, int INTEG>
+template <int MODELS, int CTRL, int INTEG, bool AERO>
 __device__ __forceinline__ void run_tile(const StepArgs& a, int4 td) {
     // td = {world, first drone, drone count, model}, uniform over the workgroup
     const int w = __builtin_amdgcn_readfirstlane(td.x);
@@ -58,33 +58,33 @@ __device__ __forceinline__ void run_tile(const StepArgs& a, int4 td) {
     const AosRec rec{a.par_aos + (size_t)w * NPARAM};
     const size_t d = (size_t)d0 + lane;
     if constexpr (MODELS == MS_FP) {
-        run_held<MODEL_FP, CTRL, INTEG>(rec, a, d, w);
+        run_held<MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w);
     } else if constexpr (MODELS == MS_ID) {
-        run_held<MODEL_ID, CTRL, INTEG>(rec, a, d, w);
+        run_held<MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w);
     } else {
-        if (model == MODEL_FP) run_held<MODEL_FP, CTRL, INTEG>(rec, a, d, w);
-        else run_held<MODEL_ID, CTRL, INTEG>(rec, a, d, w);
+        if (model == MODEL_FP) run_held<MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w);
+        else run_held<MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w);
     }
 }
 
-template <int MODELS, int CTRL, int INTEG>
+template <int MODELS, int CTRL, int INTEG, bool AERO>
 __global__ __launch_bounds__(256) void k_step_lane(StepArgs a) {
     const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= (size_t)a.D) return;
     const int w = a.drone_world[d];
     const SoaRec rec{a.par_soa, a.M, w};
-    if constexpr (MODELS == MS_FP) run_held<MODEL_FP, CTRL, INTEG>(rec, a, d, w);
-    else run_held<MODEL_ID, CTRL, INTEG>(rec, a, d, w);
+    if constexpr (MODELS == MS_FP) run_held<MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w);
+    else run_held<MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w);
 }
 
-template <int MODELS, int CTRL, int INTEG>
+template <int MODELS, int CTRL, int INTEG, bool AERO>
 __global__ __launch_bounds__(256) void k_step_tile(StepArgs a, const int4* __restrict__ tiles) {
-    run_tile<MODELS, CTRL, INTEG>(a, tiles[blockIdx.x]);
+    run_tile<MODELS, CTRL, INTEG, AERO>(a, tiles[blockIdx.x]);
 }
 
 // Persistent work queue: each workgroup pops the next tile index from *counter
 // until the tiles run out; every workgroup exits after one failed pop.
-template <int MODELS, int CTRL, int INTEG>
+template <int MODELS, int CTRL, int INTEG, bool AERO>
 __global__ __launch_bounds__(256) void k_step_wq(StepArgs a, const int4* __restrict__ tiles, int n_tiles,
                                                  unsigned* counter) {
     __shared__ int s_next;
@@ -94,48 +94,60 @@ __global__ __launch_bounds__(256) void k_step_wq(StepArgs a, const int4* __restr
         const int t = __builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
         if (t >= n_tiles) break;
-        run_tile<MODELS, CTRL, INTEG>(a, tiles[t]);
+        run_tile<MODELS, CTRL, INTEG, AERO>(a, tiles[t]);
     }
 }
 
-template <int MODELS, int CTRL, int INTEG>
+template <int MODELS, int CTRL, int INTEG, bool AERO>
 static hipError_t launch_step_t(const KernelSel& ks, const StepArgs& a, const int4* tiles, int n_tiles,
                                 unsigned* counter, int wq_blocks, hipStream_t s) {
     if (ks.mode == LM_LANE) {
         if constexpr (MODELS == MS_BOTH) return hipErrorInvalidValue;
         const int bs = ks.tile;
         const unsigned grid = (unsigned)((a.D + bs - 1) / bs);
-        hipLaunchKernelGGL((k_step_lane<MODELS, CTRL, INTEG>), dim3(grid), dim3(bs), 0, s, a);
+        hipLaunchKernelGGL((k_step_lane<MODELS, CTRL, INTEG, AERO>), dim3(grid), dim3(bs), 0, s, a);
     } else if (ks.mode == LM_TILE) {
-        hipLaunchKernelGGL((k_step_tile<MODELS, CTRL, INTEG>), dim3(n_tiles), dim3(ks.tile), 0, s, a, tiles);
+        hipLaunchKernelGGL((k_step_tile<MODELS, CTRL, INTEG, AERO>), dim3(n_tiles), dim3(ks.tile), 0, s, a, tiles);
     } else {
-        hipLaunchKernelGGL((k_step_wq<MODELS, CTRL, INTEG>), dim3(wq_blocks), dim3(ks.tile), 0, s, a, tiles,
+        hipLaunchKernelGGL((k_step_wq<MODELS, CTRL, INTEG, AERO>), dim3(wq_blocks), dim3(ks.tile), 0, s, a, tiles,
                            n_tiles, counter);
     }
     return hipGetLastError();
 }
 
-template <int MODELS, int CTRL, int INTEG>
+template <int MODELS, int CTRL, int INTEG, bool AERO>
 static int wq_blocks_t(int tile) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq<MODELS, CTRL, INTEG>, tile, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq<MODELS, CTRL, INTEG, AERO>, tile, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-#define CF_DISPATCH(FN, ...)                                                             \
-    switch (ks.models * 4 + ks.ctrl * 2 + ks.integ) {                                    \
-        case MS_FP * 4 + 0: return FN<MS_FP, CTRL_ROTOR, EULER>(__VA_ARGS__);            \
-        case MS_FP * 4 + 1: return FN<MS_FP, CTRL_ROTOR, RK4>(__VA_ARGS__);              \
-        case MS_FP * 4 + 2: return FN<MS_FP, CTRL_PID, EULER>(__VA_ARGS__);              \
-        case MS_FP * 4 + 3: return FN<MS_FP, CTRL_PID, RK4>(__VA_ARGS__);                \
-        case MS_ID * 4 + 0: case MS_ID * 4 + 2: return FN<MS_ID, CTRL_ROTOR, EULER>(__VA_ARGS__); \
-        case MS_ID * 4 + 1: case MS_ID * 4 + 3: return FN<MS_ID, CTRL_ROTOR, RK4>(__VA_ARGS__);   \
-        case MS_BOTH * 4 + 0: return FN<MS_BOTH, CTRL_ROTOR, EULER>(__VA_ARGS__);        \
-        case MS_BOTH * 4 + 1: return FN<MS_BOTH, CTRL_ROTOR, RK4>(__VA_ARGS__);          \
-        case MS_BOTH * 4 + 2: return FN<MS_BOTH, CTRL_PID, EULER>(__VA_ARGS__);          \
-        case MS_BOTH * 4 + 3: return FN<MS_BOTH, CTRL_PID, RK4>(__VA_ARGS__);            \
+#define CF_DISPATCH_A(FN, A, ...)                                                        \
+    switch (ks.models * 8 + ks.ctrl * 2 + ks.integ) {                                    \
+        case MS_FP * 8 + 0: return FN<MS_FP, CTRL_ROTOR, EULER, A>(__VA_ARGS__);         \
+        case MS_FP * 8 + 1: return FN<MS_FP, CTRL_ROTOR, RK4, A>(__VA_ARGS__);           \
+        case MS_FP * 8 + 2: return FN<MS_FP, CTRL_PID, EULER, A>(__VA_ARGS__);           \
+        case MS_FP * 8 + 3: return FN<MS_FP, CTRL_PID, RK4, A>(__VA_ARGS__);             \
+        case MS_FP * 8 + 4: return FN<MS_FP, CTRL_TORQUE, EULER, A>(__VA_ARGS__);        \
+        case MS_FP * 8 + 5: return FN<MS_FP, CTRL_TORQUE, RK4, A>(__VA_ARGS__);          \
+        case MS_ID * 8 + 0: case MS_ID * 8 + 2: case MS_ID * 8 + 4:                      \
+            return FN<MS_ID, CTRL_ROTOR, EULER, A>(__VA_ARGS__);                         \
+        case MS_ID * 8 + 1: case MS_ID * 8 + 3: case MS_ID * 8 + 5:                      \
+            return FN<MS_ID, CTRL_ROTOR, RK4, A>(__VA_ARGS__);                           \
+        case MS_BOTH * 8 + 0: return FN<MS_BOTH, CTRL_ROTOR, EULER, A>(__VA_ARGS__);     \
+        case MS_BOTH * 8 + 1: return FN<MS_BOTH, CTRL_ROTOR, RK4, A>(__VA_ARGS__);       \
+        case MS_BOTH * 8 + 2: return FN<MS_BOTH, CTRL_PID, EULER, A>(__VA_ARGS__);       \
+        case MS_BOTH * 8 + 3: return FN<MS_BOTH, CTRL_PID, RK4, A>(__VA_ARGS__);         \
+        case MS_BOTH * 8 + 4: return FN<MS_BOTH, CTRL_TORQUE, EULER, A>(__VA_ARGS__);    \
+        case MS_BOTH * 8 + 5: return FN<MS_BOTH, CTRL_TORQUE, RK4, A>(__VA_ARGS__);      \
         default: break;                                                                  \
+    }
+#define CF_DISPATCH(FN, ...)                                                             \
+    if (ks.aero) {                                                                       \
+        CF_DISPATCH_A(FN, true, __VA_ARGS__)                                             \
+    } else {                                                                             \
+        CF_DISPATCH_A(FN, false, __VA_ARGS__)                                            \
     }
 
 hipError_t launch_step(const KernelSel& ks, const StepArgs& a, const int4* tiles, int n_tiles,

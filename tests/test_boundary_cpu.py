@@ -123,14 +123,19 @@ def test_create_rejects_bad_counts_models_params(lib):
     assert _create(lib, d) == B.CF_EINVAL
     d, keep = _desc(w, params=None)
     assert _create(lib, d) == B.CF_EINVAL
-    # drag and propeller inertia are valid physics this build does not implement
+    # drag and propeller inertia are accepted; a negative propeller inertia is not
+    import torch
+    ok = B.CF_OK if torch.cuda.is_available() else B.CF_ENODEV
     d, keep = _desc(w)
     keep[2][0, B.PARAM_OFFSETS["drag"][0]] = -0.01
-    assert _create(lib, d) == B.CF_EUNSUPPORTED
+    assert _create(lib, d) == ok
     d, keep = _desc(w)
     fp = int(np.nonzero(w.model_per_world == 0)[0][0])
     keep[2][fp, B.PARAM_OFFSETS["Jp"][0]] = 1e-9
-    assert _create(lib, d) == B.CF_EUNSUPPORTED
+    assert _create(lib, d) == ok
+    d, keep = _desc(w)
+    keep[2][fp, B.PARAM_OFFSETS["Jp"][0]] = -1e-9
+    assert _create(lib, d) == B.CF_EINVAL
 
 
 def test_create_rejects_out_of_range_gain_index(lib):
@@ -176,3 +181,44 @@ def test_sim_raises_cferror_without_device():
     with pytest.raises(B.CfError) as ei:
         B.Sim.from_workload(W.small(2, 1))
     assert ei.value.status == B.CF_ENODEV
+
+
+def test_torque_interface_descriptor(lib):
+    """The torque interface is accepted (it reaches device selection) and, like the
+    attitude controller, needs a thrust curve with a positive quadratic term."""
+    import torch
+    ok = B.CF_OK if torch.cuda.is_available() else B.CF_ENODEV
+    w = W.fp_torque(seed=3, n_worlds=8)
+    d, keep = _desc(w)
+    assert _create(lib, d) == ok
+    d, keep = _desc(w)
+    keep[2][2, B.PARAM_OFFSETS["thrust_poly"][0] + 2] = 0.0
+    assert _create(lib, d) == B.CF_EINVAL
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Size and field offsets of every C struct of the header, as the host C
+    compiler lays them out, equal those of the ctypes mirrors in the binding."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"cf_desc": B._Desc, "cf_objective": B._Objective, "cf_mppi_desc": B._MppiDesc}
+    c_name = {"lambda_": "lambda"}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cfsim.h"', "int main(void) {"]
+    for s, py in structs.items():
+        lines.append(f'printf("{s} size %zu\\n", sizeof({s}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{s} {f} %zu\\n", offsetof({s}, {c_name.get(f, f)}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for s, py in structs.items():
+        assert got[(s, "size")] == ctypes.sizeof(py), s
+        for f, _ in py._fields_:
+            assert got[(s, f)] == getattr(py, f).offset, (s, f)

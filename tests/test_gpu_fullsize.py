@@ -88,17 +88,25 @@ def test_differentiable_checkpoint_invariance_full(gpu_lib):
 
 def test_uneven_2048_worlds_autotuned_launch(gpu_lib):
     """Full uneven mixed batch (~1M drones) in the autotuned launch configuration,
-    512 drones sampled against the oracle; grid and work queue give the same bits."""
+    512 drones sampled against the oracle. At one chunking (all steps in one
+    launch) the per-tile grid, the work queue and the single mixed-model launch
+    give the same bits; the autotuned chunking restarts the compensated sums at
+    each launch boundary, so it agrees with them to the parity bar."""
     w = W.config5()
     sim = B.Sim.from_workload(w)
     x = dev(w.x0)
     u = dev(w.cmds)
     sim.autotune(x, u, w.steps, 1500)
     sim.step_k(x, u, w.steps)
-    xq = dev(w.x0)
-    B.Sim.from_workload(w, flags=B.F_WORKQUEUE | B.F_NO_AUTOTUNE_CACHE).step_k(xq, u, w.steps)
+    one = {}
+    for name, flags in (("grid", 0), ("wq", B.F_WORKQUEUE), ("single", B.F_SINGLE_LAUNCH)):
+        xs = dev(w.x0)
+        B.Sim.from_workload(w, flags=flags | B.F_NO_AUTOTUNE_CACHE).step_k(xs, u, w.steps)
+        one[name] = xs
     torch.cuda.synchronize()
-    assert torch.equal(x, xq)
+    assert torch.equal(one["grid"], one["wq"])
+    assert torch.equal(one["grid"], one["single"])
+    assert_states_close(x, one["grid"], w, what="config5 autotuned vs one launch")
     idx = np.random.default_rng(1).choice(w.n_drones_total, 512, replace=False)
     ws = sample_drones(w, idx)
     assert_states_close(x[:, torch.as_tensor(idx, device="cuda")], O.simulate_held(ws), ws, what="config5 sampled")
@@ -162,3 +170,28 @@ def test_uneven_adjoint_subset_full(gpu_lib):
         ek = e[:, :, sel].permute(1, 0, 2).reshape(13, -1).t().contiguous()
         expect = gk @ ek
         assert (g_gain[k].double() - expect).norm() <= 1e-3 * expect.norm(), k
+
+
+def test_goal_gradient_2p20_worlds_sampled(gpu_lib):
+    """The gradient-throughput workload at full size (2^20 single-drone worlds,
+    10 steps, one checkpoint): per-drone loss and gradients of 256 sampled drones
+    vs the oracle; the per-drone results do not depend on the batch."""
+    w = W.gradient_goal()
+    sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
+    T = w.steps
+    x0, cmds, off = dev(w.x0), dev(w.cmds), dev(w.ref_offset)
+    obj = B.Sim.objective(ref_amp=w.ref_amp, ref_period=w.ref_period, ref_offset=off, w_u=w.w_u)
+    ckpt = torch.empty((1, sim.S, sim.D), device="cuda")
+    loss = torch.empty(sim.D, device="cuda")
+    sim.rollout(x0, cmds, T, obj, T, ckpt=ckpt, loss=loss)
+    g_cmds, g_x0 = torch.empty_like(cmds), torch.empty_like(x0)
+    sim.rollout_backward(x0, cmds, T, obj, T, ckpt, dloss=dev(w.dloss), g_cmds=g_cmds, g_x0=g_x0)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(3).choice(w.n_drones_total, 256, replace=False))
+    ws = W.subset(w, idx)
+    ref = O.rollout_workload(ws, with_grad=True)
+    ii = torch.as_tensor(idx, device="cuda")
+    lr = ref["loss"]
+    assert torch.all((loss[ii].double().cpu() - lr).abs() <= 1e-4 * lr.abs().clamp_min(1e-2))
+    assert_grad_close(g_cmds[:, :, ii], ref["g_cmds"], "goal g_cmds")
+    assert_grad_close(g_x0[:, ii], ref["g_x0"], "goal g_x0")

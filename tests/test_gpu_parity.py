@@ -304,3 +304,76 @@ def test_invalid_device_arguments_are_rejected(gpu_lib):
     with pytest.raises(B.CfError):
         sim.reset(x, x)
     assert sim.last_error() == B.CF_OK
+
+
+DRAG = np.array([-0.004, -0.006, -0.009], np.float32)
+
+
+def _with_aero(w):
+    fp = w.model_per_world == W.MODEL_FP
+    w.params["Jp"][fp, 0] = 4e-9
+    w.params["drag"][:] = DRAG
+    return w
+
+
+@pytest.mark.parametrize("wq", [False, True])
+def test_gyro_and_drag_held_steps(gpu_lib, wq):
+    """Rotor gyroscopic/reaction torques and linear drag (compile-time aero kernel
+    variant), mixed models, uneven worlds."""
+    w = _with_aero(W.small(5, seed=30))
+    sim = _sim(w, flags=B.F_WORKQUEUE if wq else 0)
+    x = dev(w.x0)
+    sim.step_k(x, dev(w.cmds), w.steps)
+    torch.cuda.synchronize()
+    assert_states_close(x, O.simulate_held(w), w, what="aero held")
+
+
+def test_gyro_and_drag_rollout_gradients(gpu_lib):
+    w = _with_aero(W.config5_adjoint(seed=31, n_worlds=12, n_subset=8, steps=100, n_max=70))
+    _check_against_oracle(w, _rollout_grads(w, 25))
+
+
+def test_gyro_and_drag_rotor_interface(gpu_lib):
+    w = _with_aero(W.config1(seed=32, n_worlds=40, steps=80))
+    w.ref_offset = w.x0[0:3].copy()
+    w.dloss = np.ones(40, np.float32)
+    w.w_u = 1e-9
+    _check_against_oracle(w, _rollout_grads(w, 20))
+
+
+@pytest.mark.parametrize("wq", [False, True])
+def test_torque_interface_held_steps(gpu_lib, wq):
+    """Collective thrust and body torques through the motor allocation, clamp and
+    thrust-curve root, 250 held steps per world."""
+    w = W.fp_torque(seed=40, n_worlds=300)
+    sim = _sim(w, flags=B.F_WORKQUEUE if wq else 0)
+    x = dev(w.x0)
+    sim.step_k(x, dev(w.cmds), w.steps)
+    torch.cuda.synchronize()
+    assert_states_close(x, O.simulate_held(w), w, what="torque held")
+
+
+def _torque_rollout_workload(seed, aero):
+    w = W.fp_torque(seed=seed, n_worlds=70, steps=60)
+    rng = np.random.default_rng(seed)
+    cmds = np.repeat(w.cmds[None], w.steps, 0).astype(np.float64)
+    cmds[:, 1:4] += rng.normal(0.0, 1e-5, size=(w.steps, 3, w.n_worlds))
+    w.cmds = cmds.astype(np.float32)
+    w.ref_offset = w.x0[0:3].copy()
+    w.dloss = np.linspace(0.5, 1.5, w.n_worlds).astype(np.float32)
+    w.w_u = 1e-2
+    return _with_aero(w) if aero else w
+
+
+@pytest.mark.parametrize("aero", [False, True])
+def test_torque_interface_rollout_gradients(gpu_lib, aero):
+    w = _torque_rollout_workload(41, aero)
+    _check_against_oracle(w, _rollout_grads(w, 15))
+
+
+def test_goal_distance_gradients(gpu_lib):
+    """Short-horizon goal-distance loss through the closed-loop controller (the
+    gradient-throughput workload at reduced size): loss and gradients w.r.t. the
+    per-step commands and the initial state vs the oracle's autograd."""
+    w = W.gradient_goal(seed=42, n_worlds=300)
+    _check_against_oracle(w, _rollout_grads(w, 10))

@@ -571,3 +571,183 @@ def test_gain_gradient_identity():
         e = traj[n, 0:13] - b.reference_state(p, v)
         acc += g["g_cmds"][n] @ e.T
     assert torch.allclose(acc, g["g_gain"][0], rtol=1e-10, atol=1e-14)
+
+
+# ---- rotor gyroscopic/reaction torques and linear drag ----------------------------------------
+
+def test_rotation_matrices_match_scipy():
+    rng = np.random.default_rng(20)
+    q = unit_quats(rng, 30)
+    assert np.allclose(O.rotation_matrix(torch.as_tensor(q)).numpy().transpose(2, 0, 1),
+                       Rotation.from_quat(q.T).as_matrix(), atol=1e-14)
+    psi = rng.uniform(-1, 1, (3, 30))
+    assert np.allclose(O.euler_zyx_matrix(torch.as_tensor(psi)).numpy().transpose(2, 0, 1),
+                       Rotation.from_euler("ZYX", psi[::-1].T).as_matrix(), atol=1e-14)
+
+
+def _gyro_batch(dt, jp=4e-9):
+    def edit(P):
+        P["Jp"][:] = jp
+        P["torque_poly"][:] = 0.0          # no rotor drag torque: no external torque at all
+        P["J"][:] = (1.3e-5, 1.55e-5, 2.3e-5)
+    return fp_batch(1, dt=dt, edit=edit)
+
+
+def test_gyroscopic_total_angular_momentum_conserved():
+    """Rotors at steady speeds (a, b, a, b): thrust and yaw torques vanish, so the
+    total angular momentum R(q) (J w + J_p Omega_s e_z) is conserved; the RK4
+    drift shrinks at fourth order. A wrong sign of the gyroscopic rows breaks
+    conservation at first order."""
+    J = np.array([1.3e-5, 1.55e-5, 2.3e-5])
+    jp = 4e-9
+    speeds = np.array([18000.0, 9000.0, 18000.0, 9000.0])
+    om_s = speeds[0] - speeds[1] + speeds[2] - speeds[3]
+    q0 = unit_quats(np.random.default_rng(21), 1)[:, 0]
+    w0 = np.array([6.0, -9.0, 4.0])
+    drifts = []
+    for dt in (2e-3, 1e-3):
+        b, _ = _gyro_batch(dt, jp)
+        x = torch.zeros(17, 1, dtype=F64)
+        x[3:7, 0] = torch.as_tensor(q0)
+        x[10:13, 0] = torch.as_tensor(w0)
+        x[13:17, 0] = torch.as_tensor(speeds)
+        y = run(b, x, torch.as_tensor(speeds[:, None]), int(round(0.5 / dt)))
+        w, q = y[10:13, 0].numpy(), y[3:7, 0].numpy()
+        L0 = Rotation.from_quat(q0).apply(J * w0 + np.array([0, 0, jp * om_s]))
+        L = Rotation.from_quat(q).apply(J * w + np.array([0, 0, jp * om_s]))
+        drifts.append(np.abs(L - L0).max())
+        assert drifts[-1] < 1e-6 * np.linalg.norm(L0)
+    assert 10 < drifts[0] / drifts[1] < 24
+    # the gyroscopic term matters here: without it the momentum is not conserved
+    b, _ = _gyro_batch(1e-3, 0.0)
+    x = torch.zeros(17, 1, dtype=F64)
+    x[3:7, 0] = torch.as_tensor(q0)
+    x[10:13, 0] = torch.as_tensor(w0)
+    x[13:17, 0] = torch.as_tensor(speeds)
+    y = run(b, x, torch.as_tensor(speeds[:, None]), 500)
+    L = Rotation.from_quat(y[3:7, 0].numpy()).apply(J * y[10:13, 0].numpy() + np.array([0, 0, jp * om_s]))
+    assert np.abs(L - L0).max() > 1e3 * drifts[1]
+
+
+def test_reaction_torque_of_rotor_spin_up():
+    """Spinning up rotors 1 and 3 from rest with no external torque: the body yaws
+    the other way, J_z w_z = -J_p (Omega_1 + Omega_3), exactly (RK4 integrates
+    both sides with the same weights)."""
+    jp = 4e-9
+    b, _ = _gyro_batch(2e-3, jp)
+    x = torch.zeros(17, 1, dtype=F64)
+    x[6] = 1.0
+    cmd = torch.tensor([[16000.0], [0.0], [16000.0], [0.0]], dtype=F64)
+    y = run(b, x, cmd, 150)
+    om_s = float(y[13, 0] - y[14, 0] + y[15, 0] - y[16, 0])
+    assert om_s > 1e4
+    assert abs(float(y[12, 0]) * 2.3e-5 + jp * om_s) < 1e-15 * jp * om_s * 1e3
+    assert abs(float(y[10, 0])) < 1e-12 and abs(float(y[11, 0])) < 1e-12
+
+
+def _affine_rk4(A, b, z0, h, n):
+    I = np.eye(len(z0))
+    X = h * A
+    R = I + X + X @ X / 2 + X @ X @ X / 6 + X @ X @ X @ X / 24
+    S = I + X / 2 + X @ X / 6 + X @ X @ X / 24
+    z = z0.copy()
+    for _ in range(n):
+        z = R @ z + h * S @ b
+    return z
+
+
+DRAG = np.array([-0.004, -0.006, -0.009])
+
+
+def test_drag_first_principles_exact_affine_map():
+    """Constant attitude, no rotor thrust: [p, v]' = [v, R C_a R^T v / m - g e_z]
+    is affine; the RK4 map is R4(hA) z + h S4(hA) b exactly. A transposed
+    rotation (R^T C_a R) fails it for a generic attitude."""
+    dt, n = 2e-3, 300
+
+    def edit(P):
+        P["drag"][:] = DRAG
+    b, P = fp_batch(1, dt=dt, edit=edit)
+    q0 = unit_quats(np.random.default_rng(22), 1)[:, 0]
+    x = torch.zeros(17, 1, dtype=F64)
+    x[3:7, 0] = torch.as_tensor(q0)
+    x[0:3, 0] = torch.tensor([0.3, -0.2, 1.0], dtype=F64)
+    x[7:10, 0] = torch.tensor([2.0, -1.5, 0.7], dtype=F64)
+    y = run(b, x, torch.zeros(4, 1, dtype=F64), n)
+    Rm = Rotation.from_quat(q0).as_matrix()
+    M = Rm @ np.diag(DRAG) @ Rm.T / W.MASS
+    A = np.zeros((6, 6))
+    A[0:3, 3:6] = np.eye(3)
+    A[3:6, 3:6] = M
+    bb = np.array([0, 0, 0, 0, 0, -W.GRAVITY])
+    z = _affine_rk4(A, bb, np.concatenate([x[0:3, 0].numpy(), x[7:10, 0].numpy()]), dt, n)
+    assert np.allclose(y[0:3, 0].numpy(), z[0:3], atol=1e-12)
+    assert np.allclose(y[7:10, 0].numpy(), z[3:6], atol=1e-12)
+    Mt = Rm.T @ np.diag(DRAG) @ Rm / W.MASS
+    A[3:6, 3:6] = Mt
+    zt = _affine_rk4(A, bb, np.concatenate([x[0:3, 0].numpy(), x[7:10, 0].numpy()]), dt, n)
+    assert np.abs(zt[3:6] - z[3:6]).max() > 1e-3
+
+
+def test_drag_identified_exact_affine_map():
+    dt, n = 2e-3, 300
+
+    def edit(P):
+        P["drag"][:] = DRAG
+    b, P = id_batch(1, dt=dt, edit=edit)
+    psi = np.array([0.2, -0.3, 0.9])
+    x = torch.zeros(13, 1, dtype=F64)
+    x[3:6, 0] = torch.as_tensor(psi)
+    x[6:9, 0] = torch.tensor([1.0, 2.0, -0.5], dtype=F64)
+    u = torch.tensor([[psi[0]], [psi[1]], [psi[2]], [0.0]], dtype=F64)   # DC gain 1 holds the attitude
+    y = run(b, x, u, n)
+    assert np.allclose(y[3:6, 0].numpy(), psi, atol=1e-14)
+    Rm = Rotation.from_euler("ZYX", psi[::-1]).as_matrix()
+    A = np.zeros((6, 6))
+    A[0:3, 3:6] = np.eye(3)
+    A[3:6, 3:6] = Rm @ np.diag(DRAG) @ Rm.T / W.MASS
+    bb = np.array([0, 0, 0, 0, 0, -W.GRAVITY])
+    z = _affine_rk4(A, bb, np.concatenate([x[0:3, 0].numpy(), x[6:9, 0].numpy()]), dt, n)
+    assert np.allclose(y[0:3, 0].numpy(), z[0:3], atol=1e-12)
+    assert np.allclose(y[6:9, 0].numpy(), z[3:6], atol=1e-12)
+
+
+def test_gradient_fd_with_gyro_and_drag():
+    for w in (W.config5_adjoint(seed=23, n_worlds=6, n_subset=4, steps=30, n_max=3),
+              W.config4(seed=24, n_worlds=3, steps=40, gain_std=0.05)):
+        fp = w.model_per_world == W.MODEL_FP
+        w.params["Jp"][fp, 0] = 4e-9
+        w.params["drag"][:] = DRAG
+        _fd_check(w)
+
+
+# ---- torque interface ------------------------------------------------------------------------
+
+def test_torque_interface_hover_and_torque_response():
+    """Collective thrust m g with zero torques hovers (allocation inverts the
+    mixing); a small pure roll torque gives the initial body angular acceleration
+    tau_x / J_x once the rotors reach their new commands."""
+    b, P = fp_batch(1, control=O.CTRL_TORQUE)
+    wh = math.sqrt(W.MASS * W.GRAVITY / (4 * W.K_THRUST))
+    x = torch.zeros(17, 1, dtype=F64)
+    x[6] = 1.0
+    x[13:17] = wh
+    u = torch.tensor([[W.MASS * W.GRAVITY], [0.0], [0.0], [0.0]], dtype=F64)
+    y = run(b, x, u, 500)
+    assert torch.allclose(y, x, atol=1e-9 * wh)
+    # rotors held at the commanded speeds: torque about x from the mixing equals tau_x
+    tau = 1e-5
+    u2 = torch.tensor([[W.MASS * W.GRAVITY], [tau], [0.0], [0.0]], dtype=F64)
+    rc = O.allocate(u2, b.P_fp)
+    thrust, torque = O.rotor_wrench(rc, b.P_fp)
+    assert abs(float(torque[0, 0]) - tau) < 1e-12 and abs(float(thrust[0]) - W.MASS * W.GRAVITY) < 1e-12
+    assert abs(float(torque[1, 0])) < 1e-15 and abs(float(torque[2, 0])) < 1e-15
+
+
+def test_gradient_fd_torque_interface():
+    w = W.fp_torque(seed=25, n_worlds=3, steps=30)
+    w.ref_offset = w.x0[0:3].copy()
+    w.dloss = np.ones(3, np.float32)
+    w.w_u = 1.0
+    w.cmds = np.repeat(w.cmds[None], w.steps, axis=0)
+    _fd_check(w, h=1e-6)

@@ -27,6 +27,7 @@ MODEL_FP = 0          # first-principles rigid body + rotor dynamics
 MODEL_ID = 1          # identified (abstracted) attitude-command model
 CTRL_ROTOR = 0        # first-principles worlds take rotor-speed commands
 CTRL_ATT_PID = 1      # first-principles worlds take [roll, pitch, yaw-rate, thrust]
+CTRL_TORQUE = 2       # first-principles worlds take [thrust, tau_x, tau_y, tau_z]
 INTEG_EULER = 0
 INTEG_RK4 = 1
 
@@ -214,6 +215,28 @@ def config1(seed: int = 1001, n_worlds: int = 16, steps: int = 500,
                     float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps, _f32(cmds))
 
 
+def fp_torque(seed: int = 1006, n_worlds: int = 256, steps: int = 250, dt: float = 0.004) -> Workload:
+    """Torque interface of the first-principles model (collective thrust and body
+    torques at 250 Hz): per-world mass and inertia x U[0.9, 1.1], held commands
+    thrust ~ m g U[0.9, 1.1], torques ~ N(0, (2e-5 N m)^2)."""
+    rng = _rng(seed)
+    M = D = n_worlds
+    P = empty_params(M)
+    mass = MASS * rng.uniform(0.9, 1.1, size=M)
+    inertia = np.asarray(INERTIA)[None, :] * rng.uniform(0.9, 1.1, size=(M, 3))
+    fill_fp_airframe(P, np.arange(M), mass, inertia)
+    x0 = np.zeros((S_FP_ROTOR, D))
+    x0[0:3] = rng.uniform(-1.0, 1.0, size=(3, D))
+    x0[3:7] = _random_attitude(rng, D, 0.2)
+    x0[13:17] = hover_speed(mass)
+    cmds = np.empty((4, D))
+    cmds[0] = mass * GRAVITY * rng.uniform(0.9, 1.1, size=D)
+    cmds[1:4] = rng.normal(0.0, 2e-5, size=(3, D))
+    return Workload("fp_torque_interface", M, np.ones(M, np.int32), np.full(M, MODEL_FP, np.uint8),
+                    CTRL_TORQUE, INTEG_RK4, float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps,
+                    _f32(cmds))
+
+
 def _fp_pid_x0(D, mass_per_drone, pos=None):
     x0 = np.zeros((S_FP_PID, D))
     if pos is not None:
@@ -306,6 +329,75 @@ def config4(seed: int = 1004, n_worlds: int = 1024, steps: int = 500,
                     float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps, _f32(ubar),
                     gain=_f32(gain), gain_index=None, ref_amp=1.0, ref_period=4.0,
                     ref_offset=None, w_u=1e-3, dloss=np.ones(D, np.float32))
+
+
+def gradient_goal(seed: int = 1007, n_worlds: int = 1 << 20, steps: int = 10,
+                  dt: float = 0.002) -> Workload:
+    """Gradient throughput workload: many single-drone worlds of the closed-loop
+    first-principles model (config-2 distributions), a short horizon of per-step
+    attitude commands, loss = distance to a per-drone goal at every step (a
+    figure-eight of amplitude 0 centred on the goal) + 1e-3 |u|^2."""
+    rng = _rng(seed)
+    M = D = n_worlds
+    P = empty_params(M)
+    mass = MASS * rng.uniform(0.9, 1.1, size=M)
+    inertia = np.asarray(INERTIA)[None, :] * rng.uniform(0.9, 1.1, size=(M, 3))
+    fill_fp_airframe(P, np.arange(M), mass, inertia)
+    x0 = _fp_pid_x0(D, mass, rng.normal(0.0, 0.05, size=(3, D)))
+    cmds = np.empty((steps, 4, D))
+    cmds[:, 0:3] = rng.uniform(-0.2, 0.2, size=(steps, 3, D))
+    cmds[:, 3] = (mass * GRAVITY)[None, :] * rng.uniform(0.8, 1.2, size=(steps, D))
+    goal = rng.uniform(-1.0, 1.0, size=(3, D))
+    return Workload("fp_pid_goal_gradient", M, np.ones(M, np.int32),
+                    np.full(M, MODEL_FP, np.uint8), CTRL_ATT_PID, INTEG_RK4,
+                    float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps, _f32(cmds),
+                    gain=None, gain_index=None, ref_amp=0.0, ref_period=4.0,
+                    ref_offset=_f32(goal), w_u=1e-3, dloss=np.ones(D, np.float32))
+
+
+def mppi_task(seed: int = 1008, n_controllers: int = 5, n_samples: int = 100_000, horizon: int = 25,
+              dt: float = 0.02, model: int = MODEL_FP, n_obstacles: int = 8, substeps: int = 1):
+    """Sampled-rollout control task: one drone hovering at (-2, 0, 1) must reach
+    (2, 0, 1) through seeded spherical obstacles; ``n_controllers`` controllers of
+    ``n_samples`` samples each over ``horizon`` steps of ``dt`` (50 Hz by
+    default). Returns (single-drone workload, controller parameters, initial
+    mean [C][H][4] = hover command)."""
+    rng = _rng(seed)
+    P = empty_params(1)
+    if model == MODEL_FP:
+        fill_fp_airframe(P, np.arange(1), np.array([MASS]), np.asarray(INERTIA)[None, :])
+        x0 = _fp_pid_x0(1, np.array([MASS]), np.array([[-2.0], [0.0], [1.0]]))
+        hover = np.array([0.0, 0.0, 0.0, MASS * GRAVITY])
+        sigma = [0.15, 0.15, 0.3, 0.05]
+        u_lo, u_hi = [-0.6, -0.6, -2.0, 0.0], [0.6, 0.6, 2.0, 0.5]
+        r_u = [0.1, 0.1, 0.01, 1.0]
+        control = CTRL_ATT_PID
+    else:
+        fill_id_model(P, np.arange(1), np.asarray(ID_GAIN)[None, :], np.asarray(ID_TAU)[None, :])
+        x0 = _id_x0(1, np.array([[-2.0], [0.0], [1.0]]))
+        hover = np.array([0.0, 0.0, 0.0, MASS * GRAVITY / ID_CF])
+        sigma = [0.15, 0.15, 0.3, 0.05]
+        u_lo, u_hi = [-0.6, -0.6, -3.2, 0.0], [0.6, 0.6, 3.2, 0.5]
+        r_u = [0.1, 0.1, 0.01, 1.0]
+        control = CTRL_ATT_PID
+    obs = np.zeros((n_obstacles, 4))
+    obs[:, 0] = rng.uniform(-1.0, 1.0, n_obstacles)
+    obs[:, 1] = rng.uniform(-0.5, 0.5, n_obstacles)
+    obs[:, 2] = rng.uniform(0.6, 1.4, n_obstacles)
+    obs[:, 3] = rng.uniform(0.15, 0.35, n_obstacles)
+    w = Workload("mppi_obstacles", 1, np.ones(1, np.int32), np.full(1, model, np.uint8), control, INTEG_RK4,
+                 float(np.float32(dt)), 1, _finish_params(P), _f32(x0), horizon, _f32(np.tile(hover, (1, 1)).T))
+    f = lambda a: [float(np.float32(v)) for v in a]
+    params = {
+        "n_controllers": n_controllers, "n_samples": n_samples, "horizon": horizon, "substeps": substeps,
+        "n_elite": max(1, int(math.ceil(0.01 * n_samples))),
+        "sigma": f(sigma), "beta": float(np.float32(0.8)), "lambda": 1.0,
+        "u_lo": f(u_lo), "u_hi": f(u_hi), "u_ref": f(hover), "r_u": f(r_u),
+        "goal": [2.0, 0.0, 1.0], "q_p": 1.0, "q_v": 0.1, "w_obs": 100.0,
+        "obstacles": _f32(obs), "seed": int(rng.integers(0, 2 ** 63)),
+    }
+    mean0 = _f32(np.tile(hover, (n_controllers, horizon, 1)))
+    return w, params, mean0
 
 
 def uneven_counts(rng, n_worlds, n_max=4000):
