@@ -117,7 +117,10 @@ typedef int32_t cf_status;
 #define CF_P_F_MAX      47   /* PID    per-rotor thrust limit [N]                  */
 #define CF_P_ALLOC      48   /* PID    4x4 row-major: f = alloc [T, tau_x, tau_y, tau_z] */
 #define CF_P_CF         64   /* ID     thrust scaling c_f                          */
-#define CF_P_CTAU       65   /* ID     thrust time coefficient c_tau [1/s]         */
+#define CF_P_CTAU       65   /* ID     thrust time coefficient c_tau [1/s], >= 0;
+                                0 selects the variant without thrust dynamics: the
+                                commanded thrust acts directly and state row 12 holds
+                                the applied thrust (12 dynamic states)            */
 #define CF_P_CPSI1      66   /* ID     attitude coefficient c1 per axis [3]        */
 #define CF_P_CPSI2      69   /* ID     c2 per axis [3]                             */
 #define CF_P_CPSI3      72   /* ID     c3 per axis [3]                             */
@@ -167,7 +170,7 @@ typedef struct cf_objective {
  * CF_F_NO_AUTOTUNE_CACHE) and return a handle in *out (NULL on failure).
  * Errors: CF_EINVAL (NULL pointers, M < 1, negative drone counts, D > 2^31-1,
  * unknown enum, dt not finite or <= 0, a non-finite parameter, mass/inertia/
- * k2/c_f not > 0, J_p < 0, gain index out of range), CF_ENODEV (no device),
+ * k2/c_f not > 0, J_p < 0, c_tau < 0, gain index out of range), CF_ENODEV (no device),
  * CF_ENOMEM, CF_EDEVICE.
  */
 cf_status cf_create(const cf_desc* desc, cf_handle** out);

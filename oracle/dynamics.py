@@ -242,9 +242,17 @@ def id_rates(x: torch.Tensor, u: torch.Tensor, P) -> torch.Tensor:
     m v' = -m g e_z + R(Psi) e_z c_f f; f' = c_tau (f_cmd - f);
     Psi'' = c1 Psi + c2 Psi' + c3 Psi_cmd (per axis; reading of the garbled
     coefficient labels as three distinct 3-vectors); the drag term R f_a with
-    f_a = C_a R^T v as in the first-principles model."""
+    f_a = C_a R^T v as in the first-principles model.
+
+    The simplified variant without thrust dynamics (same section, last
+    sentence; drag is removed by C_a = 0) is selected per drone by c_tau = 0:
+    the commanded thrust acts directly (f = f_cmd in the acceleration) and the
+    thrust row has zero rate; ``step_id`` then stores the applied thrust in
+    that row, so the dynamic state is the 12 components [p, Psi, v, dPsi]."""
     psi, v, dpsi, fs = x[3:6], x[6:9], x[9:12], x[12]
     m, g = P["mass"][0], P["gravity"][0]
+    direct = P["c_tau"][0] == 0
+    fs = torch.where(direct, u[3], fs)
     acc = (P["c_f"][0] * fs / m) * euler_zyx_body_z(psi)
     acc = acc - torch.stack([torch.zeros_like(g), torch.zeros_like(g), g])
     acc = acc + drag_acceleration(euler_zyx_matrix(psi), v, P)
@@ -284,7 +292,11 @@ def step_fp(x, u, P, control: int, integrator: int, dt: float, renorm: bool = Tr
 
 
 def step_id(x, u, P, integrator: int, dt: float):
-    return integrate(lambda s: id_rates(s, u, P), x[0:13], dt, integrator)
+    y = integrate(lambda s: id_rates(s, u, P), x[0:13], dt, integrator)
+    direct = P["c_tau"][0] == 0
+    if bool(direct.any()):
+        y = torch.cat([y[0:12], torch.where(direct, u[3], y[12])[None]], 0)
+    return y
 
 
 class Batch:

@@ -410,7 +410,7 @@ cf_status validate_desc(const cf_desc* d, std::vector<int32_t>& counts, std::vec
             if (d->control != CF_CTRL_ROTOR && !(r[CF_P_THRUST + 2] > 0.f)) return CF_EINVAL;
             if (r[CF_P_JP] < 0.f) return CF_EINVAL;
         } else {
-            if (!(r[CF_P_CF] > 0.f)) return CF_EINVAL;
+            if (!(r[CF_P_CF] > 0.f) || r[CF_P_CTAU] < 0.f) return CF_EINVAL;
         }
     }
     *D_out = D;

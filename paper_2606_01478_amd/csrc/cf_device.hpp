@@ -58,6 +58,7 @@ struct IdParams {
     float c1[3], c2[3], c3[3];
     float cd[3];
     bool drag;
+    bool direct;  // c_tau = 0: no thrust dynamics, the commanded thrust acts directly
 };
 
 // AERO = false: the gyroscopic/reaction torques and drag are compiled out (the
@@ -122,6 +123,7 @@ __device__ __forceinline__ IdParams load_id(const R& rec) {
     P.cf_m = cf / m;
     P.g = rec(P_GRAVITY);
     P.ctau = rec(P_CTAU);
+    P.direct = P.ctau == 0.f;
     P.f_hover = m * P.g / cf;
     P.inv_m = 1.0f / m;
 #pragma unroll
@@ -376,7 +378,7 @@ __device__ __forceinline__ void id_rates(const float* x, const float* u, const I
     float sn[3], cs[3];
     sincos3(x + 3, sn, cs);
     const float sph = sn[0], cph = cs[0], sth = sn[1], cth = cs[1], sps = sn[2], cps = cs[2];
-    const float a = P.cf_m * x[12];
+    const float a = P.cf_m * (P.direct ? u[3] : x[12]);
     xd[0] = x[6]; xd[1] = x[7]; xd[2] = x[8];
     xd[3] = x[9]; xd[4] = x[10]; xd[5] = x[11];
     xd[6] = a * (cps * sth * cph + sps * sph);
@@ -397,15 +399,17 @@ __device__ __forceinline__ void id_rates_vjp(const float* x, const float* u, con
     float sn[3], cs[3];
     sincos3(x + 3, sn, cs);
     const float sph = sn[0], cph = cs[0], sth = sn[1], cth = cs[1], sps = sn[2], cps = cs[2];
-    const float a = P.cf_m * x[12];
+    const float a = P.cf_m * (P.direct ? u[3] : x[12]);
     const float rz0 = cps * sth * cph + sps * sph;
     const float rz1 = sps * sth * cph - cps * sph;
     const float rz2 = cth * cph;
     // p' = v, Psi' = dPsi
     xb[6] += gb[0]; xb[7] += gb[1]; xb[8] += gb[2];
     xb[9] += gb[3]; xb[10] += gb[4]; xb[11] += gb[5];
-    // v' = a R e_z - g e_z
-    xb[12] += (gb[6] * rz0 + gb[7] * rz1 + gb[8] * rz2) * P.cf_m;
+    // v' = a R e_z - g e_z, a = c_f f / m with f the thrust state or (direct) the command
+    const float fb = (gb[6] * rz0 + gb[7] * rz1 + gb[8] * rz2) * P.cf_m;
+    if (P.direct) ub[3] += fb;
+    else xb[12] += fb;
     const float b0 = a * gb[6], b1 = a * gb[7], b2 = a * gb[8];
     xb[3] += b0 * (sps * cph - cps * sth * sph) + b1 * (-sps * sth * sph - cps * cph) + b2 * (-cth * sph);
     xb[4] += b0 * (cps * cth * cph) + b1 * (sps * cth * cph) + b2 * (-sth * cph);
@@ -727,6 +731,7 @@ __device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, c
 template <int INTEG>
 __device__ __forceinline__ void id_step(float* x, float* comp, const float* u, const IdParams& P, float dt) {
     integrate<S_ID, INTEG, COMP_ID>(x, comp, dt, [&](const float* xi, float* xd) { id_rates(xi, u, P, xd); });
+    if (P.direct) x[12] = u[3];  // the thrust row holds the applied thrust
 }
 
 // VJP of fp_step at (x, u): yb = adjoint of the new state (S components),
@@ -782,8 +787,15 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
 template <int INTEG>
 __device__ __forceinline__ void id_step_vjp(const float* x, const float* u, const IdParams& P, float dt,
                                             const float* yb, float* xb, float* ub) {
+    float ym[S_ID];
+#pragma unroll
+    for (int i = 0; i < S_ID; ++i) ym[i] = yb[i];
+    if (P.direct) {  // y[12] = u[3]; the input thrust row is not used
+        ub[3] += ym[12];
+        ym[12] = 0.f;
+    }
     integrate_vjp<S_ID, INTEG, false, false>(
-        x, dt, yb, xb,
+        x, dt, ym, xb,
         [&](const float* xi, float* xd) { id_rates(xi, u, P, xd); },
         [&](const float* xi, const float* gb, float* xa) { id_rates_vjp(xi, u, P, gb, xa, ub); },
         [](const float*, float*) {});

@@ -377,3 +377,26 @@ def test_goal_distance_gradients(gpu_lib):
     per-step commands and the initial state vs the oracle's autograd."""
     w = W.gradient_goal(seed=42, n_worlds=300)
     _check_against_oracle(w, _rollout_grads(w, 10))
+
+
+def _direct_half(w):
+    idw = np.nonzero(w.model_per_world == W.MODEL_ID)[0]
+    w.params["c_tau"][idw[::2]] = 0.0
+    return w
+
+
+@pytest.mark.parametrize("wq", [False, True])
+def test_direct_thrust_variant_held(gpu_lib, wq):
+    """Identified worlds without thrust dynamics (every other world), swarm and
+    mixed batches."""
+    for w in (_direct_half(W.small(3, seed=50)), _direct_half(W.small(5, seed=51))):
+        sim = _sim(w, flags=B.F_WORKQUEUE if wq else 0)
+        x = dev(w.x0)
+        sim.step_k(x, dev(w.cmds), w.steps)
+        torch.cuda.synchronize()
+        assert_states_close(x, O.simulate_held(w), w, what=f"{w.name} direct thrust")
+
+
+def test_direct_thrust_variant_gradients(gpu_lib):
+    w = _direct_half(W.small(4, seed=52))
+    _check_against_oracle(w, _rollout_grads(w, 25))

@@ -751,3 +751,58 @@ def test_gradient_fd_torque_interface():
     w.w_u = 1.0
     w.cmds = np.repeat(w.cmds[None], w.steps, axis=0)
     _fd_check(w, h=1e-6)
+
+
+# ---- identified model without thrust dynamics (c_tau = 0) -----------------------------
+
+def _direct(P):
+    P["c_tau"][:] = 0.0
+
+
+@pytest.mark.parametrize("integ", [O.RK4, O.EULER])
+def test_direct_thrust_level_flight_closed_form(integ):
+    """Level attitude, held thrust command f: the vertical acceleration is the
+    constant c_f f / m - g, so z is the exact quadratic (RK4; Euler with its
+    dt lag) and the thrust row holds f after every step, whatever it held before."""
+    dt, n = 0.002, 400
+    b, P = id_batch(2, integrator=integ, dt=dt, edit=_direct)
+    x = torch.zeros(13, 2, dtype=F64)
+    x[8] = torch.tensor([0.5, -1.0], dtype=F64)
+    x[12] = torch.tensor([0.0, 1.0], dtype=F64)        # ignored by the direct variant
+    f = torch.tensor([0.2, 0.4], dtype=F64)
+    u = torch.stack([torch.zeros(2, dtype=F64)] * 3 + [f])
+    y = run(b, x, u, n)
+    t = n * dt
+    a = W.ID_CF * f / W.MASS - W.GRAVITY
+    z = x[8] * t + 0.5 * a * t * t
+    if integ == O.EULER:
+        z = z - 0.5 * a * t * dt
+    assert torch.allclose(y[2], z, rtol=0, atol=1e-11)
+    assert torch.equal(y[12], f)
+    assert torch.allclose(y[8], x[8] + a * t, rtol=0, atol=1e-11)
+
+
+def test_fast_thrust_lag_converges_to_direct_variant():
+    """The 13-state model with a thrust time constant 1/c_tau -> 0 approaches the
+    direct variant at first order in 1/c_tau."""
+    dt, n = 1e-4, 2000
+    rng = np.random.default_rng(3)
+    x = torch.zeros(13, 3, dtype=F64)
+    x[3:6] = torch.as_tensor(rng.uniform(-0.2, 0.2, (3, 3)))
+    x[12] = W.MASS * W.GRAVITY
+    u = torch.as_tensor(np.vstack([rng.uniform(-0.2, 0.2, (3, 3)), rng.uniform(0.2, 0.4, (1, 3))]))
+    bd, _ = id_batch(3, dt=dt, edit=_direct)
+    yd = run(bd, x, u, n)
+    errs = []
+    for ctau in (1e2, 1e3):
+        b, _ = id_batch(3, dt=dt, edit=lambda P, c=ctau: P["c_tau"].__setitem__(slice(None), c))
+        y = run(b, x, u, n)
+        errs.append(float((y[0:12] - yd[0:12]).abs().max()))
+    assert 8 < errs[0] / errs[1] < 12, errs
+
+
+def test_gradient_fd_direct_thrust():
+    w = W.config4(seed=26, n_worlds=3, steps=40)
+    w.params["c_tau"][[0, 2]] = 0.0
+    w.gain = w.gain * 5
+    _fd_check(w)
