@@ -68,6 +68,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-comparators", action="store_true")
     p.add_argument("--copy-probe", action="store_true", help="also run a 256 MiB device copy (profile scale)")
+    p.add_argument("--hbm-sweep", action="store_true",
+                   help="also time the plain and fused kernels on 2^20..2^24 single drones (HBM roofline)")
     p.add_argument("--no-mppi", action="store_true",
                    help="skip the sampled-rollout controller measurement (5 x 100k samples x 25 steps)")
     p.add_argument("--no-grad-bench", action="store_true",
@@ -278,6 +280,8 @@ def main():
         out["gradient_benchmark"] = gradient_benchmark(B, W, dev, t2d, ev)
     if not args.no_mppi:
         out["mppi"] = mppi_benchmark(B, W, dev, t2d, ev)
+    if args.hbm_sweep:
+        out["hbm_sweep"] = hbm_sweep(B, W, dev, t2d, ev)
 
     if args.copy_probe:
         src = torch.empty(64 * 1024 * 1024, device=dev)
@@ -324,6 +328,43 @@ def gradient_benchmark(B, W, dev, t2d, ev, reps=10):
             "ms_fwd_bwd": ms, "gradients_per_s": wg.n_worlds / (ms * 1e-3),
             "drone_steps_per_s": wg.n_worlds * T / (ms * 1e-3), "reps": reps,
             "paper_context": "9e6 gradients/s at 1e6 environments x 10 steps (other hardware)"}
+
+
+def hbm_sweep(B, W, dev, t2d, ev):
+    """Plain single-step kernel (one launch per step: state in + out + held command
+    per drone-step through HBM) and the fused kernel (K steps per launch) on
+    2^20, 2^22 and 2^24 drones of the rotor-interface and identified models."""
+    import torch
+    rows = []
+    for model, name in ((W.MODEL_FP, "fp_rotor_rk4"), (W.MODEL_ID, "id_rk4")):
+        for lg in (20, 22, 24):
+            w = W.hbm_sweep(model, 1 << lg)
+            D = w.n_drones_total
+            S = w.x0.shape[0]
+            x, u = t2d(w.x0), t2d(w.cmds)
+            row = {"model": name, "drones": D, "bytes_per_drone_step_plain": 2 * S * 4 + 16}
+            for label, flags, k, reps in (("plain", B.F_PLAIN_KERNEL, 20, 1), ("fused_k10", 0, 10, 3),
+                                          ("fused_k100", 0, 100, 1)):
+                sim = B.Sim.from_workload(w, flags=flags | B.F_NO_AUTOTUNE_CACHE)
+                sim.step_k(x, u, 2)
+                torch.cuda.synchronize()
+                a, b = ev(), ev()
+                a.record()
+                for _ in range(reps):
+                    sim.step_k(x, u, k)
+                b.record()
+                torch.cuda.synchronize()
+                if sim.last_error() != 0:
+                    raise RuntimeError("device error in the bandwidth sweep")
+                ms = a.elapsed_time(b) / (reps * k)
+                row[f"{label}_ms_per_step"] = ms
+                row[f"{label}_drone_steps_per_s"] = D / (ms * 1e-3)
+                if label == "plain":
+                    row["plain_gbs"] = (2 * S * 4 + 16) * D / (ms * 1e-3) / 1e9
+                sim.close()
+            rows.append(row)
+            del x, u
+    return rows
 
 
 def mppi_benchmark(B, W, dev, t2d, ev, reps=20):

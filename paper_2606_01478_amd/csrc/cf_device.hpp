@@ -599,40 +599,9 @@ constexpr uint32_t COMP_NONE = 0u;
 // follows the step); it receives y only when NEED_Y. Writes
 // xb = (dPhi/dx)^T yb; vjp(xin, gb, xa) adds (d rates/d xin)^T gb into xa and
 // accumulates the command adjoint itself.
-// Stage states of RK4 kept in registers, or (IN_LDS) in this lane's LDS slots
-// (stride `sstride`, three stages of N values).
-template <int N, bool IN_LDS>
-struct StageStore;
-template <int N>
-struct StageStore<N, false> {
-    float reg[3][N];
-    __device__ __forceinline__ void put(int st, const float* v) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) reg[st][i] = v[i];
-    }
-    __device__ __forceinline__ void get(int st, float* v) const {
-#pragma unroll
-        for (int i = 0; i < N; ++i) v[i] = reg[st][i];
-    }
-};
-template <int N>
-struct StageStore<N, true> {
-    volatile float* stage;
-    int sstride;
-    __device__ __forceinline__ void put(int st, const float* v) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) stage[(st * N + i) * sstride] = v[i];
-    }
-    __device__ __forceinline__ void get(int st, float* v) const {
-#pragma unroll
-        for (int i = 0; i < N; ++i) v[i] = stage[(st * N + i) * sstride];
-    }
-};
-
-template <int N, int INTEG, bool NEED_Y, bool LDS_STAGES, class Rates, class Vjp, class Post>
+template <int N, int INTEG, bool NEED_Y, class Rates, class Vjp, class Post>
 __device__ __forceinline__ void integrate_vjp(const float* x, float h, const float* yb_in, float* xb,
-                                              const Rates& rates, const Vjp& vjp, const Post& post,
-                                              float* stage_lds = nullptr, int sstride = 0) {
+                                              const Rates& rates, const Vjp& vjp, const Post& post) {
     float yb[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) yb[i] = yb_in[i];
@@ -650,20 +619,13 @@ __device__ __forceinline__ void integrate_vjp(const float* x, float h, const flo
         vjp(x, gb, xb);
     } else {
         const float h2 = 0.5f * h;
-        StageStore<N, LDS_STAGES> ss;
-        if constexpr (LDS_STAGES) {
-            ss.stage = stage_lds;
-            ss.sstride = sstride;
-        }
-        float xs[N], k[N], acc[N];
+        float xs[N], k[N], acc[N], x2[N], x3[N];   // stage states 2 and 3 kept for the reverse sweep
         rates(x, k);
 #pragma unroll
-        for (int i = 0; i < N; ++i) { xs[i] = x[i] + h2 * k[i]; acc[i] = k[i]; }
-        ss.put(0, xs);
+        for (int i = 0; i < N; ++i) { xs[i] = x[i] + h2 * k[i]; acc[i] = k[i]; x2[i] = xs[i]; }
         rates(xs, k);
 #pragma unroll
-        for (int i = 0; i < N; ++i) { xs[i] = x[i] + h2 * k[i]; acc[i] += 2.f * k[i]; }
-        ss.put(1, xs);
+        for (int i = 0; i < N; ++i) { xs[i] = x[i] + h2 * k[i]; acc[i] += 2.f * k[i]; x3[i] = xs[i]; }
         rates(xs, k);
 #pragma unroll
         for (int i = 0; i < N; ++i) { xs[i] = x[i] + h * k[i]; acc[i] += 2.f * k[i]; }
@@ -683,12 +645,10 @@ __device__ __forceinline__ void integrate_vjp(const float* x, float h, const flo
         vjp(xs, gb, a);                       // stage 4 at x + h k3
 #pragma unroll
         for (int i = 0; i < N; ++i) { xb[i] += a[i]; gb[i] = h3 * yb[i] + h * a[i]; a[i] = 0.f; }
-        ss.get(1, xs);
-        vjp(xs, gb, a);                       // stage 3
+        vjp(x3, gb, a);                       // stage 3
 #pragma unroll
         for (int i = 0; i < N; ++i) { xb[i] += a[i]; gb[i] = h3 * yb[i] + h2 * a[i]; a[i] = 0.f; }
-        ss.get(0, xs);
-        vjp(xs, gb, a);                       // stage 2
+        vjp(x2, gb, a);                       // stage 2
 #pragma unroll
         for (int i = 0; i < N; ++i) { xb[i] += a[i]; gb[i] = h6 * yb[i] + h2 * a[i]; a[i] = 0.f; }
         vjp(x, gb, a);                        // stage 1
@@ -739,8 +699,7 @@ __device__ __forceinline__ void id_step(float* x, float* comp, const float* u, c
 template <int CTRL, int INTEG>
 __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, const FpParams& P,
                                             const PidParams& C, float dt, float inv_dt, int renorm,
-                                            const float* yb, float* xb, float* ub,
-                                            float* stage_lds = nullptr, int sstride = 0) {
+                                            const float* yb, float* xb, float* ub) {
     float rc[4], cs[8];
     PidTrace tr;
     if constexpr (CTRL == CTRL_PID) {
@@ -765,12 +724,10 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
             ybr[5] = (ybr[5] - q2 * dot) * inv;
             ybr[6] = (ybr[6] - q3 * dot) * inv;
         };
-        if (stage_lds) integrate_vjp<S_FP, INTEG, true, true>(x, dt, yb, xb, rates, vjp, post, stage_lds, sstride);
-        else integrate_vjp<S_FP, INTEG, true, false>(x, dt, yb, xb, rates, vjp, post);
+        integrate_vjp<S_FP, INTEG, true>(x, dt, yb, xb, rates, vjp, post);
     } else {
         const auto none = [](const float*, float*) {};
-        if (stage_lds) integrate_vjp<S_FP, INTEG, false, true>(x, dt, yb, xb, rates, vjp, none, stage_lds, sstride);
-        else integrate_vjp<S_FP, INTEG, false, false>(x, dt, yb, xb, rates, vjp, none);
+        integrate_vjp<S_FP, INTEG, false>(x, dt, yb, xb, rates, vjp, none);
     }
     if constexpr (CTRL == CTRL_PID) {
 #pragma unroll
@@ -794,7 +751,7 @@ __device__ __forceinline__ void id_step_vjp(const float* x, const float* u, cons
         ub[3] += ym[12];
         ym[12] = 0.f;
     }
-    integrate_vjp<S_ID, INTEG, false, false>(
+    integrate_vjp<S_ID, INTEG, false>(
         x, dt, ym, xb,
         [&](const float* xi, float* xd) { id_rates(xi, u, P, xd); },
         [&](const float* xi, const float* gb, float* xa) { id_rates_vjp(xi, u, P, gb, xa, ub); },

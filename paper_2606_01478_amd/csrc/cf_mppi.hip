@@ -35,7 +35,9 @@ __device__ __forceinline__ void philox4x64(uint64_t x[4], uint64_t k0, uint64_t 
 __device__ __forceinline__ float unit_open(uint32_t u) { return ((float)(u >> 9) + 0.5f) * 0x1p-23f; }
 
 // eight standard normals of block b of sample (k, c) at iteration `iter`:
-// each 64-bit word gives one Box-Muller pair from its (low, high) halves
+// each 64-bit word gives one Box-Muller pair from its (low, high) halves;
+// the hardware sine and cosine take their argument in revolutions, so
+// sin(2 pi u2) is one instruction with no range reduction (u2 in (0, 1))
 __device__ __forceinline__ void normals8(uint64_t b, uint64_t k, uint64_t c, const MppiArgs& a, float z[8]) {
     uint64_t x[4] = {b, k, c, a.iter};
     philox4x64(x, a.seed, 0ull);
@@ -43,11 +45,9 @@ __device__ __forceinline__ void normals8(uint64_t b, uint64_t k, uint64_t c, con
     for (int w = 0; w < 4; ++w) {
         const float u1 = unit_open((uint32_t)x[w]);
         const float u2 = unit_open((uint32_t)(x[w] >> 32));
-        const float r = sqrtf(-2.f * logf(u1));
-        float s, co;
-        sincospif(2.f * u2, &s, &co);
-        z[2 * w] = r * co;
-        z[2 * w + 1] = r * s;
+        const float r = sqrt_hw(-2.f * logf(u1));
+        z[2 * w] = r * __builtin_amdgcn_cosf(u2);
+        z[2 * w + 1] = r * __builtin_amdgcn_sinf(u2);
     }
 }
 

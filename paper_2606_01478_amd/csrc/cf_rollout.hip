@@ -111,10 +111,9 @@ __device__ __forceinline__ void model_step(float* x, float* comp, const float* u
 
 template <int MODEL, int CTRL, int INTEG>
 __device__ __forceinline__ void model_step_vjp(const float* x, const float* u, const DroneParams& p,
-                                               const RollArgs& a, const float* yb, float* xb, float* ub,
-                                               float* stage_lds, int sstride) {
+                                               const RollArgs& a, const float* yb, float* xb, float* ub) {
     if constexpr (MODEL == MODEL_FP)
-        fp_step_vjp<CTRL, INTEG>(x, u, p.fp, p.pid, a.dt, a.inv_dt, a.renorm, yb, xb, ub, stage_lds, sstride);
+        fp_step_vjp<CTRL, INTEG>(x, u, p.fp, p.pid, a.dt, a.inv_dt, a.renorm, yb, xb, ub);
     else
         id_step_vjp<INTEG>(x, u, p.id, a.dt, yb, xb, ub);
 }
@@ -186,11 +185,10 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
 // ---------------------------------------------------------------------------
 // adjoint of one drone's rollout
 // gacc: this lane's 52 gain-gradient accumulators in LDS, stride `gstride`
-// (one writer per slot, so the sums keep a fixed order); stage: this lane's
-// LDS slots for the RK4 stage states of the first-principles model
+// (one writer per slot, so the sums keep a fixed order)
 template <int MODEL, int CTRL, int INTEG, bool AERO, class R>
 __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
-                                                  float* gacc, float* stage, int gstride) {
+                                                  float* gacc, int gstride) {
     constexpr int S = ModelTraits<MODEL, CTRL>::S;
     const size_t D = (size_t)a.D;
     const size_t SD = (size_t)S_h * D;
@@ -261,7 +259,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
             feedback<MODEL>(a, G, xc, t, off, f_hover, uc, u, ev);
             float xb[S];
             float ub[4] = {0.f, 0.f, 0.f, 0.f};
-            model_step_vjp<MODEL, CTRL, INTEG>(xc, u, p, a, lam, xb, ub, stage, gstride);
+            model_step_vjp<MODEL, CTRL, INTEG>(xc, u, p, a, lam, xb, ub);
             if (a.has_obj) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) ub[i] += two_seed * a.w_u * u[i];
@@ -313,11 +311,10 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 template <bool BWD, int MODEL, int CTRL, int INTEG, bool AERO, class R>
 __device__ __forceinline__ void rollout_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
     if constexpr (BWD) {
-        // dynamic LDS: [52][blockDim] gain accumulators, then [3*17][blockDim] RK4 stage states
+        // dynamic LDS: [52][blockDim] gain accumulators
         extern __shared__ float bwd_lds[];
         float* gacc = bwd_lds + threadIdx.x;
-        float* stage = (MODEL == MODEL_FP && INTEG == RK4) ? bwd_lds + NG * blockDim.x + threadIdx.x : nullptr;
-        rollout_bwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h, gacc, stage, (int)blockDim.x);
+        rollout_bwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h, gacc, (int)blockDim.x);
     } else {
         rollout_fwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
     }
@@ -357,10 +354,8 @@ template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
 static hipError_t launch_roll_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                 hipStream_t s) {
     const int S_h = a.S_h;
-    // adjoint LDS per lane: gain-gradient accumulators and first-principles RK4 stage states
-    const size_t shmem = BWD ? (size_t)(NG + ((MODELS & MS_FP) && INTEG == RK4 ? 3 * S_FP : 0)) * ks.tile *
-                                   sizeof(float)
-                             : 0;
+    // adjoint LDS per lane: the gain-gradient accumulators
+    const size_t shmem = BWD ? (size_t)NG * ks.tile * sizeof(float) : 0;
     if (ks.mode == LM_LANE) {
         if constexpr (MODELS != MS_BOTH) {
             const int bs = ks.tile;

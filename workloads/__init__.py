@@ -400,6 +400,42 @@ def mppi_task(seed: int = 1008, n_controllers: int = 5, n_samples: int = 100_000
     return w, params, mean0
 
 
+def hbm_sweep(model: int, n_drones: int, seed: int = 1009, dt: float = 0.002) -> Workload:
+    """Bandwidth sweep: one world of ``n_drones`` drones with held commands, first
+    principles at the rotor interface (config-1 distributions, attitude within
+    0.3 rad drawn per drone as a small rotation vector) or the identified model
+    (config-3 distributions); drawn directly in float32 so that 2^24 drones stay
+    cheap to generate."""
+    rng = _rng(seed)
+    D = int(n_drones)
+    P = empty_params(1)
+    f32 = np.float32
+    if model == MODEL_FP:
+        fill_fp_airframe(P, np.arange(1), np.array([MASS]), np.asarray(INERTIA)[None, :])
+        wh = f32(hover_speed(MASS))
+        x0 = np.zeros((S_FP_ROTOR, D), f32)
+        x0[0:3] = rng.uniform(-1.0, 1.0, size=(3, D)).astype(f32)
+        x0[7:10] = rng.normal(0.0, 0.1, size=(3, D)).astype(f32)
+        half = rng.uniform(-0.075, 0.075, size=(3, D)).astype(f32)     # half-angle components
+        x0[3:6] = half
+        x0[6] = np.sqrt(1.0 - (half.astype(np.float64) ** 2).sum(0)).astype(f32)
+        x0[13:17] = wh
+        cmds = (wh * (1.0 + 0.05 * rng.standard_normal(size=(4, D), dtype=f32))).astype(f32)
+        ctrl = CTRL_ROTOR
+    else:
+        fill_id_model(P, np.arange(1), np.asarray(ID_GAIN)[None, :], np.asarray(ID_TAU)[None, :])
+        x0 = np.zeros((S_ID, D), f32)
+        x0[0:3] = rng.uniform(-3.0, 3.0, size=(3, D)).astype(f32)
+        x0[12] = f32(MASS * GRAVITY / ID_CF)
+        cmds = np.empty((4, D), f32)
+        cmds[0:3] = rng.uniform(-0.1, 0.1, size=(3, D)).astype(f32)
+        cmds[3] = (MASS * GRAVITY / ID_CF) * rng.uniform(0.95, 1.05, size=D).astype(f32)
+        ctrl = CTRL_ATT_PID
+    return Workload(f"hbm_sweep_{'fp' if model == MODEL_FP else 'id'}_{D}", 1, np.array([D], np.int32),
+                    np.full(1, model, np.uint8), ctrl, INTEG_RK4, float(np.float32(dt)), 1,
+                    _finish_params(P), x0, 100, cmds)
+
+
 def uneven_counts(rng, n_worlds, n_max=4000):
     n = np.round(np.exp(rng.uniform(0.0, math.log(n_max), size=n_worlds)))
     return np.clip(n, 1, n_max).astype(np.int32)
