@@ -56,6 +56,13 @@ typedef int32_t cf_status;
 #define CF_CTRL_ATT_PID  1   /* FP command = [roll, pitch, yaw rate, thrust]    */
 #define CF_CTRL_TORQUE   2   /* FP command = [thrust, tau_x, tau_y, tau_z] through the
                                 motor allocation (CF_P_ALLOC, CF_P_F_MAX)       */
+#define CF_CTRL_POSITION 3   /* FP command = [x, y, z, yaw] setpoints through a
+                                geometric controller on SO(3) and the allocation:
+                                F = m (-kp (p - p_sp) - kv v + g e_z), thrust
+                                F . R e_z, desired z axis F/|F| with the commanded
+                                yaw, tau = J_ctrl (-kR e_R - kw w) with
+                                e_R = vee(R_d^T R - R^T R_d)/2 (CF_P_POS_KP ..
+                                CF_P_ATT_KW; no controller state)               */
 #define CF_INTEG_EULER   0
 #define CF_INTEG_RK4     1
 
@@ -78,11 +85,11 @@ typedef int32_t cf_status;
  *        19-21 body-rate-error integrals, 22-24 body rate of the previous step.
  *   ID:  0-2 p, 3-5 Euler angles (roll, pitch, yaw; R = Rz Ry Rx), 6-8 v,
  *        9-11 Euler-angle rates, 12 collective thrust state f_sum [N].
- * S = 17 (FP rotor or torque interface), 25 (FP attitude), 13 (ID). A handle holding both models
+ * S = 17 (FP rotor, torque or position interface), 25 (FP attitude), 13 (ID). A handle holding both models
  * uses S = max; identified drones use rows 0..12 and leave the rest untouched.
  * Commands are [4][D]: FP rotor: Omega_cmd; FP attitude: [roll, pitch,
- * yaw rate, thrust]; FP torque: [thrust, tau_x, tau_y, tau_z]; ID: [roll,
- * pitch, yaw, thrust].
+ * yaw rate, thrust]; FP torque: [thrust, tau_x, tau_y, tau_z]; FP position:
+ * [x, y, z, yaw]; ID: [roll, pitch, yaw, thrust].
  */
 #define CF_S_FP_ROTOR 17
 #define CF_S_FP_PID   25
@@ -124,6 +131,10 @@ typedef int32_t cf_status;
 #define CF_P_CPSI1      66   /* ID     attitude coefficient c1 per axis [3]        */
 #define CF_P_CPSI2      69   /* ID     c2 per axis [3]                             */
 #define CF_P_CPSI3      72   /* ID     c3 per axis [3]                             */
+#define CF_P_POS_KP     75   /* POS    position gain per axis [1/s^2] [3]          */
+#define CF_P_POS_KV     78   /* POS    velocity gain per axis [1/s] [3]            */
+#define CF_P_ATT_KR     81   /* POS    attitude-error gain per axis [1/s^2] [3]    */
+#define CF_P_ATT_KW     84   /* POS    body-rate gain per axis [1/s] [3]           */
 
 typedef struct cf_desc {
     int32_t n_worlds;                 /* M >= 1                                       */

@@ -42,7 +42,7 @@ F64 = torch.float64
 
 # enum values of the public interface
 MODEL_FP, MODEL_ID = 0, 1
-CTRL_ROTOR, CTRL_ATT_PID, CTRL_TORQUE = 0, 1, 2
+CTRL_ROTOR, CTRL_ATT_PID, CTRL_TORQUE, CTRL_POSITION = 0, 1, 2, 3
 EULER, RK4 = 0, 1
 
 
@@ -223,6 +223,37 @@ def attitude_pid(x: torch.Tensor, u: torch.Tensor, P, dt: float):
     return allocate(wrench, P), torch.cat([i_ang, i_rate, w], 0)
 
 
+def position_controller(x: torch.Tensor, u: torch.Tensor, P) -> torch.Tensor:
+    """Position interface of the first-principles model: command u = [x, y, z,
+    yaw] setpoints, a geometric controller on SO(3) of the kind the paper
+    provides for its trajectory tracking (after Mellinger and Kumar; the paper
+    names it and says it needs only the mass; the structure below and its gains
+    are this project's design):
+      a = -kp (p - p_sp) - kv v + g e_z,   F = m a
+      T = F . (R e_z)                      (collective thrust along the body z)
+      z_d = F / |F|,  y_d = z_d x [cos yaw, sin yaw, 0] normalised,  x_d = y_d x z_d
+      e_R = vee(R_d^T R - R^T R_d) / 2,    e_w = w (rate setpoint zero)
+      tau = J_ctrl (-kR e_R - kw e_w)
+    then the attitude controller's allocation. No controller state."""
+    p, q, v, w = x[0:3], x[3:7], x[7:10], x[10:13]
+    m, g = P["mass"][0], P["gravity"][0]
+    zero = torch.zeros_like(g)
+    a = -P["pos_kp"] * (p - u[0:3]) - P["pos_kv"] * v + torch.stack([zero, zero, g])
+    F = m * a
+    R = rotation_matrix(q)
+    T = (F * R[:, 2]).sum(0)
+    z_d = F / torch.sqrt((F * F).sum(0))
+    x_c = torch.stack([torch.cos(u[3]), torch.sin(u[3]), torch.zeros_like(u[3])])
+    y_d = torch.linalg.cross(z_d, x_c, dim=0)
+    y_d = y_d / torch.sqrt((y_d * y_d).sum(0))
+    x_d = torch.linalg.cross(y_d, z_d, dim=0)
+    Rd = torch.stack([x_d, y_d, z_d], 1)                          # columns
+    E = torch.einsum("jid,jkd->ikd", Rd, R) - torch.einsum("jid,jkd->ikd", R, Rd)
+    e_R = 0.5 * torch.stack([E[2, 1], E[0, 2], E[1, 0]])
+    tau = P["J_ctrl"] * (-P["att_kr"] * e_R - P["att_kw"] * w)
+    return allocate(torch.cat([T[None], tau], 0), P)
+
+
 def allocate(wrench: torch.Tensor, P) -> torch.Tensor:
     """Motor allocation: per-rotor thrusts f = alloc [T, tau_x, tau_y, tau_z],
     clamped to [0, f_max], turned into rotor-speed commands on the thrust curve.
@@ -280,6 +311,8 @@ def step_fp(x, u, P, control: int, integrator: int, dt: float, renorm: bool = Tr
         rot_cmd, ctrl = attitude_pid(x, u, P, dt)
     elif control == CTRL_TORQUE:
         rot_cmd, ctrl = allocate(u, P), None
+    elif control == CTRL_POSITION:
+        rot_cmd, ctrl = position_controller(x, u, P), None
     else:
         rot_cmd, ctrl = u, None
     body = integrate(lambda s: fp_rates(s, rot_cmd, P), x[0:17], dt, integrator)

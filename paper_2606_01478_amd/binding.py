@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libcfsim.so")
 
 CF_OK, CF_EINVAL, CF_ENODEV, CF_ENOMEM, CF_EDEVICE, CF_ESTATE, CF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MODEL_FP, MODEL_ID = 0, 1
-CTRL_ROTOR, CTRL_ATT_PID, CTRL_TORQUE = 0, 1, 2
+CTRL_ROTOR, CTRL_ATT_PID, CTRL_TORQUE, CTRL_POSITION = 0, 1, 2, 3
 INTEG_EULER, INTEG_RK4 = 0, 1
 F_PLAIN_KERNEL, F_NONFINITE_CHECK, F_GRAPH, F_WORKQUEUE, F_NO_AUTOTUNE_CACHE = 0x1, 0x2, 0x4, 0x8, 0x10
 F_SINGLE_LAUNCH = 0x20
@@ -34,6 +34,7 @@ PARAM_OFFSETS = {
     "Jp": (27, 1), "drag": (28, 3), "ang_kp": (31, 2), "ang_ki": (33, 2), "rate_kp": (35, 3),
     "rate_ki": (38, 3), "rate_kd": (41, 3), "J_ctrl": (44, 3), "f_max": (47, 1), "alloc": (48, 16),
     "c_f": (64, 1), "c_tau": (65, 1), "c_psi1": (66, 3), "c_psi2": (69, 3), "c_psi3": (72, 3),
+    "pos_kp": (75, 3), "pos_kv": (78, 3), "att_kr": (81, 3), "att_kw": (84, 3),
 }
 
 EXPORTS = ("cf_create", "cf_destroy", "cf_state_dim", "cf_total_drones", "cf_world_offsets", "cf_set_stream",

@@ -385,7 +385,8 @@ cf_status validate_desc(const cf_desc* d, std::vector<int32_t>& counts, std::vec
         if (m != CF_MODEL_FP && m != CF_MODEL_ID) return CF_EINVAL;
         models[w] = (uint8_t)m;
     }
-    if (d->control != CF_CTRL_ROTOR && d->control != CF_CTRL_ATT_PID && d->control != CF_CTRL_TORQUE)
+    if (d->control != CF_CTRL_ROTOR && d->control != CF_CTRL_ATT_PID && d->control != CF_CTRL_TORQUE &&
+        d->control != CF_CTRL_POSITION)
         return CF_EINVAL;
     if (d->integrator != CF_INTEG_EULER && d->integrator != CF_INTEG_RK4) return CF_EINVAL;
     if (!(std::isfinite(d->dt) && d->dt > 0.f)) return CF_EINVAL;

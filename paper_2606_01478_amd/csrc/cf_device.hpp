@@ -21,10 +21,11 @@ enum : int {
     P_MIX_TY = 15, P_MIX_YAW = 19, P_MOTOR_UP = 23, P_MOTOR_DOWN = 25, P_JP = 27,
     P_DRAG = 28, P_ANG_KP = 31, P_ANG_KI = 33, P_RATE_KP = 35, P_RATE_KI = 38,
     P_RATE_KD = 41, P_J_CTRL = 44, P_F_MAX = 47, P_ALLOC = 48, P_CF = 64, P_CTAU = 65,
-    P_CPSI1 = 66, P_CPSI2 = 69, P_CPSI3 = 72, NPARAM = 96
+    P_CPSI1 = 66, P_CPSI2 = 69, P_CPSI3 = 72, P_POS_KP = 75, P_POS_KV = 78, P_ATT_KR = 81,
+    P_ATT_KW = 84, NPARAM = 96
 };
 enum : int { MODEL_FP = 0, MODEL_ID = 1 };
-enum : int { CTRL_ROTOR = 0, CTRL_PID = 1, CTRL_TORQUE = 2 };
+enum : int { CTRL_ROTOR = 0, CTRL_PID = 1, CTRL_TORQUE = 2, CTRL_POSITION = 3 };
 enum : int { EULER = 0, RK4 = 1 };
 constexpr int S_FP = 17, S_PID = 25, S_ID = 13;
 
@@ -52,6 +53,8 @@ struct FpParams {
 struct PidParams {
     float akp[2], aki[2], rkp[3], rki[3], rkd[3], jc[3], fmax;
     float A[16];
+    // position interface (geometric controller): mass, gravity and gains
+    float m, g, pkp[3], pkv[3], akr[3], akw[3];
 };
 struct IdParams {
     float cf_m, g, ctau, f_hover, inv_m;
@@ -101,8 +104,17 @@ __device__ __forceinline__ FpParams load_fp(const R& rec) {
 }
 
 template <class R>
-__device__ __forceinline__ PidParams load_pid(const R& rec) {
+__device__ __forceinline__ PidParams load_pid(const R& rec, bool position) {
     PidParams C;
+    if (position) {
+        C.m = rec(P_MASS);
+        C.g = rec(P_GRAVITY);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            C.pkp[i] = rec(P_POS_KP + i); C.pkv[i] = rec(P_POS_KV + i);
+            C.akr[i] = rec(P_ATT_KR + i); C.akw[i] = rec(P_ATT_KW + i);
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i) { C.akp[i] = rec(P_ANG_KP + i); C.aki[i] = rec(P_ANG_KI + i); }
 #pragma unroll
@@ -470,6 +482,116 @@ __device__ __forceinline__ void allocate_vjp(const PidParams& C, const PidTrace&
     }
 }
 
+// Position interface: geometric controller on SO(3) (command [x, y, z, yaw]):
+//   a = -kp (p - p_sp) - kv v + g e_z, F = m a, T = F . R e_z,
+//   z_d = F / |F|, y_d = z_d x [cos yaw, sin yaw, 0] normalised, x_d = y_d x z_d,
+//   e_R = vee(R_d^T R - R^T R_d) / 2, tau = J_ctrl (-kR e_R - kw w),
+// then the allocation. The trace keeps what the VJP needs.
+struct PosTrace {
+    float F[3], inv_nF, zd[3], inv_ny, yd[3], xd[3], R[9], s, c;
+};
+
+__device__ __forceinline__ void pos_forward(const float* x, const float* u, const FpParams& P, const PidParams& C,
+                                            float* rc, PidTrace& tr, PosTrace& pt) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pt.F[i] = C.m * (-C.pkp[i] * (x[i] - u[i]) - C.pkv[i] * x[7 + i] + (i == 2 ? C.g : 0.f));
+    quat_matrix(x[3], x[4], x[5], x[6], pt.R);
+    const float* R = pt.R;
+    const float T = pt.F[0] * R[2] + pt.F[1] * R[5] + pt.F[2] * R[8];
+    pt.inv_nF = rsqrt_hw(pt.F[0] * pt.F[0] + pt.F[1] * pt.F[1] + pt.F[2] * pt.F[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pt.zd[i] = pt.F[i] * pt.inv_nF;
+    sincos_cw(u[3], &pt.s, &pt.c);
+    // y = z_d x (c, s, 0)
+    const float yr[3] = {-pt.zd[2] * pt.s, pt.zd[2] * pt.c, pt.zd[0] * pt.s - pt.zd[1] * pt.c};
+    pt.inv_ny = rsqrt_hw(yr[0] * yr[0] + yr[1] * yr[1] + yr[2] * yr[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pt.yd[i] = yr[i] * pt.inv_ny;
+    pt.xd[0] = pt.yd[1] * pt.zd[2] - pt.yd[2] * pt.zd[1];
+    pt.xd[1] = pt.yd[2] * pt.zd[0] - pt.yd[0] * pt.zd[2];
+    pt.xd[2] = pt.yd[0] * pt.zd[1] - pt.yd[1] * pt.zd[0];
+    // columns of R: c0 = (R0, R3, R6), c1 = (R1, R4, R7), c2 = (R2, R5, R8)
+    const float e0 = 0.5f * ((pt.zd[0] * R[1] + pt.zd[1] * R[4] + pt.zd[2] * R[7]) -
+                             (R[2] * pt.yd[0] + R[5] * pt.yd[1] + R[8] * pt.yd[2]));
+    const float e1 = 0.5f * ((pt.xd[0] * R[2] + pt.xd[1] * R[5] + pt.xd[2] * R[8]) -
+                             (R[0] * pt.zd[0] + R[3] * pt.zd[1] + R[6] * pt.zd[2]));
+    const float e2 = 0.5f * ((pt.yd[0] * R[0] + pt.yd[1] * R[3] + pt.yd[2] * R[6]) -
+                             (R[1] * pt.xd[0] + R[4] * pt.xd[1] + R[7] * pt.xd[2]));
+    const float eR[3] = {e0, e1, e2};
+    float wrench[4];
+    wrench[0] = T;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) wrench[1 + i] = C.jc[i] * (-C.akr[i] * eR[i] - C.akw[i] * x[10 + i]);
+    allocate(wrench, P, C, rc, tr);
+}
+
+// xb (state, rows 0..12) and ub accumulate (d rc / d (x, u))^T rcb
+__device__ __forceinline__ void pos_vjp(const float* x, const PidParams& C, const PidTrace& tr, const PosTrace& pt,
+                                        const float* rcb, float* xb, float* ub) {
+    float wb[4] = {0.f, 0.f, 0.f, 0.f};
+    allocate_vjp(C, tr, rcb, wb);
+    const float Tb = wb[0];
+    float eb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        eb[i] = -0.5f * C.jc[i] * C.akr[i] * wb[1 + i];   // includes the 1/2 of e_R
+        xb[10 + i] -= C.jc[i] * C.akw[i] * wb[1 + i];
+    }
+    const float* R = pt.R;
+    const float c0[3] = {R[0], R[3], R[6]}, c1[3] = {R[1], R[4], R[7]}, c2[3] = {R[2], R[5], R[8]};
+    float c0b[3], c1b[3], c2b[3], zdb[3], ydb[3], xdb[3], Fb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        // e0 = (zd . c1 - c2 . yd)/2, e1 = (xd . c2 - c0 . zd)/2, e2 = (yd . c0 - c1 . xd)/2
+        zdb[i] = eb[0] * c1[i] - eb[1] * c0[i];
+        ydb[i] = -eb[0] * c2[i] + eb[2] * c0[i];
+        xdb[i] = eb[1] * c2[i] - eb[2] * c1[i];
+        c0b[i] = -eb[1] * pt.zd[i] + eb[2] * pt.yd[i];
+        c1b[i] = eb[0] * pt.zd[i] - eb[2] * pt.xd[i];
+        c2b[i] = -eb[0] * pt.yd[i] + eb[1] * pt.xd[i] + Tb * pt.F[i];   // T = F . c2
+        Fb[i] = Tb * c2[i];
+    }
+    // xd = yd x zd
+    ydb[0] += pt.zd[1] * xdb[2] - pt.zd[2] * xdb[1];
+    ydb[1] += pt.zd[2] * xdb[0] - pt.zd[0] * xdb[2];
+    ydb[2] += pt.zd[0] * xdb[1] - pt.zd[1] * xdb[0];
+    zdb[0] += xdb[1] * pt.yd[2] - xdb[2] * pt.yd[1];
+    zdb[1] += xdb[2] * pt.yd[0] - xdb[0] * pt.yd[2];
+    zdb[2] += xdb[0] * pt.yd[1] - xdb[1] * pt.yd[0];
+    // yd = y / |y|
+    const float dy = pt.yd[0] * ydb[0] + pt.yd[1] * ydb[1] + pt.yd[2] * ydb[2];
+    float yb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) yb[i] = (ydb[i] - pt.yd[i] * dy) * pt.inv_ny;
+    // y = zd x xc, xc = (c, s, 0)
+    zdb[0] += pt.s * yb[2];                       // (xc x yb)_0 = s yb2 - 0 yb1
+    zdb[1] += -pt.c * yb[2];                      // (xc x yb)_1 = 0 yb0 - c yb2
+    zdb[2] += pt.c * yb[1] - pt.s * yb[0];        // (xc x yb)_2
+    const float xcb0 = yb[1] * pt.zd[2] - yb[2] * pt.zd[1];
+    const float xcb1 = yb[2] * pt.zd[0] - yb[0] * pt.zd[2];
+    ub[3] += -pt.s * xcb0 + pt.c * xcb1;
+    // zd = F / |F|
+    const float dz = pt.zd[0] * zdb[0] + pt.zd[1] * zdb[1] + pt.zd[2] * zdb[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Fb[i] += (zdb[i] - pt.zd[i] * dz) * pt.inv_nF;
+    // F = m (-kp (p - p_sp) - kv v + g e_z)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float ab = C.m * Fb[i];
+        xb[i] -= C.pkp[i] * ab;
+        ub[i] += C.pkp[i] * ab;
+        xb[7 + i] -= C.pkv[i] * ab;
+    }
+    float Rb[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        Rb[3 * i] = c0b[i];
+        Rb[3 * i + 1] = c1b[i];
+        Rb[3 * i + 2] = c2b[i];
+    }
+    quat_matrix_vjp(x[3], x[4], x[5], x[6], Rb, xb + 3);
+}
+
 // x: 25-component state; u: [roll, pitch, yawrate, thrust]. Writes rotor
 // commands rc[4] and the new controller state cs[8] = [I_a(2), I_r(3), w_prev(3)].
 __device__ __forceinline__ void pid_forward(const float* x, const float* u, const FpParams& P,
@@ -672,6 +794,10 @@ __device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, c
     } else if constexpr (CTRL == CTRL_TORQUE) {
         PidTrace tr;
         allocate(u, P, C, rc, tr);
+    } else if constexpr (CTRL == CTRL_POSITION) {
+        PidTrace tr;
+        PosTrace pt;
+        pos_forward(x, u, P, C, rc, tr, pt);
     } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) rc[i] = u[i];
@@ -702,10 +828,13 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
                                             const float* yb, float* xb, float* ub) {
     float rc[4], cs[8];
     PidTrace tr;
+    PosTrace pt;
     if constexpr (CTRL == CTRL_PID) {
         pid_forward(x, u, P, C, dt, inv_dt, rc, cs, tr);
     } else if constexpr (CTRL == CTRL_TORQUE) {
         allocate(u, P, C, rc, tr);
+    } else if constexpr (CTRL == CTRL_POSITION) {
+        pos_forward(x, u, P, C, rc, tr, pt);
     } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) rc[i] = u[i];
@@ -735,6 +864,8 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
         pid_vjp(x, P, C, dt, inv_dt, tr, rcb, yb + S_FP, xb, ub);
     } else if constexpr (CTRL == CTRL_TORQUE) {
         allocate_vjp(C, tr, rcb, ub);
+    } else if constexpr (CTRL == CTRL_POSITION) {
+        pos_vjp(x, C, tr, pt, rcb, xb, ub);
     } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) ub[i] += rcb[i];

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_mppi_rollout(MppiArgs a) {
     IdParams Pi;
     if constexpr (MODEL == MODEL_FP) {
         P = load_fp<AERO>(rec);
-        if constexpr (CTRL != CTRL_ROTOR) Cp = load_pid(rec);
+        if constexpr (CTRL != CTRL_ROTOR) Cp = load_pid(rec, CTRL == CTRL_POSITION);
     } else {
         Pi = load_id<AERO>(rec);
     }
@@ -329,19 +329,21 @@ static hipError_t launch_roll(const KernelSel&, const MppiArgs& a, hipStream_t s
     return hipGetLastError();
 }
 
-#define CF_MPPI_DISPATCH_A(A)                                                                           \
-    switch (ks.models * 8 + ks.ctrl * 2 + ks.integ) {                                                   \
-        case MS_FP * 8 + 0: return launch_roll<MODEL_FP, CTRL_ROTOR, EULER, A>(ks, a, s);             \
-        case MS_FP * 8 + 1: return launch_roll<MODEL_FP, CTRL_ROTOR, RK4, A>(ks, a, s);               \
-        case MS_FP * 8 + 2: return launch_roll<MODEL_FP, CTRL_PID, EULER, A>(ks, a, s);               \
-        case MS_FP * 8 + 3: return launch_roll<MODEL_FP, CTRL_PID, RK4, A>(ks, a, s);                 \
-        case MS_FP * 8 + 4: return launch_roll<MODEL_FP, CTRL_TORQUE, EULER, A>(ks, a, s);            \
-        case MS_FP * 8 + 5: return launch_roll<MODEL_FP, CTRL_TORQUE, RK4, A>(ks, a, s);              \
-        case MS_ID * 8 + 0: case MS_ID * 8 + 2: case MS_ID * 8 + 4:                                    \
-            return launch_roll<MODEL_ID, CTRL_ROTOR, EULER, A>(ks, a, s);                               \
-        case MS_ID * 8 + 1: case MS_ID * 8 + 3: case MS_ID * 8 + 5:                                    \
-            return launch_roll<MODEL_ID, CTRL_ROTOR, RK4, A>(ks, a, s);                                 \
-        default: break;                                                                                 \
+#define CF_MPPI_DISPATCH_A(A)                                                                \
+    switch (ks.models * 8 + ks.ctrl * 2 + ks.integ) {                                        \
+        case MS_FP * 8 + 0: return launch_roll<MODEL_FP, CTRL_ROTOR, EULER, A>(ks, a, s);    \
+        case MS_FP * 8 + 1: return launch_roll<MODEL_FP, CTRL_ROTOR, RK4, A>(ks, a, s);      \
+        case MS_FP * 8 + 2: return launch_roll<MODEL_FP, CTRL_PID, EULER, A>(ks, a, s);      \
+        case MS_FP * 8 + 3: return launch_roll<MODEL_FP, CTRL_PID, RK4, A>(ks, a, s);        \
+        case MS_FP * 8 + 4: return launch_roll<MODEL_FP, CTRL_TORQUE, EULER, A>(ks, a, s);   \
+        case MS_FP * 8 + 5: return launch_roll<MODEL_FP, CTRL_TORQUE, RK4, A>(ks, a, s);     \
+        case MS_FP * 8 + 6: return launch_roll<MODEL_FP, CTRL_POSITION, EULER, A>(ks, a, s); \
+        case MS_FP * 8 + 7: return launch_roll<MODEL_FP, CTRL_POSITION, RK4, A>(ks, a, s);   \
+        case MS_ID * 8 + 0: case MS_ID * 8 + 2: case MS_ID * 8 + 4: case MS_ID * 8 + 6:      \
+            return launch_roll<MODEL_ID, CTRL_ROTOR, EULER, A>(ks, a, s);                    \
+        case MS_ID * 8 + 1: case MS_ID * 8 + 3: case MS_ID * 8 + 5: case MS_ID * 8 + 7:      \
+            return launch_roll<MODEL_ID, CTRL_ROTOR, RK4, A>(ks, a, s);                      \
+        default: break;                                                                      \
     }
 
 hipError_t launch_mppi_rollout(const KernelSel& ks, const MppiArgs& a, hipStream_t s) {

@@ -96,7 +96,7 @@ template <int MODEL, int CTRL, bool AERO, class R>
 __device__ __forceinline__ void load_params(const R& rec, DroneParams& p) {
     if constexpr (MODEL == MODEL_FP) {
         p.fp = load_fp<AERO>(rec);
-        if constexpr (CTRL != CTRL_ROTOR) p.pid = load_pid(rec);
+        if constexpr (CTRL != CTRL_ROTOR) p.pid = load_pid(rec, CTRL == CTRL_POSITION);
     } else {
         p.id = load_id<AERO>(rec);
     }
@@ -382,25 +382,29 @@ static hipError_t launch_bwd_t(const KernelSel& ks, const RollArgs& a, const int
     return launch_roll_t<true, MODELS, CTRL, INTEG, AERO>(ks, a, tiles, n_tiles, s);
 }
 
-#define CF_DISPATCH_A(FN, A, ...)                                                        \
-    switch (ks.models * 8 + ks.ctrl * 2 + ks.integ) {                                    \
-        case MS_FP * 8 + 0: return FN<MS_FP, CTRL_ROTOR, EULER, A>(__VA_ARGS__);         \
-        case MS_FP * 8 + 1: return FN<MS_FP, CTRL_ROTOR, RK4, A>(__VA_ARGS__);           \
-        case MS_FP * 8 + 2: return FN<MS_FP, CTRL_PID, EULER, A>(__VA_ARGS__);           \
-        case MS_FP * 8 + 3: return FN<MS_FP, CTRL_PID, RK4, A>(__VA_ARGS__);             \
-        case MS_FP * 8 + 4: return FN<MS_FP, CTRL_TORQUE, EULER, A>(__VA_ARGS__);        \
-        case MS_FP * 8 + 5: return FN<MS_FP, CTRL_TORQUE, RK4, A>(__VA_ARGS__);          \
-        case MS_ID * 8 + 0: case MS_ID * 8 + 2: case MS_ID * 8 + 4:                      \
-            return FN<MS_ID, CTRL_ROTOR, EULER, A>(__VA_ARGS__);                         \
-        case MS_ID * 8 + 1: case MS_ID * 8 + 3: case MS_ID * 8 + 5:                      \
-            return FN<MS_ID, CTRL_ROTOR, RK4, A>(__VA_ARGS__);                           \
-        case MS_BOTH * 8 + 0: return FN<MS_BOTH, CTRL_ROTOR, EULER, A>(__VA_ARGS__);     \
-        case MS_BOTH * 8 + 1: return FN<MS_BOTH, CTRL_ROTOR, RK4, A>(__VA_ARGS__);       \
-        case MS_BOTH * 8 + 2: return FN<MS_BOTH, CTRL_PID, EULER, A>(__VA_ARGS__);       \
-        case MS_BOTH * 8 + 3: return FN<MS_BOTH, CTRL_PID, RK4, A>(__VA_ARGS__);         \
-        case MS_BOTH * 8 + 4: return FN<MS_BOTH, CTRL_TORQUE, EULER, A>(__VA_ARGS__);    \
-        case MS_BOTH * 8 + 5: return FN<MS_BOTH, CTRL_TORQUE, RK4, A>(__VA_ARGS__);      \
-        default: break;                                                                  \
+#define CF_DISPATCH_A(FN, A, ...)                                                       \
+    switch (ks.models * 8 + ks.ctrl * 2 + ks.integ) {                                   \
+        case MS_FP * 8 + 0: return FN<MS_FP, CTRL_ROTOR, EULER, A>(__VA_ARGS__);        \
+        case MS_FP * 8 + 1: return FN<MS_FP, CTRL_ROTOR, RK4, A>(__VA_ARGS__);          \
+        case MS_FP * 8 + 2: return FN<MS_FP, CTRL_PID, EULER, A>(__VA_ARGS__);          \
+        case MS_FP * 8 + 3: return FN<MS_FP, CTRL_PID, RK4, A>(__VA_ARGS__);            \
+        case MS_FP * 8 + 4: return FN<MS_FP, CTRL_TORQUE, EULER, A>(__VA_ARGS__);       \
+        case MS_FP * 8 + 5: return FN<MS_FP, CTRL_TORQUE, RK4, A>(__VA_ARGS__);         \
+        case MS_FP * 8 + 6: return FN<MS_FP, CTRL_POSITION, EULER, A>(__VA_ARGS__);     \
+        case MS_FP * 8 + 7: return FN<MS_FP, CTRL_POSITION, RK4, A>(__VA_ARGS__);       \
+        case MS_ID * 8 + 0: case MS_ID * 8 + 2: case MS_ID * 8 + 4: case MS_ID * 8 + 6: \
+            return FN<MS_ID, CTRL_ROTOR, EULER, A>(__VA_ARGS__);                        \
+        case MS_ID * 8 + 1: case MS_ID * 8 + 3: case MS_ID * 8 + 5: case MS_ID * 8 + 7: \
+            return FN<MS_ID, CTRL_ROTOR, RK4, A>(__VA_ARGS__);                          \
+        case MS_BOTH * 8 + 0: return FN<MS_BOTH, CTRL_ROTOR, EULER, A>(__VA_ARGS__);    \
+        case MS_BOTH * 8 + 1: return FN<MS_BOTH, CTRL_ROTOR, RK4, A>(__VA_ARGS__);      \
+        case MS_BOTH * 8 + 2: return FN<MS_BOTH, CTRL_PID, EULER, A>(__VA_ARGS__);      \
+        case MS_BOTH * 8 + 3: return FN<MS_BOTH, CTRL_PID, RK4, A>(__VA_ARGS__);        \
+        case MS_BOTH * 8 + 4: return FN<MS_BOTH, CTRL_TORQUE, EULER, A>(__VA_ARGS__);   \
+        case MS_BOTH * 8 + 5: return FN<MS_BOTH, CTRL_TORQUE, RK4, A>(__VA_ARGS__);     \
+        case MS_BOTH * 8 + 6: return FN<MS_BOTH, CTRL_POSITION, EULER, A>(__VA_ARGS__); \
+        case MS_BOTH * 8 + 7: return FN<MS_BOTH, CTRL_POSITION, RK4, A>(__VA_ARGS__);   \
+        default: break;                                                                 \
     }
 #define CF_DISPATCH(FN, ...)                                                             \
     if (ks.aero) {                                                                       \

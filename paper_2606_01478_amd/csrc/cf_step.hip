@@ -15,7 +15,7 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
         constexpr int S = (CTRL == CTRL_PID) ? S_PID : S_FP;
         const FpParams P = load_fp<AERO>(rec);
         PidParams C;
-        if constexpr (CTRL != CTRL_ROTOR) C = load_pid(rec);
+        if constexpr (CTRL != CTRL_ROTOR) C = load_pid(rec, CTRL == CTRL_POSITION);
         float x[S], u[4], comp[S_FP];
 #pragma unroll
         for (int i = 0; i < S; ++i) x[i] = a.st[i * D + d];
@@ -123,25 +123,29 @@ static int wq_blocks_t(int tile) {
     return nb > 0 ? nb : 1;
 }
 
-#define CF_DISPATCH_A(FN, A, ...)                                                        \
-    switch (ks.models * 8 + ks.ctrl * 2 + ks.integ) {                                    \
-        case MS_FP * 8 + 0: return FN<MS_FP, CTRL_ROTOR, EULER, A>(__VA_ARGS__);         \
-        case MS_FP * 8 + 1: return FN<MS_FP, CTRL_ROTOR, RK4, A>(__VA_ARGS__);           \
-        case MS_FP * 8 + 2: return FN<MS_FP, CTRL_PID, EULER, A>(__VA_ARGS__);           \
-        case MS_FP * 8 + 3: return FN<MS_FP, CTRL_PID, RK4, A>(__VA_ARGS__);             \
-        case MS_FP * 8 + 4: return FN<MS_FP, CTRL_TORQUE, EULER, A>(__VA_ARGS__);        \
-        case MS_FP * 8 + 5: return FN<MS_FP, CTRL_TORQUE, RK4, A>(__VA_ARGS__);          \
-        case MS_ID * 8 + 0: case MS_ID * 8 + 2: case MS_ID * 8 + 4:                      \
-            return FN<MS_ID, CTRL_ROTOR, EULER, A>(__VA_ARGS__);                         \
-        case MS_ID * 8 + 1: case MS_ID * 8 + 3: case MS_ID * 8 + 5:                      \
-            return FN<MS_ID, CTRL_ROTOR, RK4, A>(__VA_ARGS__);                           \
-        case MS_BOTH * 8 + 0: return FN<MS_BOTH, CTRL_ROTOR, EULER, A>(__VA_ARGS__);     \
-        case MS_BOTH * 8 + 1: return FN<MS_BOTH, CTRL_ROTOR, RK4, A>(__VA_ARGS__);       \
-        case MS_BOTH * 8 + 2: return FN<MS_BOTH, CTRL_PID, EULER, A>(__VA_ARGS__);       \
-        case MS_BOTH * 8 + 3: return FN<MS_BOTH, CTRL_PID, RK4, A>(__VA_ARGS__);         \
-        case MS_BOTH * 8 + 4: return FN<MS_BOTH, CTRL_TORQUE, EULER, A>(__VA_ARGS__);    \
-        case MS_BOTH * 8 + 5: return FN<MS_BOTH, CTRL_TORQUE, RK4, A>(__VA_ARGS__);      \
-        default: break;                                                                  \
+#define CF_DISPATCH_A(FN, A, ...)                                                       \
+    switch (ks.models * 8 + ks.ctrl * 2 + ks.integ) {                                   \
+        case MS_FP * 8 + 0: return FN<MS_FP, CTRL_ROTOR, EULER, A>(__VA_ARGS__);        \
+        case MS_FP * 8 + 1: return FN<MS_FP, CTRL_ROTOR, RK4, A>(__VA_ARGS__);          \
+        case MS_FP * 8 + 2: return FN<MS_FP, CTRL_PID, EULER, A>(__VA_ARGS__);          \
+        case MS_FP * 8 + 3: return FN<MS_FP, CTRL_PID, RK4, A>(__VA_ARGS__);            \
+        case MS_FP * 8 + 4: return FN<MS_FP, CTRL_TORQUE, EULER, A>(__VA_ARGS__);       \
+        case MS_FP * 8 + 5: return FN<MS_FP, CTRL_TORQUE, RK4, A>(__VA_ARGS__);         \
+        case MS_FP * 8 + 6: return FN<MS_FP, CTRL_POSITION, EULER, A>(__VA_ARGS__);     \
+        case MS_FP * 8 + 7: return FN<MS_FP, CTRL_POSITION, RK4, A>(__VA_ARGS__);       \
+        case MS_ID * 8 + 0: case MS_ID * 8 + 2: case MS_ID * 8 + 4: case MS_ID * 8 + 6: \
+            return FN<MS_ID, CTRL_ROTOR, EULER, A>(__VA_ARGS__);                        \
+        case MS_ID * 8 + 1: case MS_ID * 8 + 3: case MS_ID * 8 + 5: case MS_ID * 8 + 7: \
+            return FN<MS_ID, CTRL_ROTOR, RK4, A>(__VA_ARGS__);                          \
+        case MS_BOTH * 8 + 0: return FN<MS_BOTH, CTRL_ROTOR, EULER, A>(__VA_ARGS__);    \
+        case MS_BOTH * 8 + 1: return FN<MS_BOTH, CTRL_ROTOR, RK4, A>(__VA_ARGS__);      \
+        case MS_BOTH * 8 + 2: return FN<MS_BOTH, CTRL_PID, EULER, A>(__VA_ARGS__);      \
+        case MS_BOTH * 8 + 3: return FN<MS_BOTH, CTRL_PID, RK4, A>(__VA_ARGS__);        \
+        case MS_BOTH * 8 + 4: return FN<MS_BOTH, CTRL_TORQUE, EULER, A>(__VA_ARGS__);   \
+        case MS_BOTH * 8 + 5: return FN<MS_BOTH, CTRL_TORQUE, RK4, A>(__VA_ARGS__);     \
+        case MS_BOTH * 8 + 6: return FN<MS_BOTH, CTRL_POSITION, EULER, A>(__VA_ARGS__); \
+        case MS_BOTH * 8 + 7: return FN<MS_BOTH, CTRL_POSITION, RK4, A>(__VA_ARGS__);   \
+        default: break;                                                                 \
     }
 #define CF_DISPATCH(FN, ...)                                                             \
     if (ks.aero) {                                                                       \

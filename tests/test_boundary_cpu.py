@@ -41,7 +41,8 @@ def test_param_offsets_match_header():
              "Jp": "CF_P_JP", "drag": "CF_P_DRAG", "ang_kp": "CF_P_ANG_KP", "ang_ki": "CF_P_ANG_KI",
              "rate_kp": "CF_P_RATE_KP", "rate_ki": "CF_P_RATE_KI", "rate_kd": "CF_P_RATE_KD",
              "J_ctrl": "CF_P_J_CTRL", "f_max": "CF_P_F_MAX", "alloc": "CF_P_ALLOC", "c_f": "CF_P_CF",
-             "c_tau": "CF_P_CTAU", "c_psi1": "CF_P_CPSI1", "c_psi2": "CF_P_CPSI2", "c_psi3": "CF_P_CPSI3"}
+             "c_tau": "CF_P_CTAU", "c_psi1": "CF_P_CPSI1", "c_psi2": "CF_P_CPSI2", "c_psi3": "CF_P_CPSI3",
+             "pos_kp": "CF_P_POS_KP", "pos_kv": "CF_P_POS_KV", "att_kr": "CF_P_ATT_KR", "att_kw": "CF_P_ATT_KW"}
     assert set(names) == set(B.PARAM_OFFSETS) == {n for n, _ in W.PARAM_FIELDS}
     for n, macro in names.items():
         assert B.PARAM_OFFSETS[n][0] == defs[macro], n

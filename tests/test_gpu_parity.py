@@ -400,3 +400,30 @@ def test_direct_thrust_variant_held(gpu_lib, wq):
 def test_direct_thrust_variant_gradients(gpu_lib):
     w = _direct_half(W.small(4, seed=52))
     _check_against_oracle(w, _rollout_grads(w, 25))
+
+
+@pytest.mark.parametrize("wq", [False, True])
+def test_position_interface_held_steps(gpu_lib, wq):
+    """[x, y, z, yaw] setpoints through the geometric controller and the
+    allocation, 500 held steps (1 s) per world."""
+    w = W.fp_position(seed=60, n_worlds=300)
+    sim = _sim(w, flags=B.F_WORKQUEUE if wq else 0)
+    x = dev(w.x0)
+    sim.step_k(x, dev(w.cmds), w.steps)
+    torch.cuda.synchronize()
+    assert_states_close(x, O.simulate_held(w), w, what="position held")
+
+
+@pytest.mark.parametrize("aero", [False, True])
+def test_position_interface_rollout_gradients(gpu_lib, aero):
+    w = W.fp_position(seed=61, n_worlds=70, steps=60)
+    rng = np.random.default_rng(61)
+    cmds = np.repeat(w.cmds[None], w.steps, 0).astype(np.float64)
+    cmds[:, 0:3] += rng.normal(0.0, 0.05, size=(w.steps, 3, w.n_worlds))
+    w.cmds = cmds.astype(np.float32)
+    w.ref_offset = w.x0[0:3].copy()
+    w.dloss = np.linspace(0.5, 1.5, w.n_worlds).astype(np.float32)
+    w.w_u = 1e-2
+    if aero:
+        w = _with_aero(w)
+    _check_against_oracle(w, _rollout_grads(w, 15))

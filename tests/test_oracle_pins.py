@@ -806,3 +806,89 @@ def test_gradient_fd_direct_thrust():
     w.params["c_tau"][[0, 2]] = 0.0
     w.gain = w.gain * 5
     _fd_check(w)
+
+
+# ---- position interface (geometric controller) ----------------------------------------
+
+def _hover17(p):
+    wh = math.sqrt(W.MASS * W.GRAVITY / (4 * W.K_THRUST))
+    x = torch.zeros(17, 1, dtype=F64)
+    x[0:3, 0] = torch.tensor(p, dtype=F64)
+    x[6] = 1.0
+    x[13:17] = wh
+    return x, wh
+
+
+def test_position_controller_hover_equilibrium():
+    b, _ = fp_batch(1, control=O.CTRL_POSITION)
+    x, _ = _hover17([0.3, -0.2, 1.0])
+    u = torch.tensor([[0.3], [-0.2], [1.0], [0.0]], dtype=F64)
+    y = run(b, x, u, 1000)
+    assert float((y - x).abs().max()) < 1e-9
+
+
+def test_position_controller_linearisation_is_stable():
+    """Jacobian of the closed-loop discrete map at hover on the setpoint: with no
+    integrator and every degree of freedom controlled, all modes lie strictly
+    inside the unit circle."""
+    b, _ = fp_batch(1, control=O.CTRL_POSITION)
+    x, wh = _hover17([0.0, 0.0, 1.0])
+    u = torch.tensor([[0.0], [0.0], [1.0], [0.0]], dtype=F64)
+    scale = torch.ones(17, dtype=F64)
+    scale[13:17] = wh
+    Jm = torch.zeros(17, 17, dtype=F64)
+    for j in range(17):
+        h = 1e-6 * scale[j]
+        xp, xm = x.clone(), x.clone()
+        xp[j] += h
+        xm[j] -= h
+        Jm[:, j] = (b.step(xp, u) - b.step(xm, u))[:, 0] / (2 * h)
+    keep = [i for i in range(17) if i != 6]
+    mag = np.abs(np.linalg.eigvals(Jm[keep][:, keep].numpy()))
+    assert mag.max() < 1 - 1e-3
+
+
+def test_position_controller_reaches_setpoint_and_yaw():
+    b, _ = fp_batch(1, control=O.CTRL_POSITION)
+    x, _ = _hover17([0.3, 0.0, 1.0])
+    u = torch.tensor([[1.3], [0.3], [1.5], [0.5]], dtype=F64)
+    y = run(b, x, u, 5000)
+    assert torch.allclose(y[0:3], u[0:3], atol=1e-4)
+    qx, qy, qz, qw = (float(v) for v in y[3:7, 0])
+    yaw = math.atan2(2 * (qw * qz + qx * qy), 1 - 2 * (qy * qy + qz * qz))
+    assert abs(yaw - 0.5) < 1e-4
+    assert float(y[7:13].abs().max()) < 1e-4
+
+
+def test_position_controller_yaw_equivariance():
+    """Rotating the start, the setpoint and the yaw setpoint about world z by a
+    rotates the whole closed-loop trajectory by a."""
+    b, _ = fp_batch(1, control=O.CTRL_POSITION)
+    x, _ = _hover17([0.2, -0.4, 0.8])
+    x[3:7, 0] = torch.tensor([0.05, -0.03, 0.1, 1.0], dtype=F64) / math.sqrt(1 + 0.05 ** 2 + 0.03 ** 2 + 0.01)
+    x[7:13, 0] = torch.tensor([0.3, -0.1, 0.2, 0.5, -0.4, 0.3], dtype=F64)
+    u = torch.tensor([[1.0], [0.5], [1.2], [0.3]], dtype=F64)
+    a = 0.7
+    Rz = torch.tensor([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]], dtype=F64)
+    qz = torch.tensor([[0.0], [0.0], [math.sin(a / 2)], [math.cos(a / 2)]], dtype=F64)
+    xr = x.clone()
+    xr[0:3] = Rz @ x[0:3]
+    xr[3:7] = O.quat_mul(qz, x[3:7])
+    xr[7:10] = Rz @ x[7:10]
+    ur = u.clone()
+    ur[0:3] = Rz @ u[0:3]
+    ur[3] = u[3] + a
+    y, yr = run(b, x, u, 400), run(b, xr, ur, 400)
+    assert torch.allclose(yr[0:3], Rz @ y[0:3], atol=1e-10)
+    assert torch.allclose(yr[7:10], Rz @ y[7:10], atol=1e-10)
+    assert torch.allclose(yr[3:7], O.quat_mul(qz, y[3:7]), atol=1e-10)
+    assert torch.allclose(yr[10:17], y[10:17], atol=1e-8 * 15000)
+
+
+def test_gradient_fd_position_interface():
+    w = W.fp_position(seed=27, n_worlds=3, steps=30)
+    w.ref_offset = w.cmds[0:3].copy()
+    w.dloss = np.ones(3, np.float32)
+    w.w_u = 1e-2
+    w.cmds = np.repeat(w.cmds[None], w.steps, axis=0)
+    _fd_check(w)

@@ -28,6 +28,7 @@ MODEL_ID = 1          # identified (abstracted) attitude-command model
 CTRL_ROTOR = 0        # first-principles worlds take rotor-speed commands
 CTRL_ATT_PID = 1      # first-principles worlds take [roll, pitch, yaw-rate, thrust]
 CTRL_TORQUE = 2       # first-principles worlds take [thrust, tau_x, tau_y, tau_z]
+CTRL_POSITION = 3     # first-principles worlds take [x, y, z, yaw] setpoints
 INTEG_EULER = 0
 INTEG_RK4 = 1
 
@@ -45,6 +46,7 @@ PARAM_FIELDS = (
     ("ang_kp", 2), ("ang_ki", 2), ("rate_kp", 3), ("rate_ki", 3), ("rate_kd", 3),
     ("J_ctrl", 3), ("f_max", 1), ("alloc", 16),
     ("c_f", 1), ("c_tau", 1), ("c_psi1", 3), ("c_psi2", 3), ("c_psi3", 3),
+    ("pos_kp", 3), ("pos_kv", 3), ("att_kr", 3), ("att_kw", 3),
 )
 
 # ---- nominal Crazyflie-class airframe (synthetic values) --------------------
@@ -59,6 +61,11 @@ THRUST_TO_WEIGHT = 1.9
 # attitude PID gains (own design, normalised by the nominal inertia)
 ANG_KP, ANG_KI = 6.0, 1.0
 RATE_KP, RATE_KI, RATE_KD = 17.0, 5.0, 0.1
+# geometric position controller (position interface), per axis
+POS_KP = (4.0, 4.0, 6.0)     # [1/s^2]
+POS_KV = (4.0, 4.0, 5.0)     # [1/s]
+ATT_KR = (100.0, 100.0, 25.0)  # [1/s^2]
+ATT_KW = (20.0, 20.0, 10.0)    # [1/s]
 # identified model nominal response
 ID_TAU = (0.06, 0.06, 0.12)
 ID_GAIN = (1.0, 1.0, 1.0)
@@ -140,6 +147,10 @@ def fill_fp_airframe(P: Dict[str, np.ndarray], worlds, mass, inertia) -> None:
     P["rate_kd"][worlds] = RATE_KD
     P["J_ctrl"][worlds] = INERTIA
     P["f_max"][worlds, 0] = THRUST_TO_WEIGHT * MASS * GRAVITY / 4.0
+    P["pos_kp"][worlds] = POS_KP
+    P["pos_kv"][worlds] = POS_KV
+    P["att_kr"][worlds] = ATT_KR
+    P["att_kw"][worlds] = ATT_KW
     # Allocation (controller mixer) of the x airframe: per-motor thrust from
     # [collective thrust, tau_x, tau_y, tau_z]; row i = motor i.
     sx = (-1.0, -1.0, 1.0, 1.0)
@@ -234,6 +245,28 @@ def fp_torque(seed: int = 1006, n_worlds: int = 256, steps: int = 150, dt: float
     cmds[1:4] = rng.normal(0.0, 2e-5, size=(3, D))
     return Workload("fp_torque_interface", M, np.ones(M, np.int32), np.full(M, MODEL_FP, np.uint8),
                     CTRL_TORQUE, INTEG_RK4, float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps,
+                    _f32(cmds))
+
+
+def fp_position(seed: int = 1010, n_worlds: int = 256, steps: int = 500, dt: float = 0.002) -> Workload:
+    """Position interface of the first-principles model (geometric controller):
+    per-world mass and inertia x U[0.9, 1.1], start at rest at p ~ U[-1, 1]^3 with
+    hover rotors, held setpoints p + U[-1, 1]^3 and yaw ~ U[-0.5, 0.5] rad."""
+    rng = _rng(seed)
+    M = D = n_worlds
+    P = empty_params(M)
+    mass = MASS * rng.uniform(0.9, 1.1, size=M)
+    inertia = np.asarray(INERTIA)[None, :] * rng.uniform(0.9, 1.1, size=(M, 3))
+    fill_fp_airframe(P, np.arange(M), mass, inertia)
+    x0 = np.zeros((S_FP_ROTOR, D))
+    x0[0:3] = rng.uniform(-1.0, 1.0, size=(3, D))
+    x0[6] = 1.0
+    x0[13:17] = hover_speed(mass)
+    cmds = np.empty((4, D))
+    cmds[0:3] = x0[0:3] + rng.uniform(-1.0, 1.0, size=(3, D))
+    cmds[3] = rng.uniform(-0.5, 0.5, size=D)
+    return Workload("fp_position_interface", M, np.ones(M, np.int32), np.full(M, MODEL_FP, np.uint8),
+                    CTRL_POSITION, INTEG_RK4, float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps,
                     _f32(cmds))
 
 
