@@ -267,8 +267,8 @@ void clear_graphs(cf_handle* h) {
 // model with the identified-model launch forked onto the auxiliary stream and
 // joined back with events (also valid while capturing a graph).
 template <class F>
-hipError_t per_model(cf_handle* h, hipStream_t s, F&& fn) {
-    if (!(h->models == MS_BOTH && h->split)) return fn(h->models, h->tiles, h->n_tiles, s, 0);
+hipError_t per_model(cf_handle* h, hipStream_t s, int split, F&& fn) {
+    if (!(h->models == MS_BOTH && split)) return fn(h->models, h->tiles, h->n_tiles, s, 0);
     hipError_t e;
     const int n_fp = h->n_tiles_fp, n_id = h->n_tiles - h->n_tiles_fp;
     if ((e = hipEventRecord(h->ev_fork, s)) != hipSuccess) return e;
@@ -632,7 +632,7 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
     if (plain) {
         const int mode = h->mode == LM_LANE ? LM_LANE : LM_TILE;
         const StepArgs a = step_args(h, state, cmd, 1, nf);
-        e = per_model(h, s, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
+        e = per_model(h, s, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
             KernelSel ks = selection(h, mode, h->tile);
             ks.models = models;
             hipError_t r = hipSuccess;
@@ -649,7 +649,7 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
                            0u);
         if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
     }
-    e = per_model(h, s, [&](int models, const int4* tiles, int nt, hipStream_t st, int slot) {
+    e = per_model(h, s, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int slot) {
         KernelSel ks = selection(h, h->use_wq ? LM_WQ : h->mode, h->tile);
         ks.models = models;
         int blocks = 0;
@@ -798,7 +798,7 @@ cf_status cf_rollout(cf_handle* h, const float* x0, const float* cmds, int32_t T
     if (h->D > 0) {
         const int mode = roll_mode(h);
         if (mode == LM_TILE && (e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
-        e = per_model(h, h->stream, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
+        e = per_model(h, h->stream, 0, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
             KernelSel ks = selection(h, mode, mode == LM_LANE ? 64 : h->tile);
             ks.models = models;
             return launch_rollout_fwd(ks, a, tiles, nt, st);
@@ -860,7 +860,7 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
     if (h->D > 0) {
         const int mode = roll_mode(h);
         if (mode == LM_TILE && (e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
-        e = per_model(h, h->stream, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
+        e = per_model(h, h->stream, 0, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
             KernelSel ks = selection(h, mode, mode == LM_LANE ? 64 : h->tile);
             ks.models = models;
             return launch_rollout_bwd(ks, a, tiles, nt, st);

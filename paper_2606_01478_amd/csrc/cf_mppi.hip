@@ -186,89 +186,170 @@ __global__ __launch_bounds__(MPPI_SELECT_THREADS) void k_mppi_select(MppiArgs a)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const float* J = a.cost + (size_t)c * a.N;
-    auto key_of = [&](int k) -> uint64_t { return ((uint64_t)ordered_bits(J[k]) << 32) | (uint32_t)k; };
+    // visit every sample's key; loads are issued UNR at a time so their
+    // latencies overlap (one workgroup per controller has few waves to hide them)
+    constexpr int UNR = 8;
+    auto for_each_key = [&](auto&& fn) {
+        for (int64_t k0 = tid; k0 < a.N; k0 += BS * UNR) {
+            float v[UNR];
+#pragma unroll
+            for (int j = 0; j < UNR; ++j) {
+                const int64_t k = k0 + j * BS;
+                v[j] = k < a.N ? J[k] : 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < UNR; ++j) {
+                const int64_t k = k0 + j * BS;
+                if (k < a.N) fn(((uint64_t)ordered_bits(v[j]) << 32) | (uint32_t)k);
+            }
+        }
+    };
 
-    // radix select of the n_e-th smallest key, 8 bits per pass from the top;
-    // stops once every key left in the chosen bucket is taken
-    if (tid == 0) {
-        s_prefix = 0;
-        s_mask = 0;
-        s_need = a.n_e;
-    }
-    __syncthreads();
-    for (int pass = 0; pass < 8; ++pass) {
-        const int sh = 56 - 8 * pass;
-        if (tid < 256) hist[tid] = 0;
-        __syncthreads();
-        const uint64_t prefix = s_prefix, mask = s_mask;
-        for (int k = tid; k < a.N; k += BS) {
-            const uint64_t key = key_of(k);
-            if ((key & mask) == prefix) atomicAdd(&hist[(key >> sh) & 255u], 1u);
-        }
-        __syncthreads();
-        if (wave == 0) {
-            const int need = s_need;
-            const unsigned h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
-                           h3 = hist[4 * lane + 3];
-            const unsigned tot = h0 + h1 + h2 + h3;
-            unsigned incl = tot;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const unsigned v = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += v;
-            }
-            const unsigned excl = incl - tot;
-            const bool here = excl < (unsigned)need && (unsigned)need <= incl;
-            if (here) {
-                unsigned cum = excl;
-                const unsigned hh[4] = {h0, h1, h2, h3};
-                int dig = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (cum + hh[j] >= (unsigned)need) {
-                        dig = 4 * lane + j;
-                        s_need = need - (int)cum;
-                        s_eq = (int)hh[j];
-                        break;
+    // ascending bitonic sort of keys[0, P2), P2 a power of two (all threads)
+    auto bitonic = [&](int P2) {
+        for (int size = 2; size <= P2; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int i = tid; i < P2 / 2; i += BS) {
+                    const int lo = 2 * i - (i & (stride - 1));
+                    const int hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const uint64_t x = keys[lo], y = keys[hi];
+                    if ((x > y) == up) {
+                        keys[lo] = y;
+                        keys[hi] = x;
                     }
-                    cum += hh[j];
                 }
-                s_prefix = prefix | ((uint64_t)dig << sh);
-                s_mask = mask | (255ull << sh);
+                __syncthreads();
+            }
+        }
+    };
+
+    // Common case: a threshold key just above the n_e-th smallest, taken from a
+    // sorted sample of the keys; one pass collects every key at or below it
+    // (one LDS atomic per wave) and the candidates are sorted. The radix select
+    // below is the fallback when the candidates are too few or too many.
+    bool selected = false;
+    if (2 * a.n_e <= MPPI_MAX_ELITE) {
+        constexpr int SAMPLE = 2048;
+        const int ns = (int)(a.N < SAMPLE ? a.N : SAMPLE);
+        int P2s = 1;
+        while (P2s < ns) P2s <<= 1;
+        for (int i = tid; i < P2s; i += BS) {
+            uint64_t key = ~0ull;
+            if (i < ns) {
+                const int64_t k = (int64_t)i * a.N / ns;
+                key = ((uint64_t)ordered_bits(J[k]) << 32) | (uint32_t)k;
+            }
+            keys[i] = key;
+        }
+        __syncthreads();
+        bitonic(P2s);
+        int r = (ns == a.N) ? a.n_e - 1
+                            : (int)ceilf((float)ns * (float)a.n_e / (float)a.N * 1.25f) + 8;
+        r = r < ns - 1 ? r : ns - 1;
+        const uint64_t tau = keys[r];
+        if (tid == 0) s_count = 0;
+        __syncthreads();   // tau read everywhere before keys[] is reused
+        for (int64_t k0 = 0; k0 < a.N; k0 += (int64_t)BS * UNR) {
+            float v[UNR];
+#pragma unroll
+            for (int j = 0; j < UNR; ++j) {
+                const int64_t k = k0 + j * BS + tid;
+                v[j] = k < a.N ? J[k] : 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < UNR; ++j) {
+                const int64_t k = k0 + j * BS + tid;
+                const uint64_t key = ((uint64_t)ordered_bits(v[j]) << 32) | (uint32_t)k;
+                const bool f = (k < a.N) && key <= tau;
+                const uint64_t m = __ballot(f);
+                const int nw = __popcll(m);
+                int base = 0;
+                if (lane == 0 && nw) base = atomicAdd(&s_count, nw);
+                base = __shfl(base, 0, 64);
+                const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+                if (f && pos < MPPI_MAX_ELITE) keys[pos] = key;
             }
         }
         __syncthreads();
-        if (s_eq == s_need) break;
-    }
-    // collect the n_e keys with (key & mask) <= prefix, then sort them
-    const uint64_t prefix = s_prefix, mask = s_mask;
-    int P2 = 1;
-    while (P2 < a.n_e) P2 <<= 1;
-    for (int i = tid; i < P2; i += BS) keys[i] = ~0ull;
-    if (tid == 0) s_count = 0;
-    __syncthreads();
-    for (int k = tid; k < a.N; k += BS) {
-        const uint64_t key = key_of(k);
-        if ((key & mask) <= prefix) {
-            const int pos = atomicAdd(&s_count, 1);
-            if (pos < a.n_e) keys[pos] = key;
+        const int cnt = s_count;
+        if (cnt >= a.n_e && cnt <= MPPI_MAX_ELITE) {
+            int P2 = 1;
+            while (P2 < cnt) P2 <<= 1;
+            for (int i = cnt + tid; i < P2; i += BS) keys[i] = ~0ull;
+            __syncthreads();
+            bitonic(P2);
+            selected = true;
         }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int size = 2; size <= P2; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = tid; i < P2 / 2; i += BS) {
-                const int lo = 2 * i - (i & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const uint64_t x = keys[lo], y = keys[hi];
-                if ((x > y) == up) {
-                    keys[lo] = y;
-                    keys[hi] = x;
+    if (!selected) {
+        // radix select of the n_e-th smallest key, 8 bits per pass from the top;
+        // stops once every key left in the chosen bucket is taken
+        if (tid == 0) {
+            s_prefix = 0;
+            s_mask = 0;
+            s_need = a.n_e;
+        }
+        __syncthreads();
+        for (int pass = 0; pass < 8; ++pass) {
+            const int sh = 56 - 8 * pass;
+            if (tid < 256) hist[tid] = 0;
+            __syncthreads();
+            const uint64_t prefix = s_prefix, mask = s_mask;
+            for_each_key([&](uint64_t key) {
+                if ((key & mask) == prefix) atomicAdd(&hist[(key >> sh) & 255u], 1u);
+            });
+            __syncthreads();
+            if (wave == 0) {
+                const int need = s_need;
+                const unsigned h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
+                               h3 = hist[4 * lane + 3];
+                const unsigned tot = h0 + h1 + h2 + h3;
+                unsigned incl = tot;
+    #pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const unsigned v = __shfl_up(incl, off, 64);
+                    if (lane >= off) incl += v;
+                }
+                const unsigned excl = incl - tot;
+                const bool here = excl < (unsigned)need && (unsigned)need <= incl;
+                if (here) {
+                    unsigned cum = excl;
+                    const unsigned hh[4] = {h0, h1, h2, h3};
+                    int dig = 0;
+    #pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (cum + hh[j] >= (unsigned)need) {
+                            dig = 4 * lane + j;
+                            s_need = need - (int)cum;
+                            s_eq = (int)hh[j];
+                            break;
+                        }
+                        cum += hh[j];
+                    }
+                    s_prefix = prefix | ((uint64_t)dig << sh);
+                    s_mask = mask | (255ull << sh);
                 }
             }
             __syncthreads();
+            if (s_eq == s_need) break;
         }
+        // collect the n_e keys with (key & mask) <= prefix, then sort them
+        const uint64_t prefix = s_prefix, mask = s_mask;
+        int P2 = 1;
+        while (P2 < a.n_e) P2 <<= 1;
+        for (int i = tid; i < P2; i += BS) keys[i] = ~0ull;
+        if (tid == 0) s_count = 0;
+        __syncthreads();
+        for_each_key([&](uint64_t key) {
+            if ((key & mask) <= prefix) {
+                const int pos = atomicAdd(&s_count, 1);
+                if (pos < a.n_e) keys[pos] = key;
+            }
+        });
+        __syncthreads();
+        bitonic(P2);
     }
     // weights exp(-(J - J_min) / lambda)
     const float jmin = from_ordered((uint32_t)(keys[0] >> 32));

@@ -184,11 +184,8 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
 
 // ---------------------------------------------------------------------------
 // adjoint of one drone's rollout
-// gacc: this lane's 52 gain-gradient accumulators in LDS, stride `gstride`
-// (one writer per slot, so the sums keep a fixed order)
 template <int MODEL, int CTRL, int INTEG, bool AERO, class R>
-__device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
-                                                  float* gacc, int gstride) {
+__device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
     constexpr int S = ModelTraits<MODEL, CTRL>::S;
     const size_t D = (size_t)a.D;
     const size_t SD = (size_t)S_h * D;
@@ -206,10 +203,9 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
     float lam[S];
 #pragma unroll
     for (int i = 0; i < S; ++i) lam[i] = 0.f;
-    if (G) {
+    float gG[NG];   // this drone's gain-gradient contributions, summed in step order
 #pragma unroll
-        for (int i = 0; i < NG; ++i) gacc[i * gstride] = 0.f;
-    }
+    for (int i = 0; i < NG; ++i) gG[i] = 0.f;
     const int nseg = (a.T + a.K - 1) / a.K;
     for (int s = nseg - 1; s >= 0; --s) {
         const int t0 = s * a.K;
@@ -279,7 +275,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
 #pragma unroll
-                    for (int j = 0; j < 13; ++j) atomicAdd(gacc + (i * 13 + j) * gstride, ub[i] * ev[j]);
+                    for (int j = 0; j < 13; ++j) gG[i * 13 + j] += ub[i] * ev[j];
                 }
             }
 #pragma unroll
@@ -297,7 +293,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
     if (a.ggc) {
         if (G) {
 #pragma unroll
-            for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = gacc[i * gstride];
+            for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = gG[i];
         } else {
 #pragma unroll
             for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = 0.f;
@@ -311,10 +307,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 template <bool BWD, int MODEL, int CTRL, int INTEG, bool AERO, class R>
 __device__ __forceinline__ void rollout_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
     if constexpr (BWD) {
-        // dynamic LDS: [52][blockDim] gain accumulators
-        extern __shared__ float bwd_lds[];
-        float* gacc = bwd_lds + threadIdx.x;
-        rollout_bwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h, gacc, (int)blockDim.x);
+        rollout_bwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
     } else {
         rollout_fwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
     }
@@ -354,8 +347,7 @@ template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
 static hipError_t launch_roll_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                 hipStream_t s) {
     const int S_h = a.S_h;
-    // adjoint LDS per lane: the gain-gradient accumulators
-    const size_t shmem = BWD ? (size_t)NG * ks.tile * sizeof(float) : 0;
+    const size_t shmem = 0;
     if (ks.mode == LM_LANE) {
         if constexpr (MODELS != MS_BOTH) {
             const int bs = ks.tile;

@@ -164,3 +164,17 @@ def test_rejects_invalid_arguments(gpu_lib):
                               None, None)
     assert st == B.CF_EINVAL
     assert sim.last_error() == 0
+
+
+@pytest.mark.parametrize("N,n_e,sigma0", [(8000, 3000, False), (5000, 40, True), (3000, 1500, False)])
+def test_selection_paths(gpu_lib, N, n_e, sigma0):
+    """Both selection paths (sampled threshold for n_e <= 2048, radix select above)
+    pick exactly the oracle's elites from the device's costs, also with ties."""
+    over = dict(n_elite=n_e)
+    if sigma0:
+        over["sigma"] = [0.0] * 4
+    w, P, mean0, sim, mp = _make(C=2, N=N, H=6, **over)
+    got = _run(w, P, mp, _jittered_mean(mean0, 7), 1, 3)
+    Jd = got["cost"].astype(np.float64)
+    assert np.array_equal(got["el"], OM.select_elites(Jd, n_e))
+    assert np.array_equal(got["cmin"].astype(np.float64), Jd[np.arange(2), got["el"][:, 0]])
