@@ -798,7 +798,7 @@ cf_status cf_rollout(cf_handle* h, const float* x0, const float* cmds, int32_t T
     if (h->D > 0) {
         const int mode = roll_mode(h);
         if (mode == LM_TILE && (e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
-        e = per_model(h, h->stream, 0, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
+        e = per_model(h, h->stream, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
             KernelSel ks = selection(h, mode, mode == LM_LANE ? 64 : h->tile);
             ks.models = models;
             return launch_rollout_fwd(ks, a, tiles, nt, st);
@@ -860,7 +860,7 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
     if (h->D > 0) {
         const int mode = roll_mode(h);
         if (mode == LM_TILE && (e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
-        e = per_model(h, h->stream, 0, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
+        e = per_model(h, h->stream, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
             KernelSel ks = selection(h, mode, mode == LM_LANE ? 64 : h->tile);
             ks.models = models;
             return launch_rollout_bwd(ks, a, tiles, nt, st);

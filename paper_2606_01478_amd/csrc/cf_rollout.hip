@@ -304,6 +304,12 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 // ---------------------------------------------------------------------------
 // kernels
 
+// A rollout is one long sequential chain per drone, usually with fewer waves
+// than SIMDs; when it shares the GPU with wide work (the held step of other
+// worlds) its waves take the highest issue priority on their SIMD so the
+// chain is not stretched, and the wide work fills the remaining issue slots.
+__device__ __forceinline__ void rollout_priority() { __builtin_amdgcn_s_setprio(3); }
+
 template <bool BWD, int MODEL, int CTRL, int INTEG, bool AERO, class R>
 __device__ __forceinline__ void rollout_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
     if constexpr (BWD) {
@@ -315,6 +321,7 @@ __device__ __forceinline__ void rollout_drone(const R& rec, const RollArgs& a, s
 
 template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
 __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
+    rollout_priority();
     const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= (size_t)a.D) return;
     const int w = a.drone_world[d];
@@ -325,6 +332,7 @@ __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
 
 template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
 __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __restrict__ tiles, int S_h) {
+    rollout_priority();
     const int4 td = tiles[blockIdx.x];
     const int w = __builtin_amdgcn_readfirstlane(td.x);
     const int d0 = __builtin_amdgcn_readfirstlane(td.y);
