@@ -154,7 +154,7 @@ def main():
     side = torch.cuda.Stream(device=dev)   # default priority
 
     def one_step(record=None):
-        e = [ev() for _ in range(6)]
+        e = [ev() for _ in range(7)]
         main = torch.cuda.current_stream()
         e[0].record(main)
         if args.serial:
@@ -182,6 +182,7 @@ def main():
             sim.step_k(state, cmd, T)
             e[5].record(main)
             main.wait_event(e[4])
+        e[6].record(main)
         if record is not None:
             record.append(e)
 
@@ -206,6 +207,8 @@ def main():
         ph = np.array([[r[0].elapsed_time(r[1]), r[1].elapsed_time(r[5]), r[2].elapsed_time(r[3]),
                         r[3].elapsed_time(r[4])] for r in recs])
     step_ms = wall * 1e3 / args.steps
+    # per-step job time from the events (first to last event of each step)
+    job = np.array([r[0].elapsed_time(r[6]) for r in recs])
     fwd_ms = float(ph[:, 1].mean())
     rf_ms, rb_ms = float(ph[:, 2].mean()), float(ph[:, 3].mean())
 
@@ -228,6 +231,8 @@ def main():
                    "launch": cfg, "adjoint_overlapped": not args.serial},
         "fwd_drone_steps_per_s": D * T / (fwd_ms * 1e-3),
         "fwdbwd_drone_steps_per_s": Ds * T / ((rf_ms + rb_ms) * 1e-3),
+        "step_ms_stats": {"mean": float(job.mean()), "std": float(job.std()), "median": float(np.median(job)),
+                          "min": float(job.min()), "max": float(job.max()), "n": int(len(job))},
         "phase_ms": {"reset": float(ph[:, 0].mean()), "forward": fwd_ms, "rollout_fwd": rf_ms,
                      "rollout_bwd": rb_ms, "forward_std": float(ph[:, 1].std())},
         "standalone_ms": standalone,
@@ -428,7 +433,16 @@ def cpu_baseline(w, seconds):
             x = b.step(x, u)
             n += 1
     el = time.perf_counter() - t0
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": sub.n_drones_total * n / el, "unit": "drone-steps/s", "cores": threads, "kind": "oracle",
+            "host": {"cpu_model": cpu_model, "logical_cpus": os.cpu_count()},
             "sample": f"worlds 0,16,32,... ({len(pick)} worlds, {sub.n_drones_total} drones), {n} steps, "
                       f"FP64 PyTorch CPU, {el:.1f} s"}
 
