@@ -189,6 +189,44 @@ __device__ __forceinline__ void sincos3(const float* a, float* s, float* c) {
     }
 }
 
+// Euler-angle trigonometry of RK4 stage states. A stage's angles differ from
+// the step's start angles a0 by a small offset d (h/2 or h times a stage
+// rate), so sin and cos follow from those at a0 by the angle-addition
+// formulas with short series for sin d and cos d - 1 (|d| <= 1/16: the
+// truncation is below 1e-12); a larger offset anywhere in the wave takes
+// sincos3. Stage 1 (d = 0) returns the start values exactly.
+struct EulerBase {
+    float a0[3], s0[3], c0[3];
+};
+
+__device__ __forceinline__ void euler_base(const float* a, EulerBase& b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) b.a0[i] = a[i];
+    sincos3(a, b.s0, b.c0);
+}
+
+__device__ __forceinline__ void sincos3_near(const float* a, const EulerBase& b, float* s, float* c) {
+    float d[3];
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        d[i] = a[i] - b.a0[i];
+        m = fmaxf(m, fabsf(d[i]));
+    }
+    if (m <= 0.0625f) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float d2 = d[i] * d[i];
+            const float sd = __builtin_fmaf(d[i] * d2, __builtin_fmaf(d2, 1.f / 120.f, -1.f / 6.f), d[i]);
+            const float cm1 = d2 * __builtin_fmaf(d2, __builtin_fmaf(d2, -1.f / 720.f, 1.f / 24.f), -0.5f);
+            s[i] = __builtin_fmaf(b.s0[i], cm1, __builtin_fmaf(b.c0[i], sd, b.s0[i]));
+            c[i] = __builtin_fmaf(b.c0[i], cm1, __builtin_fmaf(-b.s0[i], sd, b.c0[i]));
+        }
+    } else {
+        sincos3(a, s, c);
+    }
+}
+
 // hardware square root and reciprocal square root (within 1 ulp on gfx950)
 __device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float rsqrt_hw(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -386,9 +424,10 @@ __device__ __forceinline__ void fp_rates_vjp(const float* x, const float* rc, co
 
 // ---------------------------------------------------------------------------
 // identified model right-hand side, 13 components [p Psi v dPsi f]
-__device__ __forceinline__ void id_rates(const float* x, const float* u, const IdParams& P, float* xd) {
+__device__ __forceinline__ void id_rates(const float* x, const float* u, const IdParams& P, const EulerBase& B,
+                                         float* xd) {
     float sn[3], cs[3];
-    sincos3(x + 3, sn, cs);
+    sincos3_near(x + 3, B, sn, cs);
     const float sph = sn[0], cph = cs[0], sth = sn[1], cth = cs[1], sps = sn[2], cps = cs[2];
     const float a = P.cf_m * (P.direct ? u[3] : x[12]);
     xd[0] = x[6]; xd[1] = x[7]; xd[2] = x[8];
@@ -406,10 +445,10 @@ __device__ __forceinline__ void id_rates(const float* x, const float* u, const I
     xd[12] = P.ctau * (u[3] - x[12]);
 }
 
-__device__ __forceinline__ void id_rates_vjp(const float* x, const float* u, const IdParams& P,
+__device__ __forceinline__ void id_rates_vjp(const float* x, const float* u, const IdParams& P, const EulerBase& B,
                                              const float* gb, float* xb, float* ub) {
     float sn[3], cs[3];
-    sincos3(x + 3, sn, cs);
+    sincos3_near(x + 3, B, sn, cs);
     const float sph = sn[0], cph = cs[0], sth = sn[1], cth = cs[1], sps = sn[2], cps = cs[2];
     const float a = P.cf_m * (P.direct ? u[3] : x[12]);
     const float rz0 = cps * sth * cph + sps * sph;
@@ -816,7 +855,9 @@ __device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, c
 
 template <int INTEG>
 __device__ __forceinline__ void id_step(float* x, float* comp, const float* u, const IdParams& P, float dt) {
-    integrate<S_ID, INTEG, COMP_ID>(x, comp, dt, [&](const float* xi, float* xd) { id_rates(xi, u, P, xd); });
+    EulerBase B;
+    euler_base(x + 3, B);
+    integrate<S_ID, INTEG, COMP_ID>(x, comp, dt, [&](const float* xi, float* xd) { id_rates(xi, u, P, B, xd); });
     if (P.direct) x[12] = u[3];  // the thrust row holds the applied thrust
 }
 
@@ -882,10 +923,12 @@ __device__ __forceinline__ void id_step_vjp(const float* x, const float* u, cons
         ub[3] += ym[12];
         ym[12] = 0.f;
     }
+    EulerBase B;
+    euler_base(x + 3, B);
     integrate_vjp<S_ID, INTEG, false>(
         x, dt, ym, xb,
-        [&](const float* xi, float* xd) { id_rates(xi, u, P, xd); },
-        [&](const float* xi, const float* gb, float* xa) { id_rates_vjp(xi, u, P, gb, xa, ub); },
+        [&](const float* xi, float* xd) { id_rates(xi, u, P, B, xd); },
+        [&](const float* xi, const float* gb, float* xa) { id_rates_vjp(xi, u, P, B, gb, xa, ub); },
         [](const float*, float*) {});
 }
 
