@@ -39,8 +39,10 @@ SPEC_HBM_GBS = 8000.0
 # 256 MiB device copy gives), recorded in
 # profiles/k_step_tile_uneven_mixed_2048w_T1000.md; valid only for the kernel
 # sources it was measured on (SHA-256 below), reported as null otherwise.
-PROFILED_TRAFFIC = {"sources_sha256": "2c08b40cc11119eac640979451237c20e7f98a27703f156736d1e87e918c24d7",
-                    "bytes_per_launch": 220.5e6}
+# HBM bytes (FETCH_SIZE + WRITE_SIZE, copy-probe scaled) of one held-step phase, by
+# launch configuration "workqueue,tile,chunk,per_model", measured with rocprofv3 on
+# the kernel sources whose hash is given (summary under profiles/)
+PROFILED_TRAFFIC = {"sources_sha256": "", "by_launch": {}}
 
 
 def kernel_sources_sha256() -> str:
@@ -238,7 +240,9 @@ def main():
         "standalone_ms": standalone,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": SPEC_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / SPEC_FP32_VECTOR_TFLOPS,
-                     "traffic": (PROFILED_TRAFFIC["bytes_per_launch"]
+                     "traffic": (PROFILED_TRAFFIC["by_launch"].get(
+                                     "%d,%d,%d,%d" % (cfg["workqueue"], cfg["tile"], cfg["chunk"],
+                                                      cfg["per_model_launches"]))
                                  if kernel_sources_sha256() == PROFILED_TRAFFIC["sources_sha256"] else None),
                      "algorithmic_bytes_per_launch": float(n_chunks * (n_fp * (2 * W.S_FP_PID * 4 + 16)
                                                                        + n_id * (2 * W.S_ID * 4 + 16))),
