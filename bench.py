@@ -46,10 +46,11 @@ PROFILED_TRAFFIC = {"sources_sha256": "", "by_launch": {}}
 
 
 def kernel_sources_sha256() -> str:
-    import glob
+    """Hash of the sources that make up the held-step kernels and their launch."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2606_01478_amd", "csrc", "*"))):
+    for name in ("cf_api.hip", "cf_device.hpp", "cf_internal.hpp", "cf_step.hip"):
+        f = os.path.join(ROOT, "paper_2606_01478_amd", "csrc", name)
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
@@ -292,6 +293,11 @@ def main():
         for h, _, _ in handles:
             h.close()
 
+    pk = measured_peaks(B, dev, ev)
+    out["peaks_measured"] = pk
+    out["roofline"]["frac_of_measured_fma_peak"] = out["roofline"]["achieved"] / pk["fp32_fma_tflops"]
+    out["roofline"]["frac_standalone_of_measured_fma_peak"] = (out["roofline"]["achieved_standalone"]
+                                                              / pk["fp32_fma_tflops"])
     if not args.no_grad_bench:
         out["gradient_benchmark"] = gradient_benchmark(B, W, dev, t2d, ev)
     if not args.no_mppi:
@@ -308,6 +314,42 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def measured_peaks(B, dev, ev):
+    """Achievable peaks on this device: FP32 FMA rate of the library's probe
+    (8 independent chains per lane, 8 waves per SIMD) and device-to-device copy
+    bandwidth of a 1 GiB buffer (read + write bytes)."""
+    import torch
+    n_blocks, iters = 256 * 8, 20000
+    out = torch.empty(n_blocks * 256, device=dev)
+    B.probe_fma(out, n_blocks, 100)
+    best = 1e30
+    for _ in range(5):
+        a, b = ev(), ev()
+        a.record()
+        B.probe_fma(out, n_blocks, iters)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    tflops = n_blocks * 256 * 16.0 * iters / (best * 1e-3) / 1e12
+    src = torch.empty(256 * 1024 * 1024, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    cb = 1e30
+    for _ in range(5):
+        a, b = ev(), ev()
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        cb = min(cb, a.elapsed_time(b))
+    gbs = 2 * src.numel() * 4 / (cb * 1e-3) / 1e9
+    del src, dst, out
+    return {"fp32_fma_tflops": tflops, "copy_gbs": gbs,
+            "fma_probe": f"{n_blocks} x 256 lanes, 8 chains x {iters} FMA, best of 5",
+            "copy": "1 GiB device-to-device, read + write bytes, best of 5"}
 
 
 def gradient_benchmark(B, W, dev, t2d, ev, reps=10):

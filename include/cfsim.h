@@ -341,6 +341,16 @@ cf_status cf_mppi_step(cf_mppi* m, const float* x_now, float* mean, int32_t shif
    `iteration`, device [C][N][H][4]; zero for sample 0. */
 cf_status cf_mppi_noise(cf_mppi* m, uint64_t iteration, float* eps);
 
+/* ---- measurement helper ----------------------------------------------------
+ * cf_probe_fma: launch n_blocks workgroups of 256 lanes, each lane running 8
+ * independent FP32 FMA chains of `iters` steps (16 * iters FLOP per lane), on
+ * `stream` (hipStream_t, NULL = default), writing one float per lane to the
+ * device buffer out [n_blocks * 256]. Timing it gives the achievable unpacked
+ * FP32 FMA rate that the simulation kernels' VALU roofline is compared with.
+ * Errors: CF_EINVAL (NULL or too-small out, n_blocks < 1, iters < 1), CF_EDEVICE.
+ */
+cf_status cf_probe_fma(float* out, int32_t n_blocks, int32_t iters, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

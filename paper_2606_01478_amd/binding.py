@@ -39,7 +39,7 @@ PARAM_OFFSETS = {
 
 EXPORTS = ("cf_create", "cf_destroy", "cf_state_dim", "cf_total_drones", "cf_world_offsets", "cf_set_stream",
            "cf_reset", "cf_step_k", "cf_rollout", "cf_rollout_backward", "cf_autotune", "cf_launch_config",
-           "cf_strerror", "cf_last_error", "cf_mppi_create", "cf_mppi_destroy", "cf_mppi_step", "cf_mppi_noise")
+           "cf_strerror", "cf_last_error", "cf_mppi_create", "cf_mppi_destroy", "cf_mppi_step", "cf_mppi_noise", "cf_probe_fma")
 
 MPPI_MAX_OBSTACLES = 16
 MPPI_MAX_ELITE = 4096
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "cf_mppi_destroy": ([H], c_int32),
         "cf_mppi_step": ([H, P, P, c_int32, ctypes.c_uint64, P, P, P, P, P], c_int32),
         "cf_mppi_noise": ([H, ctypes.c_uint64, P], c_int32),
+        "cf_probe_fma": ([P, c_int32, c_int32, c_void_p], c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -361,6 +362,14 @@ class RolloutLoss:
         if cls._cached is None:
             cls._cached = cls._fn()
         return cls._cached.apply(x0, cmds, gain, sim, T, ckpt_every, obj_kw or {})
+
+
+def probe_fma(out, n_blocks: int, iters: int) -> None:
+    """Launch the FP32 FMA throughput probe on the current stream (16 * iters FLOP
+    per lane, 256 lanes per block)."""
+    if out.numel() < n_blocks * 256 or str(out.dtype) != "torch.float32":
+        raise ValueError("out must hold n_blocks * 256 float32 values")
+    _check(load().cf_probe_fma(_ptr(out), int(n_blocks), int(iters), c_void_p(_stream())), "cf_probe_fma")
 
 
 class Mppi:

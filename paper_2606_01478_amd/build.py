@@ -16,7 +16,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["cf_api.hip", "cf_step.hip", "cf_rollout.hip", "cf_mppi.hip"]
+SOURCES = ["cf_api.hip", "cf_step.hip", "cf_rollout.hip", "cf_mppi.hip", "cf_probe.hip"]
 LIB = os.path.join(HERE, "libcfsim.so")
 ARCH = os.environ.get("CFSIM_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

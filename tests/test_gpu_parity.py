@@ -427,3 +427,19 @@ def test_position_interface_rollout_gradients(gpu_lib, aero):
     if aero:
         w = _with_aero(w)
     _check_against_oracle(w, _rollout_grads(w, 15))
+
+
+def test_fma_probe_closed_form(gpu_lib):
+    """The FMA throughput probe computes a <- a b + c on eight chains per lane;
+    after n steps a_n = b^n a_0 + c (1 - b^n) / (1 - b)."""
+    n_blocks, iters = 4, 200
+    out = torch.empty(n_blocks * 256, device="cuda")
+    B.probe_fma(out, n_blocks, iters)
+    torch.cuda.synchronize()
+    b, c = float(np.float32(0.9999999)), float(np.float32(1e-7))
+    lane = np.tile(np.arange(256), n_blocks)
+    a0 = np.float32(1e-3) * lane.astype(np.float32)
+    ref = sum(b ** iters * (a0.astype(np.float64) + k) + c * (1 - b ** iters) / (1 - b) for k in range(8))
+    assert np.allclose(out.cpu().numpy(), ref, rtol=3e-5, atol=1e-5)
+    with pytest.raises(B.CfError):
+        B.probe_fma(torch.empty(100, device="cuda"), n_blocks, iters)
