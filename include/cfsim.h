@@ -345,11 +345,14 @@ cf_status cf_mppi_noise(cf_mppi* m, uint64_t iteration, float* eps);
  * cf_probe_fma: launch n_blocks workgroups of 256 lanes, each lane running 8
  * independent FP32 FMA chains of `iters` steps (16 * iters FLOP per lane), on
  * `stream` (hipStream_t, NULL = default), writing one float per lane to the
- * device buffer out [n_blocks * 256]. Timing it gives the achievable unpacked
- * FP32 FMA rate that the simulation kernels' VALU roofline is compared with.
- * Errors: CF_EINVAL (NULL or too-small out, n_blocks < 1, iters < 1), CF_EDEVICE.
+ * device buffer out [n_blocks * 256]. form 0: a <- a b + c with b = 0.9999999,
+ * c = 1e-7 (three-operand FMA); form 1: a <- b c + a with b = 1e-3, c = 1e-4
+ * (two-operand accumulate form). Timing it gives the achievable unpacked FP32
+ * FMA rate that the simulation kernels' VALU roofline is compared with.
+ * Errors: CF_EINVAL (NULL or too-small out, n_blocks < 1, iters < 1, form not
+ * 0 or 1), CF_EDEVICE.
  */
-cf_status cf_probe_fma(float* out, int32_t n_blocks, int32_t iters, void* stream);
+cf_status cf_probe_fma(float* out, int32_t n_blocks, int32_t iters, int32_t form, void* stream);
 
 #ifdef __cplusplus
 }

@@ -105,7 +105,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "cf_mppi_destroy": ([H], c_int32),
         "cf_mppi_step": ([H, P, P, c_int32, ctypes.c_uint64, P, P, P, P, P], c_int32),
         "cf_mppi_noise": ([H, ctypes.c_uint64, P], c_int32),
-        "cf_probe_fma": ([P, c_int32, c_int32, c_void_p], c_int32),
+        "cf_probe_fma": ([P, c_int32, c_int32, c_int32, c_void_p], c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -364,12 +364,13 @@ class RolloutLoss:
         return cls._cached.apply(x0, cmds, gain, sim, T, ckpt_every, obj_kw or {})
 
 
-def probe_fma(out, n_blocks: int, iters: int) -> None:
+def probe_fma(out, n_blocks: int, iters: int, form: int = 0) -> None:
     """Launch the FP32 FMA throughput probe on the current stream (16 * iters FLOP
-    per lane, 256 lanes per block)."""
+    per lane, 256 lanes per block; form 0 three-operand, 1 accumulate form)."""
     if out.numel() < n_blocks * 256 or str(out.dtype) != "torch.float32":
         raise ValueError("out must hold n_blocks * 256 float32 values")
-    _check(load().cf_probe_fma(_ptr(out), int(n_blocks), int(iters), c_void_p(_stream())), "cf_probe_fma")
+    _check(load().cf_probe_fma(_ptr(out), int(n_blocks), int(iters), int(form), c_void_p(_stream())),
+           "cf_probe_fma")
 
 
 class Mppi:

@@ -441,5 +441,11 @@ def test_fma_probe_closed_form(gpu_lib):
     a0 = np.float32(1e-3) * lane.astype(np.float32)
     ref = sum(b ** iters * (a0.astype(np.float64) + k) + c * (1 - b ** iters) / (1 - b) for k in range(8))
     assert np.allclose(out.cpu().numpy(), ref, rtol=3e-5, atol=1e-5)
-    with pytest.raises(B.CfError):
+    with pytest.raises(ValueError):
         B.probe_fma(torch.empty(100, device="cuda"), n_blocks, iters)
+    # accumulate form: a_n = a_0 + n b c
+    B.probe_fma(out, n_blocks, iters, 1)
+    torch.cuda.synchronize()
+    bc = float(np.float32(1e-3)) * float(np.float32(1e-4))
+    ref1 = sum(a0.astype(np.float64) + k + iters * bc for k in range(8))
+    assert np.allclose(out.cpu().numpy(), ref1, rtol=3e-5, atol=1e-5)
