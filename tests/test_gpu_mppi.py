@@ -178,3 +178,17 @@ def test_selection_paths(gpu_lib, N, n_e, sigma0):
     Jd = got["cost"].astype(np.float64)
     assert np.array_equal(got["el"], OM.select_elites(Jd, n_e))
     assert np.array_equal(got["cmin"].astype(np.float64), Jd[np.arange(2), got["el"][:, 0]])
+
+
+def test_diverging_samples_count_as_infinite(gpu_lib):
+    """Samples whose rollout overflows get an infinite cost and never become
+    elites; the plan stays finite."""
+    w, P, mean0, sim, mp = _make(model=W.MODEL_ID, C=2, N=3000, H=8, n_elite=20,
+                                 sigma=[0.15, 0.15, 0.3, 3e37], u_hi=[0.6, 0.6, 3.2, 3.4e38])
+    got = _run(w, P, mp, mean0, 0, 4)
+    J = got["cost"]
+    assert np.isinf(J).any() and np.isfinite(J).any()
+    assert not np.isnan(J).any()
+    assert np.all(np.isfinite(J[np.arange(2)[:, None], got["el"]]))
+    assert np.array_equal(got["el"], OM.select_elites(J.astype(np.float64), 20))
+    assert np.all(np.isfinite(got["mean"]))

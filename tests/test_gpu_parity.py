@@ -449,3 +449,30 @@ def test_fma_probe_closed_form(gpu_lib):
     bc = float(np.float32(1e-3)) * float(np.float32(1e-4))
     ref1 = sum(a0.astype(np.float64) + k + iters * bc for k in range(8))
     assert np.allclose(out.cpu().numpy(), ref1, rtol=3e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("make", [lambda: W.fp_torque(seed=70, n_worlds=130, steps=40),
+                                  lambda: W.fp_position(seed=71, n_worlds=130, steps=40)])
+def test_interfaces_graph_replay_and_masked_reset(gpu_lib, make):
+    """Torque and position interfaces: graph replays equal the eager launches at
+    every replay, and a masked reset restores exactly the masked worlds."""
+    w = make()
+    eager = _sim(w)
+    graph = _sim(w, flags=B.F_GRAPH)
+    xe, xg, u = dev(w.x0), dev(w.x0), dev(w.cmds)
+    for r in range(3):
+        eager.step_k(xe, u, 13)
+        graph.step_k(xg, u, 13)
+        torch.cuda.synchronize()
+        _ = (xe * 2).sum().item()
+        assert torch.equal(xe, xg), r
+    init = dev(w.x0)
+    moved = xe.clone()
+    mask = torch.zeros(w.n_worlds, dtype=torch.uint8, device="cuda")
+    mask[[0, 5, 129]] = 1
+    eager.reset(xe, init, mask)
+    torch.cuda.synchronize()
+    keep = torch.ones(w.n_worlds, dtype=torch.bool)
+    keep[[0, 5, 129]] = False
+    assert torch.equal(xe[:, ~keep.cuda()], init[:, ~keep.cuda()])
+    assert torch.equal(xe[:, keep.cuda()], moved[:, keep.cuda()])
