@@ -478,14 +478,22 @@ def rollout_grad(batch: Batch, x0, cmds, steps, gain=None, gain_index=None, dlos
 
 # ---- convenience entry points on a workload --------------------------------------
 
-def simulate_held(w, steps: Optional[int] = None, x0=None) -> torch.Tensor:
-    """State after ``steps`` steps with the workload's held command ``[4, D]``."""
+def simulate_held(w, steps: Optional[int] = None, x0=None, store_every: Optional[int] = None) -> torch.Tensor:
+    """State after ``steps`` steps with the workload's held command ``[4, D]``.
+
+    ``store_every = k`` rounds the state to binary32 after every k steps: the
+    state a caller sees who keeps it in the public binary32 layout between
+    calls of k steps each (the steps themselves stay in fp64). This models the
+    storage format only, not any kernel's arithmetic."""
     b = Batch.from_workload(w)
     x = t64(w.x0 if x0 is None else x0)
     u = t64(w.cmds)
+    n = w.steps if steps is None else steps
     with torch.no_grad():
-        for _ in range(w.steps if steps is None else steps):
+        for i in range(n):
             x = b.step(x, u)
+            if store_every and (i + 1) % store_every == 0:
+                x = x.to(torch.float32).to(torch.float64)
     return x
 
 

@@ -14,6 +14,11 @@
 
 namespace cfk {
 
+// hardware square root, reciprocal square root and reciprocal (within 1 ulp on gfx950)
+__device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float rsqrt_hw(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // ---------------------------------------------------------------------------
 // parameter record offsets (public layout, see include/cfsim.h)
 enum : int {
@@ -49,6 +54,19 @@ struct FpParams {
     float jp, sg[4];          // propeller inertia, rotor spin directions (-sign of the yaw mixing)
     float cd[3];              // linear drag C_a diagonal
     bool gyro, drag;          // J_p != 0, C_a != 0
+    // Inside the kernels the four rotor rows hold W - W_r, the deviation from a
+    // reference speed W_r (the world's hover speed), and rotor commands are
+    // deviations too: near 15 000 an FP32 speed resolves 1e-3, its deviation
+    // resolves 1e-4 or better, and the body torques are differences of rotor
+    // thrusts. Thrust and drag torque are evaluated as differences from their
+    // values at W_r.
+    float wr;                 // W_r
+    float w2;                 // 2 W_r
+    float k1w, t1w;           // k1 + 2 k2 W_r, t1 + 2 t2 W_r
+    float fr, tr;             // thrust and drag torque of one rotor at W_r
+    float F4r, txr, tyr, tzr; // 4 fr, fr sum tx, fr sum ty, tr sum tz
+    float sgr;                // W_r sum sigma
+    float disc_r;             // discriminant of the thrust curve at fr: (k1 + 2 k2 W_r)^2
 };
 struct PidParams {
     float akp[2], aki[2], rkp[3], rki[3], rkd[3], jc[3], fmax;
@@ -100,7 +118,40 @@ __device__ __forceinline__ FpParams load_fp(const R& rec) {
         P.gyro = false;
         P.drag = false;
     }
+    // reference speed: hover (thrust m g / 4 per rotor) on the rising branch of
+    // the thrust curve, else its vertex; never negative, so that k1 + 2 k2 W_r >= 0
+    // (the allocation's cancellation-free root relies on it)
+    float wr = 0.f;
+    if (P.k2 > 0.f) {
+        const float fh = 0.25f * P.g / P.inv_m;
+        const float dh = P.k1 * P.k1 - 4.f * P.k2 * (P.k0 - fh);
+        wr = ((dh > 0.f ? sqrt_hw(dh) : 0.f) - P.k1) * P.inv_2k2;
+        wr = isfinite(wr) ? fmaxf(wr, 0.f) : 0.f;
+    }
+    P.wr = wr;
+    P.w2 = 2.f * wr;
+    P.k1w = wr > 0.f ? fmaxf(P.k1 + 2.f * P.k2 * wr, 0.f) : P.k1;
+    P.t1w = P.t1 + 2.f * P.t2 * wr;
+    P.fr = P.k0 + wr * (P.k1 + P.k2 * wr);
+    P.tr = P.t0 + wr * (P.t1 + P.t2 * wr);
+    P.F4r = 4.f * P.fr;
+    P.txr = P.fr * ((P.tx[0] + P.tx[1]) + (P.tx[2] + P.tx[3]));
+    P.tyr = P.fr * ((P.ty[0] + P.ty[1]) + (P.ty[2] + P.ty[3]));
+    P.tzr = P.tr * ((P.tz[0] + P.tz[1]) + (P.tz[2] + P.tz[3]));
+    P.sgr = wr * ((P.sg[0] + P.sg[1]) + (P.sg[2] + P.sg[3]));
+    P.disc_r = P.k1w * P.k1w;
     return P;
+}
+
+// rotor rows 13..16 between the absolute speeds of the public state layout and
+// the in-register deviations
+__device__ __forceinline__ void rotors_to_dev(float* x, const FpParams& P) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[13 + i] -= P.wr;
+}
+__device__ __forceinline__ void rotors_from_dev(float* x, const FpParams& P) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[13 + i] += P.wr;
 }
 
 template <class R>
@@ -227,11 +278,6 @@ __device__ __forceinline__ void sincos3_near(const float* a, const EulerBase& b,
     }
 }
 
-// hardware square root and reciprocal square root (within 1 ulp on gfx950)
-__device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ float rsqrt_hw(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
-
 // ---------------------------------------------------------------------------
 // rotation matrices (row-major 3x3) and the linear drag term R C_a R^T v / m
 
@@ -304,20 +350,23 @@ __device__ __forceinline__ void drag_acc_vjp(const float* R, const float* v, con
 __device__ __forceinline__ void fp_rates(const float* x, const float* rc, const FpParams& P, float* xd) {
     const float qx = x[3], qy = x[4], qz = x[5], qw = x[6];
     const float wx = x[10], wy = x[11], wz = x[12];
-    float F = 0.f, tx = 0.f, ty = 0.f, tz = 0.f;
+    // rotor rows and commands are deviations from W_r (see FpParams); the sums
+    // start from the wrench of four rotors at W_r
+    float F = P.F4r, tx = P.txr, ty = P.tyr, tz = P.tzr;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float r = x[13 + i];
-        const bool up = rc[i] >= r;          // accelerating branch (ties included)
+        const float e = rc[i] - r;            // W_cmd - W
+        const bool up = e >= 0.f;             // accelerating branch (ties included)
         const float cv = up ? P.cvu : P.cvd;
         const float cd = up ? P.cdu : P.cdd;
-        xd[13 + i] = cv * (rc[i] - r) + cd * (rc[i] * rc[i] - r * r);
-        const float f = P.k0 + r * (P.k1 + P.k2 * r);
-        const float tq = P.t0 + r * (P.t1 + P.t2 * r);
-        F += f;
-        tx += P.tx[i] * f;
-        ty += P.ty[i] * f;
-        tz += P.tz[i] * tq;
+        xd[13 + i] = e * (cv + cd * (P.w2 + rc[i] + r));   // c_v e + c_d (W_cmd^2 - W^2)
+        const float df = r * (P.k1w + P.k2 * r);           // f(W) - f(W_r)
+        const float dq = r * (P.t1w + P.t2 * r);
+        F += df;
+        tx += P.tx[i] * df;
+        ty += P.ty[i] * df;
+        tz += P.tz[i] * dq;
     }
     xd[0] = x[7]; xd[1] = x[8]; xd[2] = x[9];
     xd[3] = 0.5f * (qw * wx + qy * wz - qz * wy);
@@ -335,7 +384,7 @@ __device__ __forceinline__ void fp_rates(const float* x, const float* rc, const 
     }
     if (P.gyro) {
         // -w x h - h', h = J_p Omega_s e_z, Omega_s = sum sigma_i Omega_i
-        float om_s = 0.f, dom_s = 0.f;
+        float om_s = P.sgr, dom_s = 0.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             om_s += P.sg[i] * x[13 + i];
@@ -355,13 +404,11 @@ __device__ __forceinline__ void fp_rates_vjp(const float* x, const float* rc, co
                                              const float* gb, float* xb, float* rcb) {
     const float qx = x[3], qy = x[4], qz = x[5], qw = x[6];
     const float wx = x[10], wy = x[11], wz = x[12];
-    float F = 0.f;
-    float f[4];
+    float F = P.F4r;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float r = x[13 + i];
-        f[i] = P.k0 + r * (P.k1 + P.k2 * r);
-        F += f[i];
+        F += r * (P.k1w + P.k2 * r);
     }
     // p' = v
     xb[7] += gb[0]; xb[8] += gb[1]; xb[9] += gb[2];
@@ -398,7 +445,7 @@ __device__ __forceinline__ void fp_rates_vjp(const float* x, const float* rc, co
     xb[12] -= hx * P.dJx * wy + hy * P.dJy * wx;
     float om_sb = 0.f;
     if (P.gyro) {
-        float om_s = 0.f;
+        float om_s = P.sgr;
 #pragma unroll
         for (int i = 0; i < 4; ++i) om_s += P.sg[i] * x[13 + i];
         xb[11] -= P.jp * om_s * hx;
@@ -410,15 +457,16 @@ __device__ __forceinline__ void fp_rates_vjp(const float* x, const float* rc, co
         const float r = x[13 + i];
         const float fb = Fb + P.tx[i] * hx + P.ty[i] * hy;
         const float tqb = P.tz[i] * hz;
-        const bool up = rc[i] >= r;
+        const bool up = rc[i] - r >= 0.f;
         const float cv = up ? P.cvu : P.cvd;
         const float cd = up ? P.cdu : P.cdd;
         // adjoint of the rotor acceleration: the state derivative, plus the reaction torque
         const float gr = gb[13 + i] - (P.gyro ? P.jp * P.sg[i] * hz : 0.f);
         if (P.gyro) xb[13 + i] += P.sg[i] * om_sb;
-        xb[13 + i] += fb * (P.k1 + 2.f * P.k2 * r) + tqb * (P.t1 + 2.f * P.t2 * r)
-                      - gr * (cv + 2.f * cd * r);
-        rcb[i] += gr * (cv + 2.f * cd * rc[i]);
+        // df/dW = k1 + 2 k2 W = k1w + 2 k2 r, d(W^2)/dW = 2 W = w2 + 2 r
+        xb[13 + i] += fb * (P.k1w + 2.f * P.k2 * r) + tqb * (P.t1w + 2.f * P.t2 * r)
+                      - gr * (cv + cd * (P.w2 + 2.f * r));
+        rcb[i] += gr * (cv + cd * (P.w2 + 2.f * rc[i]));
     }
 }
 
@@ -487,35 +535,37 @@ __device__ __forceinline__ void id_rates_vjp(const float* x, const float* u, con
 // ---------------------------------------------------------------------------
 // cascaded attitude PID + allocation (project design; evaluated once per step)
 struct PidTrace {
-    float s1, c1, s2, fraw[4], disc[4];
+    float s1, c1, s2, disc[4];
+    bool pass[4];   // allocated thrust inside [0, f_max] on the rising branch
 };
-
-__device__ __forceinline__ float rotor_root(float f, float disc, const FpParams& P) {
-    return disc > 0.f ? (sqrt_hw(disc) - P.k1) * P.inv_2k2 : -P.k1 * P.inv_2k2;
-}
 
 // Motor allocation: f = alloc [T, tau_x, tau_y, tau_z], clamped to [0, f_max],
 // rotor-speed commands from the thrust curve. Also the torque interface.
+// Commands are deviations xi from W_r: f(W_r + xi) = f is
+// xi (k1 + 2 k2 W_r + k2 xi) = f - f_r, solved as
+// xi = 2 (f - f_r) / (sqrt(disc) + k1 + 2 k2 W_r), disc = (k1 + 2 k2 W_r)^2 + 4 k2 (f - f_r),
+// which has no cancellation; f - f_r is formed with the thrust term fused.
 __device__ __forceinline__ void allocate(const float* wrench, const FpParams& P, const PidParams& C, float* rc,
                                          PidTrace& tr) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const float fr = C.A[4 * j] * wrench[0] + C.A[4 * j + 1] * wrench[1] + C.A[4 * j + 2] * wrench[2] +
-                         C.A[4 * j + 3] * wrench[3];
-        tr.fraw[j] = fr;
-        const float f = fminf(fmaxf(fr, 0.f), C.fmax);
-        tr.disc[j] = P.k1 * P.k1 - 4.f * P.k2 * (P.k0 - f);
-        rc[j] = rotor_root(f, tr.disc[j], P);
+        const float dfr = fmaf(C.A[4 * j], wrench[0], -P.fr) +
+                          (C.A[4 * j + 1] * wrench[1] + C.A[4 * j + 2] * wrench[2] + C.A[4 * j + 3] * wrench[3]);
+        const float lo = -P.fr, hi = C.fmax - P.fr;
+        const float df = fminf(fmaxf(dfr, lo), hi);
+        const float disc = fmaf(4.f * P.k2, df, P.disc_r);
+        tr.disc[j] = disc;
+        tr.pass[j] = (dfr >= lo) && (dfr <= hi) && (disc > 0.f);
+        // disc <= 0: below the curve's minimum, command its vertex
+        rc[j] = disc > 0.f ? 2.f * df * rcp_hw(sqrt_hw(disc) + P.k1w) : -P.k1w * P.inv_2k2;
     }
 }
 
-// VJP of allocate: wb += (d rc / d wrench)^T rcb
+// VJP of allocate: wb += (d rc / d wrench)^T rcb, with d xi / d f = 1 / sqrt(disc)
 __device__ __forceinline__ void allocate_vjp(const PidParams& C, const PidTrace& tr, const float* rcb, float* wb) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const float fr = tr.fraw[j];
-        const bool pass = (fr >= 0.f) && (fr <= C.fmax) && (tr.disc[j] > 0.f);
-        const float fb = pass ? rcb[j] * rsqrt_hw(tr.disc[j]) : 0.f;
+        const float fb = tr.pass[j] ? rcb[j] * rsqrt_hw(tr.disc[j]) : 0.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) wb[i] += C.A[4 * j + i] * fb;
     }
@@ -839,7 +889,7 @@ __device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, c
         pos_forward(x, u, P, C, rc, tr, pt);
     } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) rc[i] = u[i];
+        for (int i = 0; i < 4; ++i) rc[i] = u[i] - P.wr;
     }
     integrate<S_FP, INTEG, COMP_FP>(x, comp, dt, [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
     if (renorm) {
@@ -878,7 +928,7 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
         pos_forward(x, u, P, C, rc, tr, pt);
     } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) rc[i] = u[i];
+        for (int i = 0; i < 4; ++i) rc[i] = u[i] - P.wr;
     }
     float rcb[4] = {0.f, 0.f, 0.f, 0.f};
     const auto rates = [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); };

@@ -112,6 +112,7 @@ __global__ __launch_bounds__(256) void k_mppi_rollout(MppiArgs a) {
     if constexpr (MODEL == MODEL_FP) {
         P = load_fp<AERO>(rec);
         if constexpr (CTRL != CTRL_ROTOR) Cp = load_pid(rec, CTRL == CTRL_POSITION);
+        rotors_to_dev(x, P);
     } else {
         Pi = load_id<AERO>(rec);
     }

@@ -129,6 +129,26 @@ __device__ __forceinline__ void load_rows(const float* src, size_t D, size_t d, 
     for (int i = 0; i < N; ++i) x[i] = src[i * D + d];
 }
 
+// states in caller-visible buffers (x0, checkpoints, trajectory, x_T) hold
+// absolute rotor speeds; in registers and in the backward's segment buffer a
+// first-principles drone holds their deviations from its reference speed
+template <int MODEL>
+__device__ __forceinline__ void to_dev(float* x, const DroneParams& p) {
+    if constexpr (MODEL == MODEL_FP) rotors_to_dev(x, p.fp);
+}
+template <int MODEL, int N>
+__device__ __forceinline__ void store_state(float* dst, size_t D, size_t d, const float* x, const DroneParams& p) {
+    if constexpr (MODEL == MODEL_FP) {
+        float y[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) y[i] = x[i];
+        rotors_from_dev(y, p.fp);
+        store_rows<N>(dst, D, d, y);
+    } else {
+        store_rows<N>(dst, D, d, x);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // forward rollout of one drone
 template <int MODEL, int CTRL, int INTEG, bool AERO, class R>
@@ -141,6 +161,7 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
     const float f_hover = (MODEL == MODEL_ID) ? p.id.f_hover : 0.f;
     float x[S], comp[S];
     load_rows<S>(a.x0, D, d, x);
+    to_dev<MODEL>(x, p);
 #pragma unroll
     for (int i = 0; i < S; ++i) comp[i] = 0.f;
     float off[3] = {0.f, 0.f, 0.f};
@@ -149,8 +170,8 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
         for (int j = 0; j < 3; ++j) off[j] = a.ref_off[j * D + d];
     }
     const float* G = (a.has_obj && a.gain) ? a.gain + (size_t)a.gidx[w] * NG : nullptr;
-    if (a.ckpt) store_rows<S>(a.ckpt, D, d, x);
-    if (a.traj) store_rows<S>(a.traj, D, d, x);
+    if (a.ckpt) store_state<MODEL, S>(a.ckpt, D, d, x, p);
+    if (a.traj) store_state<MODEL, S>(a.traj, D, d, x, p);
     float loss = 0.f;
     float ubar[4];
     load_cmd(a, 0, d, ubar);
@@ -167,12 +188,12 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
             loss += e0 * e0 + e1 * e1 + e2 * e2;
         }
         const int tn = t + 1;
-        if (a.ckpt && tn < a.T && (tn % a.K) == 0) store_rows<S>(a.ckpt + (size_t)(tn / a.K) * SD, D, d, x);
-        if (a.traj) store_rows<S>(a.traj + (size_t)tn * SD, D, d, x);
+        if (a.ckpt && tn < a.T && (tn % a.K) == 0) store_state<MODEL, S>(a.ckpt + (size_t)(tn / a.K) * SD, D, d, x, p);
+        if (a.traj) store_state<MODEL, S>(a.traj + (size_t)tn * SD, D, d, x, p);
 #pragma unroll
         for (int i = 0; i < 4; ++i) ubar[i] = unext[i];
     }
-    if (a.xT) store_rows<S>(a.xT, D, d, x);
+    if (a.xT) store_state<MODEL, S>(a.xT, D, d, x, p);
     if (a.loss) a.loss[d] = loss;
     if (a.nonfinite) {
         bool bad = false;
@@ -215,6 +236,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
         // (only its position is needed); the last segment steps once more.
         float x[S], comp[S];
         load_rows<S>(a.ckpt_in + (size_t)s * SD, D, d, x);
+        to_dev<MODEL>(x, p);
 #pragma unroll
         for (int i = 0; i < S; ++i) comp[i] = 0.f;
         const int n_re = (s == nseg - 1) ? (t1 - t0) : (t1 - t0 - 1);
@@ -238,11 +260,13 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
         const float* ck = a.ckpt_in + (size_t)s * SD;
         float xc[S], uc[4];
         load_rows<S>((t1 - 1 > t0) ? a.seg + (size_t)(t1 - 1 - t0) * SD : ck, D, d, xc);
+        if (!(t1 - 1 > t0)) to_dev<MODEL>(xc, p);
         load_cmd(a, t1 - 1, d, uc);
         for (int t = t1 - 1; t >= t0; --t) {
             float xn[S], un[4];
             if (t > t0) {
                 load_rows<S>((t - 1 > t0) ? a.seg + (size_t)(t - 1 - t0) * SD : ck, D, d, xn);
+                if (!(t - 1 > t0)) to_dev<MODEL>(xn, p);
                 load_cmd(a, t - 1, d, un);
             }
             if (a.has_obj) {

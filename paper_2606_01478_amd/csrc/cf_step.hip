@@ -19,11 +19,13 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
         float x[S], u[4], comp[S_FP];
 #pragma unroll
         for (int i = 0; i < S; ++i) x[i] = a.st[i * D + d];
+        rotors_to_dev(x, P);
 #pragma unroll
         for (int i = 0; i < S_FP; ++i) comp[i] = 0.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) u[i] = a.cmd[i * D + d];
         for (int k = 0; k < a.K; ++k) fp_step<CTRL, INTEG>(x, comp, u, P, C, a.dt, a.inv_dt, a.renorm);
+        rotors_from_dev(x, P);
 #pragma unroll
         for (int i = 0; i < S; ++i) {
             a.st[i * D + d] = x[i];

@@ -44,13 +44,18 @@ def test_fp_rotor_open_loop_rollout(gpu_lib, integ):
 
 @pytest.mark.parametrize("plain", [False, True])
 def test_fp_pid_closed_loop_held(gpu_lib, plain):
-    """Attitude commands through the PID, 200 single-drone worlds, 1000 steps."""
+    """Attitude commands through the PID, 200 single-drone worlds, 1000 steps.
+
+    The plain kernel stores the public binary32 state after every step, so its
+    reference rounds the state to binary32 after every step too: rounding the
+    absolute rotor speeds (spacing 1e-3 rad/s near hover) alone moves this
+    closed loop by about the parity bar over 1000 steps."""
     w = W.small(2, seed=2)
     sim = _sim(w, flags=B.F_PLAIN_KERNEL if plain else 0)
     x = dev(w.x0)
     sim.step_k(x, dev(w.cmds), w.steps)
     torch.cuda.synchronize()
-    ref = O.simulate_held(w)
+    ref = O.simulate_held(w, store_every=1 if plain else None)
     assert_states_close(x, ref, w)
 
 

@@ -892,3 +892,21 @@ def test_gradient_fd_position_interface():
     w.w_u = 1e-2
     w.cmds = np.repeat(w.cmds[None], w.steps, axis=0)
     _fd_check(w)
+
+
+def test_binary32_storage_between_calls():
+    """simulate_held(store_every=k) equals k-step fp64 runs chained through a
+    binary32 copy of the state (the numpy cast is the definition of that rounding),
+    and leaves every component representable in binary32."""
+    w = W.small(2, seed=2)
+    w = W.subset(w, list(range(6)))
+    n, k = 12, 4
+    got = O.simulate_held(w, steps=n, store_every=k).numpy()
+    x = np.asarray(w.x0, np.float64)
+    for _ in range(n // k):
+        x = O.simulate_held(w, steps=k, x0=x).numpy().astype(np.float32).astype(np.float64)
+    assert np.array_equal(got, x)
+    assert np.array_equal(got.astype(np.float32).astype(np.float64), got)
+    # storing only at the end is a rounding of the fp64 result
+    full = O.simulate_held(w, steps=n).numpy()
+    assert np.array_equal(O.simulate_held(w, steps=n, store_every=n).numpy(), full.astype(np.float32).astype(np.float64))

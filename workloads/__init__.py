@@ -226,9 +226,9 @@ def config1(seed: int = 1001, n_worlds: int = 16, steps: int = 500,
                     float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps, _f32(cmds))
 
 
-def fp_torque(seed: int = 1006, n_worlds: int = 256, steps: int = 150, dt: float = 0.004) -> Workload:
+def fp_torque(seed: int = 1006, n_worlds: int = 256, steps: int = 250, dt: float = 0.004) -> Workload:
     """Torque interface of the first-principles model (collective thrust and body
-    torques at 250 Hz, 0.6 s open loop): per-world mass and inertia x U[0.9, 1.1],
+    torques at 250 Hz, 1 s open loop): per-world mass and inertia x U[0.9, 1.1],
     held commands thrust ~ m g U[0.9, 1.1], torques ~ N(0, (2e-5 N m)^2)."""
     rng = _rng(seed)
     M = D = n_worlds
