@@ -418,6 +418,63 @@ cf_status validate_desc(const cf_desc* d, std::vector<int32_t>& counts, std::vec
     return CF_OK;
 }
 
+// A world's device record: the public record followed by constants derived from
+// it (offsets D_* in cf_device.hpp). Reciprocals and differences are formed in
+// binary32 exactly as a kernel would; the reference-speed terms (the hover speed
+// W_r on the thrust curve, thrust, drag torque and slopes there) in double from
+// the binary32 W_r the kernels use to convert rotor speeds, rounded once.
+void derive_record(const float* r, float* out) {
+    std::memcpy(out, r, NPARAM * sizeof(float));
+    std::fill(out + NPARAM, out + NREC, 0.f);
+    const float m = r[P_MASS];
+    out[D_INV_M] = 1.0f / m;
+    for (int i = 0; i < 3; ++i) out[D_IJ + i] = 1.0f / r[P_J + i];
+    out[D_DJ] = r[P_J + 2] - r[P_J + 1];
+    out[D_DJ + 1] = r[P_J] - r[P_J + 2];
+    out[D_DJ + 2] = r[P_J + 1] - r[P_J];
+    out[D_INV_2K2] = 0.5f / r[P_THRUST + 2];
+    for (int i = 0; i < 4; ++i) {
+        const float tz = r[P_MIX_YAW + i];
+        out[D_SG + i] = tz > 0.f ? -1.f : (tz < 0.f ? 1.f : 0.f);
+    }
+    const double k0 = r[P_THRUST], k1 = r[P_THRUST + 1], k2 = r[P_THRUST + 2];
+    const double t0 = r[P_TORQUE], t1 = r[P_TORQUE + 1], t2 = r[P_TORQUE + 2];
+    float wr = 0.f;
+    if (k2 > 0.0) {
+        // hover (m g / 4 per rotor) on the rising branch, else the vertex; never negative
+        const double dh = k1 * k1 - 4.0 * k2 * (k0 - 0.25 * (double)m * r[P_GRAVITY]);
+        const double w = ((dh > 0.0 ? std::sqrt(dh) : 0.0) - k1) / (2.0 * k2);
+        wr = std::isfinite(w) ? (float)std::max(w, 0.0) : 0.f;
+    }
+    const double W = wr;
+    const float k1w = wr > 0.f ? (float)std::max(k1 + 2.0 * k2 * W, 0.0) : (float)k1;
+    const double fr = k0 + W * (k1 + k2 * W);
+    const double tr = t0 + W * (t1 + t2 * W);
+    double stx = 0.0, sty = 0.0, stz = 0.0, ssg = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        stx += r[P_MIX_TX + i];
+        sty += r[P_MIX_TY + i];
+        stz += r[P_MIX_YAW + i];
+        ssg += out[D_SG + i];
+    }
+    out[D_WR] = wr;
+    out[D_W2] = 2.f * wr;
+    out[D_K1W] = k1w;
+    out[D_T1W] = (float)(t1 + 2.0 * t2 * W);
+    out[D_FR] = (float)fr;
+    out[D_F4R] = (float)(4.0 * fr);
+    out[D_TXR] = (float)(fr * stx);
+    out[D_TYR] = (float)(fr * sty);
+    out[D_TZR] = (float)(tr * stz);
+    out[D_SGR] = (float)(W * ssg);
+    out[D_DISC_R] = (float)((double)k1w * k1w);
+    out[D_VTX] = k2 > 0.0 ? (float)(-(double)k1w / (2.0 * k2)) : 0.f;
+    // identified model
+    const float cf = r[P_CF];
+    out[D_CF_M] = cf / m;
+    out[D_F_HOVER] = m * r[P_GRAVITY] / cf;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -500,20 +557,21 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
     };
     hipError_t e;
     const size_t M = (size_t)h->M;
-    std::vector<float> soa((size_t)CF_NPARAM * M);
+    std::vector<float> aos((size_t)NREC * M), soa((size_t)NREC * M);
+    for (size_t w = 0; w < M; ++w) derive_record(d->params + w * CF_NPARAM, aos.data() + w * NREC);
     for (size_t w = 0; w < M; ++w)
-        for (int i = 0; i < CF_NPARAM; ++i) soa[(size_t)i * M + w] = d->params[w * CF_NPARAM + i];
+        for (int i = 0; i < NREC; ++i) soa[(size_t)i * M + w] = aos[w * NREC + i];
     std::vector<int32_t> dw((size_t)std::max<int64_t>(D, 1));
     for (int w = 0; w < h->M; ++w)
         for (int64_t k = h->offsets[w]; k < h->offsets[w + 1]; ++k) dw[k] = w;
-    if ((e = dalloc(&h->par_aos, M * CF_NPARAM)) != hipSuccess) return fail(e);
-    if ((e = dalloc(&h->par_soa, M * CF_NPARAM)) != hipSuccess) return fail(e);
+    if ((e = dalloc(&h->par_aos, M * NREC)) != hipSuccess) return fail(e);
+    if ((e = dalloc(&h->par_soa, M * NREC)) != hipSuccess) return fail(e);
     if ((e = dalloc(&h->drone_world, (size_t)std::max<int64_t>(D, 1))) != hipSuccess) return fail(e);
     if ((e = dalloc(&h->d_offsets, M + 1)) != hipSuccess) return fail(e);
     if ((e = dalloc(&h->d_gidx, M)) != hipSuccess) return fail(e);
     h->n_counters = 4096;
     if ((e = dalloc(&h->counters, (size_t)h->n_counters)) != hipSuccess) return fail(e);
-    if ((e = hipMemcpy(h->par_aos, d->params, M * CF_NPARAM * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpy(h->par_aos, aos.data(), aos.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e);
     if ((e = hipMemcpy(h->par_soa, soa.data(), soa.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e);

@@ -29,17 +29,50 @@ enum : int {
     P_CPSI1 = 66, P_CPSI2 = 69, P_CPSI3 = 72, P_POS_KP = 75, P_POS_KV = 78, P_ATT_KR = 81,
     P_ATT_KW = 84, NPARAM = 96
 };
+// Per-world constants derived on the host from the public record (library-internal
+// tail of the device copies, which have NREC floats per world): reciprocals and
+// the reference-speed terms of the first-principles model, the identified model's
+// c_f / m and hover thrust. Loaded like the record itself, so that a workgroup
+// covering one world keeps them in scalar registers.
+enum : int {
+    D_INV_M = 96, D_IJ = 97, D_DJ = 100, D_INV_2K2 = 103, D_SG = 104, D_WR = 108, D_W2 = 109,
+    D_K1W = 110, D_T1W = 111, D_FR = 112, D_F4R = 113, D_TXR = 114, D_TYR = 115, D_TZR = 116,
+    D_SGR = 117, D_DISC_R = 118, D_VTX = 119, D_CF_M = 120, D_F_HOVER = 121, NREC = 128
+};
 enum : int { MODEL_FP = 0, MODEL_ID = 1 };
 enum : int { CTRL_ROTOR = 0, CTRL_PID = 1, CTRL_TORQUE = 2, CTRL_POSITION = 3 };
 enum : int { EULER = 0, RK4 = 1 };
 constexpr int S_FP = 17, S_PID = 25, S_ID = 13;
 
-// accessor over one world's record: array-of-structs (uniform world per tile)
+// accessors over one world's record in the array-of-structs copy (uniform world
+// per workgroup): plain loads, or loads through the constant address space, which
+// with a uniform record pointer become scalar loads into scalar registers (the
+// records are never written while kernels run). Which one is faster depends on
+// the kernel's register pressure: the held-step kernels gain from freeing vector
+// registers, the rollout kernels lose to scalar-register spills.
 struct AosRec {
     const float* r;
     __device__ __forceinline__ float operator()(int i) const { return r[i]; }
 };
-// accessor over a world's record in the transposed [NPARAM][M] copy (per-lane world)
+typedef const __attribute__((address_space(4))) float const_float;
+struct ScalarRec {
+    const float* r;
+    __device__ __forceinline__ float operator()(int i) const { return ((const_float*)r)[i]; }
+};
+// public fields through scalar loads, derived constants through per-lane vector
+// loads (an offset the compiler cannot see to be uniform keeps them in vector
+// registers), for kernels whose scalar registers are already full
+struct SplitRec {
+    const float* r;
+    int zero;
+    __device__ __forceinline__ explicit SplitRec(const float* rec) : r(rec) {
+        asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    }
+    __device__ __forceinline__ float operator()(int i) const {
+        return i < NPARAM ? ((const_float*)r)[i] : r[i + zero];
+    }
+};
+// accessor over a world's record in the transposed [NREC][M] copy (per-lane world)
 struct SoaRec {
     const float* p; int M; int w;
     __device__ __forceinline__ float operator()(int i) const { return p[(size_t)i * M + w]; }
@@ -48,7 +81,7 @@ struct SoaRec {
 struct FpParams {
     float inv_m, g;
     float iJx, iJy, iJz, dJx, dJy, dJz;  // dJx = Jz - Jy, dJy = Jx - Jz, dJz = Jy - Jx
-    float k0, k1, k2, t0, t1, t2, inv_2k2;
+    float k2, t2, inv_2k2;
     float tx[4], ty[4], tz[4];
     float cvu, cdu, cvd, cdd;
     float jp, sg[4];          // propeller inertia, rotor spin directions (-sign of the yaw mixing)
@@ -63,10 +96,11 @@ struct FpParams {
     float wr;                 // W_r
     float w2;                 // 2 W_r
     float k1w, t1w;           // k1 + 2 k2 W_r, t1 + 2 t2 W_r
-    float fr, tr;             // thrust and drag torque of one rotor at W_r
+    float fr;                 // thrust of one rotor at W_r
     float F4r, txr, tyr, tzr; // 4 fr, fr sum tx, fr sum ty, tr sum tz
     float sgr;                // W_r sum sigma
     float disc_r;             // discriminant of the thrust curve at fr: (k1 + 2 k2 W_r)^2
+    float vtx;                // the curve's vertex as a deviation: -(k1 + 2 k2 W_r) / (2 k2)
 };
 struct PidParams {
     float akp[2], aki[2], rkp[3], rki[3], rkd[3], jc[3], fmax;
@@ -87,14 +121,13 @@ struct IdParams {
 template <bool AERO, class R>
 __device__ __forceinline__ FpParams load_fp(const R& rec) {
     FpParams P;
-    P.inv_m = 1.0f / rec(P_MASS);
+    P.inv_m = rec(D_INV_M);
     P.g = rec(P_GRAVITY);
-    const float Jx = rec(P_J), Jy = rec(P_J + 1), Jz = rec(P_J + 2);
-    P.iJx = 1.0f / Jx; P.iJy = 1.0f / Jy; P.iJz = 1.0f / Jz;
-    P.dJx = Jz - Jy; P.dJy = Jx - Jz; P.dJz = Jy - Jx;
-    P.k0 = rec(P_THRUST); P.k1 = rec(P_THRUST + 1); P.k2 = rec(P_THRUST + 2);
-    P.inv_2k2 = 0.5f / P.k2;
-    P.t0 = rec(P_TORQUE); P.t1 = rec(P_TORQUE + 1); P.t2 = rec(P_TORQUE + 2);
+    P.iJx = rec(D_IJ); P.iJy = rec(D_IJ + 1); P.iJz = rec(D_IJ + 2);
+    P.dJx = rec(D_DJ); P.dJy = rec(D_DJ + 1); P.dJz = rec(D_DJ + 2);
+    P.k2 = rec(P_THRUST + 2);
+    P.t2 = rec(P_TORQUE + 2);
+    P.inv_2k2 = rec(D_INV_2K2);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         P.tx[i] = rec(P_MIX_TX + i); P.ty[i] = rec(P_MIX_TY + i); P.tz[i] = rec(P_MIX_YAW + i);
@@ -104,11 +137,12 @@ __device__ __forceinline__ FpParams load_fp(const R& rec) {
     if constexpr (AERO) {
         P.jp = rec(P_JP);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) P.sg[i] = P.tz[i] > 0.f ? -1.f : (P.tz[i] < 0.f ? 1.f : 0.f);
+        for (int i = 0; i < 4; ++i) P.sg[i] = rec(D_SG + i);
 #pragma unroll
         for (int i = 0; i < 3; ++i) P.cd[i] = rec(P_DRAG + i);
         P.gyro = P.jp != 0.f;
         P.drag = (P.cd[0] != 0.f) || (P.cd[1] != 0.f) || (P.cd[2] != 0.f);
+        P.sgr = rec(D_SGR);
     } else {
         P.jp = 0.f;
 #pragma unroll
@@ -117,29 +151,19 @@ __device__ __forceinline__ FpParams load_fp(const R& rec) {
         for (int i = 0; i < 3; ++i) P.cd[i] = 0.f;
         P.gyro = false;
         P.drag = false;
+        P.sgr = 0.f;
     }
-    // reference speed: hover (thrust m g / 4 per rotor) on the rising branch of
-    // the thrust curve, else its vertex; never negative, so that k1 + 2 k2 W_r >= 0
-    // (the allocation's cancellation-free root relies on it)
-    float wr = 0.f;
-    if (P.k2 > 0.f) {
-        const float fh = 0.25f * P.g / P.inv_m;
-        const float dh = P.k1 * P.k1 - 4.f * P.k2 * (P.k0 - fh);
-        wr = ((dh > 0.f ? sqrt_hw(dh) : 0.f) - P.k1) * P.inv_2k2;
-        wr = isfinite(wr) ? fmaxf(wr, 0.f) : 0.f;
-    }
-    P.wr = wr;
-    P.w2 = 2.f * wr;
-    P.k1w = wr > 0.f ? fmaxf(P.k1 + 2.f * P.k2 * wr, 0.f) : P.k1;
-    P.t1w = P.t1 + 2.f * P.t2 * wr;
-    P.fr = P.k0 + wr * (P.k1 + P.k2 * wr);
-    P.tr = P.t0 + wr * (P.t1 + P.t2 * wr);
-    P.F4r = 4.f * P.fr;
-    P.txr = P.fr * ((P.tx[0] + P.tx[1]) + (P.tx[2] + P.tx[3]));
-    P.tyr = P.fr * ((P.ty[0] + P.ty[1]) + (P.ty[2] + P.ty[3]));
-    P.tzr = P.tr * ((P.tz[0] + P.tz[1]) + (P.tz[2] + P.tz[3]));
-    P.sgr = wr * ((P.sg[0] + P.sg[1]) + (P.sg[2] + P.sg[3]));
-    P.disc_r = P.k1w * P.k1w;
+    P.wr = rec(D_WR);
+    P.w2 = rec(D_W2);
+    P.k1w = rec(D_K1W);
+    P.t1w = rec(D_T1W);
+    P.fr = rec(D_FR);
+    P.F4r = rec(D_F4R);
+    P.txr = rec(D_TXR);
+    P.tyr = rec(D_TYR);
+    P.tzr = rec(D_TZR);
+    P.disc_r = rec(D_DISC_R);
+    P.vtx = rec(D_VTX);
     return P;
 }
 
@@ -182,13 +206,12 @@ __device__ __forceinline__ PidParams load_pid(const R& rec, bool position) {
 template <bool AERO, class R>
 __device__ __forceinline__ IdParams load_id(const R& rec) {
     IdParams P;
-    const float m = rec(P_MASS), cf = rec(P_CF);
-    P.cf_m = cf / m;
+    P.cf_m = rec(D_CF_M);
     P.g = rec(P_GRAVITY);
     P.ctau = rec(P_CTAU);
     P.direct = P.ctau == 0.f;
-    P.f_hover = m * P.g / cf;
-    P.inv_m = 1.0f / m;
+    P.f_hover = rec(D_F_HOVER);
+    P.inv_m = rec(D_INV_M);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         P.c1[i] = rec(P_CPSI1 + i); P.c2[i] = rec(P_CPSI2 + i); P.c3[i] = rec(P_CPSI3 + i);
@@ -557,7 +580,7 @@ __device__ __forceinline__ void allocate(const float* wrench, const FpParams& P,
         tr.disc[j] = disc;
         tr.pass[j] = (dfr >= lo) && (dfr <= hi) && (disc > 0.f);
         // disc <= 0: below the curve's minimum, command its vertex
-        rc[j] = disc > 0.f ? 2.f * df * rcp_hw(sqrt_hw(disc) + P.k1w) : -P.k1w * P.inv_2k2;
+        rc[j] = disc > 0.f ? 2.f * df * rcp_hw(sqrt_hw(disc) + P.k1w) : P.vtx;
     }
 }
 

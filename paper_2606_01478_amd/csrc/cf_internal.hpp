@@ -9,7 +9,7 @@ namespace cfk {
 enum : int { MS_FP = 1, MS_ID = 2, MS_BOTH = 3 };
 // how lanes are mapped to drones
 //   LM_LANE: lane = drone, world looked up per lane, parameters from the
-//            transposed [NPARAM][M] copy (worlds of a handful of drones);
+//            transposed [NREC][M] copy (worlds of a handful of drones);
 //   LM_TILE: one workgroup per tile {world, first drone, count, model}, all
 //            lanes of a tile share one world (parameters are uniform loads);
 //   LM_WQ:   persistent workgroups pop tiles from an atomic queue head.
@@ -29,8 +29,8 @@ struct StepArgs {
     const float* cmd;       // [4][D]
     int64_t D;
     int M;
-    const float* par_aos;   // [M][NPARAM]
-    const float* par_soa;   // [NPARAM][M]
+    const float* par_aos;   // [M][NREC]
+    const float* par_soa;   // [NREC][M]
     const int32_t* drone_world;  // [D]
     float dt, inv_dt;
     int renorm;
@@ -79,7 +79,7 @@ constexpr int MPPI_MAX_OBS = 16;
 constexpr int MPPI_MAX_ELITE = 4096;
 constexpr int MPPI_SELECT_THREADS = 1024;
 struct MppiArgs {
-    const float* par;        // the world's record [NPARAM]
+    const float* par;        // the world's record [NREC]
     const float* x_now;      // [S]
     const float* mean;       // [C][H][4] previous plan (read at min(t + shift, H - 1))
     float* mean_out;         // [C][H][4] new plan (may alias mean)

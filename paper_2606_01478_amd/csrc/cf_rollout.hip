@@ -10,6 +10,8 @@
 //   (xbar, ubar) = VJP of the step at (x_t, u_t) applied to lambda_{t+1}
 //   ubar += 2 dloss w_u u_t;  g_cmds[t] = ubar;  xbar[0:13] += G^T ubar;
 //   dL/dG += ubar e_t^T;  lambda_t = xbar.
+#include <type_traits>
+
 #include "cf_device.hpp"
 #include "cf_internal.hpp"
 
@@ -152,7 +154,8 @@ __device__ __forceinline__ void store_state(float* dst, size_t D, size_t d, cons
 // ---------------------------------------------------------------------------
 // forward rollout of one drone
 template <int MODEL, int CTRL, int INTEG, bool AERO, class R>
-__device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
+__device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
+                                                  const float* G) {
     constexpr int S = ModelTraits<MODEL, CTRL>::S;
     const size_t D = (size_t)a.D;
     const size_t SD = (size_t)S_h * D;
@@ -169,7 +172,6 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
         for (int j = 0; j < 3; ++j) off[j] = a.ref_off[j * D + d];
     }
-    const float* G = (a.has_obj && a.gain) ? a.gain + (size_t)a.gidx[w] * NG : nullptr;
     if (a.ckpt) store_state<MODEL, S>(a.ckpt, D, d, x, p);
     if (a.traj) store_state<MODEL, S>(a.traj, D, d, x, p);
     float loss = 0.f;
@@ -206,7 +208,8 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
 // ---------------------------------------------------------------------------
 // adjoint of one drone's rollout
 template <int MODEL, int CTRL, int INTEG, bool AERO, class R>
-__device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
+__device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
+                                                  const float* G, float* gl, int gs) {
     constexpr int S = ModelTraits<MODEL, CTRL>::S;
     const size_t D = (size_t)a.D;
     const size_t SD = (size_t)S_h * D;
@@ -218,15 +221,17 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
         for (int j = 0; j < 3; ++j) off[j] = a.ref_off[j * D + d];
     }
-    const float* G = (a.has_obj && a.gain) ? a.gain + (size_t)a.gidx[w] * NG : nullptr;
     const float seed = a.dloss ? a.dloss[d] : 1.f;
     const float two_seed = 2.f * seed;
     float lam[S];
 #pragma unroll
     for (int i = 0; i < S; ++i) lam[i] = 0.f;
-    float gG[NG];   // this drone's gain-gradient contributions, summed in step order
+    // this drone's gain-gradient contributions, summed in step order, in its own
+    // LDS column gl[k * gs] (registers are the adjoint's scarcest resource)
+    if (G) {
 #pragma unroll
-    for (int i = 0; i < NG; ++i) gG[i] = 0.f;
+        for (int i = 0; i < NG; ++i) gl[i * gs] = 0.f;
+    }
     const int nseg = (a.T + a.K - 1) / a.K;
     for (int s = nseg - 1; s >= 0; --s) {
         const int t0 = s * a.K;
@@ -255,20 +260,13 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
             for (int j = 0; j < 3; ++j) pn[j] = nxt[j * D + d];
         }
-        // x_t and ubar_t of the step being differentiated are loaded one
-        // iteration ahead, so the loads overlap the previous step's VJP
         const float* ck = a.ckpt_in + (size_t)s * SD;
-        float xc[S], uc[4];
-        load_rows<S>((t1 - 1 > t0) ? a.seg + (size_t)(t1 - 1 - t0) * SD : ck, D, d, xc);
-        if (!(t1 - 1 > t0)) to_dev<MODEL>(xc, p);
-        load_cmd(a, t1 - 1, d, uc);
         for (int t = t1 - 1; t >= t0; --t) {
-            float xn[S], un[4];
-            if (t > t0) {
-                load_rows<S>((t - 1 > t0) ? a.seg + (size_t)(t - 1 - t0) * SD : ck, D, d, xn);
-                if (!(t - 1 > t0)) to_dev<MODEL>(xn, p);
-                load_cmd(a, t - 1, d, un);
-            }
+            // x_t: the checkpoint itself or a recomputed slot of the segment
+            float xc[S], uc[4];
+            load_rows<S>((t > t0) ? a.seg + (size_t)(t - t0) * SD : ck, D, d, xc);
+            if (!(t > t0)) to_dev<MODEL>(xc, p);
+            load_cmd(a, t, d, uc);
             if (a.has_obj) {
                 float pr[3];
                 ref_pos(a, t + 1, off, pr);
@@ -299,25 +297,19 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
 #pragma unroll
-                    for (int j = 0; j < 13; ++j) gG[i * 13 + j] += ub[i] * ev[j];
+                    for (int j = 0; j < 13; ++j) gl[(i * 13 + j) * gs] += ub[i] * ev[j];
                 }
             }
 #pragma unroll
             for (int i = 0; i < S; ++i) lam[i] = xb[i];
             pn[0] = xc[0]; pn[1] = xc[1]; pn[2] = xc[2];
-            if (t > t0) {
-#pragma unroll
-                for (int i = 0; i < S; ++i) xc[i] = xn[i];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) uc[i] = un[i];
-            }
         }
     }
     if (a.g_x0) store_rows<S>(a.g_x0, D, d, lam);
     if (a.ggc) {
         if (G) {
 #pragma unroll
-            for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = gG[i];
+            for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = gl[i * gs];
         } else {
 #pragma unroll
             for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = 0.f;
@@ -335,11 +327,12 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 __device__ __forceinline__ void rollout_priority() { __builtin_amdgcn_s_setprio(3); }
 
 template <bool BWD, int MODEL, int CTRL, int INTEG, bool AERO, class R>
-__device__ __forceinline__ void rollout_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h) {
+__device__ __forceinline__ void rollout_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
+                                              const float* G, float* gl, int gs) {
     if constexpr (BWD) {
-        rollout_bwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
+        rollout_bwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
     } else {
-        rollout_fwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
+        rollout_fwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G);
     }
 }
 
@@ -350,8 +343,12 @@ __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
     if (d >= (size_t)a.D) return;
     const int w = a.drone_world[d];
     const SoaRec rec{a.par_soa, a.M, w};
-    if constexpr (MODELS == MS_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
-    else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
+    const float* G = (a.has_obj && a.gain) ? a.gain + (size_t)a.gidx[w] * NG : nullptr;
+    extern __shared__ float roll_lds[];   // backward: [NG][blockDim.x] gain-gradient sums
+    float* gl = roll_lds + threadIdx.x;
+    const int gs = blockDim.x;
+    if constexpr (MODELS == MS_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
+    else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
 }
 
 template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
@@ -362,16 +359,29 @@ __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __
     const int d0 = __builtin_amdgcn_readfirstlane(td.y);
     const int cnt = __builtin_amdgcn_readfirstlane(td.z);
     const int model = __builtin_amdgcn_readfirstlane(td.w);
+    // the world's feedback gain, shared by the workgroup, is read from LDS
+    __shared__ float sG[NG];
+    const float* G = nullptr;
+    if (a.has_obj && a.gain) {
+        const float* Gw = a.gain + (size_t)a.gidx[w] * NG;
+        for (int i = threadIdx.x; i < NG; i += blockDim.x) sG[i] = Gw[i];
+        __syncthreads();
+        G = sG;
+    }
     if ((int)threadIdx.x >= cnt) return;
-    const AosRec rec{a.par_aos + (size_t)w * NPARAM};
+    using Rec = typename std::conditional<BWD, ScalarRec, AosRec>::type;
+    const Rec rec{a.par_aos + (size_t)w * NREC};
     const size_t d = (size_t)d0 + threadIdx.x;
+    extern __shared__ float roll_lds[];   // backward: [NG][blockDim.x] gain-gradient sums
+    float* gl = roll_lds + threadIdx.x;
+    const int gs = blockDim.x;
     if constexpr (MODELS == MS_FP) {
-        rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
+        rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
     } else if constexpr (MODELS == MS_ID) {
-        rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
+        rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
     } else {
-        if (model == MODEL_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
-        else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h);
+        if (model == MODEL_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
+        else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
     }
 }
 
@@ -379,16 +389,17 @@ template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
 static hipError_t launch_roll_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                 hipStream_t s) {
     const int S_h = a.S_h;
-    const size_t shmem = 0;
     if (ks.mode == LM_LANE) {
         if constexpr (MODELS != MS_BOTH) {
             const int bs = ks.tile;
             const unsigned grid = (unsigned)((a.D + bs - 1) / bs);
+            const size_t shmem = BWD ? (size_t)NG * bs * sizeof(float) : 0;
             hipLaunchKernelGGL((k_rollout_lane<BWD, MODELS, CTRL, INTEG, AERO>), dim3(grid), dim3(bs), shmem, s, a, S_h);
         } else {
             return hipErrorInvalidValue;
         }
     } else {
+        const size_t shmem = BWD ? (size_t)NG * ks.tile * sizeof(float) : 0;
         hipLaunchKernelGGL((k_rollout_tile<BWD, MODELS, CTRL, INTEG, AERO>), dim3(n_tiles), dim3(ks.tile), shmem, s, a,
                            tiles, S_h);
     }

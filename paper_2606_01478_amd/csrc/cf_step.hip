@@ -57,7 +57,7 @@ __device__ __forceinline__ void run_tile(const StepArgs& a, int4 td) {
     const int model = __builtin_amdgcn_readfirstlane(td.w);
     const int lane = threadIdx.x;
     if (lane >= cnt) return;
-    const AosRec rec{a.par_aos + (size_t)w * NPARAM};
+    const AosRec rec{a.par_aos + (size_t)w * NREC};
     const size_t d = (size_t)d0 + lane;
     if constexpr (MODELS == MS_FP) {
         run_held<MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w);
