@@ -34,16 +34,14 @@ FLOPS_PER_DS = {"fp_pid_rk4": 943.0, "fp_rotor_rk4": 802.0, "id_rk4": 317.0}
 SPEC_FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak
 SPEC_HBM_GBS = 8000.0
 
-# HBM traffic of one held-command step launch over the whole batch, from two
-# rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
-# 256 MiB device copy gives), recorded in
-# profiles/k_step_tile_uneven_mixed_2048w_T1000.md; valid only for the kernel
+# HBM bytes of one held-step phase (all launches of one cf_step_k call over the
+# whole batch), FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (the factors a 256 MiB
+# device copy gives) from two rocprofv3 --pmc runs, by launch configuration
+# "workqueue,tile,chunk,per_model"; summary in
+# profiles/held_step_uneven_mixed_2048w_T1000.md. Valid only for the kernel
 # sources it was measured on (SHA-256 below), reported as null otherwise.
-# HBM bytes (FETCH_SIZE + WRITE_SIZE, copy-probe scaled) of one held-step phase, by
-# launch configuration "workqueue,tile,chunk,per_model", measured with rocprofv3 on
-# the kernel sources whose hash is given (summary under profiles/)
-PROFILED_TRAFFIC = {"sources_sha256": "7e51541bca33b51a6bd3e26be2fb9dfaff07d7f79da571c3d5b7236ad4d06912",
-                    "by_launch": {"1,64,100,1": 1974250452.5}}
+PROFILED_TRAFFIC = {"sources_sha256": "af8145a1ff9c149a5c9ed2147be4ce264977c4c43218c6c669b6a7142f0e8b2c",
+                    "by_launch": {"1,64,100,1": 2004274937.5}}
 
 
 def kernel_sources_sha256() -> str:

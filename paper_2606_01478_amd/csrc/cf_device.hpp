@@ -32,8 +32,8 @@ enum : int {
 // Per-world constants derived on the host from the public record (library-internal
 // tail of the device copies, which have NREC floats per world): reciprocals and
 // the reference-speed terms of the first-principles model, the identified model's
-// c_f / m and hover thrust. Loaded like the record itself, so that a workgroup
-// covering one world keeps them in scalar registers.
+// c_f / m and hover thrust. Kernels read them like the public fields instead of
+// spending registers and instructions forming them.
 enum : int {
     D_INV_M = 96, D_IJ = 97, D_DJ = 100, D_INV_2K2 = 103, D_SG = 104, D_WR = 108, D_W2 = 109,
     D_K1W = 110, D_T1W = 111, D_FR = 112, D_F4R = 113, D_TXR = 114, D_TYR = 115, D_TZR = 116,
@@ -44,12 +44,13 @@ enum : int { CTRL_ROTOR = 0, CTRL_PID = 1, CTRL_TORQUE = 2, CTRL_POSITION = 3 };
 enum : int { EULER = 0, RK4 = 1 };
 constexpr int S_FP = 17, S_PID = 25, S_ID = 13;
 
-// accessors over one world's record in the array-of-structs copy (uniform world
-// per workgroup): plain loads, or loads through the constant address space, which
-// with a uniform record pointer become scalar loads into scalar registers (the
-// records are never written while kernels run). Which one is faster depends on
-// the kernel's register pressure: the held-step kernels gain from freeing vector
-// registers, the rollout kernels lose to scalar-register spills.
+// Accessors over one world's record in the array-of-structs copy (uniform world
+// per workgroup). Where the values live is a register-budget choice made per
+// kernel by measurement: plain loads (the compiler decides); loads through the
+// constant address space, which with a uniform pointer become scalar loads into
+// scalar registers (the records are never written while kernels run) and free
+// vector registers for the reverse step; forced per-lane vector loads for the
+// sampled-rollout kernel, whose scalar registers hold its large argument block.
 struct AosRec {
     const float* r;
     __device__ __forceinline__ float operator()(int i) const { return r[i]; }
@@ -59,18 +60,16 @@ struct ScalarRec {
     const float* r;
     __device__ __forceinline__ float operator()(int i) const { return ((const_float*)r)[i]; }
 };
-// public fields through scalar loads, derived constants through per-lane vector
-// loads (an offset the compiler cannot see to be uniform keeps them in vector
-// registers), for kernels whose scalar registers are already full
-struct SplitRec {
+// every field through per-lane vector loads even where the pointer is uniform
+// (an offset the compiler cannot see to be zero), for kernels whose scalar
+// registers are already full with kernel arguments
+struct VecRec {
     const float* r;
     int zero;
-    __device__ __forceinline__ explicit SplitRec(const float* rec) : r(rec) {
+    __device__ __forceinline__ explicit VecRec(const float* rec) : r(rec) {
         asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
     }
-    __device__ __forceinline__ float operator()(int i) const {
-        return i < NPARAM ? ((const_float*)r)[i] : r[i + zero];
-    }
+    __device__ __forceinline__ float operator()(int i) const { return r[i + zero]; }
 };
 // accessor over a world's record in the transposed [NREC][M] copy (per-lane world)
 struct SoaRec {

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_mppi_rollout(MppiArgs a) {
     const int c = blockIdx.y;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.N) return;
-    const SplitRec rec(a.par);
+    const VecRec rec(a.par);
     constexpr int S = MODEL == MODEL_ID ? S_ID : (CTRL == CTRL_PID ? S_PID : S_FP);
     constexpr int V = MODEL == MODEL_ID ? 6 : 7;  // first velocity row
     float x[S], comp[S];
