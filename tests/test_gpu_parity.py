@@ -346,6 +346,56 @@ def test_gyro_and_drag_rotor_interface(gpu_lib):
     _check_against_oracle(w, _rollout_grads(w, 20))
 
 
+def test_reference_speed_fallbacks_rotor_interface(gpu_lib):
+    """Inside the kernels rotor speeds are deviations from a per-world reference
+    speed (hover on the thrust curve). Worlds on its fallbacks, open loop through
+    the rotor interface: a linear thrust curve (k2 = 0: reference 0), a curve
+    whose minimum lies above the hover thrust (no hover speed: reference at the
+    vertex, here 0), and a negative linear term (vertex at 5000 rad/s below the
+    hover speed)."""
+    w = W.config1(seed=77, n_worlds=6, steps=200)
+    tp = w.params["thrust_poly"].astype(np.float64)
+    fh = W.MASS * W.GRAVITY / 4.0
+    wh = float(W.hover_speed(W.MASS))
+    tp[0] = (0.0, fh / wh, 0.0)
+    tp[1] = (1.5 * fh, 0.0, W.K_THRUST)
+    tp[2] = (0.0, -2.0 * 5000.0 * fh / (wh * wh - 10000.0 * wh), fh / (wh * wh - 10000.0 * wh))
+    w.params["thrust_poly"] = tp.astype(np.float32)
+    sim = _sim(w)
+    T = w.steps
+    x0, cmds = dev(w.x0), dev(w.cmds)
+    xT = torch.empty_like(x0)
+    traj = torch.empty((T + 1, sim.S, sim.D), device="cuda")
+    sim.rollout(x0, cmds, T, None, 20, x_T=xT, traj=traj)
+    torch.cuda.synchronize()
+    with torch.no_grad():
+        ref = O.rollout(O.Batch.from_workload(w), O.t64(w.x0), O.t64(w.cmds), T, with_loss=False, keep_traj=True)
+    for t in (1, 50, T):
+        assert_states_close(traj[t], ref["traj"][t], w, what=f"fallback traj[{t}]")
+
+
+def test_allocation_below_the_thrust_curve_minimum(gpu_lib):
+    """Torque interface on worlds whose thrust curve starts at k0 = 0.3 of the
+    hover thrust: collective commands of 0.1-0.3 m g ask for rotor thrusts below
+    the curve's minimum, where the allocation commands the vertex speed (here 0)."""
+    w = W.fp_torque(seed=78, n_worlds=40, steps=100)
+    tp = w.params["thrust_poly"].astype(np.float64)
+    mass = w.params["mass"][:, 0].astype(np.float64)
+    fh = mass * W.GRAVITY / 4.0
+    tp[:20, 0] = 0.3 * fh[:20]
+    tp[:20, 2] = 0.7 * fh[:20] / (W.hover_speed(mass[:20]) ** 2)
+    w.params["thrust_poly"] = tp.astype(np.float32)
+    rng = np.random.default_rng(78)
+    cmds = w.cmds.astype(np.float64)
+    cmds[0, :10] = mass[:10] * W.GRAVITY * rng.uniform(0.1, 0.3, size=10)
+    w.cmds = cmds.astype(np.float32)
+    sim = _sim(w)
+    x = dev(w.x0)
+    sim.step_k(x, dev(w.cmds), w.steps)
+    torch.cuda.synchronize()
+    assert_states_close(x, O.simulate_held(w), w, what="below the curve minimum")
+
+
 @pytest.mark.parametrize("wq", [False, True])
 def test_torque_interface_held_steps(gpu_lib, wq):
     """Collective thrust and body torques through the motor allocation, clamp and
