@@ -152,7 +152,24 @@ typedef struct cf_desc {
     void* stream;                     /* hipStream_t, NULL = default stream           */
     uint32_t flags;                   /* CF_F_*                                       */
     int32_t device;                   /* HIP device ordinal, -1 = current device      */
+    int32_t ctrl_every;               /* onboard controller every n physics steps (0, 1: every step) */
 } cf_desc;
+
+/*
+ * Control rate (the paper runs its controllers at 50-500 Hz on a faster
+ * physics loop; section "Architecture", control interfaces). With
+ * ctrl_every = n > 1 the onboard controller of first-principles worlds
+ * (attitude PID, position controller, torque allocation) is evaluated at the
+ * start of every block of n physics steps with period n dt (the PID's
+ * integrators and derivative use it) and its rotor-speed commands are held,
+ * zero-order, over the block; the PID state rows change only at evaluations.
+ * The rotor interface and identified worlds have no onboard controller and
+ * ignore it. Blocks are counted from the first step of each cf_step_k call
+ * (k must be a multiple of n) and from t = 0 in cf_rollout (T need not be;
+ * ckpt_every K must divide n or be a multiple of it). The plain single-step
+ * kernel (CF_F_PLAIN_KERNEL) launches once per block. n <= CF_MAX_CTRL_EVERY.
+ */
+#define CF_MAX_CTRL_EVERY 4096
 
 typedef struct cf_handle cf_handle;
 
@@ -212,6 +229,8 @@ cf_status cf_reset(cf_handle* h, float* state, const float* init, const uint8_t*
  * Kernel: fused k-step kernel that keeps the state in registers (chunked by
  * the autotuned K), or k single-step launches with CF_F_PLAIN_KERNEL, or the
  * persistent work-queue kernel (CF_F_WORKQUEUE or autotune choice).
+ * With a controller period of n > 1 steps (cf_desc.ctrl_every), k must be a
+ * multiple of n (CF_EINVAL otherwise).
  */
 cf_status cf_step_k(cf_handle* h, float* state, const float* cmd, int32_t k,
                     uint32_t* nonfinite_world);

@@ -305,6 +305,18 @@ def integrate(rates, x: torch.Tensor, dt: float, integrator: int) -> torch.Tenso
     return x + (dt / 6) * (k1 + 2 * k2 + 2 * k3 + k4)
 
 
+def _advance_fp(x, rot_cmd, ctrl, P, integrator: int, dt: float, renorm: bool):
+    """Integrate the 17 rigid-body and rotor components under rotor-speed commands
+    held over the step, renormalise the quaternion, append the controller state."""
+    body = integrate(lambda s: fp_rates(s, rot_cmd, P), x[0:17], dt, integrator)
+    if renorm:
+        q = body[3:7]
+        body = torch.cat([body[0:3], q / torch.sqrt((q * q).sum(0)), body[7:17]], 0)
+    if ctrl is None:
+        return body
+    return torch.cat([body, ctrl], 0)
+
+
 def step_fp(x, u, P, control: int, integrator: int, dt: float, renorm: bool = True):
     """One step of a first-principles drone (state 17, or 25 with the PID)."""
     if control == CTRL_ATT_PID:
@@ -315,13 +327,34 @@ def step_fp(x, u, P, control: int, integrator: int, dt: float, renorm: bool = Tr
         rot_cmd, ctrl = position_controller(x, u, P), None
     else:
         rot_cmd, ctrl = u, None
-    body = integrate(lambda s: fp_rates(s, rot_cmd, P), x[0:17], dt, integrator)
-    if renorm:
-        q = body[3:7]
-        body = torch.cat([body[0:3], q / torch.sqrt((q * q).sum(0)), body[7:17]], 0)
-    if ctrl is None:
-        return body
-    return torch.cat([body, ctrl], 0)
+    return _advance_fp(x, rot_cmd, ctrl, P, integrator, dt, renorm)
+
+
+def step_fp_multirate(x, u, P, control: int, integrator: int, dt: float, renorm: bool,
+                      run_ctrl: bool, held, dt_ctrl: float):
+    """One physics step of a first-principles drone whose onboard controller runs
+    at a lower rate than the physics (control interfaces and rates, section
+    "Architecture"; reading: the controller is evaluated at the start of every
+    block of n physics steps with its own period dt_ctrl = n dt, and its rotor
+    commands are held, zero-order, until the next evaluation). On a controller
+    step the attitude PID, position controller or torque allocation is evaluated
+    and its rotor commands become the held ones; on the other steps the held
+    commands drive the rotors and the controller state is carried unchanged. The
+    rotor interface has no onboard controller: its commands apply every step.
+    Returns (next state, held rotor commands)."""
+    if control == CTRL_ROTOR:
+        return step_fp(x, u, P, control, integrator, dt, renorm), None
+    if run_ctrl:
+        if control == CTRL_ATT_PID:
+            rot_cmd, ctrl = attitude_pid(x, u, P, dt_ctrl)
+        elif control == CTRL_TORQUE:
+            rot_cmd, ctrl = allocate(u, P), None
+        else:
+            rot_cmd, ctrl = position_controller(x, u, P), None
+    else:
+        rot_cmd = held
+        ctrl = x[17:25] if control == CTRL_ATT_PID else None
+    return _advance_fp(x, rot_cmd, ctrl, P, integrator, dt, renorm), rot_cmd
 
 
 def step_id(x, u, P, integrator: int, dt: float):
@@ -336,7 +369,7 @@ class Batch:
     """Per-drone view of a set of worlds (models, parameters, world index)."""
 
     def __init__(self, drones_per_world, model_per_world, params, control, integrator,
-                 dt, renorm=1):
+                 dt, renorm=1, ctrl_every=1):
         self.counts = np.asarray(drones_per_world, np.int64)
         self.models = np.asarray(model_per_world, np.int64)
         self.world = np.repeat(np.arange(len(self.counts)), self.counts)
@@ -352,11 +385,12 @@ class Batch:
         self.integrator = int(integrator)
         self.dt = float(dt)
         self.renorm = bool(renorm)
+        self.ctrl_every = max(int(ctrl_every), 1)
 
     @classmethod
     def from_workload(cls, w):
         return cls(w.drones_per_world, w.model_per_world, w.params, w.control,
-                   w.integrator, w.dt, w.renorm_q)
+                   w.integrator, w.dt, w.renorm_q, getattr(w, "ctrl_every", 1))
 
     def step(self, x: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
         """x ``[S, D]`` -> state after one step under command u ``[4, D]``."""
@@ -376,6 +410,31 @@ class Batch:
                 yi = torch.cat([yi, xi[13:]], 0)
             out = out.index_copy(1, self.id_idx, yi)
         return out
+
+    def step_at(self, x: torch.Tensor, u: torch.Tensor, n: int, held):
+        """Physics step n of a run in which the first-principles drones' onboard
+        controller runs on the steps with n % ctrl_every == 0 (period ctrl_every
+        dt) and its rotor commands are held in between (``step_fp_multirate``).
+        ``held`` carries those commands between calls (None before the first).
+        Returns (next state, held). With ctrl_every = 1 this is ``step``."""
+        if self.ctrl_every == 1 or len(self.fp_idx) == 0 or self.control == CTRL_ROTOR:
+            return self.step(x, u), held
+        out = x
+        xf = x[:, self.fp_idx]
+        nf = 25 if self.control == CTRL_ATT_PID else 17
+        yf, held = step_fp_multirate(xf[:nf], u[:, self.fp_idx], self.P_fp, self.control, self.integrator,
+                                     self.dt, self.renorm, n % self.ctrl_every == 0, held,
+                                     self.ctrl_every * self.dt)
+        if x.shape[0] > nf:
+            yf = torch.cat([yf, xf[nf:]], 0)
+        out = out.index_copy(1, self.fp_idx, yf)
+        if len(self.id_idx):
+            xi = x[:, self.id_idx]
+            yi = step_id(xi[:13], u[:, self.id_idx], self.P_id, self.integrator, self.dt)
+            if x.shape[0] > 13:
+                yi = torch.cat([yi, xi[13:]], 0)
+            out = out.index_copy(1, self.id_idx, yi)
+        return out, held
 
     # -- reference and objective -------------------------------------------------
 
@@ -435,6 +494,7 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
         p, v = batch.figure_eight(t, ref_amp, ref_period, ref_offset)
         return p, (batch.reference_state(p, v) if G is not None else None)
 
+    held = None
     for n in range(steps):
         ubar = cmds[n] if cmds.dim() == 3 else cmds
         if G is not None:
@@ -445,7 +505,7 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
             u = ubar
         if with_loss:
             loss = loss + w_u * (u * u).sum(0)
-        x = batch.step(x, u)
+        x, held = batch.step_at(x, u, n, held)
         if with_loss:
             p_ref, _ = ref(n + 1)
             d = x[0:3] - p_ref
@@ -489,9 +549,10 @@ def simulate_held(w, steps: Optional[int] = None, x0=None, store_every: Optional
     x = t64(w.x0 if x0 is None else x0)
     u = t64(w.cmds)
     n = w.steps if steps is None else steps
+    held = None
     with torch.no_grad():
         for i in range(n):
-            x = b.step(x, u)
+            x, held = b.step_at(x, u, i, held)
             if store_every and (i + 1) % store_every == 0:
                 x = x.to(torch.float32).to(torch.float64)
     return x

@@ -143,10 +143,11 @@ def sample_commands(mean_s: np.ndarray, ctrl, eps: np.ndarray, P: Dict) -> np.nd
 def rollout_costs(w, x_now: np.ndarray, u: np.ndarray, P: Dict) -> np.ndarray:
     """Cost of m5 for each command sequence u ``[n, H, 4]`` started at x_now ``[S]``
     on the single world of workload ``w`` (its model, interface, integrator,
-    dt), with ``substeps`` simulator steps per horizon step."""
+    dt, controller period), with ``substeps`` simulator steps per horizon step;
+    the onboard controller's blocks count physics steps from the first one."""
     n, H, _ = u.shape
     batch = Batch([n], w.model_per_world[:1], {k: v[:1] for k, v in w.params.items()}, w.control,
-                  w.integrator, w.dt, w.renorm_q)
+                  w.integrator, w.dt, w.renorm_q, getattr(w, "ctrl_every", 1))
     x = torch.as_tensor(np.asarray(x_now, np.float64))[:, None].repeat(1, n)
     ut = torch.as_tensor(u, dtype=torch.float64)
     goal = torch.as_tensor(np.asarray(P["goal"], np.float64))[:, None]
@@ -155,12 +156,14 @@ def rollout_costs(w, x_now: np.ndarray, u: np.ndarray, P: Dict) -> np.ndarray:
     r_u = torch.as_tensor(np.asarray(P["r_u"], np.float64))[:, None]
     u_ref = torch.as_tensor(np.asarray(P["u_ref"], np.float64))[:, None]
     J = torch.zeros(n, dtype=torch.float64)
+    sub = int(P.get("substeps", 1))
+    held = None
     with torch.no_grad():
         for t in range(H):
             ct = ut[:, t].T.contiguous()
             J = J + (r_u * (ct - u_ref) ** 2).sum(0)
-            for _ in range(int(P.get("substeps", 1))):
-                x = batch.step(x, ct)
+            for k in range(sub):
+                x, held = batch.step_at(x, ct, t * sub + k, held)
             p, v = x[0:3], x[vrow:vrow + 3]
             J = J + P["q_p"] * ((p - goal) ** 2).sum(0) + P["q_v"] * (v ** 2).sum(0)
             for o in obs:

@@ -56,7 +56,7 @@ class _Desc(ctypes.Structure):
                 ("model", c_int32), ("model_per_world", POINTER(c_uint8)), ("control", c_int32),
                 ("integrator", c_int32), ("dt", c_float), ("renorm_q", c_int32), ("params", POINTER(c_float)),
                 ("n_gains", c_int32), ("gain_index", POINTER(c_int32)), ("stream", c_void_p),
-                ("flags", c_uint32), ("device", c_int32)]
+                ("flags", c_uint32), ("device", c_int32), ("ctrl_every", c_int32)]
 
 
 class _Objective(ctypes.Structure):
@@ -151,7 +151,7 @@ class Sim:
 
     def __init__(self, n_worlds: int, drones_per_world, model_per_world, control: int, integrator: int,
                  dt: float, params, *, renorm_q: int = 1, n_gains: int = 0, gain_index=None, flags: int = 0,
-                 device: int = -1):
+                 device: int = -1, ctrl_every: int = 1):
         import torch
         lib = load()
         self._lib = lib
@@ -183,6 +183,7 @@ class Sim:
         d.stream = c_void_p(_stream() if torch.cuda.is_available() else 0)
         d.flags = int(flags)
         d.device = int(device)
+        d.ctrl_every = int(ctrl_every)
         _check(lib.cf_create(ctypes.byref(d), ctypes.byref(self._h)), "cf_create")
         S = c_int32()
         D = c_int64()
@@ -194,10 +195,12 @@ class Sim:
         self.offsets = off
         self.n_gains = int(n_gains)
         self.flags = int(flags)
+        self.ctrl_every = int(ctrl_every)
 
     @classmethod
     def from_workload(cls, w, flags: int = 0, **kw):
         n_gains = 0 if w.gain is None else int(w.gain.shape[0])
+        kw.setdefault("ctrl_every", getattr(w, "ctrl_every", 1))
         return cls(w.n_worlds, w.drones_per_world, w.model_per_world, w.control, w.integrator, w.dt,
                    w.params, renorm_q=w.renorm_q, n_gains=n_gains, gain_index=w.gain_index, flags=flags, **kw)
 

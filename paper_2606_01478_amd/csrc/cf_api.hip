@@ -120,6 +120,8 @@ struct cf_handle {
     int models = 0;  // MS_*
     int control = 0, integ = 0, renorm = 1;
     float dt = 0.f;
+    int ctrl_every = 1;              // onboard controller every n physics steps (1 without one)
+    float dtc = 0.f, inv_dtc = 0.f;  // its period and inverse
     uint32_t flags = 0;
     int n_gains = 0;
     std::vector<int32_t> counts;
@@ -300,7 +302,9 @@ StepArgs step_args(const cf_handle* h, float* st, const float* cmd, int K, uint3
     a.par_soa = h->par_soa;
     a.drone_world = h->drone_world;
     a.dt = h->dt;
-    a.inv_dt = 1.0f / h->dt;
+    a.dtc = h->dtc;
+    a.inv_dtc = h->inv_dtc;
+    a.ctrl_every = h->ctrl_every;
     a.renorm = h->renorm;
     a.K = K;
     a.nonfinite = (h->flags & CF_F_NONFINITE_CHECK) ? nf : nullptr;
@@ -391,6 +395,7 @@ cf_status validate_desc(const cf_desc* d, std::vector<int32_t>& counts, std::vec
     if (d->integrator != CF_INTEG_EULER && d->integrator != CF_INTEG_RK4) return CF_EINVAL;
     if (!(std::isfinite(d->dt) && d->dt > 0.f)) return CF_EINVAL;
     if (d->renorm_q != 0 && d->renorm_q != 1) return CF_EINVAL;
+    if (d->ctrl_every < 0 || d->ctrl_every > CF_MAX_CTRL_EVERY) return CF_EINVAL;
     if (!d->params) return CF_EINVAL;
     if (d->n_gains < 0) return CF_EINVAL;
     gidx.assign(M, 0);
@@ -533,6 +538,11 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
     for (int w = 0; w < h->M; ++w) h->offsets[w + 1] = h->offsets[w] + counts[w];
     int has_fp = 0, has_id = 0;
     for (auto m : models) (m == CF_MODEL_FP ? has_fp : has_id) = 1;
+    // only first-principles worlds behind the attitude, torque or position
+    // interface have an onboard controller whose rate can differ
+    h->ctrl_every = (has_fp && d->control != CF_CTRL_ROTOR && d->ctrl_every > 1) ? d->ctrl_every : 1;
+    h->dtc = (float)((double)h->ctrl_every * (double)h->dt);
+    h->inv_dtc = 1.0f / h->dtc;
     h->models = (has_fp ? MS_FP : 0) | (has_id ? MS_ID : 0);
     h->S = has_fp ? (h->control == CF_CTRL_ATT_PID ? CF_S_FP_PID : CF_S_FP_ROTOR) : CF_S_ID;
     h->lane_ok = (h->models != MS_BOTH);
@@ -687,19 +697,23 @@ cf_status cf_reset(cf_handle* h, float* state, const float* init, const uint8_t*
 static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int k, uint32_t* nf, hipStream_t s,
                                int plain) {
     hipError_t e = hipSuccess;
+    const int n = h->ctrl_every;  // k is a multiple of n: every launch starts on a controller step
     if (plain) {
+        // one step per launch; with a slower onboard controller, one controller
+        // period per launch (its held commands are not part of the state)
         const int mode = h->mode == LM_LANE ? LM_LANE : LM_TILE;
-        const StepArgs a = step_args(h, state, cmd, 1, nf);
+        const StepArgs a = step_args(h, state, cmd, n, nf);
         e = per_model(h, s, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
             KernelSel ks = selection(h, mode, h->tile);
             ks.models = models;
             hipError_t r = hipSuccess;
-            for (int i = 0; i < k && r == hipSuccess; ++i) r = launch_step(ks, a, tiles, nt, nullptr, 0, st);
+            for (int i = 0; i < k / n && r == hipSuccess; ++i) r = launch_step(ks, a, tiles, nt, nullptr, 0, st);
             return r;
         });
         return note(h, e);
     }
-    const int chunk = (h->chunk > 0 && h->chunk < k) ? h->chunk : k;
+    int chunk = (h->chunk > 0 && h->chunk < k) ? h->chunk : k;
+    chunk = ((chunk + n - 1) / n) * n;
     const int n_launch = (k + chunk - 1) / chunk;
     if (h->use_wq) {
         if (2 * n_launch > h->n_counters) return CF_EINVAL;
@@ -725,6 +739,7 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
 
 cf_status cf_step_k(cf_handle* h, float* state, const float* cmd, int32_t k, uint32_t* nf) {
     if (!h || k < 1) return CF_EINVAL;
+    if (k % h->ctrl_every != 0) return CF_EINVAL;
     if (h->sticky != CF_OK) return h->sticky;
     if (h->D == 0) return CF_OK;
     if (check_dev(state, (size_t)h->S * h->D * sizeof(float)) ||
@@ -813,7 +828,9 @@ static RollArgs roll_args(const cf_handle* h, const float* x0, const float* cmds
     a.par_soa = h->par_soa;
     a.drone_world = h->drone_world;
     a.dt = h->dt;
-    a.inv_dt = 1.0f / h->dt;
+    a.dtc = h->dtc;
+    a.inv_dtc = h->inv_dtc;
+    a.ctrl_every = h->ctrl_every;
     a.renorm = h->renorm;
     a.K = K;
     return a;
@@ -826,6 +843,7 @@ static int roll_mode(const cf_handle* h) {
 cf_status cf_rollout(cf_handle* h, const float* x0, const float* cmds, int32_t T, const cf_objective* obj,
                      int32_t K, float* ckpt, float* x_T, float* traj, float* loss, float* loss_world) {
     if (!h || T < 1 || K < 1) return CF_EINVAL;
+    if (K % h->ctrl_every != 0 && h->ctrl_every % K != 0) return CF_EINVAL;
     if (h->sticky != CF_OK) return h->sticky;
     if (!obj && (loss || loss_world)) return CF_EINVAL;
     const size_t SD = (size_t)h->S * h->D * sizeof(float);
@@ -878,6 +896,7 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
                               int32_t K, const float* ckpt, const float* dloss, float* g_cmds, float* g_x0,
                               float* g_gain) {
     if (!h || T < 1 || K < 1 || !ckpt) return CF_EINVAL;
+    if (K % h->ctrl_every != 0 && h->ctrl_every % K != 0) return CF_EINVAL;
     if (h->sticky != CF_OK) return h->sticky;
     if (ckpt != h->last_ckpt || T != h->last_T || K != h->last_K) return CF_ESTATE;
     if (g_gain && (!obj || !obj->gain)) return CF_EINVAL;
@@ -1059,7 +1078,9 @@ cf_status cf_mppi_create(cf_handle* h, const cf_mppi_desc* d, cf_mppi** out) {
     a.sub = d->substeps;
     a.n_e = d->n_elite;
     a.dt = h->dt;
-    a.inv_dt = 1.0f / h->dt;
+    a.dtc = h->dtc;
+    a.inv_dtc = h->inv_dtc;
+    a.ctrl_every = h->ctrl_every;
     a.renorm = h->renorm;
     for (int i = 0; i < 4; ++i) {
         a.sigma[i] = d->sigma[i];

@@ -893,25 +893,38 @@ __device__ __forceinline__ void integrate_vjp(const float* x, float h, const flo
 // ---------------------------------------------------------------------------
 // whole steps
 
-// first-principles step; S = 17 (rotor interface) or 25 (attitude PID)
-template <int CTRL, int INTEG>
-__device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, const FpParams& P,
-                                        const PidParams& C, float dt, float inv_dt, int renorm) {
-    float rc[4];
-    float cs[8];
+// The onboard controller of the first-principles model (attitude PID, position
+// controller, torque allocation) at (x, u) with controller period dtc: rotor
+// commands rc (deviations from W_r) and, for the PID, its new state cs.
+template <int CTRL>
+__device__ __forceinline__ void fp_ctrl_forward(const float* x, const float* u, const FpParams& P,
+                                                const PidParams& C, float dtc, float inv_dtc, float* rc, float* cs) {
+    PidTrace tr;
     if constexpr (CTRL == CTRL_PID) {
-        PidTrace tr;
-        pid_forward(x, u, P, C, dt, inv_dt, rc, cs, tr);
+        pid_forward(x, u, P, C, dtc, inv_dtc, rc, cs, tr);
     } else if constexpr (CTRL == CTRL_TORQUE) {
-        PidTrace tr;
         allocate(u, P, C, rc, tr);
     } else if constexpr (CTRL == CTRL_POSITION) {
-        PidTrace tr;
         PosTrace pt;
         pos_forward(x, u, P, C, rc, tr, pt);
-    } else {
+    }
+}
+
+// first-principles step; S = 17 (rotor interface) or 25 (attitude PID).
+// rc holds the rotor-speed commands across steps (owned by the caller). The
+// onboard controller runs when ctrl_now, with its own period dtc (a whole number
+// of physics steps); in between its commands are held and the PID state is
+// carried. The rotor interface applies its command every step.
+template <int CTRL, int INTEG>
+__device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, const FpParams& P,
+                                        const PidParams& C, float dt, float dtc, float inv_dtc, int renorm,
+                                        float* rc, bool ctrl_now) {
+    float cs[8];
+    if constexpr (CTRL == CTRL_ROTOR) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) rc[i] = u[i] - P.wr;
+    } else {
+        if (ctrl_now) fp_ctrl_forward<CTRL>(x, u, P, C, dtc, inv_dtc, rc, cs);
     }
     integrate<S_FP, INTEG, COMP_FP>(x, comp, dt, [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
     if (renorm) {
@@ -920,8 +933,10 @@ __device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, c
         x[3] *= inv; x[4] *= inv; x[5] *= inv; x[6] *= inv;
     }
     if constexpr (CTRL == CTRL_PID) {
+        if (ctrl_now) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) x[17 + i] = cs[i];
+            for (int i = 0; i < 8; ++i) x[17 + i] = cs[i];
+        }
     }
 }
 
@@ -933,17 +948,29 @@ __device__ __forceinline__ void id_step(float* x, float* comp, const float* u, c
     if (P.direct) x[12] = u[3];  // the thrust row holds the applied thrust
 }
 
-// VJP of fp_step at (x, u): yb = adjoint of the new state (S components),
-// writes xb (S) and accumulates ub (4).
+// adjoint of the renormalisation q_out = q / |q| that follows a step, given the
+// integrator output y: qb <- (qb_out - q_out (q_out . qb_out)) / |q|
+__device__ __forceinline__ void renorm_vjp(const float* y, float* ybr) {
+    const float inv = rsqrt_hw(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]);
+    const float q0 = y[3] * inv, q1 = y[4] * inv, q2 = y[5] * inv, q3 = y[6] * inv;
+    const float dot = q0 * ybr[3] + q1 * ybr[4] + q2 * ybr[5] + q3 * ybr[6];
+    ybr[3] = (ybr[3] - q0 * dot) * inv;
+    ybr[4] = (ybr[4] - q1 * dot) * inv;
+    ybr[5] = (ybr[5] - q2 * dot) * inv;
+    ybr[6] = (ybr[6] - q3 * dot) * inv;
+}
+
+// VJP of fp_step at (x, u) with the controller evaluated in this step: yb =
+// adjoint of the new state (S components), writes xb (S) and accumulates ub (4).
 template <int CTRL, int INTEG>
 __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, const FpParams& P,
-                                            const PidParams& C, float dt, float inv_dt, int renorm,
+                                            const PidParams& C, float dt, float dtc, float inv_dtc, int renorm,
                                             const float* yb, float* xb, float* ub) {
     float rc[4], cs[8];
     PidTrace tr;
     PosTrace pt;
     if constexpr (CTRL == CTRL_PID) {
-        pid_forward(x, u, P, C, dt, inv_dt, rc, cs, tr);
+        pid_forward(x, u, P, C, dtc, inv_dtc, rc, cs, tr);
     } else if constexpr (CTRL == CTRL_TORQUE) {
         allocate(u, P, C, rc, tr);
     } else if constexpr (CTRL == CTRL_POSITION) {
@@ -956,17 +983,7 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
     const auto rates = [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); };
     const auto vjp = [&](const float* xi, const float* gb, float* xa) { fp_rates_vjp(xi, rc, P, gb, xa, rcb); };
     if (renorm) {
-        // q_out = q / |q| after the step: qb <- (qb_out - q_out (q_out . qb_out)) / |q|
-        const auto post = [&](const float* y, float* ybr) {
-            const float inv = rsqrt_hw(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]);
-            const float q0 = y[3] * inv, q1 = y[4] * inv, q2 = y[5] * inv, q3 = y[6] * inv;
-            const float dot = q0 * ybr[3] + q1 * ybr[4] + q2 * ybr[5] + q3 * ybr[6];
-            ybr[3] = (ybr[3] - q0 * dot) * inv;
-            ybr[4] = (ybr[4] - q1 * dot) * inv;
-            ybr[5] = (ybr[5] - q2 * dot) * inv;
-            ybr[6] = (ybr[6] - q3 * dot) * inv;
-        };
-        integrate_vjp<S_FP, INTEG, true>(x, dt, yb, xb, rates, vjp, post);
+        integrate_vjp<S_FP, INTEG, true>(x, dt, yb, xb, rates, vjp, renorm_vjp);
     } else {
         const auto none = [](const float*, float*) {};
         integrate_vjp<S_FP, INTEG, false>(x, dt, yb, xb, rates, vjp, none);
@@ -974,7 +991,7 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
     if constexpr (CTRL == CTRL_PID) {
 #pragma unroll
         for (int i = S_FP; i < S_PID; ++i) xb[i] = 0.f;
-        pid_vjp(x, P, C, dt, inv_dt, tr, rcb, yb + S_FP, xb, ub);
+        pid_vjp(x, P, C, dtc, inv_dtc, tr, rcb, yb + S_FP, xb, ub);
     } else if constexpr (CTRL == CTRL_TORQUE) {
         allocate_vjp(C, tr, rcb, ub);
     } else if constexpr (CTRL == CTRL_POSITION) {
@@ -982,6 +999,45 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
     } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) ub[i] += rcb[i];
+    }
+}
+
+// Reverse pieces of a step whose controller runs every n > 1 physics steps.
+// fp_held_vjp: VJP of the rigid-body and rotor integration under the held
+// commands rc: writes xb rows 0..16 and accumulates rcb.
+template <int INTEG>
+__device__ __forceinline__ void fp_held_vjp(const float* x, const float* rc, const FpParams& P, float dt,
+                                            int renorm, const float* yb, float* xb, float* rcb) {
+    const auto rates = [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); };
+    const auto vjp = [&](const float* xi, const float* gb, float* xa) { fp_rates_vjp(xi, rc, P, gb, xa, rcb); };
+    if (renorm) {
+        integrate_vjp<S_FP, INTEG, true>(x, dt, yb, xb, rates, vjp, renorm_vjp);
+    } else {
+        const auto none = [](const float*, float*) {};
+        integrate_vjp<S_FP, INTEG, false>(x, dt, yb, xb, rates, vjp, none);
+    }
+}
+
+// fp_ctrl_vjp: VJP of one controller evaluation at (x, u), given the adjoint rcb
+// of its held commands (summed over the steps that used them) and csb of the PID
+// state it wrote (rows 17..24 of the next state): accumulates into xb and ub.
+template <int CTRL>
+__device__ __forceinline__ void fp_ctrl_vjp(const float* x, const float* u, const FpParams& P,
+                                            const PidParams& C, float dtc, float inv_dtc, const float* rcb,
+                                            const float* csb, float* xb, float* ub) {
+    float rc[4];
+    PidTrace tr;
+    if constexpr (CTRL == CTRL_PID) {
+        float cs[8];
+        pid_forward(x, u, P, C, dtc, inv_dtc, rc, cs, tr);
+        pid_vjp(x, P, C, dtc, inv_dtc, tr, rcb, csb, xb, ub);
+    } else if constexpr (CTRL == CTRL_TORQUE) {
+        allocate(u, P, C, rc, tr);
+        allocate_vjp(C, tr, rcb, ub);
+    } else if constexpr (CTRL == CTRL_POSITION) {
+        PosTrace pt;
+        pos_forward(x, u, P, C, rc, tr, pt);
+        pos_vjp(x, C, tr, pt, rcb, xb, ub);
     }
 }
 

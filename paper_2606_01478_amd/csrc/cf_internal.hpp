@@ -32,7 +32,9 @@ struct StepArgs {
     const float* par_aos;   // [M][NREC]
     const float* par_soa;   // [NREC][M]
     const int32_t* drone_world;  // [D]
-    float dt, inv_dt;
+    float dt;
+    float dtc, inv_dtc;     // onboard controller period (ctrl_every physics steps) and its inverse
+    int ctrl_every;         // the controller runs on every ctrl_every-th step (launches start on one)
     int renorm;
     int K;                  // steps per launch
     uint32_t* nonfinite;    // [M] or null
@@ -48,7 +50,9 @@ struct RollArgs {
     const float* par_aos;
     const float* par_soa;
     const int32_t* drone_world;
-    float dt, inv_dt;
+    float dt;
+    float dtc, inv_dtc;     // onboard controller period and its inverse
+    int ctrl_every;         // the controller runs on steps t with t % ctrl_every == 0
     int renorm;
     // objective
     int has_obj;
@@ -84,7 +88,9 @@ struct MppiArgs {
     const float* mean;       // [C][H][4] previous plan (read at min(t + shift, H - 1))
     float* mean_out;         // [C][H][4] new plan (may alias mean)
     int C, N, H, sub, n_e, shift;
-    float dt, inv_dt;
+    float dt;
+    float dtc, inv_dtc;      // onboard controller period and its inverse
+    int ctrl_every;          // controller on physics steps t * sub + s divisible by it
     int renorm;
     float sigma[4], beta, beta_c, inv_lambda;
     float u_lo[4], u_hi[4], u_ref[4], r_u[4];

@@ -92,7 +92,8 @@ struct NoiseSeq {
 };
 
 // ---- rollout + cost: one lane per sample ---------------------------------------
-template <int MODEL, int CTRL, int INTEG, bool AERO>
+// MR: variant for an onboard controller slower than the physics
+template <int MODEL, int CTRL, int INTEG, bool AERO, bool MR>
 __global__ __launch_bounds__(256) void k_mppi_rollout(MppiArgs a) {
     const int c = blockIdx.y;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,6 +120,8 @@ __global__ __launch_bounds__(256) void k_mppi_rollout(MppiArgs a) {
     NoiseSeq ns;
     ns.init((uint64_t)k, (uint64_t)c);
     float J = 0.f;
+    float rc[4] = {0.f, 0.f, 0.f, 0.f};   // held rotor commands
+    int phase = 0;                        // physics step within the controller period
     for (int t = 0; t < a.H; ++t) {
         ns.next(t, a);
         float u[4];
@@ -129,8 +132,14 @@ __global__ __launch_bounds__(256) void k_mppi_rollout(MppiArgs a) {
             J += a.r_u[i] * du * du;
         }
         for (int s = 0; s < a.sub; ++s) {
-            if constexpr (MODEL == MODEL_FP) fp_step<CTRL, INTEG>(x, comp, u, P, Cp, a.dt, a.inv_dt, a.renorm);
-            else id_step<INTEG>(x, comp, u, Pi, a.dt);
+            if constexpr (MODEL == MODEL_FP) {
+                fp_step<CTRL, INTEG>(x, comp, u, P, Cp, a.dt, a.dtc, a.inv_dtc, a.renorm, rc, MR ? phase == 0 : true);
+                if constexpr (MR) {
+                    if (++phase == a.ctrl_every) phase = 0;
+                }
+            } else {
+                id_step<INTEG>(x, comp, u, Pi, a.dt);
+            }
         }
         const float ex = x[0] - a.goal[0], ey = x[1] - a.goal[1], ez = x[2] - a.goal[2];
         J += a.q_p * (ex * ex + ey * ey + ez * ez) +
@@ -407,7 +416,13 @@ __global__ void k_mppi_pick(MppiArgs a) {
 template <int MODEL, int CTRL, int INTEG, bool AERO>
 static hipError_t launch_roll(const KernelSel&, const MppiArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((a.N + 255) / 256), (unsigned)a.C);
-    hipLaunchKernelGGL((k_mppi_rollout<MODEL, CTRL, INTEG, AERO>), grid, dim3(256), 0, s, a);
+    if constexpr (MODEL == MODEL_FP && CTRL != CTRL_ROTOR) {
+        if (a.ctrl_every > 1) {
+            hipLaunchKernelGGL((k_mppi_rollout<MODEL, CTRL, INTEG, AERO, true>), grid, dim3(256), 0, s, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_mppi_rollout<MODEL, CTRL, INTEG, AERO, false>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

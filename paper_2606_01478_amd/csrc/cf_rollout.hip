@@ -104,18 +104,23 @@ __device__ __forceinline__ void load_params(const R& rec, DroneParams& p) {
     }
 }
 
+// one step; rc holds the first-principles rotor commands across steps, the
+// onboard controller runs when ctrl_now
 template <int MODEL, int CTRL, int INTEG>
 __device__ __forceinline__ void model_step(float* x, float* comp, const float* u, const DroneParams& p,
-                                           const RollArgs& a) {
-    if constexpr (MODEL == MODEL_FP) fp_step<CTRL, INTEG>(x, comp, u, p.fp, p.pid, a.dt, a.inv_dt, a.renorm);
-    else id_step<INTEG>(x, comp, u, p.id, a.dt);
+                                           const RollArgs& a, float* rc, bool ctrl_now) {
+    if constexpr (MODEL == MODEL_FP)
+        fp_step<CTRL, INTEG>(x, comp, u, p.fp, p.pid, a.dt, a.dtc, a.inv_dtc, a.renorm, rc, ctrl_now);
+    else
+        id_step<INTEG>(x, comp, u, p.id, a.dt);
 }
 
+// VJP of a step whose controller (if any) runs every step
 template <int MODEL, int CTRL, int INTEG>
 __device__ __forceinline__ void model_step_vjp(const float* x, const float* u, const DroneParams& p,
                                                const RollArgs& a, const float* yb, float* xb, float* ub) {
     if constexpr (MODEL == MODEL_FP)
-        fp_step_vjp<CTRL, INTEG>(x, u, p.fp, p.pid, a.dt, a.inv_dt, a.renorm, yb, xb, ub);
+        fp_step_vjp<CTRL, INTEG>(x, u, p.fp, p.pid, a.dt, a.dtc, a.inv_dtc, a.renorm, yb, xb, ub);
     else
         id_step_vjp<INTEG>(x, u, p.id, a.dt, yb, xb, ub);
 }
@@ -153,7 +158,7 @@ __device__ __forceinline__ void store_state(float* dst, size_t D, size_t d, cons
 
 // ---------------------------------------------------------------------------
 // forward rollout of one drone
-template <int MODEL, int CTRL, int INTEG, bool AERO, class R>
+template <int MODEL, int CTRL, int INTEG, bool AERO, bool MR, class R>
 __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
                                                   const float* G) {
     constexpr int S = ModelTraits<MODEL, CTRL>::S;
@@ -177,12 +182,17 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
     float loss = 0.f;
     float ubar[4];
     load_cmd(a, 0, d, ubar);
+    float rc[4] = {0.f, 0.f, 0.f, 0.f};   // held rotor commands
+    int phase = 0;                        // step within the controller period
     for (int t = 0; t < a.T; ++t) {
         float u[4], ev[13], unext[4];
         if (t + 1 < a.T) load_cmd(a, t + 1, d, unext);   // issued early, used next step
         feedback<MODEL>(a, G, x, t, off, f_hover, ubar, u, ev);
         if (a.has_obj) loss += a.w_u * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3]);
-        model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a);
+        model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a, rc, MR ? phase == 0 : true);
+        if constexpr (MR) {
+            if (++phase == a.ctrl_every) phase = 0;
+        }
         if (a.has_obj) {
             float pr[3];
             ref_pos(a, t + 1, off, pr);
@@ -205,9 +215,28 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
     }
 }
 
+// The held rotor commands of the controller block starting at step tb: the
+// controller evaluated at x_tb (checkpoint tb / K when tb is a checkpoint step,
+// else slot tb - t0 of the current segment) under the command applied there.
+template <int MODEL, int CTRL, int S>
+__device__ __forceinline__ void block_commands(const RollArgs& a, const DroneParams& p, const float* G,
+                                               const float* off, float f_hover, size_t D, size_t d, size_t SD,
+                                               int tb, int t0, float* rc) {
+    float xs[S], ubs[4], us[4], evs[13], cs[8];
+    if (tb % a.K == 0) {
+        load_rows<S>(a.ckpt_in + (size_t)(tb / a.K) * SD, D, d, xs);
+        to_dev<MODEL>(xs, p);
+    } else {
+        load_rows<S>(a.seg + (size_t)(tb - t0) * SD, D, d, xs);
+    }
+    load_cmd(a, tb, d, ubs);
+    feedback<MODEL>(a, G, xs, tb, off, f_hover, ubs, us, evs);
+    fp_ctrl_forward<CTRL>(xs, us, p.fp, p.pid, a.dtc, a.inv_dtc, rc, cs);
+}
+
 // ---------------------------------------------------------------------------
 // adjoint of one drone's rollout
-template <int MODEL, int CTRL, int INTEG, bool AERO, class R>
+template <int MODEL, int CTRL, int INTEG, bool AERO, bool MR, class R>
 __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
                                                   const float* G, float* gl, int gs) {
     constexpr int S = ModelTraits<MODEL, CTRL>::S;
@@ -232,6 +261,12 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
         for (int i = 0; i < NG; ++i) gl[i * gs] = 0.f;
     }
+    // controller slower than the physics (first-principles, onboard controller):
+    // the commands of a block are held over its steps, so their adjoints are
+    // summed over the block (rcb) and taken through the controller at its start
+    constexpr bool HAS_CTRL = (MR && MODEL == MODEL_FP && CTRL != CTRL_ROTOR);
+    const int n_c = HAS_CTRL ? a.ctrl_every : 1;
+    float rch[4] = {0.f, 0.f, 0.f, 0.f}, rcb[4] = {0.f, 0.f, 0.f, 0.f};
     const int nseg = (a.T + a.K - 1) / a.K;
     for (int s = nseg - 1; s >= 0; --s) {
         const int t0 = s * a.K;
@@ -245,11 +280,18 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
         for (int i = 0; i < S; ++i) comp[i] = 0.f;
         const int n_re = (s == nseg - 1) ? (t1 - t0) : (t1 - t0 - 1);
+        float rcf[4] = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (HAS_CTRL) {
+            // a segment that starts inside a block (period longer than the
+            // checkpoint interval) starts with that block's held commands
+            if (n_re > 0 && t0 % n_c != 0)
+                block_commands<MODEL, CTRL, S>(a, p, G, off, f_hover, D, d, SD, t0 - t0 % n_c, t0, rcf);
+        }
         for (int j = 0; j < n_re; ++j) {
             float u[4], ev[13], ubar[4];
             load_cmd(a, t0 + j, d, ubar);
             feedback<MODEL>(a, G, x, t0 + j, off, f_hover, ubar, u, ev);
-            model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a);
+            model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a, rcf, (t0 + j) % n_c == 0);
             if (j + 1 < t1 - t0) store_rows<S>(a.seg + (size_t)(j + 1) * SD, D, d, x);
         }
         float pn[3];  // position of x_{t+1}
@@ -277,7 +319,27 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
             feedback<MODEL>(a, G, xc, t, off, f_hover, uc, u, ev);
             float xb[S];
             float ub[4] = {0.f, 0.f, 0.f, 0.f};
-            model_step_vjp<MODEL, CTRL, INTEG>(xc, u, p, a, lam, xb, ub);
+            bool held = false;
+            if constexpr (HAS_CTRL) {
+                if (n_c > 1) {
+                    held = true;
+                    const int tb = t - t % n_c;
+                    if (t == a.T - 1 || (t + 1) % n_c == 0)   // first visit of this block
+                        block_commands<MODEL, CTRL, S>(a, p, G, off, f_hover, D, d, SD, tb, t0, rch);
+                    fp_held_vjp<INTEG>(xc, rch, p.fp, a.dt, a.renorm, lam, xb, rcb);
+                    if constexpr (S > S_FP) {
+#pragma unroll
+                        for (int i = S_FP; i < S; ++i) xb[i] = (t == tb) ? 0.f : lam[i];
+                    }
+                    if (t == tb) {
+                        const float* csb = (S > S_FP) ? lam + S_FP : lam;   // PID state adjoint
+                        fp_ctrl_vjp<CTRL>(xc, u, p.fp, p.pid, a.dtc, a.inv_dtc, rcb, csb, xb, ub);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) rcb[i] = 0.f;
+                    }
+                }
+            }
+            if (!held) model_step_vjp<MODEL, CTRL, INTEG>(xc, u, p, a, lam, xb, ub);
             if (a.has_obj) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) ub[i] += two_seed * a.w_u * u[i];
@@ -326,17 +388,18 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 // chain is not stretched, and the wide work fills the remaining issue slots.
 __device__ __forceinline__ void rollout_priority() { __builtin_amdgcn_s_setprio(3); }
 
-template <bool BWD, int MODEL, int CTRL, int INTEG, bool AERO, class R>
+template <bool BWD, int MODEL, int CTRL, int INTEG, bool AERO, bool MR, class R>
 __device__ __forceinline__ void rollout_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
                                               const float* G, float* gl, int gs) {
     if constexpr (BWD) {
-        rollout_bwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
+        rollout_bwd_drone<MODEL, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
     } else {
-        rollout_fwd_drone<MODEL, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G);
+        rollout_fwd_drone<MODEL, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G);
     }
 }
 
-template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
+// MR: variant for an onboard controller slower than the physics
+template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
 __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
     rollout_priority();
     const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -347,11 +410,11 @@ __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
     extern __shared__ float roll_lds[];   // backward: [NG][blockDim.x] gain-gradient sums
     float* gl = roll_lds + threadIdx.x;
     const int gs = blockDim.x;
-    if constexpr (MODELS == MS_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
-    else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
+    if constexpr (MODELS == MS_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
+    else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
 }
 
-template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
+template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
 __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __restrict__ tiles, int S_h) {
     rollout_priority();
     const int4 td = tiles[blockIdx.x];
@@ -376,17 +439,17 @@ __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __
     float* gl = roll_lds + threadIdx.x;
     const int gs = blockDim.x;
     if constexpr (MODELS == MS_FP) {
-        rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
+        rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
     } else if constexpr (MODELS == MS_ID) {
-        rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
+        rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
     } else {
-        if (model == MODEL_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
-        else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w, S_h, G, gl, gs);
+        if (model == MODEL_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
+        else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
     }
 }
 
-template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
-static hipError_t launch_roll_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
+template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
+static hipError_t launch_roll_k(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                 hipStream_t s) {
     const int S_h = a.S_h;
     if (ks.mode == LM_LANE) {
@@ -394,16 +457,27 @@ static hipError_t launch_roll_t(const KernelSel& ks, const RollArgs& a, const in
             const int bs = ks.tile;
             const unsigned grid = (unsigned)((a.D + bs - 1) / bs);
             const size_t shmem = BWD ? (size_t)NG * bs * sizeof(float) : 0;
-            hipLaunchKernelGGL((k_rollout_lane<BWD, MODELS, CTRL, INTEG, AERO>), dim3(grid), dim3(bs), shmem, s, a, S_h);
+            hipLaunchKernelGGL((k_rollout_lane<BWD, MODELS, CTRL, INTEG, AERO, MR>), dim3(grid), dim3(bs), shmem, s, a,
+                               S_h);
         } else {
             return hipErrorInvalidValue;
         }
     } else {
         const size_t shmem = BWD ? (size_t)NG * ks.tile * sizeof(float) : 0;
-        hipLaunchKernelGGL((k_rollout_tile<BWD, MODELS, CTRL, INTEG, AERO>), dim3(n_tiles), dim3(ks.tile), shmem, s, a,
-                           tiles, S_h);
+        hipLaunchKernelGGL((k_rollout_tile<BWD, MODELS, CTRL, INTEG, AERO, MR>), dim3(n_tiles), dim3(ks.tile), shmem, s,
+                           a, tiles, S_h);
     }
     return hipGetLastError();
+}
+
+// the slow-controller variant exists only where there is an onboard controller
+template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
+static hipError_t launch_roll_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
+                                hipStream_t s) {
+    if constexpr (MODELS != MS_ID && CTRL != CTRL_ROTOR) {
+        if (a.ctrl_every > 1) return launch_roll_k<BWD, MODELS, CTRL, INTEG, AERO, true>(ks, a, tiles, n_tiles, s);
+    }
+    return launch_roll_k<BWD, MODELS, CTRL, INTEG, AERO, false>(ks, a, tiles, n_tiles, s);
 }
 
 template <int MODELS, int CTRL, int INTEG, bool AERO>

@@ -7,7 +7,8 @@
 namespace cfk {
 
 // One drone, K steps with a held command; state rows st[i*D + d].
-template <int MODEL, int CTRL, int INTEG, bool AERO, class R>
+// MR: variant for an onboard controller slower than the physics
+template <int MODEL, int CTRL, int INTEG, bool AERO, bool MR, class R>
 __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t d, int w) {
     const size_t D = (size_t)a.D;
     bool bad = false;
@@ -24,7 +25,14 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
         for (int i = 0; i < S_FP; ++i) comp[i] = 0.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) u[i] = a.cmd[i * D + d];
-        for (int k = 0; k < a.K; ++k) fp_step<CTRL, INTEG>(x, comp, u, P, C, a.dt, a.inv_dt, a.renorm);
+        float rc[4] = {0.f, 0.f, 0.f, 0.f};   // held rotor commands
+        int phase = 0;                        // launches start on a controller step
+        for (int k = 0; k < a.K; ++k) {
+            fp_step<CTRL, INTEG>(x, comp, u, P, C, a.dt, a.dtc, a.inv_dtc, a.renorm, rc, MR ? phase == 0 : true);
+            if constexpr (MR) {
+                if (++phase == a.ctrl_every) phase = 0;
+            }
+        }
         rotors_from_dev(x, P);
 #pragma unroll
         for (int i = 0; i < S; ++i) {
@@ -48,7 +56,7 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
     if (a.nonfinite && bad) atomicOr(a.nonfinite + w, 1u);
 }
 
-template <int MODELS, int CTRL, int INTEG, bool AERO>
+template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
 __device__ __forceinline__ void run_tile(const StepArgs& a, int4 td) {
     // td = {world, first drone, drone count, model}, uniform over the workgroup
     const int w = __builtin_amdgcn_readfirstlane(td.x);
@@ -60,33 +68,33 @@ __device__ __forceinline__ void run_tile(const StepArgs& a, int4 td) {
     const AosRec rec{a.par_aos + (size_t)w * NREC};
     const size_t d = (size_t)d0 + lane;
     if constexpr (MODELS == MS_FP) {
-        run_held<MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w);
+        run_held<MODEL_FP, CTRL, INTEG, AERO, MR>(rec, a, d, w);
     } else if constexpr (MODELS == MS_ID) {
-        run_held<MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w);
+        run_held<MODEL_ID, CTRL, INTEG, AERO, MR>(rec, a, d, w);
     } else {
-        if (model == MODEL_FP) run_held<MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w);
-        else run_held<MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w);
+        if (model == MODEL_FP) run_held<MODEL_FP, CTRL, INTEG, AERO, MR>(rec, a, d, w);
+        else run_held<MODEL_ID, CTRL, INTEG, AERO, MR>(rec, a, d, w);
     }
 }
 
-template <int MODELS, int CTRL, int INTEG, bool AERO>
+template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
 __global__ __launch_bounds__(256) void k_step_lane(StepArgs a) {
     const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= (size_t)a.D) return;
     const int w = a.drone_world[d];
     const SoaRec rec{a.par_soa, a.M, w};
-    if constexpr (MODELS == MS_FP) run_held<MODEL_FP, CTRL, INTEG, AERO>(rec, a, d, w);
-    else run_held<MODEL_ID, CTRL, INTEG, AERO>(rec, a, d, w);
+    if constexpr (MODELS == MS_FP) run_held<MODEL_FP, CTRL, INTEG, AERO, MR>(rec, a, d, w);
+    else run_held<MODEL_ID, CTRL, INTEG, AERO, MR>(rec, a, d, w);
 }
 
-template <int MODELS, int CTRL, int INTEG, bool AERO>
+template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
 __global__ __launch_bounds__(256) void k_step_tile(StepArgs a, const int4* __restrict__ tiles) {
-    run_tile<MODELS, CTRL, INTEG, AERO>(a, tiles[blockIdx.x]);
+    run_tile<MODELS, CTRL, INTEG, AERO, MR>(a, tiles[blockIdx.x]);
 }
 
 // Persistent work queue: each workgroup pops the next tile index from *counter
 // until the tiles run out; every workgroup exits after one failed pop.
-template <int MODELS, int CTRL, int INTEG, bool AERO>
+template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
 __global__ __launch_bounds__(256) void k_step_wq(StepArgs a, const int4* __restrict__ tiles, int n_tiles,
                                                  unsigned* counter) {
     __shared__ int s_next;
@@ -96,31 +104,45 @@ __global__ __launch_bounds__(256) void k_step_wq(StepArgs a, const int4* __restr
         const int t = __builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
         if (t >= n_tiles) break;
-        run_tile<MODELS, CTRL, INTEG, AERO>(a, tiles[t]);
+        run_tile<MODELS, CTRL, INTEG, AERO, MR>(a, tiles[t]);
     }
 }
 
-template <int MODELS, int CTRL, int INTEG, bool AERO>
-static hipError_t launch_step_t(const KernelSel& ks, const StepArgs& a, const int4* tiles, int n_tiles,
+template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
+static hipError_t launch_step_k(const KernelSel& ks, const StepArgs& a, const int4* tiles, int n_tiles,
                                 unsigned* counter, int wq_blocks, hipStream_t s) {
     if (ks.mode == LM_LANE) {
         if constexpr (MODELS == MS_BOTH) return hipErrorInvalidValue;
         const int bs = ks.tile;
         const unsigned grid = (unsigned)((a.D + bs - 1) / bs);
-        hipLaunchKernelGGL((k_step_lane<MODELS, CTRL, INTEG, AERO>), dim3(grid), dim3(bs), 0, s, a);
+        hipLaunchKernelGGL((k_step_lane<MODELS, CTRL, INTEG, AERO, MR>), dim3(grid), dim3(bs), 0, s, a);
     } else if (ks.mode == LM_TILE) {
-        hipLaunchKernelGGL((k_step_tile<MODELS, CTRL, INTEG, AERO>), dim3(n_tiles), dim3(ks.tile), 0, s, a, tiles);
+        hipLaunchKernelGGL((k_step_tile<MODELS, CTRL, INTEG, AERO, MR>), dim3(n_tiles), dim3(ks.tile), 0, s, a, tiles);
     } else {
-        hipLaunchKernelGGL((k_step_wq<MODELS, CTRL, INTEG, AERO>), dim3(wq_blocks), dim3(ks.tile), 0, s, a, tiles,
+        // work-queue workgroups that do not fit at once start later, find the
+        // queue empty and exit
+        hipLaunchKernelGGL((k_step_wq<MODELS, CTRL, INTEG, AERO, MR>), dim3(wq_blocks), dim3(ks.tile), 0, s, a, tiles,
                            n_tiles, counter);
     }
     return hipGetLastError();
 }
 
+// the slow-controller variant exists only where there is an onboard controller
+template <int MODELS, int CTRL, int INTEG, bool AERO>
+static hipError_t launch_step_t(const KernelSel& ks, const StepArgs& a, const int4* tiles, int n_tiles,
+                                unsigned* counter, int wq_blocks, hipStream_t s) {
+    if constexpr (MODELS != MS_ID && CTRL != CTRL_ROTOR) {
+        if (a.ctrl_every > 1)
+            return launch_step_k<MODELS, CTRL, INTEG, AERO, true>(ks, a, tiles, n_tiles, counter, wq_blocks, s);
+    }
+    return launch_step_k<MODELS, CTRL, INTEG, AERO, false>(ks, a, tiles, n_tiles, counter, wq_blocks, s);
+}
+
 template <int MODELS, int CTRL, int INTEG, bool AERO>
 static int wq_blocks_t(int tile) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq<MODELS, CTRL, INTEG, AERO>, tile, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq<MODELS, CTRL, INTEG, AERO, false>, tile, 0) !=
+        hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }

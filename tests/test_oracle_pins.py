@@ -910,3 +910,77 @@ def test_binary32_storage_between_calls():
     # storing only at the end is a rounding of the fp64 result
     full = O.simulate_held(w, steps=n).numpy()
     assert np.array_equal(O.simulate_held(w, steps=n, store_every=n).numpy(), full.astype(np.float32).astype(np.float64))
+
+
+# ---- onboard controller at a lower rate than the physics ---------------------------
+
+@pytest.mark.parametrize("n", [2, 5])
+def test_multirate_controller_is_blocks_of_rotor_interface_steps(n):
+    """With the controller every n physics steps, a run equals, block by block: the
+    attitude PID evaluated once with period n dt, then n steps of the rotor
+    interface under its commands, then the controller state it produced (built
+    here from the rotor-interface path, not from the multirate step)."""
+    w = W.small(2, seed=2)
+    w = W.subset(w, list(range(8)))
+    w.ctrl_every = n
+    steps = 3 * n + 1
+    got = O.simulate_held(w, steps=steps).numpy()
+    b = O.Batch.from_workload(w)
+    P = b.P_fp
+    x = O.t64(w.x0)
+    u = O.t64(w.cmds)
+    t = 0
+    with torch.no_grad():
+        while t < steps:
+            rot, cs = O.attitude_pid(x, u, P, n * b.dt)
+            for _ in range(min(n, steps - t)):
+                body = O.step_fp(x[0:17], rot, P, O.CTRL_ROTOR, b.integrator, b.dt, b.renorm)
+                x = torch.cat([body, x[17:25]], 0)
+                t += 1
+            x = torch.cat([x[0:17], cs], 0)
+    assert np.allclose(got, x.numpy(), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("control", [O.CTRL_TORQUE, O.CTRL_POSITION])
+def test_multirate_torque_and_position_hold_commands(control):
+    """Torque and position interfaces with the controller every 3 steps: the
+    rotor commands of each evaluation drive three rotor-interface steps."""
+    w = W.fp_torque(seed=31, n_worlds=5, steps=9) if control == O.CTRL_TORQUE else \
+        W.fp_position(seed=32, n_worlds=5, steps=9)
+    w.ctrl_every = 3
+    got = O.simulate_held(w).numpy()
+    b = O.Batch.from_workload(w)
+    x, u = O.t64(w.x0), O.t64(w.cmds)
+    with torch.no_grad():
+        for t in range(w.steps):
+            if t % 3 == 0:
+                rot = O.allocate(u, b.P_fp) if control == O.CTRL_TORQUE else O.position_controller(x, u, b.P_fp)
+            x = O.step_fp(x, rot, b.P_fp, O.CTRL_ROTOR, b.integrator, b.dt, b.renorm)
+    assert np.allclose(got, x.numpy(), rtol=0, atol=1e-14)
+
+
+def test_multirate_hover_fixed_point():
+    """Hover with the attitude PID evaluated every 5 steps stays put."""
+    b, P = fp_batch(2, control=O.CTRL_ATT_PID)
+    b.ctrl_every = 5
+    wh = math.sqrt(W.MASS * W.GRAVITY / (4 * W.K_THRUST))
+    x = torch.zeros(25, 2, dtype=F64)
+    x[6] = 1.0
+    x[13:17] = wh
+    u = torch.tensor([[0.0] * 2, [0.0] * 2, [0.0] * 2, [W.MASS * W.GRAVITY] * 2], dtype=F64)
+    held = None
+    y = x
+    with torch.no_grad():
+        for t in range(500):
+            y, held = b.step_at(y, u, t, held)
+    assert torch.allclose(y[0:13], x[0:13], atol=1e-11)
+    assert torch.allclose(y[13:17], x[13:17], rtol=1e-12)
+    assert torch.allclose(y[17:25], x[17:25], atol=1e-12)
+
+
+def test_gradient_fd_multirate_controller():
+    """Reverse-mode gradient through held controller outputs (PID every 3 steps)
+    against central differences."""
+    w = W.config5_adjoint(seed=14, n_worlds=6, n_subset=4, steps=31, n_max=3)
+    w.ctrl_every = 3
+    _fd_check(w)

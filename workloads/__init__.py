@@ -94,6 +94,7 @@ class Workload:
     ref_offset: Optional[np.ndarray] = None   # float32 [3, D]
     w_u: float = 1e-3
     dloss: Optional[np.ndarray] = None    # float32 [D]
+    ctrl_every: int = 1                   # onboard controller every n physics steps
 
     @property
     def n_drones_total(self) -> int:
