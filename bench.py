@@ -40,8 +40,8 @@ SPEC_HBM_GBS = 8000.0
 # "workqueue,tile,chunk,per_model"; summary in
 # profiles/held_step_uneven_mixed_2048w_T1000.md. Valid only for the kernel
 # sources it was measured on (SHA-256 below), reported as null otherwise.
-PROFILED_TRAFFIC = {"sources_sha256": "af8145a1ff9c149a5c9ed2147be4ce264977c4c43218c6c669b6a7142f0e8b2c",
-                    "by_launch": {"1,64,100,1": 2004274937.5}}
+PROFILED_TRAFFIC = {"sources_sha256": "4376e568cfbcd11de25d9792e0f329907b986842cd086439acee385cd233ca1c",
+                    "by_launch": {"1,64,100,1": 1982307731.5}}
 
 
 def kernel_sources_sha256() -> str:
