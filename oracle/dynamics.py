@@ -465,15 +465,70 @@ class Batch:
         return xr
 
 
+def _safe_sqrt(a: torch.Tensor) -> torch.Tensor:
+    """sqrt with gradient 0 at 0 (a subgradient of the norm's kink)."""
+    pos = a > 0
+    return torch.where(pos, torch.sqrt(torch.where(pos, a, torch.ones_like(a))), torch.zeros_like(a))
+
+
+def tilt_angle(batch: "Batch", x: torch.Tensor) -> torch.Tensor:
+    """Angle between the body z axis and the world z axis (the reward's angle
+    from the upright orientation): first principles 2 asin(|(q_x, q_y)| / |q|);
+    identified atan2(sqrt(sin^2 phi + cos^2 phi sin^2 theta), cos phi cos theta)
+    (the same angle for R = Rz Ry Rx, written without cancellation)."""
+    out = torch.zeros(batch.D, dtype=x.dtype)
+    if len(batch.fp_idx):
+        q = x[3:7, batch.fp_idx]
+        s2 = (q[0] * q[0] + q[1] * q[1]) / (q * q).sum(0)
+        out = out.index_copy(0, batch.fp_idx, 2 * torch.asin(torch.clamp(_safe_sqrt(s2), max=1.0)))
+    if len(batch.id_idx):
+        phi, th = x[3, batch.id_idx], x[4, batch.id_idx]
+        a = torch.sin(phi) ** 2 + (torch.cos(phi) * torch.sin(th)) ** 2
+        out = out.index_copy(0, batch.id_idx, torch.atan2(_safe_sqrt(a), torch.cos(phi) * torch.cos(th)))
+    return out
+
+
+def hover_action(batch: "Batch") -> torch.Tensor:
+    """The commands that hold a drone in hover, per drone ``[4, D]``: identified
+    [0, 0, 0, m g / c_f]; attitude interface [0, 0, 0, m g]; torque interface
+    [m g, 0, 0, 0]; rotor interface the hover speed on every rotor. The position
+    interface has none (its command is a place, not an action)."""
+    a = torch.zeros(4, batch.D, dtype=F64)
+    if len(batch.fp_idx):
+        P = batch.P_fp
+        mg = P["mass"][0] * P["gravity"][0]
+        if batch.control == CTRL_ATT_PID:
+            a[3, batch.fp_idx] = mg
+        elif batch.control == CTRL_TORQUE:
+            a[0, batch.fp_idx] = mg
+        elif batch.control == CTRL_ROTOR:
+            a[:, batch.fp_idx] = rotor_speed_for_thrust(0.25 * mg[None, :].expand(4, -1), P)
+        else:
+            raise ValueError("the position interface has no hover action")
+    if len(batch.id_idx):
+        P = batch.P_id
+        a[3, batch.id_idx] = P["mass"][0] * P["gravity"][0] / P["c_f"][0]
+    return a
+
+
 def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
             gain: Optional[torch.Tensor] = None, gain_index=None,
             ref_amp: float = 1.0, ref_period: float = 4.0, ref_offset=None,
             ref_table: Optional[torch.Tensor] = None, w_u: float = 1e-3,
-            with_loss: bool = True, keep_traj: bool = False):
+            with_loss: bool = True, keep_traj: bool = False, reward: Optional[Dict] = None):
     """Roll out ``steps`` steps with per-step commands ``cmds`` [T, 4, D] (or held
     [4, D]). With ``gain`` [G, 4, 13] the applied command is
     u_t = ubar_t + G_w (x_t[0:13] - x_ref(t)). Loss per drone:
     sum_{t=1..T} |p_t - p_ref(t)|^2 + w_u sum_{t=0..T-1} |u_t|^2, with t_n = n dt.
+
+    With ``reward`` = dict(w_tilt, w_act[4], w_dact[4]) the loss is instead minus
+    the summed reward of the paper's BPTT tracking task (Methods,
+    "Backpropagation Through Time"): for t = 0..T-1, with the action a_t = u_t
+    and the state x_{t+1} it leads to,
+      r_t = exp(-2 |p_{t+1} - p_ref(t+1)|) - w_tilt * tilt(x_{t+1})
+            - sum_i w_act_i (a_t,i - a_hover,i)^2 - sum_i w_dact_i (a_t,i - a_{t-1},i)^2
+    (reading: the previous action before the first step is the hover action;
+    the goal is the reference point; norms have gradient 0 at their kink).
     Returns dict(x=x_T, loss=[D] or None, traj=[T+1, S, D] or None)."""
     x = x0
     D = batch.D
@@ -495,6 +550,11 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
         return p, (batch.reference_state(p, v) if G is not None else None)
 
     held = None
+    if reward is not None:
+        a_hover = hover_action(batch)
+        w_act = t64(reward["w_act"])[:, None]
+        w_dact = t64(reward["w_dact"])[:, None]
+        u_prev = a_hover
     for n in range(steps):
         ubar = cmds[n] if cmds.dim() == 3 else cmds
         if G is not None:
@@ -503,13 +563,19 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
             u = ubar + (G * e.T[:, None, :]).sum(2).T
         else:
             u = ubar
-        if with_loss:
+        if with_loss and reward is None:
             loss = loss + w_u * (u * u).sum(0)
         x, held = batch.step_at(x, u, n, held)
         if with_loss:
             p_ref, _ = ref(n + 1)
             d = x[0:3] - p_ref
-            loss = loss + (d * d).sum(0)
+            if reward is None:
+                loss = loss + (d * d).sum(0)
+            else:
+                r = (torch.exp(-2 * _safe_sqrt((d * d).sum(0))) - reward["w_tilt"] * tilt_angle(batch, x)
+                     - (w_act * (u - a_hover) ** 2).sum(0) - (w_dact * (u - u_prev) ** 2).sum(0))
+                loss = loss - r
+                u_prev = u
         if keep_traj:
             traj.append(x)
     return {"x": x, "loss": loss if with_loss else None,
@@ -561,7 +627,8 @@ def simulate_held(w, steps: Optional[int] = None, x0=None, store_every: Optional
 def rollout_workload(w, with_grad: bool = False, keep_traj: bool = False):
     b = Batch.from_workload(w)
     kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period,
-              ref_offset=None if w.ref_offset is None else t64(w.ref_offset), w_u=w.w_u)
+              ref_offset=None if w.ref_offset is None else t64(w.ref_offset), w_u=w.w_u,
+              reward=getattr(w, "reward", None))
     gain = None if w.gain is None else t64(w.gain)
     if with_grad:
         return rollout_grad(b, w.x0, w.cmds, w.steps, gain=gain, gain_index=w.gain_index,

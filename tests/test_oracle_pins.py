@@ -506,7 +506,7 @@ def _fd_check(w, n_dirs=4, h=1e-4, seed=0):
     per-step commands, the initial state and the gain vs the autograd gradient."""
     b = O.Batch.from_workload(w)
     kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u,
-              ref_offset=None if w.ref_offset is None else O.t64(w.ref_offset))
+              ref_offset=None if w.ref_offset is None else O.t64(w.ref_offset), reward=w.reward)
     x0, cmds = O.t64(w.x0), O.t64(w.cmds)
     gain = None if w.gain is None else O.t64(w.gain)
     g = O.rollout_grad(b, x0, cmds, w.steps, gain=gain, gain_index=w.gain_index, dloss=w.dloss, **kw)
@@ -984,3 +984,108 @@ def test_gradient_fd_multirate_controller():
     w = W.config5_adjoint(seed=14, n_worlds=6, n_subset=4, steps=31, n_max=3)
     w.ctrl_every = 3
     _fd_check(w)
+
+
+# ---- the BPTT tracking reward ----------------------------------------------------
+
+def test_tilt_angle_matches_scipy():
+    """Angle between the body and world z axes vs SciPy's rotations, for random
+    quaternions (first principles) and ZYX Euler angles (identified)."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(5)
+    n = 64
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    eul = rng.uniform(-1.2, 1.2, size=(n, 3))
+    bf, _ = fp_batch(n, control=O.CTRL_ATT_PID)
+    x = torch.zeros(25, n, dtype=F64)
+    x[3:7] = torch.as_tensor(q.T)
+    zf = Rotation.from_quat(q).apply([0.0, 0.0, 1.0])
+    assert np.allclose(O.tilt_angle(bf, x).numpy(), np.arccos(np.clip(zf[:, 2], -1, 1)), atol=1e-7)
+    wi = W.config4(seed=3, n_worlds=n, steps=1)
+    bi = O.Batch.from_workload(wi)
+    xi = torch.zeros(13, n, dtype=F64)
+    xi[3:6] = torch.as_tensor(eul.T)
+    zi = Rotation.from_euler("ZYX", eul[:, ::-1]).apply([0.0, 0.0, 1.0])
+    assert np.allclose(O.tilt_angle(bi, xi).numpy(), np.arccos(np.clip(zi[:, 2], -1, 1)), atol=1e-7)
+
+
+def _hover_on_reference(w):
+    """Hover at the reference point with the hover action: amplitude-0 reference
+    centred on each drone, zero velocity, no feedback."""
+    b = O.Batch.from_workload(w)
+    a = O.hover_action(b).numpy()
+    w.ref_amp = 0.0
+    w.ref_offset = w.x0[0:3].copy()
+    w.gain = None
+    w.cmds = np.repeat(a[None], w.steps, 0).astype(np.float32)
+    return w
+
+
+@pytest.mark.parametrize("model", ["id", "fp_pid"])
+def test_reward_is_one_per_step_in_hover_on_the_reference(model):
+    if model == "id":
+        w = W.config4(seed=7, n_worlds=5, steps=20)
+        w.x0[6:9] = 0.0
+        w.x0[3:6] = 0.0
+        w.x0[12] = W.MASS * W.GRAVITY / W.ID_CF
+    else:
+        w = W.config2(seed=7, n_worlds=5, steps=20)
+        w.x0[3:7] = np.array([0, 0, 0, 1.0])[:, None]
+        w.x0[7:13] = 0.0
+        w.x0[17:25] = 0.0
+    w = _hover_on_reference(w)
+    w.reward = W.BPTT_REWARD
+    out = O.rollout_workload(w)
+    assert np.allclose(out["loss"].numpy(), -w.steps, atol=1e-9)
+
+
+def test_smoothness_term_telescopes_for_a_held_action():
+    """With the same action at every step the smoothness penalty is paid once,
+    against the hover action before the first step."""
+    w = W.config4(seed=8, n_worlds=4, steps=15)
+    w.gain = None
+    a = O.hover_action(O.Batch.from_workload(w)).numpy() + np.array([0.05, -0.03, 0.02, 0.01])[:, None]
+    w.cmds = np.repeat(a[None], w.steps, 0).astype(np.float32)
+    r0 = dict(W.BPTT_REWARD, w_dact=[0.0] * 4)
+    r1 = dict(W.BPTT_REWARD, w_dact=[1.0, 2.0, 3.0, 4.0])
+    w.reward = r0
+    l0 = O.rollout_workload(w)["loss"].numpy()
+    w.reward = r1
+    l1 = O.rollout_workload(w)["loss"].numpy()
+    da = w.cmds[0].astype(np.float64) - O.hover_action(O.Batch.from_workload(w)).numpy()
+    assert np.allclose(l1 - l0, (np.array(r1["w_dact"])[:, None] * da ** 2).sum(0), rtol=1e-12, atol=1e-12)
+
+
+def _tilted(w, seed):
+    """Start every drone tilted (0.05-0.15 rad) so the tilt term stays away from
+    its kink at the upright orientation, where differences are not derivatives."""
+    rng = np.random.default_rng(seed)
+    x0 = w.x0.astype(np.float64)
+    D = x0.shape[1]
+    ang = rng.uniform(0.05, 0.15, size=D) * rng.choice([-1.0, 1.0], size=(2, D))
+    if x0.shape[0] >= 17:
+        world = np.repeat(np.arange(w.n_worlds), w.drones_per_world)
+        fp = w.model_per_world[world] == W.MODEL_FP
+        q = np.stack([np.sin(ang[0] / 2), np.sin(ang[1] / 2), np.zeros(D), np.ones(D)])
+        q /= np.linalg.norm(q, axis=0, keepdims=True)
+        x0[3:7, fp] = q[:, fp]
+        x0[3:5, ~fp] = ang[:, ~fp]
+    else:
+        x0[3:5] = ang
+    w.x0 = x0.astype(np.float32)
+    return w
+
+
+def test_gradient_fd_reward_identified():
+    w = W.small(4, seed=16)
+    w.steps = 40
+    w.cmds = w.cmds[:40]
+    w.reward = W.BPTT_REWARD
+    _fd_check(_tilted(w, 16), h=1e-5)
+
+
+def test_gradient_fd_reward_first_principles_pid():
+    w = W.config5_adjoint(seed=17, n_worlds=6, n_subset=4, steps=30, n_max=3)
+    w.reward = W.BPTT_REWARD
+    _fd_check(_tilted(w, 17), h=3e-6)

@@ -95,6 +95,7 @@ class Workload:
     w_u: float = 1e-3
     dloss: Optional[np.ndarray] = None    # float32 [D]
     ctrl_every: int = 1                   # onboard controller every n physics steps
+    reward: Optional[dict] = None         # BPTT reward weights (w_tilt, w_act[4], w_dact[4]) or None
 
     @property
     def n_drones_total(self) -> int:
@@ -340,6 +341,10 @@ def config3(seed: int = 1003, n_worlds: int = 64, n_drones: int = 4000,
     return Workload("id_swarm", M, np.full(M, N, np.int32),
                     np.full(M, MODEL_ID, np.uint8), CTRL_ATT_PID, integrator,
                     float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps, _f32(cmds))
+
+
+# weights of the paper's BPTT tracking reward (Methods, BPTT parameter table)
+BPTT_REWARD = {"w_tilt": 0.1, "w_act": [0.12, 0.12, 0.0, 0.02], "w_dact": [1.4, 1.4, 0.0, 0.8]}
 
 
 def config4(seed: int = 1004, n_worlds: int = 1024, steps: int = 500,
