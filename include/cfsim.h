@@ -190,7 +190,28 @@ typedef struct cf_objective {
     float ref_period;         /* P [s], > 0                                      */
     const float* ref_offset;  /* device [3][D] or NULL                           */
     float w_u;                /* command weight, >= 0                            */
+    int32_t kind;             /* CF_OBJ_TRACKING (0) or CF_OBJ_BPTT_REWARD (1)   */
+    float w_tilt;             /* reward: tilt weight, >= 0                       */
+    float w_act[4];           /* reward: weights of (u - u_hover)^2, >= 0        */
+    float w_dact[4];          /* reward: weights of (u_t - u_{t-1})^2, >= 0      */
 } cf_objective;
+
+/*
+ * Objective kinds. CF_OBJ_TRACKING: the loss above. CF_OBJ_BPTT_REWARD: minus
+ * the summed reward of the paper's BPTT tracking task (Methods,
+ * "Backpropagation Through Time"), for t = 0..T-1 with u_t the applied command
+ * and x_{t+1} the state it leads to:
+ *   r_t = exp(-2 |p_{t+1} - p_ref(t+1)|) - w_tilt tilt(x_{t+1})
+ *         - sum_i w_act_i (u_t,i - u_hover,i)^2 - sum_i w_dact_i (u_t,i - u_{t-1},i)^2,
+ * tilt = angle between the body and world z axes, u_{-1} = u_hover, the hover
+ * command of the drone's interface (identified [0, 0, 0, m g / c_f]; attitude
+ * [0, 0, 0, m g]; torque [m g, 0, 0, 0]; rotor: the reference speed on every
+ * rotor). Norms take gradient 0 at their kinks. Not for the position interface
+ * (CF_EINVAL). w_u is unused. The forward keeps the applied commands in a
+ * library buffer for the backward.
+ */
+#define CF_OBJ_TRACKING    0
+#define CF_OBJ_BPTT_REWARD 1
 
 /*
  * cf_create: validate *desc, copy the parameter records and the world layout

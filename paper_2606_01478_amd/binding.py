@@ -23,6 +23,7 @@ CTRL_ROTOR, CTRL_ATT_PID, CTRL_TORQUE, CTRL_POSITION = 0, 1, 2, 3
 INTEG_EULER, INTEG_RK4 = 0, 1
 F_PLAIN_KERNEL, F_NONFINITE_CHECK, F_GRAPH, F_WORKQUEUE, F_NO_AUTOTUNE_CACHE = 0x1, 0x2, 0x4, 0x8, 0x10
 F_SINGLE_LAUNCH = 0x20
+CF_OBJ_TRACKING, CF_OBJ_BPTT_REWARD = 0, 1
 S_FP_ROTOR, S_FP_PID, S_ID = 17, 25, 13
 NPARAM = 96
 NGAIN = 52
@@ -61,7 +62,8 @@ class _Desc(ctypes.Structure):
 
 class _Objective(ctypes.Structure):
     _fields_ = [("gain", c_void_p), ("ref_table", c_void_p), ("ref_amp", c_float), ("ref_period", c_float),
-                ("ref_offset", c_void_p), ("w_u", c_float)]
+                ("ref_offset", c_void_p), ("w_u", c_float), ("kind", c_int32), ("w_tilt", c_float),
+                ("w_act", c_float * 4), ("w_dact", c_float * 4)]
 
 
 class _MppiDesc(ctypes.Structure):
@@ -250,7 +252,10 @@ class Sim:
         _check(self._lib.cf_step_k(self._h, _ptr(state), _ptr(cmd), int(k), _ptr(nonfinite)), "cf_step_k")
 
     @staticmethod
-    def objective(gain=None, ref_table=None, ref_amp=1.0, ref_period=4.0, ref_offset=None, w_u=1e-3):
+    def objective(gain=None, ref_table=None, ref_amp=1.0, ref_period=4.0, ref_offset=None, w_u=1e-3,
+                  reward=None):
+        """Tracking objective; with ``reward`` = dict(w_tilt, w_act[4], w_dact[4]) the
+        BPTT reward objective (CF_OBJ_BPTT_REWARD) instead."""
         o = _Objective()
         o.gain = _ptr(gain)
         o.ref_table = _ptr(ref_table)
@@ -258,6 +263,12 @@ class Sim:
         o.ref_period = float(ref_period)
         o.ref_offset = _ptr(ref_offset)
         o.w_u = float(w_u)
+        if reward is not None:
+            o.kind = CF_OBJ_BPTT_REWARD
+            o.w_tilt = float(reward["w_tilt"])
+            for i in range(4):
+                o.w_act[i] = float(reward["w_act"][i])
+                o.w_dact[i] = float(reward["w_dact"][i])
         o._tensors = (gain, ref_table, ref_offset)
         return o
 

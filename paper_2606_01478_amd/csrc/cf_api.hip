@@ -151,7 +151,7 @@ struct cf_handle {
     int split = 1;       // mixed handles: one launch per model on two streams
     int mode = LM_TILE;
     // scratch
-    DevBuf ref_tab, seg, ggc, wsum, loss_tmp;
+    DevBuf ref_tab, seg, ggc, wsum, loss_tmp, ubuf;
     // last rollout (for the backward's consistency check)
     const float* last_ckpt = nullptr;
     int last_T = -1, last_K = -1;
@@ -621,7 +621,7 @@ cf_status cf_destroy(cf_handle* h) {
     hipFree(h->d_gidx);
     hipFree(h->tiles);
     hipFree(h->counters);
-    for (DevBuf* b : {&h->ref_tab, &h->seg, &h->ggc, &h->wsum, &h->loss_tmp})
+    for (DevBuf* b : {&h->ref_tab, &h->seg, &h->ggc, &h->wsum, &h->loss_tmp, &h->ubuf})
         if (b->p) hipFree(b->p);
     if (h->capture_stream) hipStreamDestroy(h->capture_stream);
     if (h->aux_stream) {
@@ -786,8 +786,31 @@ static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T,
     a.ref_user = 0;
     a.ref_off = nullptr;
     a.w_u = 0.f;
+    a.obj_kind = 0;
+    a.ubuf = nullptr;
     if (!obj) return CF_OK;
     if (!(std::isfinite(obj->w_u) && obj->w_u >= 0.f)) return CF_EINVAL;
+    if (obj->kind != CF_OBJ_TRACKING && obj->kind != CF_OBJ_BPTT_REWARD) return CF_EINVAL;
+    if (obj->kind == CF_OBJ_BPTT_REWARD) {
+        if (h->control == CF_CTRL_POSITION && (h->models & MS_FP)) return CF_EINVAL;
+        bool ok = std::isfinite(obj->w_tilt) && obj->w_tilt >= 0.f;
+        for (int i = 0; i < 4; ++i) {
+            ok = ok && std::isfinite(obj->w_act[i]) && obj->w_act[i] >= 0.f;
+            ok = ok && std::isfinite(obj->w_dact[i]) && obj->w_dact[i] >= 0.f;
+        }
+        if (!ok) return CF_EINVAL;
+        a.obj_kind = 1;
+        a.w_tilt = obj->w_tilt;
+        for (int i = 0; i < 4; ++i) {
+            a.w_act[i] = obj->w_act[i];
+            a.w_dact[i] = obj->w_dact[i];
+        }
+        if (h->D > 0) {
+            hipError_t e = ensure(h->ubuf, (size_t)T * 4 * h->D * sizeof(float));
+            if (e != hipSuccess) return note(h, e);
+            a.ubuf = (float*)h->ubuf.p;
+        }
+    }
     if (obj->gain) {
         if (h->n_gains < 1) return CF_EINVAL;
         if (check_dev(obj->gain, (size_t)h->n_gains * 52 * sizeof(float))) return CF_EINVAL;
@@ -921,9 +944,11 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
     a.g_cmds = g_cmds;
     a.g_x0 = g_x0;
     const int64_t Dm = std::max<int64_t>(h->D, 1);
-    // segment slots 1..K-1 hold recomputed states (slot 0 is the checkpoint itself)
-    if (std::min(K, T) > 1) {
-        if ((e = ensure(h->seg, (size_t)std::min(K, T) * h->S * Dm * sizeof(float))) != hipSuccess)
+    // segment slots 1..K-1 hold recomputed states (slot 0 is the checkpoint itself);
+    // with the reward objective slot K holds the final state of the last segment
+    const int slots = std::min(K, T) + (a.obj_kind == 1 ? 1 : 0);
+    if (slots > 1) {
+        if ((e = ensure(h->seg, (size_t)slots * h->S * Dm * sizeof(float))) != hipSuccess)
             return note(h, e);
         a.seg = (float*)h->seg.p;
     } else {

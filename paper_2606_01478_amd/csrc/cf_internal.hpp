@@ -62,6 +62,9 @@ struct RollArgs {
     int ref_user;
     const float* ref_off;   // [3][D] or null
     float w_u;
+    int obj_kind;           // 0: tracking loss, 1: BPTT reward
+    float w_tilt, w_act[4], w_dact[4];
+    float* ubuf;            // reward: applied commands [T][4][D], written forward, read backward
     // forward outputs
     int K;                  // checkpoint interval
     float* ckpt;            // [ceil(T/K)][S][D] or null

@@ -94,6 +94,79 @@ struct DroneParams {
     IdParams id;
 };
 
+// ---- the BPTT reward objective -------------------------------------------------
+// hover command of the drone's interface: identified [0, 0, 0, m g / c_f];
+// attitude [0, 0, 0, m g]; torque [m g, 0, 0, 0]; rotor the reference speed
+template <int MODEL, int CTRL>
+__device__ __forceinline__ void hover_action(const DroneParams& p, float* ah) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ah[i] = 0.f;
+    if constexpr (MODEL == MODEL_ID) {
+        ah[3] = p.id.f_hover;
+    } else if constexpr (CTRL == CTRL_PID) {
+        ah[3] = p.fp.g / p.fp.inv_m;
+    } else if constexpr (CTRL == CTRL_TORQUE) {
+        ah[0] = p.fp.g / p.fp.inv_m;
+    } else if constexpr (CTRL == CTRL_ROTOR) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ah[i] = p.fp.wr;
+    }
+}
+
+// angle between the body and world z axes from the attitude rows at[4]
+// (quaternion x, y, z, w; or roll, pitch of the identified model's ZYX angles)
+template <int MODEL>
+__device__ __forceinline__ float tilt_of(const float* at) {
+    if constexpr (MODEL == MODEL_FP) {
+        const float n = sqrtf(at[0] * at[0] + at[1] * at[1]);
+        const float c = sqrtf(at[2] * at[2] + at[3] * at[3]);
+        return 2.f * atan2f(n, c);
+    } else {
+        float sf, cf, st, ct;
+        sincosf(at[0], &sf, &cf);
+        sincosf(at[1], &st, &ct);
+        return atan2f(sqrtf(sf * sf + cf * cf * st * st), cf * ct);
+    }
+}
+
+// xb (attitude rows) += g d tilt / d at; zero gradient at the kinks
+template <int MODEL>
+__device__ __forceinline__ void tilt_vjp(const float* at, float g, float* xb) {
+    if constexpr (MODEL == MODEL_FP) {
+        // tilt = 2 atan2(n, c), n = |(qx, qy)|, c = |(qz, qw)|
+        const float n = sqrtf(at[0] * at[0] + at[1] * at[1]);
+        const float c = sqrtf(at[2] * at[2] + at[3] * at[3]);
+        const float Q = n * n + c * c;
+        if (n > 0.f && c > 0.f) {
+            const float gn = g * 2.f * c / (Q * n), gc = -g * 2.f * n / (Q * c);
+            xb[3] += gn * at[0];
+            xb[4] += gn * at[1];
+            xb[5] += gc * at[2];
+            xb[6] += gc * at[3];
+        }
+    } else {
+        // tilt = atan2(S, C), S^2 + C^2 = 1: d tilt = C dS - S dC
+        float sf, cf, st, ct;
+        sincosf(at[0], &sf, &cf);
+        sincosf(at[1], &st, &ct);
+        const float S = sqrtf(sf * sf + cf * cf * st * st), C = cf * ct;
+        if (S > 0.f) {
+            xb[3] += g * (C * sf * cf * ct * ct / S + S * sf * ct);
+            xb[4] += g * (C * cf * cf * st * ct / S + S * cf * st);
+        }
+    }
+}
+
+// attitude rows of a state: quaternion (FP) or roll, pitch (ID)
+template <int MODEL>
+__device__ __forceinline__ void attitude_rows(const float* x, float* at) {
+    at[0] = x[3];
+    at[1] = x[4];
+    at[2] = MODEL == MODEL_FP ? x[5] : 0.f;
+    at[3] = MODEL == MODEL_FP ? x[6] : 0.f;
+}
+
+
 template <int MODEL, int CTRL, bool AERO, class R>
 __device__ __forceinline__ void load_params(const R& rec, DroneParams& p) {
     if constexpr (MODEL == MODEL_FP) {
@@ -158,7 +231,7 @@ __device__ __forceinline__ void store_state(float* dst, size_t D, size_t d, cons
 
 // ---------------------------------------------------------------------------
 // forward rollout of one drone
-template <int MODEL, int CTRL, int INTEG, bool AERO, bool MR, class R>
+template <int MODEL, int CTRL, int INTEG, bool AERO, bool EXT, class R>
 __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
                                                   const float* G) {
     constexpr int S = ModelTraits<MODEL, CTRL>::S;
@@ -184,20 +257,43 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
     load_cmd(a, 0, d, ubar);
     float rc[4] = {0.f, 0.f, 0.f, 0.f};   // held rotor commands
     int phase = 0;                        // step within the controller period
+    const bool rew = EXT && a.has_obj && a.obj_kind == 1;
     for (int t = 0; t < a.T; ++t) {
         float u[4], ev[13], unext[4];
         if (t + 1 < a.T) load_cmd(a, t + 1, d, unext);   // issued early, used next step
         feedback<MODEL>(a, G, x, t, off, f_hover, ubar, u, ev);
-        if (a.has_obj) loss += a.w_u * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3]);
-        model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a, rc, MR ? phase == 0 : true);
-        if constexpr (MR) {
+        if (rew) {
+            // the previous command is read back from the command buffer, so the
+            // reward keeps no values in registers across steps
+            float ah[4];
+            hover_action<MODEL, CTRL>(p, ah);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float up = t > 0 ? a.ubuf[((size_t)(t - 1) * 4 + i) * D + d] : ah[i];
+                const float da = u[i] - ah[i], dd = u[i] - up;
+                loss += a.w_act[i] * da * da + a.w_dact[i] * dd * dd;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a.ubuf[((size_t)t * 4 + i) * D + d] = u[i];
+        } else if (a.has_obj) {
+            loss += a.w_u * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3]);
+        }
+        model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a, rc, EXT ? phase == 0 : true);
+        if constexpr (EXT) {
             if (++phase == a.ctrl_every) phase = 0;
         }
         if (a.has_obj) {
             float pr[3];
             ref_pos(a, t + 1, off, pr);
             const float e0 = x[0] - pr[0], e1 = x[1] - pr[1], e2 = x[2] - pr[2];
-            loss += e0 * e0 + e1 * e1 + e2 * e2;
+            const float d2 = e0 * e0 + e1 * e1 + e2 * e2;
+            if (rew) {
+                float at[4];
+                attitude_rows<MODEL>(x, at);
+                loss += a.w_tilt * tilt_of<MODEL>(at) - expf(-2.f * sqrtf(d2));
+            } else {
+                loss += d2;
+            }
         }
         const int tn = t + 1;
         if (a.ckpt && tn < a.T && (tn % a.K) == 0) store_state<MODEL, S>(a.ckpt + (size_t)(tn / a.K) * SD, D, d, x, p);
@@ -236,7 +332,7 @@ __device__ __forceinline__ void block_commands(const RollArgs& a, const DronePar
 
 // ---------------------------------------------------------------------------
 // adjoint of one drone's rollout
-template <int MODEL, int CTRL, int INTEG, bool AERO, bool MR, class R>
+template <int MODEL, int CTRL, int INTEG, bool AERO, bool EXT, class R>
 __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
                                                   const float* G, float* gl, int gs) {
     constexpr int S = ModelTraits<MODEL, CTRL>::S;
@@ -264,9 +360,13 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
     // controller slower than the physics (first-principles, onboard controller):
     // the commands of a block are held over its steps, so their adjoints are
     // summed over the block (rcb) and taken through the controller at its start
-    constexpr bool HAS_CTRL = (MR && MODEL == MODEL_FP && CTRL != CTRL_ROTOR);
+    constexpr bool HAS_CTRL = (EXT && MODEL == MODEL_FP && CTRL != CTRL_ROTOR);
     const int n_c = HAS_CTRL ? a.ctrl_every : 1;
     float rch[4] = {0.f, 0.f, 0.f, 0.f}, rcb[4] = {0.f, 0.f, 0.f, 0.f};
+    // reward objective: its terms read the neighbouring commands from the command
+    // buffer and the attitude of x_{t+1} from memory, so it keeps no values in
+    // registers across steps
+    const bool rew = EXT && a.has_obj && a.obj_kind == 1;
     const int nseg = (a.T + a.K - 1) / a.K;
     for (int s = nseg - 1; s >= 0; --s) {
         const int t0 = s * a.K;
@@ -292,7 +392,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
             load_cmd(a, t0 + j, d, ubar);
             feedback<MODEL>(a, G, x, t0 + j, off, f_hover, ubar, u, ev);
             model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a, rcf, (t0 + j) % n_c == 0);
-            if (j + 1 < t1 - t0) store_rows<S>(a.seg + (size_t)(j + 1) * SD, D, d, x);
+            if (j + 1 < t1 - t0 || rew) store_rows<S>(a.seg + (size_t)(j + 1) * SD, D, d, x);
         }
         float pn[3];  // position of x_{t+1}
         if (s == nseg - 1) {
@@ -312,8 +412,25 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
             if (a.has_obj) {
                 float pr[3];
                 ref_pos(a, t + 1, off, pr);
+                if (rew) {
+                    // -exp(-2 |e|) and w_tilt tilt at x_{t+1}: a recomputed slot, the
+                    // next checkpoint, or the last segment's final state (extra slot)
+                    const float* nx = (t + 1 < t1 || s == nseg - 1) ? a.seg + (size_t)(t + 1 - t0) * SD
+                                                                   : a.ckpt_in + (size_t)(s + 1) * SD;
+                    float an[4];
 #pragma unroll
-                for (int j = 0; j < 3; ++j) lam[j] += two_seed * (pn[j] - pr[j]);
+                    for (int j = 0; j < 4; ++j) an[j] = (MODEL == MODEL_FP || j < 2) ? nx[(3 + j) * D + d] : 0.f;
+                    const float e0 = pn[0] - pr[0], e1 = pn[1] - pr[1], e2 = pn[2] - pr[2];
+                    const float dn = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+                    const float g = dn > 0.f ? seed * 2.f * expf(-2.f * dn) / dn : 0.f;
+                    lam[0] += g * e0;
+                    lam[1] += g * e1;
+                    lam[2] += g * e2;
+                    tilt_vjp<MODEL>(an, seed * a.w_tilt, lam);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) lam[j] += two_seed * (pn[j] - pr[j]);
+                }
             }
             float u[4], ev[13];
             feedback<MODEL>(a, G, xc, t, off, f_hover, uc, u, ev);
@@ -340,7 +457,23 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
                 }
             }
             if (!held) model_step_vjp<MODEL, CTRL, INTEG>(xc, u, p, a, lam, xb, ub);
-            if (a.has_obj) {
+            if (rew) {
+                // action terms: (u_t - u_hover)^2, (u_t - u_{t-1})^2 and, from the
+                // next step, (u_{t+1} - u_t)^2
+                float ah[4], up[4], un[4];
+                hover_action<MODEL, CTRL>(p, ah);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    up[i] = t > 0 ? a.ubuf[((size_t)(t - 1) * 4 + i) * D + d] : ah[i];
+                    un[i] = t + 1 < a.T ? a.ubuf[((size_t)(t + 1) * 4 + i) * D + d] : u[i];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float gi = a.w_act[i] * (u[i] - ah[i]) + a.w_dact[i] * (u[i] - up[i])
+                                     - a.w_dact[i] * (un[i] - u[i]);
+                    ub[i] += two_seed * gi;
+                }
+            } else if (a.has_obj) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) ub[i] += two_seed * a.w_u * u[i];
             }
@@ -388,18 +521,20 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 // chain is not stretched, and the wide work fills the remaining issue slots.
 __device__ __forceinline__ void rollout_priority() { __builtin_amdgcn_s_setprio(3); }
 
-template <bool BWD, int MODEL, int CTRL, int INTEG, bool AERO, bool MR, class R>
+template <bool BWD, int MODEL, int CTRL, int INTEG, bool AERO, bool EXT, class R>
 __device__ __forceinline__ void rollout_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
                                               const float* G, float* gl, int gs) {
     if constexpr (BWD) {
-        rollout_bwd_drone<MODEL, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
+        rollout_bwd_drone<MODEL, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
     } else {
-        rollout_fwd_drone<MODEL, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G);
+        rollout_fwd_drone<MODEL, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G);
     }
 }
 
-// MR: variant for an onboard controller slower than the physics
-template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
+// EXT: the extended variant, for an onboard controller slower than the physics
+// and for the BPTT reward objective; the plain variant keeps the registers of
+// the every-step, tracking-loss path
+template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool EXT>
 __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
     rollout_priority();
     const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -410,11 +545,11 @@ __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
     extern __shared__ float roll_lds[];   // backward: [NG][blockDim.x] gain-gradient sums
     float* gl = roll_lds + threadIdx.x;
     const int gs = blockDim.x;
-    if constexpr (MODELS == MS_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
-    else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
+    if constexpr (MODELS == MS_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
+    else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
 }
 
-template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
+template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool EXT>
 __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __restrict__ tiles, int S_h) {
     rollout_priority();
     const int4 td = tiles[blockIdx.x];
@@ -439,16 +574,16 @@ __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __
     float* gl = roll_lds + threadIdx.x;
     const int gs = blockDim.x;
     if constexpr (MODELS == MS_FP) {
-        rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
+        rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
     } else if constexpr (MODELS == MS_ID) {
-        rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
+        rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
     } else {
-        if (model == MODEL_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
-        else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO, MR>(rec, a, d, w, S_h, G, gl, gs);
+        if (model == MODEL_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
+        else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
     }
 }
 
-template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
+template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool EXT>
 static hipError_t launch_roll_k(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                 hipStream_t s) {
     const int S_h = a.S_h;
@@ -457,26 +592,26 @@ static hipError_t launch_roll_k(const KernelSel& ks, const RollArgs& a, const in
             const int bs = ks.tile;
             const unsigned grid = (unsigned)((a.D + bs - 1) / bs);
             const size_t shmem = BWD ? (size_t)NG * bs * sizeof(float) : 0;
-            hipLaunchKernelGGL((k_rollout_lane<BWD, MODELS, CTRL, INTEG, AERO, MR>), dim3(grid), dim3(bs), shmem, s, a,
+            hipLaunchKernelGGL((k_rollout_lane<BWD, MODELS, CTRL, INTEG, AERO, EXT>), dim3(grid), dim3(bs), shmem, s, a,
                                S_h);
         } else {
             return hipErrorInvalidValue;
         }
     } else {
         const size_t shmem = BWD ? (size_t)NG * ks.tile * sizeof(float) : 0;
-        hipLaunchKernelGGL((k_rollout_tile<BWD, MODELS, CTRL, INTEG, AERO, MR>), dim3(n_tiles), dim3(ks.tile), shmem, s,
+        hipLaunchKernelGGL((k_rollout_tile<BWD, MODELS, CTRL, INTEG, AERO, EXT>), dim3(n_tiles), dim3(ks.tile), shmem, s,
                            a, tiles, S_h);
     }
     return hipGetLastError();
 }
 
-// the slow-controller variant exists only where there is an onboard controller
+// the extended variant serves a slower onboard controller and the reward objective
 template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
 static hipError_t launch_roll_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                 hipStream_t s) {
-    if constexpr (MODELS != MS_ID && CTRL != CTRL_ROTOR) {
-        if (a.ctrl_every > 1) return launch_roll_k<BWD, MODELS, CTRL, INTEG, AERO, true>(ks, a, tiles, n_tiles, s);
-    }
+    constexpr bool CAN_MR = MODELS != MS_ID && CTRL != CTRL_ROTOR;
+    if ((CAN_MR && a.ctrl_every > 1) || (a.has_obj && a.obj_kind == 1))
+        return launch_roll_k<BWD, MODELS, CTRL, INTEG, AERO, true>(ks, a, tiles, n_tiles, s);
     return launch_roll_k<BWD, MODELS, CTRL, INTEG, AERO, false>(ks, a, tiles, n_tiles, s);
 }
 

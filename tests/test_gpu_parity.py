@@ -126,7 +126,8 @@ def _rollout_grads(w, K, sim=None):
     x0, cmds = dev(w.x0), dev(w.cmds)
     gain = None if w.gain is None else dev(w.gain)
     off = None if w.ref_offset is None else dev(w.ref_offset)
-    obj = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, ref_offset=off, w_u=w.w_u)
+    obj = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, ref_offset=off, w_u=w.w_u,
+                          reward=w.reward)
     nseg = (T + K - 1) // K
     ckpt = torch.empty((nseg, sim.S, sim.D), device="cuda")
     loss = torch.empty(sim.D, device="cuda")
