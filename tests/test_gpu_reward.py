@@ -85,3 +85,13 @@ def test_bptt_on_the_paper_reward(gpu_lib):
     # the start is already close to the reference (reward about 0.85 per step of
     # a maximum of 1), so the gain is modest: the reward ends higher than it began
     assert losses[-1] < losses[0] - 0.004 * abs(losses[0]), (losses[0], losses[-1])
+
+
+def test_reward_with_slow_controller(gpu_lib):
+    """The reward objective and a PID running every third step together
+    (checkpoint interval 3)."""
+    w = W.config5_adjoint(seed=37, n_worlds=10, n_subset=6, steps=61, n_max=50)
+    w.reward = W.BPTT_REWARD
+    w.ctrl_every = 3
+    w = _tilted(w, 37)
+    _check_against_oracle(w, _rollout_grads(w, 3))
