@@ -591,8 +591,13 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
         return fail(e);
     if ((e = hipMemcpy(h->d_gidx, gidx.data(), M * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e);
-    if ((e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking)) != hipSuccess) return fail(e);
-    if ((e = hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking)) != hipSuccess) return fail(e);
+    // streams beyond the caller's are created only where they are used (the
+    // auxiliary stream for mixed handles here, the capture stream at the first
+    // graph capture): with few hardware queues per process, every extra stream
+    // raises the chance that two busy streams share one
+    if (h->models == MS_BOTH &&
+        (e = hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking)) != hipSuccess)
+        return fail(e);
     if ((e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming)) != hipSuccess) return fail(e);
     if ((e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming)) != hipSuccess) return fail(e);
 
@@ -756,6 +761,9 @@ cf_status cf_step_k(cf_handle* h, float* state, const float* cmd, int32_t k, uin
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         if (h->graphs.size() >= 64) clear_graphs(h);
+        if (!h->capture_stream &&
+            (e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+            return note(h, e);
         hipStream_t cs = h->capture_stream;
         if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return note(h, e);
         cf_status st = enqueue_steps(h, state, cmd, k, nf, cs, plain);
