@@ -24,6 +24,10 @@
  *     to one call must not overlap unless stated.
  *   - Streams: all device work is enqueued on the handle's HIP stream and is
  *     asynchronous; only cf_create, cf_destroy and cf_autotune synchronise.
+ *     A handle holding both models owns one more non-blocking stream (its
+ *     second per-model launch, forked and joined with events), and a handle
+ *     created with CF_F_GRAPH creates a capture stream at its first capture;
+ *     no other streams are created.
  *   - Errors: every call returns a cf_status. Argument validation happens on
  *     the host before anything is enqueued; a call that fails validation
  *     writes no output. Asynchronous device faults are reported as
