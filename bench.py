@@ -79,6 +79,8 @@ def parse():
                    help="skip the gradient-throughput measurement (2^20 worlds, 10 steps)")
     p.add_argument("--no-bptt", action="store_true",
                    help="skip the BPTT training-loop measurement (16 worlds, 40-step rollouts)")
+    p.add_argument("--interfaces", action="store_true",
+                   help="also time held steps behind each control interface (2^20 single-drone worlds)")
     return p.parse_args()
 
 
@@ -329,6 +331,8 @@ def main():
         out["bptt"] = bptt_benchmark(B, W, dev, t2d, ev)
     if args.hbm_sweep:
         out["hbm_sweep"] = hbm_sweep(B, W, dev, t2d, ev)
+    if args.interfaces:
+        out["interfaces"] = interface_benchmark(B, W, dev, t2d, ev)
 
     if args.copy_probe:
         src = torch.empty(64 * 1024 * 1024, device=dev)
@@ -415,6 +419,45 @@ def gradient_benchmark(B, W, dev, t2d, ev, reps=10):
             "ms_fwd_bwd": ms, "gradients_per_s": wg.n_worlds / (ms * 1e-3),
             "drone_steps_per_s": wg.n_worlds * T / (ms * 1e-3), "reps": reps,
             "paper_context": "9e6 gradients/s at 1e6 environments x 10 steps (other hardware)"}
+
+
+def interface_benchmark(B, W, dev, t2d, ev, n=1 << 20, T=100, reps=5):
+    """Held-command RK4 steps of the first-principles model behind each control
+    interface, and with the attitude controller at a fifth of the physics rate:
+    2^20 single-drone worlds, T steps per call, each handle with the launch shape
+    the autotuner picks for it."""
+    import dataclasses
+
+    import torch
+    pid = W.config2(n_worlds=n, steps=T)
+    cases = [("rotor_speeds", W.config1(n_worlds=n, steps=1)),
+             ("attitude_pid", pid),
+             ("attitude_pid_ctrl_every_5", dataclasses.replace(pid, ctrl_every=5)),
+             ("thrust_torques", W.fp_torque(n_worlds=n)),
+             ("position", W.fp_position(n_worlds=n))]
+    rows = []
+    for name, w in cases:
+        sim = B.Sim.from_workload(w)
+        x0 = t2d(w.x0)
+        cmd = t2d(w.cmds[0] if w.cmds.ndim == 3 else w.cmds)
+        st = x0.clone()
+        sim.autotune(st, cmd, T, 500)
+        sim.step_k(st, cmd, T)
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(reps):
+            sim.step_k(st, cmd, T)
+        b.record()
+        torch.cuda.synchronize()
+        if sim.last_error() != 0:
+            raise RuntimeError(f"device error in the interface benchmark ({name})")
+        ms = a.elapsed_time(b) / (reps * T)
+        rows.append({"interface": name, "drones": w.n_drones_total, "state_dim": sim.S,
+                     "ctrl_every": w.ctrl_every, "ms_per_step": ms,
+                     "drone_steps_per_s": w.n_drones_total / (ms * 1e-3), "launch": sim.launch_config()})
+        sim.close()
+    return rows
 
 
 def hbm_sweep(B, W, dev, t2d, ev):
