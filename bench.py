@@ -40,8 +40,8 @@ SPEC_HBM_GBS = 8000.0
 # "workqueue,tile,chunk,per_model"; summary in
 # profiles/held_step_uneven_mixed_2048w_T1000.md. Valid only for the kernel
 # sources it was measured on (SHA-256 below), reported as null otherwise.
-PROFILED_TRAFFIC = {"sources_sha256": "e3092a3588025d9a8b6699c25cf943112bc47b92a9992606cd473a912aa336f5",
-                    "by_launch": {"1,64,100,1": 1997395368.0}}
+PROFILED_TRAFFIC = {"sources_sha256": "dbf378fd9076022f2c5c91d7074b47ae80b0ec70b65a2d78e8a6ff9c51be621a",
+                    "by_launch": {"1,64,100,1": 1988140298.0}}
 
 
 def kernel_sources_sha256() -> str:

@@ -293,7 +293,10 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
  * cmd (device [S][D], [4][D], not modified) for about budget_ms, keep the
  * fastest for this handle and store it in the autotune cache file
  * ($CFSIM_AUTOTUNE_CACHE, default $HOME/.cache/cfsim_autotune.txt: one line per
- * handle signature with the chosen shape and its time). Synchronises.
+ * handle signature with the chosen shape and its time; the signature is the
+ * device architecture, worlds, drones, first-principles worlds, interface,
+ * integrator, whether drag or rotor inertia is present, and the control
+ * interval). Synchronises.
  */
 cf_status cf_autotune(cf_handle* h, const float* state, const float* cmd, int32_t k, int32_t budget_ms);
 

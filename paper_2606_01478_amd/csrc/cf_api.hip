@@ -322,8 +322,9 @@ std::string signature(const cf_handle* h) {
     char buf[256];
     int nfp = 0;
     for (auto m : h->model_of_world) nfp += (m == MODEL_FP);
-    std::snprintf(buf, sizeof buf, "v2|%s|M%d|D%lld|fp%d|c%d|i%d", h->arch.c_str(), h->M, (long long)h->D, nfp,
-                  h->control, h->integ);
+    // every field that selects a different kernel or changes its work per step
+    std::snprintf(buf, sizeof buf, "v3|%s|M%d|D%lld|fp%d|c%d|i%d|a%d|n%d", h->arch.c_str(), h->M, (long long)h->D,
+                  nfp, h->control, h->integ, h->aero, h->ctrl_every);
     return buf;
 }
 
