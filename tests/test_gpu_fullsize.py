@@ -1,6 +1,8 @@
 """Parity at the full workload sizes, in the launch configuration bench.py times:
 every drone where the oracle finishes in seconds, otherwise drones sampled one
 by one (drones never interact) plus properties that hold at any size."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -195,3 +197,32 @@ def test_goal_gradient_2p20_worlds_sampled(gpu_lib):
     assert torch.all((loss[ii].double().cpu() - lr).abs() <= 1e-4 * lr.abs().clamp_min(1e-2))
     assert_grad_close(g_cmds[:, :, ii], ref["g_cmds"], "goal g_cmds")
     assert_grad_close(g_x0[:, ii], ref["g_x0"], "goal g_x0")
+
+
+def _interface_case(name):
+    n, T = 1 << 20, 100
+    if name == "torque":
+        return W.fp_torque(n_worlds=n, steps=T)
+    if name == "position":
+        return W.fp_position(n_worlds=n, steps=T)
+    return dataclasses.replace(W.config2(n_worlds=n, steps=T), ctrl_every=5)
+
+
+@pytest.mark.parametrize("name", ["torque", "position", "pid_every_5"])
+def test_interfaces_2p20_worlds_sampled(gpu_lib, name):
+    """The interface measurement's workloads (2^20 single-drone worlds, 100 held
+    steps, launch shape autotuned as the measurement does): 256 sampled drones
+    against the oracle, and every state finite."""
+    w = _interface_case(name)
+    sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
+    x, u = dev(w.x0), dev(w.cmds)
+    sim.autotune(x, u, w.steps, 300)
+    sim.step_k(x, u, w.steps)
+    torch.cuda.synchronize()
+    assert sim.last_error() == 0
+    assert bool(torch.isfinite(x).all())
+    idx = np.random.default_rng(7).choice(w.n_drones_total, 256, replace=False)
+    ws = sample_drones(w, idx)
+    ii = torch.as_tensor(idx, device="cuda")
+    assert_states_close(x[:, ii], O.simulate_held(ws), ws, what=f"{name} 2^20 worlds, sampled")
+    sim.close()
