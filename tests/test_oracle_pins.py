@@ -1089,3 +1089,108 @@ def test_gradient_fd_reward_first_principles_pid():
     w = W.config5_adjoint(seed=17, n_worlds=6, n_subset=4, steps=30, n_max=3)
     w.reward = W.BPTT_REWARD
     _fd_check(_tilted(w, 17), h=3e-6)
+
+
+# ---- the figure-eight reference of the tracking objective (reading r19) -----------------
+
+def _eight_batch():
+    """Two first-principles and two identified single-drone worlds with distinct
+    masses and thrust scalings, so per-drone reference rows are told apart."""
+    n = 4
+    P = W.empty_params(n)
+    masses = np.array([0.027, 0.031, 0.024, 0.035])
+    W.fill_fp_airframe(P, np.arange(2), masses[:2], np.tile(W.INERTIA, (2, 1)))
+    W.fill_id_model(P, np.arange(2, 4), np.tile(W.ID_GAIN, (2, 1)), np.tile(W.ID_TAU, (2, 1)))
+    P["mass"][2:4, 0] = masses[2:]
+    P["c_f"][2:4, 0] = [0.9, 1.2]
+    b = O.Batch(np.ones(n, np.int64), np.array([0, 0, 1, 1]), P, O.CTRL_ATT_PID, O.RK4, 0.002)
+    b.params_in = P
+    return b, masses
+
+
+def test_figure_eight_passes_its_quarter_points():
+    """A sin(2 pi t/P), (A/2) sin(4 pi t/P): through the origin at t = 0 and P/2,
+    at (A/sqrt2, +-A/2) at t = P/8 and 3P/8, at (A, 0) at t = P/4; there the
+    curve moves along -y at speed 2 pi A/P, and through the origin at t = 0 it
+    moves along the diagonal (1, 1) at speed 2 sqrt2 pi A/P."""
+    b, _ = _eight_batch()
+    A, Pd = 1.3, 4.0
+    s = 1.0 / math.sqrt(2.0)
+    pts = {0.0: (0.0, 0.0), Pd / 8: (A * s, A / 2), Pd / 4: (A, 0.0), 3 * Pd / 8: (A * s, -A / 2),
+           Pd / 2: (0.0, 0.0)}
+    for t, (x, y) in pts.items():
+        p, _ = b.figure_eight(t, A, Pd, None)
+        assert torch.allclose(p[:, 0], torch.tensor([x, y, 0.0], dtype=F64), atol=1e-14), t
+    w0 = 2 * math.pi / Pd
+    _, v = b.figure_eight(Pd / 4, A, Pd, None)
+    assert torch.allclose(v[:, 0], torch.tensor([0.0, -A * w0, 0.0], dtype=F64), atol=1e-13)
+    _, v = b.figure_eight(0.0, A, Pd, None)
+    assert torch.allclose(v[:, 0], torch.tensor([A * w0, A * w0, 0.0], dtype=F64), atol=1e-13)
+    _, v = b.figure_eight(Pd / 2, A, Pd, None)
+    assert torch.allclose(v[:, 0], torch.tensor([-A * w0, A * w0, 0.0], dtype=F64), atol=1e-13)
+
+
+def test_figure_eight_is_a_periodic_gerono_lemniscate():
+    """Every point satisfies the lemniscate of Gerono's implicit equation
+    y^2 = x^2 (1 - x^2 / A^2) with z = 0, and p(t + P) = p(t)."""
+    b, _ = _eight_batch()
+    A, Pd = 0.8, 3.0
+    for t in np.random.default_rng(3).uniform(0.0, 10.0, 40):
+        p, _ = b.figure_eight(float(t), A, Pd, None)
+        x, y, z = (float(c) for c in p[:, 0])
+        assert abs(y * y - x * x * (1.0 - x * x / (A * A))) <= 1e-14
+        assert z == 0.0
+        p2, _ = b.figure_eight(float(t) + Pd, A, Pd, None)
+        assert torch.allclose(p, p2, atol=1e-13)
+
+
+def test_figure_eight_velocity_is_the_derivative_of_the_position():
+    """v_ref equals a central difference of p_ref (h = 1e-5: truncation ~1e-10)."""
+    b, _ = _eight_batch()
+    A, Pd, h = 1.0, 4.0, 1e-5
+    for t in np.random.default_rng(4).uniform(0.0, 8.0, 25):
+        t = float(t)
+        _, v = b.figure_eight(t, A, Pd, None)
+        pp, _ = b.figure_eight(t + h, A, Pd, None)
+        pm, _ = b.figure_eight(t - h, A, Pd, None)
+        assert torch.allclose((pp - pm) / (2 * h), v, atol=1e-8)
+
+
+def test_figure_eight_offset_translates_position_only():
+    b, _ = _eight_batch()
+    off = torch.as_tensor(np.random.default_rng(5).normal(size=(3, 4)))
+    p0, v0 = b.figure_eight(0.7, 1.0, 4.0, None)
+    p1, v1 = b.figure_eight(0.7, 1.0, 4.0, off)
+    assert torch.allclose(p1 - p0, off, atol=1e-15)
+    assert torch.equal(v1, v0)
+
+
+def test_reference_state_rows_per_model():
+    """First principles: [p, (0, 0, 0, 1), v, 0]; identified: [p, 0, v, 0, m g / c_f]
+    with each drone's own mass and thrust scaling (reading r18). Hover check: an
+    identified drone at its reference thrust state with the level attitude and
+    zero velocity keeps its altitude (the thrust row balances gravity)."""
+    b, masses = _eight_batch()
+    p, v = b.figure_eight(1.1, 1.0, 4.0, None)
+    xr = b.reference_state(p, v)
+    for d in range(2):
+        assert torch.equal(xr[0:3, d], p[:, d])
+        assert torch.equal(xr[3:7, d], torch.tensor([0.0, 0.0, 0.0, 1.0], dtype=F64))
+        assert torch.equal(xr[7:10, d], v[:, d])
+        assert torch.equal(xr[10:13, d], torch.zeros(3, dtype=F64))
+    for d, cf in ((2, 0.9), (3, 1.2)):
+        assert torch.equal(xr[0:3, d], p[:, d])
+        assert torch.equal(xr[3:6, d], torch.zeros(3, dtype=F64))
+        assert torch.equal(xr[6:9, d], v[:, d])
+        assert torch.equal(xr[9:12, d], torch.zeros(3, dtype=F64))
+        assert abs(float(xr[12, d]) - masses[d] * W.GRAVITY / cf) <= 1e-15
+    # the identified drones at [p, 0, 0, 0, f_ref] with command [0, 0, 0, f_ref] hover
+    x = torch.zeros(13, 4, dtype=F64)
+    x[12] = xr[12]
+    x = x[:, 2:4]
+    bi = O.Batch(np.ones(2, np.int64), np.ones(2), {k: v_[2:4] for k, v_ in b.params_in.items()},
+                 O.CTRL_ATT_PID, O.RK4, 0.002)
+    u = torch.zeros(4, 2, dtype=F64)
+    u[3] = x[12]
+    y = run(bi, x.clone(), u, 50)
+    assert torch.allclose(y, x, atol=1e-12)
