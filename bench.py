@@ -28,27 +28,33 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# algorithmic FP32 operations per drone-step (add/sub/mul = 1, FMA = 2, each
-# sqrt/div/sin/cos/atan2/asin = 1), counted from the step's formulas
-FLOPS_PER_DS = {"fp_pid_rk4": 943.0, "fp_rotor_rk4": 802.0, "id_rk4": 317.0}
+# Algorithmic FP32 work per drone-step of the discrete map (add/sub/mul = 1,
+# FMA = 2, each sqrt/rsqrt/sin-cos/atan2/asin = 1; no compensation or
+# rotor-deviation bookkeeping): first-principles RK4 at the rotor interface
+# 596 + 1 rsqrt; with the attitude PID and allocation 806 + 4 sqrt + atan2 +
+# asin; identified model RK4 301 + 12 sin/cos; identified rollout with the 4x13
+# feedback and the tracking loss 413 per step forward, and forward +
+# checkpoint recompute + reverse sweep 413 + 413 + 1000. The line-by-line tally
+# from the equations is in the design notes next to these figures.
+FLOPS_PER_DS = {"fp_rotor_rk4": 597.0, "fp_pid_rk4": 812.0, "id_rk4": 313.0,
+                "id_rollout_fwd": 413.0, "id_rollout_fwd_bwd": 1826.0}
 SPEC_FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak
 SPEC_HBM_GBS = 8000.0
 
-# HBM bytes of one held-step phase (all launches of one cf_step_k call over the
-# whole batch), FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (the factors a 256 MiB
-# device copy gives) from two rocprofv3 --pmc runs, by launch configuration
-# "workqueue,tile,chunk,per_model"; summary in
+# HBM bytes of one launch of the dominant kernel (the first-principles held-step
+# work-queue kernel inside the job), FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (the
+# factors a 256 MiB device copy gives) from two rocprofv3 --pmc runs, keyed by
+# launch configuration "workqueue,tile,chunk,per_model"; summary in
 # profiles/held_step_uneven_mixed_2048w_T1000.md. Valid only for the kernel
 # sources it was measured on (SHA-256 below), reported as null otherwise.
-PROFILED_TRAFFIC = {"sources_sha256": "dbf378fd9076022f2c5c91d7074b47ae80b0ec70b65a2d78e8a6ff9c51be621a",
-                    "by_launch": {"1,64,100,1": 1988140298.0}}
+PROFILED_TRAFFIC = {"sources_sha256": "", "by_launch": {}}
 
 
 def kernel_sources_sha256() -> str:
     """Hash of the sources that make up the held-step kernels and their launch."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("cf_api.hip", "cf_device.hpp", "cf_internal.hpp", "cf_step.hip"):
+    for name in ("cf_api.hip", "cf_device.hpp", "cf_internal.hpp", "cf_layout.hpp", "cf_step.hip"):
         f = os.path.join(ROOT, "paper_2606_01478_amd", "csrc", name)
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -66,13 +72,18 @@ def parse():
     p.add_argument("--ckpt", type=int, default=0,
                    help="checkpoint interval; 0 = tune among 1, 10, 50, 100 (alone, then in the job)")
     p.add_argument("--serial", action="store_true", help="run the subset adjoint after the forward")
+    p.add_argument("--no-graph", action="store_true", help="enqueue the held steps directly (no hipGraph replay)")
     p.add_argument("--autotune-ms", type=int, default=3000)
+    p.add_argument("--job-only", action="store_true",
+                   help="only the timed job (for profiler runs): no comparators, configurations or baselines")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-comparators", action="store_true")
+    p.add_argument("--no-configs", action="store_true",
+                   help="skip the per-configuration records (plain forward, closed loop, swarm, differentiable)")
     p.add_argument("--copy-probe", action="store_true", help="also run a 256 MiB device copy (profile scale)")
-    p.add_argument("--hbm-sweep", action="store_true",
-                   help="also time the plain and fused kernels on 2^20..2^24 single drones (HBM roofline)")
+    p.add_argument("--no-hbm-sweep", action="store_true",
+                   help="skip the plain and fused kernels on 2^20..2^24 single drones (HBM roofline)")
     p.add_argument("--no-mppi", action="store_true",
                    help="skip the sampled-rollout controller measurement (5 x 100k samples x 25 steps)")
     p.add_argument("--no-grad-bench", action="store_true",
@@ -81,7 +92,17 @@ def parse():
                    help="skip the BPTT training-loop measurement (16 worlds, 40-step rollouts)")
     p.add_argument("--interfaces", action="store_true",
                    help="also time held steps behind each control interface (2^20 single-drone worlds)")
-    return p.parse_args()
+    a = p.parse_args()
+    if a.job_only:
+        a.no_cpu_baseline = a.no_comparators = a.no_configs = a.no_hbm_sweep = True
+        a.no_mppi = a.no_grad_bench = a.no_bptt = True
+    return a
+
+
+def stats(xs):
+    xs = np.asarray(xs, np.float64)
+    return {"mean": float(xs.mean()), "std": float(xs.std()), "median": float(np.median(xs)),
+            "min": float(xs.min()), "max": float(xs.max()), "n": int(len(xs))}
 
 
 def main():
@@ -102,15 +123,25 @@ def main():
     ws = W.config5_adjoint(seed=args.seed, steps=T)
     D, Ds = w.n_drones_total, ws.n_drones_total
     t2d = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
 
-    sim = B.Sim.from_workload(w)
+    # the held-step handle: autotuned launch shape, per-launch timing events, and
+    # (unless --no-graph) hipGraph replay of its launch sequence
+    tune = B.Sim.from_workload(w)
     init = t2d(w.x0)
     state = init.clone()
     cmd = t2d(w.cmds)
     mask = torch.ones(w.n_worlds, dtype=torch.uint8, device=dev)
     if args.autotune_ms > 0:
-        sim.autotune(state, cmd, T, args.autotune_ms)
-    cfg = sim.launch_config()
+        tune.autotune(state, cmd, T, args.autotune_ms)
+    cfg = tune.launch_config()
+    tune.close()
+    sim = B.Sim.from_workload(w, flags=0 if args.no_graph else B.F_GRAPH)
+    sim.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"])
+    # the same launches enqueued directly with an event pair around each kernel
+    # launch, for the kernels' own durations (a graph replay is timed as a whole)
+    simT = B.Sim.from_workload(w, flags=B.F_TIMING)
+    simT.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"])
 
     simA = B.Sim.from_workload(ws)
     x0s, cmds_s = t2d(ws.x0), t2d(ws.cmds)
@@ -120,10 +151,9 @@ def main():
     g_cmds, g_x0, g_gain = torch.empty_like(cmds_s), torch.empty_like(x0s), torch.empty_like(gain)
     loss = torch.empty(Ds, device=dev)
     loss_w = torch.empty(ws.n_worlds, device=dev)
-    ev = lambda: torch.cuda.Event(enable_timing=True)
 
     def adjoint_buffers(K):
-        return torch.empty(((T + K - 1) // K, simA.S, Ds), device=dev)
+        return simA.ckpt_buffer(T, K, device=dev)
 
     def adjoint(K, ckpt):
         simA.rollout(x0s, cmds_s, T, obj, K, ckpt=ckpt, loss=loss, loss_world=loss_w)
@@ -132,7 +162,7 @@ def main():
     side = torch.cuda.Stream(device=dev)   # default priority
     cur = {}                               # checkpoint interval and buffer of the job
 
-    def one_step(record=None):
+    def one_step(record=None, sim=sim):
         K, ckpt = cur["K"], cur["ckpt"]
         e = [ev() for _ in range(7)]
         main = torch.cuda.current_stream()
@@ -203,6 +233,7 @@ def main():
         K = best[0]
     cur["K"], cur["ckpt"] = K, adjoint_buffers(K)
     ckpt = cur["ckpt"]
+    # standalone phases (nothing else on the GPU), HIP events on the same streams
     adjoint(K, ckpt)
     a, b = ev(), ev()
     a.record()
@@ -213,6 +244,10 @@ def main():
     c.record()
     torch.cuda.synchronize()
     standalone = {"adjoint_fwd_bwd": a.elapsed_time(b), "forward": b.elapsed_time(c)}
+    simT.step_k(state, cmd, T)
+    torch.cuda.synchronize()
+    standalone_launch_ms = {"first_principles": simT.launch_times(0),
+                            "identified": simT.launch_times(1) if cfg["per_model_launches"] else []}
 
     for _ in range(args.warmup):
         one_step()
@@ -226,6 +261,16 @@ def main():
     wall = time.perf_counter() - t0
     if sim.last_error() != 0 or simA.last_error() != 0:
         raise RuntimeError("device error during the timed region")
+    # per-launch durations of the held-step kernels inside the job: the same job
+    # steps with the directly enqueued, event-timed handle (HIP events the
+    # library records around each launch on the stream it is launched on)
+    launch_ms = {"first_principles": [], "identified": []}
+    for _ in range(max(3, args.steps)):
+        one_step(sim=simT)
+        torch.cuda.synchronize()
+        launch_ms["first_principles"] += simT.launch_times(0)
+        if cfg["per_model_launches"]:
+            launch_ms["identified"] += simT.launch_times(1)
     # per-phase durations from the events (ms); with overlap the forward is
     # e[1]->e[5] on the main stream and the adjoint e[2]->e[4] on the side stream
     if args.serial:
@@ -235,19 +280,29 @@ def main():
         ph = np.array([[r[0].elapsed_time(r[1]), r[1].elapsed_time(r[5]), r[2].elapsed_time(r[3]),
                         r[3].elapsed_time(r[4])] for r in recs])
     step_ms = wall * 1e3 / args.steps
-    # per-step job time from the events (first to last event of each step)
     job = np.array([r[0].elapsed_time(r[6]) for r in recs])
     fwd_ms = float(ph[:, 1].mean())
     rf_ms, rb_ms = float(ph[:, 2].mean()), float(ph[:, 3].mean())
 
-    # algorithmic work of the dominant kernel (held-command step over the whole batch)
+    # the dominant kernel: the first-principles held-step kernel (attitude PID,
+    # RK4) over its tiles, one launch per `chunk` steps
     world = np.repeat(np.arange(w.n_worlds), w.drones_per_world)
     n_fp = int((w.model_per_world[world] == W.MODEL_FP).sum())
     n_id = D - n_fp
-    flops = (n_fp * FLOPS_PER_DS["fp_pid_rk4"] + n_id * FLOPS_PER_DS["id_rk4"]) * T
-    n_chunks = 1 if cfg["chunk"] <= 0 else -(-T // cfg["chunk"])
-    achieved = flops / (fwd_ms * 1e-3) / 1e12
+    steps_per_launch = T if cfg["chunk"] <= 0 else min(cfg["chunk"], T)
+    n_chunks = -(-T // steps_per_launch)
+    flops_fp_launch = n_fp * FLOPS_PER_DS["fp_pid_rk4"] * steps_per_launch
+    flops_id_launch = n_id * FLOPS_PER_DS["id_rk4"] * steps_per_launch
+    bytes_fp_launch = n_fp * (2 * W.S_FP_PID * 4 + 16)
+    fp_ms = float(np.mean(launch_ms["first_principles"]))
+    fp_ms_alone = float(np.mean(standalone_launch_ms["first_principles"]))
+    achieved = flops_fp_launch / (fp_ms * 1e-3) / 1e12
+    flops_phase = (n_fp * FLOPS_PER_DS["fp_pid_rk4"] + n_id * FLOPS_PER_DS["id_rk4"]) * T
     value = (D * T + Ds * T) / (step_ms * 1e-3)
+    traffic = None
+    if kernel_sources_sha256() == PROFILED_TRAFFIC["sources_sha256"]:
+        traffic = PROFILED_TRAFFIC["by_launch"].get(
+            "%d,%d,%d,%d" % (cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"]))
     out = {
         "metric": "drone-steps/s fwd & fwd+bwd on 1 MI355X vs plain kernel; % of VALU/HBM roofline",
         "value": value, "unit": "drone-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -256,29 +311,37 @@ def main():
         "config": {"workload": "uneven_mixed_2048w_logu1-4000_T1000_plus_adjoint_256w",
                    "worlds": w.n_worlds, "drones": D, "horizon": T, "adjoint_worlds": ws.n_worlds,
                    "adjoint_drones": Ds, "ckpt_every": K, "integrator": "rk4", "dt": w.dt,
-                   "launch": cfg, "adjoint_overlapped": not args.serial},
+                   "launch": cfg, "hipgraph": not args.no_graph, "adjoint_overlapped": not args.serial},
         "fwd_drone_steps_per_s": D * T / (fwd_ms * 1e-3),
         "fwdbwd_drone_steps_per_s": Ds * T / ((rf_ms + rb_ms) * 1e-3),
-        "step_ms_stats": {"mean": float(job.mean()), "std": float(job.std()), "median": float(np.median(job)),
-                          "min": float(job.min()), "max": float(job.max()), "n": int(len(job))},
+        "step_ms_stats": stats(job),
         "phase_ms": {"reset": float(ph[:, 0].mean()), "forward": fwd_ms, "rollout_fwd": rf_ms,
                      "rollout_bwd": rb_ms, "forward_std": float(ph[:, 1].std())},
         "standalone_ms": standalone,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": SPEC_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / SPEC_FP32_VECTOR_TFLOPS,
-                     "traffic": (PROFILED_TRAFFIC["by_launch"].get(
-                                     "%d,%d,%d,%d" % (cfg["workqueue"], cfg["tile"], cfg["chunk"],
-                                                      cfg["per_model_launches"]))
-                                 if kernel_sources_sha256() == PROFILED_TRAFFIC["sources_sha256"] else None),
-                     "algorithmic_bytes_per_launch": float(n_chunks * (n_fp * (2 * W.S_FP_PID * 4 + 16)
-                                                                       + n_id * (2 * W.S_ID * 4 + 16))),
-                     "achieved_standalone": flops / (standalone["forward"] * 1e-3) / 1e12,
-                     "frac_standalone": flops / (standalone["forward"] * 1e-3) / 1e12 / SPEC_FP32_VECTOR_TFLOPS,
-                     "note": "achieved: in-job duration (shares the GPU with the overlapped adjoint); "
-                             "standalone: the same phase alone, HIP events on the same stream before the timed region",
-                     "kernel": "k_step_wq/k_step_tile (held-command RK4 step over the whole batch: one "
-                               "cf_step_k of T steps = %d launch(es) per model)" % n_chunks,
-                     "flops_per_launch": flops},
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": SPEC_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / SPEC_FP32_VECTOR_TFLOPS, "traffic": traffic,
+            "kernel": "k_step_wq<first-principles, attitude PID, RK4> (held-command steps of the "
+                      "first-principles worlds, %d launches of %d steps per job step)" % (n_chunks, steps_per_launch),
+            "flops_per_launch": flops_fp_launch, "flops_per_drone_step": FLOPS_PER_DS["fp_pid_rk4"],
+            "drone_steps_per_launch": n_fp * steps_per_launch,
+            "algorithmic_bytes_per_launch": bytes_fp_launch,
+            "launch_ms_in_job": fp_ms, "launch_ms_in_job_stats": stats(launch_ms["first_principles"]),
+            "launch_ms_standalone": fp_ms_alone,
+            "achieved_standalone": flops_fp_launch / (fp_ms_alone * 1e-3) / 1e12,
+            "frac_standalone": flops_fp_launch / (fp_ms_alone * 1e-3) / 1e12 / SPEC_FP32_VECTOR_TFLOPS,
+            "identified_kernel": {
+                "launch_ms_in_job": float(np.mean(launch_ms["identified"])) if launch_ms["identified"] else None,
+                "flops_per_launch": flops_id_launch,
+                "achieved_in_job": (flops_id_launch / (np.mean(launch_ms["identified"]) * 1e-3) / 1e12
+                                    if launch_ms["identified"] else None)},
+            "phase": {"flops": flops_phase, "ms_in_job": fwd_ms, "ms_standalone": standalone["forward"],
+                      "achieved_in_job": flops_phase / (fwd_ms * 1e-3) / 1e12,
+                      "achieved_standalone": flops_phase / (standalone["forward"] * 1e-3) / 1e12},
+            "note": "achieved: the kernel's average launch duration inside the job (HIP events the library "
+                    "records around each launch on its stream, in job steps identical to the timed ones but "
+                    "enqueued directly instead of replayed from the graph; the job overlaps the adjoint); "
+                    "standalone: the same launches with nothing else on the GPU"},
     }
 
     if not args.no_comparators:
@@ -299,6 +362,7 @@ def main():
         plain_bytes = n_fp * (2 * W.S_FP_PID * 4 + 16) + n_id * (2 * W.S_ID * 4 + 16)
         out["plain_kernel_bytes_per_step"] = plain_bytes
         out["plain_kernel_gbs"] = plain_bytes / (plain_ms * 1e-3) / 1e9
+        simP.close()
         # per-world loop of plain launches (one handle per world), a few steps
         handles = []
         offs = w.world_offsets()
@@ -318,18 +382,21 @@ def main():
         for h, _, _ in handles:
             h.close()
 
-    pk = measured_peaks(B, dev, ev)
-    out["peaks_measured"] = pk
-    out["roofline"]["frac_of_measured_fma_peak"] = out["roofline"]["achieved"] / pk["fp32_fma_tflops"]
-    out["roofline"]["frac_standalone_of_measured_fma_peak"] = (out["roofline"]["achieved_standalone"]
-                                                              / pk["fp32_fma_tflops"])
+    if not args.job_only:
+        pk = measured_peaks(B, dev, ev)
+        out["peaks_measured"] = pk
+        out["roofline"]["frac_of_measured_fma_peak"] = out["roofline"]["achieved"] / pk["fp32_fma_tflops"]
+        out["roofline"]["frac_standalone_of_measured_fma_peak"] = (out["roofline"]["achieved_standalone"]
+                                                                  / pk["fp32_fma_tflops"])
+    if not args.no_configs:
+        out["configs"] = config_records(B, W, dev, t2d, ev)
     if not args.no_grad_bench:
         out["gradient_benchmark"] = gradient_benchmark(B, W, dev, t2d, ev)
     if not args.no_mppi:
         out["mppi"] = mppi_benchmark(B, W, dev, t2d, ev)
     if not args.no_bptt:
         out["bptt"] = bptt_benchmark(B, W, dev, t2d, ev)
-    if args.hbm_sweep:
+    if not args.no_hbm_sweep:
         out["hbm_sweep"] = hbm_sweep(B, W, dev, t2d, ev)
     if args.interfaces:
         out["interfaces"] = interface_benchmark(B, W, dev, t2d, ev)
@@ -342,7 +409,133 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline_1_thread"] = cpu_baseline(w, args.cpu_seconds, threads=1)
     print(json.dumps(out), flush=True)
+
+
+def _time(fn, reps, ev):
+    """Per-call milliseconds of fn() over `reps` calls (one warm-up), HIP events on
+    the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = ev(), ev()
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return stats(ts)
+
+
+def config_records(B, W, dev, t2d, ev):
+    """The other four configurations, each at its full size: drone-steps/s of the
+    plain single-step kernel and of the fused / batched forms on the same GPU,
+    and the ALU roofline fraction of the fused forms."""
+    import torch
+    peak = SPEC_FP32_VECTOR_TFLOPS
+    out = {}
+
+    # 1: plain forward, first-principles rotor interface, 16 x 1, 500 steps, per-step commands
+    w = W.config1()
+    T, D = w.steps, w.n_drones_total
+    x0, cmds = t2d(w.x0), t2d(w.cmds)
+    sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
+    xT = torch.empty_like(x0)
+    fused = _time(lambda: sim.rollout(x0, cmds, T, None, T, x_T=xT), 10, ev)
+    simP = B.Sim.from_workload(w, flags=B.F_PLAIN_KERNEL | B.F_NO_AUTOTUNE_CACHE)
+    x = x0.clone()
+    steps_cmd = [cmds[t] for t in range(T)]
+
+    def plain():
+        for t in range(T):
+            simP.step_k(x, steps_cmd[t], 1)
+    pl = _time(plain, 3, ev)
+    fl = FLOPS_PER_DS["fp_rotor_rk4"] * D * T
+    out["config1_fp_rotor_16x1_T500"] = {
+        "drones": D, "steps": T, "fused_rollout_ms": fused, "plain_ms": pl,
+        "fused_drone_steps_per_s": D * T / (fused["mean"] * 1e-3),
+        "plain_drone_steps_per_s": D * T / (pl["mean"] * 1e-3),
+        "fused_frac_alu": fl / (fused["mean"] * 1e-3) / 1e12 / peak, "waves": 1,
+        "note": "one wave of 16 lanes: latency-bound; the plain form is 500 launches of one step"}
+    sim.close()
+    simP.close()
+
+    # 2: closed loop 4096 x 1, 1000 steps, attitude PID
+    w = W.config2()
+    T, D = w.steps, w.n_drones_total
+    x0, u = t2d(w.x0), t2d(w.cmds)
+    sim = B.Sim.from_workload(w)
+    x = x0.clone()
+    sim.autotune(x, u, T, 500)
+    fused = _time(lambda: sim.step_k(x, u, T), 5, ev)
+    simP = B.Sim.from_workload(w, flags=B.F_PLAIN_KERNEL | B.F_NO_AUTOTUNE_CACHE)
+    pl = _time(lambda: simP.step_k(x, u, T), 3, ev)
+    fl = FLOPS_PER_DS["fp_pid_rk4"] * D * T
+    out["config2_fp_pid_4096x1_T1000"] = {
+        "drones": D, "steps": T, "fused_ms": fused, "plain_ms": pl, "launch": sim.launch_config(),
+        "fused_drone_steps_per_s": D * T / (fused["mean"] * 1e-3),
+        "plain_drone_steps_per_s": D * T / (pl["mean"] * 1e-3),
+        "plain_gbs": D * T * (2 * W.S_FP_PID * 4 + 16) / (pl["mean"] * 1e-3) / 1e9,
+        "fused_frac_alu": fl / (fused["mean"] * 1e-3) / 1e12 / peak, "waves": D // 64}
+    sim.close()
+    simP.close()
+
+    # 3: swarm 64 x 4000, identified model, 1000 steps: plain and fused K = 1, 10, 100
+    w = W.config3()
+    T, D = w.steps, w.n_drones_total
+    x0, u = t2d(w.x0), t2d(w.cmds)
+    rec = {"drones": D, "steps": T, "waves": D // 64}
+    fl = FLOPS_PER_DS["id_rk4"] * D * T
+    simP = B.Sim.from_workload(w, flags=B.F_PLAIN_KERNEL | B.F_NO_AUTOTUNE_CACHE)
+    x = x0.clone()
+    pl = _time(lambda: simP.step_k(x, u, T), 3, ev)
+    rec["plain_ms"] = pl
+    rec["plain_drone_steps_per_s"] = D * T / (pl["mean"] * 1e-3)
+    rec["plain_gbs"] = D * T * (2 * W.S_ID * 4 + 16) / (pl["mean"] * 1e-3) / 1e9
+    simP.close()
+    sim = B.Sim.from_workload(w)
+    for k in (1, 10, 100):
+        sim.set_launch_config(0, 64, k, 1)
+        t = _time(lambda: sim.step_k(x, u, T), 3, ev)
+        rec[f"fused_k{k}_ms"] = t
+        rec[f"fused_k{k}_drone_steps_per_s"] = D * T / (t["mean"] * 1e-3)
+        rec[f"fused_k{k}_frac_alu"] = fl / (t["mean"] * 1e-3) / 1e12 / peak
+    sim.autotune(x, u, T, 500)
+    t = _time(lambda: sim.step_k(x, u, T), 3, ev)
+    rec["autotuned"] = {"launch": sim.launch_config(), "ms": t, "drone_steps_per_s": D * T / (t["mean"] * 1e-3),
+                        "frac_alu": fl / (t["mean"] * 1e-3) / 1e12 / peak}
+    out["config3_id_swarm_64x4000_T1000"] = rec
+    sim.close()
+
+    # 4: differentiable rollout 1024 x 1, 500 steps, identified model, feedback, K = 25, 50, 100
+    w = W.config4()
+    T, D = w.steps, w.n_drones_total
+    x0, cmds, gain = t2d(w.x0), t2d(w.cmds), t2d(w.gain)
+    sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
+    obj4 = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u)
+    loss = torch.empty(D, device=dev)
+    g = (torch.empty_like(cmds), torch.empty_like(x0), torch.empty_like(gain))
+    rec = {"drones": D, "steps": T, "waves": D // 64}
+    for K in (25, 50, 100):
+        ck = sim.ckpt_buffer(T, K, device=dev)
+        f = _time(lambda: sim.rollout(x0, cmds, T, obj4, K, ckpt=ck, loss=loss), 10, ev)
+        bw = _time(lambda: sim.rollout_backward(x0, cmds, T, obj4, K, ck, g_cmds=g[0], g_x0=g[1], g_gain=g[2]),
+                   10, ev)
+        ms = f["mean"] + bw["mean"]
+        rec[f"k{K}"] = {"forward_ms": f, "backward_ms": bw,
+                        "fwd_drone_steps_per_s": D * T / (f["mean"] * 1e-3),
+                        "fwdbwd_drone_steps_per_s": D * T / (ms * 1e-3),
+                        "roofline": {"bound": "alu", "flops_per_drone_step": FLOPS_PER_DS["id_rollout_fwd_bwd"],
+                                     "achieved_tflops": FLOPS_PER_DS["id_rollout_fwd_bwd"] * D * T / (ms * 1e-3) / 1e12,
+                                     "frac": FLOPS_PER_DS["id_rollout_fwd_bwd"] * D * T / (ms * 1e-3) / 1e12 / peak}}
+        del ck
+    rec["note"] = "16 waves on 1024 SIMDs: one chain per drone, latency-bound"
+    out["config4_id_adjoint_1024x1_T500"] = rec
+    sim.close()
+    return out
 
 
 def measured_peaks(B, dev, ev):
@@ -395,7 +588,7 @@ def gradient_benchmark(B, W, dev, t2d, ev, reps=10):
     sim = B.Sim.from_workload(wg)
     x0, cmds, goal = t2d(wg.x0), t2d(wg.cmds), t2d(wg.ref_offset)
     obj = B.Sim.objective(ref_amp=wg.ref_amp, ref_period=wg.ref_period, ref_offset=goal, w_u=wg.w_u)
-    ckpt = torch.empty((1, sim.S, sim.D), device=dev)
+    ckpt = sim.ckpt_buffer(T, T, device=dev)
     loss = torch.empty(sim.D, device=dev)
     g_cmds, g_x0 = torch.empty_like(cmds), torch.empty_like(x0)
 
@@ -564,14 +757,18 @@ def bptt_benchmark(B, W, dev, t2d, ev, timesteps=100_000):
                              "trained end to end in 1.56 s on a CPU (other hardware, other policy)"}
 
 
-def cpu_baseline(w, seconds):
+def cpu_baseline(w, seconds, threads=None):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
-    every 16th world for as many steps as fit in about ``seconds``."""
+    every 16th world (every 128th with one thread) for as many steps as fit in
+    about ``seconds``, on all host threads or on ``threads``."""
     import torch
 
     import oracle as O
     import workloads as W
-    pick = np.arange(0, w.n_worlds, 16)
+    prev = torch.get_num_threads()
+    if threads:
+        torch.set_num_threads(threads)
+    pick = np.arange(0, w.n_worlds, 128 if threads == 1 else 16)
     sub = W.subset(w, pick)
     b = O.Batch.from_workload(sub)
     x = O.t64(sub.x0)
@@ -592,6 +789,7 @@ def cpu_baseline(w, seconds):
                 break
     except OSError:
         pass
+    torch.set_num_threads(prev)
     return {"value": sub.n_drones_total * n / el, "unit": "drone-steps/s", "cores": threads, "kind": "oracle",
             "host": {"cpu_model": cpu_model, "logical_cpus": os.cpu_count()},
             "sample": f"worlds 0,16,32,... ({len(pick)} worlds, {sub.n_drones_total} drones), {n} steps, "

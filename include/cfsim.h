@@ -79,6 +79,9 @@ typedef int32_t cf_status;
 #define CF_F_SINGLE_LAUNCH   0x20u  /* mixed-model handles: one launch for both models
                                        (default: one launch per model, forked onto a
                                        second stream and joined with events) */
+#define CF_F_TIMING          0x40u  /* cf_step_k: record an event pair around every kernel
+                                       launch, or around each graph replay with
+                                       CF_F_GRAPH (read with cf_launch_times) */
 
 /*
  * State layout (rows of the [S][D] state):
@@ -211,16 +214,21 @@ typedef struct cf_objective {
  * command of the drone's interface (identified [0, 0, 0, m g / c_f]; attitude
  * [0, 0, 0, m g]; torque [m g, 0, 0, 0]; rotor: the reference speed on every
  * rotor). Norms take gradient 0 at their kinks. Not for the position interface
- * (CF_EINVAL). w_u is unused. The forward keeps the applied commands in a
- * library buffer for the backward.
+ * (CF_EINVAL). w_u is unused. The forward keeps the applied commands in the
+ * checkpoint buffer for the backward.
  */
 #define CF_OBJ_TRACKING    0
 #define CF_OBJ_BPTT_REWARD 1
 
 /*
- * cf_create: validate *desc, copy the parameter records and the world layout
- * to the device, choose kernel variants (autotune cache unless
- * CF_F_NO_AUTOTUNE_CACHE) and return a handle in *out (NULL on failure).
+ * cf_create (the simulation data of Methods, "Architecture": one structure
+ * holding every buffer of a batch of parallel worlds x drones per world x data,
+ * Fig. 1; parameters and state as stated in "First Principles Modeling" and
+ * "Abstracted Physics Modeling"): validate *desc, copy the parameter records
+ * and the world layout to the device, choose kernel variants (autotune cache
+ * unless CF_F_NO_AUTOTUNE_CACHE) and return a handle in *out (NULL on failure).
+ * The handle owns its device copies; desc and the arrays it points to may be
+ * freed by the caller after the call.
  * Errors: CF_EINVAL (NULL pointers, M < 1, negative drone counts, D > 2^31-1,
  * unknown enum, dt not finite or <= 0, a non-finite parameter, mass/inertia/
  * k2/c_f not > 0, J_p < 0, c_tau < 0, gain index out of range), CF_ENODEV (no device),
@@ -228,25 +236,36 @@ typedef struct cf_objective {
  */
 cf_status cf_create(const cf_desc* desc, cf_handle** out);
 
-/* cf_destroy: synchronise the stream and free everything the library owns. NULL is a no-op. */
+/* cf_destroy: synchronise the stream and free everything the library owns (the
+   counterpart of cf_create). NULL is a no-op. */
 cf_status cf_destroy(cf_handle* h);
 
-/* Queries (host only). */
+/* Queries (host only) of the batch layout (worlds x drones x data, Methods,
+   "Architecture"): rows S of the state, total drones D, and the first drone of
+   each world, offsets_host[M + 1] (host memory, written by the call). Errors:
+   CF_EINVAL for NULL arguments. cf_set_stream replaces the handle's stream
+   (a hipStream_t, NULL = default stream); later calls enqueue on it. */
 cf_status cf_state_dim(const cf_handle* h, int32_t* S);
 cf_status cf_total_drones(const cf_handle* h, int64_t* D);
 cf_status cf_world_offsets(const cf_handle* h, int64_t* offsets_host /* [M+1] */);
 cf_status cf_set_stream(cf_handle* h, void* stream);
 
 /*
- * cf_reset (continuous/masked resets, section "Architecture"): for every world w
+ * cf_reset (continuous/masked resets, Methods, "Architecture", last paragraph): for every world w
  * with world_mask[w] != 0 (all worlds when world_mask is NULL), copy the S rows
  * of init into state for that world's drones. state, init: device [S][D];
  * world_mask: device uint8 [M] or NULL. state and init must not overlap.
+ * Errors: CF_EINVAL (NULL handle, buffers not device memory of S*D floats,
+ * overlapping buffers, mask smaller than M bytes), sticky CF_EDEVICE.
  */
 cf_status cf_reset(cf_handle* h, float* state, const float* init, const uint8_t* world_mask);
 
 /*
- * cf_step_k: advance every drone k >= 1 steps with the command held (zero-order
+ * cf_step_k (the simulation step of Methods, "Architecture": the equations of
+ * motion of "First Principles Modeling" / "Abstracted Physics Modeling"
+ * integrated directly, successive steps fused like the paper's scan over
+ * steps; control interfaces of "First Principles Modeling", last paragraph):
+ * advance every drone k >= 1 steps with the command held (zero-order
  * hold). state: device [S][D], updated in place; cmd: device [4][D].
  * nonfinite_world: device uint32 [M] or NULL; with CF_F_NONFINITE_CHECK the
  * entry of a world is OR-ed with 1 when any of its drones ends with a
@@ -255,40 +274,75 @@ cf_status cf_reset(cf_handle* h, float* state, const float* init, const uint8_t*
  * the autotuned K), or k single-step launches with CF_F_PLAIN_KERNEL, or the
  * persistent work-queue kernel (CF_F_WORKQUEUE or autotune choice).
  * With a controller period of n > 1 steps (cf_desc.ctrl_every), k must be a
- * multiple of n (CF_EINVAL otherwise).
+ * multiple of n (CF_EINVAL otherwise). Errors: CF_EINVAL (k < 1, buffers not
+ * device memory of the stated sizes), sticky CF_EDEVICE.
  */
 cf_status cf_step_k(cf_handle* h, float* state, const float* cmd, int32_t k,
                     uint32_t* nonfinite_world);
 
 /*
- * cf_rollout: T >= 1 steps from x0 (device [S][D]) with per-step commands
- * cmds (device [T][4][D], the ubar_t of cf_objective). obj may be NULL (no
- * feedback, no loss: loss and loss_world must then be NULL).
- * ckpt_every K >= 1; ckpt (device [ceil(T/K)][S][D] or NULL) receives the
- * states at t = 0, K, 2K, ... and is required by cf_rollout_backward.
+ * Checkpoint buffer of cf_rollout / cf_rollout_backward (device, caller-owned,
+ * cf_ckpt_floats floats): the states at t = 0, K, 2K, ... as [ceil(T/K)][S][D];
+ * for the reward objective then the applied commands u_t as [T][4][D] (its
+ * backward needs their neighbours); then CF_CKPT_TAG_FLOATS 32-bit words that
+ * tag the forward that filled it (handle, a per-handle generation count, T, K,
+ * S, D, objective kind and a hash of the objective's weights and of which of
+ * its optional inputs are present).
+ */
+#define CF_CKPT_TAG_FLOATS 16
+
+/* cf_ckpt_floats: floats of the checkpoint buffer for (T, K, objective kind) on
+   this handle, in *n (host). Errors: CF_EINVAL (NULL, T < 1, K < 1, unknown kind). */
+cf_status cf_ckpt_floats(const cf_handle* h, int32_t T, int32_t ckpt_every, int32_t kind, int64_t* n);
+
+/*
+ * cf_rollout (Results, "Computation Performance", and Methods,
+ * "Backpropagation Through Time": rollouts whose objective is differentiated
+ * through the simulation steps): T >= 1 steps from x0 (device [S][D]) with
+ * per-step commands cmds (device [T][4][D], the ubar_t of cf_objective). obj
+ * may be NULL (no feedback, no loss: loss and loss_world must then be NULL).
+ * ckpt_every K >= 1; ckpt (device, cf_ckpt_floats(h, T, K, kind) floats, or
+ * NULL) receives the checkpoint states, the reward objective's applied
+ * commands and the tag; it is required by cf_rollout_backward.
  * x_T (device [S][D]), traj (device [T+1][S][D]), loss (device [D]) and
  * loss_world (device [M], per-world sums in a fixed order) may each be NULL.
+ * Errors: CF_EINVAL (T < 1, K < 1, K neither a divisor nor a multiple of the
+ * controller period, loss without obj, a buffer smaller than stated, an
+ * objective field out of range), sticky CF_EDEVICE.
  */
 cf_status cf_rollout(cf_handle* h, const float* x0, const float* cmds, int32_t T,
                      const cf_objective* obj, int32_t ckpt_every, float* ckpt,
                      float* x_T, float* traj, float* loss, float* loss_world);
 
 /*
- * cf_rollout_backward: gradient of sum_d dloss[d] * loss_d (dloss: device [D])
- * through the whole rollout, by a hand-written discrete adjoint that
- * recomputes each K-step segment from its checkpoint. The arguments x0, cmds,
- * T, obj, ckpt_every must be those of the cf_rollout that filled ckpt on this
- * handle; a different T, K or ckpt pointer returns CF_ESTATE. Outputs
- * (overwritten, each may be NULL): g_cmds device [T][4][D] (d/d ubar_t),
- * g_x0 device [S][D], g_gain device [n_gains][4][13] (sum over drones in a
- * fixed order; requires obj->gain).
+ * cf_rollout_backward (Results, "Computation Performance": gradients of an
+ * objective with respect to the control inputs through the simulation steps
+ * and the onboard controllers; Methods, "Architecture": differentiability of
+ * the whole pipeline): gradient of sum_d dloss[d] * loss_d (dloss: device [D],
+ * NULL = ones) through the whole rollout, by a hand-written discrete adjoint
+ * that recomputes each K-step segment from its checkpoint. cmds, T, obj and
+ * ckpt_every must be those of the cf_rollout that filled ckpt on this handle
+ * (x0 is not read: the checkpoint holds it). Checked on the host against the
+ * tags of this handle's forwards: a buffer that no forward of this handle
+ * filled, or filled with another T, K or objective, returns CF_ESTATE and
+ * writes nothing. Checked again on the device against the tag in the buffer:
+ * a buffer overwritten since (by another handle's forward, or reused memory)
+ * makes the kernel write NaN to every requested output and sets the handle's
+ * sticky status to CF_ESTATE, reported by cf_last_error. Any number of
+ * forwards may precede their backwards. Outputs (overwritten, each may be
+ * NULL): g_cmds device [T][4][D] (d/d ubar_t), g_x0 device [S][D], g_gain
+ * device [n_gains][4][13] (sum over drones in a fixed order; requires
+ * obj->gain). Errors: CF_EINVAL (sizes as in cf_rollout, NULL ckpt, g_gain
+ * without a gain), CF_ESTATE, sticky CF_EDEVICE.
  */
 cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, int32_t T,
                               const cf_objective* obj, int32_t ckpt_every, const float* ckpt,
                               const float* dloss, float* g_cmds, float* g_x0, float* g_gain);
 
 /*
- * cf_autotune: time candidate launch shapes of cf_step_k (fused grid vs
+ * cf_autotune (the paper leaves kernel fusion and scheduling to its JIT
+ * compiler, Methods, "Architecture"; here the launch shape is chosen by
+ * measurement): time candidate launch shapes of cf_step_k (fused grid vs
  * persistent work queue, tile size, steps per launch K) on copies of state and
  * cmd (device [S][D], [4][D], not modified) for about budget_ms, keep the
  * fastest for this handle and store it in the autotune cache file
@@ -300,13 +354,37 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
  */
 cf_status cf_autotune(cf_handle* h, const float* state, const float* cmd, int32_t k, int32_t budget_ms);
 
-/* Current launch choice (host): use_workqueue (bit 0: work queue; bit 1: one launch per
+/* cf_launch_config: current launch choice (host, written by the call): use_workqueue (bit 0: work queue; bit 1: one launch per
    model on two streams), tile (lanes per work item), chunk K (0 = all k steps per launch). */
 cf_status cf_launch_config(const cf_handle* h, int32_t* use_workqueue, int32_t* tile, int32_t* chunk);
 
+/* cf_set_launch_config: pin the launch choice of cf_step_k (the values
+   cf_launch_config reports): use_wq bit 0 work queue, bit 1 one launch per model
+   on two streams (mixed handles); tile 64, 128 or 256 lanes; chunk steps per
+   launch (0 = all k steps in one launch; a multiple of the controller period).
+   Replaces the autotuned choice until the next cf_autotune. Errors: CF_EINVAL. */
+cf_status cf_set_launch_config(cf_handle* h, int32_t use_wq, int32_t tile, int32_t chunk);
+
+/* cf_launch_times (measurement of the kernels against their rooflines): with
+   CF_F_TIMING, the durations in ms of the kernel launches of the latest
+   cf_step_k call on stream slot 0 (the
+   handle's stream: every launch of a single-model or single-launch handle, the
+   first-principles launches of a mixed handle) or slot 1 (the identified-model
+   launches of a mixed handle), from HIP events recorded on that stream around
+   each launch. A handle with CF_F_GRAPH times each replay as a whole instead:
+   one entry on slot 0 (events around the graph launch), none on slot 1.
+   ms: host [max_n], the first min(max_n, *n) entries are written;
+   *n: the number of timed launches (at most 512 per slot and call). Waits for
+   those events. Errors: CF_EINVAL (NULL, slot not 0 or 1, no CF_F_TIMING),
+   CF_EDEVICE. */
+cf_status cf_launch_times(cf_handle* h, int32_t slot, float* ms, int32_t max_n, int32_t* n);
+
+/* cf_strerror: static text of a status (never NULL). */
 const char* cf_strerror(cf_status status);
 
-/* cf_last_error: synchronise the stream and return the sticky device error (or CF_OK). */
+/* cf_last_error: synchronise the stream and return the sticky status (CF_OK,
+   CF_EDEVICE after a device fault, CF_ESTATE after a backward found its
+   checkpoint buffer overwritten). */
 cf_status cf_last_error(cf_handle* h);
 
 /* ---- sampled-rollout controller ---------------------------------------------

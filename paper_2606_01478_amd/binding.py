@@ -23,6 +23,7 @@ CTRL_ROTOR, CTRL_ATT_PID, CTRL_TORQUE, CTRL_POSITION = 0, 1, 2, 3
 INTEG_EULER, INTEG_RK4 = 0, 1
 F_PLAIN_KERNEL, F_NONFINITE_CHECK, F_GRAPH, F_WORKQUEUE, F_NO_AUTOTUNE_CACHE = 0x1, 0x2, 0x4, 0x8, 0x10
 F_SINGLE_LAUNCH = 0x20
+F_TIMING = 0x40
 CF_OBJ_TRACKING, CF_OBJ_BPTT_REWARD = 0, 1
 S_FP_ROTOR, S_FP_PID, S_ID = 17, 25, 13
 NPARAM = 96
@@ -39,7 +40,7 @@ PARAM_OFFSETS = {
 }
 
 EXPORTS = ("cf_create", "cf_destroy", "cf_state_dim", "cf_total_drones", "cf_world_offsets", "cf_set_stream",
-           "cf_reset", "cf_step_k", "cf_rollout", "cf_rollout_backward", "cf_autotune", "cf_launch_config",
+           "cf_reset", "cf_step_k", "cf_rollout", "cf_rollout_backward", "cf_ckpt_floats", "cf_autotune", "cf_launch_config", "cf_set_launch_config", "cf_launch_times",
            "cf_strerror", "cf_last_error", "cf_mppi_create", "cf_mppi_destroy", "cf_mppi_step", "cf_mppi_noise", "cf_probe_fma")
 
 MPPI_MAX_OBSTACLES = 16
@@ -99,8 +100,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "cf_step_k": ([H, P, P, c_int32, P], c_int32),
         "cf_rollout": ([H, P, P, c_int32, POINTER(_Objective), c_int32, P, P, P, P, P], c_int32),
         "cf_rollout_backward": ([H, P, P, c_int32, POINTER(_Objective), c_int32, P, P, P, P, P], c_int32),
+        "cf_ckpt_floats": ([H, c_int32, c_int32, c_int32, POINTER(c_int64)], c_int32),
         "cf_autotune": ([H, P, P, c_int32, c_int32], c_int32),
         "cf_launch_config": ([H, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)], c_int32),
+        "cf_set_launch_config": ([H, c_int32, c_int32, c_int32], c_int32),
+        "cf_launch_times": ([H, c_int32, POINTER(c_float), c_int32, POINTER(c_int32)], c_int32),
         "cf_strerror": ([c_int32], ctypes.c_char_p),
         "cf_last_error": ([H], c_int32),
         "cf_mppi_create": ([H, POINTER(_MppiDesc), POINTER(c_void_p)], c_int32),
@@ -272,13 +276,39 @@ class Sim:
         o._tensors = (gain, ref_table, ref_offset)
         return o
 
+    def ckpt_floats(self, T: int, ckpt_every: int, kind: int = CF_OBJ_TRACKING) -> int:
+        """Floats of the checkpoint buffer of a rollout (states every ``ckpt_every``
+        steps, the reward objective's applied commands, the forward's tag)."""
+        n = c_int64()
+        _check(self._lib.cf_ckpt_floats(self._h, int(T), int(ckpt_every), int(kind), ctypes.byref(n)),
+               "cf_ckpt_floats")
+        return int(n.value)
+
+    def ckpt_buffer(self, T: int, ckpt_every: int, kind: int = CF_OBJ_TRACKING, device="cuda"):
+        """A device buffer for the checkpoints of a rollout (flat float32)."""
+        import torch
+        return torch.empty(self.ckpt_floats(T, ckpt_every, kind), device=device, dtype=torch.float32)
+
+    def ckpt_states(self, ckpt, T: int, ckpt_every: int):
+        """View of the checkpoint states inside a checkpoint buffer, ``[ceil(T/K), S, D]``."""
+        nseg = (int(T) + int(ckpt_every) - 1) // int(ckpt_every)
+        return ckpt[:nseg * self.S * self.D].view(nseg, self.S, self.D)
+
+    def _need_ckpt(self, ckpt, T, ckpt_every, obj) -> None:
+        if ckpt is None:
+            return
+        kind = CF_OBJ_TRACKING if obj is None else int(obj.kind)
+        n = self.ckpt_floats(T, ckpt_every, kind)
+        if ckpt.dim() != 1 or ckpt.numel() != n or str(ckpt.dtype) != "torch.float32":
+            raise ValueError(f"ckpt: expected a flat float32 buffer of {n} values (Sim.ckpt_buffer), "
+                             f"got {tuple(ckpt.shape)} {ckpt.dtype}")
+
     def rollout(self, x0, cmds, T: int, obj=None, ckpt_every: int = 50, ckpt=None, x_T=None, traj=None,
                 loss=None, loss_world=None) -> None:
         T = int(T)
-        nseg = (T + int(ckpt_every) - 1) // int(ckpt_every) if ckpt_every > 0 else 0
         self._need(x0, (self.S, self.D), "x0")
         self._need(cmds, (T, 4, self.D), "cmds")
-        self._need(ckpt, (nseg, self.S, self.D), "ckpt")
+        self._need_ckpt(ckpt, T, ckpt_every, obj)
         self._need(x_T, (self.S, self.D), "x_T")
         self._need(traj, (T + 1, self.S, self.D), "traj")
         self._need(loss, (self.D,), "loss")
@@ -292,9 +322,8 @@ class Sim:
     def rollout_backward(self, x0, cmds, T: int, obj, ckpt_every: int, ckpt, dloss=None, g_cmds=None,
                          g_x0=None, g_gain=None) -> None:
         T = int(T)
-        nseg = (T + int(ckpt_every) - 1) // int(ckpt_every) if ckpt_every > 0 else 0
         self._need(cmds, (T, 4, self.D), "cmds")
-        self._need(ckpt, (nseg, self.S, self.D), "ckpt")
+        self._need_ckpt(ckpt, T, ckpt_every, obj)
         self._need(dloss, (self.D,), "dloss")
         self._need(g_cmds, (T, 4, self.D), "g_cmds")
         self._need(g_x0, (self.S, self.D), "g_x0")
@@ -318,6 +347,19 @@ class Sim:
                "cf_launch_config")
         return {"workqueue": a.value & 1, "per_model_launches": (a.value >> 1) & 1, "tile": b.value, "chunk": c.value}
 
+    def set_launch_config(self, workqueue: int = 0, tile: int = 64, chunk: int = 0, per_model_launches: int = 1):
+        """Pin the launch choice of step_k (see launch_config)."""
+        wq = (int(workqueue) & 1) | ((int(per_model_launches) & 1) << 1)
+        _check(self._lib.cf_set_launch_config(self._h, wq, int(tile), int(chunk)), "cf_set_launch_config")
+
+    def launch_times(self, slot: int = 0):
+        """Durations (ms) of the kernel launches of the latest step_k call on stream
+        slot 0 or 1 (handles created with F_TIMING)."""
+        buf = (c_float * 512)()
+        n = c_int32()
+        _check(self._lib.cf_launch_times(self._h, int(slot), buf, 512, ctypes.byref(n)), "cf_launch_times")
+        return [float(buf[i]) for i in range(min(n.value, 512))]
+
     def last_error(self) -> int:
         return int(self._lib.cf_last_error(self._h))
 
@@ -325,10 +367,9 @@ class Sim:
 def _rollout_loss_apply(sim: Sim, x0, cmds, gain, T, ckpt_every, obj_kw):
     import torch
     dev = x0.device
-    nseg = (T + ckpt_every - 1) // ckpt_every
-    ckpt = torch.empty((nseg, sim.S, sim.D), device=dev, dtype=torch.float32)
-    loss = torch.empty(sim.D, device=dev, dtype=torch.float32)
     obj = Sim.objective(gain=gain, **obj_kw)
+    ckpt = sim.ckpt_buffer(T, ckpt_every, int(obj.kind), device=dev)
+    loss = torch.empty(sim.D, device=dev, dtype=torch.float32)
     sim.rollout(x0, cmds, T, obj, ckpt_every, ckpt=ckpt, loss=loss)
     return loss, ckpt, obj
 
@@ -336,7 +377,9 @@ def _rollout_loss_apply(sim: Sim, x0, cmds, gain, T, ckpt_every, obj_kw):
 class RolloutLoss:
     """``loss = RolloutLoss.apply(x0, cmds, gain, sim, T, ckpt_every, obj_kw)``: per-drone
     tracking loss ``[D]`` of a rollout; backward runs the library's discrete adjoint and
-    returns gradients for ``x0`` ``[S][D]``, ``cmds`` ``[T][4][D]`` and ``gain``."""
+    returns gradients for ``x0`` ``[S][D]``, ``cmds`` ``[T][4][D]`` and ``gain``. Each
+    application owns its checkpoint buffer (saved for its backward), so several
+    applications on one handle may precede their backwards."""
 
     @staticmethod
     def _fn():

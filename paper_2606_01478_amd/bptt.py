@@ -3,10 +3,11 @@
 is trained on analytical gradients through the unrolled dynamics, with no value
 network. Here the policy is the linear state feedback of the rollout objective,
 u_t = ubar_t + G_w (x_t[0:13] - x_ref(t)), optionally with the open-loop
-commands ubar_t as parameters too, and the objective is the library's tracking
-loss (position error to the reference plus w_u |u_t|^2; the paper's reward
-shaping is not built). Every rollout and adjoint runs in the HIP library; Adam
-is PyTorch's, on the device."""
+commands ubar_t as parameters too, and the objective is one of the library's:
+the tracking loss (position error to the reference plus w_u |u_t|^2) or, with
+``reward`` in ``obj_kw``, minus the paper's BPTT reward (exponential distance
+term, tilt, action and action-change penalties). Every rollout and adjoint runs
+in the HIP library; Adam is PyTorch's, on the device."""
 from __future__ import annotations
 
 from typing import Callable, Dict, Optional

@@ -5,19 +5,21 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
-#include <sys/stat.h>
 #include <string>
 #include <tuple>
 #include <vector>
 
 #include "../../include/cfsim.h"
 #include "cf_device.hpp"
+#include "cf_host.hpp"
 #include "cf_internal.hpp"
 
 using namespace cfk;
@@ -28,6 +30,16 @@ using namespace cfk;
 __global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+struct TagWords {
+    uint32_t w[CF_CKPT_TAG_FLOATS];
+};
+
+// the forward's tag at the end of its checkpoint buffer
+__global__ void k_write_tag(uint32_t* dst, TagWords t) {
+    const int i = threadIdx.x;
+    if (i < CF_CKPT_TAG_FLOATS) dst[i] = t.w[i];
 }
 
 // state[:, d] = init[:, d] for drones of masked worlds
@@ -76,16 +88,53 @@ __global__ __launch_bounds__(256) void k_reduce_world(const float* __restrict__ 
     }
 }
 
-// g[k][c] = sum over worlds w (in order) with gidx[w] == k of ws[w][c]
-__global__ void k_reduce_gain(const float* __restrict__ ws, const int32_t* __restrict__ gidx, int M,
-                              int n_gains, int ncomp, float* __restrict__ g) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_gains * ncomp) return;
-    const int k = i / ncomp, c = i % ncomp;
+// Gain gradient g[k][c] = sum over drones d whose world uses gain k of
+// v[c][d] (c < 52), in a fixed order that depends only on D and the grid:
+// stage 1, workgroup b of gain k sums the drones of chunk b (each thread a
+// strided subset, then an LDS tree per component) into part[k][b][c];
+// stage 2 sums part[k][0..nb) in order. O(D / (nb 256) + log 256 + nb) deep.
+constexpr int GAIN_COMP = 52;
+constexpr int GAIN_MAX_BLOCKS = 1024;
+
+__global__ __launch_bounds__(256) void k_gain_partial(const float* __restrict__ v, int64_t D,
+                                                      const int32_t* __restrict__ drone_world,
+                                                      const int32_t* __restrict__ gidx, int64_t chunk,
+                                                      float* __restrict__ part) {
+    __shared__ float sh[256];
+    const int b = blockIdx.x, k = blockIdx.y, nb = gridDim.x;
+    const int64_t lo = (int64_t)b * chunk, hi = min(D, lo + chunk);
+    float acc[GAIN_COMP];
+#pragma unroll
+    for (int c = 0; c < GAIN_COMP; ++c) acc[c] = 0.f;
+    for (int64_t d = lo + threadIdx.x; d < hi; d += blockDim.x) {
+        if (gidx[drone_world[d]] != k) continue;
+#pragma unroll
+        for (int c = 0; c < GAIN_COMP; ++c) acc[c] += v[(size_t)c * D + d];
+    }
+    for (int c = 0; c < GAIN_COMP; ++c) {
+        sh[threadIdx.x] = acc[c];
+        __syncthreads();
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[((size_t)k * nb + b) * GAIN_COMP + c] = sh[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_gain_final(const float* __restrict__ part, int nb, float* __restrict__ g) {
+    const int k = blockIdx.x, c = threadIdx.x;
+    if (c >= GAIN_COMP) return;
     float s = 0.f;
-    for (int w = 0; w < M; ++w)
-        if (gidx[w] == k) s += ws[(size_t)w * ncomp + c];
-    g[i] = s;
+    for (int b = 0; b < nb; ++b) s += part[((size_t)k * nb + b) * GAIN_COMP + c];
+    g[(size_t)k * GAIN_COMP + c] = s;
+}
+
+// workgroups per gain of the stage-1 reduction for D drones
+static int gain_blocks(int64_t D) {
+    const int64_t nb = (D + 2047) / 2048;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, GAIN_MAX_BLOCKS));
 }
 
 // ---------------------------------------------------------------------------
@@ -104,6 +153,17 @@ struct GraphKey {
 struct DevBuf {
     void* p = nullptr;
     size_t n = 0;
+};
+
+// Per-launch timing of the held-step kernels (CF_F_TIMING): an event pair around
+// every kernel launch of a cf_step_k call, recorded on the stream the kernel is
+// launched on (slot 0: the handle's stream, slot 1: the second per-model stream).
+constexpr int MAX_TIMED = 512;
+struct LaunchTimer {
+    hipEvent_t a[MAX_TIMED] = {};
+    hipEvent_t b[MAX_TIMED] = {};
+    int n = 0;
+    int made = 0;
 };
 
 }  // namespace
@@ -151,12 +211,17 @@ struct cf_handle {
     int split = 1;       // mixed handles: one launch per model on two streams
     int mode = LM_TILE;
     // scratch
-    DevBuf ref_tab, seg, ggc, wsum, loss_tmp, ubuf;
-    // last rollout (for the backward's consistency check)
-    const float* last_ckpt = nullptr;
-    int last_T = -1, last_K = -1;
+    DevBuf ref_tab, seg, ggc, gpart, loss_tmp;
+    // checkpoint tags: this handle's id, its count of forwards with a checkpoint
+    // buffer, their tags by buffer, and a device word the backward kernels set
+    // when a buffer no longer holds the tag the host matched
+    uint32_t id = 0;
+    uint32_t generation = 0;
+    cfh::CkptRegistry ckpts;
+    uint32_t* dflag = nullptr;
     cf_status sticky = CF_OK;
     std::map<GraphKey, hipGraphExec_t> graphs;
+    LaunchTimer timers[2];
 };
 
 struct cf_mppi {
@@ -218,43 +283,19 @@ cf_status check_dev(const void* ptr, size_t bytes) {
     return CF_OK;
 }
 
-int model_cost(int model, int ctrl) {
-    if (model == MODEL_ID) return 2;
-    return ctrl == CTRL_ROTOR ? 4 : 5;
-}
-
 hipError_t build_tiles(cf_handle* h, int tile) {
     if (h->tiles && h->tiles_for == tile) return hipSuccess;
-    struct T { int4 v; int cost; };
-    std::vector<T> ts;
-    for (int w = 0; w < h->M; ++w) {
-        const int n = h->counts[w];
-        for (int s = 0; s < n; s += tile) {
-            const int c = std::min(tile, n - s);
-            const int waves = (c + 63) / 64;
-            ts.push_back({make_int4(w, (int)(h->offsets[w] + s), c, h->model_of_world[w]),
-                          waves * model_cost(h->model_of_world[w], h->control)});
-        }
-    }
-    // first-principles tiles first; within a model the most expensive first
-    // (longest-processing-time order), ties by position
-    std::stable_sort(ts.begin(), ts.end(), [](const T& a, const T& b) {
-        if (a.v.w != b.v.w) return a.v.w < b.v.w;
-        return a.cost > b.cost;
-    });
-    std::vector<int4> v(ts.size());
     int nfp = 0;
-    for (size_t i = 0; i < ts.size(); ++i) {
-        v[i] = ts[i].v;
-        nfp += (ts[i].v.w == MODEL_FP);
-    }
+    const std::vector<cfh::Tile> v = cfh::tile_list(h->counts, h->offsets, h->model_of_world, h->control, tile, &nfp);
+    std::vector<int4> dv(v.size());
+    for (size_t i = 0; i < v.size(); ++i) dv[i] = make_int4(v[i].world, v[i].first, v[i].count, v[i].model);
     if (h->tiles) hipFree(h->tiles);
     h->tiles = nullptr;
-    h->n_tiles = (int)v.size();
+    h->n_tiles = (int)dv.size();
     h->n_tiles_fp = nfp;
-    hipError_t e = dalloc(&h->tiles, v.size());
+    hipError_t e = dalloc(&h->tiles, dv.size());
     if (e != hipSuccess) return e;
-    if (!v.empty()) e = hipMemcpy(h->tiles, v.data(), v.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (!dv.empty()) e = hipMemcpy(h->tiles, dv.data(), dv.size() * sizeof(int4), hipMemcpyHostToDevice);
     h->tiles_for = tile;
     return e;
 }
@@ -328,40 +369,6 @@ std::string signature(const cf_handle* h) {
     return buf;
 }
 
-bool cache_lookup(const std::string& key, int* wq, int* tile, int* chunk, int* split) {
-    FILE* f = std::fopen(cache_path().c_str(), "r");
-    if (!f) return false;
-    char k[256];
-    int a, b, c, sp;
-    float ms;
-    bool found = false;
-    while (std::fscanf(f, "%255s %d %d %d %d %f", k, &a, &b, &c, &sp, &ms) == 6) {
-        if (key == k) { *wq = a; *tile = b; *chunk = c; *split = sp; found = true; }
-    }
-    std::fclose(f);
-    return found;
-}
-
-void cache_store(const std::string& key, int wq, int tile, int chunk, int split, float ms) {
-    const std::string path = cache_path();
-    std::vector<std::string> lines;
-    if (FILE* f = std::fopen(path.c_str(), "r")) {
-        char line[512];
-        while (std::fgets(line, sizeof line, f)) {
-            char k[256];
-            if (std::sscanf(line, "%255s", k) == 1 && key != k) lines.push_back(line);
-        }
-        std::fclose(f);
-    }
-    const size_t slash = path.find_last_of('/');
-    if (slash != std::string::npos && slash > 0) mkdir(path.substr(0, slash).c_str(), 0755);
-    FILE* f = std::fopen(path.c_str(), "w");
-    if (!f) return;
-    for (auto& l : lines) std::fputs(l.c_str(), f);
-    std::fprintf(f, "%s %d %d %d %d %.6f\n", key.c_str(), wq, tile, chunk, split, ms);
-    std::fclose(f);
-}
-
 void apply_choice(cf_handle* h, int wq, int tile, int chunk, int split) {
     if (tile != 64 && tile != 128 && tile != 256) tile = 64;
     h->split = split ? 1 : 0;
@@ -370,115 +377,6 @@ void apply_choice(cf_handle* h, int wq, int tile, int chunk, int split) {
     h->chunk = chunk > 0 ? chunk : 0;
     h->mode = (h->lane_ok && !h->use_wq && h->D > 0 && (double)h->D / h->M < 32.0) ? LM_LANE : LM_TILE;
     clear_graphs(h);
-}
-
-cf_status validate_desc(const cf_desc* d, std::vector<int32_t>& counts, std::vector<uint8_t>& models,
-                        std::vector<int32_t>& gidx, int64_t* D_out) {
-    if (!d) return CF_EINVAL;
-    if (d->n_worlds < 1) return CF_EINVAL;
-    const int M = d->n_worlds;
-    counts.assign(M, 0);
-    models.assign(M, 0);
-    int64_t D = 0;
-    for (int w = 0; w < M; ++w) {
-        const int n = d->drones_per_world ? d->drones_per_world[w] : d->n_drones;
-        if (n < 0) return CF_EINVAL;
-        counts[w] = n;
-        D += n;
-        if (D > 2147483647LL) return CF_EINVAL;
-        const int m = d->model_per_world ? d->model_per_world[w] : d->model;
-        if (m != CF_MODEL_FP && m != CF_MODEL_ID) return CF_EINVAL;
-        models[w] = (uint8_t)m;
-    }
-    if (d->control != CF_CTRL_ROTOR && d->control != CF_CTRL_ATT_PID && d->control != CF_CTRL_TORQUE &&
-        d->control != CF_CTRL_POSITION)
-        return CF_EINVAL;
-    if (d->integrator != CF_INTEG_EULER && d->integrator != CF_INTEG_RK4) return CF_EINVAL;
-    if (!(std::isfinite(d->dt) && d->dt > 0.f)) return CF_EINVAL;
-    if (d->renorm_q != 0 && d->renorm_q != 1) return CF_EINVAL;
-    if (d->ctrl_every < 0 || d->ctrl_every > CF_MAX_CTRL_EVERY) return CF_EINVAL;
-    if (!d->params) return CF_EINVAL;
-    if (d->n_gains < 0) return CF_EINVAL;
-    gidx.assign(M, 0);
-    if (d->gain_index) {
-        for (int w = 0; w < M; ++w) {
-            if (d->gain_index[w] < 0 || d->gain_index[w] >= std::max(d->n_gains, 1)) return CF_EINVAL;
-            gidx[w] = d->gain_index[w];
-        }
-    }
-    for (int w = 0; w < M; ++w) {
-        const float* r = d->params + (size_t)w * CF_NPARAM;
-        for (int i = 0; i < CF_NPARAM; ++i)
-            if (!std::isfinite(r[i])) return CF_EINVAL;
-        if (!(r[CF_P_MASS] > 0.f)) return CF_EINVAL;
-        if (models[w] == CF_MODEL_FP) {
-            for (int i = 0; i < 3; ++i)
-                if (!(r[CF_P_J + i] > 0.f)) return CF_EINVAL;
-            if (d->control != CF_CTRL_ROTOR && !(r[CF_P_THRUST + 2] > 0.f)) return CF_EINVAL;
-            if (r[CF_P_JP] < 0.f) return CF_EINVAL;
-        } else {
-            if (!(r[CF_P_CF] > 0.f) || r[CF_P_CTAU] < 0.f) return CF_EINVAL;
-        }
-    }
-    *D_out = D;
-    return CF_OK;
-}
-
-// A world's device record: the public record followed by constants derived from
-// it (offsets D_* in cf_device.hpp). Reciprocals and differences are formed in
-// binary32 exactly as a kernel would; the reference-speed terms (the hover speed
-// W_r on the thrust curve, thrust, drag torque and slopes there) in double from
-// the binary32 W_r the kernels use to convert rotor speeds, rounded once.
-void derive_record(const float* r, float* out) {
-    std::memcpy(out, r, NPARAM * sizeof(float));
-    std::fill(out + NPARAM, out + NREC, 0.f);
-    const float m = r[P_MASS];
-    out[D_INV_M] = 1.0f / m;
-    for (int i = 0; i < 3; ++i) out[D_IJ + i] = 1.0f / r[P_J + i];
-    out[D_DJ] = r[P_J + 2] - r[P_J + 1];
-    out[D_DJ + 1] = r[P_J] - r[P_J + 2];
-    out[D_DJ + 2] = r[P_J + 1] - r[P_J];
-    out[D_INV_2K2] = 0.5f / r[P_THRUST + 2];
-    for (int i = 0; i < 4; ++i) {
-        const float tz = r[P_MIX_YAW + i];
-        out[D_SG + i] = tz > 0.f ? -1.f : (tz < 0.f ? 1.f : 0.f);
-    }
-    const double k0 = r[P_THRUST], k1 = r[P_THRUST + 1], k2 = r[P_THRUST + 2];
-    const double t0 = r[P_TORQUE], t1 = r[P_TORQUE + 1], t2 = r[P_TORQUE + 2];
-    float wr = 0.f;
-    if (k2 > 0.0) {
-        // hover (m g / 4 per rotor) on the rising branch, else the vertex; never negative
-        const double dh = k1 * k1 - 4.0 * k2 * (k0 - 0.25 * (double)m * r[P_GRAVITY]);
-        const double w = ((dh > 0.0 ? std::sqrt(dh) : 0.0) - k1) / (2.0 * k2);
-        wr = std::isfinite(w) ? (float)std::max(w, 0.0) : 0.f;
-    }
-    const double W = wr;
-    const float k1w = wr > 0.f ? (float)std::max(k1 + 2.0 * k2 * W, 0.0) : (float)k1;
-    const double fr = k0 + W * (k1 + k2 * W);
-    const double tr = t0 + W * (t1 + t2 * W);
-    double stx = 0.0, sty = 0.0, stz = 0.0, ssg = 0.0;
-    for (int i = 0; i < 4; ++i) {
-        stx += r[P_MIX_TX + i];
-        sty += r[P_MIX_TY + i];
-        stz += r[P_MIX_YAW + i];
-        ssg += out[D_SG + i];
-    }
-    out[D_WR] = wr;
-    out[D_W2] = 2.f * wr;
-    out[D_K1W] = k1w;
-    out[D_T1W] = (float)(t1 + 2.0 * t2 * W);
-    out[D_FR] = (float)fr;
-    out[D_F4R] = (float)(4.0 * fr);
-    out[D_TXR] = (float)(fr * stx);
-    out[D_TYR] = (float)(fr * sty);
-    out[D_TZR] = (float)(tr * stz);
-    out[D_SGR] = (float)(W * ssg);
-    out[D_DISC_R] = (float)((double)k1w * k1w);
-    out[D_VTX] = k2 > 0.0 ? (float)(-(double)k1w / (2.0 * k2)) : 0.f;
-    // identified model
-    const float cf = r[P_CF];
-    out[D_CF_M] = cf / m;
-    out[D_F_HOVER] = m * r[P_GRAVITY] / cf;
 }
 
 }  // namespace
@@ -507,7 +405,7 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
     std::vector<int32_t> counts, gidx;
     std::vector<uint8_t> models;
     int64_t D = 0;
-    cf_status st = validate_desc(d, counts, models, gidx, &D);
+    cf_status st = cfh::validate_desc(d, counts, models, gidx, &D);
     if (st != CF_OK) return st;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
@@ -569,7 +467,7 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
     hipError_t e;
     const size_t M = (size_t)h->M;
     std::vector<float> aos((size_t)NREC * M), soa((size_t)NREC * M);
-    for (size_t w = 0; w < M; ++w) derive_record(d->params + w * CF_NPARAM, aos.data() + w * NREC);
+    for (size_t w = 0; w < M; ++w) cfh::derive_record(d->params + w * CF_NPARAM, aos.data() + w * NREC);
     for (size_t w = 0; w < M; ++w)
         for (int i = 0; i < NREC; ++i) soa[(size_t)i * M + w] = aos[w * NREC + i];
     std::vector<int32_t> dw((size_t)std::max<int64_t>(D, 1));
@@ -580,6 +478,10 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
     if ((e = dalloc(&h->drone_world, (size_t)std::max<int64_t>(D, 1))) != hipSuccess) return fail(e);
     if ((e = dalloc(&h->d_offsets, M + 1)) != hipSuccess) return fail(e);
     if ((e = dalloc(&h->d_gidx, M)) != hipSuccess) return fail(e);
+    static std::atomic<uint32_t> next_id{1};
+    h->id = next_id.fetch_add(1);
+    if ((e = dalloc(&h->dflag, 1)) != hipSuccess) return fail(e);
+    if ((e = hipMemset(h->dflag, 0, sizeof(uint32_t))) != hipSuccess) return fail(e);
     h->n_counters = 4096;
     if ((e = dalloc(&h->counters, (size_t)h->n_counters)) != hipSuccess) return fail(e);
     if ((e = hipMemcpy(h->par_aos, aos.data(), aos.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
@@ -604,8 +506,8 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
 
     int wq = (h->flags & CF_F_WORKQUEUE) ? 1 : 0, tile = 64, chunk = 0, split = 1;
     if (!(h->flags & CF_F_NO_AUTOTUNE_CACHE) && !(h->flags & CF_F_WORKQUEUE)) {
-        int a, b, c, sp;
-        if (cache_lookup(signature(h), &a, &b, &c, &sp)) { wq = a; tile = b; chunk = c; split = sp; }
+        cfh::LaunchChoice c;
+        if (cfh::cache_lookup(cache_path(), signature(h), &c)) { wq = c.wq; tile = c.tile; chunk = c.chunk; split = c.split; }
     }
     if (h->flags & CF_F_SINGLE_LAUNCH) split = 0;
     apply_choice(h, wq, tile, chunk, split);
@@ -627,13 +529,20 @@ cf_status cf_destroy(cf_handle* h) {
     hipFree(h->d_gidx);
     hipFree(h->tiles);
     hipFree(h->counters);
-    for (DevBuf* b : {&h->ref_tab, &h->seg, &h->ggc, &h->wsum, &h->loss_tmp, &h->ubuf})
+    hipFree(h->dflag);
+    for (DevBuf* b : {&h->ref_tab, &h->seg, &h->ggc, &h->gpart, &h->loss_tmp})
         if (b->p) hipFree(b->p);
     if (h->capture_stream) hipStreamDestroy(h->capture_stream);
     if (h->aux_stream) {
         hipStreamSynchronize(h->aux_stream);
         hipStreamDestroy(h->aux_stream);
     }
+    for (auto& T : h->timers)
+        if (T.made)
+            for (int i = 0; i < MAX_TIMED; ++i) {
+                hipEventDestroy(T.a[i]);
+                hipEventDestroy(T.b[i]);
+            }
     if (h->ev_fork) hipEventDestroy(h->ev_fork);
     if (h->ev_join) hipEventDestroy(h->ev_join);
     delete h;
@@ -672,6 +581,29 @@ cf_status cf_launch_config(const cf_handle* h, int32_t* use_wq, int32_t* tile, i
     return CF_OK;
 }
 
+cf_status cf_set_launch_config(cf_handle* h, int32_t use_wq, int32_t tile, int32_t chunk) {
+    if (!h || use_wq < 0 || use_wq > 3 || (tile != 64 && tile != 128 && tile != 256) || chunk < 0) return CF_EINVAL;
+    if (chunk > 0 && chunk % h->ctrl_every != 0) return CF_EINVAL;
+    hipSetDevice(h->device);
+    apply_choice(h, use_wq & 1, tile, chunk, (use_wq >> 1) & 1);
+    return note(h, build_tiles(h, h->tile));
+}
+
+cf_status cf_launch_times(cf_handle* h, int32_t slot, float* ms, int32_t max_n, int32_t* n) {
+    if (!h || !n || slot < 0 || slot > 1 || max_n < 0 || (max_n > 0 && !ms)) return CF_EINVAL;
+    if (!(h->flags & CF_F_TIMING)) return CF_EINVAL;
+    hipSetDevice(h->device);
+    const LaunchTimer& T = h->timers[slot];
+    const int m = std::min(T.n, (int)max_n);
+    for (int i = 0; i < m; ++i) {
+        hipError_t e = hipEventSynchronize(T.b[i]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], T.a[i], T.b[i]);
+        if (e != hipSuccess) return note(h, e);
+    }
+    *n = T.n;
+    return CF_OK;
+}
+
 cf_status cf_last_error(cf_handle* h) {
     if (!h) return CF_EINVAL;
     hipSetDevice(h->device);
@@ -679,6 +611,9 @@ cf_status cf_last_error(cf_handle* h) {
     if (e != hipSuccess) note(h, e);
     hipError_t e2 = hipGetLastError();
     if (e2 != hipSuccess) note(h, e2);
+    uint32_t flag = 0;
+    if (h->sticky == CF_OK && hipMemcpy(&flag, h->dflag, sizeof flag, hipMemcpyDeviceToHost) == hipSuccess && flag)
+        h->sticky = CF_ESTATE;
     return h->sticky;
 }
 
@@ -699,10 +634,43 @@ cf_status cf_reset(cf_handle* h, float* state, const float* init, const uint8_t*
     return note(h, hipGetLastError());
 }
 
+// CF_F_TIMING: the event before (end = 0) or after (end = 1) a kernel launch on
+// stream st; the pairs of one cf_step_k call (or of the graph it captured)
+static int slot_of(const cf_handle* h, hipStream_t st) { return (h->aux_stream && st == h->aux_stream) ? 1 : 0; }
+
+static hipError_t timer_event(cf_handle* h, int slot, hipStream_t st, int end);
+
+static hipError_t timer_mark(cf_handle* h, int slot, hipStream_t st, int end) {
+    // launches captured into a graph are timed as a whole at each replay
+    if (!(h->flags & CF_F_TIMING) || (h->flags & CF_F_GRAPH)) return hipSuccess;
+    return timer_event(h, slot, st, end);
+}
+
+static hipError_t timer_event(cf_handle* h, int slot, hipStream_t st, int end) {
+    LaunchTimer& T = h->timers[slot];
+    if (T.n >= MAX_TIMED) return hipSuccess;   // launches beyond the capacity are not timed
+    hipError_t e;
+    if (!T.made) {
+        for (int i = 0; i < MAX_TIMED; ++i) {
+            if ((e = hipEventCreate(&T.a[i])) != hipSuccess) return e;
+            if ((e = hipEventCreate(&T.b[i])) != hipSuccess) return e;
+        }
+        T.made = 1;
+    }
+    if (!end) return hipEventRecord(T.a[T.n], st);
+    e = hipEventRecord(T.b[T.n], st);
+    ++T.n;
+    return e;
+}
+
 // enqueue k held-command steps with the current launch choice on stream s
 static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int k, uint32_t* nf, hipStream_t s,
                                int plain) {
     hipError_t e = hipSuccess;
+    if (!(h->flags & CF_F_GRAPH)) {
+        h->timers[0].n = 0;
+        h->timers[1].n = 0;
+    }
     const int n = h->ctrl_every;  // k is a multiple of n: every launch starts on a controller step
     if (plain) {
         // one step per launch; with a slower onboard controller, one controller
@@ -713,7 +681,11 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
             KernelSel ks = selection(h, mode, h->tile);
             ks.models = models;
             hipError_t r = hipSuccess;
-            for (int i = 0; i < k / n && r == hipSuccess; ++i) r = launch_step(ks, a, tiles, nt, nullptr, 0, st);
+            for (int i = 0; i < k / n && r == hipSuccess; ++i) {
+                if ((r = timer_mark(h, slot_of(h, st), st, 0)) != hipSuccess) break;
+                r = launch_step(ks, a, tiles, nt, nullptr, 0, st);
+                if (r == hipSuccess) r = timer_mark(h, slot_of(h, st), st, 1);
+            }
             return r;
         });
         return note(h, e);
@@ -736,7 +708,9 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
         for (int c = 0; c < n_launch && r == hipSuccess; ++c) {
             const int kk = std::min(chunk, k - c * chunk);
             const StepArgs a = step_args(h, state, cmd, kk, nf);
+            if ((r = timer_mark(h, slot, st, 0)) != hipSuccess) break;
             r = launch_step(ks, a, tiles, nt, h->use_wq ? h->counters + 2 * c + slot : nullptr, blocks, st);
+            if (r == hipSuccess) r = timer_mark(h, slot, st, 1);
         }
         return r;
     });
@@ -781,13 +755,23 @@ cf_status cf_step_k(cf_handle* h, float* state, const float* cmd, int32_t k, uin
         if (e != hipSuccess) return note(h, e);
         it = h->graphs.emplace(key, ge).first;
     }
-    return note(h, hipGraphLaunch(it->second, h->stream));
+    // with CF_F_TIMING one event pair brackets the whole replay (slot 0)
+    const bool timed = (h->flags & CF_F_TIMING) != 0;
+    h->timers[0].n = 0;
+    h->timers[1].n = 0;
+    if (timed && (e = timer_event(h, 0, h->stream, 0)) != hipSuccess) return note(h, e);
+    if ((e = hipGraphLaunch(it->second, h->stream)) != hipSuccess) return note(h, e);
+    if (timed && (e = timer_event(h, 0, h->stream, 1)) != hipSuccess) return note(h, e);
+    return CF_OK;
 }
 
 // ---------------------------------------------------------------------------
 // rollout
 
-static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T, RollArgs& a) {
+// ref_tab_buf: device [(T + 1)][6] for the figure-eight table, or null to use the
+// handle's own (grown on demand)
+static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T, RollArgs& a,
+                                   float* ref_tab_buf = nullptr) {
     a.has_obj = obj ? 1 : 0;
     a.gain = nullptr;
     a.gidx = h->d_gidx;
@@ -814,11 +798,6 @@ static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T,
             a.w_act[i] = obj->w_act[i];
             a.w_dact[i] = obj->w_dact[i];
         }
-        if (h->D > 0) {
-            hipError_t e = ensure(h->ubuf, (size_t)T * 4 * h->D * sizeof(float));
-            if (e != hipSuccess) return note(h, e);
-            a.ubuf = (float*)h->ubuf.p;
-        }
     }
     if (obj->gain) {
         if (h->n_gains < 1) return CF_EINVAL;
@@ -837,12 +816,16 @@ static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T,
     } else {
         if (!(std::isfinite(obj->ref_period) && obj->ref_period > 0.f) || !std::isfinite(obj->ref_amp))
             return CF_EINVAL;
-        hipError_t e = ensure(h->ref_tab, (size_t)(T + 1) * 6 * sizeof(float));
-        if (e != hipSuccess) return note(h, e);
-        hipLaunchKernelGGL(k_eight_table, dim3((T + 1 + 255) / 256), dim3(256), 0, h->stream, (float*)h->ref_tab.p,
-                           T, h->dt, obj->ref_amp, obj->ref_period);
+        hipError_t e = hipSuccess;
+        float* tab = ref_tab_buf;
+        if (!tab) {
+            if ((e = ensure(h->ref_tab, (size_t)(T + 1) * 6 * sizeof(float))) != hipSuccess) return note(h, e);
+            tab = (float*)h->ref_tab.p;
+        }
+        hipLaunchKernelGGL(k_eight_table, dim3((T + 1 + 255) / 256), dim3(256), 0, h->stream, tab, T, h->dt,
+                           obj->ref_amp, obj->ref_period);
         if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
-        a.ref_tab = (const float*)h->ref_tab.p;
+        a.ref_tab = tab;
     }
     return CF_OK;
 }
@@ -872,17 +855,26 @@ static int roll_mode(const cf_handle* h) {
     return (h->lane_ok && h->D > 0 && (double)h->D / h->M < 32.0) ? LM_LANE : LM_TILE;
 }
 
+cf_status cf_ckpt_floats(const cf_handle* h, int32_t T, int32_t K, int32_t kind, int64_t* n) {
+    if (!h || !n || T < 1 || K < 1) return CF_EINVAL;
+    if (kind != CF_OBJ_TRACKING && kind != CF_OBJ_BPTT_REWARD) return CF_EINVAL;
+    *n = cfh::ckpt_floats(T, K, h->S, h->D, kind);
+    return CF_OK;
+}
+
 cf_status cf_rollout(cf_handle* h, const float* x0, const float* cmds, int32_t T, const cf_objective* obj,
                      int32_t K, float* ckpt, float* x_T, float* traj, float* loss, float* loss_world) {
     if (!h || T < 1 || K < 1) return CF_EINVAL;
     if (K % h->ctrl_every != 0 && h->ctrl_every % K != 0) return CF_EINVAL;
     if (h->sticky != CF_OK) return h->sticky;
     if (!obj && (loss || loss_world)) return CF_EINVAL;
+    if (obj && obj->kind != CF_OBJ_TRACKING && obj->kind != CF_OBJ_BPTT_REWARD) return CF_EINVAL;
+    const int kind = obj ? obj->kind : CF_OBJ_TRACKING;
     const size_t SD = (size_t)h->S * h->D * sizeof(float);
-    const int nseg = (T + K - 1) / K;
     if (h->D > 0) {
         if (check_dev(x0, SD) || check_dev(cmds, (size_t)T * 4 * h->D * sizeof(float))) return CF_EINVAL;
-        if (ckpt && check_dev(ckpt, (size_t)nseg * SD)) return CF_EINVAL;
+        if (ckpt && check_dev(ckpt, (size_t)cfh::ckpt_floats(T, K, h->S, h->D, kind) * sizeof(float)))
+            return CF_EINVAL;
         if (x_T && check_dev(x_T, SD)) return CF_EINVAL;
         if (traj && check_dev(traj, (size_t)(T + 1) * SD)) return CF_EINVAL;
         if (loss && check_dev(loss, (size_t)h->D * sizeof(float))) return CF_EINVAL;
@@ -893,6 +885,7 @@ cf_status cf_rollout(cf_handle* h, const float* x0, const float* cmds, int32_t T
     cf_status st = prepare_objective(h, obj, T, a);
     if (st != CF_OK) return st;
     a.ckpt = ckpt;
+    if (ckpt && a.obj_kind == 1) a.ubuf = ckpt + cfh::ckpt_ubuf_offset(T, K, h->S, h->D);
     a.xT = x_T;
     a.traj = traj;
     a.loss = loss;
@@ -918,56 +911,83 @@ cf_status cf_rollout(cf_handle* h, const float* x0, const float* cmds, int32_t T
                            loss_world);
         if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
     }
-    h->last_ckpt = ckpt;
-    h->last_T = T;
-    h->last_K = K;
+    if (ckpt) {
+        const cfh::CkptTag tag = cfh::make_tag(h->id, ++h->generation, T, K, h->S, h->D, obj);
+        if (h->D > 0) {
+            TagWords tw;
+            std::memcpy(tw.w, tag.w, sizeof tw.w);
+            uint32_t* dst = (uint32_t*)(ckpt + cfh::ckpt_tag_offset(T, K, h->S, h->D, kind));
+            hipLaunchKernelGGL(k_write_tag, dim3(1), dim3(64), 0, h->stream, dst, tw);
+            if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
+        }
+        h->ckpts.record(ckpt, tag);
+    }
     return CF_OK;
 }
 
-cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, int32_t T, const cf_objective* obj,
-                              int32_t K, const float* ckpt, const float* dloss, float* g_cmds, float* g_x0,
-                              float* g_gain) {
+// Device scratch of one backward call (the handle's buffers, grown on demand).
+struct BwdScratch {
+    float* ref_tab = nullptr;   // [T + 1][6], figure-eight objectives
+    float* seg = nullptr;       // [slots][S][D] recomputed segment states
+    float* ggc = nullptr;       // [52][D] per-drone gain-gradient contributions
+    float* gpart = nullptr;     // [n_gains][blocks][52] stage-1 gain sums
+};
+
+static cf_status rollout_backward_impl(cf_handle* h, const float* cmds, int32_t T, const cf_objective* obj,
+                                       int32_t K, const float* ckpt, const float* dloss, float* g_cmds, float* g_x0,
+                                       float* g_gain) {
     if (!h || T < 1 || K < 1 || !ckpt) return CF_EINVAL;
     if (K % h->ctrl_every != 0 && h->ctrl_every % K != 0) return CF_EINVAL;
     if (h->sticky != CF_OK) return h->sticky;
-    if (ckpt != h->last_ckpt || T != h->last_T || K != h->last_K) return CF_ESTATE;
     if (g_gain && (!obj || !obj->gain)) return CF_EINVAL;
+    if (obj && obj->kind != CF_OBJ_TRACKING && obj->kind != CF_OBJ_BPTT_REWARD) return CF_EINVAL;
+    const int kind = obj ? obj->kind : CF_OBJ_TRACKING;
+    cfh::CkptTag tag;
+    if (h->ckpts.match(ckpt, T, K, h->S, h->D, obj, &tag) != CF_OK) return CF_ESTATE;
     const size_t SD = (size_t)h->S * h->D * sizeof(float);
-    const int nseg = (T + K - 1) / K;
     if (h->D > 0) {
         if (check_dev(cmds, (size_t)T * 4 * h->D * sizeof(float))) return CF_EINVAL;
-        if (check_dev(ckpt, (size_t)nseg * SD)) return CF_EINVAL;
+        if (check_dev(ckpt, (size_t)cfh::ckpt_floats(T, K, h->S, h->D, kind) * sizeof(float))) return CF_EINVAL;
         if (dloss && check_dev(dloss, (size_t)h->D * sizeof(float))) return CF_EINVAL;
         if (g_cmds && check_dev(g_cmds, (size_t)T * 4 * h->D * sizeof(float))) return CF_EINVAL;
         if (g_x0 && check_dev(g_x0, SD)) return CF_EINVAL;
     }
     if (g_gain && check_dev(g_gain, (size_t)h->n_gains * 52 * sizeof(float))) return CF_EINVAL;
-    (void)x0;
-    hipSetDevice(h->device);
-    RollArgs a = roll_args(h, x0, cmds, T, K);
-    cf_status st = prepare_objective(h, obj, T, a);
-    if (st != CF_OK) return st;
-    hipError_t e;
-    a.ckpt_in = ckpt;
-    a.dloss = dloss;
-    a.g_cmds = g_cmds;
-    a.g_x0 = g_x0;
+    // scratch sizes (floats)
     const int64_t Dm = std::max<int64_t>(h->D, 1);
     // segment slots 1..K-1 hold recomputed states (slot 0 is the checkpoint itself);
     // with the reward objective slot K holds the final state of the last segment
-    const int slots = std::min(K, T) + (a.obj_kind == 1 ? 1 : 0);
-    if (slots > 1) {
-        if ((e = ensure(h->seg, (size_t)slots * h->S * Dm * sizeof(float))) != hipSuccess)
-            return note(h, e);
-        a.seg = (float*)h->seg.p;
-    } else {
-        a.seg = nullptr;
+    const int slots = std::min(K, T) + (kind == CF_OBJ_BPTT_REWARD ? 1 : 0);
+    const int nb = gain_blocks(h->D);
+    const size_t n_tab = (obj && !obj->ref_table) ? (size_t)(T + 1) * 6 : 0;
+    const size_t n_seg = slots > 1 ? (size_t)slots * h->S * Dm : 0;
+    const size_t n_ggc = g_gain ? (size_t)52 * Dm : 0;
+    const size_t n_part = g_gain ? (size_t)h->n_gains * nb * GAIN_COMP : 0;
+    hipSetDevice(h->device);
+    hipError_t e;
+    BwdScratch sc;
+    {
+        if (n_seg && (e = ensure(h->seg, n_seg * sizeof(float))) != hipSuccess) return note(h, e);
+        if (n_ggc && (e = ensure(h->ggc, n_ggc * sizeof(float))) != hipSuccess) return note(h, e);
+        if (n_part && (e = ensure(h->gpart, n_part * sizeof(float))) != hipSuccess) return note(h, e);
+        sc.seg = (float*)h->seg.p;
+        sc.ggc = (float*)h->ggc.p;
+        sc.gpart = (float*)h->gpart.p;
+        sc.ref_tab = nullptr;   // prepare_objective uses the handle's table
     }
-    if (g_gain) {
-        if ((e = ensure(h->ggc, (size_t)52 * Dm * sizeof(float))) != hipSuccess) return note(h, e);
-        if ((e = ensure(h->wsum, (size_t)h->M * 52 * sizeof(float))) != hipSuccess) return note(h, e);
-        a.ggc = (float*)h->ggc.p;
-    }
+    RollArgs a = roll_args(h, nullptr, cmds, T, K);
+    cf_status st = prepare_objective(h, obj, T, a, sc.ref_tab);
+    if (st != CF_OK) return st;
+    a.ckpt_in = ckpt;
+    if (a.obj_kind == 1) a.ubuf = const_cast<float*>(ckpt) + cfh::ckpt_ubuf_offset(T, K, h->S, h->D);
+    a.tag_in = (const uint32_t*)(ckpt + cfh::ckpt_tag_offset(T, K, h->S, h->D, kind));
+    std::memcpy(a.tag_exp, tag.w, sizeof a.tag_exp);
+    a.dflag = h->dflag;
+    a.dloss = dloss;
+    a.g_cmds = g_cmds;
+    a.g_x0 = g_x0;
+    a.seg = n_seg ? sc.seg : nullptr;
+    a.ggc = g_gain ? sc.ggc : nullptr;
     if (h->D > 0) {
         const int mode = roll_mode(h);
         if (mode == LM_TILE && (e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
@@ -980,19 +1000,26 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
     }
     if (g_gain) {
         if (h->D > 0) {
-            hipLaunchKernelGGL(k_reduce_world, dim3(h->M), dim3(256), 0, h->stream, (const float*)h->ggc.p, 52,
-                               h->D, h->d_offsets, (float*)h->wsum.p);
+            const int64_t chunk = (h->D + nb - 1) / nb;
+            hipLaunchKernelGGL(k_gain_partial, dim3(nb, h->n_gains), dim3(256), 0, h->stream, (const float*)sc.ggc,
+                               h->D, h->drone_world, h->d_gidx, chunk, sc.gpart);
+            if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
+            hipLaunchKernelGGL(k_gain_final, dim3(h->n_gains), dim3(64), 0, h->stream, (const float*)sc.gpart, nb,
+                               g_gain);
         } else {
-            hipLaunchKernelGGL(k_fill_u32, dim3((h->M * 52 + 255) / 256), dim3(256), 0, h->stream,
-                               (unsigned*)h->wsum.p, h->M * 52, 0u);
+            hipLaunchKernelGGL(k_fill_u32, dim3((h->n_gains * 52 + 255) / 256), dim3(256), 0, h->stream,
+                               (unsigned*)g_gain, h->n_gains * 52, 0u);
         }
-        if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
-        const int n = h->n_gains * 52;
-        hipLaunchKernelGGL(k_reduce_gain, dim3((n + 255) / 256), dim3(256), 0, h->stream, (const float*)h->wsum.p,
-                           h->d_gidx, h->M, h->n_gains, 52, g_gain);
         if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
     }
     return CF_OK;
+}
+
+cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, int32_t T, const cf_objective* obj,
+                              int32_t K, const float* ckpt, const float* dloss, float* g_cmds, float* g_x0,
+                              float* g_gain) {
+    (void)x0;   // the checkpoint holds it
+    return rollout_backward_impl(h, cmds, T, obj, K, ckpt, dloss, g_cmds, g_x0, g_gain);
 }
 
 // ---------------------------------------------------------------------------
@@ -1057,7 +1084,9 @@ cf_status cf_autotune(cf_handle* h, const float* state, const float* cmd, int32_
     }
     apply_choice(h, bc.wq, bc.tile, bc.chunk, bc.split);
     if ((e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
-    cache_store(signature(h), bc.wq, bc.tile, bc.chunk, bc.split, best);
+    cfh::LaunchChoice lc;
+    lc.wq = bc.wq; lc.tile = bc.tile; lc.chunk = bc.chunk; lc.split = bc.split; lc.ms = best;
+    cfh::cache_store(cache_path(), signature(h), lc);
     return CF_OK;
 }
 

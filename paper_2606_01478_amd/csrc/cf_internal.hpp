@@ -64,7 +64,8 @@ struct RollArgs {
     float w_u;
     int obj_kind;           // 0: tracking loss, 1: BPTT reward
     float w_tilt, w_act[4], w_dact[4];
-    float* ubuf;            // reward: applied commands [T][4][D], written forward, read backward
+    float* ubuf;            // reward: applied commands [T][4][D] inside the checkpoint buffer
+                            // (written by the forward, read by the backward) or null
     // forward outputs
     int K;                  // checkpoint interval
     float* ckpt;            // [ceil(T/K)][S][D] or null
@@ -74,6 +75,9 @@ struct RollArgs {
     uint32_t* nonfinite;
     // backward
     const float* ckpt_in;
+    const uint32_t* tag_in;  // the tag words at the end of ckpt_in
+    uint32_t tag_exp[16];    // the tag the host matched for this buffer
+    uint32_t* dflag;         // set to 1 when tag_in differs from tag_exp
     const float* dloss;     // [D] or null (ones)
     float* g_cmds;          // [T][4][D] or null
     float* g_x0;            // [S][D] or null

@@ -19,10 +19,17 @@ namespace cfk {
 
 constexpr int NG = 52;  // 4 x 13 gain entries
 
+// The reference table is the same for every drone and never written while a
+// rollout runs: its rows are read through the constant address space, i.e.
+// with scalar loads into the wave's scalar registers.
+__device__ __forceinline__ const const_float* ref_row(const RollArgs& a, int t, int stride) {
+    return (const const_float*)(a.ref_tab + (size_t)t * stride);
+}
+
 // position reference at step t (figure-eight table rows are [p(3), v(3)])
 __device__ __forceinline__ void ref_pos(const RollArgs& a, int t, const float* off, float* pr) {
     const int stride = a.ref_user ? 13 : 6;
-    const float* row = a.ref_tab + (size_t)t * stride;
+    const const_float* row = ref_row(a, t, stride);
 #pragma unroll
     for (int j = 0; j < 3; ++j) pr[j] = row[j] + off[j];
 }
@@ -31,14 +38,14 @@ __device__ __forceinline__ void ref_pos(const RollArgs& a, int t, const float* o
 template <int MODEL>
 __device__ __forceinline__ void ref_state(const RollArgs& a, int t, const float* off, float f_hover, float* xr) {
     if (a.ref_user) {
-        const float* row = a.ref_tab + (size_t)t * 13;
+        const const_float* row = ref_row(a, t, 13);
 #pragma unroll
         for (int j = 0; j < 13; ++j) xr[j] = row[j];
 #pragma unroll
         for (int j = 0; j < 3; ++j) xr[j] += off[j];
         return;
     }
-    const float* row = a.ref_tab + (size_t)t * 6;
+    const const_float* row = ref_row(a, t, 6);
 #pragma unroll
     for (int j = 0; j < 13; ++j) xr[j] = 0.f;
 #pragma unroll
@@ -258,23 +265,26 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
     float rc[4] = {0.f, 0.f, 0.f, 0.f};   // held rotor commands
     int phase = 0;                        // step within the controller period
     const bool rew = EXT && a.has_obj && a.obj_kind == 1;
+    float uprev[4] = {0.f, 0.f, 0.f, 0.f};   // reward: the previous applied command
+    if (rew) hover_action<MODEL, CTRL>(p, uprev);
     for (int t = 0; t < a.T; ++t) {
         float u[4], ev[13], unext[4];
         if (t + 1 < a.T) load_cmd(a, t + 1, d, unext);   // issued early, used next step
         feedback<MODEL>(a, G, x, t, off, f_hover, ubar, u, ev);
         if (rew) {
-            // the previous command is read back from the command buffer, so the
-            // reward keeps no values in registers across steps
             float ah[4];
             hover_action<MODEL, CTRL>(p, ah);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float up = t > 0 ? a.ubuf[((size_t)(t - 1) * 4 + i) * D + d] : ah[i];
-                const float da = u[i] - ah[i], dd = u[i] - up;
+                const float da = u[i] - ah[i], dd = u[i] - uprev[i];
                 loss += a.w_act[i] * da * da + a.w_dact[i] * dd * dd;
+                uprev[i] = u[i];
             }
+            // kept for the backward, which needs the neighbours of every command
+            if (a.ubuf) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a.ubuf[((size_t)t * 4 + i) * D + d] = u[i];
+                for (int i = 0; i < 4; ++i) a.ubuf[((size_t)t * 4 + i) * D + d] = u[i];
+            }
         } else if (a.has_obj) {
             loss += a.w_u * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3]);
         }
@@ -368,47 +378,72 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
     // registers across steps
     const bool rew = EXT && a.has_obj && a.obj_kind == 1;
     const int nseg = (a.T + a.K - 1) / a.K;
+    float pn[3];          // position of x_{t+1} of the step being reversed
+    // state and command of the next step to reverse, loaded one step ahead so
+    // that their memory latency overlaps the current step's arithmetic
+    float xq[S], uq[4];
+    bool have_q = false, q_ck = false;
     for (int s = nseg - 1; s >= 0; --s) {
         const int t0 = s * a.K;
         const int t1 = min(a.T, t0 + a.K);
         // recompute x_{t0+1} .. x_{t1-1} into segment slots 1..; slot 0 is the
-        // checkpoint itself. The state after the segment is the next checkpoint
-        // (only its position is needed); the last segment steps once more.
-        float x[S], comp[S];
-        load_rows<S>(a.ckpt_in + (size_t)s * SD, D, d, x);
-        to_dev<MODEL>(x, p);
-#pragma unroll
-        for (int i = 0; i < S; ++i) comp[i] = 0.f;
+        // checkpoint itself. The state after the segment is the next checkpoint,
+        // whose position the previous (later) segment's sweep ended on; the last
+        // segment steps once more for the final position.
         const int n_re = (s == nseg - 1) ? (t1 - t0) : (t1 - t0 - 1);
-        float rcf[4] = {0.f, 0.f, 0.f, 0.f};
-        if constexpr (HAS_CTRL) {
-            // a segment that starts inside a block (period longer than the
-            // checkpoint interval) starts with that block's held commands
-            if (n_re > 0 && t0 % n_c != 0)
-                block_commands<MODEL, CTRL, S>(a, p, G, off, f_hover, D, d, SD, t0 - t0 % n_c, t0, rcf);
-        }
-        for (int j = 0; j < n_re; ++j) {
-            float u[4], ev[13], ubar[4];
-            load_cmd(a, t0 + j, d, ubar);
-            feedback<MODEL>(a, G, x, t0 + j, off, f_hover, ubar, u, ev);
-            model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a, rcf, (t0 + j) % n_c == 0);
-            if (j + 1 < t1 - t0 || rew) store_rows<S>(a.seg + (size_t)(j + 1) * SD, D, d, x);
-        }
-        float pn[3];  // position of x_{t+1}
-        if (s == nseg - 1) {
-            pn[0] = x[0]; pn[1] = x[1]; pn[2] = x[2];
-        } else {
-            const float* nxt = a.ckpt_in + (size_t)(s + 1) * SD;
+        if (n_re > 0) {
+            float x[S], comp[S];
+            load_rows<S>(a.ckpt_in + (size_t)s * SD, D, d, x);
+            to_dev<MODEL>(x, p);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) pn[j] = nxt[j * D + d];
+            for (int i = 0; i < S; ++i) comp[i] = 0.f;
+            float rcf[4] = {0.f, 0.f, 0.f, 0.f};
+            if constexpr (HAS_CTRL) {
+                // a segment that starts inside a block (period longer than the
+                // checkpoint interval) starts with that block's held commands
+                if (t0 % n_c != 0)
+                    block_commands<MODEL, CTRL, S>(a, p, G, off, f_hover, D, d, SD, t0 - t0 % n_c, t0, rcf);
+            }
+            for (int j = 0; j < n_re; ++j) {
+                float u[4], ev[13], ubar[4];
+                load_cmd(a, t0 + j, d, ubar);
+                feedback<MODEL>(a, G, x, t0 + j, off, f_hover, ubar, u, ev);
+                model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a, rcf, (t0 + j) % n_c == 0);
+                if (j + 1 < t1 - t0 || rew) store_rows<S>(a.seg + (size_t)(j + 1) * SD, D, d, x);
+            }
+            if (s == nseg - 1) {
+                pn[0] = x[0]; pn[1] = x[1]; pn[2] = x[2];
+            }
         }
         const float* ck = a.ckpt_in + (size_t)s * SD;
+        // x_t: the checkpoint itself or a recomputed slot of the segment
+        float xc[S], uc[4];
+        if (have_q) {
+#pragma unroll
+            for (int i = 0; i < S; ++i) xc[i] = xq[i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) uc[i] = uq[i];
+            if (q_ck) to_dev<MODEL>(xc, p);
+        } else {
+            load_rows<S>((t1 - 1 > t0) ? a.seg + (size_t)(t1 - 1 - t0) * SD : ck, D, d, xc);
+            if (!(t1 - 1 > t0)) to_dev<MODEL>(xc, p);
+            load_cmd(a, t1 - 1, d, uc);
+        }
         for (int t = t1 - 1; t >= t0; --t) {
-            // x_t: the checkpoint itself or a recomputed slot of the segment
-            float xc[S], uc[4];
-            load_rows<S>((t > t0) ? a.seg + (size_t)(t - t0) * SD : ck, D, d, xc);
-            if (!(t > t0)) to_dev<MODEL>(xc, p);
-            load_cmd(a, t, d, uc);
+            // issue the loads of step t - 1: a slot or the checkpoint of this
+            // segment, or, with a checkpoint every step, the previous checkpoint
+            have_q = false;
+            if (t > t0) {
+                q_ck = !(t - 1 > t0);
+                load_rows<S>(q_ck ? ck : a.seg + (size_t)(t - 1 - t0) * SD, D, d, xq);
+                load_cmd(a, t - 1, d, uq);
+                have_q = true;
+            } else if (a.K == 1 && s > 0) {
+                q_ck = true;
+                load_rows<S>(a.ckpt_in + (size_t)(s - 1) * SD, D, d, xq);
+                load_cmd(a, t - 1, d, uq);
+                have_q = true;
+            }
             if (a.has_obj) {
                 float pr[3];
                 ref_pos(a, t + 1, off, pr);
@@ -498,9 +533,21 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
             for (int i = 0; i < S; ++i) lam[i] = xb[i];
             pn[0] = xc[0]; pn[1] = xc[1]; pn[2] = xc[2];
+            if (t > t0) {
+#pragma unroll
+                for (int i = 0; i < S; ++i) xc[i] = xq[i];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) uc[i] = uq[i];
+                if (q_ck) to_dev<MODEL>(xc, p);
+            }
         }
     }
-    if (a.g_x0) store_rows<S>(a.g_x0, D, d, lam);
+    if (a.g_x0) {
+        store_rows<S>(a.g_x0, D, d, lam);
+        // rows the drone's model does not use (identified drones of a handle with
+        // more rows) do not affect the loss
+        for (int i = S; i < S_h; ++i) a.g_x0[(size_t)i * D + d] = 0.f;
+    }
     if (a.ggc) {
         if (G) {
 #pragma unroll
@@ -510,6 +557,28 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
             for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = 0.f;
         }
     }
+}
+
+// The backward reads a checkpoint buffer only while it still holds the tag of
+// the forward the host matched; otherwise every requested output of the drone
+// is NaN and the handle's device flag is raised (reported as CF_ESTATE).
+__device__ __forceinline__ bool ckpt_tag_intact(const RollArgs& a) {
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) ok &= (a.tag_in[i] == a.tag_exp[i]);
+    return ok;
+}
+
+__device__ __forceinline__ void poison_gradients(const RollArgs& a, size_t d) {
+    const size_t D = (size_t)a.D;
+    const float nan = __builtin_nanf("");
+    if (a.g_cmds)
+        for (size_t i = 0; i < (size_t)a.T * 4; ++i) a.g_cmds[i * D + d] = nan;
+    if (a.g_x0)
+        for (int i = 0; i < a.S_h; ++i) a.g_x0[(size_t)i * D + d] = nan;
+    if (a.ggc)
+        for (int i = 0; i < NG; ++i) a.ggc[(size_t)i * D + d] = nan;
+    atomicOr(a.dflag, 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -539,6 +608,12 @@ __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
     rollout_priority();
     const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= (size_t)a.D) return;
+    if constexpr (BWD) {
+        if (!ckpt_tag_intact(a)) {
+            poison_gradients(a, d);
+            return;
+        }
+    }
     const int w = a.drone_world[d];
     const SoaRec rec{a.par_soa, a.M, w};
     const float* G = (a.has_obj && a.gain) ? a.gain + (size_t)a.gidx[w] * NG : nullptr;
@@ -570,6 +645,12 @@ __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __
     using Rec = typename std::conditional<BWD, ScalarRec, AosRec>::type;
     const Rec rec{a.par_aos + (size_t)w * NREC};
     const size_t d = (size_t)d0 + threadIdx.x;
+    if constexpr (BWD) {
+        if (!ckpt_tag_intact(a)) {
+            poison_gradients(a, d);
+            return;
+        }
+    }
     extern __shared__ float roll_lds[];   // backward: [NG][blockDim.x] gain-gradient sums
     float* gl = roll_lds + threadIdx.x;
     const int gs = blockDim.x;

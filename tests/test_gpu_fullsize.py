@@ -44,6 +44,17 @@ def test_swarm_64x4000_chunkings_and_samples(gpu_lib):
         assert_states_close(outs[k], outs[1000], w, what=f"config3 all drones, {k} vs 1000 steps per launch")
 
 
+_CONFIG4_ORACLE = {}
+
+
+def _config4_oracle(w):
+    """The oracle's loss and gradients of the full differentiable workload,
+    computed once for the three checkpoint intervals."""
+    if "ref" not in _CONFIG4_ORACLE:
+        _CONFIG4_ORACLE["ref"] = O.rollout_workload(w, with_grad=True)
+    return _CONFIG4_ORACLE["ref"]
+
+
 @pytest.mark.parametrize("K", [25, 50, 100])
 def test_differentiable_1024_worlds(gpu_lib, K):
     w = W.config4()
@@ -51,19 +62,17 @@ def test_differentiable_1024_worlds(gpu_lib, K):
     T = w.steps
     x0, cmds, gain = dev(w.x0), dev(w.cmds), dev(w.gain)
     obj = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u)
-    ckpt = torch.empty(((T + K - 1) // K, sim.S, sim.D), device="cuda")
+    ckpt = sim.ckpt_buffer(T, K)
     loss = torch.empty(sim.D, device="cuda")
     sim.rollout(x0, cmds, T, obj, K, ckpt=ckpt, loss=loss)
     g_cmds, g_x0, g_gain = torch.empty_like(cmds), torch.empty_like(x0), torch.empty_like(gain)
     sim.rollout_backward(x0, cmds, T, obj, K, ckpt, dloss=dev(w.dloss), g_cmds=g_cmds, g_x0=g_x0, g_gain=g_gain)
     torch.cuda.synchronize()
-    if K != 50:
-        return  # the oracle comparison is done once; other K are checked against K = 50 below
-    ref = O.rollout_workload(w, with_grad=True)
+    ref = _config4_oracle(w)
     lr = ref["loss"]
     assert torch.all((loss.double().cpu() - lr).abs() <= 1e-4 * lr.abs().clamp_min(1e-2))
-    assert_grad_close(g_cmds, ref["g_cmds"], "config4 g_cmds")
-    assert_grad_close(g_x0, ref["g_x0"], "config4 g_x0")
+    assert_grad_close(g_cmds, ref["g_cmds"], f"config4 K={K} g_cmds")
+    assert_grad_close(g_x0, ref["g_x0"], f"config4 K={K} g_x0")
     assert (g_gain.double().cpu() - ref["g_gain"]).norm() <= 1e-3 * ref["g_gain"].norm()
 
 
@@ -75,7 +84,7 @@ def test_differentiable_checkpoint_invariance_full(gpu_lib):
     obj = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u)
     res = {}
     for K in (25, 50, 100):
-        ckpt = torch.empty(((T + K - 1) // K, sim.S, sim.D), device="cuda")
+        ckpt = sim.ckpt_buffer(T, K)
         sim.rollout(x0, cmds, T, obj, K, ckpt=ckpt)
         g = [torch.empty_like(cmds), torch.empty_like(x0), torch.empty_like(gain)]
         sim.rollout_backward(x0, cmds, T, obj, K, ckpt, g_cmds=g[0], g_x0=g[1], g_gain=g[2])
@@ -123,7 +132,7 @@ def test_uneven_adjoint_subset_full(gpu_lib):
     T, K = w.steps, 50
     x0, cmds, gain, off = dev(w.x0), dev(w.cmds), dev(w.gain), dev(w.ref_offset)
     obj = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, ref_offset=off, w_u=w.w_u)
-    ckpt = torch.empty(((T + K - 1) // K, sim.S, sim.D), device="cuda")
+    ckpt = sim.ckpt_buffer(T, K)
     traj = torch.empty((T + 1, sim.S, sim.D), device="cuda")
     loss = torch.empty(sim.D, device="cuda")
     sim.rollout(x0, cmds, T, obj, K, ckpt=ckpt, traj=traj, loss=loss)
@@ -183,7 +192,7 @@ def test_goal_gradient_2p20_worlds_sampled(gpu_lib):
     T = w.steps
     x0, cmds, off = dev(w.x0), dev(w.cmds), dev(w.ref_offset)
     obj = B.Sim.objective(ref_amp=w.ref_amp, ref_period=w.ref_period, ref_offset=off, w_u=w.w_u)
-    ckpt = torch.empty((1, sim.S, sim.D), device="cuda")
+    ckpt = sim.ckpt_buffer(T, T)
     loss = torch.empty(sim.D, device="cuda")
     sim.rollout(x0, cmds, T, obj, T, ckpt=ckpt, loss=loss)
     g_cmds, g_x0 = torch.empty_like(cmds), torch.empty_like(x0)
@@ -226,3 +235,38 @@ def test_interfaces_2p20_worlds_sampled(gpu_lib, name):
     ii = torch.as_tensor(idx, device="cuda")
     assert_states_close(x[:, ii], O.simulate_held(ws), ws, what=f"{name} 2^20 worlds, sampled")
     sim.close()
+
+
+def test_shared_gain_gradient_over_2p20_worlds(gpu_lib):
+    """2^20 single-drone identified worlds sharing one 4x13 gain, 10 steps: the
+    gain gradient (a fixed-order two-stage reduction over the drones) is
+    bit-identical across calls and equals sum_t sum_d g_cmds[t, :, d] e_t[d]^T
+    evaluated in float64 from the trajectory."""
+    w = W.config4(seed=95, n_worlds=1 << 20, steps=10)
+    sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
+    T, D = w.steps, w.n_drones_total
+    x0, cmds, gain = dev(w.x0), dev(w.cmds), dev(w.gain)
+    obj = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u)
+    ckpt = sim.ckpt_buffer(T, T)
+    traj = torch.empty((T + 1, sim.S, D), device="cuda")
+    sim.rollout(x0, cmds, T, obj, T, ckpt=ckpt, traj=traj)
+    g_cmds = torch.empty_like(cmds)
+    gg = [torch.empty_like(gain), torch.empty_like(gain)]
+    for g in gg:
+        sim.rollout_backward(x0, cmds, T, obj, T, ckpt, g_cmds=g_cmds, g_gain=g)
+    torch.cuda.synchronize()
+    assert torch.equal(gg[0], gg[1])
+    t = torch.arange(T, device="cuda", dtype=torch.float64) * np.float32(w.dt)
+    w0 = 2 * np.pi / w.ref_period
+    xr = torch.zeros((T, 13, 1), device="cuda", dtype=torch.float64)
+    xr[:, 0, 0] = w.ref_amp * torch.sin(w0 * t)
+    xr[:, 1, 0] = 0.5 * w.ref_amp * torch.sin(2 * w0 * t)
+    xr[:, 6, 0] = w.ref_amp * w0 * torch.cos(w0 * t)
+    xr[:, 7, 0] = w.ref_amp * w0 * torch.cos(2 * w0 * t)
+    xr[:, 12, 0] = float(np.float32(W.MASS) * np.float32(W.GRAVITY) / np.float32(W.ID_CF))
+    ref = torch.zeros((4, 13), device="cuda", dtype=torch.float64)
+    for n in range(T):
+        e = traj[n, 0:13].double() - xr[n]
+        ref += g_cmds[n].double() @ e.T
+    err = (gg[0][0].double() - ref).norm() / ref.norm()
+    assert err <= 1e-4, err

@@ -111,7 +111,7 @@ def test_rejects_step_counts_and_intervals_off_the_block(gpu_lib):
     with pytest.raises(B.CfError):
         sim.step_k(x, u, 4)
     T, K = w.steps, 2
-    ckpt = torch.empty(((T + K - 1) // K, sim.S, sim.D), device="cuda")
+    ckpt = sim.ckpt_buffer(T, K)
     with pytest.raises(B.CfError):
         sim.rollout(x, dev(w.cmds), T, None, K, ckpt=ckpt)
     sim.step_k(x, u, 6)   # a multiple of the block is accepted

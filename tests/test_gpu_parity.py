@@ -128,8 +128,7 @@ def _rollout_grads(w, K, sim=None):
     off = None if w.ref_offset is None else dev(w.ref_offset)
     obj = B.Sim.objective(gain=gain, ref_amp=w.ref_amp, ref_period=w.ref_period, ref_offset=off, w_u=w.w_u,
                           reward=w.reward)
-    nseg = (T + K - 1) // K
-    ckpt = torch.empty((nseg, sim.S, sim.D), device="cuda")
+    ckpt = sim.ckpt_buffer(T, K, int(obj.kind))
     loss = torch.empty(sim.D, device="cuda")
     lw = torch.empty(sim.n_worlds, device="cuda")
     xT = torch.empty_like(x0)

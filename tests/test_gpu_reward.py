@@ -49,7 +49,7 @@ def test_reward_one_per_step_in_hover(gpu_lib):
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     loss = torch.empty(sim.D, device="cuda")
     obj = B.Sim.objective(ref_amp=0.0, ref_period=w.ref_period, ref_offset=dev(w.ref_offset), reward=w.reward)
-    ckpt = torch.empty((3, sim.S, sim.D), device="cuda")
+    ckpt = sim.ckpt_buffer(w.steps, 10, B.CF_OBJ_BPTT_REWARD)
     sim.rollout(dev(w.x0), dev(w.cmds), w.steps, obj, 10, ckpt=ckpt, loss=loss)
     torch.cuda.synchronize()
     assert np.allclose(loss.cpu().numpy(), -w.steps, rtol=0, atol=1e-4 * w.steps)
@@ -60,13 +60,13 @@ def test_reward_rejects_position_interface_and_bad_weights(gpu_lib):
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     x0 = dev(w.x0)
     cmds = dev(np.repeat(w.cmds[None], 10, 0))
-    ckpt = torch.empty((1, sim.S, sim.D), device="cuda")
+    ckpt = sim.ckpt_buffer(10, 10, B.CF_OBJ_BPTT_REWARD)
     with pytest.raises(B.CfError):
         sim.rollout(x0, cmds, 10, B.Sim.objective(reward=W.BPTT_REWARD), 10, ckpt=ckpt)
     w2 = W.small(4, seed=35)
     sim2 = B.Sim.from_workload(w2, flags=B.F_NO_AUTOTUNE_CACHE)
     bad = dict(W.BPTT_REWARD, w_tilt=-1.0)
-    ck2 = torch.empty((10, sim2.S, sim2.D), device="cuda")
+    ck2 = sim2.ckpt_buffer(w2.steps, 10, B.CF_OBJ_BPTT_REWARD)
     with pytest.raises(B.CfError):
         sim2.rollout(dev(w2.x0), dev(w2.cmds), w2.steps, B.Sim.objective(reward=bad), 10, ckpt=ck2)
 

@@ -557,6 +557,23 @@ def test_gradient_fd_first_principles_rotor():
     _fd_check(w, h=1e-3)
 
 
+def test_gradient_fd_asymmetric_rotor_law_away_from_the_kink():
+    """Distinct acceleration/deceleration coefficients with quadratic terms:
+    commands held 20 % above or below hover per rotor, so no rotor's command
+    crosses its speed in 20 steps (no branch switch) and the central
+    differences see a smooth map."""
+    w = W.config1(seed=15, n_worlds=3, steps=20)
+    w.params["motor_up"][:] = (40.0, 5e-4)
+    w.params["motor_down"][:] = (20.0, 1e-3)
+    hov = float(W.hover_speed(W.MASS))
+    sgn = np.array([[1.0, -1.0, 1.0], [-1.0, -1.0, 1.0], [1.0, 1.0, -1.0], [-1.0, 1.0, 1.0]])
+    w.cmds = np.broadcast_to(hov * (1.0 + 0.2 * sgn), (w.steps, 4, 3)).astype(np.float32).copy()
+    w.ref_offset = w.x0[0:3].copy()
+    w.dloss = np.ones(3, np.float32)
+    w.w_u = 1e-9
+    _fd_check(w, h=1e-3)
+
+
 def test_gain_gradient_identity():
     """u_t = ubar_t + G e_t gives dL/dG = sum_t (dL/du_t) e_t^T exactly."""
     w = W.config4(seed=14, n_worlds=4, steps=25, gain_std=0.05)
