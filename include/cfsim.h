@@ -340,6 +340,28 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
                               const float* dloss, float* g_cmds, float* g_x0, float* g_gain);
 
 /*
+ * cf_rollout_backward_noalloc: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving or training loops, harnesses
+ * that forbid hipMalloc). The same gradients as cf_rollout_backward, with the
+ * same arguments, ownership and errors, but every scratch buffer (the
+ * figure-eight table, recomputed segment states, per-drone gain-gradient terms
+ * and the gain reduction's partial sums) lives in one static device array of
+ * CF_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from the first
+ * cf_create on that GPU until the process ends; the call allocates nothing.
+ * A request whose scratch exceeds the array returns CF_EINVAL before any work:
+ * it needs (T + 1) * 6 floats with a figure-eight objective, plus
+ * (min(K, T) + 1{reward}) * S * D floats when that is more than one state, plus
+ * 52 * D + n_gains * 52 * min(1024, ceil(D / 2048)) floats with g_gain, each
+ * rounded up to 64 floats. Every call on one GPU uses the same array, so calls
+ * that overlap on one GPU (other streams, other handles, other threads) race;
+ * nothing in it needs to start at zero.
+ */
+#define CF_NOALLOC_SCRATCH_BYTES (64u << 20)
+cf_status cf_rollout_backward_noalloc(cf_handle* h, const float* x0, const float* cmds, int32_t T,
+                                      const cf_objective* obj, int32_t ckpt_every, const float* ckpt,
+                                      const float* dloss, float* g_cmds, float* g_x0, float* g_gain);
+
+/*
  * cf_autotune (the paper leaves kernel fusion and scheduling to its JIT
  * compiler, Methods, "Architecture"; here the launch shape is chosen by
  * measurement): time candidate launch shapes of cf_step_k (fused grid vs

@@ -40,7 +40,7 @@ PARAM_OFFSETS = {
 }
 
 EXPORTS = ("cf_create", "cf_destroy", "cf_state_dim", "cf_total_drones", "cf_world_offsets", "cf_set_stream",
-           "cf_reset", "cf_step_k", "cf_rollout", "cf_rollout_backward", "cf_ckpt_floats", "cf_autotune", "cf_launch_config", "cf_set_launch_config", "cf_launch_times",
+           "cf_reset", "cf_step_k", "cf_rollout", "cf_rollout_backward", "cf_rollout_backward_noalloc", "cf_ckpt_floats", "cf_autotune", "cf_launch_config", "cf_set_launch_config", "cf_launch_times",
            "cf_strerror", "cf_last_error", "cf_mppi_create", "cf_mppi_destroy", "cf_mppi_step", "cf_mppi_noise", "cf_probe_fma")
 
 MPPI_MAX_OBSTACLES = 16
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "cf_step_k": ([H, P, P, c_int32, P], c_int32),
         "cf_rollout": ([H, P, P, c_int32, POINTER(_Objective), c_int32, P, P, P, P, P], c_int32),
         "cf_rollout_backward": ([H, P, P, c_int32, POINTER(_Objective), c_int32, P, P, P, P, P], c_int32),
+        "cf_rollout_backward_noalloc": ([H, P, P, c_int32, POINTER(_Objective), c_int32, P, P, P, P, P], c_int32),
         "cf_ckpt_floats": ([H, c_int32, c_int32, c_int32, POINTER(c_int64)], c_int32),
         "cf_autotune": ([H, P, P, c_int32, c_int32], c_int32),
         "cf_launch_config": ([H, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)], c_int32),
@@ -334,6 +335,24 @@ class Sim:
         _check(self._lib.cf_rollout_backward(self._h, _ptr(x0), _ptr(cmds), int(T), o, int(ckpt_every),
                                              _ptr(ckpt), _ptr(dloss), _ptr(g_cmds), _ptr(g_x0), _ptr(g_gain)),
                "cf_rollout_backward")
+
+    def rollout_backward_noalloc(self, x0, cmds, T: int, obj, ckpt_every: int, ckpt, dloss=None, g_cmds=None,
+                                 g_x0=None, g_gain=None) -> None:
+        """rollout_backward without device allocation (scratch in the library's
+        static per-GPU array; calls on one GPU must not overlap)."""
+        T = int(T)
+        self._need(cmds, (T, 4, self.D), "cmds")
+        self._need_ckpt(ckpt, T, ckpt_every, obj)
+        self._need(dloss, (self.D,), "dloss")
+        self._need(g_cmds, (T, 4, self.D), "g_cmds")
+        self._need(g_x0, (self.S, self.D), "g_x0")
+        self._need(g_gain, (self.n_gains, 4, 13), "g_gain")
+        self._need_obj(obj, T)
+        self._sync_stream()
+        o = ctypes.byref(obj) if obj is not None else None
+        _check(self._lib.cf_rollout_backward_noalloc(self._h, _ptr(x0), _ptr(cmds), int(T), o, int(ckpt_every),
+                                                     _ptr(ckpt), _ptr(dloss), _ptr(g_cmds), _ptr(g_x0),
+                                                     _ptr(g_gain)), "cf_rollout_backward_noalloc")
 
     def autotune(self, state, cmd, k: int, budget_ms: int = 2000) -> None:
         self._need(state, (self.S, self.D), "state")

@@ -137,6 +137,33 @@ static int gain_blocks(int64_t D) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, GAIN_MAX_BLOCKS));
 }
 
+// Scratch of cf_rollout_backward_noalloc: one static device array, each GPU that
+// runs the library holds its own copy until the process ends. Host code reaches
+// it only through the address hipGetSymbolAddress gives per device (at
+// cf_create); calls on one GPU share it.
+static __device__ __align__(256) float scratch[CF_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+constexpr int MAX_SCRATCH_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[MAX_SCRATCH_DEVICES] = {};
+
+// the scratch address of the current device h->device, looked up once per device
+static hipError_t scratch_setup(int dev) {
+    if (dev < 0 || dev >= MAX_SCRATCH_DEVICES) return hipSuccess;   // no static scratch there
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (float*)p;
+    return hipSuccess;
+}
+
+static float* scratch_of(int dev) {
+    if (dev < 0 || dev >= MAX_SCRATCH_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
 // ---------------------------------------------------------------------------
 // handle
 
@@ -478,6 +505,7 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
     if ((e = dalloc(&h->drone_world, (size_t)std::max<int64_t>(D, 1))) != hipSuccess) return fail(e);
     if ((e = dalloc(&h->d_offsets, M + 1)) != hipSuccess) return fail(e);
     if ((e = dalloc(&h->d_gidx, M)) != hipSuccess) return fail(e);
+    if ((e = scratch_setup(dev)) != hipSuccess) return fail(e);
     static std::atomic<uint32_t> next_id{1};
     h->id = next_id.fetch_add(1);
     if ((e = dalloc(&h->dflag, 1)) != hipSuccess) return fail(e);
@@ -925,7 +953,8 @@ cf_status cf_rollout(cf_handle* h, const float* x0, const float* cmds, int32_t T
     return CF_OK;
 }
 
-// Device scratch of one backward call (the handle's buffers, grown on demand).
+// Device scratch of one backward call: the handle's buffers (grown on demand) or,
+// without allocation, consecutive 256-byte-aligned slices of the static array.
 struct BwdScratch {
     float* ref_tab = nullptr;   // [T + 1][6], figure-eight objectives
     float* seg = nullptr;       // [slots][S][D] recomputed segment states
@@ -935,7 +964,7 @@ struct BwdScratch {
 
 static cf_status rollout_backward_impl(cf_handle* h, const float* cmds, int32_t T, const cf_objective* obj,
                                        int32_t K, const float* ckpt, const float* dloss, float* g_cmds, float* g_x0,
-                                       float* g_gain) {
+                                       float* g_gain, bool noalloc) {
     if (!h || T < 1 || K < 1 || !ckpt) return CF_EINVAL;
     if (K % h->ctrl_every != 0 && h->ctrl_every % K != 0) return CF_EINVAL;
     if (h->sticky != CF_OK) return h->sticky;
@@ -966,7 +995,25 @@ static cf_status rollout_backward_impl(cf_handle* h, const float* cmds, int32_t 
     hipSetDevice(h->device);
     hipError_t e;
     BwdScratch sc;
-    {
+    if (noalloc) {
+        float* base = scratch_of(h->device);
+        if (!base) return CF_EUNSUPPORTED;
+        // 256-byte-aligned slices; sizes beyond the array are refused before any work
+        auto up = [](size_t n) { return (n + 63) / 64 * 64; };
+        const size_t cap = CF_NOALLOC_SCRATCH_BYTES / sizeof(float);
+        if (up(n_tab) + up(n_seg) + up(n_ggc) + up(n_part) > cap) return CF_EINVAL;
+        float* q = base;
+        auto take = [&](size_t n) -> float* {
+            if (n == 0) return nullptr;
+            float* r = q;
+            q += up(n);
+            return r;
+        };
+        sc.ref_tab = take(n_tab);
+        sc.seg = take(n_seg);
+        sc.ggc = take(n_ggc);
+        sc.gpart = take(n_part);
+    } else {
         if (n_seg && (e = ensure(h->seg, n_seg * sizeof(float))) != hipSuccess) return note(h, e);
         if (n_ggc && (e = ensure(h->ggc, n_ggc * sizeof(float))) != hipSuccess) return note(h, e);
         if (n_part && (e = ensure(h->gpart, n_part * sizeof(float))) != hipSuccess) return note(h, e);
@@ -1019,8 +1066,16 @@ cf_status cf_rollout_backward(cf_handle* h, const float* x0, const float* cmds, 
                               int32_t K, const float* ckpt, const float* dloss, float* g_cmds, float* g_x0,
                               float* g_gain) {
     (void)x0;   // the checkpoint holds it
-    return rollout_backward_impl(h, cmds, T, obj, K, ckpt, dloss, g_cmds, g_x0, g_gain);
+    return rollout_backward_impl(h, cmds, T, obj, K, ckpt, dloss, g_cmds, g_x0, g_gain, false);
 }
+
+cf_status cf_rollout_backward_noalloc(cf_handle* h, const float* x0, const float* cmds, int32_t T,
+                                      const cf_objective* obj, int32_t K, const float* ckpt, const float* dloss,
+                                      float* g_cmds, float* g_x0, float* g_gain) {
+    (void)x0;
+    return rollout_backward_impl(h, cmds, T, obj, K, ckpt, dloss, g_cmds, g_x0, g_gain, true);
+}
+
 
 // ---------------------------------------------------------------------------
 // autotune
