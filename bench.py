@@ -29,14 +29,14 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 # Algorithmic FP32 work per drone-step of the discrete map (add/sub/mul = 1,
-# FMA = 2, each sqrt/rsqrt/sin-cos/atan2/asin = 1; no compensation or
-# rotor-deviation bookkeeping): first-principles RK4 at the rotor interface
-# 596 + 1 rsqrt; with the attitude PID and allocation 806 + 4 sqrt + atan2 +
-# asin; identified model RK4 301 + 12 sin/cos; identified rollout with the 4x13
-# feedback and the tracking loss 413 per step forward, and forward +
-# checkpoint recompute + reverse sweep 413 + 413 + 1000. The line-by-line tally
-# from the equations is in the design notes next to these figures.
-FLOPS_PER_DS = {"fp_rotor_rk4": 597.0, "fp_pid_rk4": 812.0, "id_rk4": 313.0,
+# FMA = 2, each sqrt/rsqrt/sin-cos pair/atan2/asin = 1; no compensation or
+# rotor-deviation bookkeeping), the smaller of two counts per path (an
+# estimate from the equations and a line-by-line tally of them):
+# first-principles RK4 at the rotor interface 596 + 1 rsqrt; with the attitude
+# PID and allocation 806 + 4 sqrt + atan2 + asin; identified model RK4 293 + 12
+# sin-cos; identified rollout with the 4x13 feedback and the tracking loss 413
+# per step forward, and forward + checkpoint recompute + reverse 413 + 413 + 1000.
+FLOPS_PER_DS = {"fp_rotor_rk4": 597.0, "fp_pid_rk4": 812.0, "id_rk4": 305.0,
                 "id_rollout_fwd": 413.0, "id_rollout_fwd_bwd": 1826.0}
 SPEC_FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak
 SPEC_HBM_GBS = 8000.0
@@ -72,7 +72,9 @@ def parse():
     p.add_argument("--ckpt", type=int, default=0,
                    help="checkpoint interval; 0 = tune among 1, 10, 50, 100 (alone, then in the job)")
     p.add_argument("--serial", action="store_true", help="run the subset adjoint after the forward")
-    p.add_argument("--no-graph", action="store_true", help="enqueue the held steps directly (no hipGraph replay)")
+    p.add_argument("--graph", action="store_true",
+                   help="time the job with the held steps replayed from a hipGraph (default: enqueued directly; "
+                        "the other form is timed too and reported under graph_comparison)")
     p.add_argument("--autotune-ms", type=int, default=3000)
     p.add_argument("--job-only", action="store_true",
                    help="only the timed job (for profiler runs): no comparators, configurations or baselines")
@@ -136,8 +138,10 @@ def main():
         tune.autotune(state, cmd, T, args.autotune_ms)
     cfg = tune.launch_config()
     tune.close()
-    sim = B.Sim.from_workload(w, flags=0 if args.no_graph else B.F_GRAPH)
+    sim = B.Sim.from_workload(w, flags=B.F_GRAPH if args.graph else 0)
     sim.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"])
+    simO = B.Sim.from_workload(w, flags=0 if args.graph else B.F_GRAPH)   # the other form
+    simO.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"])
     # the same launches enqueued directly with an event pair around each kernel
     # launch, for the kernels' own durations (a graph replay is timed as a whole)
     simT = B.Sim.from_workload(w, flags=B.F_TIMING)
@@ -233,6 +237,25 @@ def main():
         K = best[0]
     cur["K"], cur["ckpt"] = K, adjoint_buffers(K)
     ckpt = cur["ckpt"]
+    # resident work-queue waves per SIMD of the held step inside the job: every
+    # wave that fits, or fewer so that adjoint waves find registers on more SIMDs
+    # (median of 4 job steps per candidate)
+    wq_best = (0, None)
+    if cfg["workqueue"] and not args.serial:
+        for cap in (0, 2, 1):
+            for h_ in (sim, simO, simT):
+                h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"], cap)
+            one_step()
+            torch.cuda.synchronize()
+            trial = []
+            for _ in range(4):
+                one_step(trial)
+            torch.cuda.synchronize()
+            med = float(np.median([r[0].elapsed_time(r[6]) for r in trial]))
+            if wq_best[1] is None or med < wq_best[1]:
+                wq_best = (cap, med)
+        for h_ in (sim, simO, simT):
+            h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"], wq_best[0])
     # standalone phases (nothing else on the GPU), HIP events on the same streams
     adjoint(K, ckpt)
     a, b = ev(), ev()
@@ -261,6 +284,17 @@ def main():
     wall = time.perf_counter() - t0
     if sim.last_error() != 0 or simA.last_error() != 0:
         raise RuntimeError("device error during the timed region")
+    # the same job with the held steps in the other form (graph replay or direct)
+    for _ in range(args.warmup + 1):
+        one_step(sim=simO)
+    torch.cuda.synchronize()
+    recsO = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(recsO, sim=simO)
+    torch.cuda.synchronize()
+    wallO = time.perf_counter() - t0
+    jobO = np.array([r[0].elapsed_time(r[6]) for r in recsO])
     # per-launch durations of the held-step kernels inside the job: the same job
     # steps with the directly enqueued, event-timed handle (HIP events the
     # library records around each launch on the stream it is launched on)
@@ -311,10 +345,14 @@ def main():
         "config": {"workload": "uneven_mixed_2048w_logu1-4000_T1000_plus_adjoint_256w",
                    "worlds": w.n_worlds, "drones": D, "horizon": T, "adjoint_worlds": ws.n_worlds,
                    "adjoint_drones": Ds, "ckpt_every": K, "integrator": "rk4", "dt": w.dt,
-                   "launch": cfg, "hipgraph": not args.no_graph, "adjoint_overlapped": not args.serial},
+                   "launch": dict(cfg, wq_waves_per_simd=wq_best[0]), "hipgraph": bool(args.graph),
+                   "adjoint_overlapped": not args.serial},
         "fwd_drone_steps_per_s": D * T / (fwd_ms * 1e-3),
         "fwdbwd_drone_steps_per_s": Ds * T / ((rf_ms + rb_ms) * 1e-3),
         "step_ms_stats": stats(job),
+        "graph_comparison": {"held_steps_replayed_from_hipgraph": not args.graph,
+                             "ms_per_step": wallO * 1e3 / args.steps, "step_ms_stats": stats(jobO),
+                             "value": (D * T + Ds * T) / (wallO / args.steps)},
         "phase_ms": {"reset": float(ph[:, 0].mean()), "forward": fwd_ms, "rollout_fwd": rf_ms,
                      "rollout_bwd": rb_ms, "forward_std": float(ph[:, 1].std())},
         "standalone_ms": standalone,

@@ -104,7 +104,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "cf_ckpt_floats": ([H, c_int32, c_int32, c_int32, POINTER(c_int64)], c_int32),
         "cf_autotune": ([H, P, P, c_int32, c_int32], c_int32),
         "cf_launch_config": ([H, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)], c_int32),
-        "cf_set_launch_config": ([H, c_int32, c_int32, c_int32], c_int32),
+        "cf_set_launch_config": ([H, c_int32, c_int32, c_int32, c_int32], c_int32),
         "cf_launch_times": ([H, c_int32, POINTER(c_float), c_int32, POINTER(c_int32)], c_int32),
         "cf_strerror": ([c_int32], ctypes.c_char_p),
         "cf_last_error": ([H], c_int32),
@@ -366,10 +366,13 @@ class Sim:
                "cf_launch_config")
         return {"workqueue": a.value & 1, "per_model_launches": (a.value >> 1) & 1, "tile": b.value, "chunk": c.value}
 
-    def set_launch_config(self, workqueue: int = 0, tile: int = 64, chunk: int = 0, per_model_launches: int = 1):
-        """Pin the launch choice of step_k (see launch_config)."""
+    def set_launch_config(self, workqueue: int = 0, tile: int = 64, chunk: int = 0, per_model_launches: int = 1,
+                          wq_waves: int = 0):
+        """Pin the launch choice of step_k (see launch_config); ``wq_waves`` caps the
+        work queue's resident waves per SIMD (0 = as many as fit)."""
         wq = (int(workqueue) & 1) | ((int(per_model_launches) & 1) << 1)
-        _check(self._lib.cf_set_launch_config(self._h, wq, int(tile), int(chunk)), "cf_set_launch_config")
+        _check(self._lib.cf_set_launch_config(self._h, wq, int(tile), int(chunk), int(wq_waves)),
+               "cf_set_launch_config")
 
     def launch_times(self, slot: int = 0):
         """Durations (ms) of the kernel launches of the latest step_k call on stream

@@ -231,11 +231,12 @@ struct cf_handle {
     int n_counters = 0;
     // launch choice
     int lane_ok = 0;     // all worlds one model: per-lane mapping possible
-    int aero = 0;        // some world has propeller inertia or drag
+    int aero = 0;        // some world has propeller inertia, drag or a general rotor law
     int use_wq = 0;
     int tile = 64;
     int chunk = 0;       // 0 = all k steps in one launch
     int split = 1;       // mixed handles: one launch per model on two streams
+    int wq_waves = 0;    // work queue: resident waves per SIMD of each launch (0 = all that fit)
     int mode = LM_TILE;
     // scratch
     DevBuf ref_tab, seg, ggc, gpart, loss_tmp;
@@ -474,8 +475,12 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
     h->lane_ok = (h->models != MS_BOTH);
     for (int w = 0; w < h->M; ++w) {
         const float* r = d->params + (size_t)w * CF_NPARAM;
+        // the kernel variants with the full first-principles terms: rotor inertia,
+        // drag, or a rotor law beyond W' = c_v (W_cmd - W)
         if (r[CF_P_DRAG] != 0.f || r[CF_P_DRAG + 1] != 0.f || r[CF_P_DRAG + 2] != 0.f ||
-            (models[w] == CF_MODEL_FP && r[CF_P_JP] != 0.f))
+            (models[w] == CF_MODEL_FP &&
+             (r[CF_P_JP] != 0.f || r[CF_P_MOTOR_UP + 1] != 0.f || r[CF_P_MOTOR_DOWN + 1] != 0.f ||
+              r[CF_P_MOTOR_DOWN] != r[CF_P_MOTOR_UP])))
             h->aero = 1;
     }
     hipDeviceProp_t prop;
@@ -609,11 +614,13 @@ cf_status cf_launch_config(const cf_handle* h, int32_t* use_wq, int32_t* tile, i
     return CF_OK;
 }
 
-cf_status cf_set_launch_config(cf_handle* h, int32_t use_wq, int32_t tile, int32_t chunk) {
+cf_status cf_set_launch_config(cf_handle* h, int32_t use_wq, int32_t tile, int32_t chunk, int32_t wq_waves) {
     if (!h || use_wq < 0 || use_wq > 3 || (tile != 64 && tile != 128 && tile != 256) || chunk < 0) return CF_EINVAL;
     if (chunk > 0 && chunk % h->ctrl_every != 0) return CF_EINVAL;
+    if (wq_waves < 0 || wq_waves > 32) return CF_EINVAL;
     hipSetDevice(h->device);
     apply_choice(h, use_wq & 1, tile, chunk, (use_wq >> 1) & 1);
+    h->wq_waves = wq_waves;
     return note(h, build_tiles(h, h->tile));
 }
 
@@ -731,7 +738,12 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
         KernelSel ks = selection(h, h->use_wq ? LM_WQ : h->mode, h->tile);
         ks.models = models;
         int blocks = 0;
-        if (h->use_wq) blocks = std::max(1, std::min(nt, step_wq_blocks_per_cu(ks) * h->cus));
+        if (h->use_wq) {
+            int per_cu = step_wq_blocks_per_cu(ks);
+            // a cap leaves SIMD registers to work on other streams (the overlapped adjoint)
+            if (h->wq_waves > 0) per_cu = std::min(per_cu, std::max(1, h->wq_waves * 4 * 64 / ks.tile));
+            blocks = std::max(1, std::min(nt, per_cu * h->cus));
+        }
         hipError_t r = hipSuccess;
         for (int c = 0; c < n_launch && r == hipSuccess; ++c) {
             const int kk = std::min(chunk, k - c * chunk);
@@ -1103,6 +1115,7 @@ cf_status cf_autotune(cf_handle* h, const float* state, const float* cmd, int32_
                     cands.push_back({wq, tile, chunk, split});
                 }
     const int save_wq = h->use_wq, save_tile = h->tile, save_chunk = h->chunk, save_split = h->split;
+    h->wq_waves = 0;   // candidates run with every wave that fits
     const uint32_t save_flags = h->flags;
     h->flags &= ~(CF_F_PLAIN_KERNEL | CF_F_GRAPH);
     float best = 1e30f;

@@ -64,6 +64,9 @@ struct FpParams {
     float jp, sg[4];          // propeller inertia, rotor spin directions (-sign of the yaw mixing)
     float cd[3];              // linear drag C_a diagonal
     bool gyro, drag;          // J_p != 0, C_a != 0
+    // rotor law with distinct acceleration / deceleration coefficients or a
+    // quadratic term; otherwise W' = c_v (W_cmd - W) on both branches
+    bool rotor_general;
     // Inside the kernels the four rotor rows hold W - W_r, the deviation from a
     // reference speed W_r (the world's hover speed), and rotor commands are
     // deviations too: near 15 000 an FP32 speed resolves 1e-3, its deviation
@@ -93,8 +96,9 @@ struct IdParams {
     bool direct;  // c_tau = 0: no thrust dynamics, the commanded thrust acts directly
 };
 
-// AERO = false: the gyroscopic/reaction torques and drag are compiled out (the
-// flags below become constants and their branches fold away)
+// AERO = false: the gyroscopic/reaction torques, drag and the general rotor law
+// (distinct acceleration / deceleration coefficients, quadratic term) are
+// compiled out (the flags below become constants and their branches fold away)
 template <bool AERO, class R>
 __device__ __forceinline__ FpParams load_fp(const R& rec) {
     FpParams P;
@@ -109,9 +113,11 @@ __device__ __forceinline__ FpParams load_fp(const R& rec) {
     for (int i = 0; i < 4; ++i) {
         P.tx[i] = rec(P_MIX_TX + i); P.ty[i] = rec(P_MIX_TY + i); P.tz[i] = rec(P_MIX_YAW + i);
     }
-    P.cvu = rec(P_MOTOR_UP); P.cdu = rec(P_MOTOR_UP + 1);
-    P.cvd = rec(P_MOTOR_DOWN); P.cdd = rec(P_MOTOR_DOWN + 1);
+    P.cvu = rec(P_MOTOR_UP);
     if constexpr (AERO) {
+        P.cdu = rec(P_MOTOR_UP + 1);
+        P.cvd = rec(P_MOTOR_DOWN); P.cdd = rec(P_MOTOR_DOWN + 1);
+        P.rotor_general = (P.cdu != 0.f) || (P.cdd != 0.f) || (P.cvd != P.cvu);
         P.jp = rec(P_JP);
 #pragma unroll
         for (int i = 0; i < 4; ++i) P.sg[i] = rec(D_SG + i);
@@ -129,6 +135,8 @@ __device__ __forceinline__ FpParams load_fp(const R& rec) {
         P.gyro = false;
         P.drag = false;
         P.sgr = 0.f;
+        P.cdu = 0.f; P.cvd = P.cvu; P.cdd = 0.f;
+        P.rotor_general = false;
     }
     P.wr = rec(D_WR);
     P.w2 = rec(D_W2);
@@ -357,10 +365,14 @@ __device__ __forceinline__ void fp_rates(const float* x, const float* rc, const 
     for (int i = 0; i < 4; ++i) {
         const float r = x[13 + i];
         const float e = rc[i] - r;            // W_cmd - W
-        const bool up = e >= 0.f;             // accelerating branch (ties included)
-        const float cv = up ? P.cvu : P.cvd;
-        const float cd = up ? P.cdu : P.cdd;
-        xd[13 + i] = e * (cv + cd * (P.w2 + rc[i] + r));   // c_v e + c_d (W_cmd^2 - W^2)
+        if (P.rotor_general) {
+            const bool up = e >= 0.f;         // accelerating branch (ties included)
+            const float cv = up ? P.cvu : P.cvd;
+            const float cd = up ? P.cdu : P.cdd;
+            xd[13 + i] = e * (cv + cd * (P.w2 + rc[i] + r));   // c_v e + c_d (W_cmd^2 - W^2)
+        } else {
+            xd[13 + i] = P.cvu * e;
+        }
         const float df = r * (P.k1w + P.k2 * r);           // f(W) - f(W_r)
         const float dq = r * (P.t1w + P.t2 * r);
         F += df;
@@ -457,16 +469,21 @@ __device__ __forceinline__ void fp_rates_vjp(const float* x, const float* rc, co
         const float r = x[13 + i];
         const float fb = Fb + P.tx[i] * hx + P.ty[i] * hy;
         const float tqb = P.tz[i] * hz;
-        const bool up = rc[i] - r >= 0.f;
-        const float cv = up ? P.cvu : P.cvd;
-        const float cd = up ? P.cdu : P.cdd;
         // adjoint of the rotor acceleration: the state derivative, plus the reaction torque
         const float gr = gb[13 + i] - (P.gyro ? P.jp * P.sg[i] * hz : 0.f);
         if (P.gyro) xb[13 + i] += P.sg[i] * om_sb;
         // df/dW = k1 + 2 k2 W = k1w + 2 k2 r, d(W^2)/dW = 2 W = w2 + 2 r
-        xb[13 + i] += fb * (P.k1w + 2.f * P.k2 * r) + tqb * (P.t1w + 2.f * P.t2 * r)
-                      - gr * (cv + cd * (P.w2 + 2.f * r));
-        rcb[i] += gr * (cv + cd * (P.w2 + 2.f * rc[i]));
+        xb[13 + i] += fb * (P.k1w + 2.f * P.k2 * r) + tqb * (P.t1w + 2.f * P.t2 * r);
+        if (P.rotor_general) {
+            const bool up = rc[i] - r >= 0.f;
+            const float cv = up ? P.cvu : P.cvd;
+            const float cd = up ? P.cdu : P.cdd;
+            xb[13 + i] -= gr * (cv + cd * (P.w2 + 2.f * r));
+            rcb[i] += gr * (cv + cd * (P.w2 + 2.f * rc[i]));
+        } else {
+            xb[13 + i] -= gr * P.cvu;
+            rcb[i] += gr * P.cvu;
+        }
     }
 }
 
@@ -897,24 +914,26 @@ template <int CTRL, int INTEG>
 __device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, const FpParams& P,
                                         const PidParams& C, float dt, float dtc, float inv_dtc, int renorm,
                                         float* rc, bool ctrl_now) {
-    float cs[8];
     if constexpr (CTRL == CTRL_ROTOR) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) rc[i] = u[i] - P.wr;
     } else {
-        if (ctrl_now) fp_ctrl_forward<CTRL>(x, u, P, C, dtc, inv_dtc, rc, cs);
+        if (ctrl_now) {
+            float cs[8];
+            fp_ctrl_forward<CTRL>(x, u, P, C, dtc, inv_dtc, rc, cs);
+            // the PID's new state goes to its rows at once: the integration below
+            // reads and writes rows 0..16 only
+            if constexpr (CTRL == CTRL_PID) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) x[17 + i] = cs[i];
+            }
+        }
     }
     integrate<S_FP, INTEG, COMP_FP>(x, comp, dt, [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
     if (renorm) {
         const float n2 = x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6];
         const float inv = rsqrt_hw(n2);
         x[3] *= inv; x[4] *= inv; x[5] *= inv; x[6] *= inv;
-    }
-    if constexpr (CTRL == CTRL_PID) {
-        if (ctrl_now) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) x[17 + i] = cs[i];
-        }
     }
 }
 

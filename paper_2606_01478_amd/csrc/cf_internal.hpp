@@ -21,7 +21,7 @@ struct KernelSel {
     int integ;   // EULER / RK4
     int mode;    // LM_*
     int tile;    // lanes per workgroup (64, 128, 256)
-    int aero;    // kernels with gyroscopic/reaction torques and drag compiled in
+    int aero;    // kernels with gyroscopic/reaction torques, drag and the general rotor law compiled in
 };
 
 struct StepArgs {

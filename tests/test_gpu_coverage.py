@@ -336,3 +336,20 @@ def test_launch_times_of_a_mixed_handle(gpu_lib, graph):
     assert sum(t0) <= total * 1.05 + 0.05
     with pytest.raises(B.CfError):
         ref.launch_times(0)
+
+
+@pytest.mark.parametrize("cap", [1, 2])
+def test_work_queue_wave_cap_gives_identical_states(gpu_lib, cap):
+    """Capping the work queue's resident waves per SIMD changes only which
+    workgroup takes which tile: the states are bit-identical."""
+    w = W.small(5, seed=99)
+    a, b = _sim(w, flags=B.F_WORKQUEUE), _sim(w, flags=B.F_WORKQUEUE)
+    cfg = a.launch_config()
+    b.set_launch_config(1, cfg["tile"], cfg["chunk"], cfg["per_model_launches"], cap)
+    xa, xb, u = dev(w.x0), dev(w.x0), dev(w.cmds)
+    a.step_k(xa, u, 200)
+    b.step_k(xb, u, 200)
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xb)
+    with pytest.raises(B.CfError):
+        b.set_launch_config(1, 64, 0, 1, 33)
