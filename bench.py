@@ -72,6 +72,10 @@ def parse():
     p.add_argument("--ckpt", type=int, default=0,
                    help="checkpoint interval; 0 = tune among 1, 10, 50, 100 (alone, then in the job)")
     p.add_argument("--serial", action="store_true", help="run the subset adjoint after the forward")
+    p.add_argument("--wq-waves", type=int, default=-1,
+                   help="cap on the held step's resident work-queue waves per SIMD; -1 = tune in the job")
+    p.add_argument("--no-standalone", action="store_true",
+                   help="skip the standalone phase timings (profiler runs: every held-step dispatch is in the job)")
     p.add_argument("--graph", action="store_true",
                    help="time the job with the held steps replayed from a hipGraph (default: enqueued directly; "
                         "the other form is timed too and reported under graph_comparison)")
@@ -240,8 +244,8 @@ def main():
     # resident work-queue waves per SIMD of the held step inside the job: every
     # wave that fits, or fewer so that adjoint waves find registers on more SIMDs
     # (median of 4 job steps per candidate)
-    wq_best = (0, None)
-    if cfg["workqueue"] and not args.serial:
+    wq_best = (max(args.wq_waves, 0), None)
+    if cfg["workqueue"] and not args.serial and args.wq_waves < 0:
         for cap in (0, 2, 1):
             for h_ in (sim, simO, simT):
                 h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"], cap)
@@ -254,23 +258,26 @@ def main():
             med = float(np.median([r[0].elapsed_time(r[6]) for r in trial]))
             if wq_best[1] is None or med < wq_best[1]:
                 wq_best = (cap, med)
-        for h_ in (sim, simO, simT):
-            h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"], wq_best[0])
+    for h_ in (sim, simO, simT):
+        h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"], wq_best[0])
     # standalone phases (nothing else on the GPU), HIP events on the same streams
-    adjoint(K, ckpt)
-    a, b = ev(), ev()
-    a.record()
-    adjoint(K, ckpt)
-    b.record()
-    sim.step_k(state, cmd, T)
-    c = ev()
-    c.record()
-    torch.cuda.synchronize()
-    standalone = {"adjoint_fwd_bwd": a.elapsed_time(b), "forward": b.elapsed_time(c)}
-    simT.step_k(state, cmd, T)
-    torch.cuda.synchronize()
-    standalone_launch_ms = {"first_principles": simT.launch_times(0),
-                            "identified": simT.launch_times(1) if cfg["per_model_launches"] else []}
+    standalone = {"adjoint_fwd_bwd": float("nan"), "forward": float("nan")}
+    standalone_launch_ms = {"first_principles": [float("nan")], "identified": []}
+    if not args.no_standalone:
+        adjoint(K, ckpt)
+        a, b = ev(), ev()
+        a.record()
+        adjoint(K, ckpt)
+        b.record()
+        sim.step_k(state, cmd, T)
+        c = ev()
+        c.record()
+        torch.cuda.synchronize()
+        standalone = {"adjoint_fwd_bwd": a.elapsed_time(b), "forward": b.elapsed_time(c)}
+        simT.step_k(state, cmd, T)
+        torch.cuda.synchronize()
+        standalone_launch_ms = {"first_principles": simT.launch_times(0),
+                                "identified": simT.launch_times(1) if cfg["per_model_launches"] else []}
 
     for _ in range(args.warmup):
         one_step()

@@ -10,5 +10,5 @@ from .dynamics import (  # noqa: F401
     id_rates, rotation_matrix,
     integrate, per_drone_params, quat_mul, roll_pitch_from_quat, rollout, rollout_grad,
     rollout_workload, rotor_rates, rotor_speed_for_thrust, rotor_wrench, simulate_held,
-    step_fp, step_fp_multirate, step_id, t64, tilt_angle, hover_action,
+    step_fp, step_fp_multirate, step_id, t64, tilt_angle, hover_action, mlp_param_count, mlp_policy,
 )

@@ -511,11 +511,39 @@ def hover_action(batch: "Batch") -> torch.Tensor:
     return a
 
 
+def mlp_param_count(hidden: int) -> int:
+    """Parameters of the small MLP policy with `hidden` units per hidden layer."""
+    H = int(hidden)
+    return 13 * H + H + H * H + H + 4 * H + 4
+
+
+def mlp_policy(theta: torch.Tensor, hidden: int, e: torch.Tensor) -> torch.Tensor:
+    """Small MLP actor of the BPTT setup (Methods, "Backpropagation Through Time":
+    an actor network trained on analytical gradients; its architecture is not
+    printed). Reading: o = W3 tanh(W2 tanh(W1 e + b1) + b2) + b3 on the tracking
+    error e [13, D], tanh hidden layers of `hidden` units, linear output [4, D].
+    theta [D, P] holds each drone's parameters, packed
+    [W1 (H x 13, row-major) | b1 (H) | W2 (H x H) | b2 (H) | W3 (4 x H) | b3 (4)]."""
+    H = int(hidden)
+    D = theta.shape[0]
+    o = 0
+    W1 = theta[:, o:o + 13 * H].reshape(D, H, 13); o += 13 * H
+    b1 = theta[:, o:o + H]; o += H
+    W2 = theta[:, o:o + H * H].reshape(D, H, H); o += H * H
+    b2 = theta[:, o:o + H]; o += H
+    W3 = theta[:, o:o + 4 * H].reshape(D, 4, H); o += 4 * H
+    b3 = theta[:, o:o + 4]
+    h1 = torch.tanh(torch.einsum("dji,di->dj", W1, e.T) + b1)
+    h2 = torch.tanh(torch.einsum("djk,dk->dj", W2, h1) + b2)
+    return (torch.einsum("dok,dk->do", W3, h2) + b3).T
+
+
 def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
             gain: Optional[torch.Tensor] = None, gain_index=None,
             ref_amp: float = 1.0, ref_period: float = 4.0, ref_offset=None,
             ref_table: Optional[torch.Tensor] = None, w_u: float = 1e-3,
-            with_loss: bool = True, keep_traj: bool = False, reward: Optional[Dict] = None):
+            with_loss: bool = True, keep_traj: bool = False, reward: Optional[Dict] = None,
+            policy_hidden: int = 0):
     """Roll out ``steps`` steps with per-step commands ``cmds`` [T, 4, D] (or held
     [4, D]). With ``gain`` [G, 4, 13] the applied command is
     u_t = ubar_t + G_w (x_t[0:13] - x_ref(t)). Loss per drone:
@@ -529,13 +557,16 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
             - sum_i w_act_i (a_t,i - a_hover,i)^2 - sum_i w_dact_i (a_t,i - a_{t-1},i)^2
     (reading: the previous action before the first step is the hover action;
     the goal is the reference point; norms have gradient 0 at their kink).
+
+    With ``policy_hidden`` = H > 0, ``gain`` [G, P] holds MLP policies instead of
+    linear gains and u_t = ubar_t + mlp_policy(theta_w, H, x_t[0:13] - x_ref(t)).
     Returns dict(x=x_T, loss=[D] or None, traj=[T+1, S, D] or None)."""
     x = x0
     D = batch.D
     G = None
     if gain is not None:
         gi = np.zeros(len(batch.counts), np.int64) if gain_index is None else np.asarray(gain_index, np.int64)
-        G = gain[torch.as_tensor(gi[batch.world])]            # [D, 4, 13]
+        G = gain[torch.as_tensor(gi[batch.world])]            # [D, 4, 13], or [D, P] for an MLP policy
     loss = torch.zeros(D, dtype=F64)
     traj = [x] if keep_traj else None
 
@@ -560,7 +591,10 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
         if G is not None:
             _, xr = ref(n)
             e = x[0:13] - xr
-            u = ubar + (G * e.T[:, None, :]).sum(2).T
+            if policy_hidden:
+                u = ubar + mlp_policy(G, policy_hidden, e)
+            else:
+                u = ubar + (G * e.T[:, None, :]).sum(2).T
         else:
             u = ubar
         if with_loss and reward is None:
@@ -628,7 +662,7 @@ def rollout_workload(w, with_grad: bool = False, keep_traj: bool = False):
     b = Batch.from_workload(w)
     kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period,
               ref_offset=None if w.ref_offset is None else t64(w.ref_offset), w_u=w.w_u,
-              reward=getattr(w, "reward", None))
+              reward=getattr(w, "reward", None), policy_hidden=getattr(w, "policy_hidden", 0))
     gain = None if w.gain is None else t64(w.gain)
     if with_grad:
         return rollout_grad(b, w.x0, w.cmds, w.steps, gain=gain, gain_index=w.gain_index,

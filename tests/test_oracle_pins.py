@@ -506,7 +506,8 @@ def _fd_check(w, n_dirs=4, h=1e-4, seed=0):
     per-step commands, the initial state and the gain vs the autograd gradient."""
     b = O.Batch.from_workload(w)
     kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u,
-              ref_offset=None if w.ref_offset is None else O.t64(w.ref_offset), reward=w.reward)
+              ref_offset=None if w.ref_offset is None else O.t64(w.ref_offset), reward=w.reward,
+              policy_hidden=w.policy_hidden)
     x0, cmds = O.t64(w.x0), O.t64(w.cmds)
     gain = None if w.gain is None else O.t64(w.gain)
     g = O.rollout_grad(b, x0, cmds, w.steps, gain=gain, gain_index=w.gain_index, dloss=w.dloss, **kw)
@@ -1211,3 +1212,62 @@ def test_reference_state_rows_per_model():
     u[3] = x[12]
     y = run(bi, x.clone(), u, 50)
     assert torch.allclose(y, x, atol=1e-12)
+
+
+# ---- the small-MLP policy of the BPTT setup (reading r30) -------------------------------
+
+def test_mlp_policy_with_small_weights_is_the_linear_feedback():
+    """With W1 = eps A, W2 = B, W3 = C and zero biases the MLP output is
+    eps C B A e + O(eps^3): the rollout converges to the one with the linear
+    gain eps C B A at second order in eps (relative)."""
+    w = W.config4_mlp(seed=40, n_worlds=6, steps=60, hidden=8)
+    H = 8
+    rng = np.random.default_rng(40)
+    A = rng.normal(size=(H, 13))
+    Bm = rng.normal(size=(H, H)) / math.sqrt(H)
+    C = rng.normal(size=(4, H)) * 0.3
+    b = O.Batch.from_workload(w)
+    kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u)
+    errs = []
+    for eps in (0.02, 0.01, 0.005):
+        theta = np.concatenate([(eps * A).ravel(), np.zeros(H), Bm.ravel(), np.zeros(H), C.ravel(), np.zeros(4)])
+        G = (eps * C @ Bm @ A)[None]
+        with torch.no_grad():
+            m = O.rollout(b, O.t64(w.x0), O.t64(w.cmds), w.steps, gain=torch.as_tensor(theta)[None],
+                          policy_hidden=H, **kw)
+            l = O.rollout(b, O.t64(w.x0), O.t64(w.cmds), w.steps, gain=torch.as_tensor(G), **kw)
+        # compare the feedback's effect: trajectories differ from the open loop by O(eps)
+        errs.append(float((m["x"] - l["x"]).abs().max()))
+    assert errs[0] / errs[1] > 6.0 and errs[1] / errs[2] > 6.0, errs   # third order in eps
+
+
+def test_mlp_policy_output_layer_gradient_identity():
+    """u_t = ubar_t + W3 h2_t + b3 gives dL/dW3 = sum_t (dL/du_t) h2_t^T and
+    dL/db3 = sum_t dL/du_t exactly."""
+    w = W.config4_mlp(seed=41, n_worlds=3, steps=25, hidden=6, out_scale=0.05)
+    H = 6
+    b = O.Batch.from_workload(w)
+    kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u, policy_hidden=H)
+    theta = O.t64(w.gain)
+    g = O.rollout_grad(b, w.x0, w.cmds, w.steps, gain=theta, dloss=w.dloss, **kw)
+    out = O.rollout(b, O.t64(w.x0), O.t64(w.cmds), w.steps, gain=theta, keep_traj=True, **kw)
+    traj = out["traj"].detach()
+    P = O.mlp_param_count(H)
+    th = theta[0]
+    W1 = th[:13 * H].reshape(H, 13); b1 = th[13 * H:14 * H]
+    W2 = th[14 * H:14 * H + H * H].reshape(H, H); b2 = th[14 * H + H * H:15 * H + H * H]
+    accW, accb = torch.zeros(4, H, dtype=F64), torch.zeros(4, dtype=F64)
+    for n in range(w.steps):
+        p, v = b.figure_eight(n * b.dt, w.ref_amp, w.ref_period, None)
+        e = traj[n, 0:13] - b.reference_state(p, v)
+        h2 = torch.tanh(W2 @ torch.tanh(W1 @ e + b1[:, None]) + b2[:, None])
+        accW += g["g_cmds"][n] @ h2.T
+        accb += g["g_cmds"][n].sum(1)
+    gth = g["g_gain"][0]
+    assert torch.allclose(accW, gth[P - 4 - 4 * H:P - 4].reshape(4, H), rtol=1e-10, atol=1e-14)
+    assert torch.allclose(accb, gth[P - 4:], rtol=1e-10, atol=1e-14)
+
+
+def test_gradient_fd_mlp_policy():
+    w = W.config4_mlp(seed=42, n_worlds=3, steps=20, hidden=5, out_scale=0.05)
+    _fd_check(w)

@@ -96,6 +96,7 @@ class Workload:
     dloss: Optional[np.ndarray] = None    # float32 [D]
     ctrl_every: int = 1                   # onboard controller every n physics steps
     reward: Optional[dict] = None         # BPTT reward weights (w_tilt, w_act[4], w_dact[4]) or None
+    policy_hidden: int = 0                # > 0: `gain` holds [G, P] small-MLP policies of this width
 
     @property
     def n_drones_total(self) -> int:
@@ -559,6 +560,29 @@ def config5_adjoint(seed: int = 1005, n_worlds: int = 2048, n_subset: int = 256,
         w, name="uneven_mixed_adjoint", steps=steps, cmds=_f32(ubar), gain=_f32(gain),
         gain_index=gidx, ref_amp=1.0, ref_period=4.0, ref_offset=_f32(w.x0[0:3]),
         w_u=1e-3, dloss=np.ones(D, np.float32))
+
+
+def mlp_policy_params(rng, n_policies: int, hidden: int, out_scale: float = 0.01) -> np.ndarray:
+    """Random small-MLP policies [G, P], packed [W1 (H x 13) | b1 | W2 (H x H) | b2 |
+    W3 (4 x H) | b3]: hidden weights N(0, 1/fan_in), output weights N(0, out_scale^2),
+    biases 0 (a random draw and its layout only)."""
+    H = int(hidden)
+    out = []
+    for _ in range(n_policies):
+        out += [rng.normal(0.0, 1.0 / math.sqrt(13.0), size=13 * H), np.zeros(H),
+                rng.normal(0.0, 1.0 / math.sqrt(H), size=H * H), np.zeros(H),
+                rng.normal(0.0, out_scale, size=4 * H), np.zeros(4)]
+    return _f32(np.concatenate(out).reshape(n_policies, -1))
+
+
+def config4_mlp(seed: int = 1012, n_worlds: int = 1024, steps: int = 500, hidden: int = 32,
+                dt: float = 0.002, out_scale: float = 0.01) -> Workload:
+    """The differentiable workload with a small-MLP policy (width `hidden`) in place
+    of the linear feedback gain."""
+    w = config4(seed, n_worlds, steps, dt)
+    rng = _rng(seed + 104729)
+    return dataclasses.replace(w, name="id_rollout_grad_mlp", gain=mlp_policy_params(rng, 1, hidden, out_scale),
+                               policy_hidden=int(hidden))
 
 
 def small(cfg: int, seed: int) -> Workload:
