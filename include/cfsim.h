@@ -182,9 +182,10 @@ typedef struct cf_handle cf_handle;
 
 /*
  * Tracking objective and linear feedback of cf_rollout / cf_rollout_backward.
- * Applied command u_t = ubar_t + G_w (x_t[0:13] - x_ref(t)) when gain != NULL.
+ * Applied command u_t = ubar_t + G_w (x_t[0:13] - x_ref(t)) when gain != NULL
+ * (with policy_hidden > 0 the small-MLP policy's output replaces G_w (...)).
  * Loss per drone: sum_{t=1..T} |p_t - p_ref(t)|^2 + w_u sum_{t=0..T-1} |u_t|^2,
- * t_n = n dt. Reference (ref_table == NULL): figure-eight
+ * t_n = (ref_step0 + n) dt. Reference (ref_table == NULL): figure-eight
  * p_ref = [A sin(2 pi t/P), (A/2) sin(4 pi t/P), 0] + offset_d and its
  * derivative; x_ref = [p_ref, (0,0,0,1), v_ref, 0] (FP) or
  * [p_ref, 0, v_ref, 0, m g / c_f] (ID). With ref_table, x_ref(t) is row t
@@ -201,7 +202,30 @@ typedef struct cf_objective {
     float w_tilt;             /* reward: tilt weight, >= 0                       */
     float w_act[4];           /* reward: weights of (u - u_hover)^2, >= 0        */
     float w_dact[4];          /* reward: weights of (u_t - u_{t-1})^2, >= 0      */
+    int32_t policy_hidden;    /* 0: linear feedback, gain [n_gains][4][13]; H in
+                                 1..CF_MLP_MAX_HIDDEN: small-MLP policies in gain,
+                                 [n_gains][CF_MLP_PARAMS(H)] (see below)          */
+    int32_t ref_step0;        /* figure-eight: step n of the rollout tracks the
+                                 reference at t = (ref_step0 + n) dt, >= 0, so that
+                                 consecutive rollouts continue along it          */
 } cf_objective;
+
+/*
+ * Small-MLP policy (the actor network of the paper's BPTT setup, Methods,
+ * "Backpropagation Through Time"; its architecture is not printed, this is
+ * the library's): u_t = ubar_t + W3 tanh(W2 tanh(W1 e_t + b1) + b2) + b3 with
+ * e_t = x_t[0:13] - x_ref(t), H units per hidden layer. Each policy is packed
+ * [W1 (H x 13, row-major) | b1 (H) | W2 (H x H) | b2 (H) | W3 (4 x H) | b3 (4)],
+ * CF_MLP_PARAMS(H) = 13 H + H + H H + H + 4 H + 4 floats; world w uses policy
+ * gain_index[w]. The backward's g_gain receives the gradient in the same packing.
+ * Limits: (n_gains * CF_MLP_PARAMS(H) + 4 * 64 * H) * 4 bytes <= 64 KiB (the
+ * policies and each lane's activations live in LDS), and the handle's tile
+ * size must be 64 lanes when its worlds are tiled (CF_EUNSUPPORTED otherwise).
+ * The backward keeps (17 + 4 H) floats per drone-step of scratch for the
+ * weight-gradient reduction.
+ */
+#define CF_MLP_MAX_HIDDEN 32
+#define CF_MLP_PARAMS(H) (13 * (H) + (H) + (H) * (H) + (H) + 4 * (H) + 4)
 
 /*
  * Objective kinds. CF_OBJ_TRACKING: the loss above. CF_OBJ_BPTT_REWARD: minus

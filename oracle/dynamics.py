@@ -543,7 +543,7 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
             ref_amp: float = 1.0, ref_period: float = 4.0, ref_offset=None,
             ref_table: Optional[torch.Tensor] = None, w_u: float = 1e-3,
             with_loss: bool = True, keep_traj: bool = False, reward: Optional[Dict] = None,
-            policy_hidden: int = 0):
+            policy_hidden: int = 0, ref_step0: int = 0):
     """Roll out ``steps`` steps with per-step commands ``cmds`` [T, 4, D] (or held
     [4, D]). With ``gain`` [G, 4, 13] the applied command is
     u_t = ubar_t + G_w (x_t[0:13] - x_ref(t)). Loss per drone:
@@ -559,7 +559,9 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
     the goal is the reference point; norms have gradient 0 at their kink).
 
     With ``policy_hidden`` = H > 0, ``gain`` [G, P] holds MLP policies instead of
-    linear gains and u_t = ubar_t + mlp_policy(theta_w, H, x_t[0:13] - x_ref(t)).
+    linear gains and u_t = ubar_t + mlp_policy(theta_w, H, x_t[0:13] - x_ref(t)). With
+    ``ref_step0`` = k the figure-eight is followed from t = k dt: step n tracks
+    p_ref((k + n) dt), so that consecutive rollouts continue along it.
     Returns dict(x=x_T, loss=[D] or None, traj=[T+1, S, D] or None)."""
     x = x0
     D = batch.D
@@ -571,7 +573,7 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
     traj = [x] if keep_traj else None
 
     def ref(n):
-        t = n * batch.dt
+        t = (ref_step0 + n) * batch.dt
         if ref_table is not None:
             xr = ref_table[n][:, None].expand(13, D)
             if ref_offset is not None:
@@ -662,7 +664,8 @@ def rollout_workload(w, with_grad: bool = False, keep_traj: bool = False):
     b = Batch.from_workload(w)
     kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period,
               ref_offset=None if w.ref_offset is None else t64(w.ref_offset), w_u=w.w_u,
-              reward=getattr(w, "reward", None), policy_hidden=getattr(w, "policy_hidden", 0))
+              reward=getattr(w, "reward", None), policy_hidden=getattr(w, "policy_hidden", 0),
+              ref_step0=getattr(w, "ref_step0", 0))
     gain = None if w.gain is None else t64(w.gain)
     if with_grad:
         return rollout_grad(b, w.x0, w.cmds, w.steps, gain=gain, gain_index=w.gain_index,

@@ -64,7 +64,8 @@ class _Desc(ctypes.Structure):
 class _Objective(ctypes.Structure):
     _fields_ = [("gain", c_void_p), ("ref_table", c_void_p), ("ref_amp", c_float), ("ref_period", c_float),
                 ("ref_offset", c_void_p), ("w_u", c_float), ("kind", c_int32), ("w_tilt", c_float),
-                ("w_act", c_float * 4), ("w_dact", c_float * 4)]
+                ("w_act", c_float * 4), ("w_dact", c_float * 4), ("policy_hidden", c_int32),
+                ("ref_step0", c_int32)]
 
 
 class _MppiDesc(ctypes.Structure):
@@ -125,6 +126,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
 def _check(status: int, what: str) -> None:
     if status != CF_OK:
         raise CfError(status, what)
+
+
+def mlp_params(hidden: int) -> int:
+    """Floats of one small-MLP policy of width ``hidden`` (CF_MLP_PARAMS in the C header)."""
+    H = int(hidden)
+    return 13 * H + H + H * H + H + 4 * H + 4
 
 
 def pack_params(params: Dict[str, np.ndarray], n_worlds: int) -> np.ndarray:
@@ -230,11 +237,17 @@ class Sim:
         if str(t.dtype).replace("torch.", "") not in dtypes:
             raise ValueError(f"{name}: expected dtype {dtypes}, got {t.dtype}")
 
+    def _gain_shape(self, obj):
+        """Shape of the feedback parameters: linear gains or small-MLP policies."""
+        if obj is not None and obj.policy_hidden > 0:
+            return (self.n_gains, mlp_params(obj.policy_hidden))
+        return (self.n_gains, 4, 13)
+
     def _need_obj(self, obj, T) -> None:
         if obj is None:
             return
         g, rt, ro = getattr(obj, "_tensors", (None, None, None))
-        self._need(g, (self.n_gains, 4, 13), "gain")
+        self._need(g, self._gain_shape(obj), "gain")
         self._need(rt, (T + 1, 13), "ref_table")
         self._need(ro, (3, self.D), "ref_offset")
 
@@ -258,10 +271,14 @@ class Sim:
 
     @staticmethod
     def objective(gain=None, ref_table=None, ref_amp=1.0, ref_period=4.0, ref_offset=None, w_u=1e-3,
-                  reward=None):
+                  reward=None, policy_hidden=0, ref_step0=0):
         """Tracking objective; with ``reward`` = dict(w_tilt, w_act[4], w_dact[4]) the
-        BPTT reward objective (CF_OBJ_BPTT_REWARD) instead."""
+        BPTT reward objective (CF_OBJ_BPTT_REWARD) instead. With ``policy_hidden`` = H
+        > 0, ``gain`` holds small-MLP policies [n_gains, mlp_params(H)] instead of
+        linear gains [n_gains, 4, 13]."""
         o = _Objective()
+        o.policy_hidden = int(policy_hidden)
+        o.ref_step0 = int(ref_step0)
         o.gain = _ptr(gain)
         o.ref_table = _ptr(ref_table)
         o.ref_amp = float(ref_amp)
@@ -328,7 +345,7 @@ class Sim:
         self._need(dloss, (self.D,), "dloss")
         self._need(g_cmds, (T, 4, self.D), "g_cmds")
         self._need(g_x0, (self.S, self.D), "g_x0")
-        self._need(g_gain, (self.n_gains, 4, 13), "g_gain")
+        self._need(g_gain, self._gain_shape(obj), "g_gain")
         self._need_obj(obj, T)
         self._sync_stream()
         o = ctypes.byref(obj) if obj is not None else None
@@ -346,7 +363,7 @@ class Sim:
         self._need(dloss, (self.D,), "dloss")
         self._need(g_cmds, (T, 4, self.D), "g_cmds")
         self._need(g_x0, (self.S, self.D), "g_x0")
-        self._need(g_gain, (self.n_gains, 4, 13), "g_gain")
+        self._need(g_gain, self._gain_shape(obj), "g_gain")
         self._need_obj(obj, T)
         self._sync_stream()
         o = ctypes.byref(obj) if obj is not None else None
@@ -392,8 +409,9 @@ def _rollout_loss_apply(sim: Sim, x0, cmds, gain, T, ckpt_every, obj_kw):
     obj = Sim.objective(gain=gain, **obj_kw)
     ckpt = sim.ckpt_buffer(T, ckpt_every, int(obj.kind), device=dev)
     loss = torch.empty(sim.D, device=dev, dtype=torch.float32)
-    sim.rollout(x0, cmds, T, obj, ckpt_every, ckpt=ckpt, loss=loss)
-    return loss, ckpt, obj
+    x_T = torch.empty_like(x0)
+    sim.rollout(x0, cmds, T, obj, ckpt_every, ckpt=ckpt, x_T=x_T, loss=loss)
+    return loss, ckpt, obj, x_T
 
 
 class RolloutLoss:
@@ -401,7 +419,9 @@ class RolloutLoss:
     tracking loss ``[D]`` of a rollout; backward runs the library's discrete adjoint and
     returns gradients for ``x0`` ``[S][D]``, ``cmds`` ``[T][4][D]`` and ``gain``. Each
     application owns its checkpoint buffer (saved for its backward), so several
-    applications on one handle may precede their backwards."""
+    applications on one handle may precede their backwards. With
+    ``return_state=True`` it also returns the final state ``[S][D]`` (not
+    differentiable), e.g. to start the next rollout from it."""
 
     @staticmethod
     def _fn():
@@ -412,14 +432,15 @@ class RolloutLoss:
             def forward(ctx, x0, cmds, gain, sim, T, ckpt_every, obj_kw):
                 x0c, cmdsc = x0.detach().contiguous(), cmds.detach().contiguous()
                 gc = None if gain is None else gain.detach().contiguous()
-                loss, ckpt, _ = _rollout_loss_apply(sim, x0c, cmdsc, gc, T, ckpt_every, obj_kw)
+                loss, ckpt, _, x_T = _rollout_loss_apply(sim, x0c, cmdsc, gc, T, ckpt_every, obj_kw)
                 ctx.sim, ctx.T, ctx.K, ctx.obj_kw = sim, T, ckpt_every, obj_kw
                 ctx.save_for_backward(x0c, cmdsc, ckpt, *( [gc] if gc is not None else []))
                 ctx.has_gain = gc is not None
-                return loss
+                ctx.mark_non_differentiable(x_T)
+                return loss, x_T
 
             @staticmethod
-            def backward(ctx, dloss):
+            def backward(ctx, dloss, dx_T=None):
                 saved = ctx.saved_tensors
                 x0, cmds, ckpt = saved[0], saved[1], saved[2]
                 gain = saved[3] if ctx.has_gain else None
@@ -437,10 +458,11 @@ class RolloutLoss:
     _cached = None
 
     @classmethod
-    def apply(cls, x0, cmds, gain, sim, T, ckpt_every=50, obj_kw=None):
+    def apply(cls, x0, cmds, gain, sim, T, ckpt_every=50, obj_kw=None, return_state=False):
         if cls._cached is None:
             cls._cached = cls._fn()
-        return cls._cached.apply(x0, cmds, gain, sim, T, ckpt_every, obj_kw or {})
+        loss, x_T = cls._cached.apply(x0, cmds, gain, sim, T, ckpt_every, obj_kw or {})
+        return (loss, x_T) if return_state else loss
 
 
 def probe_fma(out, n_blocks: int, iters: int, form: int = 0) -> None:

@@ -51,12 +51,13 @@ __global__ void k_reset(float* __restrict__ st, const float* __restrict__ init, 
     for (int i = 0; i < S; ++i) st[(size_t)i * D + d] = init[(size_t)i * D + d];
 }
 
-// figure-eight (lemniscate of Gerono) rows [p(3), v(3)] for t = 0..T
-__global__ void k_eight_table(float* tab, int T, float dt, float amp, float period) {
+// figure-eight (lemniscate of Gerono) rows [p(3), v(3)] for steps t = 0..T of a
+// rollout that starts at reference step step0
+__global__ void k_eight_table(float* tab, int T, float dt, float amp, float period, int step0) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t > T) return;
     const double w0 = 2.0 * 3.14159265358979323846 / (double)period;
-    const double tt = (double)t * (double)dt;
+    const double tt = ((double)step0 + (double)t) * (double)dt;
     const double A = amp;
     float* r = tab + (size_t)t * 6;
     r[0] = (float)(A * sin(w0 * tt));
@@ -131,9 +132,95 @@ __global__ void k_gain_final(const float* __restrict__ part, int nb, float* __re
     g[(size_t)k * GAIN_COMP + c] = s;
 }
 
+// Weight gradient of the small-MLP policies from the reverse sweep's records
+// rec[r][n] (n = t D + d; rows: e 13, h1 H, h2 H, dz1 H, dz2 H, d3 4):
+//   dW1 = sum_n dz1 e^T, db1 = sum_n dz1, dW2 = sum_n dz2 h1^T, db2 = sum_n dz2,
+//   dW3 = sum_n d3 h2^T, db3 = sum_n d3,
+// over the drones whose world uses policy k, in the packing of the policy. Stage 1:
+// workgroup b of policy k stages tiles of 64 records into LDS (zero for other
+// policies' drones) and each thread accumulates its parameters over the tiles of
+// chunk b; stage 2 sums the chunks in order.
+constexpr int MLP_MAX_P = 2048;   // CF_MLP_PARAMS(CF_MLP_MAX_HIDDEN) = 1636
+constexpr int MLP_PER_THREAD = MLP_MAX_P / 256;
+
+__device__ __forceinline__ void mlp_param_rows(int p, int H, int* ra, int* rb) {
+    const int E = 0, H1 = 13, H2 = 13 + H, DZ1 = 13 + 2 * H, DZ2 = 13 + 3 * H, D3 = 13 + 4 * H;
+    if (p < 13 * H) { *ra = DZ1 + p / 13; *rb = E + p % 13; return; }
+    p -= 13 * H;
+    if (p < H) { *ra = DZ1 + p; *rb = -1; return; }
+    p -= H;
+    if (p < H * H) { *ra = DZ2 + p / H; *rb = H1 + p % H; return; }
+    p -= H * H;
+    if (p < H) { *ra = DZ2 + p; *rb = -1; return; }
+    p -= H;
+    if (p < 4 * H) { *ra = D3 + p / H; *rb = H2 + p % H; return; }
+    p -= 4 * H;
+    *ra = D3 + p;
+    *rb = -1;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_partial(const float* __restrict__ rec, int64_t N, int64_t D, int H,
+                                                     int P, const int32_t* __restrict__ drone_world,
+                                                     const int32_t* __restrict__ gidx, int64_t chunk,
+                                                     float* __restrict__ part) {
+    extern __shared__ float tile[];   // [R][64]
+    const int R = 17 + 4 * H;
+    const int b = blockIdx.x, k = blockIdx.y, nb = gridDim.x;
+    const int64_t lo = (int64_t)b * chunk, hi = min(N, lo + chunk);
+    int ra[MLP_PER_THREAD], rb[MLP_PER_THREAD];
+    float acc[MLP_PER_THREAD];
+#pragma unroll
+    for (int q = 0; q < MLP_PER_THREAD; ++q) {
+        const int p = threadIdx.x + q * 256;
+        ra[q] = 0;
+        rb[q] = -1;
+        if (p < P) mlp_param_rows(p, H, &ra[q], &rb[q]);
+        acc[q] = 0.f;
+    }
+    for (int64_t n0 = lo; n0 < hi; n0 += 64) {
+        for (int i = threadIdx.x; i < R * 64; i += 256) {
+            const int r = i / 64, c = i % 64;
+            const int64_t n = n0 + c;
+            float v = 0.f;
+            if (n < hi && gidx[drone_world[n % D]] == k) v = rec[(size_t)r * N + n];
+            tile[r * 64 + c] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MLP_PER_THREAD; ++q) {
+            if (threadIdx.x + q * 256 >= P) continue;
+            const float* A = tile + ra[q] * 64;
+            float s = 0.f;
+            if (rb[q] < 0) {
+                for (int c = 0; c < 64; ++c) s += A[c];
+            } else {
+                const float* Bv = tile + rb[q] * 64;
+                for (int c = 0; c < 64; ++c) s = fmaf(A[c], Bv[c], s);
+            }
+            acc[q] += s;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < MLP_PER_THREAD; ++q) {
+        const int p = threadIdx.x + q * 256;
+        if (p < P) part[((size_t)k * nb + b) * P + p] = acc[q];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_final(const float* __restrict__ part, int nb, int P,
+                                                   float* __restrict__ g) {
+    const int k = blockIdx.x;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        float s = 0.f;
+        for (int b = 0; b < nb; ++b) s += part[((size_t)k * nb + b) * P + p];
+        g[(size_t)k * P + p] = s;
+    }
+}
+
 // workgroups per gain of the stage-1 reduction for D drones
 static int gain_blocks(int64_t D) {
-    const int64_t nb = (D + 2047) / 2048;
+    const int64_t nb = (D + 511) / 512;
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, GAIN_MAX_BLOCKS));
 }
 
@@ -239,7 +326,7 @@ struct cf_handle {
     int wq_waves = 0;    // work queue: resident waves per SIMD of each launch (0 = all that fit)
     int mode = LM_TILE;
     // scratch
-    DevBuf ref_tab, seg, ggc, gpart, loss_tmp;
+    DevBuf ref_tab, seg, ggc, rec, gpart, loss_tmp;
     // checkpoint tags: this handle's id, its count of forwards with a checkpoint
     // buffer, their tags by buffer, and a device word the backward kernels set
     // when a buffer no longer holds the tag the host matched
@@ -563,7 +650,7 @@ cf_status cf_destroy(cf_handle* h) {
     hipFree(h->tiles);
     hipFree(h->counters);
     hipFree(h->dflag);
-    for (DevBuf* b : {&h->ref_tab, &h->seg, &h->ggc, &h->gpart, &h->loss_tmp})
+    for (DevBuf* b : {&h->ref_tab, &h->seg, &h->ggc, &h->rec, &h->gpart, &h->loss_tmp})
         if (b->p) hipFree(b->p);
     if (h->capture_stream) hipStreamDestroy(h->capture_stream);
     if (h->aux_stream) {
@@ -808,6 +895,10 @@ cf_status cf_step_k(cf_handle* h, float* state, const float* cmd, int32_t k, uin
 // ---------------------------------------------------------------------------
 // rollout
 
+static int roll_mode(const cf_handle* h) {
+    return (h->lane_ok && h->D > 0 && (double)h->D / h->M < 32.0) ? LM_LANE : LM_TILE;
+}
+
 // ref_tab_buf: device [(T + 1)][6] for the figure-eight table, or null to use the
 // handle's own (grown on demand)
 static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T, RollArgs& a,
@@ -839,7 +930,23 @@ static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T,
             a.w_dact[i] = obj->w_dact[i];
         }
     }
-    if (obj->gain) {
+    a.mlp_H = 0;
+    a.mlp_P = 0;
+    a.n_pol = 0;
+    a.mlp_rec = nullptr;
+    if (obj->policy_hidden < 0 || obj->policy_hidden > CF_MLP_MAX_HIDDEN) return CF_EINVAL;
+    if (obj->policy_hidden > 0) {
+        const int H = obj->policy_hidden, P = CF_MLP_PARAMS(H);
+        if (!obj->gain || h->n_gains < 1) return CF_EINVAL;
+        if (check_dev(obj->gain, (size_t)h->n_gains * P * sizeof(float))) return CF_EINVAL;
+        // policies and each lane's activations in LDS; tiles of 64 lanes
+        if (((size_t)h->n_gains * P + (size_t)4 * 64 * H) * sizeof(float) > 65536) return CF_EUNSUPPORTED;
+        if (roll_mode(h) == LM_TILE && h->tile != 64) return CF_EUNSUPPORTED;
+        a.mlp_H = H;
+        a.mlp_P = P;
+        a.n_pol = h->n_gains;
+        a.gain = obj->gain;
+    } else if (obj->gain) {
         if (h->n_gains < 1) return CF_EINVAL;
         if (check_dev(obj->gain, (size_t)h->n_gains * 52 * sizeof(float))) return CF_EINVAL;
         a.gain = obj->gain;
@@ -854,7 +961,8 @@ static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T,
         a.ref_tab = obj->ref_table;
         a.ref_user = 1;
     } else {
-        if (!(std::isfinite(obj->ref_period) && obj->ref_period > 0.f) || !std::isfinite(obj->ref_amp))
+        if (!(std::isfinite(obj->ref_period) && obj->ref_period > 0.f) || !std::isfinite(obj->ref_amp) ||
+            obj->ref_step0 < 0)
             return CF_EINVAL;
         hipError_t e = hipSuccess;
         float* tab = ref_tab_buf;
@@ -863,7 +971,7 @@ static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T,
             tab = (float*)h->ref_tab.p;
         }
         hipLaunchKernelGGL(k_eight_table, dim3((T + 1 + 255) / 256), dim3(256), 0, h->stream, tab, T, h->dt,
-                           obj->ref_amp, obj->ref_period);
+                           obj->ref_amp, obj->ref_period, obj->ref_step0);
         if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
         a.ref_tab = tab;
     }
@@ -891,9 +999,6 @@ static RollArgs roll_args(const cf_handle* h, const float* x0, const float* cmds
     return a;
 }
 
-static int roll_mode(const cf_handle* h) {
-    return (h->lane_ok && h->D > 0 && (double)h->D / h->M < 32.0) ? LM_LANE : LM_TILE;
-}
 
 cf_status cf_ckpt_floats(const cf_handle* h, int32_t T, int32_t K, int32_t kind, int64_t* n) {
     if (!h || !n || T < 1 || K < 1) return CF_EINVAL;
@@ -971,7 +1076,8 @@ struct BwdScratch {
     float* ref_tab = nullptr;   // [T + 1][6], figure-eight objectives
     float* seg = nullptr;       // [slots][S][D] recomputed segment states
     float* ggc = nullptr;       // [52][D] per-drone gain-gradient contributions
-    float* gpart = nullptr;     // [n_gains][blocks][52] stage-1 gain sums
+    float* rec = nullptr;       // MLP policy: [17 + 4 H][T][D] per-step records
+    float* gpart = nullptr;     // [n_gains][blocks][52 or P] stage-1 sums
 };
 
 static cf_status rollout_backward_impl(cf_handle* h, const float* cmds, int32_t T, const cf_objective* obj,
@@ -993,7 +1099,10 @@ static cf_status rollout_backward_impl(cf_handle* h, const float* cmds, int32_t 
         if (g_cmds && check_dev(g_cmds, (size_t)T * 4 * h->D * sizeof(float))) return CF_EINVAL;
         if (g_x0 && check_dev(g_x0, SD)) return CF_EINVAL;
     }
-    if (g_gain && check_dev(g_gain, (size_t)h->n_gains * 52 * sizeof(float))) return CF_EINVAL;
+    const int Hp = obj ? obj->policy_hidden : 0;   // MLP policy width (validated below)
+    if (Hp < 0 || Hp > CF_MLP_MAX_HIDDEN) return CF_EINVAL;
+    const int Pp = Hp > 0 ? CF_MLP_PARAMS(Hp) : 52;
+    if (g_gain && check_dev(g_gain, (size_t)h->n_gains * Pp * sizeof(float))) return CF_EINVAL;
     // scratch sizes (floats)
     const int64_t Dm = std::max<int64_t>(h->D, 1);
     // segment slots 1..K-1 hold recomputed states (slot 0 is the checkpoint itself);
@@ -1002,8 +1111,12 @@ static cf_status rollout_backward_impl(cf_handle* h, const float* cmds, int32_t 
     const int nb = gain_blocks(h->D);
     const size_t n_tab = (obj && !obj->ref_table) ? (size_t)(T + 1) * 6 : 0;
     const size_t n_seg = slots > 1 ? (size_t)slots * h->S * Dm : 0;
-    const size_t n_ggc = g_gain ? (size_t)52 * Dm : 0;
-    const size_t n_part = g_gain ? (size_t)h->n_gains * nb * GAIN_COMP : 0;
+    const int64_t N_rec = (int64_t)T * Dm;
+    const int nb_mlp = (int)std::max<int64_t>(1, std::min<int64_t>((N_rec + 2047) / 2048, GAIN_MAX_BLOCKS));
+    const size_t n_ggc = (g_gain && Hp == 0) ? (size_t)52 * Dm : 0;
+    const size_t n_rec = (g_gain && Hp > 0) ? (size_t)(17 + 4 * Hp) * N_rec : 0;
+    const size_t n_part = !g_gain ? 0
+                                  : (Hp > 0 ? (size_t)h->n_gains * nb_mlp * Pp : (size_t)h->n_gains * nb * GAIN_COMP);
     hipSetDevice(h->device);
     hipError_t e;
     BwdScratch sc;
@@ -1013,7 +1126,7 @@ static cf_status rollout_backward_impl(cf_handle* h, const float* cmds, int32_t 
         // 256-byte-aligned slices; sizes beyond the array are refused before any work
         auto up = [](size_t n) { return (n + 63) / 64 * 64; };
         const size_t cap = CF_NOALLOC_SCRATCH_BYTES / sizeof(float);
-        if (up(n_tab) + up(n_seg) + up(n_ggc) + up(n_part) > cap) return CF_EINVAL;
+        if (up(n_tab) + up(n_seg) + up(n_ggc) + up(n_rec) + up(n_part) > cap) return CF_EINVAL;
         float* q = base;
         auto take = [&](size_t n) -> float* {
             if (n == 0) return nullptr;
@@ -1024,13 +1137,16 @@ static cf_status rollout_backward_impl(cf_handle* h, const float* cmds, int32_t 
         sc.ref_tab = take(n_tab);
         sc.seg = take(n_seg);
         sc.ggc = take(n_ggc);
+        sc.rec = take(n_rec);
         sc.gpart = take(n_part);
     } else {
         if (n_seg && (e = ensure(h->seg, n_seg * sizeof(float))) != hipSuccess) return note(h, e);
         if (n_ggc && (e = ensure(h->ggc, n_ggc * sizeof(float))) != hipSuccess) return note(h, e);
+        if (n_rec && (e = ensure(h->rec, n_rec * sizeof(float))) != hipSuccess) return note(h, e);
         if (n_part && (e = ensure(h->gpart, n_part * sizeof(float))) != hipSuccess) return note(h, e);
         sc.seg = (float*)h->seg.p;
         sc.ggc = (float*)h->ggc.p;
+        sc.rec = (float*)h->rec.p;
         sc.gpart = (float*)h->gpart.p;
         sc.ref_tab = nullptr;   // prepare_objective uses the handle's table
     }
@@ -1046,7 +1162,8 @@ static cf_status rollout_backward_impl(cf_handle* h, const float* cmds, int32_t 
     a.g_cmds = g_cmds;
     a.g_x0 = g_x0;
     a.seg = n_seg ? sc.seg : nullptr;
-    a.ggc = g_gain ? sc.ggc : nullptr;
+    a.ggc = (g_gain && Hp == 0) ? sc.ggc : nullptr;
+    a.mlp_rec = (g_gain && Hp > 0) ? sc.rec : nullptr;
     if (h->D > 0) {
         const int mode = roll_mode(h);
         if (mode == LM_TILE && (e = build_tiles(h, h->tile)) != hipSuccess) return note(h, e);
@@ -1057,7 +1174,21 @@ static cf_status rollout_backward_impl(cf_handle* h, const float* cmds, int32_t 
         });
         if (e != hipSuccess) return note(h, e);
     }
-    if (g_gain) {
+    if (g_gain && Hp > 0) {
+        if (h->D > 0) {
+            const int64_t chunk = (N_rec + nb_mlp - 1) / nb_mlp;
+            hipLaunchKernelGGL(k_mlp_partial, dim3(nb_mlp, h->n_gains), dim3(256),
+                               (size_t)(17 + 4 * Hp) * 64 * sizeof(float), h->stream, (const float*)sc.rec,
+                               (int64_t)T * h->D, h->D, Hp, Pp, h->drone_world, h->d_gidx, chunk, sc.gpart);
+            if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
+            hipLaunchKernelGGL(k_mlp_final, dim3(h->n_gains), dim3(256), 0, h->stream, (const float*)sc.gpart,
+                               nb_mlp, Pp, g_gain);
+        } else {
+            hipLaunchKernelGGL(k_fill_u32, dim3((h->n_gains * Pp + 255) / 256), dim3(256), 0, h->stream,
+                               (unsigned*)g_gain, h->n_gains * Pp, 0u);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
+    } else if (g_gain) {
         if (h->D > 0) {
             const int64_t chunk = (h->D + nb - 1) / nb;
             hipLaunchKernelGGL(k_gain_partial, dim3(nb, h->n_gains), dim3(256), 0, h->stream, (const float*)sc.ggc,

@@ -244,6 +244,8 @@ uint32_t objective_hash(const cf_objective* obj) {
     f.add(obj->ref_amp);
     f.add(obj->ref_period);
     f.add(obj->w_u);
+    f.add(obj->policy_hidden);
+    f.add(obj->ref_step0);
     if (obj->kind == CF_OBJ_BPTT_REWARD) {
         f.add(obj->w_tilt);
         for (int i = 0; i < 4; ++i) f.add(obj->w_act[i]);

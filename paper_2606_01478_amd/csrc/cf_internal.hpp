@@ -66,6 +66,11 @@ struct RollArgs {
     float w_tilt, w_act[4], w_dact[4];
     float* ubuf;            // reward: applied commands [T][4][D] inside the checkpoint buffer
                             // (written by the forward, read by the backward) or null
+    int mlp_H;              // small-MLP policy width (0: linear feedback through `gain`)
+    int mlp_P;              // floats per policy
+    int n_pol;              // policies in `gain` (staged into LDS)
+    float* mlp_rec;         // backward: per drone-step records [17 + 4 H][T][D] for the
+                            // weight-gradient reduction
     // forward outputs
     int K;                  // checkpoint interval
     float* ckpt;            // [ceil(T/K)][S][D] or null

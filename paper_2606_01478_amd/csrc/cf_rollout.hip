@@ -89,6 +89,99 @@ __device__ __forceinline__ void feedback(const RollArgs& a, const float* G, cons
     }
 }
 
+// ---- small-MLP policy ----------------------------------------------------------
+// o = W3 tanh(W2 tanh(W1 e + b1) + b2) + b3, one policy packed
+// [W1 (H x 13) | b1 (H) | W2 (H x H) | b2 (H) | W3 (4 x H) | b3 (4)] in LDS (the
+// same address for every lane: broadcast reads). A lane keeps its activations
+// in its own LDS columns hc[k * ws]: h1 at k < H, h2 at H <= k < 2H, and in the
+// backward dz2 at 2H <= k < 3H, dz1 at 3H <= k < 4H.
+struct MlpView {
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+    int H;
+    __device__ __forceinline__ MlpView(const float* w, int H_) : H(H_) {
+        W1 = w;
+        b1 = W1 + 13 * H;
+        W2 = b1 + H;
+        b2 = W2 + H * H;
+        W3 = b2 + H;
+        b3 = W3 + 4 * H;
+    }
+};
+
+__device__ __forceinline__ void mlp_forward(const MlpView& m, const float* e, float* hc, int ws, float* o) {
+    const int H = m.H;
+    for (int j = 0; j < H; ++j) {
+        float z = m.b1[j];
+#pragma unroll
+        for (int i = 0; i < 13; ++i) z = fmaf(m.W1[j * 13 + i], e[i], z);
+        hc[j * ws] = tanhf(z);
+    }
+    for (int j = 0; j < H; ++j) {
+        float z = m.b2[j];
+        for (int k = 0; k < H; ++k) z = fmaf(m.W2[j * H + k], hc[k * ws], z);
+        hc[(H + j) * ws] = tanhf(z);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float z = m.b3[r];
+        for (int k = 0; k < H; ++k) z = fmaf(m.W3[r * H + k], hc[(H + k) * ws], z);
+        o[r] = z;
+    }
+}
+
+// VJP of mlp_forward at the activations in hc, given the adjoint d3 of o:
+// writes dz2 and dz1 to their columns and adds W1^T dz1 to eb (13)
+__device__ __forceinline__ void mlp_vjp(const MlpView& m, const float* d3, float* hc, int ws, float* eb) {
+    const int H = m.H;
+    for (int k = 0; k < H; ++k) {
+        float s = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s = fmaf(m.W3[r * H + k], d3[r], s);
+        const float h2 = hc[(H + k) * ws];
+        hc[(2 * H + k) * ws] = s * (1.f - h2 * h2);
+    }
+    for (int k = 0; k < H; ++k) {
+        float s = 0.f;
+        for (int j = 0; j < H; ++j) s = fmaf(m.W2[j * H + k], hc[(2 * H + j) * ws], s);
+        const float h1 = hc[k * ws];
+        hc[(3 * H + k) * ws] = s * (1.f - h1 * h1);
+    }
+    for (int j = 0; j < H; ++j) {
+        const float dz = hc[(3 * H + j) * ws];
+#pragma unroll
+        for (int i = 0; i < 13; ++i) eb[i] = fmaf(m.W1[j * 13 + i], dz, eb[i]);
+    }
+}
+
+// applied command through the MLP policy: u = ubar + o(e), e = x[0:13] - x_ref(t)
+template <int MODEL>
+__device__ __forceinline__ void feedback_mlp(const RollArgs& a, const MlpView& m, const float* x, int t,
+                                             const float* off, float f_hover, const float* ubar, float* u,
+                                             float* ev, float* hc, int ws) {
+    float xr[13], o[4];
+    ref_state<MODEL>(a, t, off, f_hover, xr);
+#pragma unroll
+    for (int j = 0; j < 13; ++j) ev[j] = x[j] - xr[j];
+    mlp_forward(m, ev, hc, ws, o);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] = ubar[i] + o[i];
+}
+
+// the applied command of step t: linear feedback through G, or (extended kernels,
+// mlp_H > 0) the MLP policy whose weights G points to
+template <int MODEL, bool EXT>
+__device__ __forceinline__ void apply_feedback(const RollArgs& a, const float* G, float* hc, int ws, const float* x,
+                                               int t, const float* off, float f_hover, const float* ubar, float* u,
+                                               float* ev) {
+    if constexpr (EXT) {
+        if (a.mlp_H > 0) {
+            feedback_mlp<MODEL>(a, MlpView(G, a.mlp_H), x, t, off, f_hover, ubar, u, ev, hc, ws);
+            return;
+        }
+    }
+    feedback<MODEL>(a, G, x, t, off, f_hover, ubar, u, ev);
+}
+
 template <int MODEL, int CTRL>
 struct ModelTraits {
     static constexpr int S = MODEL == MODEL_ID ? S_ID : (CTRL == CTRL_PID ? S_PID : S_FP);
@@ -240,7 +333,7 @@ __device__ __forceinline__ void store_state(float* dst, size_t D, size_t d, cons
 // forward rollout of one drone
 template <int MODEL, int CTRL, int INTEG, bool AERO, bool EXT, class R>
 __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& a, size_t d, int w, int S_h,
-                                                  const float* G) {
+                                                  const float* G, float* hc, int ws) {
     constexpr int S = ModelTraits<MODEL, CTRL>::S;
     const size_t D = (size_t)a.D;
     const size_t SD = (size_t)S_h * D;
@@ -270,7 +363,7 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
     for (int t = 0; t < a.T; ++t) {
         float u[4], ev[13], unext[4];
         if (t + 1 < a.T) load_cmd(a, t + 1, d, unext);   // issued early, used next step
-        feedback<MODEL>(a, G, x, t, off, f_hover, ubar, u, ev);
+        apply_feedback<MODEL, EXT>(a, G, hc, ws, x, t, off, f_hover, ubar, u, ev);
         if (rew) {
             float ah[4];
             hover_action<MODEL, CTRL>(p, ah);
@@ -325,9 +418,9 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
 // controller evaluated at x_tb (checkpoint tb / K when tb is a checkpoint step,
 // else slot tb - t0 of the current segment) under the command applied there.
 template <int MODEL, int CTRL, int S>
-__device__ __forceinline__ void block_commands(const RollArgs& a, const DroneParams& p, const float* G,
-                                               const float* off, float f_hover, size_t D, size_t d, size_t SD,
-                                               int tb, int t0, float* rc) {
+__device__ __forceinline__ void block_commands(const RollArgs& a, const DroneParams& p, const float* G, float* hc,
+                                               int ws, const float* off, float f_hover, size_t D, size_t d,
+                                               size_t SD, int tb, int t0, float* rc) {
     float xs[S], ubs[4], us[4], evs[13], cs[8];
     if (tb % a.K == 0) {
         load_rows<S>(a.ckpt_in + (size_t)(tb / a.K) * SD, D, d, xs);
@@ -336,7 +429,7 @@ __device__ __forceinline__ void block_commands(const RollArgs& a, const DronePar
         load_rows<S>(a.seg + (size_t)(tb - t0) * SD, D, d, xs);
     }
     load_cmd(a, tb, d, ubs);
-    feedback<MODEL>(a, G, xs, tb, off, f_hover, ubs, us, evs);
+    apply_feedback<MODEL, true>(a, G, hc, ws, xs, tb, off, f_hover, ubs, us, evs);
     fp_ctrl_forward<CTRL>(xs, us, p.fp, p.pid, a.dtc, a.inv_dtc, rc, cs);
 }
 
@@ -363,7 +456,8 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
     for (int i = 0; i < S; ++i) lam[i] = 0.f;
     // this drone's gain-gradient contributions, summed in step order, in its own
     // LDS column gl[k * gs] (registers are the adjoint's scarcest resource)
-    if (G) {
+    const bool mlp = EXT && a.mlp_H > 0;
+    if (G && !mlp) {
 #pragma unroll
         for (int i = 0; i < NG; ++i) gl[i * gs] = 0.f;
     }
@@ -402,12 +496,12 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
                 // a segment that starts inside a block (period longer than the
                 // checkpoint interval) starts with that block's held commands
                 if (t0 % n_c != 0)
-                    block_commands<MODEL, CTRL, S>(a, p, G, off, f_hover, D, d, SD, t0 - t0 % n_c, t0, rcf);
+                    block_commands<MODEL, CTRL, S>(a, p, G, gl, gs, off, f_hover, D, d, SD, t0 - t0 % n_c, t0, rcf);
             }
             for (int j = 0; j < n_re; ++j) {
                 float u[4], ev[13], ubar[4];
                 load_cmd(a, t0 + j, d, ubar);
-                feedback<MODEL>(a, G, x, t0 + j, off, f_hover, ubar, u, ev);
+                apply_feedback<MODEL, EXT>(a, G, gl, gs, x, t0 + j, off, f_hover, ubar, u, ev);
                 model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a, rcf, (t0 + j) % n_c == 0);
                 if (j + 1 < t1 - t0 || rew) store_rows<S>(a.seg + (size_t)(j + 1) * SD, D, d, x);
             }
@@ -468,7 +562,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
                 }
             }
             float u[4], ev[13];
-            feedback<MODEL>(a, G, xc, t, off, f_hover, uc, u, ev);
+            apply_feedback<MODEL, EXT>(a, G, gl, gs, xc, t, off, f_hover, uc, u, ev);
             float xb[S];
             float ub[4] = {0.f, 0.f, 0.f, 0.f};
             bool held = false;
@@ -477,7 +571,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
                     held = true;
                     const int tb = t - t % n_c;
                     if (t == a.T - 1 || (t + 1) % n_c == 0)   // first visit of this block
-                        block_commands<MODEL, CTRL, S>(a, p, G, off, f_hover, D, d, SD, tb, t0, rch);
+                        block_commands<MODEL, CTRL, S>(a, p, G, gl, gs, off, f_hover, D, d, SD, tb, t0, rch);
                     fp_held_vjp<INTEG>(xc, rch, p.fp, a.dt, a.renorm, lam, xb, rcb);
                     if constexpr (S > S_FP) {
 #pragma unroll
@@ -516,7 +610,33 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) a.g_cmds[((size_t)t * 4 + i) * D + d] = ub[i];
             }
-            if (G) {
+            if (G && mlp) {
+                // the policy's activations at e_t (recomputed: a controller block's
+                // first visit may have evaluated the policy at another state), its
+                // VJP into x_t, and the step's record for the weight gradient
+                const MlpView m(G, a.mlp_H);
+                const int H = a.mlp_H;
+                float o[4], eb[13];
+                mlp_forward(m, ev, gl, gs, o);
+#pragma unroll
+                for (int j = 0; j < 13; ++j) eb[j] = 0.f;
+                mlp_vjp(m, ub, gl, gs, eb);
+#pragma unroll
+                for (int j = 0; j < 13; ++j) xb[j] += eb[j];
+                if (a.mlp_rec) {
+                    const size_t TD = (size_t)a.T * D, base = (size_t)t * D + d;
+#pragma unroll
+                    for (int j = 0; j < 13; ++j) a.mlp_rec[j * TD + base] = ev[j];
+                    for (int k = 0; k < H; ++k) {
+                        a.mlp_rec[(13 + k) * TD + base] = gl[k * gs];                  // h1
+                        a.mlp_rec[(13 + H + k) * TD + base] = gl[(H + k) * gs];        // h2
+                        a.mlp_rec[(13 + 2 * H + k) * TD + base] = gl[(3 * H + k) * gs];  // dz1
+                        a.mlp_rec[(13 + 3 * H + k) * TD + base] = gl[(2 * H + k) * gs];  // dz2
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) a.mlp_rec[(13 + 4 * H + i) * TD + base] = ub[i];
+                }
+            } else if (G) {
 #pragma unroll
                 for (int j = 0; j < 13; ++j) {
                     float s2 = 0.f;
@@ -549,7 +669,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
         for (int i = S; i < S_h; ++i) a.g_x0[(size_t)i * D + d] = 0.f;
     }
     if (a.ggc) {
-        if (G) {
+        if (G && !mlp) {
 #pragma unroll
             for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = gl[i * gs];
         } else {
@@ -596,16 +716,35 @@ __device__ __forceinline__ void rollout_drone(const R& rec, const RollArgs& a, s
     if constexpr (BWD) {
         rollout_bwd_drone<MODEL, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
     } else {
-        rollout_fwd_drone<MODEL, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G);
+        rollout_fwd_drone<MODEL, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
     }
 }
 
-// EXT: the extended variant, for an onboard controller slower than the physics
-// and for the BPTT reward objective; the plain variant keeps the registers of
-// the every-step, tracking-loss path
+// EXT: the extended variant, for an onboard controller slower than the physics,
+// the BPTT reward objective and the MLP policy; the plain variant keeps the
+// registers of the every-step, tracking-loss path with linear feedback
+// Dynamic LDS of the rollout kernels: the linear backward keeps each lane's 52
+// gain-gradient sums in a column ([52][lanes]); with the MLP policy the
+// policies are staged first ([n_pol][P]), followed by each lane's activation
+// columns ([2H or 4H][lanes]). Returns the lane's column base.
+template <bool EXT>
+__device__ __forceinline__ float* stage_policies(const RollArgs& a, float* lds) {
+    if constexpr (EXT) {
+        if (a.mlp_H > 0) {
+            const int n = a.n_pol * a.mlp_P;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = a.gain[i];
+            __syncthreads();
+            return lds + n + threadIdx.x;
+        }
+    }
+    return lds + threadIdx.x;
+}
+
 template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool EXT>
 __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
     rollout_priority();
+    extern __shared__ float roll_lds[];
+    float* gl = stage_policies<EXT>(a, roll_lds);
     const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= (size_t)a.D) return;
     if constexpr (BWD) {
@@ -617,8 +756,7 @@ __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
     const int w = a.drone_world[d];
     const SoaRec rec{a.par_soa, a.M, w};
     const float* G = (a.has_obj && a.gain) ? a.gain + (size_t)a.gidx[w] * NG : nullptr;
-    extern __shared__ float roll_lds[];   // backward: [NG][blockDim.x] gain-gradient sums
-    float* gl = roll_lds + threadIdx.x;
+    if (EXT && a.mlp_H > 0) G = roll_lds + (size_t)a.gidx[w] * a.mlp_P;
     const int gs = blockDim.x;
     if constexpr (MODELS == MS_FP) rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
     else rollout_drone<BWD, MODEL_ID, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
@@ -632,10 +770,14 @@ __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __
     const int d0 = __builtin_amdgcn_readfirstlane(td.y);
     const int cnt = __builtin_amdgcn_readfirstlane(td.z);
     const int model = __builtin_amdgcn_readfirstlane(td.w);
-    // the world's feedback gain, shared by the workgroup, is read from LDS
+    // the world's feedback gain (or MLP policy), shared by the workgroup, is read from LDS
     __shared__ float sG[NG];
+    extern __shared__ float roll_lds[];
+    float* gl = stage_policies<EXT>(a, roll_lds);
     const float* G = nullptr;
-    if (a.has_obj && a.gain) {
+    if (EXT && a.mlp_H > 0) {
+        G = roll_lds + (size_t)a.gidx[w] * a.mlp_P;
+    } else if (a.has_obj && a.gain) {
         const float* Gw = a.gain + (size_t)a.gidx[w] * NG;
         for (int i = threadIdx.x; i < NG; i += blockDim.x) sG[i] = Gw[i];
         __syncthreads();
@@ -651,8 +793,6 @@ __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __
             return;
         }
     }
-    extern __shared__ float roll_lds[];   // backward: [NG][blockDim.x] gain-gradient sums
-    float* gl = roll_lds + threadIdx.x;
     const int gs = blockDim.x;
     if constexpr (MODELS == MS_FP) {
         rollout_drone<BWD, MODEL_FP, CTRL, INTEG, AERO, EXT>(rec, a, d, w, S_h, G, gl, gs);
@@ -664,6 +804,13 @@ __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __
     }
 }
 
+template <bool BWD, bool EXT>
+static size_t roll_lds_bytes(const RollArgs& a, int lanes) {
+    if (EXT && a.mlp_H > 0)
+        return ((size_t)a.n_pol * a.mlp_P + (size_t)(BWD ? 4 : 2) * a.mlp_H * lanes) * sizeof(float);
+    return BWD ? (size_t)NG * lanes * sizeof(float) : 0;
+}
+
 template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool EXT>
 static hipError_t launch_roll_k(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                 hipStream_t s) {
@@ -672,26 +819,26 @@ static hipError_t launch_roll_k(const KernelSel& ks, const RollArgs& a, const in
         if constexpr (MODELS != MS_BOTH) {
             const int bs = ks.tile;
             const unsigned grid = (unsigned)((a.D + bs - 1) / bs);
-            const size_t shmem = BWD ? (size_t)NG * bs * sizeof(float) : 0;
-            hipLaunchKernelGGL((k_rollout_lane<BWD, MODELS, CTRL, INTEG, AERO, EXT>), dim3(grid), dim3(bs), shmem, s, a,
-                               S_h);
+            const size_t lds = roll_lds_bytes<BWD, EXT>(a, bs);
+            hipLaunchKernelGGL((k_rollout_lane<BWD, MODELS, CTRL, INTEG, AERO, EXT>), dim3(grid), dim3(bs), lds, s,
+                               a, S_h);
         } else {
             return hipErrorInvalidValue;
         }
     } else {
-        const size_t shmem = BWD ? (size_t)NG * ks.tile * sizeof(float) : 0;
-        hipLaunchKernelGGL((k_rollout_tile<BWD, MODELS, CTRL, INTEG, AERO, EXT>), dim3(n_tiles), dim3(ks.tile), shmem, s,
-                           a, tiles, S_h);
+        const size_t lds = roll_lds_bytes<BWD, EXT>(a, ks.tile);
+        hipLaunchKernelGGL((k_rollout_tile<BWD, MODELS, CTRL, INTEG, AERO, EXT>), dim3(n_tiles), dim3(ks.tile), lds,
+                           s, a, tiles, S_h);
     }
     return hipGetLastError();
 }
 
-// the extended variant serves a slower onboard controller and the reward objective
+// the extended variant serves a slower onboard controller, the reward objective and the MLP policy
 template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
 static hipError_t launch_roll_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                 hipStream_t s) {
     constexpr bool CAN_MR = MODELS != MS_ID && CTRL != CTRL_ROTOR;
-    if ((CAN_MR && a.ctrl_every > 1) || (a.has_obj && a.obj_kind == 1))
+    if ((CAN_MR && a.ctrl_every > 1) || (a.has_obj && a.obj_kind == 1) || a.mlp_H > 0)
         return launch_roll_k<BWD, MODELS, CTRL, INTEG, AERO, true>(ks, a, tiles, n_tiles, s);
     return launch_roll_k<BWD, MODELS, CTRL, INTEG, AERO, false>(ks, a, tiles, n_tiles, s);
 }

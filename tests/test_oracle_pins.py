@@ -1271,3 +1271,23 @@ def test_mlp_policy_output_layer_gradient_identity():
 def test_gradient_fd_mlp_policy():
     w = W.config4_mlp(seed=42, n_worlds=3, steps=20, hidden=5, out_scale=0.05)
     _fd_check(w)
+
+
+def test_reference_time_offset_equals_the_shifted_table():
+    """A rollout that follows the figure-eight from step k equals the same rollout
+    given the reference rows of steps k .. k + T as an explicit table."""
+    w = W.config4(seed=43, n_worlds=4, steps=30)
+    k = 777
+    b = O.Batch.from_workload(w)
+    rows = []
+    for n in range(w.steps + 1):
+        p, v = b.figure_eight((k + n) * b.dt, w.ref_amp, w.ref_period, None)
+        rows.append(b.reference_state(p, v)[:, 0])
+    table = torch.stack(rows)
+    kw = dict(gain=O.t64(w.gain), w_u=w.w_u)
+    with torch.no_grad():
+        a = O.rollout(b, O.t64(w.x0), O.t64(w.cmds), w.steps, ref_amp=w.ref_amp, ref_period=w.ref_period,
+                      ref_step0=k, **kw)
+        c = O.rollout(b, O.t64(w.x0), O.t64(w.cmds), w.steps, ref_table=table, **kw)
+    assert torch.allclose(a["loss"], c["loss"], rtol=1e-12, atol=0)
+    assert torch.allclose(a["x"], c["x"], rtol=1e-12, atol=1e-15)

@@ -97,6 +97,7 @@ class Workload:
     ctrl_every: int = 1                   # onboard controller every n physics steps
     reward: Optional[dict] = None         # BPTT reward weights (w_tilt, w_act[4], w_dact[4]) or None
     policy_hidden: int = 0                # > 0: `gain` holds [G, P] small-MLP policies of this width
+    ref_step0: int = 0                    # the figure-eight is followed from t = ref_step0 dt
 
     @property
     def n_drones_total(self) -> int:
