@@ -183,9 +183,10 @@ typedef struct cf_handle cf_handle;
 /*
  * Tracking objective and linear feedback of cf_rollout / cf_rollout_backward.
  * Applied command u_t = ubar_t + G_w (x_t[0:13] - x_ref(t)) when gain != NULL
- * (with policy_hidden > 0 the small-MLP policy's output replaces G_w (...)).
+ * (with policy_hidden > 0 the small-MLP policy's output replaces G_w (...);
+ * with policy_scale set, that output o enters as policy_scale * tanh(o)).
  * Loss per drone: sum_{t=1..T} |p_t - p_ref(t)|^2 + w_u sum_{t=0..T-1} |u_t|^2,
- * t_n = (ref_step0 + n) dt. Reference (ref_table == NULL): figure-eight
+ * t_n = (ref_step0 + n) dt (+ s_d with ref_time_shift). Reference (ref_table == NULL): figure-eight
  * p_ref = [A sin(2 pi t/P), (A/2) sin(4 pi t/P), 0] + offset_d and its
  * derivative; x_ref = [p_ref, (0,0,0,1), v_ref, 0] (FP) or
  * [p_ref, 0, v_ref, 0, m g / c_f] (ID). With ref_table, x_ref(t) is row t
@@ -208,6 +209,20 @@ typedef struct cf_objective {
     int32_t ref_step0;        /* figure-eight: step n of the rollout tracks the
                                  reference at t = (ref_step0 + n) dt, >= 0, so that
                                  consecutive rollouts continue along it          */
+    const float* ref_time_shift; /* device [D] or NULL; figure-eight only: drone d
+                                 tracks the reference at t_n + s_d, which places
+                                 starts along the trajectory (Methods,
+                                 "Backpropagation Through Time"). The phase
+                                 2 pi s_d / P is formed in binary32: keep |s_d|
+                                 within a few periods. Selects the extended
+                                 kernel variant.                                 */
+    float policy_scale[4];    /* all 0: the policy output o is added to ubar as
+                                 is. Else u_i = ubar_i + policy_scale[i] tanh(o_i),
+                                 each >= 0: actions normalised to [-1, 1] that map
+                                 linearly onto command ranges, as the paper states
+                                 for its policies' action space (Methods, "Proximal
+                                 Policy Optimization"); selects the extended kernel
+                                 variant.                                        */
 } cf_objective;
 
 /*

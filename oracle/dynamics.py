@@ -438,10 +438,17 @@ class Batch:
 
     # -- reference and objective -------------------------------------------------
 
-    def figure_eight(self, t: float, amp: float, period: float, offset):
+    def figure_eight(self, t: float, amp: float, period: float, offset, shift=None):
         """Lemniscate of Gerono: p = [A sin(2 pi t/P), (A/2) sin(4 pi t/P), 0] plus
-        the drone's offset; returns (p_ref [3,D], v_ref [3,D])."""
+        the drone's offset; returns (p_ref [3,D], v_ref [3,D]). With ``shift`` [D]
+        (seconds) drone d is evaluated at t + shift_d instead."""
         w0 = 2 * math.pi / period
+        if shift is not None:
+            td = t + t64(shift)
+            z = torch.zeros(self.D, dtype=F64)
+            p = torch.stack([amp * torch.sin(w0 * td), 0.5 * amp * torch.sin(2 * w0 * td), z])
+            v = torch.stack([amp * w0 * torch.cos(w0 * td), amp * w0 * torch.cos(2 * w0 * td), z])
+            return (p + offset if offset is not None else p), v
         p = torch.tensor([amp * math.sin(w0 * t), 0.5 * amp * math.sin(2 * w0 * t), 0.0], dtype=F64)
         v = torch.tensor([amp * w0 * math.cos(w0 * t), amp * w0 * math.cos(2 * w0 * t), 0.0], dtype=F64)
         p = p[:, None].expand(3, self.D)
@@ -543,7 +550,7 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
             ref_amp: float = 1.0, ref_period: float = 4.0, ref_offset=None,
             ref_table: Optional[torch.Tensor] = None, w_u: float = 1e-3,
             with_loss: bool = True, keep_traj: bool = False, reward: Optional[Dict] = None,
-            policy_hidden: int = 0, ref_step0: int = 0):
+            policy_hidden: int = 0, ref_step0: int = 0, ref_time_shift=None, policy_scale=None):
     """Roll out ``steps`` steps with per-step commands ``cmds`` [T, 4, D] (or held
     [4, D]). With ``gain`` [G, 4, 13] the applied command is
     u_t = ubar_t + G_w (x_t[0:13] - x_ref(t)). Loss per drone:
@@ -561,7 +568,12 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
     With ``policy_hidden`` = H > 0, ``gain`` [G, P] holds MLP policies instead of
     linear gains and u_t = ubar_t + mlp_policy(theta_w, H, x_t[0:13] - x_ref(t)). With
     ``ref_step0`` = k the figure-eight is followed from t = k dt: step n tracks
-    p_ref((k + n) dt), so that consecutive rollouts continue along it.
+    p_ref((k + n) dt), so that consecutive rollouts continue along it. With
+    ``ref_time_shift`` [D] drone d follows the figure-eight at t + shift_d
+    (starts spread along the trajectory; not with ``ref_table``). With
+    ``policy_scale`` s (4 values, not all 0) the policy output o (linear or MLP)
+    enters as s * tanh(o): a normalised action in [-1, 1] mapped linearly onto
+    each command's range.
     Returns dict(x=x_T, loss=[D] or None, traj=[T+1, S, D] or None)."""
     x = x0
     D = batch.D
@@ -571,6 +583,11 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
         G = gain[torch.as_tensor(gi[batch.world])]            # [D, 4, 13], or [D, P] for an MLP policy
     loss = torch.zeros(D, dtype=F64)
     traj = [x] if keep_traj else None
+    if ref_time_shift is not None and ref_table is not None:
+        raise ValueError("a time shift applies to the figure-eight only")
+    squash = None
+    if policy_scale is not None and any(float(v) != 0.0 for v in policy_scale):
+        squash = t64(np.asarray(policy_scale, np.float32))[:, None]
 
     def ref(n):
         t = (ref_step0 + n) * batch.dt
@@ -579,7 +596,7 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
             if ref_offset is not None:
                 xr = torch.cat([xr[0:3] + ref_offset, xr[3:]], 0)
             return xr[0:3], xr
-        p, v = batch.figure_eight(t, ref_amp, ref_period, ref_offset)
+        p, v = batch.figure_eight(t, ref_amp, ref_period, ref_offset, ref_time_shift)
         return p, (batch.reference_state(p, v) if G is not None else None)
 
     held = None
@@ -594,9 +611,12 @@ def rollout(batch: Batch, x0: torch.Tensor, cmds: torch.Tensor, steps: int,
             _, xr = ref(n)
             e = x[0:13] - xr
             if policy_hidden:
-                u = ubar + mlp_policy(G, policy_hidden, e)
+                o = mlp_policy(G, policy_hidden, e)
             else:
-                u = ubar + (G * e.T[:, None, :]).sum(2).T
+                o = (G * e.T[:, None, :]).sum(2).T
+            if squash is not None:
+                o = squash * torch.tanh(o)
+            u = ubar + o
         else:
             u = ubar
         if with_loss and reward is None:
@@ -665,7 +685,9 @@ def rollout_workload(w, with_grad: bool = False, keep_traj: bool = False):
     kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period,
               ref_offset=None if w.ref_offset is None else t64(w.ref_offset), w_u=w.w_u,
               reward=getattr(w, "reward", None), policy_hidden=getattr(w, "policy_hidden", 0),
-              ref_step0=getattr(w, "ref_step0", 0))
+              ref_step0=getattr(w, "ref_step0", 0),
+              ref_time_shift=getattr(w, "ref_time_shift", None),
+              policy_scale=getattr(w, "policy_scale", None))
     gain = None if w.gain is None else t64(w.gain)
     if with_grad:
         return rollout_grad(b, w.x0, w.cmds, w.steps, gain=gain, gain_index=w.gain_index,

@@ -65,7 +65,8 @@ class _Objective(ctypes.Structure):
     _fields_ = [("gain", c_void_p), ("ref_table", c_void_p), ("ref_amp", c_float), ("ref_period", c_float),
                 ("ref_offset", c_void_p), ("w_u", c_float), ("kind", c_int32), ("w_tilt", c_float),
                 ("w_act", c_float * 4), ("w_dact", c_float * 4), ("policy_hidden", c_int32),
-                ("ref_step0", c_int32)]
+                ("ref_step0", c_int32),
+                ("ref_time_shift", c_void_p), ("policy_scale", c_float * 4)]
 
 
 class _MppiDesc(ctypes.Structure):
@@ -246,10 +247,11 @@ class Sim:
     def _need_obj(self, obj, T) -> None:
         if obj is None:
             return
-        g, rt, ro = getattr(obj, "_tensors", (None, None, None))
+        g, rt, ro, rs = getattr(obj, "_tensors", (None, None, None, None))
         self._need(g, self._gain_shape(obj), "gain")
         self._need(rt, (T + 1, 13), "ref_table")
         self._need(ro, (3, self.D), "ref_offset")
+        self._need(rs, (self.D,), "ref_time_shift")
 
     def _sync_stream(self) -> None:
         _check(self._lib.cf_set_stream(self._h, c_void_p(_stream())), "cf_set_stream")
@@ -271,11 +273,13 @@ class Sim:
 
     @staticmethod
     def objective(gain=None, ref_table=None, ref_amp=1.0, ref_period=4.0, ref_offset=None, w_u=1e-3,
-                  reward=None, policy_hidden=0, ref_step0=0):
+                  reward=None, policy_hidden=0, ref_step0=0, ref_time_shift=None, policy_scale=None):
         """Tracking objective; with ``reward`` = dict(w_tilt, w_act[4], w_dact[4]) the
         BPTT reward objective (CF_OBJ_BPTT_REWARD) instead. With ``policy_hidden`` = H
         > 0, ``gain`` holds small-MLP policies [n_gains, mlp_params(H)] instead of
-        linear gains [n_gains, 4, 13]."""
+        linear gains [n_gains, 4, 13]. ``ref_time_shift`` [D] (seconds) moves each
+        drone's point on the figure-eight. ``policy_scale`` (4 floats) squashes the
+        policy output o into ``policy_scale * tanh(o)``."""
         o = _Objective()
         o.policy_hidden = int(policy_hidden)
         o.ref_step0 = int(ref_step0)
@@ -284,6 +288,10 @@ class Sim:
         o.ref_amp = float(ref_amp)
         o.ref_period = float(ref_period)
         o.ref_offset = _ptr(ref_offset)
+        o.ref_time_shift = _ptr(ref_time_shift)
+        if policy_scale is not None:
+            for i in range(4):
+                o.policy_scale[i] = float(policy_scale[i])
         o.w_u = float(w_u)
         if reward is not None:
             o.kind = CF_OBJ_BPTT_REWARD
@@ -291,7 +299,7 @@ class Sim:
             for i in range(4):
                 o.w_act[i] = float(reward["w_act"][i])
                 o.w_dact[i] = float(reward["w_dact"][i])
-        o._tensors = (gain, ref_table, ref_offset)
+        o._tensors = (gain, ref_table, ref_offset, ref_time_shift)
         return o
 
     def ckpt_floats(self, T: int, ckpt_every: int, kind: int = CF_OBJ_TRACKING) -> int:

@@ -909,6 +909,8 @@ static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T,
     a.ref_tab = nullptr;
     a.ref_user = 0;
     a.ref_off = nullptr;
+    a.ref_shift = nullptr;
+    a.squash = 0;
     a.w_u = 0.f;
     a.obj_kind = 0;
     a.ubuf = nullptr;
@@ -956,6 +958,24 @@ static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T,
         a.ref_off = obj->ref_offset;
     }
     a.w_u = obj->w_u;
+    {
+        bool any = false, ok = true;
+        for (int i = 0; i < 4; ++i) {
+            ok = ok && std::isfinite(obj->policy_scale[i]) && obj->policy_scale[i] >= 0.f;
+            any = any || obj->policy_scale[i] > 0.f;
+        }
+        if (!ok) return CF_EINVAL;
+        if (any) {
+            a.squash = 1;
+            for (int i = 0; i < 4; ++i) a.act_s[i] = obj->policy_scale[i];
+        }
+    }
+    if (obj->ref_time_shift) {
+        // the shift moves the analytic figure-eight; a user table has no such form
+        if (obj->ref_table) return CF_EINVAL;
+        if (check_dev(obj->ref_time_shift, (size_t)h->D * sizeof(float))) return CF_EINVAL;
+        a.ref_shift = obj->ref_time_shift;
+    }
     if (obj->ref_table) {
         if (check_dev(obj->ref_table, (size_t)(T + 1) * 13 * sizeof(float))) return CF_EINVAL;
         a.ref_tab = obj->ref_table;
@@ -974,6 +994,9 @@ static cf_status prepare_objective(cf_handle* h, const cf_objective* obj, int T,
                            obj->ref_amp, obj->ref_period, obj->ref_step0);
         if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
         a.ref_tab = tab;
+        const double w0 = 2.0 * 3.14159265358979323846 / (double)obj->ref_period;
+        a.ref_w = (float)w0;
+        a.ref_inv_w = (float)(1.0 / w0);
     }
     return CF_OK;
 }

@@ -238,7 +238,8 @@ uint32_t objective_hash(const cf_objective* obj) {
     const int32_t present = obj ? 1 : 0;
     f.add(present);
     if (!obj) return f.h;
-    const int32_t flags = (obj->gain ? 1 : 0) | (obj->ref_table ? 2 : 0) | (obj->ref_offset ? 4 : 0);
+    const int32_t flags =
+        (obj->gain ? 1 : 0) | (obj->ref_table ? 2 : 0) | (obj->ref_offset ? 4 : 0) | (obj->ref_time_shift ? 8 : 0);
     f.add(obj->kind);
     f.add(flags);
     f.add(obj->ref_amp);
@@ -246,6 +247,7 @@ uint32_t objective_hash(const cf_objective* obj) {
     f.add(obj->w_u);
     f.add(obj->policy_hidden);
     f.add(obj->ref_step0);
+    for (int i = 0; i < 4; ++i) f.add(obj->policy_scale[i]);
     if (obj->kind == CF_OBJ_BPTT_REWARD) {
         f.add(obj->w_tilt);
         for (int i = 0; i < 4; ++i) f.add(obj->w_act[i]);

@@ -61,12 +61,16 @@ struct RollArgs {
     const float* ref_tab;   // [T+1][6] figure-eight (p, v) or [T+1][13] user table
     int ref_user;
     const float* ref_off;   // [3][D] or null
+    const float* ref_shift; // [D] per-drone reference time shift [s] or null (extended kernels)
+    float ref_w, ref_inv_w; // figure-eight angular rate 2 pi / P and its inverse
     float w_u;
     int obj_kind;           // 0: tracking loss, 1: BPTT reward
     float w_tilt, w_act[4], w_dact[4];
     float* ubuf;            // reward: applied commands [T][4][D] inside the checkpoint buffer
                             // (written by the forward, read by the backward) or null
     int mlp_H;              // small-MLP policy width (0: linear feedback through `gain`)
+    int squash;             // policy output o enters as act_s * tanh(o) (extended kernels)
+    float act_s[4];
     int mlp_P;              // floats per policy
     int n_pol;              // policies in `gain` (staged into LDS)
     float* mlp_rec;         // backward: per drone-step records [17 + 4 H][T][D] for the

@@ -26,37 +26,97 @@ __device__ __forceinline__ const const_float* ref_row(const RollArgs& a, int t, 
     return (const const_float*)(a.ref_tab + (size_t)t * stride);
 }
 
-// position reference at step t (figure-eight table rows are [p(3), v(3)])
-__device__ __forceinline__ void ref_pos(const RollArgs& a, int t, const float* off, float* pr) {
-    const int stride = a.ref_user ? 13 : 6;
-    const const_float* row = ref_row(a, t, stride);
+// What of the reference is the drone's own: its position offset and, in the
+// extended kernels, the rotation (cos, sin of w s and of 2 w s, w = 2 pi / P)
+// that moves the shared figure-eight rows from time t to t + s for its time
+// shift s. The lemniscate's x and y components are sinusoids of w t and 2 w t,
+// so the shifted row follows from the shared row by the angle-sum identities:
+// with p = A sin(w t), v = A w cos(w t),
+//   A sin(w (t + s)) = p cos(w s) + (v / w) sin(w s),
+//   A w cos(w (t + s)) = v cos(w s) - w p sin(w s),
+// and likewise for the y component at 2 w.
+struct RefLane {
+    float off[3];
+    float c1, s1, c2, s2;
+};
+
+template <bool EXT>
+__device__ __forceinline__ RefLane ref_lane(const RollArgs& a, size_t D, size_t d) {
+    RefLane r{{0.f, 0.f, 0.f}, 1.f, 0.f, 1.f, 0.f};
+    if (a.has_obj && a.ref_off) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j) pr[j] = row[j] + off[j];
+        for (int j = 0; j < 3; ++j) r.off[j] = a.ref_off[j * D + d];
+    }
+    if constexpr (EXT) {
+        if (a.has_obj && a.ref_shift) {
+            sincosf(a.ref_w * a.ref_shift[d], &r.s1, &r.c1);
+            r.c2 = r.c1 * r.c1 - r.s1 * r.s1;
+            r.s2 = 2.f * r.s1 * r.c1;
+        }
+    }
+    return r;
+}
+
+// figure-eight row t moved by the drone's time shift: p (3), v (3)
+template <bool SH>
+__device__ __forceinline__ void eight_row(const RollArgs& a, int t, const RefLane& rl, float* p, float* v) {
+    const const_float* row = ref_row(a, t, 6);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        p[j] = row[j];
+        v[j] = row[3 + j];
+    }
+    if constexpr (SH) {
+        if (a.ref_shift) {
+            const float w = a.ref_w, iw = a.ref_inv_w;
+            const float px = p[0], vx = v[0], py = p[1], vy = v[1];
+            p[0] = px * rl.c1 + (vx * iw) * rl.s1;
+            v[0] = vx * rl.c1 - (w * px) * rl.s1;
+            p[1] = py * rl.c2 + (vy * (0.5f * iw)) * rl.s2;
+            v[1] = vy * rl.c2 - (2.f * w * py) * rl.s2;
+        }
+    }
+}
+
+// position reference at step t (figure-eight table rows are [p(3), v(3)])
+template <bool SH>
+__device__ __forceinline__ void ref_pos(const RollArgs& a, int t, const RefLane& rl, float* pr) {
+    if (a.ref_user) {
+        const const_float* row = ref_row(a, t, 13);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) pr[j] = row[j] + rl.off[j];
+        return;
+    }
+    float v[3];
+    eight_row<SH>(a, t, rl, pr, v);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) pr[j] += rl.off[j];
 }
 
 // 13-component reference state of a drone of model MODEL
-template <int MODEL>
-__device__ __forceinline__ void ref_state(const RollArgs& a, int t, const float* off, float f_hover, float* xr) {
+template <int MODEL, bool SH>
+__device__ __forceinline__ void ref_state(const RollArgs& a, int t, const RefLane& rl, float f_hover, float* xr) {
     if (a.ref_user) {
         const const_float* row = ref_row(a, t, 13);
 #pragma unroll
         for (int j = 0; j < 13; ++j) xr[j] = row[j];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) xr[j] += off[j];
+        for (int j = 0; j < 3; ++j) xr[j] += rl.off[j];
         return;
     }
-    const const_float* row = ref_row(a, t, 6);
+    float p[3], v[3];
+    eight_row<SH>(a, t, rl, p, v);
 #pragma unroll
     for (int j = 0; j < 13; ++j) xr[j] = 0.f;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) xr[j] = row[j] + off[j];
+    for (int j = 0; j < 3; ++j) xr[j] = p[j] + rl.off[j];
     if constexpr (MODEL == MODEL_FP) {
         xr[6] = 1.f;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) xr[7 + j] = row[3 + j];
+        for (int j = 0; j < 3; ++j) xr[7 + j] = v[j];
     } else {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) xr[6 + j] = row[3 + j];
+        for (int j = 0; j < 3; ++j) xr[6 + j] = v[j];
         xr[12] = f_hover;
     }
 }
@@ -68,24 +128,57 @@ __device__ __forceinline__ void load_cmd(const RollArgs& a, int t, size_t d, flo
     for (int i = 0; i < 4; ++i) ub[i] = a.cmds[((size_t)t * 4 + i) * D + d];
 }
 
+// u += o, or u += s * tanh(o) for a squashed policy output (extended kernels):
+// bounded commands, a normalised action a = tanh(o) scaled by s per component
+template <bool EXT>
+__device__ __forceinline__ void add_policy_output(const RollArgs& a, const float* o, float* u) {
+    if constexpr (EXT) {
+        if (a.squash) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) u[i] += a.act_s[i] * tanhf(o[i]);
+            return;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] += o[i];
+}
+
+// adjoint of the policy output from the adjoint ub of the applied command
+template <bool EXT>
+__device__ __forceinline__ void policy_output_vjp(const RollArgs& a, const float* o, const float* ub, float* ob) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ob[i] = ub[i];
+    if constexpr (EXT) {
+        if (a.squash) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float th = tanhf(o[i]);
+                ob[i] = ub[i] * a.act_s[i] * (1.f - th * th);
+            }
+        }
+    }
+}
+
 // applied command u = ubar + G e, e = x[0:13] - x_ref(t); returns e in ev
-template <int MODEL>
-__device__ __forceinline__ void feedback(const RollArgs& a, const float* G, const float* x, int t, const float* off,
+template <int MODEL, bool SH>
+__device__ __forceinline__ void feedback(const RollArgs& a, const float* G, const float* x, int t, const RefLane& off,
                                          float f_hover, const float* ubar, float* u, float* ev) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) u[i] = ubar[i];
     if (G) {
         float xr[13];
-        ref_state<MODEL>(a, t, off, f_hover, xr);
+        ref_state<MODEL, SH>(a, t, off, f_hover, xr);
 #pragma unroll
         for (int j = 0; j < 13; ++j) ev[j] = x[j] - xr[j];
+        float o[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             float s = 0.f;
 #pragma unroll
             for (int j = 0; j < 13; ++j) s += G[i * 13 + j] * ev[j];
-            u[i] += s;
+            o[i] = s;
         }
+        add_policy_output<SH>(a, o, u);
     }
 }
 
@@ -156,22 +249,23 @@ __device__ __forceinline__ void mlp_vjp(const MlpView& m, const float* d3, float
 // applied command through the MLP policy: u = ubar + o(e), e = x[0:13] - x_ref(t)
 template <int MODEL>
 __device__ __forceinline__ void feedback_mlp(const RollArgs& a, const MlpView& m, const float* x, int t,
-                                             const float* off, float f_hover, const float* ubar, float* u,
+                                             const RefLane& off, float f_hover, const float* ubar, float* u,
                                              float* ev, float* hc, int ws) {
     float xr[13], o[4];
-    ref_state<MODEL>(a, t, off, f_hover, xr);
+    ref_state<MODEL, true>(a, t, off, f_hover, xr);
 #pragma unroll
     for (int j = 0; j < 13; ++j) ev[j] = x[j] - xr[j];
     mlp_forward(m, ev, hc, ws, o);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) u[i] = ubar[i] + o[i];
+    for (int i = 0; i < 4; ++i) u[i] = ubar[i];
+    add_policy_output<true>(a, o, u);
 }
 
 // the applied command of step t: linear feedback through G, or (extended kernels,
 // mlp_H > 0) the MLP policy whose weights G points to
 template <int MODEL, bool EXT>
 __device__ __forceinline__ void apply_feedback(const RollArgs& a, const float* G, float* hc, int ws, const float* x,
-                                               int t, const float* off, float f_hover, const float* ubar, float* u,
+                                               int t, const RefLane& off, float f_hover, const float* ubar, float* u,
                                                float* ev) {
     if constexpr (EXT) {
         if (a.mlp_H > 0) {
@@ -179,7 +273,7 @@ __device__ __forceinline__ void apply_feedback(const RollArgs& a, const float* G
             return;
         }
     }
-    feedback<MODEL>(a, G, x, t, off, f_hover, ubar, u, ev);
+    feedback<MODEL, EXT>(a, G, x, t, off, f_hover, ubar, u, ev);
 }
 
 template <int MODEL, int CTRL>
@@ -345,11 +439,7 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
     to_dev<MODEL>(x, p);
 #pragma unroll
     for (int i = 0; i < S; ++i) comp[i] = 0.f;
-    float off[3] = {0.f, 0.f, 0.f};
-    if (a.has_obj && a.ref_off) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) off[j] = a.ref_off[j * D + d];
-    }
+    const RefLane off = ref_lane<EXT>(a, D, d);
     if (a.ckpt) store_state<MODEL, S>(a.ckpt, D, d, x, p);
     if (a.traj) store_state<MODEL, S>(a.traj, D, d, x, p);
     float loss = 0.f;
@@ -387,7 +477,7 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
         }
         if (a.has_obj) {
             float pr[3];
-            ref_pos(a, t + 1, off, pr);
+            ref_pos<EXT>(a, t + 1, off, pr);
             const float e0 = x[0] - pr[0], e1 = x[1] - pr[1], e2 = x[2] - pr[2];
             const float d2 = e0 * e0 + e1 * e1 + e2 * e2;
             if (rew) {
@@ -419,7 +509,7 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
 // else slot tb - t0 of the current segment) under the command applied there.
 template <int MODEL, int CTRL, int S>
 __device__ __forceinline__ void block_commands(const RollArgs& a, const DroneParams& p, const float* G, float* hc,
-                                               int ws, const float* off, float f_hover, size_t D, size_t d,
+                                               int ws, const RefLane& off, float f_hover, size_t D, size_t d,
                                                size_t SD, int tb, int t0, float* rc) {
     float xs[S], ubs[4], us[4], evs[13], cs[8];
     if (tb % a.K == 0) {
@@ -444,11 +534,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
     DroneParams p;
     load_params<MODEL, CTRL, AERO>(rec, p);
     const float f_hover = (MODEL == MODEL_ID) ? p.id.f_hover : 0.f;
-    float off[3] = {0.f, 0.f, 0.f};
-    if (a.has_obj && a.ref_off) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) off[j] = a.ref_off[j * D + d];
-    }
+    const RefLane off = ref_lane<EXT>(a, D, d);
     const float seed = a.dloss ? a.dloss[d] : 1.f;
     const float two_seed = 2.f * seed;
     float lam[S];
@@ -540,7 +626,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
             }
             if (a.has_obj) {
                 float pr[3];
-                ref_pos(a, t + 1, off, pr);
+                ref_pos<EXT>(a, t + 1, off, pr);
                 if (rew) {
                     // -exp(-2 |e|) and w_tilt tilt at x_{t+1}: a recomputed slot, the
                     // next checkpoint, or the last segment's final state (extra slot)
@@ -616,11 +702,12 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
                 // VJP into x_t, and the step's record for the weight gradient
                 const MlpView m(G, a.mlp_H);
                 const int H = a.mlp_H;
-                float o[4], eb[13];
+                float o[4], ob[4], eb[13];
                 mlp_forward(m, ev, gl, gs, o);
+                policy_output_vjp<EXT>(a, o, ub, ob);
 #pragma unroll
                 for (int j = 0; j < 13; ++j) eb[j] = 0.f;
-                mlp_vjp(m, ub, gl, gs, eb);
+                mlp_vjp(m, ob, gl, gs, eb);
 #pragma unroll
                 for (int j = 0; j < 13; ++j) xb[j] += eb[j];
                 if (a.mlp_rec) {
@@ -634,20 +721,36 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
                         a.mlp_rec[(13 + 3 * H + k) * TD + base] = gl[(2 * H + k) * gs];  // dz2
                     }
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) a.mlp_rec[(13 + 4 * H + i) * TD + base] = ub[i];
+                    for (int i = 0; i < 4; ++i) a.mlp_rec[(13 + 4 * H + i) * TD + base] = ob[i];
                 }
             } else if (G) {
+                float ob[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ob[i] = ub[i];
+                if constexpr (EXT) {
+                    if (a.squash) {
+                        float o[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            float s2 = 0.f;
+#pragma unroll
+                            for (int j = 0; j < 13; ++j) s2 += G[i * 13 + j] * ev[j];
+                            o[i] = s2;
+                        }
+                        policy_output_vjp<EXT>(a, o, ub, ob);
+                    }
+                }
 #pragma unroll
                 for (int j = 0; j < 13; ++j) {
                     float s2 = 0.f;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) s2 += G[i * 13 + j] * ub[i];
+                    for (int i = 0; i < 4; ++i) s2 += G[i * 13 + j] * ob[i];
                     xb[j] += s2;
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
 #pragma unroll
-                    for (int j = 0; j < 13; ++j) gl[(i * 13 + j) * gs] += ub[i] * ev[j];
+                    for (int j = 0; j < 13; ++j) gl[(i * 13 + j) * gs] += ob[i] * ev[j];
                 }
             }
 #pragma unroll
@@ -838,7 +941,7 @@ template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO>
 static hipError_t launch_roll_t(const KernelSel& ks, const RollArgs& a, const int4* tiles, int n_tiles,
                                 hipStream_t s) {
     constexpr bool CAN_MR = MODELS != MS_ID && CTRL != CTRL_ROTOR;
-    if ((CAN_MR && a.ctrl_every > 1) || (a.has_obj && a.obj_kind == 1) || a.mlp_H > 0)
+    if ((CAN_MR && a.ctrl_every > 1) || (a.has_obj && (a.obj_kind == 1 || a.ref_shift || a.squash)) || a.mlp_H > 0)
         return launch_roll_k<BWD, MODELS, CTRL, INTEG, AERO, true>(ks, a, tiles, n_tiles, s);
     return launch_roll_k<BWD, MODELS, CTRL, INTEG, AERO, false>(ks, a, tiles, n_tiles, s);
 }

@@ -26,7 +26,9 @@ def _mlp(w, hidden, seed, out_scale=0.02):
 def _obj(w):
     return B.Sim.objective(gain=dev(w.gain), ref_amp=w.ref_amp, ref_period=w.ref_period,
                            ref_offset=None if w.ref_offset is None else dev(w.ref_offset), w_u=w.w_u,
-                           reward=w.reward, policy_hidden=w.policy_hidden)
+                           reward=w.reward, policy_hidden=w.policy_hidden, ref_step0=w.ref_step0,
+                           ref_time_shift=None if w.ref_time_shift is None else dev(w.ref_time_shift),
+                           policy_scale=w.policy_scale)
 
 
 def _grads(sim, w, K, noalloc=False):

@@ -4,6 +4,7 @@ symmetries, and central finite differences for its gradients.
 
 Each test names the part of the oracle a plausible mistake would break.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -1291,3 +1292,117 @@ def test_reference_time_offset_equals_the_shifted_table():
         c = O.rollout(b, O.t64(w.x0), O.t64(w.cmds), w.steps, ref_table=table, **kw)
     assert torch.allclose(a["loss"], c["loss"], rtol=1e-12, atol=0)
     assert torch.allclose(a["x"], c["x"], rtol=1e-12, atol=1e-15)
+
+
+def test_reference_time_shift_equals_per_drone_start_steps():
+    """A per-drone time shift of k_d steps equals following the figure-eight from
+    step k_d (dt a power of two, so k dt is exact in both forms), drone by drone,
+    with the linear feedback, per-drone offsets and both objectives."""
+    w = W.config4(seed=44, n_worlds=5, steps=30, dt=2.0 ** -9)
+    ks = np.array([0, 3, 250, 1024, 4095])
+    w.ref_offset = W._f32(np.random.Generator(np.random.Philox(44)).normal(0.0, 0.3, size=(3, 5)))
+    w.ref_time_shift = (ks * w.dt).astype(np.float32)
+    assert np.array_equal(w.ref_time_shift.astype(np.float64), ks * w.dt)
+    for reward in (None, W.BPTT_REWARD):
+        w.reward = reward
+        both = O.rollout_workload(w)
+        for d, k in enumerate(ks):
+            one = W.subset(w, [d])
+            one.ref_time_shift = None
+            one.ref_step0 = int(k)
+            r = O.rollout_workload(one)
+            assert torch.allclose(both["loss"][d:d + 1], r["loss"], rtol=1e-13, atol=1e-13), (reward, d)
+            assert torch.allclose(both["x"][:, d:d + 1], r["x"], rtol=1e-13, atol=1e-13), (reward, d)
+
+
+def test_reference_time_shift_of_one_period_is_no_shift():
+    w = W.config4(seed=45, n_worlds=3, steps=40)
+    base = O.rollout_workload(w)
+    w.ref_time_shift = np.full(3, w.ref_period, np.float32)
+    r = O.rollout_workload(w)
+    assert torch.allclose(base["loss"], r["loss"], rtol=1e-10, atol=0)
+    assert torch.allclose(base["x"], r["x"], rtol=1e-10, atol=1e-12)
+
+
+def test_bptt_tracking_starts_on_the_reference():
+    """The BPTT setup's starts: position and velocity equal the figure-eight at each
+    drone's time shift (closed form), hover thrust, level attitude."""
+    w = W.bptt_tracking(n_envs=8, period=10.0)
+    s = w.ref_time_shift.astype(np.float64)
+    assert np.allclose(s, np.arange(8) * 10.0 / 8)
+    w0 = 2 * math.pi / 10.0
+    assert np.allclose(w.x0[0], np.sin(w0 * s), atol=1e-6)
+    assert np.allclose(w.x0[1], 0.5 * np.sin(2 * w0 * s), atol=1e-6)
+    assert np.allclose(w.x0[6], w0 * np.cos(w0 * s), atol=1e-6)
+    assert np.allclose(w.x0[7], w0 * np.cos(2 * w0 * s), atol=1e-6)
+    assert np.all(w.x0[[2, 3, 4, 5, 8, 9, 10, 11]] == 0)
+    assert np.allclose(w.x0[12], W.MASS * W.GRAVITY / W.ID_CF)
+    # hover thrust and a zero policy: no acceleration, so after one step the error
+    # is the reference's own curvature, |a_ref| dt^2 / 2 <= sqrt(5) A w^2 dt^2 / 2
+    r = O.rollout_workload(dataclasses.replace(w, steps=1, reward=None, w_u=0.0))
+    bound = 0.5 * math.sqrt(5.0) * w0 ** 2 * w.dt ** 2
+    assert float(r["loss"].max()) <= (1.01 * bound) ** 2
+    assert float(r["loss"].max()) > (0.5 * bound) ** 2
+
+
+def _squash_case(scale, gain_mult=1.0, steps=20, hidden=0):
+    w = W.config4(seed=46, n_worlds=6, steps=steps)
+    if hidden:
+        w = W.config4_mlp(seed=46, n_worlds=6, steps=steps, hidden=hidden, out_scale=0.3)
+    w.gain = W._f32(w.gain * gain_mult)
+    w.policy_scale = None if scale is None else W._f32(scale)
+    return w
+
+
+def test_squashed_policy_small_output_limit_is_the_scaled_linear_policy():
+    """s tanh(o) = s o - s o^3 / 3 + ...: with the gain shrunk by eps the squashed
+    rollout and the unsquashed rollout with gain diag(s) G differ at third order in
+    eps (halving eps divides the gap by 8)."""
+    s = np.array([0.5, 0.4, 0.3, 0.2])
+    gaps = []
+    for eps in (0.1, 0.05, 0.025):
+        w1 = _squash_case(s, gain_mult=eps * 20.0)
+        w2 = _squash_case(None, gain_mult=eps * 20.0)
+        w2.gain = w1.gain.astype(np.float64) * s[None, :, None]   # exact, not rounded to binary32
+        a, b = O.rollout_workload(w1), O.rollout_workload(w2)
+        base = O.rollout_workload(_squash_case(None, gain_mult=0.0))
+        gaps.append(float((a["loss"] - b["loss"]).abs().max()))
+        assert float((a["loss"] - base["loss"]).abs().max()) > 100 * gaps[-1]
+    assert 7.0 < gaps[0] / gaps[1] < 9.0 and 7.5 < gaps[1] / gaps[2] < 8.5, gaps
+
+
+def test_squashed_policy_saturates_at_the_range():
+    """A huge gain saturates tanh: the first applied command is ubar + s sign(G e),
+    i.e. one step equals the plain step under that command."""
+    s = np.array([0.3, 0.2, 0.1, 0.05])
+    w = _squash_case(s, gain_mult=1e7, steps=1)
+    b = O.Batch.from_workload(w)
+    x0 = O.t64(w.x0)
+    p, v = b.figure_eight(0.0, w.ref_amp, w.ref_period, None)
+    e = x0[0:13] - b.reference_state(p, v)
+    o = (O.t64(w.gain)[0][None] * e.T[:, None, :]).sum(2).T
+    assert float(o.abs().min()) > 40.0        # tanh(40) is 1 in binary64
+    u = O.t64(w.cmds[0]) + O.t64(w.policy_scale)[:, None] * torch.sign(o)
+    r = O.rollout_workload(w)
+    x1, _ = b.step_at(x0, u, 0, None)
+    assert torch.allclose(r["x"], x1, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("hidden", [0, 6])
+def test_squashed_policy_gradients_match_central_differences(hidden):
+    w = _squash_case(np.array([0.5, 0.5, 0.5, 0.2]), steps=15, hidden=hidden, gain_mult=1.0 if hidden else 30.0)
+    w.reward = W.BPTT_REWARD
+    w = _tilted(w, 47 + hidden)
+    g = O.rollout_workload(w, with_grad=True)
+    rng = np.random.Generator(np.random.Philox(47))
+    for key, arr in (("g_gain", "gain"), ("g_cmds", "cmds"), ("g_x0", "x0")):
+        base = getattr(w, arr).astype(np.float64)
+        dirn = rng.normal(size=base.shape)
+        h = 1e-6
+        vals = []
+        for sgn in (1, -1):
+            wp = dataclasses.replace(w, **{arr: base + sgn * h * dirn})
+            vals.append(float((O.rollout_workload(wp)["loss"] * O.t64(w.dloss)).sum()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = float((g[key] * O.t64(dirn)).sum())
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (key, fd, an)

@@ -98,6 +98,8 @@ class Workload:
     reward: Optional[dict] = None         # BPTT reward weights (w_tilt, w_act[4], w_dact[4]) or None
     policy_hidden: int = 0                # > 0: `gain` holds [G, P] small-MLP policies of this width
     ref_step0: int = 0                    # the figure-eight is followed from t = ref_step0 dt
+    ref_time_shift: Optional[np.ndarray] = None   # float32 [D]: drone d follows it at t + shift_d
+    policy_scale: Optional[np.ndarray] = None     # float32 [4]: policy output o enters as s * tanh(o)
 
     @property
     def n_drones_total(self) -> int:
@@ -532,6 +534,7 @@ def subset(w: Workload, worlds) -> Workload:
         x0=np.ascontiguousarray(w.x0[:, cols]), cmds=np.ascontiguousarray(cmds),
         gain_index=None if w.gain_index is None else w.gain_index[worlds].copy(),
         ref_offset=None if w.ref_offset is None else np.ascontiguousarray(w.ref_offset[:, cols]),
+        ref_time_shift=None if w.ref_time_shift is None else w.ref_time_shift[cols].copy(),
         dloss=None if w.dloss is None else w.dloss[cols].copy())
 
 
@@ -584,6 +587,48 @@ def config4_mlp(seed: int = 1012, n_worlds: int = 1024, steps: int = 500, hidden
     rng = _rng(seed + 104729)
     return dataclasses.replace(w, name="id_rollout_grad_mlp", gain=mlp_policy_params(rng, 1, hidden, out_scale),
                                policy_hidden=int(hidden))
+
+
+# command ranges of the normalised BPTT actions: +-0.5 rad on the attitude
+# commands, +-0.9 of the hover thrust on the thrust command
+BPTT_ACTION_RANGE = (0.5, 0.5, 0.5, 0.9 * MASS * GRAVITY / ID_CF)
+
+
+def bptt_tracking(n_envs: int = 16, steps: int = 40, dt: float = 0.02, period: float = 10.0,
+                  amp: float = 1.0, hidden: int = 0, seed: int = 1013, out_scale: float = 0.01) -> Workload:
+    """The BPTT tracking setup shaped after the paper's (Methods, "Backpropagation
+    Through Time"): ``n_envs`` identified-model drones with nominal parameters,
+    start times spread evenly over one period of a figure-eight of period
+    ``period`` (a 10 s closed trajectory), each drone starting exactly on the
+    reference with its velocity and the hover thrust, no randomisation; per-step
+    commands = the hover command, to which the policy adds its normalised action
+    a = tanh(o) in [-1, 1] times BPTT_ACTION_RANGE; the paper's reward weights,
+    which act on the normalised actions (so the raw-command weights are divided
+    by the squared ranges). ``hidden`` = 0 gives a zero linear gain, > 0 a
+    small-MLP policy drawn from ``seed``. Attitude commands at 1 / dt = 50 Hz."""
+    M = D = n_envs
+    P = empty_params(M)
+    fill_id_model(P, np.arange(M), np.tile(ID_GAIN, (M, 1)), np.tile(ID_TAU, (M, 1)))
+    shift = _f32(np.arange(D) * (period / D))
+    s = shift.astype(np.float64)
+    w0 = 2 * math.pi / period
+    x0 = _id_x0(D, np.stack([amp * np.sin(w0 * s), 0.5 * amp * np.sin(2 * w0 * s), np.zeros(D)]))
+    x0[6:9] = np.stack([amp * w0 * np.cos(w0 * s), amp * w0 * np.cos(2 * w0 * s), np.zeros(D)])
+    ubar = np.zeros((steps, 4, D))
+    ubar[:, 3] = MASS * GRAVITY / ID_CF
+    if hidden:
+        gain = mlp_policy_params(_rng(seed), 1, hidden, out_scale)
+    else:
+        gain = np.zeros((1, 4, 13))
+    span = _f32(BPTT_ACTION_RANGE).astype(np.float64)
+    reward = {"w_tilt": BPTT_REWARD["w_tilt"],
+              "w_act": [float(np.float32(v / span[i] ** 2)) for i, v in enumerate(BPTT_REWARD["w_act"])],
+              "w_dact": [float(np.float32(v / span[i] ** 2)) for i, v in enumerate(BPTT_REWARD["w_dact"])]}
+    return Workload("id_bptt_tracking", M, np.ones(M, np.int32), np.full(M, MODEL_ID, np.uint8), CTRL_ATT_PID,
+                    INTEG_RK4, float(np.float32(dt)), 1, _finish_params(P), _f32(x0), steps, _f32(ubar),
+                    gain=_f32(gain), gain_index=None, ref_amp=amp, ref_period=period, ref_offset=None, w_u=0.0,
+                    dloss=np.ones(D, np.float32), reward=reward, policy_hidden=int(hidden),
+                    ref_time_shift=shift, policy_scale=_f32(BPTT_ACTION_RANGE))
 
 
 def small(cfg: int, seed: int) -> Workload:
