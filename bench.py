@@ -260,7 +260,9 @@ def main():
                 wq_best = (cap, med)
     for h_ in (sim, simO, simT):
         h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"], wq_best[0])
-    # standalone phases (nothing else on the GPU), HIP events on the same streams
+    # standalone phases (nothing else on the GPU), HIP events on the same streams;
+    # the held steps alone run with every work-queue wave that fits (the cap only
+    # serves the overlap)
     standalone = {"adjoint_fwd_bwd": float("nan"), "forward": float("nan")}
     standalone_launch_ms = {"first_principles": [float("nan")], "identified": []}
     if not args.no_standalone:
@@ -269,6 +271,8 @@ def main():
         a.record()
         adjoint(K, ckpt)
         b.record()
+        for h_ in (sim, simT):
+            h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"], 0)
         sim.step_k(state, cmd, T)
         c = ev()
         c.record()
@@ -278,6 +282,8 @@ def main():
         torch.cuda.synchronize()
         standalone_launch_ms = {"first_principles": simT.launch_times(0),
                                 "identified": simT.launch_times(1) if cfg["per_model_launches"] else []}
+        for h_ in (sim, simT):
+            h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"], wq_best[0])
 
     for _ in range(args.warmup):
         one_step()

@@ -563,11 +563,13 @@ cf_status cf_create(const cf_desc* d, cf_handle** out) {
     for (int w = 0; w < h->M; ++w) {
         const float* r = d->params + (size_t)w * CF_NPARAM;
         // the kernel variants with the full first-principles terms: rotor inertia,
-        // drag, or a rotor law beyond W' = c_v (W_cmd - W)
+        // drag, a rotor law beyond W' = c_v (W_cmd - W), or a drag-torque
+        // polynomial that is not the thrust polynomial scaled
+        double kap = 0.0;
         if (r[CF_P_DRAG] != 0.f || r[CF_P_DRAG + 1] != 0.f || r[CF_P_DRAG + 2] != 0.f ||
             (models[w] == CF_MODEL_FP &&
              (r[CF_P_JP] != 0.f || r[CF_P_MOTOR_UP + 1] != 0.f || r[CF_P_MOTOR_DOWN + 1] != 0.f ||
-              r[CF_P_MOTOR_DOWN] != r[CF_P_MOTOR_UP])))
+              r[CF_P_MOTOR_DOWN] != r[CF_P_MOTOR_UP] || !cfh::torque_proportional(r, &kap))))
             h->aero = 1;
     }
     hipDeviceProp_t prop;

@@ -55,6 +55,22 @@ struct SoaRec {
     __device__ __forceinline__ float operator()(int i) const { return p[(size_t)i * M + w]; }
 };
 
+// The record with its base pointer hidden from the optimiser: loads through the
+// copy are issued where they are written (e.g. once per controller evaluation)
+// instead of being hoisted out of the step loop and held in registers across it.
+__device__ __forceinline__ AosRec laundered(AosRec r) {
+    asm volatile("" : "+s"(r.r));
+    return r;
+}
+__device__ __forceinline__ SoaRec laundered(SoaRec r) {
+    asm volatile("" : "+s"(r.p));
+    return r;
+}
+__device__ __forceinline__ ScalarRec laundered(ScalarRec r) {
+    asm volatile("" : "+s"(r.r));
+    return r;
+}
+
 struct FpParams {
     float inv_m, g;
     float iJx, iJy, iJz, dJx, dJy, dJz;  // dJx = Jz - Jy, dJy = Jx - Jz, dJz = Jy - Jx
@@ -67,6 +83,10 @@ struct FpParams {
     // rotor law with distinct acceleration / deceleration coefficients or a
     // quadratic term; otherwise W' = c_v (W_cmd - W) on both branches
     bool rotor_general;
+    // drag torque = kappa * thrust for every rotor: the yaw torque is formed from
+    // the thrust differences with coefficients tzk = kappa * yaw mixing
+    bool tprop;
+    float tzk[4];
     // Inside the kernels the four rotor rows hold W - W_r, the deviation from a
     // reference speed W_r (the world's hover speed), and rotor commands are
     // deviations too: near 15 000 an FP32 speed resolves 1e-3, its deviation
@@ -118,6 +138,7 @@ __device__ __forceinline__ FpParams load_fp(const R& rec) {
         P.cdu = rec(P_MOTOR_UP + 1);
         P.cvd = rec(P_MOTOR_DOWN); P.cdd = rec(P_MOTOR_DOWN + 1);
         P.rotor_general = (P.cdu != 0.f) || (P.cdd != 0.f) || (P.cvd != P.cvu);
+        P.tprop = rec(D_TPROP) != 0.f;
         P.jp = rec(P_JP);
 #pragma unroll
         for (int i = 0; i < 4; ++i) P.sg[i] = rec(D_SG + i);
@@ -137,7 +158,10 @@ __device__ __forceinline__ FpParams load_fp(const R& rec) {
         P.sgr = 0.f;
         P.cdu = 0.f; P.cvd = P.cvu; P.cdd = 0.f;
         P.rotor_general = false;
+        P.tprop = true;
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) P.tzk[i] = rec(D_TZK + i);
     P.wr = rec(D_WR);
     P.w2 = rec(D_W2);
     P.k1w = rec(D_K1W);
@@ -374,11 +398,15 @@ __device__ __forceinline__ void fp_rates(const float* x, const float* rc, const 
             xd[13 + i] = P.cvu * e;
         }
         const float df = r * (P.k1w + P.k2 * r);           // f(W) - f(W_r)
-        const float dq = r * (P.t1w + P.t2 * r);
         F += df;
         tx += P.tx[i] * df;
         ty += P.ty[i] * df;
-        tz += P.tz[i] * dq;
+        if (P.tprop) {
+            tz += P.tzk[i] * df;
+        } else {
+            const float dq = r * (P.t1w + P.t2 * r);
+            tz += P.tz[i] * dq;
+        }
     }
     xd[0] = x[7]; xd[1] = x[8]; xd[2] = x[9];
     xd[3] = 0.5f * (qw * wx + qy * wz - qz * wy);
@@ -467,13 +495,14 @@ __device__ __forceinline__ void fp_rates_vjp(const float* x, const float* rc, co
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float r = x[13 + i];
-        const float fb = Fb + P.tx[i] * hx + P.ty[i] * hy;
-        const float tqb = P.tz[i] * hz;
+        const float fb = Fb + P.tx[i] * hx + P.ty[i] * hy + (P.tprop ? P.tzk[i] * hz : 0.f);
+        const float tqb = P.tprop ? 0.f : P.tz[i] * hz;
         // adjoint of the rotor acceleration: the state derivative, plus the reaction torque
         const float gr = gb[13 + i] - (P.gyro ? P.jp * P.sg[i] * hz : 0.f);
         if (P.gyro) xb[13 + i] += P.sg[i] * om_sb;
         // df/dW = k1 + 2 k2 W = k1w + 2 k2 r, d(W^2)/dW = 2 W = w2 + 2 r
-        xb[13 + i] += fb * (P.k1w + 2.f * P.k2 * r) + tqb * (P.t1w + 2.f * P.t2 * r);
+        xb[13 + i] += fb * (P.k1w + 2.f * P.k2 * r);
+        if (!P.tprop) xb[13 + i] += tqb * (P.t1w + 2.f * P.t2 * r);
         if (P.rotor_general) {
             const bool up = rc[i] - r >= 0.f;
             const float cv = up ? P.cvu : P.cvd;
@@ -815,9 +844,9 @@ __device__ __forceinline__ void integrate(float* x, float* c, float h, const Rat
     }
 }
 
-// rows with compensated updates: position, velocity, rotor speeds (first
-// principles); position, velocity (identified)
-constexpr uint32_t COMP_FP = 0x7u | (0x7u << 7) | (0xFu << 13);
+// rows with compensated updates: position, velocity (both models; the rotor
+// rows hold deviations from the reference speed, whose increments are not lost)
+constexpr uint32_t COMP_FP = 0x7u | (0x7u << 7);
 constexpr uint32_t COMP_ID = 0x7u | (0x7u << 6);
 constexpr uint32_t COMP_NONE = 0u;
 
@@ -935,6 +964,31 @@ __device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, c
         const float inv = rsqrt_hw(n2);
         x[3] *= inv; x[4] *= inv; x[5] *= inv; x[6] *= inv;
     }
+}
+
+// Moves the Euler-angle base to the angles a: sin and cos at a by the angle
+// addition from the current base (a is one step away, so the offset is small;
+// beyond 1/16 rad sincos3 takes over). Chained over a few steps the rounding
+// of the recurrence grows by about one ulp per step, so callers re-anchor with
+// euler_base periodically.
+__device__ __forceinline__ void euler_rebase(const float* a, EulerBase& b) {
+    float s[3], c[3];
+    sincos3_near(a, b, s, c);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        b.a0[i] = a[i];
+        b.s0[i] = s[i];
+        b.c0[i] = c[i];
+    }
+}
+
+// identified-model step with the Euler-angle trigonometry of the step's start
+// state given in B
+template <int INTEG>
+__device__ __forceinline__ void id_step_base(float* x, float* comp, const float* u, const IdParams& P, float dt,
+                                             const EulerBase& B) {
+    integrate<S_ID, INTEG, COMP_ID>(x, comp, dt, [&](const float* xi, float* xd) { id_rates(xi, u, P, B, xd); });
+    if (P.direct) x[12] = u[3];  // the thrust row holds the applied thrust
 }
 
 template <int INTEG>

@@ -70,6 +70,22 @@ cf_status validate_desc(const cf_desc* d, std::vector<int32_t>& counts, std::vec
 // the reference-speed terms (the hover speed W_r on the thrust curve, thrust,
 // drag torque and slopes there) in double from the binary32 W_r the kernels use
 // to convert rotor speeds, rounded once.
+bool torque_proportional(const float* r, double* kappa) {
+    const double k0 = r[P_THRUST], k1 = r[P_THRUST + 1], k2 = r[P_THRUST + 2];
+    const double t0 = r[P_TORQUE], t1 = r[P_TORQUE + 1], t2 = r[P_TORQUE + 2];
+    const double kk[3] = {k0, k1, k2}, tt[3] = {t0, t1, t2};
+    int j = 2;
+    while (j >= 0 && kk[j] == 0.0) --j;
+    if (j < 0) return false;
+    const double kap = tt[j] / kk[j];
+    for (int i = 0; i < 3; ++i) {
+        const double d = tt[i] - kap * kk[i];
+        if (!(std::fabs(d) <= 0x1p-20 * std::max(std::fabs(tt[i]), std::fabs(kap * kk[i])))) return false;
+    }
+    *kappa = kap;
+    return std::isfinite(kap);
+}
+
 void derive_record(const float* r, float* out) {
     std::memcpy(out, r, NPARAM * sizeof(float));
     std::fill(out + NPARAM, out + NREC, 0.f);
@@ -119,6 +135,11 @@ void derive_record(const float* r, float* out) {
     const float cf = r[P_CF];
     out[D_CF_M] = cf / m;
     out[D_F_HOVER] = m * r[P_GRAVITY] / cf;
+    double kap = 0.0;
+    if (torque_proportional(r, &kap)) {
+        out[D_TPROP] = 1.f;
+        for (int i = 0; i < 4; ++i) out[D_TZK + i] = (float)(kap * r[P_MIX_YAW + i]);
+    }
 }
 
 namespace {

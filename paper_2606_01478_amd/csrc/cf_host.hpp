@@ -28,6 +28,12 @@ cf_status validate_desc(const cf_desc* d, std::vector<int32_t>& counts, std::vec
 // thrust of the identified model).
 void derive_record(const float* r, float* out);
 
+// True when the rotor drag-torque polynomial is the thrust polynomial times one
+// constant kappa (t_j = kappa k_j for j = 0, 1, 2, to 2^-20 relative); *kappa
+// receives it. The reduced kernel variants then form the yaw torque from the
+// thrust differences (coefficients kappa * yaw mixing, D_TZK).
+bool torque_proportional(const float* r, double* kappa);
+
 // ---- uneven batches --------------------------------------------------------------
 
 struct Tile {

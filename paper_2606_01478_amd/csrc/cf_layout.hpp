@@ -23,7 +23,8 @@ enum : int {
 enum : int {
     D_INV_M = 96, D_IJ = 97, D_DJ = 100, D_INV_2K2 = 103, D_SG = 104, D_WR = 108, D_W2 = 109,
     D_K1W = 110, D_T1W = 111, D_FR = 112, D_F4R = 113, D_TXR = 114, D_TYR = 115, D_TZR = 116,
-    D_SGR = 117, D_DISC_R = 118, D_VTX = 119, D_CF_M = 120, D_F_HOVER = 121, NREC = 128
+    D_SGR = 117, D_DISC_R = 118, D_VTX = 119, D_CF_M = 120, D_F_HOVER = 121, D_TPROP = 122, D_TZK = 123,
+    NREC = 128
 };
 enum : int { MODEL_FP = 0, MODEL_ID = 1 };
 enum : int { CTRL_ROTOR = 0, CTRL_PID = 1, CTRL_TORQUE = 2, CTRL_POSITION = 3 };

@@ -365,10 +365,17 @@ template <int MODEL, int CTRL, bool AERO, class R>
 __device__ __forceinline__ void load_params(const R& rec, DroneParams& p) {
     if constexpr (MODEL == MODEL_FP) {
         p.fp = load_fp<AERO>(rec);
-        if constexpr (CTRL != CTRL_ROTOR) p.pid = load_pid(rec, CTRL == CTRL_POSITION);
     } else {
         p.id = load_id<AERO>(rec);
     }
+}
+
+// The onboard controller's gains, read right before each use (scalar loads of
+// the world's record through a pointer the optimiser cannot hoist) so that they
+// do not occupy registers through the integration and its reverse sweep.
+template <int MODEL, int CTRL, class R>
+__device__ __forceinline__ void controller_gains(const R& rec, DroneParams& p) {
+    if constexpr (MODEL == MODEL_FP && CTRL != CTRL_ROTOR) p.pid = load_pid(laundered(rec), CTRL == CTRL_POSITION);
 }
 
 // one step; rc holds the first-principles rotor commands across steps, the
@@ -471,6 +478,7 @@ __device__ __forceinline__ void rollout_fwd_drone(const R& rec, const RollArgs& 
         } else if (a.has_obj) {
             loss += a.w_u * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3]);
         }
+        controller_gains<MODEL, CTRL>(rec, p);
         model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a, rc, EXT ? phase == 0 : true);
         if constexpr (EXT) {
             if (++phase == a.ctrl_every) phase = 0;
@@ -582,12 +590,14 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
                 // a segment that starts inside a block (period longer than the
                 // checkpoint interval) starts with that block's held commands
                 if (t0 % n_c != 0)
+                    controller_gains<MODEL, CTRL>(rec, p);
                     block_commands<MODEL, CTRL, S>(a, p, G, gl, gs, off, f_hover, D, d, SD, t0 - t0 % n_c, t0, rcf);
             }
             for (int j = 0; j < n_re; ++j) {
                 float u[4], ev[13], ubar[4];
                 load_cmd(a, t0 + j, d, ubar);
                 apply_feedback<MODEL, EXT>(a, G, gl, gs, x, t0 + j, off, f_hover, ubar, u, ev);
+                controller_gains<MODEL, CTRL>(rec, p);
                 model_step<MODEL, CTRL, INTEG>(x, comp, u, p, a, rcf, (t0 + j) % n_c == 0);
                 if (j + 1 < t1 - t0 || rew) store_rows<S>(a.seg + (size_t)(j + 1) * SD, D, d, x);
             }
@@ -657,6 +667,7 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
                     held = true;
                     const int tb = t - t % n_c;
                     if (t == a.T - 1 || (t + 1) % n_c == 0)   // first visit of this block
+                        controller_gains<MODEL, CTRL>(rec, p);
                         block_commands<MODEL, CTRL, S>(a, p, G, gl, gs, off, f_hover, D, d, SD, tb, t0, rch);
                     fp_held_vjp<INTEG>(xc, rch, p.fp, a.dt, a.renorm, lam, xb, rcb);
                     if constexpr (S > S_FP) {
@@ -665,13 +676,17 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
                     }
                     if (t == tb) {
                         const float* csb = (S > S_FP) ? lam + S_FP : lam;   // PID state adjoint
+                        controller_gains<MODEL, CTRL>(rec, p);
                         fp_ctrl_vjp<CTRL>(xc, u, p.fp, p.pid, a.dtc, a.inv_dtc, rcb, csb, xb, ub);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) rcb[i] = 0.f;
                     }
                 }
             }
-            if (!held) model_step_vjp<MODEL, CTRL, INTEG>(xc, u, p, a, lam, xb, ub);
+            if (!held) {
+                controller_gains<MODEL, CTRL>(rec, p);
+                model_step_vjp<MODEL, CTRL, INTEG>(xc, u, p, a, lam, xb, ub);
+            }
             if (rew) {
                 // action terms: (u_t - u_hover)^2, (u_t - u_{t-1})^2 and, from the
                 // next step, (u_{t+1} - u_t)^2

@@ -15,8 +15,6 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
     if constexpr (MODEL == MODEL_FP) {
         constexpr int S = (CTRL == CTRL_PID) ? S_PID : S_FP;
         const FpParams P = load_fp<AERO>(rec);
-        PidParams C;
-        if constexpr (CTRL != CTRL_ROTOR) C = load_pid(rec, CTRL == CTRL_POSITION);
         float x[S], u[4], comp[S_FP];
 #pragma unroll
         for (int i = 0; i < S; ++i) x[i] = a.st[i * D + d];
@@ -28,7 +26,14 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
         float rc[4] = {0.f, 0.f, 0.f, 0.f};   // held rotor commands
         int phase = 0;                        // launches start on a controller step
         for (int k = 0; k < a.K; ++k) {
-            fp_step<CTRL, INTEG>(x, comp, u, P, C, a.dt, a.dtc, a.inv_dtc, a.renorm, rc, MR ? phase == 0 : true);
+            const bool ctrl_now = MR ? phase == 0 : true;
+            // the controller's gains are read where it runs (scalar loads of the
+            // world's record) rather than held in registers through the integration
+            PidParams C;
+            if constexpr (CTRL != CTRL_ROTOR) {
+                if (ctrl_now) C = load_pid(laundered(rec), CTRL == CTRL_POSITION);
+            }
+            fp_step<CTRL, INTEG>(x, comp, u, P, C, a.dt, a.dtc, a.inv_dtc, a.renorm, rc, ctrl_now);
             if constexpr (MR) {
                 if (++phase == a.ctrl_every) phase = 0;
             }
@@ -46,7 +51,14 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
         for (int i = 0; i < S_ID; ++i) { x[i] = a.st[i * D + d]; comp[i] = 0.f; }
 #pragma unroll
         for (int i = 0; i < 4; ++i) u[i] = a.cmd[i * D + d];
-        for (int k = 0; k < a.K; ++k) id_step<INTEG>(x, comp, u, P, a.dt);
+        // the start angles' sines and cosines: exact every 8th step, in between
+        // carried from the previous step by the angle addition
+        EulerBase B;
+        for (int k = 0; k < a.K; ++k) {
+            if ((k & 7) == 0) euler_base(x + 3, B);
+            else euler_rebase(x + 3, B);
+            id_step_base<INTEG>(x, comp, u, P, a.dt, B);
+        }
 #pragma unroll
         for (int i = 0; i < S_ID; ++i) {
             a.st[i * D + d] = x[i];
@@ -95,8 +107,8 @@ __global__ __launch_bounds__(256) void k_step_tile(StepArgs a, const int4* __res
 // Persistent work queue: each workgroup pops the next tile index from *counter
 // until the tiles run out; every workgroup exits after one failed pop.
 template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
-__global__ __launch_bounds__(256) void k_step_wq(StepArgs a, const int4* __restrict__ tiles, int n_tiles,
-                                                 unsigned* counter) {
+__device__ __forceinline__ void run_queue(const StepArgs& a, const int4* __restrict__ tiles, int n_tiles,
+                                          unsigned* counter) {
     __shared__ int s_next;
     for (;;) {
         if (threadIdx.x == 0) s_next = (int)atomicAdd(counter, 1u);
@@ -107,6 +119,13 @@ __global__ __launch_bounds__(256) void k_step_wq(StepArgs a, const int4* __restr
         run_tile<MODELS, CTRL, INTEG, AERO, MR>(a, tiles[t]);
     }
 }
+
+template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
+__global__ __launch_bounds__(256) void k_step_wq(StepArgs a, const int4* __restrict__ tiles, int n_tiles,
+                                                 unsigned* counter) {
+    run_queue<MODELS, CTRL, INTEG, AERO, MR>(a, tiles, n_tiles, counter);
+}
+
 
 template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
 static hipError_t launch_step_k(const KernelSel& ks, const StepArgs& a, const int4* tiles, int n_tiles,

@@ -128,6 +128,23 @@ static void test_derive_record() {
     cfh::derive_record(f.params.data() + CF_NPARAM, outi);
     CHECK(std::fabs(outi[cfk::D_F_HOVER] - 0.03f * 9.81f) <= 1e-6f);
     CHECK(outi[cfk::D_CF_M] == 1.f / 0.03f);
+    // drag torque proportional to thrust: flagged, yaw coefficients scaled by kappa
+    std::vector<float> r(f.params.begin(), f.params.begin() + CF_NPARAM);
+    for (int j = 0; j < 3; ++j) r[CF_P_TORQUE + j] = 0.006f * r[CF_P_THRUST + j];
+    double kap = 0.0;
+    CHECK(cfh::torque_proportional(r.data(), &kap));
+    CHECK(std::fabs(kap - 0.006) <= 1e-9);
+    cfh::derive_record(r.data(), out);
+    CHECK(out[cfk::D_TPROP] == 1.f);
+    for (int i = 0; i < 4; ++i) CHECK(out[cfk::D_TZK + i] == (float)(kap * r[CF_P_MIX_YAW + i]));
+    // a linear term in the torque only: not proportional
+    r[CF_P_TORQUE + 1] = 1e-9f;
+    CHECK(!cfh::torque_proportional(r.data(), &kap));
+    cfh::derive_record(r.data(), out);
+    CHECK(out[cfk::D_TPROP] == 0.f);
+    // no thrust curve at all: not proportional
+    for (int j = 0; j < 3; ++j) r[CF_P_THRUST + j] = 0.f;
+    CHECK(!cfh::torque_proportional(r.data(), &kap));
 }
 
 static void test_tile_list() {

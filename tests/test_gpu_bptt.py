@@ -1,7 +1,9 @@
 """The BPTT tracking setup on the GPU: per-drone reference time shifts (starts
 spread along the figure-eight), the reference time offset of chained rollouts,
 the squashed (normalised) policy output, each against the oracle's autograd, and
-a short training run through the library whose tracking error must fall."""
+a short training run through the library whose tracking error must fall; Adam
+on the feedback gain with the library's rollout and adjoint against the same
+Adam driven by the FP64 oracle's autograd gradients."""
 import dataclasses
 import math
 
@@ -13,7 +15,7 @@ import oracle as O
 import workloads as W
 from gpu_helpers import dev
 from paper_2606_01478_amd import binding as B
-from paper_2606_01478_amd.bptt import tracking_rms, train_policy
+from paper_2606_01478_amd.bptt import tracking_rms, train_linear_policy, train_policy
 from test_gpu_mlp import _grads
 from test_gpu_parity import _check_against_oracle, _sim
 
@@ -84,3 +86,55 @@ def test_bptt_training_lowers_tracking_error(gpu_lib):
     print(f"tracking RMS before {rms0:.4f} m, after {rms1:.4f} m")
     assert sim.last_error() == 0
     assert math.isfinite(rms1) and rms0 > 1.0 and rms1 < 0.1
+
+
+# ---- Adam through the library vs Adam on the oracle ---------------------------
+
+def _setup(seed=12):
+    w = W.small(4, seed=seed)
+    sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
+    kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u)
+    return w, sim, kw
+
+
+def test_adam_steps_match_oracle_driven_adam(gpu_lib):
+    w, sim, kw = _setup()
+    lr, iters = 1e-2, 3
+    out = train_linear_policy(sim, dev(w.x0), dev(w.cmds), w.steps, dev(w.gain), iters=iters, lr=lr,
+                              ckpt_every=10, obj_kw=kw)
+    torch.cuda.synchronize()
+    b = O.Batch.from_workload(w)
+    G = torch.tensor(w.gain, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([G], lr=lr)
+    ref_losses, g0 = [], None
+    for _ in range(iters):
+        opt.zero_grad()
+        r = O.rollout(b, O.t64(w.x0), O.t64(w.cmds), w.steps, gain=G, gain_index=w.gain_index, **kw)
+        total = r["loss"].sum()
+        total.backward()
+        g0 = G.grad.detach().clone() if g0 is None else g0
+        opt.step()
+        ref_losses.append(float(total.detach()))
+    got = out["gain"].double().cpu()
+    step_ref = G.detach() - torch.tensor(w.gain, dtype=torch.float64)
+    step_got = got - torch.tensor(w.gain, dtype=torch.float64)
+    # Adam normalises each coordinate's step, so a coordinate whose gradient is
+    # near zero may step either way; where the gradient is significant the
+    # device's gradients (within 1e-3) give the same updates to a small
+    # fraction of lr
+    sig = g0.abs() > 1e-3 * g0.abs().max()
+    assert sig.sum() > 10
+    err = torch.max(torch.abs(step_got - step_ref)[sig])
+    assert err <= 0.05 * lr, err
+    gl = out["losses"].double().cpu().numpy()
+    assert np.allclose(gl, ref_losses, rtol=1e-4, atol=0)
+
+
+def test_training_lowers_the_objective(gpu_lib):
+    w, sim, kw = _setup(seed=21)
+    out = train_linear_policy(sim, dev(w.x0), dev(w.cmds), w.steps, dev(w.gain), iters=40, lr=1e-2,
+                              ckpt_every=10, obj_kw=kw, train_commands=True)
+    torch.cuda.synchronize()
+    losses = out["losses"].cpu().numpy()
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.8 * losses[0], (losses[0], losses[-1])
