@@ -314,6 +314,13 @@ struct cf_handle {
     int n_tiles = 0;
     int n_tiles_fp = 0;  // tiles of first-principles worlds come first
     int tiles_for = 0;
+    // packed tiles of the held-step kernels (tiles span worlds of one model) and
+    // the drone list they index
+    int4* ptiles = nullptr;
+    int n_ptiles = 0;
+    int n_ptiles_fp = 0;
+    int ptiles_for = 0;
+    int32_t* plist = nullptr;
     unsigned* counters = nullptr;
     int n_counters = 0;
     // launch choice
@@ -415,26 +422,64 @@ hipError_t build_tiles(cf_handle* h, int tile) {
     return e;
 }
 
+hipError_t build_packed_tiles(cf_handle* h, int tile) {
+    if (h->ptiles && h->ptiles_for == tile) return hipSuccess;
+    int nfp = 0;
+    std::vector<int32_t> list;
+    const std::vector<cfh::PackedTile> v =
+        cfh::packed_tiles(h->counts, h->offsets, h->model_of_world, tile, &list, &nfp);
+    hipError_t e = hipSuccess;
+    if (!h->plist && !list.empty()) {
+        if ((e = dalloc(&h->plist, list.size())) != hipSuccess) return e;
+        if ((e = hipMemcpy(h->plist, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+            return e;
+    }
+    std::vector<int4> dv(v.size());
+    for (size_t i = 0; i < v.size(); ++i) dv[i] = make_int4(v[i].first, v[i].count, v[i].model, 0);
+    if (h->ptiles) hipFree(h->ptiles);
+    h->ptiles = nullptr;
+    h->n_ptiles = (int)dv.size();
+    h->n_ptiles_fp = nfp;
+    if ((e = dalloc(&h->ptiles, dv.size())) != hipSuccess) return e;
+    if (!dv.empty()) e = hipMemcpy(h->ptiles, dv.data(), dv.size() * sizeof(int4), hipMemcpyHostToDevice);
+    h->ptiles_for = tile;
+    return e;
+}
+
 void clear_graphs(cf_handle* h) {
     for (auto& kv : h->graphs) hipGraphExecDestroy(kv.second);
     h->graphs.clear();
 }
 
-// Runs fn(models, tiles, n_tiles, stream, slot) over the tile list: once for
-// all tiles (uniform-model handles, or a single mixed launch), or once per
-// model with the identified-model launch forked onto the auxiliary stream and
-// joined back with events (also valid while capturing a graph).
+// Runs fn(models, tiles, n_tiles, stream, slot) over a tile list whose
+// first-principles tiles come first: once for all tiles (uniform-model handles,
+// or a single mixed launch), or once per model with the identified-model launch
+// forked onto the auxiliary stream and joined back with events (also valid
+// while capturing a graph).
 template <class F>
-hipError_t per_model(cf_handle* h, hipStream_t s, int split, F&& fn) {
-    if (!(h->models == MS_BOTH && split)) return fn(h->models, h->tiles, h->n_tiles, s, 0);
+hipError_t per_model_on(cf_handle* h, hipStream_t s, int split, const int4* tiles, int n, int n_fp, F&& fn) {
+    if (!(h->models == MS_BOTH && split)) return fn(h->models, tiles, n, s, 0);
     hipError_t e;
-    const int n_fp = h->n_tiles_fp, n_id = h->n_tiles - h->n_tiles_fp;
+    const int n_id = n - n_fp;
     if ((e = hipEventRecord(h->ev_fork, s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(h->aux_stream, h->ev_fork, 0)) != hipSuccess) return e;
-    if (n_fp > 0 && (e = fn(MS_FP, h->tiles, n_fp, s, 0)) != hipSuccess) return e;
-    if (n_id > 0 && (e = fn(MS_ID, h->tiles + n_fp, n_id, h->aux_stream, 1)) != hipSuccess) return e;
+    if (n_fp > 0 && (e = fn(MS_FP, tiles, n_fp, s, 0)) != hipSuccess) return e;
+    if (n_id > 0 && (e = fn(MS_ID, tiles + n_fp, n_id, h->aux_stream, 1)) != hipSuccess) return e;
     if ((e = hipEventRecord(h->ev_join, h->aux_stream)) != hipSuccess) return e;
     return hipStreamWaitEvent(s, h->ev_join, 0);
+}
+
+// over the per-world tiles (rollouts)
+template <class F>
+hipError_t per_model(cf_handle* h, hipStream_t s, int split, F&& fn) {
+    return per_model_on(h, s, split, h->tiles, h->n_tiles, h->n_tiles_fp, fn);
+}
+
+// over the packed tiles (held steps)
+template <class F>
+hipError_t per_model_packed(cf_handle* h, hipStream_t s, int split, F&& fn) {
+    return per_model_on(h, s, split, h->ptiles, h->n_ptiles, h->n_ptiles_fp, fn);
 }
 
 KernelSel selection(const cf_handle* h, int mode, int tile) {
@@ -464,6 +509,7 @@ StepArgs step_args(const cf_handle* h, float* st, const float* cmd, int K, uint3
     a.renorm = h->renorm;
     a.K = K;
     a.nonfinite = (h->flags & CF_F_NONFINITE_CHECK) ? nf : nullptr;
+    a.plist = h->plist;
     return a;
 }
 
@@ -650,6 +696,8 @@ cf_status cf_destroy(cf_handle* h) {
     hipFree(h->d_offsets);
     hipFree(h->d_gidx);
     hipFree(h->tiles);
+    hipFree(h->ptiles);
+    hipFree(h->plist);
     hipFree(h->counters);
     hipFree(h->dflag);
     for (DevBuf* b : {&h->ref_tab, &h->seg, &h->ggc, &h->rec, &h->gpart, &h->loss_tmp})
@@ -795,13 +843,16 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
         h->timers[0].n = 0;
         h->timers[1].n = 0;
     }
+    // the packed tiles of the current tile size (built before any graph capture
+    // by cf_step_k, so this returns at once there)
+    if ((e = build_packed_tiles(h, h->tile)) != hipSuccess) return note(h, e);
     const int n = h->ctrl_every;  // k is a multiple of n: every launch starts on a controller step
     if (plain) {
         // one step per launch; with a slower onboard controller, one controller
         // period per launch (its held commands are not part of the state)
         const int mode = h->mode == LM_LANE ? LM_LANE : LM_TILE;
         const StepArgs a = step_args(h, state, cmd, n, nf);
-        e = per_model(h, s, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
+        e = per_model_packed(h, s, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
             KernelSel ks = selection(h, mode, h->tile);
             ks.models = models;
             hipError_t r = hipSuccess;
@@ -823,9 +874,11 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
                            0u);
         if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
     }
-    e = per_model(h, s, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int slot) {
+    e = per_model_packed(h, s, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int slot) {
         KernelSel ks = selection(h, h->use_wq ? LM_WQ : h->mode, h->tile);
         ks.models = models;
+        // uncapped (or capped at three or more waves): the three-wave variant
+        ks.wide = (h->wq_waves == 0 || h->wq_waves >= 3) ? 1 : 0;
         int blocks = 0;
         if (h->use_wq) {
             int per_cu = step_wq_blocks_per_cu(ks);
@@ -856,7 +909,7 @@ cf_status cf_step_k(cf_handle* h, float* state, const float* cmd, int32_t k, uin
         return CF_EINVAL;
     if (nf && check_dev(nf, (size_t)h->M * sizeof(uint32_t))) return CF_EINVAL;
     hipSetDevice(h->device);
-    hipError_t e = build_tiles(h, h->tile);
+    hipError_t e = build_packed_tiles(h, h->tile);
     if (e != hipSuccess) return note(h, e);
     const int plain = (h->flags & CF_F_PLAIN_KERNEL) ? 1 : 0;
     if (!(h->flags & CF_F_GRAPH)) return enqueue_steps(h, state, cmd, k, nf, h->stream, plain);

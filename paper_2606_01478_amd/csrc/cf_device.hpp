@@ -58,9 +58,12 @@ struct SoaRec {
 // The record with its base pointer hidden from the optimiser: loads through the
 // copy are issued where they are written (e.g. once per controller evaluation)
 // instead of being hoisted out of the step loop and held in registers across it.
-__device__ __forceinline__ AosRec laundered(AosRec r) {
+// A uniform record's copy reads through the constant address space (scalar
+// loads), since the pointer the optimiser cannot follow would otherwise take
+// generic vector loads.
+__device__ __forceinline__ ScalarRec laundered(AosRec r) {
     asm volatile("" : "+s"(r.r));
-    return r;
+    return ScalarRec{r.r};
 }
 __device__ __forceinline__ SoaRec laundered(SoaRec r) {
     asm volatile("" : "+s"(r.p));
@@ -68,6 +71,19 @@ __device__ __forceinline__ SoaRec laundered(SoaRec r) {
 }
 __device__ __forceinline__ ScalarRec laundered(ScalarRec r) {
     asm volatile("" : "+s"(r.r));
+    return r;
+}
+
+// a world record whose address differs across the lanes of a wave (a packed
+// tile across a world boundary): per-lane vector loads
+struct LaneRec {
+    const float* r;
+    __device__ __forceinline__ float operator()(int i) const {
+        return ((const __attribute__((address_space(1))) float*)r)[i];
+    }
+};
+__device__ __forceinline__ LaneRec laundered(LaneRec r) {
+    asm volatile("" : "+v"(r.r));
     return r;
 }
 

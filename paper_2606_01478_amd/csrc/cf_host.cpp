@@ -179,6 +179,29 @@ std::vector<Tile> tile_list(const std::vector<int32_t>& counts, const std::vecto
     return v;
 }
 
+std::vector<PackedTile> packed_tiles(const std::vector<int32_t>& counts, const std::vector<int64_t>& offsets,
+                                     const std::vector<uint8_t>& models, int tile, std::vector<int32_t>* list,
+                                     int* n_fp) {
+    std::vector<PackedTile> v;
+    list->clear();
+    int nfp = 0;
+    const int M = (int)counts.size();
+    for (int model : {(int)MODEL_FP, (int)MODEL_ID}) {
+        const int start = (int)list->size();
+        for (int w = 0; w < M; ++w) {
+            if (models[w] != model) continue;
+            for (int i = 0; i < counts[w]; ++i) list->push_back((int32_t)(offsets[w] + i));
+        }
+        const int n = (int)list->size() - start;
+        for (int s = 0; s < n; s += tile) {
+            v.push_back({start + s, std::min(tile, n - s), model});
+            nfp += (model == MODEL_FP);
+        }
+    }
+    if (n_fp) *n_fp = nfp;
+    return v;
+}
+
 bool cache_lookup(const std::string& path, const std::string& key, LaunchChoice* c) {
     FILE* f = std::fopen(path.c_str(), "r");
     if (!f) return false;

@@ -47,6 +47,19 @@ struct Tile {
 std::vector<Tile> tile_list(const std::vector<int32_t>& counts, const std::vector<int64_t>& offsets,
                             const std::vector<uint8_t>& models, int control, int tile, int* n_fp);
 
+// Packed tiles of the held-step kernels: the drones of each model listed world
+// after world (first-principles worlds first, worlds in index order, a world's
+// drones in order) in *list, cut into tiles of `tile` consecutive entries
+// {first entry, count, model}, so that every tile but each model's last is full
+// and a tile may span several worlds of its model. *n_fp receives the number of
+// first-principles tiles (they come first).
+struct PackedTile {
+    int first, count, model;
+};
+std::vector<PackedTile> packed_tiles(const std::vector<int32_t>& counts, const std::vector<int64_t>& offsets,
+                                     const std::vector<uint8_t>& models, int tile, std::vector<int32_t>* list,
+                                     int* n_fp);
+
 // ---- autotune cache ---------------------------------------------------------------
 
 struct LaunchChoice {

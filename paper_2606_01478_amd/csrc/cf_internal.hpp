@@ -10,9 +10,12 @@ enum : int { MS_FP = 1, MS_ID = 2, MS_BOTH = 3 };
 // how lanes are mapped to drones
 //   LM_LANE: lane = drone, world looked up per lane, parameters from the
 //            transposed [NREC][M] copy (worlds of a handful of drones);
-//   LM_TILE: one workgroup per tile {world, first drone, count, model}, all
-//            lanes of a tile share one world (parameters are uniform loads);
-//   LM_WQ:   persistent workgroups pop tiles from an atomic queue head.
+//   LM_TILE: one workgroup per tile. Rollouts take per-world tiles {world,
+//            first drone, count, model} (parameters are uniform loads); held
+//            steps take packed tiles {first list entry, count, model} of one
+//            model that may span worlds (a wave within one world reads its
+//            parameters with uniform loads, a wave across worlds per lane);
+//   LM_WQ:   persistent workgroups pop packed tiles from an atomic queue head.
 enum : int { LM_LANE = 0, LM_TILE = 1, LM_WQ = 2 };
 
 struct KernelSel {
@@ -22,6 +25,7 @@ struct KernelSel {
     int mode;    // LM_*
     int tile;    // lanes per workgroup (64, 128, 256)
     int aero;    // kernels with gyroscopic/reaction torques, drag and the general rotor law compiled in
+    int wide = 0;  // work queue: the variant held to three waves per SIMD where it exists
 };
 
 struct StepArgs {
@@ -38,6 +42,7 @@ struct StepArgs {
     int renorm;
     int K;                  // steps per launch
     uint32_t* nonfinite;    // [M] or null
+    const int32_t* plist;   // [D] drones in packed-tile order (tile kernels)
 };
 
 struct RollArgs {

@@ -68,17 +68,8 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
     if (a.nonfinite && bad) atomicOr(a.nonfinite + w, 1u);
 }
 
-template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
-__device__ __forceinline__ void run_tile(const StepArgs& a, int4 td) {
-    // td = {world, first drone, drone count, model}, uniform over the workgroup
-    const int w = __builtin_amdgcn_readfirstlane(td.x);
-    const int d0 = __builtin_amdgcn_readfirstlane(td.y);
-    const int cnt = __builtin_amdgcn_readfirstlane(td.z);
-    const int model = __builtin_amdgcn_readfirstlane(td.w);
-    const int lane = threadIdx.x;
-    if (lane >= cnt) return;
-    const AosRec rec{a.par_aos + (size_t)w * NREC};
-    const size_t d = (size_t)d0 + lane;
+template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR, class R>
+__device__ __forceinline__ void run_model(int model, const R& rec, const StepArgs& a, size_t d, int w) {
     if constexpr (MODELS == MS_FP) {
         run_held<MODEL_FP, CTRL, INTEG, AERO, MR>(rec, a, d, w);
     } else if constexpr (MODELS == MS_ID) {
@@ -86,6 +77,29 @@ __device__ __forceinline__ void run_tile(const StepArgs& a, int4 td) {
     } else {
         if (model == MODEL_FP) run_held<MODEL_FP, CTRL, INTEG, AERO, MR>(rec, a, d, w);
         else run_held<MODEL_ID, CTRL, INTEG, AERO, MR>(rec, a, d, w);
+    }
+}
+
+// A packed tile: `count` consecutive entries of the drone list from `first`, all
+// of one model, possibly of several worlds (every tile but each model's last is
+// full, so no lanes idle at world ends). A wave whose lanes share one world
+// reads that world's parameters with scalar loads into scalar registers; a wave
+// across a world boundary reads each lane's own with vector loads.
+template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
+__device__ __forceinline__ void run_tile(const StepArgs& a, int4 td) {
+    // td = {first list entry, drone count, model, 0}, uniform over the workgroup
+    const int first = __builtin_amdgcn_readfirstlane(td.x);
+    const int cnt = __builtin_amdgcn_readfirstlane(td.y);
+    const int model = __builtin_amdgcn_readfirstlane(td.z);
+    const int lane = threadIdx.x;
+    if (lane >= cnt) return;
+    const size_t d = (size_t)a.plist[first + lane];
+    const int w = a.drone_world[d];
+    const int w0 = __builtin_amdgcn_readfirstlane(w);
+    if (__builtin_amdgcn_ballot_w64(w != w0) == 0) {
+        run_model<MODELS, CTRL, INTEG, AERO, MR>(model, AosRec{a.par_aos + (size_t)w0 * NREC}, a, d, w0);
+    } else {
+        run_model<MODELS, CTRL, INTEG, AERO, MR>(model, LaneRec{a.par_aos + (size_t)w * NREC}, a, d, w);
     }
 }
 
@@ -126,6 +140,24 @@ __global__ __launch_bounds__(256) void k_step_wq(StepArgs a, const int4* __restr
     run_queue<MODELS, CTRL, INTEG, AERO, MR>(a, tiles, n_tiles, counter);
 }
 
+// The same queue held to three waves per SIMD (at most 168 registers), for when
+// nothing else needs the SIMDs' registers: for the first-principles model behind
+// the attitude controller the compiler otherwise takes about 200 registers and
+// leaves two waves, too few to hide the latency of the step's dependent
+// arithmetic. The few values it then keeps in scratch are per tile, outside the
+// step loop. Built for the single-model reduced variants only (the others would
+// spill inside the loop).
+template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_step_wq3(
+    StepArgs a, const int4* __restrict__ tiles, int n_tiles, unsigned* counter) {
+    run_queue<MODELS, CTRL, INTEG, AERO, MR>(a, tiles, n_tiles, counter);
+}
+
+template <int MODELS, bool AERO, bool MR>
+constexpr bool has_wq3() {
+    return MODELS != MS_BOTH && !AERO && !MR;
+}
+
 
 template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
 static hipError_t launch_step_k(const KernelSel& ks, const StepArgs& a, const int4* tiles, int n_tiles,
@@ -140,6 +172,13 @@ static hipError_t launch_step_k(const KernelSel& ks, const StepArgs& a, const in
     } else {
         // work-queue workgroups that do not fit at once start later, find the
         // queue empty and exit
+        if constexpr (has_wq3<MODELS, AERO, MR>()) {
+            if (ks.wide) {
+                hipLaunchKernelGGL((k_step_wq3<MODELS, CTRL, INTEG, AERO, MR>), dim3(wq_blocks), dim3(ks.tile), 0, s,
+                                   a, tiles, n_tiles, counter);
+                return hipGetLastError();
+            }
+        }
         hipLaunchKernelGGL((k_step_wq<MODELS, CTRL, INTEG, AERO, MR>), dim3(wq_blocks), dim3(ks.tile), 0, s, a, tiles,
                            n_tiles, counter);
     }
@@ -158,11 +197,20 @@ static hipError_t launch_step_t(const KernelSel& ks, const StepArgs& a, const in
 }
 
 template <int MODELS, int CTRL, int INTEG, bool AERO>
-static int wq_blocks_t(int tile) {
+static int wq_blocks_t(int tile, int wide) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq<MODELS, CTRL, INTEG, AERO, false>, tile, 0) !=
-        hipSuccess)
-        return 1;
+    hipError_t e;
+    if constexpr (has_wq3<MODELS, AERO, false>()) {
+        if (wide)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq3<MODELS, CTRL, INTEG, AERO, false>, tile,
+                                                             0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq<MODELS, CTRL, INTEG, AERO, false>, tile,
+                                                             0);
+    } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq<MODELS, CTRL, INTEG, AERO, false>, tile, 0);
+    }
+    if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
@@ -204,7 +252,7 @@ hipError_t launch_step(const KernelSel& ks, const StepArgs& a, const int4* tiles
 }
 
 int step_wq_blocks_per_cu(const KernelSel& ks) {
-    CF_DISPATCH(wq_blocks_t, ks.tile)
+    CF_DISPATCH(wq_blocks_t, ks.tile, ks.wide)
     return 1;
 }
 

@@ -147,6 +147,45 @@ static void test_derive_record() {
     CHECK(!cfh::torque_proportional(r.data(), &kap));
 }
 
+static void test_packed_tiles() {
+    std::vector<int32_t> counts{130, 0, 1, 64, 200, 7, 3};
+    std::vector<uint8_t> models{1, 0, 0, 1, 0, 1, 0};
+    std::vector<int64_t> off{0};
+    for (int c : counts) off.push_back(off.back() + c);
+    std::vector<int32_t> world_of(off.back());
+    for (size_t w = 0; w < counts.size(); ++w)
+        for (int64_t d = off[w]; d < off[w + 1]; ++d) world_of[d] = (int32_t)w;
+    for (int tile : {64, 128, 256}) {
+        int nfp = -1;
+        std::vector<int32_t> list;
+        auto v = cfh::packed_tiles(counts, off, models, tile, &list, &nfp);
+        CHECK((int64_t)list.size() == off.back());
+        std::vector<int> seen(off.back(), 0);
+        for (int32_t d : list) seen[d]++;
+        for (int s : seen) CHECK(s == 1);
+        // first-principles drones first, each model's drones world after world, in order
+        for (size_t i = 1; i < list.size(); ++i) {
+            const int m0 = models[world_of[list[i - 1]]], m1 = models[world_of[list[i]]];
+            CHECK(m0 <= m1);
+            if (m0 == m1) CHECK(list[i] > list[i - 1]);
+        }
+        int covered = 0, fp_tiles = 0;
+        for (size_t k = 0; k < v.size(); ++k) {
+            const auto& t = v[k];
+            CHECK(t.first == covered);
+            CHECK(t.count >= 1 && t.count <= tile);
+            for (int i = 0; i < t.count; ++i) CHECK(models[world_of[list[t.first + i]]] == t.model);
+            // full tiles except the last of each model
+            const bool last_of_model = k + 1 == v.size() || v[k + 1].model != t.model;
+            if (!last_of_model) CHECK(t.count == tile);
+            fp_tiles += t.model == 0;
+            covered += t.count;
+        }
+        CHECK(covered == (int)off.back());
+        CHECK(fp_tiles == nfp);
+    }
+}
+
 static void test_tile_list() {
     std::vector<int32_t> counts{130, 0, 1, 64, 200, 7};
     std::vector<uint8_t> models{1, 0, 0, 1, 0, 1};
@@ -273,6 +312,7 @@ int main(int argc, char** argv) {
     test_validate_desc();
     test_derive_record();
     test_tile_list();
+    test_packed_tiles();
     test_cache(dir);
     test_tags();
     std::printf("host tests passed: %d checks\n", g_checks);
