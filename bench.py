@@ -73,7 +73,7 @@ def parse():
                    help="checkpoint interval; 0 = tune among 1, 10, 50, 100 (alone, then in the job)")
     p.add_argument("--serial", action="store_true", help="run the subset adjoint after the forward")
     p.add_argument("--wq-waves", type=int, default=-1,
-                   help="cap on the held step's resident work-queue waves per SIMD; -1 = tune in the job")
+                   help="cap on the held step's resident work-queue waves per compute unit; -1 = tune in the job")
     p.add_argument("--no-standalone", action="store_true",
                    help="skip the standalone phase timings (profiler runs: every held-step dispatch is in the job)")
     p.add_argument("--graph", action="store_true",
@@ -241,12 +241,13 @@ def main():
         K = best[0]
     cur["K"], cur["ckpt"] = K, adjoint_buffers(K)
     ckpt = cur["ckpt"]
-    # resident work-queue waves per SIMD of the held step inside the job: every
-    # wave that fits, or fewer so that adjoint waves find registers on more SIMDs
+    # resident work-queue waves per compute unit of the held step inside the job:
+    # every wave that fits, or fewer so that the adjoint's waves, whose chain is
+    # the job's critical path, find registers and issue slots on more SIMDs
     # (median of 4 job steps per candidate)
     wq_best = (max(args.wq_waves, 0), None)
     if cfg["workqueue"] and not args.serial and args.wq_waves < 0:
-        for cap in (0, 2, 1):
+        for cap in (0, 8, 4, 2):
             for h_ in (sim, simO, simT):
                 h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"], cap)
             one_step()
@@ -358,7 +359,7 @@ def main():
         "config": {"workload": "uneven_mixed_2048w_logu1-4000_T1000_plus_adjoint_256w",
                    "worlds": w.n_worlds, "drones": D, "horizon": T, "adjoint_worlds": ws.n_worlds,
                    "adjoint_drones": Ds, "ckpt_every": K, "integrator": "rk4", "dt": w.dt,
-                   "launch": dict(cfg, wq_waves_per_simd=wq_best[0]), "hipgraph": bool(args.graph),
+                   "launch": dict(cfg, wq_waves_per_cu=wq_best[0]), "hipgraph": bool(args.graph),
                    "adjoint_overlapped": not args.serial},
         "fwd_drone_steps_per_s": D * T / (fwd_ms * 1e-3),
         "fwdbwd_drone_steps_per_s": Ds * T / ((rf_ms + rb_ms) * 1e-3),

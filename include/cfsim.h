@@ -424,9 +424,10 @@ cf_status cf_launch_config(const cf_handle* h, int32_t* use_workqueue, int32_t* 
    on two streams (mixed handles); tile 64, 128 or 256 lanes; chunk steps per
    launch (0 = all k steps in one launch; a multiple of the controller period);
    wq_waves: with the work queue, at most this many of its waves resident per
-   SIMD (0 = as many as fit; 1..32), which leaves registers to kernels on other
-   streams. Replaces the autotuned choice until the next cf_autotune (which
-   resets wq_waves to 0). Errors: CF_EINVAL. */
+   compute unit (0 = as many as fit; 1..128; a compute unit has four SIMDs),
+   which leaves registers and issue slots to kernels on other streams. Replaces
+   the autotuned choice until the next cf_autotune (which resets wq_waves to 0).
+   Errors: CF_EINVAL. */
 cf_status cf_set_launch_config(cf_handle* h, int32_t use_wq, int32_t tile, int32_t chunk, int32_t wq_waves);
 
 /* cf_launch_times (measurement of the kernels against their rooflines): with

@@ -394,7 +394,7 @@ class Sim:
     def set_launch_config(self, workqueue: int = 0, tile: int = 64, chunk: int = 0, per_model_launches: int = 1,
                           wq_waves: int = 0):
         """Pin the launch choice of step_k (see launch_config); ``wq_waves`` caps the
-        work queue's resident waves per SIMD (0 = as many as fit)."""
+        work queue's resident waves per compute unit (0 = as many as fit)."""
         wq = (int(workqueue) & 1) | ((int(per_model_launches) & 1) << 1)
         _check(self._lib.cf_set_launch_config(self._h, wq, int(tile), int(chunk), int(wq_waves)),
                "cf_set_launch_config")

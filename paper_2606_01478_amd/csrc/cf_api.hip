@@ -330,7 +330,7 @@ struct cf_handle {
     int tile = 64;
     int chunk = 0;       // 0 = all k steps in one launch
     int split = 1;       // mixed handles: one launch per model on two streams
-    int wq_waves = 0;    // work queue: resident waves per SIMD of each launch (0 = all that fit)
+    int wq_waves = 0;    // work queue: resident waves per compute unit of each launch (0 = all that fit)
     int mode = LM_TILE;
     // scratch
     DevBuf ref_tab, seg, ggc, rec, gpart, loss_tmp;
@@ -754,7 +754,7 @@ cf_status cf_launch_config(const cf_handle* h, int32_t* use_wq, int32_t* tile, i
 cf_status cf_set_launch_config(cf_handle* h, int32_t use_wq, int32_t tile, int32_t chunk, int32_t wq_waves) {
     if (!h || use_wq < 0 || use_wq > 3 || (tile != 64 && tile != 128 && tile != 256) || chunk < 0) return CF_EINVAL;
     if (chunk > 0 && chunk % h->ctrl_every != 0) return CF_EINVAL;
-    if (wq_waves < 0 || wq_waves > 32) return CF_EINVAL;
+    if (wq_waves < 0 || wq_waves > 128) return CF_EINVAL;
     hipSetDevice(h->device);
     apply_choice(h, use_wq & 1, tile, chunk, (use_wq >> 1) & 1);
     h->wq_waves = wq_waves;
@@ -877,13 +877,13 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
     e = per_model_packed(h, s, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int slot) {
         KernelSel ks = selection(h, h->use_wq ? LM_WQ : h->mode, h->tile);
         ks.models = models;
-        // uncapped (or capped at three or more waves): the three-wave variant
-        ks.wide = (h->wq_waves == 0 || h->wq_waves >= 3) ? 1 : 0;
+        // uncapped (or capped at three or more waves per SIMD): the three-wave variant
+        ks.wide = (h->wq_waves == 0 || h->wq_waves >= 12) ? 1 : 0;
         int blocks = 0;
         if (h->use_wq) {
             int per_cu = step_wq_blocks_per_cu(ks);
             // a cap leaves SIMD registers to work on other streams (the overlapped adjoint)
-            if (h->wq_waves > 0) per_cu = std::min(per_cu, std::max(1, h->wq_waves * 4 * 64 / ks.tile));
+            if (h->wq_waves > 0) per_cu = std::min(per_cu, std::max(1, h->wq_waves * 64 / ks.tile));
             blocks = std::max(1, std::min(nt, per_cu * h->cus));
         }
         hipError_t r = hipSuccess;
