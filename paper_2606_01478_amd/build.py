@@ -16,7 +16,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["cf_api.hip", "cf_step.hip", "cf_rollout.hip", "cf_mppi.hip", "cf_probe.hip"]
+SOURCES = ["cf_api.hip", "cf_step.hip", "cf_rollout.hip", "cf_rollout_bwd.hip", "cf_mppi.hip", "cf_probe.hip"]
 # host-only runtime pieces (no device code), compiled by the host compiler
 HOST_SOURCES = ["cf_host.cpp"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-I", os.path.join(ROOT, "include")]
