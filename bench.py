@@ -80,6 +80,12 @@ def parse():
                    help="time the job with the held steps replayed from a hipGraph (default: enqueued directly; "
                         "the other form is timed too and reported under graph_comparison)")
     p.add_argument("--autotune-ms", type=int, default=3000)
+    p.add_argument("--launch", default="",
+                   help="pin the held-step launch as 'workqueue,tile,chunk,per_model' (e.g. 1,64,100,1) "
+                        "instead of autotuning it (profiler runs of one configuration)")
+    p.add_argument("--adjoint-only", action="store_true",
+                   help="only the forward rollout and adjoint of the 256-world subset, alone on the GPU "
+                        "(profiler runs of the rollout kernels)")
     p.add_argument("--job-only", action="store_true",
                    help="only the timed job (for profiler runs): no comparators, configurations or baselines")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -138,7 +144,10 @@ def main():
     state = init.clone()
     cmd = t2d(w.cmds)
     mask = torch.ones(w.n_worlds, dtype=torch.uint8, device=dev)
-    if args.autotune_ms > 0:
+    if args.launch:
+        wq_, tile_, chunk_, split_ = (int(v) for v in args.launch.split(","))
+        tune.set_launch_config(wq_, tile_, chunk_, split_)
+    elif args.autotune_ms > 0:
         tune.autotune(state, cmd, T, args.autotune_ms)
     cfg = tune.launch_config()
     tune.close()
@@ -166,6 +175,34 @@ def main():
     def adjoint(K, ckpt):
         simA.rollout(x0s, cmds_s, T, obj, K, ckpt=ckpt, loss=loss, loss_world=loss_w)
         simA.rollout_backward(x0s, cmds_s, T, obj, K, ckpt, dloss=dloss, g_cmds=g_cmds, g_x0=g_x0, g_gain=g_gain)
+
+    if args.adjoint_only:
+        # the subset's forward rollout and adjoint alone, checkpoint interval
+        # --ckpt (default 1), `steps` timed repetitions
+        Ka = max(args.ckpt, 1)
+        ck = adjoint_buffers(Ka)
+        for _ in range(max(args.warmup, 1)):
+            adjoint(Ka, ck)
+        torch.cuda.synchronize()
+        recs = []
+        for _ in range(args.steps):
+            e = [ev() for _ in range(3)]
+            e[0].record()
+            simA.rollout(x0s, cmds_s, T, obj, Ka, ckpt=ck, loss=loss, loss_world=loss_w)
+            e[1].record()
+            simA.rollout_backward(x0s, cmds_s, T, obj, Ka, ck, dloss=dloss, g_cmds=g_cmds, g_x0=g_x0, g_gain=g_gain)
+            e[2].record()
+            recs.append(e)
+        torch.cuda.synchronize()
+        if simA.last_error() != 0:
+            raise RuntimeError("device error in the adjoint run")
+        fwd = [r[0].elapsed_time(r[1]) for r in recs]
+        bwd = [r[1].elapsed_time(r[2]) for r in recs]
+        ms = float(np.mean(fwd) + np.mean(bwd))
+        print(json.dumps({"metric": "adjoint subset drone-steps/s (forward + backward)", "value": Ds * T / (ms * 1e-3),
+                          "unit": "drone-steps/s", "ckpt_every": Ka, "drones": Ds, "horizon": T,
+                          "forward_ms": stats(fwd), "backward_ms": stats(bwd)}))
+        return
 
     side = torch.cuda.Stream(device=dev)   # default priority
     cur = {}                               # checkpoint interval and buffer of the job

@@ -39,9 +39,13 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
             }
         }
         rotors_from_dev(x, P);
+        // the row addresses are formed again here rather than kept from the loads
+        // through the step loop (where they would take registers or scratch)
+        size_t ds = d;
+        asm volatile("" : "+v"(ds));
 #pragma unroll
         for (int i = 0; i < S; ++i) {
-            a.st[i * D + d] = x[i];
+            a.st[i * D + ds] = x[i];
             bad |= !isfinite(x[i]);
         }
     } else {
@@ -59,9 +63,11 @@ __device__ __forceinline__ void run_held(const R& rec, const StepArgs& a, size_t
             else euler_rebase(x + 3, B);
             id_step_base<INTEG>(x, comp, u, P, a.dt, B);
         }
+        size_t ds = d;
+        asm volatile("" : "+v"(ds));
 #pragma unroll
         for (int i = 0; i < S_ID; ++i) {
-            a.st[i * D + d] = x[i];
+            a.st[i * D + ds] = x[i];
             bad |= !isfinite(x[i]);
         }
     }
