@@ -877,8 +877,6 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
     e = per_model_packed(h, s, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int slot) {
         KernelSel ks = selection(h, h->use_wq ? LM_WQ : h->mode, h->tile);
         ks.models = models;
-        // uncapped (or capped at three or more waves per SIMD): the three-wave variant
-        ks.wide = (h->wq_waves == 0 || h->wq_waves >= 12) ? 1 : 0;
         int blocks = 0;
         if (h->use_wq) {
             int per_cu = step_wq_blocks_per_cu(ks);

@@ -25,7 +25,6 @@ struct KernelSel {
     int mode;    // LM_*
     int tile;    // lanes per workgroup (64, 128, 256)
     int aero;    // kernels with gyroscopic/reaction torques, drag and the general rotor law compiled in
-    int wide = 0;  // work queue: the variant held to three waves per SIMD where it exists
 };
 
 struct StepArgs {

@@ -146,23 +146,6 @@ __global__ __launch_bounds__(256) void k_step_wq(StepArgs a, const int4* __restr
     run_queue<MODELS, CTRL, INTEG, AERO, MR>(a, tiles, n_tiles, counter);
 }
 
-// The same queue held to three waves per SIMD (at most 168 registers), for when
-// nothing else needs the SIMDs' registers: for the first-principles model behind
-// the attitude controller the compiler otherwise takes about 200 registers and
-// leaves two waves, too few to hide the latency of the step's dependent
-// arithmetic. The few values it then keeps in scratch are per tile, outside the
-// step loop. Built for the single-model reduced variants only (the others would
-// spill inside the loop).
-template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_step_wq3(
-    StepArgs a, const int4* __restrict__ tiles, int n_tiles, unsigned* counter) {
-    run_queue<MODELS, CTRL, INTEG, AERO, MR>(a, tiles, n_tiles, counter);
-}
-
-template <int MODELS, bool AERO, bool MR>
-constexpr bool has_wq3() {
-    return MODELS != MS_BOTH && !AERO && !MR;
-}
 
 
 template <int MODELS, int CTRL, int INTEG, bool AERO, bool MR>
@@ -178,13 +161,6 @@ static hipError_t launch_step_k(const KernelSel& ks, const StepArgs& a, const in
     } else {
         // work-queue workgroups that do not fit at once start later, find the
         // queue empty and exit
-        if constexpr (has_wq3<MODELS, AERO, MR>()) {
-            if (ks.wide) {
-                hipLaunchKernelGGL((k_step_wq3<MODELS, CTRL, INTEG, AERO, MR>), dim3(wq_blocks), dim3(ks.tile), 0, s,
-                                   a, tiles, n_tiles, counter);
-                return hipGetLastError();
-            }
-        }
         hipLaunchKernelGGL((k_step_wq<MODELS, CTRL, INTEG, AERO, MR>), dim3(wq_blocks), dim3(ks.tile), 0, s, a, tiles,
                            n_tiles, counter);
     }
@@ -203,20 +179,11 @@ static hipError_t launch_step_t(const KernelSel& ks, const StepArgs& a, const in
 }
 
 template <int MODELS, int CTRL, int INTEG, bool AERO>
-static int wq_blocks_t(int tile, int wide) {
+static int wq_blocks_t(int tile) {
     int nb = 0;
-    hipError_t e;
-    if constexpr (has_wq3<MODELS, AERO, false>()) {
-        if (wide)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq3<MODELS, CTRL, INTEG, AERO, false>, tile,
-                                                             0);
-        else
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq<MODELS, CTRL, INTEG, AERO, false>, tile,
-                                                             0);
-    } else {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq<MODELS, CTRL, INTEG, AERO, false>, tile, 0);
-    }
-    if (e != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_wq<MODELS, CTRL, INTEG, AERO, false>, tile, 0) !=
+        hipSuccess)
+        return 1;
     return nb > 0 ? nb : 1;
 }
 
@@ -258,7 +225,7 @@ hipError_t launch_step(const KernelSel& ks, const StepArgs& a, const int4* tiles
 }
 
 int step_wq_blocks_per_cu(const KernelSel& ks) {
-    CF_DISPATCH(wq_blocks_t, ks.tile, ks.wide)
+    CF_DISPATCH(wq_blocks_t, ks.tile)
     return 1;
 }
 

@@ -341,8 +341,7 @@ def test_launch_times_of_a_mixed_handle(gpu_lib, graph):
 @pytest.mark.parametrize("cap", [2, 4, 8])
 def test_work_queue_wave_cap_gives_identical_states(gpu_lib, cap):
     """Capping the work queue's resident waves per compute unit changes only
-    which workgroup takes which tile (and, below three waves per SIMD, which of
-    two register budgets the kernel was built for): the states are bit-identical."""
+    which workgroup takes which tile: the states are bit-identical."""
     w = W.small(5, seed=99)
     a, b = _sim(w, flags=B.F_WORKQUEUE), _sim(w, flags=B.F_WORKQUEUE)
     cfg = a.launch_config()
