@@ -47,7 +47,8 @@ SPEC_HBM_GBS = 8000.0
 # launch configuration "workqueue,tile,chunk,per_model"; summary in
 # profiles/held_step_uneven_mixed_2048w_T1000.md. Valid only for the kernel
 # sources it was measured on (SHA-256 below), reported as null otherwise.
-PROFILED_TRAFFIC = {"sources_sha256": "", "by_launch": {}}
+PROFILED_TRAFFIC = {"sources_sha256": "078a92058205952d1e335bdb72f814b5906c7ed62a47fa468113425b518cd96d",
+                    "by_launch": {"1,64,100,1": 133577369, "1,256,100,1": 115025798}}
 
 
 def kernel_sources_sha256() -> str:
