@@ -47,8 +47,8 @@ SPEC_HBM_GBS = 8000.0
 # launch configuration "workqueue,tile,chunk,per_model"; summary in
 # profiles/held_step_uneven_mixed_2048w_T1000.md. Valid only for the kernel
 # sources it was measured on (SHA-256 below), reported as null otherwise.
-PROFILED_TRAFFIC = {"sources_sha256": "078a92058205952d1e335bdb72f814b5906c7ed62a47fa468113425b518cd96d",
-                    "by_launch": {"1,64,100,1": 133577369, "1,256,100,1": 115025798}}
+PROFILED_TRAFFIC = {"sources_sha256": "400d68e7cfce2ec314df53b3ade5e77de151869727b431661bd09715473676bf",
+                    "by_launch": {"1,64,100,1": 132323871, "1,256,100,1": 114715689}}
 
 
 def kernel_sources_sha256() -> str:
@@ -347,6 +347,14 @@ def main():
     torch.cuda.synchronize()
     wallO = time.perf_counter() - t0
     jobO = np.array([r[0].elapsed_time(r[6]) for r in recsO])
+    # the two forms alternated step by step (same conditions for both; the
+    # blocks above run one after the other)
+    alt = {"timed_form": [], "other_form": []}
+    for i in range(2 * max(args.steps, 4)):
+        rec = []
+        one_step(rec, sim=sim if i % 2 == 0 else simO)
+        torch.cuda.synchronize()
+        alt["timed_form" if i % 2 == 0 else "other_form"].append(rec[0][0].elapsed_time(rec[0][6]))
     # per-launch durations of the held-step kernels inside the job: the same job
     # steps with the directly enqueued, event-timed handle (HIP events the
     # library records around each launch on the stream it is launched on)
@@ -404,7 +412,8 @@ def main():
         "step_ms_stats": stats(job),
         "graph_comparison": {"held_steps_replayed_from_hipgraph": not args.graph,
                              "ms_per_step": wallO * 1e3 / args.steps, "step_ms_stats": stats(jobO),
-                             "value": (D * T + Ds * T) / (wallO / args.steps)},
+                             "value": (D * T + Ds * T) / (wallO / args.steps),
+                             "alternating_step_ms": {k: stats(v) for k, v in alt.items()}},
         "phase_ms": {"reset": float(ph[:, 0].mean()), "forward": fwd_ms, "rollout_fwd": rf_ms,
                      "rollout_bwd": rb_ms, "forward_std": float(ph[:, 1].std())},
         "standalone_ms": standalone,

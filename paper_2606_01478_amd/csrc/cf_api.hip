@@ -256,11 +256,14 @@ static float* scratch_of(int dev) {
 
 namespace {
 
+// part: 0 the whole launch sequence, MS_FP / MS_ID one model's launches of a
+// mixed handle (captured and replayed separately, each on its own stream)
 struct GraphKey {
-    const void* st; const void* cmd; const void* nf; int k; int wq; int tile; int chunk; int plain;
+    const void* st; const void* cmd; const void* nf; int k; int wq; int tile; int chunk; int plain; int waves;
+    int part;
     bool operator<(const GraphKey& o) const {
-        return std::tie(st, cmd, nf, k, wq, tile, chunk, plain) <
-               std::tie(o.st, o.cmd, o.nf, o.k, o.wq, o.tile, o.chunk, o.plain);
+        return std::tie(st, cmd, nf, k, wq, tile, chunk, plain, waves, part) <
+               std::tie(o.st, o.cmd, o.nf, o.k, o.wq, o.tile, o.chunk, o.plain, o.waves, o.part);
     }
 };
 
@@ -476,9 +479,15 @@ hipError_t per_model(cf_handle* h, hipStream_t s, int split, F&& fn) {
     return per_model_on(h, s, split, h->tiles, h->n_tiles, h->n_tiles_fp, fn);
 }
 
-// over the packed tiles (held steps)
+// over the packed tiles (held steps); only = MS_FP or MS_ID: that model's tiles
+// alone, on stream s (its slot: 0 first-principles, 1 identified)
 template <class F>
-hipError_t per_model_packed(cf_handle* h, hipStream_t s, int split, F&& fn) {
+hipError_t per_model_packed(cf_handle* h, hipStream_t s, int split, int only, F&& fn) {
+    if (only == MS_FP) return h->n_ptiles_fp > 0 ? fn(MS_FP, h->ptiles, h->n_ptiles_fp, s, 0) : hipSuccess;
+    if (only == MS_ID) {
+        const int n_id = h->n_ptiles - h->n_ptiles_fp;
+        return n_id > 0 ? fn(MS_ID, h->ptiles + h->n_ptiles_fp, n_id, s, 1) : hipSuccess;
+    }
     return per_model_on(h, s, split, h->ptiles, h->n_ptiles, h->n_ptiles_fp, fn);
 }
 
@@ -835,9 +844,10 @@ static hipError_t timer_event(cf_handle* h, int slot, hipStream_t st, int end) {
     return e;
 }
 
-// enqueue k held-command steps with the current launch choice on stream s
+// enqueue k held-command steps with the current launch choice on stream s; only
+// = MS_FP or MS_ID enqueues that model's launches alone, on s
 static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int k, uint32_t* nf, hipStream_t s,
-                               int plain) {
+                               int plain, int only = 0) {
     hipError_t e = hipSuccess;
     if (!(h->flags & CF_F_GRAPH)) {
         h->timers[0].n = 0;
@@ -852,7 +862,7 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
         // period per launch (its held commands are not part of the state)
         const int mode = h->mode == LM_LANE ? LM_LANE : LM_TILE;
         const StepArgs a = step_args(h, state, cmd, n, nf);
-        e = per_model_packed(h, s, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
+        e = per_model_packed(h, s, h->split, only, [&](int models, const int4* tiles, int nt, hipStream_t st, int) {
             KernelSel ks = selection(h, mode, h->tile);
             ks.models = models;
             hipError_t r = hipSuccess;
@@ -868,13 +878,20 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
     int chunk = (h->chunk > 0 && h->chunk < k) ? h->chunk : k;
     chunk = ((chunk + n - 1) / n) * n;
     const int n_launch = (k + chunk - 1) / chunk;
+    // queue heads: one per launch, the first-principles launches' in the first half
+    // of the counter array, the identified ones' in the second (a model's graph
+    // clears only its own)
+    const int half = h->n_counters / 2;
     if (h->use_wq) {
-        if (2 * n_launch > h->n_counters) return CF_EINVAL;
-        hipLaunchKernelGGL(k_fill_u32, dim3((2 * n_launch + 255) / 256), dim3(256), 0, s, h->counters, 2 * n_launch,
-                           0u);
-        if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
+        if (n_launch > half) return CF_EINVAL;
+        for (int slot = 0; slot < 2; ++slot) {
+            if ((only == MS_FP && slot == 1) || (only == MS_ID && slot == 0)) continue;
+            hipLaunchKernelGGL(k_fill_u32, dim3((n_launch + 255) / 256), dim3(256), 0, s, h->counters + slot * half,
+                               n_launch, 0u);
+            if ((e = hipGetLastError()) != hipSuccess) return note(h, e);
+        }
     }
-    e = per_model_packed(h, s, h->split, [&](int models, const int4* tiles, int nt, hipStream_t st, int slot) {
+    e = per_model_packed(h, s, h->split, only, [&](int models, const int4* tiles, int nt, hipStream_t st, int slot) {
         KernelSel ks = selection(h, h->use_wq ? LM_WQ : h->mode, h->tile);
         ks.models = models;
         int blocks = 0;
@@ -889,7 +906,7 @@ static cf_status enqueue_steps(cf_handle* h, float* state, const float* cmd, int
             const int kk = std::min(chunk, k - c * chunk);
             const StepArgs a = step_args(h, state, cmd, kk, nf);
             if ((r = timer_mark(h, slot, st, 0)) != hipSuccess) break;
-            r = launch_step(ks, a, tiles, nt, h->use_wq ? h->counters + 2 * c + slot : nullptr, blocks, st);
+            r = launch_step(ks, a, tiles, nt, h->use_wq ? h->counters + slot * half + c : nullptr, blocks, st);
             if (r == hipSuccess) r = timer_mark(h, slot, st, 1);
         }
         return r;
@@ -912,35 +929,55 @@ cf_status cf_step_k(cf_handle* h, float* state, const float* cmd, int32_t k, uin
     const int plain = (h->flags & CF_F_PLAIN_KERNEL) ? 1 : 0;
     if (!(h->flags & CF_F_GRAPH)) return enqueue_steps(h, state, cmd, k, nf, h->stream, plain);
 
-    const GraphKey key{state, cmd, nf, k, h->use_wq * 2 + h->split, h->tile, h->chunk, plain};
-    auto it = h->graphs.find(key);
-    if (it == h->graphs.end()) {
-        if (h->graphs.size() >= 64) clear_graphs(h);
-        if (!h->capture_stream &&
-            (e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking)) != hipSuccess)
-            return note(h, e);
-        hipStream_t cs = h->capture_stream;
-        if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return note(h, e);
-        cf_status st = enqueue_steps(h, state, cmd, k, nf, cs, plain);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(cs, &g);
-        if (st != CF_OK) {
-            if (g) hipGraphDestroy(g);
-            return st;
+    // a mixed handle with one launch per model keeps a graph per model and replays
+    // them on its two streams, as the direct form runs them
+    const bool two = h->models == MS_BOTH && h->split;
+    hipGraphExec_t ge[2] = {nullptr, nullptr};
+    for (int p = 0; p < (two ? 2 : 1); ++p) {
+        const int part = two ? (p == 0 ? MS_FP : MS_ID) : 0;
+        const GraphKey key{state, cmd, nf, k, h->use_wq * 2 + h->split, h->tile, h->chunk, plain, h->wq_waves, part};
+        auto it = h->graphs.find(key);
+        if (it == h->graphs.end()) {
+            if (h->graphs.size() >= 64) {
+                clear_graphs(h);
+                if (p == 1) return cf_step_k(h, state, cmd, k, nf);   // the first model's graph was cleared too
+            }
+            if (!h->capture_stream &&
+                (e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+                return note(h, e);
+            hipStream_t cs = h->capture_stream;
+            if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return note(h, e);
+            cf_status st = enqueue_steps(h, state, cmd, k, nf, cs, plain, part);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (st != CF_OK) {
+                if (g) hipGraphDestroy(g);
+                return st;
+            }
+            if (e2 != hipSuccess) return note(h, e2);
+            hipGraphExec_t x = nullptr;
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) return note(h, e);
+            it = h->graphs.emplace(key, x).first;
         }
-        if (e2 != hipSuccess) return note(h, e2);
-        hipGraphExec_t ge = nullptr;
-        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
-        if (e != hipSuccess) return note(h, e);
-        it = h->graphs.emplace(key, ge).first;
+        ge[p] = it->second;
     }
     // with CF_F_TIMING one event pair brackets the whole replay (slot 0)
     const bool timed = (h->flags & CF_F_TIMING) != 0;
     h->timers[0].n = 0;
     h->timers[1].n = 0;
     if (timed && (e = timer_event(h, 0, h->stream, 0)) != hipSuccess) return note(h, e);
-    if ((e = hipGraphLaunch(it->second, h->stream)) != hipSuccess) return note(h, e);
+    if (two) {
+        if ((e = hipEventRecord(h->ev_fork, h->stream)) != hipSuccess) return note(h, e);
+        if ((e = hipStreamWaitEvent(h->aux_stream, h->ev_fork, 0)) != hipSuccess) return note(h, e);
+        if ((e = hipGraphLaunch(ge[0], h->stream)) != hipSuccess) return note(h, e);
+        if ((e = hipGraphLaunch(ge[1], h->aux_stream)) != hipSuccess) return note(h, e);
+        if ((e = hipEventRecord(h->ev_join, h->aux_stream)) != hipSuccess) return note(h, e);
+        if ((e = hipStreamWaitEvent(h->stream, h->ev_join, 0)) != hipSuccess) return note(h, e);
+    } else if ((e = hipGraphLaunch(ge[0], h->stream)) != hipSuccess) {
+        return note(h, e);
+    }
     if (timed && (e = timer_event(h, 0, h->stream, 1)) != hipSuccess) return note(h, e);
     return CF_OK;
 }

@@ -269,7 +269,13 @@ def test_graph_replay_matches_eager(gpu_lib):
     eager = _sim(w)
     graph = _sim(w, flags=B.F_GRAPH | B.F_WORKQUEUE)
     xe, xg, u = dev(w.x0), dev(w.x0), dev(w.cmds)
+    assert graph.launch_config()["per_model_launches"] == 1   # a graph per model, on two streams
     for r in range(4):
+        if r == 2:
+            # a different work-queue cap captures new graphs
+            cfg = graph.launch_config()
+            for s_ in (eager, graph):
+                s_.set_launch_config(1, cfg["tile"], cfg["chunk"], 1, 4)
         eager.step_k(xe, u, 30)
         graph.step_k(xg, u, 30)
         torch.cuda.synchronize()
