@@ -609,7 +609,9 @@ def config_records(B, W, dev, t2d, ev):
     out["config3_id_swarm_64x4000_T1000"] = rec
     sim.close()
 
-    # 4: differentiable rollout 1024 x 1, 500 steps, identified model, feedback, K = 25, 50, 100
+    # 4: differentiable rollout 1024 x 1, 500 steps, identified model, feedback, K = 25, 50, 100,
+    # and K = 1: every state kept by the forward (computed for all drones in parallel), so the
+    # reverse sweep recomputes nothing
     w = W.config4()
     T, D = w.steps, w.n_drones_total
     x0, cmds, gain = t2d(w.x0), t2d(w.cmds), t2d(w.gain)
@@ -618,7 +620,7 @@ def config_records(B, W, dev, t2d, ev):
     loss = torch.empty(D, device=dev)
     g = (torch.empty_like(cmds), torch.empty_like(x0), torch.empty_like(gain))
     rec = {"drones": D, "steps": T, "waves": D // 64}
-    for K in (25, 50, 100):
+    for K in (1, 25, 50, 100):
         ck = sim.ckpt_buffer(T, K, device=dev)
         f = _time(lambda: sim.rollout(x0, cmds, T, obj4, K, ckpt=ck, loss=loss), 10, ev)
         bw = _time(lambda: sim.rollout_backward(x0, cmds, T, obj4, K, ck, g_cmds=g[0], g_x0=g[1], g_gain=g[2]),
