@@ -594,11 +594,15 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
 #pragma unroll
     for (int i = 0; i < S; ++i) lam[i] = 0.f;
     // this drone's gain-gradient contributions, summed in step order, in its own
-    // LDS column gl[k * gs] (registers are the adjoint's scarcest resource)
+    // LDS column (registers are the adjoint's scarcest resource): entry k in
+    // component k % 4 of the 16-byte quad gq[(k / 4) * gs], so that a step's 52
+    // read-modify-writes take 13 quad reads and 13 quad writes (a wave's quads are
+    // consecutive: no bank conflicts)
     const bool mlp = EXT && a.mlp_H > 0;
+    float4* const gq = reinterpret_cast<float4*>(gl - threadIdx.x) + threadIdx.x;
     if (G && !mlp) {
 #pragma unroll
-        for (int i = 0; i < NG; ++i) gl[i * gs] = 0.f;
+        for (int q = 0; q < NG / 4; ++q) gq[q * gs] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     // controller slower than the physics (first-principles, onboard controller):
     // the commands of a block are held over its steps, so their adjoints are
@@ -807,10 +811,20 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
                     for (int i = 0; i < 4; ++i) s2 += G[i * 13 + j] * ob[i];
                     xb[j] += s2;
                 }
+                float gv[NG];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
 #pragma unroll
-                    for (int j = 0; j < 13; ++j) gl[(i * 13 + j) * gs] += ob[i] * ev[j];
+                    for (int j = 0; j < 13; ++j) gv[i * 13 + j] = ob[i] * ev[j];
+                }
+#pragma unroll
+                for (int q = 0; q < NG / 4; ++q) {
+                    float4 s4 = gq[q * gs];
+                    s4.x += gv[4 * q];
+                    s4.y += gv[4 * q + 1];
+                    s4.z += gv[4 * q + 2];
+                    s4.w += gv[4 * q + 3];
+                    gq[q * gs] = s4;
                 }
             }
 #pragma unroll
@@ -834,7 +848,13 @@ __device__ __forceinline__ void rollout_bwd_drone(const R& rec, const RollArgs& 
     if (a.ggc) {
         if (G && !mlp) {
 #pragma unroll
-            for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = gl[i * gs];
+            for (int q = 0; q < NG / 4; ++q) {
+                const float4 s4 = gq[q * gs];
+                a.ggc[(4 * q) * D + d] = s4.x;
+                a.ggc[(4 * q + 1) * D + d] = s4.y;
+                a.ggc[(4 * q + 2) * D + d] = s4.z;
+                a.ggc[(4 * q + 3) * D + d] = s4.w;
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < NG; ++i) a.ggc[i * D + d] = 0.f;
@@ -906,7 +926,7 @@ __device__ __forceinline__ float* stage_policies(const RollArgs& a, float* lds) 
 template <bool BWD, int MODELS, int CTRL, int INTEG, bool AERO, bool EXT>
 __global__ __launch_bounds__(256) void k_rollout_lane(RollArgs a, int S_h) {
     rollout_priority();
-    extern __shared__ float roll_lds[];
+    extern __shared__ __align__(16) float roll_lds[];
     float* gl = stage_policies<EXT>(a, roll_lds);
     const size_t d = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= (size_t)a.D) return;
@@ -935,7 +955,7 @@ __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __
     const int model = __builtin_amdgcn_readfirstlane(td.w);
     // the world's feedback gain (or MLP policy), shared by the workgroup, is read from LDS
     __shared__ float sG[NG];
-    extern __shared__ float roll_lds[];
+    extern __shared__ __align__(16) float roll_lds[];
     float* gl = stage_policies<EXT>(a, roll_lds);
     const float* G = nullptr;
     if (EXT && a.mlp_H > 0) {
