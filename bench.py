@@ -71,7 +71,7 @@ def parse():
     p.add_argument("--seed", type=int, default=1005)
     p.add_argument("--horizon", type=int, default=1000)
     p.add_argument("--ckpt", type=int, default=0,
-                   help="checkpoint interval; 0 = tune among 1, 10, 50, 100 (alone, then in the job)")
+                   help="checkpoint interval; 0 = tune among 1, 2, 5, 10, 50, 100 (alone, then in the job)")
     p.add_argument("--serial", action="store_true", help="run the subset adjoint after the forward")
     p.add_argument("--wq-waves", type=int, default=-1,
                    help="cap on the held step's resident work-queue waves per compute unit; -1 = tune in the job")
@@ -249,7 +249,7 @@ def main():
         cands = [args.ckpt]
     else:
         alone = []
-        for Kc in (1, 10, 50, 100):
+        for Kc in (1, 2, 5, 10, 50, 100):
             ck = adjoint_buffers(Kc)
             adjoint(Kc, ck)
             a, b = ev(), ev()

@@ -954,7 +954,7 @@ __global__ __launch_bounds__(256) void k_rollout_tile(RollArgs a, const int4* __
     const int cnt = __builtin_amdgcn_readfirstlane(td.z);
     const int model = __builtin_amdgcn_readfirstlane(td.w);
     // the world's feedback gain (or MLP policy), shared by the workgroup, is read from LDS
-    __shared__ float sG[NG];
+    __shared__ __align__(16) float sG[NG];
     extern __shared__ __align__(16) float roll_lds[];
     float* gl = stage_policies<EXT>(a, roll_lds);
     const float* G = nullptr;
