@@ -234,6 +234,10 @@ def main():
                                       g_gain=g_gain)
                 e[4].record(side)
             sim.reset(state, init, mask)
+            if cur.get("fwd_first"):
+                # the held steps start once the subset's forward rollout is done
+                # (it then runs with the GPU to itself)
+                main.wait_event(e[3])
             e[1].record(main)
             sim.step_k(state, cmd, T)
             e[5].record(main)
@@ -299,6 +303,21 @@ def main():
                 wq_best = (cap, med)
     for h_ in (sim, simO, simT):
         h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"], wq_best[0])
+    # schedule inside the job: everything overlapped from the start, or the held
+    # steps held back until the subset's forward rollout is done (median of 4
+    # job steps each)
+    if not args.serial:
+        sched = []
+        for ff in (False, True):
+            cur["fwd_first"] = ff
+            one_step()
+            torch.cuda.synchronize()
+            trial = []
+            for _ in range(4):
+                one_step(trial)
+            torch.cuda.synchronize()
+            sched.append((float(np.median([r[0].elapsed_time(r[6]) for r in trial])), ff))
+        cur["fwd_first"] = min(sched)[1]
     # standalone phases (nothing else on the GPU), HIP events on the same streams;
     # the held steps alone run with every work-queue wave that fits (the cap only
     # serves the overlap)
@@ -406,6 +425,7 @@ def main():
                    "worlds": w.n_worlds, "drones": D, "horizon": T, "adjoint_worlds": ws.n_worlds,
                    "adjoint_drones": Ds, "ckpt_every": K, "integrator": "rk4", "dt": w.dt,
                    "launch": dict(cfg, wq_waves_per_cu=wq_best[0]), "hipgraph": bool(args.graph),
+                   "held_steps_after_subset_forward": bool(cur.get("fwd_first", False)),
                    "adjoint_overlapped": not args.serial},
         "fwd_drone_steps_per_s": D * T / (fwd_ms * 1e-3),
         "fwdbwd_drone_steps_per_s": Ds * T / ((rf_ms + rb_ms) * 1e-3),
