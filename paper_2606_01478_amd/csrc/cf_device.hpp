@@ -891,6 +891,74 @@ __device__ __forceinline__ void integrate(float* x, float* c, float h, const Rat
     }
 }
 
+// The first-principles step when the rotor law is W' = c_v (W_cmd - W) (no
+// quadratic term, one coefficient on both branches, no rotor inertia): with the
+// command held over the step the four rotor rows form a linear system of their
+// own, so their RK4 stage values and update are polynomials in z = c_v h applied
+// to e0 = W - W_cmd (the same numbers RK4 produces, without its per-row
+// bookkeeping):
+//   stage 2: W_cmd + e0 (1 - z/2), stage 3: W_cmd + e0 (1 - z/2 + z^2/4),
+//   stage 4: W_cmd + e0 (1 - z + z^2/2 - z^3/4),
+//   update:  W_cmd + e0 (1 - z + z^2/2 - z^3/6 + z^4/24);
+// Euler: W_cmd + e0 (1 - z). The rigid-body rows 0..12 integrate as in
+// integrate(), with the rotor rates of the rates function left unused.
+template <int INTEG, uint32_t MASK, class Rates>
+__device__ __forceinline__ void integrate_fp_linear_rotors(float* x, float* c, float h, const float* rc, float cv,
+                                                           const Rates& rates) {
+    constexpr int NB = 13;   // rigid-body rows
+    const float z = cv * h;
+    float e0[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e0[i] = x[13 + i] - rc[i];
+    float k[S_FP], d[NB];
+    if constexpr (INTEG == EULER) {
+        rates(x, k);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) d[i] = h * k[i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[13 + i] = __builtin_fmaf(e0[i], 1.f - z, rc[i]);
+    } else {
+        const float z2 = z * z;
+        const float p2 = __builtin_fmaf(-0.5f, z, 1.f);
+        const float p3 = __builtin_fmaf(0.25f, z2, p2);
+        const float p4 = __builtin_fmaf(z2, __builtin_fmaf(-0.25f, z, 0.5f), 1.f - z);
+        const float pf = __builtin_fmaf(z2, __builtin_fmaf(z, __builtin_fmaf(z, 1.f / 24.f, -1.f / 6.f), 0.5f), 1.f - z);
+        float acc[NB], xs[S_FP];
+        const float h2 = 0.5f * h, h6 = h * (1.0f / 6.0f);
+        rates(x, k);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) { acc[i] = k[i]; xs[i] = x[i] + h2 * k[i]; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xs[13 + i] = __builtin_fmaf(e0[i], p2, rc[i]);
+        rates(xs, k);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) { acc[i] += 2.f * k[i]; xs[i] = x[i] + h2 * k[i]; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xs[13 + i] = __builtin_fmaf(e0[i], p3, rc[i]);
+        rates(xs, k);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) { acc[i] += 2.f * k[i]; xs[i] = x[i] + h * k[i]; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xs[13 + i] = __builtin_fmaf(e0[i], p4, rc[i]);
+        rates(xs, k);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) d[i] = h6 * (acc[i] + k[i]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[13 + i] = __builtin_fmaf(e0[i], pf, rc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        if ((MASK >> i) & 1u) {
+            const float y = d[i] - c[i];
+            const float t = x[i] + y;
+            c[i] = (t - x[i]) - y;
+            x[i] = t;
+        } else {
+            x[i] += d[i];
+        }
+    }
+}
+
 // rows with compensated updates: position, velocity (both models; the rotor
 // rows hold deviations from the reference speed, whose increments are not lost)
 constexpr uint32_t COMP_FP = 0x7u | (0x7u << 7);
@@ -1005,7 +1073,11 @@ __device__ __forceinline__ void fp_step(float* x, float* comp, const float* u, c
             }
         }
     }
-    integrate<S_FP, INTEG, COMP_FP>(x, comp, dt, [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
+    if (!P.rotor_general && !P.gyro)
+        integrate_fp_linear_rotors<INTEG, COMP_FP>(x, comp, dt, rc, P.cvu,
+                                                   [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
+    else
+        integrate<S_FP, INTEG, COMP_FP>(x, comp, dt, [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); });
     if (renorm) {
         const float n2 = x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6];
         const float inv = rsqrt_hw(n2);
