@@ -1029,6 +1029,112 @@ __device__ __forceinline__ void integrate_vjp(const float* x, float h, const flo
     }
 }
 
+// VJP of integrate_fp_linear_rotors: the rigid-body rows 0..12 run the RK4
+// (or Euler) reverse sweep of integrate_vjp; the rotor rows enter each stage
+// through the closed form W_s = W_cmd + c_s (W - W_cmd), so the adjoint a_s that
+// a stage's rates hand to its rotor values goes to W with c_s and to W_cmd with
+// 1 - c_s (c = 1, 1 - z/2, 1 - z/2 + z^2/4, 1 - z + z^2/2 - z^3/4; the update
+// carries the fourth-order polynomial). vjp(xin, gb, xa) receives rotor-row
+// rate adjoints of zero. Writes xb rows 0..16 and accumulates rcb.
+template <int INTEG, bool NEED_Y, class Rates, class Vjp, class Post>
+__device__ __forceinline__ void integrate_vjp_fp_linear_rotors(const float* x, float h, const float* rc, float cv,
+                                                               const float* yb_in, float* xb, float* rcb,
+                                                               const Rates& rates, const Vjp& vjp, const Post& post) {
+    constexpr int NB = 13;
+    const float z = cv * h;
+    float yb[S_FP], e0[4];
+#pragma unroll
+    for (int i = 0; i < S_FP; ++i) yb[i] = yb_in[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e0[i] = x[13 + i] - rc[i];
+    if constexpr (INTEG == EULER) {
+        if constexpr (NEED_Y) {
+            float k[S_FP], y[S_FP];
+            rates(x, k);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) y[i] = x[i] + h * k[i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) y[13 + i] = __builtin_fmaf(e0[i], 1.f - z, rc[i]);
+            post(y, yb);
+        }
+        float gb[S_FP];
+#pragma unroll
+        for (int i = 0; i < S_FP; ++i) { xb[i] = i < NB ? yb[i] : 0.f; gb[i] = i < NB ? h * yb[i] : 0.f; }
+        vjp(x, gb, xb);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            xb[13 + i] += (1.f - z) * yb[13 + i];
+            rcb[i] += z * yb[13 + i];
+        }
+    } else {
+        const float h2 = 0.5f * h;
+        const float z2 = z * z;
+        const float p2 = __builtin_fmaf(-0.5f, z, 1.f);
+        const float p3 = __builtin_fmaf(0.25f, z2, p2);
+        const float p4 = __builtin_fmaf(z2, __builtin_fmaf(-0.25f, z, 0.5f), 1.f - z);
+        const float pf = __builtin_fmaf(z2, __builtin_fmaf(z, __builtin_fmaf(z, 1.f / 24.f, -1.f / 6.f), 0.5f), 1.f - z);
+        float xs[S_FP], k[S_FP], acc[NB], x2[S_FP], x3[S_FP];
+        rates(x, k);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) { xs[i] = x[i] + h2 * k[i]; acc[i] = k[i]; x2[i] = xs[i]; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { xs[13 + i] = __builtin_fmaf(e0[i], p2, rc[i]); x2[13 + i] = xs[13 + i]; }
+        rates(xs, k);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) { xs[i] = x[i] + h2 * k[i]; acc[i] += 2.f * k[i]; x3[i] = xs[i]; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { xs[13 + i] = __builtin_fmaf(e0[i], p3, rc[i]); x3[13 + i] = xs[13 + i]; }
+        rates(xs, k);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) { xs[i] = x[i] + h * k[i]; acc[i] += 2.f * k[i]; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xs[13 + i] = __builtin_fmaf(e0[i], p4, rc[i]);
+        const float h6 = h * (1.0f / 6.0f), h3 = h * (1.0f / 3.0f);
+        if constexpr (NEED_Y) {
+            rates(xs, k);
+            float y[S_FP];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) y[i] = x[i] + h6 * (acc[i] + k[i]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) y[13 + i] = __builtin_fmaf(e0[i], pf, rc[i]);
+            post(y, yb);
+        }
+        // rigid rows: kb4 = h/6 yb, kb3 = h/3 yb + h a4, kb2 = h/3 yb + h/2 a3,
+        // kb1 = h/6 yb + h/2 a2; rotor rows: W gets sum_s c_s a_s + pf yb, W_cmd
+        // the remainder of sum_s a_s + yb
+        float gb[S_FP], a[S_FP], wr[4], cr[4];
+#pragma unroll
+        for (int i = 0; i < S_FP; ++i) { gb[i] = i < NB ? h6 * yb[i] : 0.f; a[i] = 0.f; }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) xb[i] = yb[i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { wr[i] = pf * yb[13 + i]; cr[i] = yb[13 + i]; }
+        vjp(xs, gb, a);                       // stage 4 at (x + h k3, W_cmd + p4 e0)
+#pragma unroll
+        for (int i = 0; i < NB; ++i) { xb[i] += a[i]; gb[i] = h3 * yb[i] + h * a[i]; a[i] = 0.f; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { wr[i] = __builtin_fmaf(p4, a[13 + i], wr[i]); cr[i] += a[13 + i]; a[13 + i] = 0.f; }
+        vjp(x3, gb, a);                       // stage 3
+#pragma unroll
+        for (int i = 0; i < NB; ++i) { xb[i] += a[i]; gb[i] = h3 * yb[i] + h2 * a[i]; a[i] = 0.f; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { wr[i] = __builtin_fmaf(p3, a[13 + i], wr[i]); cr[i] += a[13 + i]; a[13 + i] = 0.f; }
+        vjp(x2, gb, a);                       // stage 2
+#pragma unroll
+        for (int i = 0; i < NB; ++i) { xb[i] += a[i]; gb[i] = h6 * yb[i] + h2 * a[i]; a[i] = 0.f; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { wr[i] = __builtin_fmaf(p2, a[13 + i], wr[i]); cr[i] += a[13 + i]; a[13 + i] = 0.f; }
+        vjp(x, gb, a);                        // stage 1 (c = 1: nothing for W_cmd)
+#pragma unroll
+        for (int i = 0; i < NB; ++i) xb[i] += a[i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            xb[13 + i] = wr[i] + a[13 + i];
+            rcb[i] += cr[i] - wr[i];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // whole steps
 
@@ -1130,6 +1236,29 @@ __device__ __forceinline__ void renorm_vjp(const float* y, float* ybr) {
     ybr[6] = (ybr[6] - q3 * dot) * inv;
 }
 
+// fp_held_vjp: VJP of the rigid-body and rotor integration under the held
+// commands rc (the step's own controller output, or commands held from an
+// earlier controller step): writes xb rows 0..16 and accumulates rcb. The
+// linear rotor law without gyroscopic torques takes the closed-form rotor rows
+// of the forward step.
+template <int INTEG>
+__device__ __forceinline__ void fp_held_vjp(const float* x, const float* rc, const FpParams& P, float dt,
+                                            int renorm, const float* yb, float* xb, float* rcb) {
+    const auto rates = [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); };
+    const auto vjp = [&](const float* xi, const float* gb, float* xa) { fp_rates_vjp(xi, rc, P, gb, xa, rcb); };
+    const auto none = [](const float*, float*) {};
+    if (!P.rotor_general && !P.gyro) {
+        if (renorm)
+            integrate_vjp_fp_linear_rotors<INTEG, true>(x, dt, rc, P.cvu, yb, xb, rcb, rates, vjp, renorm_vjp);
+        else
+            integrate_vjp_fp_linear_rotors<INTEG, false>(x, dt, rc, P.cvu, yb, xb, rcb, rates, vjp, none);
+    } else if (renorm) {
+        integrate_vjp<S_FP, INTEG, true>(x, dt, yb, xb, rates, vjp, renorm_vjp);
+    } else {
+        integrate_vjp<S_FP, INTEG, false>(x, dt, yb, xb, rates, vjp, none);
+    }
+}
+
 // VJP of fp_step at (x, u) with the controller evaluated in this step: yb =
 // adjoint of the new state (S components), writes xb (S) and accumulates ub (4).
 template <int CTRL, int INTEG>
@@ -1150,14 +1279,7 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
         for (int i = 0; i < 4; ++i) rc[i] = u[i] - P.wr;
     }
     float rcb[4] = {0.f, 0.f, 0.f, 0.f};
-    const auto rates = [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); };
-    const auto vjp = [&](const float* xi, const float* gb, float* xa) { fp_rates_vjp(xi, rc, P, gb, xa, rcb); };
-    if (renorm) {
-        integrate_vjp<S_FP, INTEG, true>(x, dt, yb, xb, rates, vjp, renorm_vjp);
-    } else {
-        const auto none = [](const float*, float*) {};
-        integrate_vjp<S_FP, INTEG, false>(x, dt, yb, xb, rates, vjp, none);
-    }
+    fp_held_vjp<INTEG>(x, rc, P, dt, renorm, yb, xb, rcb);
     if constexpr (CTRL == CTRL_PID) {
 #pragma unroll
         for (int i = S_FP; i < S_PID; ++i) xb[i] = 0.f;
@@ -1172,22 +1294,7 @@ __device__ __forceinline__ void fp_step_vjp(const float* x, const float* u, cons
     }
 }
 
-// Reverse pieces of a step whose controller runs every n > 1 physics steps.
-// fp_held_vjp: VJP of the rigid-body and rotor integration under the held
-// commands rc: writes xb rows 0..16 and accumulates rcb.
-template <int INTEG>
-__device__ __forceinline__ void fp_held_vjp(const float* x, const float* rc, const FpParams& P, float dt,
-                                            int renorm, const float* yb, float* xb, float* rcb) {
-    const auto rates = [&](const float* xi, float* xd) { fp_rates(xi, rc, P, xd); };
-    const auto vjp = [&](const float* xi, const float* gb, float* xa) { fp_rates_vjp(xi, rc, P, gb, xa, rcb); };
-    if (renorm) {
-        integrate_vjp<S_FP, INTEG, true>(x, dt, yb, xb, rates, vjp, renorm_vjp);
-    } else {
-        const auto none = [](const float*, float*) {};
-        integrate_vjp<S_FP, INTEG, false>(x, dt, yb, xb, rates, vjp, none);
-    }
-}
-
+// Reverse piece of a step whose controller runs every n > 1 physics steps.
 // fp_ctrl_vjp: VJP of one controller evaluation at (x, u), given the adjoint rcb
 // of its held commands (summed over the steps that used them) and csb of the PID
 // state it wrote (rows 17..24 of the next state): accumulates into xb and ub.
