@@ -47,8 +47,7 @@ SPEC_HBM_GBS = 8000.0
 # launch configuration "workqueue,tile,chunk,per_model"; summary in
 # profiles/held_step_uneven_mixed_2048w_T1000.md. Valid only for the kernel
 # sources it was measured on (SHA-256 below), reported as null otherwise.
-PROFILED_TRAFFIC = {"sources_sha256": "400d68e7cfce2ec314df53b3ade5e77de151869727b431661bd09715473676bf",
-                    "by_launch": {"1,64,100,1": 132323871, "1,256,100,1": 114715689}}
+PROFILED_TRAFFIC = {"sources_sha256": "453501ce8774ac1caf7d1bfd9be6529feaba836a251466b33ead10e44ad433c5", "by_launch": {"1,64,100,1": 134006806, "1,256,100,1": 115432342}}
 
 
 def kernel_sources_sha256() -> str:
