@@ -91,7 +91,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-comparators", action="store_true")
-    p.add_argument("--no-configs", action="store_true",
+    p.add_argument("--no-workloads", action="store_true",
                    help="skip the per-configuration records (plain forward, closed loop, swarm, differentiable)")
     p.add_argument("--copy-probe", action="store_true", help="also run a 256 MiB device copy (profile scale)")
     p.add_argument("--no-hbm-sweep", action="store_true",
@@ -106,7 +106,7 @@ def parse():
                    help="also time held steps behind each control interface (2^20 single-drone worlds)")
     a = p.parse_args()
     if a.job_only:
-        a.no_cpu_baseline = a.no_comparators = a.no_configs = a.no_hbm_sweep = True
+        a.no_cpu_baseline = a.no_comparators = a.no_workloads = a.no_hbm_sweep = True
         a.no_mppi = a.no_grad_bench = a.no_bptt = True
     return a
 
@@ -131,8 +131,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     T = args.horizon
-    w = W.config5(seed=args.seed, steps=T)
-    ws = W.config5_adjoint(seed=args.seed, steps=T)
+    w = W.uneven_mixed(seed=args.seed, steps=T)
+    ws = W.uneven_mixed_adjoint(seed=args.seed, steps=T)
     D, Ds = w.n_drones_total, ws.n_drones_total
     t2d = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt)
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -506,8 +506,8 @@ def main():
         out["roofline"]["frac_of_measured_fma_peak"] = out["roofline"]["achieved"] / pk["fp32_fma_tflops"]
         out["roofline"]["frac_standalone_of_measured_fma_peak"] = (out["roofline"]["achieved_standalone"]
                                                                   / pk["fp32_fma_tflops"])
-    if not args.no_configs:
-        out["configs"] = config_records(B, W, dev, t2d, ev)
+    if not args.no_workloads:
+        out["other_workloads"] = workload_records(B, W, dev, t2d, ev)
     if not args.no_grad_bench:
         out["gradient_benchmark"] = gradient_benchmark(B, W, dev, t2d, ev)
     if not args.no_mppi:
@@ -548,7 +548,7 @@ def _time(fn, reps, ev):
     return stats(ts)
 
 
-def config_records(B, W, dev, t2d, ev):
+def workload_records(B, W, dev, t2d, ev):
     """The other four configurations, each at its full size: drone-steps/s of the
     plain single-step kernel and of the fused / batched forms on the same GPU,
     and the ALU roofline fraction of the fused forms."""
@@ -557,7 +557,7 @@ def config_records(B, W, dev, t2d, ev):
     out = {}
 
     # 1: plain forward, first-principles rotor interface, 16 x 1, 500 steps, per-step commands
-    w = W.config1()
+    w = W.fp_rotor_open_loop()
     T, D = w.steps, w.n_drones_total
     x0, cmds = t2d(w.x0), t2d(w.cmds)
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
@@ -572,7 +572,7 @@ def config_records(B, W, dev, t2d, ev):
             simP.step_k(x, steps_cmd[t], 1)
     pl = _time(plain, 3, ev)
     fl = FLOPS_PER_DS["fp_rotor_rk4"] * D * T
-    out["config1_fp_rotor_16x1_T500"] = {
+    out["fp_rotor_16x1_T500"] = {
         "drones": D, "steps": T, "fused_rollout_ms": fused, "plain_ms": pl,
         "fused_drone_steps_per_s": D * T / (fused["mean"] * 1e-3),
         "plain_drone_steps_per_s": D * T / (pl["mean"] * 1e-3),
@@ -582,7 +582,7 @@ def config_records(B, W, dev, t2d, ev):
     simP.close()
 
     # 2: closed loop 4096 x 1, 1000 steps, attitude PID
-    w = W.config2()
+    w = W.fp_pid_closed_loop()
     T, D = w.steps, w.n_drones_total
     x0, u = t2d(w.x0), t2d(w.cmds)
     sim = B.Sim.from_workload(w)
@@ -592,7 +592,7 @@ def config_records(B, W, dev, t2d, ev):
     simP = B.Sim.from_workload(w, flags=B.F_PLAIN_KERNEL | B.F_NO_AUTOTUNE_CACHE)
     pl = _time(lambda: simP.step_k(x, u, T), 3, ev)
     fl = FLOPS_PER_DS["fp_pid_rk4"] * D * T
-    out["config2_fp_pid_4096x1_T1000"] = {
+    out["fp_pid_4096x1_T1000"] = {
         "drones": D, "steps": T, "fused_ms": fused, "plain_ms": pl, "launch": sim.launch_config(),
         "fused_drone_steps_per_s": D * T / (fused["mean"] * 1e-3),
         "plain_drone_steps_per_s": D * T / (pl["mean"] * 1e-3),
@@ -602,7 +602,7 @@ def config_records(B, W, dev, t2d, ev):
     simP.close()
 
     # 3: swarm 64 x 4000, identified model, 1000 steps: plain and fused K = 1, 10, 100
-    w = W.config3()
+    w = W.id_swarm()
     T, D = w.steps, w.n_drones_total
     x0, u = t2d(w.x0), t2d(w.cmds)
     rec = {"drones": D, "steps": T, "waves": D // 64}
@@ -625,13 +625,13 @@ def config_records(B, W, dev, t2d, ev):
     t = _time(lambda: sim.step_k(x, u, T), 3, ev)
     rec["autotuned"] = {"launch": sim.launch_config(), "ms": t, "drone_steps_per_s": D * T / (t["mean"] * 1e-3),
                         "frac_alu": fl / (t["mean"] * 1e-3) / 1e12 / peak}
-    out["config3_id_swarm_64x4000_T1000"] = rec
+    out["id_swarm_64x4000_T1000"] = rec
     sim.close()
 
     # 4: differentiable rollout 1024 x 1, 500 steps, identified model, feedback, K = 25, 50, 100,
     # and K = 1: every state kept by the forward (computed for all drones in parallel), so the
     # reverse sweep recomputes nothing
-    w = W.config4()
+    w = W.id_rollout_grad()
     T, D = w.steps, w.n_drones_total
     x0, cmds, gain = t2d(w.x0), t2d(w.cmds), t2d(w.gain)
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
@@ -653,7 +653,7 @@ def config_records(B, W, dev, t2d, ev):
                                      "frac": FLOPS_PER_DS["id_rollout_fwd_bwd"] * D * T / (ms * 1e-3) / 1e12 / peak}}
         del ck
     rec["note"] = "16 waves on 1024 SIMDs: one chain per drone, latency-bound"
-    out["config4_id_adjoint_1024x1_T500"] = rec
+    out["id_adjoint_1024x1_T500"] = rec
     sim.close()
     return out
 
@@ -742,8 +742,8 @@ def interface_benchmark(B, W, dev, t2d, ev, n=1 << 20, T=100, reps=5):
     import dataclasses
 
     import torch
-    pid = W.config2(n_worlds=n, steps=T)
-    cases = [("rotor_speeds", W.config1(n_worlds=n, steps=1)),
+    pid = W.fp_pid_closed_loop(n_worlds=n, steps=T)
+    cases = [("rotor_speeds", W.fp_rotor_open_loop(n_worlds=n, steps=1)),
              ("attitude_pid", pid),
              ("attitude_pid_ctrl_every_5", dataclasses.replace(pid, ctrl_every=5)),
              ("thrust_torques", W.fp_torque(n_worlds=n)),

@@ -23,7 +23,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_cpu_baseline_record_on_a_small_uneven_batch():
-    w = W.config5(n_worlds=32, steps=3)
+    w = W.uneven_mixed(n_worlds=32, steps=3)
     rec = bench.cpu_baseline(w, seconds=0.5)
     assert rec["kind"] == "oracle" and rec["unit"] == "drone-steps/s"
     assert rec["value"] > 0 and rec["cores"] >= 1
@@ -43,7 +43,7 @@ def test_source_hash_is_a_stable_sha256():
 def test_one_thread_cpu_baseline_uses_one_thread():
     import torch
     before = torch.get_num_threads()
-    w = W.config5(n_worlds=256, steps=2)
+    w = W.uneven_mixed(n_worlds=256, steps=2)
     rec = bench.cpu_baseline(w, seconds=0.3, threads=1)
     assert rec["cores"] == 1 and rec["value"] > 0
     assert "(2 worlds," in rec["sample"]          # every 128th world

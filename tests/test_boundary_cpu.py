@@ -58,7 +58,7 @@ def test_param_offsets_match_header():
 
 
 def test_pack_params_places_fields():
-    w = W.small(5, 1)
+    w = W.small("uneven_mixed", 1)
     flat = B.pack_params(w.params, w.n_worlds)
     assert flat.shape == (w.n_worlds, B.NPARAM) and flat.dtype == np.float32
     for n, (off, k) in B.PARAM_OFFSETS.items():
@@ -104,12 +104,12 @@ def _create(lib, d):
     ("renorm_q", 3), ("n_gains", -1),
 ])
 def test_create_rejects_invalid_fields(lib, field, value):
-    d, keep = _desc(W.small(2, 1), **{field: value})
+    d, keep = _desc(W.small("fp_pid_closed_loop", 1), **{field: value})
     assert _create(lib, d) == B.CF_EINVAL
 
 
 def test_create_rejects_bad_counts_models_params(lib):
-    w = W.small(5, 1)
+    w = W.small("uneven_mixed", 1)
     d, keep = _desc(w)
     keep[0][3] = -1
     assert _create(lib, d) == B.CF_EINVAL
@@ -140,7 +140,7 @@ def test_create_rejects_bad_counts_models_params(lib):
 
 
 def test_create_rejects_out_of_range_gain_index(lib):
-    w = W.small(4, 1)
+    w = W.small("id_rollout_grad", 1)
     gi = np.zeros(w.n_worlds, np.int32)
     gi[5] = 2
     d, keep = _desc(w, n_gains=2, gain_index=gi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
@@ -148,14 +148,14 @@ def test_create_rejects_out_of_range_gain_index(lib):
 
 
 def test_create_too_many_drones(lib):
-    w = W.small(3, 1)
+    w = W.small("id_swarm", 1)
     counts = np.full(w.n_worlds, 2 ** 30, np.int32)
     d, keep = _desc(w, drones_per_world=counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     assert _create(lib, d) == B.CF_EINVAL
 
 
 def test_valid_create_reports_no_device_or_succeeds(lib):
-    d, keep = _desc(W.small(1, 1))
+    d, keep = _desc(W.small("fp_rotor_open_loop", 1))
     st = _create(lib, d)
     import torch
     assert st == (B.CF_OK if torch.cuda.is_available() else B.CF_ENODEV)
@@ -180,7 +180,7 @@ def test_sim_raises_cferror_without_device():
     if torch.cuda.is_available():
         pytest.skip("device present")
     with pytest.raises(B.CfError) as ei:
-        B.Sim.from_workload(W.small(2, 1))
+        B.Sim.from_workload(W.small("fp_pid_closed_loop", 1))
     assert ei.value.status == B.CF_ENODEV
 
 

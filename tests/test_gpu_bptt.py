@@ -36,7 +36,7 @@ def test_bptt_setup_paper_scale_against_oracle(gpu_lib, hidden):
 def test_time_shift_on_tiles_with_offsets_and_linear_policy(gpu_lib):
     """Mixed first-principles (PID) / identified worlds in 64-lane tiles, per-drone
     offsets and random time shifts, the tracking loss (not the reward)."""
-    w = W.config5_adjoint(seed=71, n_worlds=12, n_subset=8, steps=60, n_max=90)
+    w = W.uneven_mixed_adjoint(seed=71, n_worlds=12, n_subset=8, steps=60, n_max=90)
     rng = np.random.Generator(np.random.Philox(71))
     w.ref_time_shift = W._f32(rng.uniform(-4.0, 8.0, size=w.n_drones_total))
     sim = _sim(w)
@@ -47,7 +47,7 @@ def test_time_shift_on_tiles_with_offsets_and_linear_policy(gpu_lib):
 def test_reference_time_offset_against_oracle(gpu_lib):
     """Step n tracks the figure-eight at (ref_step0 + n) dt: a rollout that starts
     deep into the reference, with the linear feedback and the tracking loss."""
-    w = W.config4(seed=72, n_worlds=100, steps=80)
+    w = W.id_rollout_grad(seed=72, n_worlds=100, steps=80)
     w.ref_step0 = 777
     _check_against_oracle(w, _grads(_sim(w), w, 20))
 
@@ -57,9 +57,9 @@ def test_squashed_policy_saturating_against_oracle(gpu_lib, hidden):
     """Policy outputs of order 1-3 (tanh partly saturated) on the identified lane
     kernel, tracking loss, checkpoint every step and every 16 steps."""
     if hidden:
-        w = W.config4_mlp(seed=73, n_worlds=90, steps=48, hidden=hidden, out_scale=1.0)
+        w = W.id_rollout_grad_mlp(seed=73, n_worlds=90, steps=48, hidden=hidden, out_scale=1.0)
     else:
-        w = W.config4(seed=73, n_worlds=90, steps=48, gain_std=2.0)
+        w = W.id_rollout_grad(seed=73, n_worlds=90, steps=48, gain_std=2.0)
     w.policy_scale = W._f32([0.4, 0.3, 0.2, 0.1])
     sim = _sim(w)
     _check_against_oracle(w, _grads(sim, w, 16))
@@ -91,7 +91,7 @@ def test_bptt_training_lowers_tracking_error(gpu_lib):
 # ---- Adam through the library vs Adam on the oracle ---------------------------
 
 def _setup(seed=12):
-    w = W.small(4, seed=seed)
+    w = W.small("id_rollout_grad", seed=seed)
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u)
     return w, sim, kw

@@ -27,7 +27,7 @@ EULER, RK4 = W.INTEG_EULER, W.INTEG_RK4
 def test_plain_kernel_closed_loop_against_unrounded_oracle(gpu_lib):
     """One launch per step for 1000 steps of the PID closed loop (200 worlds),
     compared with the oracle that keeps its state in FP64 throughout."""
-    w = W.small(2, seed=2)
+    w = W.small("fp_pid_closed_loop", seed=2)
     sim = _sim(w, flags=B.F_PLAIN_KERNEL)
     x = dev(w.x0)
     sim.step_k(x, dev(w.cmds), w.steps)
@@ -43,7 +43,7 @@ def test_mixed_subset_tracking_adjoint_checkpoint_every_step(gpu_lib):
     tracking loss with feedback, a checkpoint at every step (K = 1, the interval
     the benchmark tunes to): 48 sampled drones against the oracle's autograd and
     every drone against K = 50."""
-    w = W.config5_adjoint()
+    w = W.uneven_mixed_adjoint()
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     assert sim.launch_config()["per_model_launches"] == 1
     T = w.steps
@@ -88,7 +88,7 @@ def _euler(w):
 
 
 def test_euler_rotor_interface_rollout_gradients(gpu_lib):
-    w = _euler(W.config1(seed=80, n_worlds=70, steps=60))
+    w = _euler(W.fp_rotor_open_loop(seed=80, n_worlds=70, steps=60))
     w.ref_offset = w.x0[0:3].copy()
     w.dloss = np.linspace(0.5, 1.5, 70).astype(np.float32)
     w.w_u = 1e-9
@@ -98,19 +98,19 @@ def test_euler_rotor_interface_rollout_gradients(gpu_lib):
 def test_euler_mixed_pid_and_identified_rollout_gradients(gpu_lib):
     """First-principles worlds behind the attitude PID and identified worlds,
     Euler, feedback, per-drone offsets, one gain per model."""
-    w = _euler(W.config5_adjoint(seed=81, n_worlds=12, n_subset=8, steps=120, n_max=70))
+    w = _euler(W.uneven_mixed_adjoint(seed=81, n_worlds=12, n_subset=8, steps=120, n_max=70))
     _check_against_oracle(w, _rollout_grads(w, 40))
 
 
 def test_euler_identified_rollout_gradients(gpu_lib):
-    w = _euler(W.small(4, seed=82))
+    w = _euler(W.small("id_rollout_grad", seed=82))
     _check_against_oracle(w, _rollout_grads(w, 25))
 
 
 @pytest.mark.parametrize("k_launch", [1, 100])
 def test_euler_identified_held_steps(gpu_lib, k_launch):
     """Identified swarm worlds (tiles with a ragged tail), 1000 Euler steps."""
-    w = _euler(W.small(3, seed=83))
+    w = _euler(W.small("id_swarm", seed=83))
     sim = _sim(w)
     x, u = dev(w.x0), dev(w.cmds)
     for _ in range(w.steps // k_launch):
@@ -157,7 +157,7 @@ def _branch_switches(w, steps):
 def test_asymmetric_rotor_law_open_loop(gpu_lib, integ):
     """Per-step rotor commands around hover (every rotor's command crosses its
     speed many times), 500 steps, trajectory and x_T."""
-    w = _asymmetric(W.config1(seed=84, integrator=integ))
+    w = _asymmetric(W.fp_rotor_open_loop(seed=84, integrator=integ))
     assert _branch_switches(w, 100) > 100
     sim = _sim(w)
     T = w.steps
@@ -177,7 +177,7 @@ def test_asymmetric_rotor_law_open_loop(gpu_lib, integ):
 def test_asymmetric_rotor_law_closed_loop(gpu_lib, wq):
     """The attitude PID moves every rotor command up and down through the run:
     1000 held-command steps of 200 worlds, fused or work-queue launch."""
-    w = _asymmetric(W.small(2, seed=85))
+    w = _asymmetric(W.small("fp_pid_closed_loop", seed=85))
     sim = _sim(w, flags=B.F_WORKQUEUE if wq else 0)
     x = dev(w.x0)
     sim.step_k(x, dev(w.cmds), w.steps)
@@ -186,7 +186,7 @@ def test_asymmetric_rotor_law_closed_loop(gpu_lib, wq):
 
 
 def test_asymmetric_rotor_law_rollout_gradients_rotor_interface(gpu_lib):
-    w = _asymmetric(W.config1(seed=86, n_worlds=70, steps=60))
+    w = _asymmetric(W.fp_rotor_open_loop(seed=86, n_worlds=70, steps=60))
     w.ref_offset = w.x0[0:3].copy()
     w.dloss = np.linspace(0.5, 1.5, 70).astype(np.float32)
     w.w_u = 1e-9
@@ -194,7 +194,7 @@ def test_asymmetric_rotor_law_rollout_gradients_rotor_interface(gpu_lib):
 
 
 def test_asymmetric_rotor_law_rollout_gradients_mixed(gpu_lib):
-    w = _asymmetric(W.config5_adjoint(seed=87, n_worlds=12, n_subset=8, steps=120, n_max=70))
+    w = _asymmetric(W.uneven_mixed_adjoint(seed=87, n_worlds=12, n_subset=8, steps=120, n_max=70))
     _check_against_oracle(w, _rollout_grads(w, 40))
 
 
@@ -203,7 +203,7 @@ def test_asymmetric_rotor_law_rollout_gradients_mixed(gpu_lib):
 def test_two_forwards_before_their_backwards(gpu_lib):
     """Two forwards into two buffers, then their backwards in reverse order:
     each backward gives what it gives right after its own forward."""
-    w = W.small(4, seed=90)
+    w = W.small("id_rollout_grad", seed=90)
     sim = _sim(w)
     T, K = w.steps, 25
     x0, gain = dev(w.x0), dev(w.gain)
@@ -234,7 +234,7 @@ def test_two_forwards_before_their_backwards(gpu_lib):
 def test_sum_of_two_rollout_losses_backward(gpu_lib, reward):
     """loss(ubar) + loss(1.01 ubar) through RolloutLoss on one handle, one
     backward: the gradient is g(ubar) + 1.01 g(1.01 ubar) of the oracle."""
-    w = W.small(4, seed=91)
+    w = W.small("id_rollout_grad", seed=91)
     if reward:
         w.reward = W.BPTT_REWARD
     sim = _sim(w)
@@ -259,7 +259,7 @@ def test_backward_after_the_buffer_was_overwritten(gpu_lib):
     """A buffer filled by this handle's forward and then by another handle's
     forward of the same shape: the backward finds the other tag on the device,
     writes NaN gradients and the handle reports CF_ESTATE."""
-    w = W.small(4, seed=92)
+    w = W.small("id_rollout_grad", seed=92)
     a, b = _sim(w), _sim(w)
     T, K = w.steps, 25
     x0, cmds, gain = dev(w.x0), dev(w.cmds), dev(w.gain)
@@ -282,7 +282,7 @@ def test_backward_after_the_buffer_was_overwritten(gpu_lib):
 
 
 def test_backward_refuses_a_different_objective(gpu_lib):
-    w = W.small(4, seed=93)
+    w = W.small("id_rollout_grad", seed=93)
     sim = _sim(w)
     T, K = w.steps, 25
     x0, cmds, gain = dev(w.x0), dev(w.cmds), dev(w.gain)
@@ -308,7 +308,7 @@ def test_launch_times_of_a_mixed_handle(gpu_lib, graph):
     """CF_F_TIMING: one duration per kernel launch of the latest cf_step_k, on
     the stream of each model; the launches fit inside the call's wall time and
     the states equal those of an untimed handle."""
-    w = W.small(5, seed=94)
+    w = W.small("uneven_mixed", seed=94)
     flags = B.F_WORKQUEUE | B.F_TIMING | (B.F_GRAPH if graph else 0)
     sim = _sim(w, flags=flags)
     ref = _sim(w, flags=B.F_WORKQUEUE)
@@ -342,7 +342,7 @@ def test_launch_times_of_a_mixed_handle(gpu_lib, graph):
 def test_work_queue_wave_cap_gives_identical_states(gpu_lib, cap):
     """Capping the work queue's resident waves per compute unit changes only
     which workgroup takes which tile: the states are bit-identical."""
-    w = W.small(5, seed=99)
+    w = W.small("uneven_mixed", seed=99)
     a, b = _sim(w, flags=B.F_WORKQUEUE), _sim(w, flags=B.F_WORKQUEUE)
     cfg = a.launch_config()
     b.set_launch_config(1, cfg["tile"], cfg["chunk"], cfg["per_model_launches"], cap)

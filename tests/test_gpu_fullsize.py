@@ -16,16 +16,16 @@ pytestmark = pytest.mark.gpu
 
 
 def test_closed_loop_4096_worlds_all_drones(gpu_lib):
-    w = W.config2()
+    w = W.fp_pid_closed_loop()
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     x = dev(w.x0)
     sim.step_k(x, dev(w.cmds), w.steps)
     torch.cuda.synchronize()
-    assert_states_close(x, O.simulate_held(w), w, what="config2 x_1000")
+    assert_states_close(x, O.simulate_held(w), w, what="4096 PID worlds x_1000")
 
 
 def test_swarm_64x4000_chunkings_and_samples(gpu_lib):
-    w = W.config3()
+    w = W.id_swarm()
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     u = dev(w.cmds)
     outs = {}
@@ -40,14 +40,14 @@ def test_swarm_64x4000_chunkings_and_samples(gpu_lib):
     ref = O.simulate_held(ws)
     ii = torch.as_tensor(idx, device="cuda")
     for k in (1, 10, 100, 1000):
-        assert_states_close(outs[k][:, ii], ref, ws, what=f"config3 sampled, {k} steps per launch")
-        assert_states_close(outs[k], outs[1000], w, what=f"config3 all drones, {k} vs 1000 steps per launch")
+        assert_states_close(outs[k][:, ii], ref, ws, what=f"64 x 4000 swarm sampled, {k} steps per launch")
+        assert_states_close(outs[k], outs[1000], w, what=f"64 x 4000 swarm all drones, {k} vs 1000 steps per launch")
 
 
 _CONFIG4_ORACLE = {}
 
 
-def _config4_oracle(w):
+def _tracking_oracle(w):
     """The oracle's loss and gradients of the full differentiable workload,
     computed once for the three checkpoint intervals."""
     if "ref" not in _CONFIG4_ORACLE:
@@ -57,7 +57,7 @@ def _config4_oracle(w):
 
 @pytest.mark.parametrize("K", [25, 50, 100])
 def test_differentiable_1024_worlds(gpu_lib, K):
-    w = W.config4()
+    w = W.id_rollout_grad()
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     T = w.steps
     x0, cmds, gain = dev(w.x0), dev(w.cmds), dev(w.gain)
@@ -68,16 +68,16 @@ def test_differentiable_1024_worlds(gpu_lib, K):
     g_cmds, g_x0, g_gain = torch.empty_like(cmds), torch.empty_like(x0), torch.empty_like(gain)
     sim.rollout_backward(x0, cmds, T, obj, K, ckpt, dloss=dev(w.dloss), g_cmds=g_cmds, g_x0=g_x0, g_gain=g_gain)
     torch.cuda.synchronize()
-    ref = _config4_oracle(w)
+    ref = _tracking_oracle(w)
     lr = ref["loss"]
     assert torch.all((loss.double().cpu() - lr).abs() <= 1e-4 * lr.abs().clamp_min(1e-2))
-    assert_grad_close(g_cmds, ref["g_cmds"], f"config4 K={K} g_cmds")
-    assert_grad_close(g_x0, ref["g_x0"], f"config4 K={K} g_x0")
+    assert_grad_close(g_cmds, ref["g_cmds"], f"1024 tracking worlds K={K} g_cmds")
+    assert_grad_close(g_x0, ref["g_x0"], f"1024 tracking worlds K={K} g_x0")
     assert (g_gain.double().cpu() - ref["g_gain"]).norm() <= 1e-3 * ref["g_gain"].norm()
 
 
 def test_differentiable_checkpoint_invariance_full(gpu_lib):
-    w = W.config4()
+    w = W.id_rollout_grad()
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     T = w.steps
     x0, cmds, gain = dev(w.x0), dev(w.cmds), dev(w.gain)
@@ -103,7 +103,7 @@ def test_uneven_2048_worlds_autotuned_launch(gpu_lib):
     launch) the per-tile grid, the work queue and the single mixed-model launch
     give the same bits; the autotuned chunking restarts the compensated sums at
     each launch boundary, so it agrees with them to the parity bar."""
-    w = W.config5()
+    w = W.uneven_mixed()
     sim = B.Sim.from_workload(w)
     x = dev(w.x0)
     u = dev(w.cmds)
@@ -117,17 +117,17 @@ def test_uneven_2048_worlds_autotuned_launch(gpu_lib):
     torch.cuda.synchronize()
     assert torch.equal(one["grid"], one["wq"])
     assert torch.equal(one["grid"], one["single"])
-    assert_states_close(x, one["grid"], w, what="config5 autotuned vs one launch")
+    assert_states_close(x, one["grid"], w, what="uneven 2048 worlds autotuned vs one launch")
     idx = np.random.default_rng(1).choice(w.n_drones_total, 512, replace=False)
     ws = sample_drones(w, idx)
-    assert_states_close(x[:, torch.as_tensor(idx, device="cuda")], O.simulate_held(ws), ws, what="config5 sampled")
+    assert_states_close(x[:, torch.as_tensor(idx, device="cuda")], O.simulate_held(ws), ws, what="uneven 2048 worlds sampled")
 
 
 def test_uneven_adjoint_subset_full(gpu_lib):
     """256-world subset, T = 1000: per-drone gradients on sampled drones vs the
     oracle; the gain gradient against sum_t sum_d g_cmds[t] e_t^T computed from
     the full trajectory (an identity that holds at any size)."""
-    w = W.config5_adjoint()
+    w = W.uneven_mixed_adjoint()
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     T, K = w.steps, 50
     x0, cmds, gain, off = dev(w.x0), dev(w.cmds), dev(w.gain), dev(w.ref_offset)
@@ -146,12 +146,12 @@ def test_uneven_adjoint_subset_full(gpu_lib):
     ii = torch.as_tensor(idx, device="cuda")
     lr = ref["loss"]
     assert torch.all((loss[ii].double().cpu() - lr).abs() <= 1e-4 * lr.abs().clamp_min(1e-2))
-    assert_grad_close(g_cmds[:, :, ii], ref["g_cmds"], "config5 subset g_cmds")
+    assert_grad_close(g_cmds[:, :, ii], ref["g_cmds"], "uneven subset g_cmds")
     gx, rx = g_x0[:, ii].double().cpu(), ref["g_x0"].clone()
     idm = torch.as_tensor(ws.model_per_world == W.MODEL_ID)
     gx[13:, idm] = 0
     rx[13:, idm] = 0
-    assert_grad_close(gx, rx, "config5 subset g_x0")
+    assert_grad_close(gx, rx, "uneven subset g_x0")
     # gain gradient identity on the full subset
     world = np.repeat(np.arange(w.n_worlds), w.drones_per_world)
     models = torch.as_tensor(w.model_per_world[world], device="cuda")
@@ -214,7 +214,7 @@ def _interface_case(name):
         return W.fp_torque(n_worlds=n, steps=T)
     if name == "position":
         return W.fp_position(n_worlds=n, steps=T)
-    return dataclasses.replace(W.config2(n_worlds=n, steps=T), ctrl_every=5)
+    return dataclasses.replace(W.fp_pid_closed_loop(n_worlds=n, steps=T), ctrl_every=5)
 
 
 @pytest.mark.parametrize("name", ["torque", "position", "pid_every_5"])
@@ -242,7 +242,7 @@ def test_shared_gain_gradient_over_2p20_worlds(gpu_lib):
     gain gradient (a fixed-order two-stage reduction over the drones) is
     bit-identical across calls and equals sum_t sum_d g_cmds[t, :, d] e_t[d]^T
     evaluated in float64 from the trajectory."""
-    w = W.config4(seed=95, n_worlds=1 << 20, steps=10)
+    w = W.id_rollout_grad(seed=95, n_worlds=1 << 20, steps=10)
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     T, D = w.steps, w.n_drones_total
     x0, cmds, gain = dev(w.x0), dev(w.cmds), dev(w.gain)

@@ -50,14 +50,14 @@ def _grads(sim, w, K, noalloc=False):
 @pytest.mark.parametrize("hidden", [8, 32])
 def test_mlp_identified_lane_kernel(gpu_lib, hidden):
     """100 single-drone identified worlds (one drone per lane), 80 steps, one policy."""
-    w = W.config4_mlp(seed=60, n_worlds=100, steps=80, hidden=hidden)
+    w = W.id_rollout_grad_mlp(seed=60, n_worlds=100, steps=80, hidden=hidden)
     _check_against_oracle(w, _grads(_sim(w), w, 20))
 
 
 def test_mlp_mixed_tiles_two_policies_reward(gpu_lib):
     """First-principles (PID) and identified worlds in 64-lane tiles, a policy per
     model (width 16), the paper's BPTT reward, checkpoint every 10 steps."""
-    w = _mlp(W.config5_adjoint(seed=61, n_worlds=12, n_subset=8, steps=60, n_max=140), 16, 61)
+    w = _mlp(W.uneven_mixed_adjoint(seed=61, n_worlds=12, n_subset=8, steps=60, n_max=140), 16, 61)
     w.reward = W.BPTT_REWARD
     sim = _sim(w)
     assert sim.launch_config()["tile"] == 64
@@ -66,13 +66,13 @@ def test_mlp_mixed_tiles_two_policies_reward(gpu_lib):
 
 def test_mlp_slow_controller(gpu_lib):
     """The PID every third step with the policy in front of it (width 8)."""
-    w = _mlp(W.config5_adjoint(seed=62, n_worlds=10, n_subset=6, steps=61, n_max=50), 8, 62)
+    w = _mlp(W.uneven_mixed_adjoint(seed=62, n_worlds=10, n_subset=6, steps=61, n_max=50), 8, 62)
     w.ctrl_every = 3
     _check_against_oracle(w, _grads(_sim(w, ctrl_every=3), w, 3))
 
 
 def test_mlp_checkpoint_interval_invariance_and_noalloc(gpu_lib):
-    w = W.config4_mlp(seed=63, n_worlds=70, steps=60, hidden=16)
+    w = W.id_rollout_grad_mlp(seed=63, n_worlds=70, steps=60, hidden=16)
     sim = _sim(w)
     base = _grads(sim, w, 60)
     for K in (1, 7):
@@ -86,7 +86,7 @@ def test_mlp_checkpoint_interval_invariance_and_noalloc(gpu_lib):
 
 
 def test_mlp_through_rollout_loss(gpu_lib):
-    w = W.config4_mlp(seed=64, n_worlds=40, steps=50, hidden=16)
+    w = W.id_rollout_grad_mlp(seed=64, n_worlds=40, steps=50, hidden=16)
     sim = _sim(w)
     x0 = dev(w.x0).requires_grad_(True)
     cmds = dev(w.cmds).requires_grad_(True)
@@ -102,7 +102,7 @@ def test_mlp_through_rollout_loss(gpu_lib):
 
 
 def test_mlp_argument_checks(gpu_lib):
-    w = W.config4_mlp(seed=65, n_worlds=20, steps=10, hidden=8)
+    w = W.id_rollout_grad_mlp(seed=65, n_worlds=20, steps=10, hidden=8)
     sim = _sim(w)
     x0, cmds = dev(w.x0), dev(w.cmds)
     bad = B.Sim.objective(gain=dev(w.gain), policy_hidden=33)
@@ -110,7 +110,7 @@ def test_mlp_argument_checks(gpu_lib):
                              None, None)
     assert st == B.CF_EINVAL
     # six width-32 policies and the activations do not fit the 64 KiB of LDS
-    w6 = W.config4(seed=66, n_worlds=12, steps=10)
+    w6 = W.id_rollout_grad(seed=66, n_worlds=12, steps=10)
     w6.gain_index = np.arange(12, dtype=np.int32) % 6
     w6 = _mlp(dataclasses.replace(w6, gain=np.zeros((6, 4, 13), np.float32)), 32, 66)
     sim6 = _sim(w6)

@@ -152,7 +152,7 @@ def test_rejects_invalid_arguments(gpu_lib):
     obs = np.array([[0, 0, 1, 0.0]], np.float32)
     with pytest.raises(B.CfError):
         B.Mppi(sim, dict(P, obstacles=obs))
-    w2 = W.config2(seed=1, n_worlds=2, steps=1)
+    w2 = W.fp_pid_closed_loop(seed=1, n_worlds=2, steps=1)
     with pytest.raises(B.CfError):
         B.Mppi(B.Sim.from_workload(w2, flags=B.F_NO_AUTOTUNE_CACHE), P)
     mp = B.Mppi(sim, P)

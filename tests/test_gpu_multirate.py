@@ -28,7 +28,7 @@ def test_pid_every_fifth_step_held(gpu_lib, mode):
     """Attitude PID every 5 physics steps, 200 single-drone worlds, 1000 steps;
     the plain kernel launches once per block and stores the binary32 state, so
     its reference rounds the state after every block."""
-    w = W.small(2, seed=2)
+    w = W.small("fp_pid_closed_loop", seed=2)
     w.ctrl_every = 5
     flags = {"grid": 0, "wq": B.F_WORKQUEUE, "plain": B.F_PLAIN_KERNEL}[mode]
     sim = _sim(w, flags)
@@ -41,7 +41,7 @@ def test_pid_every_fifth_step_held(gpu_lib, mode):
 
 def test_pid_every_fifth_step_in_chunks(gpu_lib):
     """The same run as 20 calls of 50 steps: blocks restart with every call."""
-    w = W.small(2, seed=2)
+    w = W.small("fp_pid_closed_loop", seed=2)
     w.ctrl_every = 5
     sim = _sim(w)
     x, u = dev(w.x0), dev(w.cmds)
@@ -71,7 +71,7 @@ def test_rollout_gradients_slow_pid(gpu_lib, K):
     """Mixed first-principles (PID every 3 steps) and identified worlds, 100 steps
     (the last block is one step long), checkpoints every K steps (K divides the
     block or the block divides K): loss, x_T and gradients vs autograd."""
-    w = W.config5_adjoint(seed=9, n_worlds=12, n_subset=8, steps=100, n_max=70)
+    w = W.uneven_mixed_adjoint(seed=9, n_worlds=12, n_subset=8, steps=100, n_max=70)
     w.ctrl_every = 3
     _check_against_oracle(w, _rollout_grads(w, K))
 
@@ -103,7 +103,7 @@ def test_sampled_rollouts_with_slow_controller(gpu_lib):
 
 
 def test_rejects_step_counts_and_intervals_off_the_block(gpu_lib):
-    w = W.config5_adjoint(seed=9, n_worlds=4, n_subset=3, steps=12, n_max=20)
+    w = W.uneven_mixed_adjoint(seed=9, n_worlds=4, n_subset=3, steps=12, n_max=20)
     w.ctrl_every = 3
     sim = _sim(w)
     x = dev(w.x0)

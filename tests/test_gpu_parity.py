@@ -26,7 +26,7 @@ def _oracle_traj(w):
 @pytest.mark.parametrize("integ", [W.INTEG_RK4, W.INTEG_EULER])
 def test_fp_rotor_open_loop_rollout(gpu_lib, integ):
     """Per-step rotor commands, 16 worlds x 1 drone, 500 steps."""
-    w = W.config1(seed=1, integrator=integ)
+    w = W.fp_rotor_open_loop(seed=1, integrator=integ)
     sim = _sim(w)
     T = w.steps
     x0, cmds = dev(w.x0), dev(w.cmds)
@@ -50,7 +50,7 @@ def test_fp_pid_closed_loop_held(gpu_lib, plain):
     reference rounds the state to binary32 after every step too: rounding the
     absolute rotor speeds (spacing 1e-3 rad/s near hover) alone moves this
     closed loop by about the parity bar over 1000 steps."""
-    w = W.small(2, seed=2)
+    w = W.small("fp_pid_closed_loop", seed=2)
     sim = _sim(w, flags=B.F_PLAIN_KERNEL if plain else 0)
     x = dev(w.x0)
     sim.step_k(x, dev(w.cmds), w.steps)
@@ -63,7 +63,7 @@ def test_plain_and_fused_agree(gpu_lib):
     """The fused kernel carries its compensated-summation terms across the steps it
     keeps in registers; the plain kernel restarts them every launch. Both follow
     the same discrete map, so they agree to the parity bar."""
-    w = W.small(2, seed=3)
+    w = W.small("fp_pid_closed_loop", seed=3)
     a, b = dev(w.x0), dev(w.x0)
     _sim(w).step_k(a, dev(w.cmds), 300)
     _sim(w, flags=B.F_PLAIN_KERNEL).step_k(b, dev(w.cmds), 300)
@@ -75,7 +75,7 @@ def test_plain_and_fused_agree(gpu_lib):
 def test_id_swarm_chunks(gpu_lib, k_launch):
     """Identified model, 3 worlds x 150 drones (tiles with a ragged tail), 1000
     steps as 1000/k_launch fused launches of k_launch steps."""
-    w = W.small(3, seed=4)
+    w = W.small("id_swarm", seed=4)
     sim = _sim(w)
     x, u = dev(w.x0), dev(w.cmds)
     for _ in range(w.steps // k_launch):
@@ -88,7 +88,7 @@ def test_id_swarm_chunks(gpu_lib, k_launch):
 def test_uneven_mixed_models(gpu_lib, wq):
     """Uneven drones per world, first-principles (PID) and identified worlds in one
     handle, grid of per-world tiles or the persistent work queue."""
-    w = W.small(5, seed=5)
+    w = W.small("uneven_mixed", seed=5)
     sim = _sim(w, flags=B.F_WORKQUEUE if wq else 0)
     x = dev(w.x0)
     sim.step_k(x, dev(w.cmds), w.steps)
@@ -98,7 +98,7 @@ def test_uneven_mixed_models(gpu_lib, wq):
 
 def test_batch_composition_invariance(gpu_lib):
     """A world gives bit-identical results alone or inside a larger batch."""
-    w = W.small(3, seed=6)
+    w = W.small("id_swarm", seed=6)
     full = dev(w.x0)
     _sim(w).step_k(full, dev(w.cmds), 200)
     sub = W.subset(w, [1])
@@ -110,7 +110,7 @@ def test_batch_composition_invariance(gpu_lib):
 
 
 def test_workqueue_deterministic_and_equal_to_grid(gpu_lib):
-    w = W.small(5, seed=7)
+    w = W.small("uneven_mixed", seed=7)
     outs = []
     for flags in (0, B.F_WORKQUEUE, B.F_WORKQUEUE):
         x = dev(w.x0)
@@ -168,19 +168,19 @@ def _check_against_oracle(w, got):
 def test_identified_rollout_gradients(gpu_lib):
     """Figure-eight tracking with a shared 4x13 gain: loss, per-world loss, x_T and
     gradients w.r.t. commands, initial state and gain vs the oracle's autograd."""
-    w = W.small(4, seed=8)
+    w = W.small("id_rollout_grad", seed=8)
     _check_against_oracle(w, _rollout_grads(w, 25))
 
 
 def test_mixed_rollout_gradients(gpu_lib):
     """First-principles (PID, S=25) and identified worlds, uneven sizes, one gain
     per model, per-drone figure-eight offsets."""
-    w = W.config5_adjoint(seed=9, n_worlds=12, n_subset=8, steps=120, n_max=70)
+    w = W.uneven_mixed_adjoint(seed=9, n_worlds=12, n_subset=8, steps=120, n_max=70)
     _check_against_oracle(w, _rollout_grads(w, 40))
 
 
 def test_fp_rotor_rollout_gradients(gpu_lib):
-    w = W.config1(seed=10, n_worlds=70, steps=60)
+    w = W.fp_rotor_open_loop(seed=10, n_worlds=70, steps=60)
     w.ref_offset = w.x0[0:3].copy()
     w.dloss = np.linspace(0.5, 1.5, 70).astype(np.float32)
     w.w_u = 1e-9
@@ -188,7 +188,7 @@ def test_fp_rotor_rollout_gradients(gpu_lib):
 
 
 def test_checkpoint_interval_invariance(gpu_lib):
-    w = W.small(4, seed=11)
+    w = W.small("id_rollout_grad", seed=11)
     base = _rollout_grads(w, 100)
     for K in (25, 50, 7):
         g = _rollout_grads(w, K)
@@ -198,7 +198,7 @@ def test_checkpoint_interval_invariance(gpu_lib):
 
 
 def test_autograd_function(gpu_lib):
-    w = W.small(4, seed=12)
+    w = W.small("id_rollout_grad", seed=12)
     sim = _sim(w)
     x0 = dev(w.x0).requires_grad_(True)
     cmds = dev(w.cmds).requires_grad_(True)
@@ -213,7 +213,7 @@ def test_autograd_function(gpu_lib):
 
 
 def test_backward_rejects_foreign_checkpoints(gpu_lib):
-    w = W.small(4, seed=13)
+    w = W.small("id_rollout_grad", seed=13)
     sim = _sim(w)
     g = _rollout_grads(w, 25, sim=sim)
     x0, cmds = dev(w.x0), dev(w.cmds)
@@ -230,7 +230,7 @@ def test_backward_rejects_foreign_checkpoints(gpu_lib):
 
 
 def test_masked_reset(gpu_lib):
-    w = W.small(5, seed=14)
+    w = W.small("uneven_mixed", seed=14)
     sim = _sim(w)
     x = dev(w.x0)
     init = x.clone()
@@ -250,7 +250,7 @@ def test_masked_reset(gpu_lib):
 
 
 def test_nonfinite_flag(gpu_lib):
-    w = W.small(5, seed=15)
+    w = W.small("uneven_mixed", seed=15)
     sim = _sim(w, flags=B.F_NONFINITE_CHECK)
     x = dev(w.x0)
     off = w.world_offsets()
@@ -265,7 +265,7 @@ def test_nonfinite_flag(gpu_lib):
 def test_graph_replay_matches_eager(gpu_lib):
     """hipGraph replays of a captured 30-step sequence, with eager work and
     synchronisation between replays, give the eager result every time."""
-    w = W.small(5, seed=16)
+    w = W.small("uneven_mixed", seed=16)
     eager = _sim(w)
     graph = _sim(w, flags=B.F_GRAPH | B.F_WORKQUEUE)
     xe, xg, u = dev(w.x0), dev(w.x0), dev(w.cmds)
@@ -284,7 +284,7 @@ def test_graph_replay_matches_eager(gpu_lib):
 
 
 def test_empty_worlds_and_ragged_counts(gpu_lib):
-    w = W.small(5, seed=17)
+    w = W.small("uneven_mixed", seed=17)
     counts = w.drones_per_world.copy()
     counts[[0, 5]] = 0
     keep = np.concatenate([np.arange(o, o + c) for o, c in zip(w.world_offsets()[:-1], counts)])
@@ -300,7 +300,7 @@ def test_empty_worlds_and_ragged_counts(gpu_lib):
 
 
 def test_invalid_device_arguments_are_rejected(gpu_lib):
-    w = W.small(2, seed=18)
+    w = W.small("fp_pid_closed_loop", seed=18)
     sim = _sim(w)
     x = dev(w.x0)
     short = torch.empty((sim.S, sim.D - 1), device="cuda")
@@ -331,7 +331,7 @@ def _with_aero(w):
 def test_gyro_and_drag_held_steps(gpu_lib, wq):
     """Rotor gyroscopic/reaction torques and linear drag (compile-time aero kernel
     variant), mixed models, uneven worlds."""
-    w = _with_aero(W.small(5, seed=30))
+    w = _with_aero(W.small("uneven_mixed", seed=30))
     sim = _sim(w, flags=B.F_WORKQUEUE if wq else 0)
     x = dev(w.x0)
     sim.step_k(x, dev(w.cmds), w.steps)
@@ -340,12 +340,12 @@ def test_gyro_and_drag_held_steps(gpu_lib, wq):
 
 
 def test_gyro_and_drag_rollout_gradients(gpu_lib):
-    w = _with_aero(W.config5_adjoint(seed=31, n_worlds=12, n_subset=8, steps=100, n_max=70))
+    w = _with_aero(W.uneven_mixed_adjoint(seed=31, n_worlds=12, n_subset=8, steps=100, n_max=70))
     _check_against_oracle(w, _rollout_grads(w, 25))
 
 
 def test_gyro_and_drag_rotor_interface(gpu_lib):
-    w = _with_aero(W.config1(seed=32, n_worlds=40, steps=80))
+    w = _with_aero(W.fp_rotor_open_loop(seed=32, n_worlds=40, steps=80))
     w.ref_offset = w.x0[0:3].copy()
     w.dloss = np.ones(40, np.float32)
     w.w_u = 1e-9
@@ -359,7 +359,7 @@ def test_reference_speed_fallbacks_rotor_interface(gpu_lib):
     whose minimum lies above the hover thrust (no hover speed: reference at the
     vertex, here 0), and a negative linear term (vertex at 5000 rad/s below the
     hover speed)."""
-    w = W.config1(seed=77, n_worlds=6, steps=200)
+    w = W.fp_rotor_open_loop(seed=77, n_worlds=6, steps=200)
     tp = w.params["thrust_poly"].astype(np.float64)
     fh = W.MASS * W.GRAVITY / 4.0
     wh = float(W.hover_speed(W.MASS))
@@ -450,7 +450,7 @@ def _direct_half(w):
 def test_direct_thrust_variant_held(gpu_lib, wq):
     """Identified worlds without thrust dynamics (every other world), swarm and
     mixed batches."""
-    for w in (_direct_half(W.small(3, seed=50)), _direct_half(W.small(5, seed=51))):
+    for w in (_direct_half(W.small("id_swarm", seed=50)), _direct_half(W.small("uneven_mixed", seed=51))):
         sim = _sim(w, flags=B.F_WORKQUEUE if wq else 0)
         x = dev(w.x0)
         sim.step_k(x, dev(w.cmds), w.steps)
@@ -459,7 +459,7 @@ def test_direct_thrust_variant_held(gpu_lib, wq):
 
 
 def test_direct_thrust_variant_gradients(gpu_lib):
-    w = _direct_half(W.small(4, seed=52))
+    w = _direct_half(W.small("id_rollout_grad", seed=52))
     _check_against_oracle(w, _rollout_grads(w, 25))
 
 

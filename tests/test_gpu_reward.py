@@ -19,14 +19,14 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("K", [1, 10])
 def test_reward_gradients_identified(gpu_lib, K):
-    w = W.small(4, seed=31)
+    w = W.small("id_rollout_grad", seed=31)
     w.reward = W.BPTT_REWARD
     _check_against_oracle(_tilted(w, 31), _rollout_grads(w, K))
 
 
 @pytest.mark.parametrize("K", [1, 10])
 def test_reward_gradients_mixed_pid(gpu_lib, K):
-    w = W.config5_adjoint(seed=32, n_worlds=12, n_subset=8, steps=120, n_max=70)
+    w = W.uneven_mixed_adjoint(seed=32, n_worlds=12, n_subset=8, steps=120, n_max=70)
     w.reward = W.BPTT_REWARD
     w = _tilted(w, 32)
     _check_against_oracle(w, _rollout_grads(w, K))
@@ -40,7 +40,7 @@ def test_reward_torque_interface(gpu_lib):
 
 
 def test_reward_one_per_step_in_hover(gpu_lib):
-    w = W.config4(seed=7, n_worlds=70, steps=30)
+    w = W.id_rollout_grad(seed=7, n_worlds=70, steps=30)
     w.x0[6:9] = 0.0
     w.x0[3:6] = 0.0
     w.x0[12] = W.MASS * W.GRAVITY / W.ID_CF
@@ -63,7 +63,7 @@ def test_reward_rejects_position_interface_and_bad_weights(gpu_lib):
     ckpt = sim.ckpt_buffer(10, 10, B.CF_OBJ_BPTT_REWARD)
     with pytest.raises(B.CfError):
         sim.rollout(x0, cmds, 10, B.Sim.objective(reward=W.BPTT_REWARD), 10, ckpt=ckpt)
-    w2 = W.small(4, seed=35)
+    w2 = W.small("id_rollout_grad", seed=35)
     sim2 = B.Sim.from_workload(w2, flags=B.F_NO_AUTOTUNE_CACHE)
     bad = dict(W.BPTT_REWARD, w_tilt=-1.0)
     ck2 = sim2.ckpt_buffer(w2.steps, 10, B.CF_OBJ_BPTT_REWARD)
@@ -74,7 +74,7 @@ def test_reward_rejects_position_interface_and_bad_weights(gpu_lib):
 def test_bptt_on_the_paper_reward(gpu_lib):
     """16 environments, 40-step rollouts, the paper's weights and learning rate:
     the summed reward rises."""
-    w = W.config4(seed=36, n_worlds=16, steps=40)
+    w = W.id_rollout_grad(seed=36, n_worlds=16, steps=40)
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period, reward=W.BPTT_REWARD)
     out = train_linear_policy(sim, dev(w.x0), dev(w.cmds), w.steps, dev(w.gain), iters=60, lr=4.6e-2,
@@ -90,7 +90,7 @@ def test_bptt_on_the_paper_reward(gpu_lib):
 def test_reward_with_slow_controller(gpu_lib):
     """The reward objective and a PID running every third step together
     (checkpoint interval 3)."""
-    w = W.config5_adjoint(seed=37, n_worlds=10, n_subset=6, steps=61, n_max=50)
+    w = W.uneven_mixed_adjoint(seed=37, n_worlds=10, n_subset=6, steps=61, n_max=50)
     w.reward = W.BPTT_REWARD
     w.ctrl_every = 3
     w = _tilted(w, 37)

@@ -542,17 +542,17 @@ def _fd_check(w, n_dirs=4, h=1e-4, seed=0):
 
 
 def test_gradient_fd_identified_with_feedback():
-    w = W.config4(seed=11, n_worlds=3, steps=40, gain_std=0.05)
+    w = W.id_rollout_grad(seed=11, n_worlds=3, steps=40, gain_std=0.05)
     _fd_check(w)
 
 
 def test_gradient_fd_first_principles_pid():
-    w = W.config5_adjoint(seed=12, n_worlds=6, n_subset=4, steps=30, n_max=3)
+    w = W.uneven_mixed_adjoint(seed=12, n_worlds=6, n_subset=4, steps=30, n_max=3)
     _fd_check(w)
 
 
 def test_gradient_fd_first_principles_rotor():
-    w = W.config1(seed=13, n_worlds=2, steps=30)
+    w = W.fp_rotor_open_loop(seed=13, n_worlds=2, steps=30)
     w.ref_offset = w.x0[0:3].copy()
     w.dloss = np.ones(2, np.float32)
     w.w_u = 1e-9
@@ -564,7 +564,7 @@ def test_gradient_fd_asymmetric_rotor_law_away_from_the_kink():
     commands held 20 % above or below hover per rotor, so no rotor's command
     crosses its speed in 20 steps (no branch switch) and the central
     differences see a smooth map."""
-    w = W.config1(seed=15, n_worlds=3, steps=20)
+    w = W.fp_rotor_open_loop(seed=15, n_worlds=3, steps=20)
     w.params["motor_up"][:] = (40.0, 5e-4)
     w.params["motor_down"][:] = (20.0, 1e-3)
     hov = float(W.hover_speed(W.MASS))
@@ -578,7 +578,7 @@ def test_gradient_fd_asymmetric_rotor_law_away_from_the_kink():
 
 def test_gain_gradient_identity():
     """u_t = ubar_t + G e_t gives dL/dG = sum_t (dL/du_t) e_t^T exactly."""
-    w = W.config4(seed=14, n_worlds=4, steps=25, gain_std=0.05)
+    w = W.id_rollout_grad(seed=14, n_worlds=4, steps=25, gain_std=0.05)
     b = O.Batch.from_workload(w)
     kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u)
     g = O.rollout_grad(b, w.x0, w.cmds, w.steps, gain=O.t64(w.gain), dloss=w.dloss, **kw)
@@ -732,8 +732,8 @@ def test_drag_identified_exact_affine_map():
 
 
 def test_gradient_fd_with_gyro_and_drag():
-    for w in (W.config5_adjoint(seed=23, n_worlds=6, n_subset=4, steps=30, n_max=3),
-              W.config4(seed=24, n_worlds=3, steps=40, gain_std=0.05)):
+    for w in (W.uneven_mixed_adjoint(seed=23, n_worlds=6, n_subset=4, steps=30, n_max=3),
+              W.id_rollout_grad(seed=24, n_worlds=3, steps=40, gain_std=0.05)):
         fp = w.model_per_world == W.MODEL_FP
         w.params["Jp"][fp, 0] = 4e-9
         w.params["drag"][:] = DRAG
@@ -821,7 +821,7 @@ def test_fast_thrust_lag_converges_to_direct_variant():
 
 
 def test_gradient_fd_direct_thrust():
-    w = W.config4(seed=26, n_worlds=3, steps=40)
+    w = W.id_rollout_grad(seed=26, n_worlds=3, steps=40)
     w.params["c_tau"][[0, 2]] = 0.0
     w.gain = w.gain * 5
     _fd_check(w)
@@ -917,7 +917,7 @@ def test_binary32_storage_between_calls():
     """simulate_held(store_every=k) equals k-step fp64 runs chained through a
     binary32 copy of the state (the numpy cast is the definition of that rounding),
     and leaves every component representable in binary32."""
-    w = W.small(2, seed=2)
+    w = W.small("fp_pid_closed_loop", seed=2)
     w = W.subset(w, list(range(6)))
     n, k = 12, 4
     got = O.simulate_held(w, steps=n, store_every=k).numpy()
@@ -939,7 +939,7 @@ def test_multirate_controller_is_blocks_of_rotor_interface_steps(n):
     attitude PID evaluated once with period n dt, then n steps of the rotor
     interface under its commands, then the controller state it produced (built
     here from the rotor-interface path, not from the multirate step)."""
-    w = W.small(2, seed=2)
+    w = W.small("fp_pid_closed_loop", seed=2)
     w = W.subset(w, list(range(8)))
     w.ctrl_every = n
     steps = 3 * n + 1
@@ -1000,7 +1000,7 @@ def test_multirate_hover_fixed_point():
 def test_gradient_fd_multirate_controller():
     """Reverse-mode gradient through held controller outputs (PID every 3 steps)
     against central differences."""
-    w = W.config5_adjoint(seed=14, n_worlds=6, n_subset=4, steps=31, n_max=3)
+    w = W.uneven_mixed_adjoint(seed=14, n_worlds=6, n_subset=4, steps=31, n_max=3)
     w.ctrl_every = 3
     _fd_check(w)
 
@@ -1021,7 +1021,7 @@ def test_tilt_angle_matches_scipy():
     x[3:7] = torch.as_tensor(q.T)
     zf = Rotation.from_quat(q).apply([0.0, 0.0, 1.0])
     assert np.allclose(O.tilt_angle(bf, x).numpy(), np.arccos(np.clip(zf[:, 2], -1, 1)), atol=1e-7)
-    wi = W.config4(seed=3, n_worlds=n, steps=1)
+    wi = W.id_rollout_grad(seed=3, n_worlds=n, steps=1)
     bi = O.Batch.from_workload(wi)
     xi = torch.zeros(13, n, dtype=F64)
     xi[3:6] = torch.as_tensor(eul.T)
@@ -1044,12 +1044,12 @@ def _hover_on_reference(w):
 @pytest.mark.parametrize("model", ["id", "fp_pid"])
 def test_reward_is_one_per_step_in_hover_on_the_reference(model):
     if model == "id":
-        w = W.config4(seed=7, n_worlds=5, steps=20)
+        w = W.id_rollout_grad(seed=7, n_worlds=5, steps=20)
         w.x0[6:9] = 0.0
         w.x0[3:6] = 0.0
         w.x0[12] = W.MASS * W.GRAVITY / W.ID_CF
     else:
-        w = W.config2(seed=7, n_worlds=5, steps=20)
+        w = W.fp_pid_closed_loop(seed=7, n_worlds=5, steps=20)
         w.x0[3:7] = np.array([0, 0, 0, 1.0])[:, None]
         w.x0[7:13] = 0.0
         w.x0[17:25] = 0.0
@@ -1062,7 +1062,7 @@ def test_reward_is_one_per_step_in_hover_on_the_reference(model):
 def test_smoothness_term_telescopes_for_a_held_action():
     """With the same action at every step the smoothness penalty is paid once,
     against the hover action before the first step."""
-    w = W.config4(seed=8, n_worlds=4, steps=15)
+    w = W.id_rollout_grad(seed=8, n_worlds=4, steps=15)
     w.gain = None
     a = O.hover_action(O.Batch.from_workload(w)).numpy() + np.array([0.05, -0.03, 0.02, 0.01])[:, None]
     w.cmds = np.repeat(a[None], w.steps, 0).astype(np.float32)
@@ -1097,7 +1097,7 @@ def _tilted(w, seed):
 
 
 def test_gradient_fd_reward_identified():
-    w = W.small(4, seed=16)
+    w = W.small("id_rollout_grad", seed=16)
     w.steps = 40
     w.cmds = w.cmds[:40]
     w.reward = W.BPTT_REWARD
@@ -1105,7 +1105,7 @@ def test_gradient_fd_reward_identified():
 
 
 def test_gradient_fd_reward_first_principles_pid():
-    w = W.config5_adjoint(seed=17, n_worlds=6, n_subset=4, steps=30, n_max=3)
+    w = W.uneven_mixed_adjoint(seed=17, n_worlds=6, n_subset=4, steps=30, n_max=3)
     w.reward = W.BPTT_REWARD
     _fd_check(_tilted(w, 17), h=3e-6)
 
@@ -1221,7 +1221,7 @@ def test_mlp_policy_with_small_weights_is_the_linear_feedback():
     """With W1 = eps A, W2 = B, W3 = C and zero biases the MLP output is
     eps C B A e + O(eps^3): the rollout converges to the one with the linear
     gain eps C B A at second order in eps (relative)."""
-    w = W.config4_mlp(seed=40, n_worlds=6, steps=60, hidden=8)
+    w = W.id_rollout_grad_mlp(seed=40, n_worlds=6, steps=60, hidden=8)
     H = 8
     rng = np.random.default_rng(40)
     A = rng.normal(size=(H, 13))
@@ -1245,7 +1245,7 @@ def test_mlp_policy_with_small_weights_is_the_linear_feedback():
 def test_mlp_policy_output_layer_gradient_identity():
     """u_t = ubar_t + W3 h2_t + b3 gives dL/dW3 = sum_t (dL/du_t) h2_t^T and
     dL/db3 = sum_t dL/du_t exactly."""
-    w = W.config4_mlp(seed=41, n_worlds=3, steps=25, hidden=6, out_scale=0.05)
+    w = W.id_rollout_grad_mlp(seed=41, n_worlds=3, steps=25, hidden=6, out_scale=0.05)
     H = 6
     b = O.Batch.from_workload(w)
     kw = dict(ref_amp=w.ref_amp, ref_period=w.ref_period, w_u=w.w_u, policy_hidden=H)
@@ -1270,14 +1270,14 @@ def test_mlp_policy_output_layer_gradient_identity():
 
 
 def test_gradient_fd_mlp_policy():
-    w = W.config4_mlp(seed=42, n_worlds=3, steps=20, hidden=5, out_scale=0.05)
+    w = W.id_rollout_grad_mlp(seed=42, n_worlds=3, steps=20, hidden=5, out_scale=0.05)
     _fd_check(w)
 
 
 def test_reference_time_offset_equals_the_shifted_table():
     """A rollout that follows the figure-eight from step k equals the same rollout
     given the reference rows of steps k .. k + T as an explicit table."""
-    w = W.config4(seed=43, n_worlds=4, steps=30)
+    w = W.id_rollout_grad(seed=43, n_worlds=4, steps=30)
     k = 777
     b = O.Batch.from_workload(w)
     rows = []
@@ -1298,7 +1298,7 @@ def test_reference_time_shift_equals_per_drone_start_steps():
     """A per-drone time shift of k_d steps equals following the figure-eight from
     step k_d (dt a power of two, so k dt is exact in both forms), drone by drone,
     with the linear feedback, per-drone offsets and both objectives."""
-    w = W.config4(seed=44, n_worlds=5, steps=30, dt=2.0 ** -9)
+    w = W.id_rollout_grad(seed=44, n_worlds=5, steps=30, dt=2.0 ** -9)
     ks = np.array([0, 3, 250, 1024, 4095])
     w.ref_offset = W._f32(np.random.Generator(np.random.Philox(44)).normal(0.0, 0.3, size=(3, 5)))
     w.ref_time_shift = (ks * w.dt).astype(np.float32)
@@ -1316,7 +1316,7 @@ def test_reference_time_shift_equals_per_drone_start_steps():
 
 
 def test_reference_time_shift_of_one_period_is_no_shift():
-    w = W.config4(seed=45, n_worlds=3, steps=40)
+    w = W.id_rollout_grad(seed=45, n_worlds=3, steps=40)
     base = O.rollout_workload(w)
     w.ref_time_shift = np.full(3, w.ref_period, np.float32)
     r = O.rollout_workload(w)
@@ -1346,9 +1346,9 @@ def test_bptt_tracking_starts_on_the_reference():
 
 
 def _squash_case(scale, gain_mult=1.0, steps=20, hidden=0):
-    w = W.config4(seed=46, n_worlds=6, steps=steps)
+    w = W.id_rollout_grad(seed=46, n_worlds=6, steps=steps)
     if hidden:
-        w = W.config4_mlp(seed=46, n_worlds=6, steps=steps, hidden=hidden, out_scale=0.3)
+        w = W.id_rollout_grad_mlp(seed=46, n_worlds=6, steps=steps, hidden=hidden, out_scale=0.3)
     w.gain = W._f32(w.gain * gain_mult)
     w.policy_scale = None if scale is None else W._f32(scale)
     return w

@@ -33,8 +33,8 @@ def _grads(sim, w, K, noalloc):
 
 
 def test_noalloc_backward_equals_the_allocating_backward(gpu_lib):
-    big = W.config5_adjoint(seed=96, n_worlds=24, n_subset=12, steps=150, n_max=300)   # both models, 2 gains
-    small = W.config4(seed=97, n_worlds=90, steps=40)                                     # fewer drones, shorter
+    big = W.uneven_mixed_adjoint(seed=96, n_worlds=24, n_subset=12, steps=150, n_max=300)   # both models, 2 gains
+    small = W.id_rollout_grad(seed=97, n_worlds=90, steps=40)                                     # fewer drones, shorter
     small.reward = W.BPTT_REWARD
     for w, K in ((big, 40), (small, 10)):
         sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
@@ -49,7 +49,7 @@ def test_noalloc_backward_equals_the_allocating_backward(gpu_lib):
 
 
 def test_noalloc_backward_refuses_scratch_beyond_the_static_array(gpu_lib):
-    w = W.config4(seed=98, n_worlds=70000, steps=200)   # 100 segment slots x 13 rows x 70 000 drones
+    w = W.id_rollout_grad(seed=98, n_worlds=70000, steps=200)   # 100 segment slots x 13 rows x 70 000 drones
     sim = B.Sim.from_workload(w, flags=B.F_NO_AUTOTUNE_CACHE)
     T, K = w.steps, 100
     x0, cmds, gain = dev(w.x0), dev(w.cmds), dev(w.gain)

@@ -213,7 +213,7 @@ def _grid_positions(rng, n, dims=None, spacing=0.3, jitter=0.03):
 
 # ---- the five workloads ------------------------------------------------------
 
-def config1(seed: int = 1001, n_worlds: int = 16, steps: int = 500,
+def fp_rotor_open_loop(seed: int = 1001, n_worlds: int = 16, steps: int = 500,
             integrator: int = INTEG_RK4, dt: float = 0.002) -> Workload:
     """Plain forward, first-principles rotor-speed interface, 1 drone per world."""
     rng = _rng(seed)
@@ -293,7 +293,7 @@ def _attitude_cmds(rng, D):
     return c
 
 
-def config2(seed: int = 1002, n_worlds: int = 4096, steps: int = 1000,
+def fp_pid_closed_loop(seed: int = 1002, n_worlds: int = 4096, steps: int = 1000,
             dt: float = 0.002) -> Workload:
     """Closed loop: attitude commands -> cascaded PID -> mixer -> first-principles model."""
     rng = _rng(seed)
@@ -329,7 +329,7 @@ def _id_x0(D, pos):
     return x0
 
 
-def config3(seed: int = 1003, n_worlds: int = 64, n_drones: int = 4000,
+def id_swarm(seed: int = 1003, n_worlds: int = 64, n_drones: int = 4000,
             steps: int = 1000, dt: float = 0.002, integrator: int = INTEG_RK4) -> Workload:
     """Swarm: identified attitude-command model, jittered 20x20x10 grid per world."""
     rng = _rng(seed)
@@ -351,7 +351,7 @@ def config3(seed: int = 1003, n_worlds: int = 64, n_drones: int = 4000,
 BPTT_REWARD = {"w_tilt": 0.1, "w_act": [0.12, 0.12, 0.0, 0.02], "w_dact": [1.4, 1.4, 0.0, 0.8]}
 
 
-def config4(seed: int = 1004, n_worlds: int = 1024, steps: int = 500,
+def id_rollout_grad(seed: int = 1004, n_worlds: int = 1024, steps: int = 500,
             dt: float = 0.002, gain_std: float = 0.01) -> Workload:
     """Differentiable rollout of the identified model with a shared 4x13 feedback gain,
     tracking a figure-eight (amplitude 1 m, period 4 s)."""
@@ -484,7 +484,7 @@ def uneven_counts(rng, n_worlds, n_max=4000):
     return np.clip(n, 1, n_max).astype(np.int32)
 
 
-def config5(seed: int = 1005, n_worlds: int = 2048, steps: int = 1000, dt: float = 0.002,
+def uneven_mixed(seed: int = 1005, n_worlds: int = 2048, steps: int = 1000, dt: float = 0.002,
             n_max: int = 4000) -> Workload:
     """Uneven batch: log-uniform drones per world, half first-principles closed loop,
     half identified model, held commands."""
@@ -538,13 +538,13 @@ def subset(w: Workload, worlds) -> Workload:
         dloss=None if w.dloss is None else w.dloss[cols].copy())
 
 
-def config5_adjoint(seed: int = 1005, n_worlds: int = 2048, n_subset: int = 256,
+def uneven_mixed_adjoint(seed: int = 1005, n_worlds: int = 2048, n_subset: int = 256,
                     steps: int = 1000, dt: float = 0.002, n_max: int = 4000,
                     gain_std: float = 0.01) -> Workload:
     """The seeded world subset of the uneven batch that is differentiated: per-step
     commands (hover + noise), per-drone figure-eight offsets at the drones' start
     positions, one feedback gain per model (index 0 first-principles, 1 identified)."""
-    base = config5(seed, n_worlds, 1, dt, n_max)
+    base = uneven_mixed(seed, n_worlds, 1, dt, n_max)
     rng = _rng(seed + 7919)
     pick = np.sort(rng.permutation(n_worlds)[:n_subset])
     w = subset(base, pick)
@@ -579,11 +579,11 @@ def mlp_policy_params(rng, n_policies: int, hidden: int, out_scale: float = 0.01
     return _f32(np.concatenate(out).reshape(n_policies, -1))
 
 
-def config4_mlp(seed: int = 1012, n_worlds: int = 1024, steps: int = 500, hidden: int = 32,
+def id_rollout_grad_mlp(seed: int = 1012, n_worlds: int = 1024, steps: int = 500, hidden: int = 32,
                 dt: float = 0.002, out_scale: float = 0.01) -> Workload:
     """The differentiable workload with a small-MLP policy (width `hidden`) in place
     of the linear feedback gain."""
-    w = config4(seed, n_worlds, steps, dt)
+    w = id_rollout_grad(seed, n_worlds, steps, dt)
     rng = _rng(seed + 104729)
     return dataclasses.replace(w, name="id_rollout_grad_mlp", gain=mlp_policy_params(rng, 1, hidden, out_scale),
                                policy_hidden=int(hidden))
@@ -631,17 +631,17 @@ def bptt_tracking(n_envs: int = 16, steps: int = 40, dt: float = 0.02, period: f
                     ref_time_shift=shift, policy_scale=_f32(BPTT_ACTION_RANGE))
 
 
-def small(cfg: int, seed: int) -> Workload:
-    """Reduced versions of the five workloads that the oracle finishes in seconds but
-    that still span several 64-lane waves and a ragged tail."""
-    if cfg == 1:
-        return config1(seed, n_worlds=16, steps=500)
-    if cfg == 2:
-        return config2(seed, n_worlds=200, steps=1000)
-    if cfg == 3:
-        return config3(seed, n_worlds=3, n_drones=150, steps=1000)
-    if cfg == 4:
-        return config4(seed, n_worlds=100, steps=100)
-    if cfg == 5:
-        return config5(seed, n_worlds=24, steps=300, n_max=120)
-    raise ValueError(cfg)
+def small(name: str, seed: int) -> Workload:
+    """Reduced versions of the five workloads, by name, that the oracle finishes in
+    seconds but that still span several 64-lane waves and a ragged tail."""
+    if name == "fp_rotor_open_loop":
+        return fp_rotor_open_loop(seed, n_worlds=16, steps=500)
+    if name == "fp_pid_closed_loop":
+        return fp_pid_closed_loop(seed, n_worlds=200, steps=1000)
+    if name == "id_swarm":
+        return id_swarm(seed, n_worlds=3, n_drones=150, steps=1000)
+    if name == "id_rollout_grad":
+        return id_rollout_grad(seed, n_worlds=100, steps=100)
+    if name == "uneven_mixed":
+        return uneven_mixed(seed, n_worlds=24, steps=300, n_max=120)
+    raise ValueError(name)
