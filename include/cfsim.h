@@ -51,7 +51,7 @@ typedef int32_t cf_status;
 #define CF_ENOMEM       (-3)  /* device or host allocation failed */
 #define CF_EDEVICE      (-4)  /* a HIP runtime call or kernel failed */
 #define CF_ESTATE       (-5)  /* call sequence violated (e.g. checkpoint mismatch) */
-#define CF_EUNSUPPORTED (-6)  /* valid request that this build does not implement */
+#define CF_EUNSUPPORTED (-6)  /* valid request that the library does not implement */
 
 /* models, control interfaces, integrators */
 #define CF_MODEL_FP      0

@@ -564,7 +564,7 @@ const char* cf_strerror(cf_status s) {
         case CF_ENOMEM: return "out of memory";
         case CF_EDEVICE: return "HIP device or runtime error";
         case CF_ESTATE: return "call sequence or checkpoint mismatch";
-        case CF_EUNSUPPORTED: return "unsupported by this build";
+        case CF_EUNSUPPORTED: return "unsupported by this library";
         default: return "unknown status";
     }
 }
