@@ -282,6 +282,28 @@ def main():
         K = best[0]
     cur["K"], cur["ckpt"] = K, adjoint_buffers(K)
     ckpt = cur["ckpt"]
+    # tile size of the held step inside the job: on the held steps alone the
+    # candidate tiles come out within a few per cent of each other, and the
+    # overlap with the adjoint decides between them (median of 4 job steps each)
+    if not args.serial and not args.launch:
+        best_t = None
+        for tl in sorted({64, 256, cfg["tile"]}):
+            for h_ in (sim, simO, simT):
+                h_.set_launch_config(cfg["workqueue"], tl, cfg["chunk"], cfg["per_model_launches"],
+                                     max(args.wq_waves, 0))
+            one_step()
+            torch.cuda.synchronize()
+            trial = []
+            for _ in range(4):
+                one_step(trial)
+            torch.cuda.synchronize()
+            med = float(np.median([r[0].elapsed_time(r[6]) for r in trial]))
+            if best_t is None or med < best_t[1]:
+                best_t = (tl, med)
+        cfg["tile"] = best_t[0]
+        for h_ in (sim, simO, simT):
+            h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"],
+                                 max(args.wq_waves, 0))
     # resident work-queue waves per compute unit of the held step inside the job:
     # every wave that fits, or fewer so that the adjoint's waves, whose chain is
     # the job's critical path, find registers and issue slots on more SIMDs
