@@ -565,10 +565,19 @@ __device__ __forceinline__ void fp_rates_vjp(const float* x, const float* rc, co
 
 // ---------------------------------------------------------------------------
 // identified model right-hand side, 13 components [p Psi v dPsi f]
+// AT_BASE: x holds the base angles themselves (an RK4 step's first stage), whose
+// sines and cosines B already holds (the angle-addition form returns exactly
+// these at a zero offset)
+template <bool AT_BASE = false>
 __device__ __forceinline__ void id_rates(const float* x, const float* u, const IdParams& P, const EulerBase& B,
                                          float* xd) {
     float sn[3], cs[3];
-    sincos3_near(x + 3, B, sn, cs);
+    if constexpr (AT_BASE) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { sn[i] = B.s0[i]; cs[i] = B.c0[i]; }
+    } else {
+        sincos3_near(x + 3, B, sn, cs);
+    }
     const float sph = sn[0], cph = cs[0], sth = sn[1], cth = cs[1], sps = sn[2], cps = cs[2];
     const float a = P.cf_m * (P.direct ? u[3] : x[12]);
     xd[0] = x[6]; xd[1] = x[7]; xd[2] = x[8];
@@ -586,10 +595,16 @@ __device__ __forceinline__ void id_rates(const float* x, const float* u, const I
     xd[12] = P.ctau * (u[3] - x[12]);
 }
 
+template <bool AT_BASE = false>
 __device__ __forceinline__ void id_rates_vjp(const float* x, const float* u, const IdParams& P, const EulerBase& B,
                                              const float* gb, float* xb, float* ub) {
     float sn[3], cs[3];
-    sincos3_near(x + 3, B, sn, cs);
+    if constexpr (AT_BASE) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { sn[i] = B.s0[i]; cs[i] = B.c0[i]; }
+    } else {
+        sincos3_near(x + 3, B, sn, cs);
+    }
     const float sph = sn[0], cph = cs[0], sth = sn[1], cth = cs[1], sps = sn[2], cps = cs[2];
     const float a = P.cf_m * (P.direct ? u[3] : x[12]);
     const float rz0 = cps * sth * cph + sps * sph;
@@ -855,17 +870,18 @@ __device__ __forceinline__ void pid_vjp(const float* x, const FpParams& P, const
 // summation; c[] carries each row's lost low-order part from step to step while
 // the state stays in registers (rotor speeds ~1e4 and growing positions and
 // velocities would otherwise drop increments below half an FP32 ulp).
-template <int N, int INTEG, uint32_t MASK, class Rates>
-__device__ __forceinline__ void integrate(float* x, float* c, float h, const Rates& rates) {
+// rates1 evaluates the first stage (at x itself), rates the others
+template <int N, int INTEG, uint32_t MASK, class Rates1, class Rates>
+__device__ __forceinline__ void integrate(float* x, float* c, float h, const Rates1& rates1, const Rates& rates) {
     float k[N], d[N];
     if constexpr (INTEG == EULER) {
-        rates(x, k);
+        rates1(x, k);
 #pragma unroll
         for (int i = 0; i < N; ++i) d[i] = h * k[i];
     } else {
         float acc[N], xs[N];
         const float h2 = 0.5f * h, h6 = h * (1.0f / 6.0f);
-        rates(x, k);
+        rates1(x, k);
 #pragma unroll
         for (int i = 0; i < N; ++i) { acc[i] = k[i]; xs[i] = x[i] + h2 * k[i]; }
         rates(xs, k);
@@ -889,6 +905,11 @@ __device__ __forceinline__ void integrate(float* x, float* c, float h, const Rat
             x[i] += d[i];
         }
     }
+}
+
+template <int N, int INTEG, uint32_t MASK, class Rates>
+__device__ __forceinline__ void integrate(float* x, float* c, float h, const Rates& rates) {
+    integrate<N, INTEG, MASK>(x, c, h, rates, rates);
 }
 
 // The first-principles step when the rotor law is W' = c_v (W_cmd - W) (no
@@ -971,16 +992,18 @@ constexpr uint32_t COMP_NONE = 0u;
 // follows the step); it receives y only when NEED_Y. Writes
 // xb = (dPhi/dx)^T yb; vjp(xin, gb, xa) adds (d rates/d xin)^T gb into xa and
 // accumulates the command adjoint itself.
-template <int N, int INTEG, bool NEED_Y, class Rates, class Vjp, class Post>
+// rates1 / vjp1 serve the first stage (at x itself), rates / vjp the others
+template <int N, int INTEG, bool NEED_Y, class Rates, class Vjp, class Post, class Rates1, class Vjp1>
 __device__ __forceinline__ void integrate_vjp(const float* x, float h, const float* yb_in, float* xb,
-                                              const Rates& rates, const Vjp& vjp, const Post& post) {
+                                              const Rates& rates, const Vjp& vjp, const Post& post,
+                                              const Rates1& rates1, const Vjp1& vjp1) {
     float yb[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) yb[i] = yb_in[i];
     if constexpr (INTEG == EULER) {
         if constexpr (NEED_Y) {
             float k[N], y[N];
-            rates(x, k);
+            rates1(x, k);
 #pragma unroll
             for (int i = 0; i < N; ++i) y[i] = x[i] + h * k[i];
             post(y, yb);
@@ -988,11 +1011,11 @@ __device__ __forceinline__ void integrate_vjp(const float* x, float h, const flo
         float gb[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) { xb[i] = yb[i]; gb[i] = h * yb[i]; }
-        vjp(x, gb, xb);
+        vjp1(x, gb, xb);
     } else {
         const float h2 = 0.5f * h;
         float xs[N], k[N], acc[N], x2[N], x3[N];   // stage states 2 and 3 kept for the reverse sweep
-        rates(x, k);
+        rates1(x, k);
 #pragma unroll
         for (int i = 0; i < N; ++i) { xs[i] = x[i] + h2 * k[i]; acc[i] = k[i]; x2[i] = xs[i]; }
         rates(xs, k);
@@ -1023,10 +1046,16 @@ __device__ __forceinline__ void integrate_vjp(const float* x, float h, const flo
         vjp(x2, gb, a);                       // stage 2
 #pragma unroll
         for (int i = 0; i < N; ++i) { xb[i] += a[i]; gb[i] = h6 * yb[i] + h2 * a[i]; a[i] = 0.f; }
-        vjp(x, gb, a);                        // stage 1
+        vjp1(x, gb, a);                       // stage 1
 #pragma unroll
         for (int i = 0; i < N; ++i) xb[i] += a[i];
     }
+}
+
+template <int N, int INTEG, bool NEED_Y, class Rates, class Vjp, class Post>
+__device__ __forceinline__ void integrate_vjp(const float* x, float h, const float* yb_in, float* xb,
+                                              const Rates& rates, const Vjp& vjp, const Post& post) {
+    integrate_vjp<N, INTEG, NEED_Y>(x, h, yb_in, xb, rates, vjp, post, rates, vjp);
 }
 
 // VJP of integrate_fp_linear_rotors: the rigid-body rows 0..12 run the RK4
@@ -1212,7 +1241,9 @@ __device__ __forceinline__ void euler_rebase(const float* a, EulerBase& b) {
 template <int INTEG>
 __device__ __forceinline__ void id_step_base(float* x, float* comp, const float* u, const IdParams& P, float dt,
                                              const EulerBase& B) {
-    integrate<S_ID, INTEG, COMP_ID>(x, comp, dt, [&](const float* xi, float* xd) { id_rates(xi, u, P, B, xd); });
+    integrate<S_ID, INTEG, COMP_ID>(
+        x, comp, dt, [&](const float* xi, float* xd) { id_rates<true>(xi, u, P, B, xd); },
+        [&](const float* xi, float* xd) { id_rates(xi, u, P, B, xd); });
     if (P.direct) x[12] = u[3];  // the thrust row holds the applied thrust
 }
 
@@ -1220,7 +1251,9 @@ template <int INTEG>
 __device__ __forceinline__ void id_step(float* x, float* comp, const float* u, const IdParams& P, float dt) {
     EulerBase B;
     euler_base(x + 3, B);
-    integrate<S_ID, INTEG, COMP_ID>(x, comp, dt, [&](const float* xi, float* xd) { id_rates(xi, u, P, B, xd); });
+    integrate<S_ID, INTEG, COMP_ID>(
+        x, comp, dt, [&](const float* xi, float* xd) { id_rates<true>(xi, u, P, B, xd); },
+        [&](const float* xi, float* xd) { id_rates(xi, u, P, B, xd); });
     if (P.direct) x[12] = u[3];  // the thrust row holds the applied thrust
 }
 
@@ -1334,7 +1367,9 @@ __device__ __forceinline__ void id_step_vjp(const float* x, const float* u, cons
         x, dt, ym, xb,
         [&](const float* xi, float* xd) { id_rates(xi, u, P, B, xd); },
         [&](const float* xi, const float* gb, float* xa) { id_rates_vjp(xi, u, P, B, gb, xa, ub); },
-        [](const float*, float*) {});
+        [](const float*, float*) {},
+        [&](const float* xi, float* xd) { id_rates<true>(xi, u, P, B, xd); },
+        [&](const float* xi, const float* gb, float* xa) { id_rates_vjp<true>(xi, u, P, B, gb, xa, ub); });
 }
 
 }  // namespace cfk
