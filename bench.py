@@ -47,7 +47,8 @@ SPEC_HBM_GBS = 8000.0
 # launch configuration "workqueue,tile,chunk,per_model"; summary in
 # profiles/held_step_uneven_mixed_2048w_T1000.md. Valid only for the kernel
 # sources it was measured on (SHA-256 below), reported as null otherwise.
-PROFILED_TRAFFIC = {"sources_sha256": "86e1fc2c825168a9e46eb437e7ce3bb816678efe3c1a398b210b6b9c87f4d3cb", "by_launch": {"1,64,100,1": 134006806, "1,256,100,1": 115432342}}
+PROFILED_TRAFFIC = {"sources_sha256": "c247793ad9bfb4d4c921b12a5793c93d669903915fbbb998d13e87b43f612cb7",
+                    "by_launch": {"1,64,100,1": 134419568, "1,256,100,1": 115490200}}
 
 
 def kernel_sources_sha256() -> str:
