@@ -39,6 +39,9 @@ import numpy as np  # noqa: E402
 FLOPS_PER_DS = {"fp_rotor_rk4": 597.0, "fp_pid_rk4": 812.0, "id_rk4": 305.0,
                 "id_rollout_fwd": 413.0, "id_rollout_fwd_bwd": 1826.0}
 SPEC_FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak
+# job steps timed per candidate when the launch choices are tuned inside the job
+# (job steps vary by about 3 %; the median of 8 separates candidates 2 % apart)
+TUNE_STEPS = 8
 SPEC_HBM_GBS = 8000.0
 
 # HBM bytes of one launch of the dominant kernel (the first-principles held-step
@@ -248,7 +251,7 @@ def main():
 
     # checkpoint interval: the caller's choice; otherwise the candidates whose
     # adjoint alone is within 10 % of the fastest are tried inside the
-    # overlapped job (median of 4 job steps) and the fastest job wins
+    # overlapped job (median of TUNE_STEPS job steps) and the fastest job wins
     if args.ckpt > 0:
         cands = [args.ckpt]
     else:
@@ -273,7 +276,7 @@ def main():
             one_step()
             torch.cuda.synchronize()
             trial = []
-            for _ in range(4):
+            for _ in range(TUNE_STEPS):
                 one_step(trial)
             torch.cuda.synchronize()
             med = float(np.median([r[0].elapsed_time(r[6]) for r in trial]))
@@ -285,7 +288,7 @@ def main():
     ckpt = cur["ckpt"]
     # tile size of the held step inside the job: on the held steps alone the
     # candidate tiles come out within a few per cent of each other, and the
-    # overlap with the adjoint decides between them (median of 4 job steps each)
+    # overlap with the adjoint decides between them (median of TUNE_STEPS job steps each)
     if not args.serial and not args.launch:
         best_t = None
         for tl in sorted({64, 256, cfg["tile"]}):
@@ -295,7 +298,7 @@ def main():
             one_step()
             torch.cuda.synchronize()
             trial = []
-            for _ in range(4):
+            for _ in range(TUNE_STEPS):
                 one_step(trial)
             torch.cuda.synchronize()
             med = float(np.median([r[0].elapsed_time(r[6]) for r in trial]))
@@ -308,7 +311,7 @@ def main():
     # resident work-queue waves per compute unit of the held step inside the job:
     # every wave that fits, or fewer so that the adjoint's waves, whose chain is
     # the job's critical path, find registers and issue slots on more SIMDs
-    # (median of 4 job steps per candidate)
+    # (median of TUNE_STEPS job steps per candidate)
     wq_best = (max(args.wq_waves, 0), None)
     if cfg["workqueue"] and not args.serial and args.wq_waves < 0:
         for cap in (0, 8, 4, 2):
@@ -317,7 +320,7 @@ def main():
             one_step()
             torch.cuda.synchronize()
             trial = []
-            for _ in range(4):
+            for _ in range(TUNE_STEPS):
                 one_step(trial)
             torch.cuda.synchronize()
             med = float(np.median([r[0].elapsed_time(r[6]) for r in trial]))
@@ -326,7 +329,7 @@ def main():
     for h_ in (sim, simO, simT):
         h_.set_launch_config(cfg["workqueue"], cfg["tile"], cfg["chunk"], cfg["per_model_launches"], wq_best[0])
     # schedule inside the job: everything overlapped from the start, or the held
-    # steps held back until the subset's forward rollout is done (median of 4
+    # steps held back until the subset's forward rollout is done (median of TUNE_STEPS
     # job steps each)
     if not args.serial:
         sched = []
@@ -335,7 +338,7 @@ def main():
             one_step()
             torch.cuda.synchronize()
             trial = []
-            for _ in range(4):
+            for _ in range(TUNE_STEPS):
                 one_step(trial)
             torch.cuda.synchronize()
             sched.append((float(np.median([r[0].elapsed_time(r[6]) for r in trial])), ff))
