@@ -537,3 +537,40 @@ def test_interfaces_graph_replay_and_masked_reset(gpu_lib, make):
     keep[[0, 5, 129]] = False
     assert torch.equal(xe[:, ~keep.cuda()], init[:, ~keep.cuda()])
     assert torch.equal(xe[:, keep.cuda()], moved[:, keep.cuda()])
+
+
+# ---- quaternion renormalisation switched off ----------------------------------------
+
+@pytest.mark.parametrize("integ", [W.INTEG_RK4, W.INTEG_EULER])
+def test_rotor_interface_gradients_without_renormalisation(gpu_lib, integ):
+    """renorm_q = 0: the forward keeps the integrator's quaternion as it is and the
+    reverse step has no renormalisation adjoint (the closed-form rotor rows of the
+    linear rotor law), against the oracle's autograd."""
+    w = W.fp_rotor_open_loop(seed=40, n_worlds=70, steps=60, integrator=integ)
+    w.renorm_q = 0
+    w.ref_offset = w.x0[0:3].copy()
+    w.dloss = np.linspace(0.5, 1.5, 70).astype(np.float32)
+    w.w_u = 1e-9
+    _check_against_oracle(w, _rollout_grads(w, 16))
+
+
+@pytest.mark.parametrize("aero", [False, True])
+def test_mixed_gradients_without_renormalisation(gpu_lib, aero):
+    """renorm_q = 0 with the attitude PID and the identified model, with and without
+    the rotor-inertia and drag terms (the general RK4 reverse step)."""
+    w = W.uneven_mixed_adjoint(seed=41, n_worlds=12, n_subset=8, steps=100, n_max=70)
+    if aero:
+        w = _with_aero(w)
+    w.renorm_q = 0
+    _check_against_oracle(w, _rollout_grads(w, 25))
+
+
+@pytest.mark.parametrize("wq", [False, True])
+def test_held_steps_without_renormalisation(gpu_lib, wq):
+    w = W.small("uneven_mixed", seed=43)
+    w.renorm_q = 0
+    sim = _sim(w, flags=B.F_WORKQUEUE if wq else 0)
+    x = dev(w.x0)
+    sim.step_k(x, dev(w.cmds), w.steps)
+    torch.cuda.synchronize()
+    assert_states_close(x, O.simulate_held(w), w, what="held steps, renormalisation off")
