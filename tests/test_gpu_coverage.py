@@ -119,6 +119,18 @@ def test_euler_identified_held_steps(gpu_lib, k_launch):
     assert_states_close(x, O.simulate_held(w), w, what=f"identified Euler, {k_launch} steps per launch")
 
 
+@pytest.mark.parametrize("wq", [False, True])
+def test_euler_mixed_held_steps(gpu_lib, wq):
+    """First-principles worlds behind the attitude PID and identified worlds, uneven
+    sizes, 300 Euler held steps (grid tiles and the work queue)."""
+    w = _euler(W.small("uneven_mixed", seed=85))
+    sim = _sim(w, flags=B.F_WORKQUEUE if wq else 0)
+    x = dev(w.x0)
+    sim.step_k(x, dev(w.cmds), w.steps)
+    torch.cuda.synchronize()
+    assert_states_close(x, O.simulate_held(w), w, what="mixed Euler held steps")
+
+
 # ---- rotor law with distinct acceleration / deceleration coefficients -------------------
 
 # c_v and c_d when the command is at least the speed (accelerating) and otherwise;
